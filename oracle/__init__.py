@@ -1,0 +1,261 @@
+"""FP64 CPU oracle for the CRKSPH neighbour passes (test infrastructure).
+
+Only the tests, the smoke check and the CPU-baseline leg of the benchmark
+import this package. The GPU library never does, and this package never
+imports the library: the two share nothing but the seeded inputs.
+
+The arithmetic lives in ``crk_oracle.c`` (plain C, FP64, built with
+-ffp-contract=off, OpenMP over particles); this module loads it with ctypes
+and wraps each pass. ``hnet.py`` holds the NumPy FP64 oracle of the
+smoothing-length network.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "crk_oracle.c")
+_LIB = os.path.join(_HERE, "liborc.so")
+
+_d = C.c_double
+_i64 = C.c_int64
+_int = C.c_int
+_p = C.c_void_p
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc (FP64, no contraction, OpenMP)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared",
+                               "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        L = C.CDLL(_LIB)
+        L.orc_W.restype = _d
+        L.orc_W.argtypes = [_d, _d]
+        L.orc_dWdr.restype = _d
+        L.orc_dWdr.argtypes = [_d, _d]
+        L.orc_kernel_eval.argtypes = [_i64, _p, _p, _p, _p]
+        L.orc_neighbors_brute.restype = _i64
+        L.orc_neighbors_brute.argtypes = [_i64, _p, _p, _p, _p, _d, _int, _int, _p, _p]
+        L.orc_neighbors_grid.restype = _i64
+        L.orc_neighbors_grid.argtypes = [_i64, _p, _p, _p, _p, _d, _int, _p, _p]
+        L.orc_volume.argtypes = [_i64, _p, _p, _p, _p, _d, _int, _p, _p, _p, _p, _p]
+        L.orc_nsum_at.restype = _d
+        L.orc_nsum_at.argtypes = [_i64, _p, _p, _p, _d, _int, _i64, _d]
+        L.orc_moments.argtypes = [_i64, _p, _p, _p, _p, _p, _d, _int, _p, _p] + [_p] * 6
+        L.orc_corrections.restype = _i64
+        L.orc_corrections.argtypes = [_i64] + [_p] * 11
+        L.orc_rk_pairs.argtypes = [_i64, _p, _p, _p, _p, _d, _int, _p, _p, _p, _p, _i64,
+                                   _p, _p, _p, _p, _p]
+        L.orc_gradv.argtypes = [_i64, _p, _p, _p, _p, _d, _int, _p, _p, _p, _p, _p, _p, _p, _p, _p]
+        L.orc_limiter.restype = _d
+        L.orc_limiter.argtypes = [_d, _d, _d, _d, _d]
+        L.orc_derivatives.argtypes = [_i64, _p, _p, _p, _p, _d, _int] + [_p] * 16
+        L.orc_thacker_step.restype = _d
+        L.orc_thacker_step.argtypes = [_d, _d, _d]
+        L.orc_hsolve.restype = _i64
+        L.orc_hsolve.argtypes = [_i64, _p, _p, _p, _d, _int, _d, _d, _int, _p, _p]
+        _lib = L
+    return _lib
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(_p)
+
+
+# ---------------------------------------------------------------- kernel
+def W(r, H):
+    r = _f64(np.broadcast_to(r, np.broadcast(r, H).shape))
+    H = _f64(np.broadcast_to(H, r.shape))
+    w = np.empty_like(r)
+    dw = np.empty_like(r)
+    lib().orc_kernel_eval(r.size, _ptr(r), _ptr(H), _ptr(w), _ptr(dw))
+    return w
+
+
+def dWdr(r, H):
+    r = _f64(np.broadcast_to(r, np.broadcast(r, H).shape))
+    H = _f64(np.broadcast_to(H, r.shape))
+    w = np.empty_like(r)
+    dw = np.empty_like(r)
+    lib().orc_kernel_eval(r.size, _ptr(r), _ptr(H), _ptr(w), _ptr(dw))
+    return dw
+
+
+# ------------------------------------------------------------ neighbours
+def neighbors(x, y, z, H, L=1.0, periodic=True, which=0, method="auto"):
+    """CSR (offsets int64 [n+1], idx int32) of N_g (which=0, self included)
+    or N_s (which=1), rows ascending."""
+    x, y, z, H = map(_f64, (x, y, z, H))
+    n = x.shape[0]
+    off = np.zeros(n + 1, dtype=np.int64)
+    if method == "auto":
+        method = "brute" if (n <= 4096 or not periodic) else "grid"
+    if method == "brute":
+        tot = lib().orc_neighbors_brute(n, _ptr(x), _ptr(y), _ptr(z), _ptr(H), L, int(periodic),
+                                        which, _ptr(off), None)
+        idx = np.empty(tot, dtype=np.int32)
+        lib().orc_neighbors_brute(n, _ptr(x), _ptr(y), _ptr(z), _ptr(H), L, int(periodic), which,
+                                  _ptr(off), _ptr(idx))
+    else:
+        if not periodic:
+            raise ValueError("the grid search is for periodic boxes")
+        tot = lib().orc_neighbors_grid(n, _ptr(x), _ptr(y), _ptr(z), _ptr(H), L, which,
+                                       _ptr(off), None)
+        idx = np.empty(tot, dtype=np.int32)
+        lib().orc_neighbors_grid(n, _ptr(x), _ptr(y), _ptr(z), _ptr(H), L, which, _ptr(off),
+                                 _ptr(idx))
+    return off, idx
+
+
+# ----------------------------------------------------------------- passes
+def volume(x, y, z, H, goff, gidx, L=1.0, periodic=True):
+    x, y, z, H = map(_f64, (x, y, z, H))
+    n = x.shape[0]
+    nsum, V, N = np.empty(n), np.empty(n), np.empty(n)
+    lib().orc_volume(n, _ptr(x), _ptr(y), _ptr(z), _ptr(H), L, int(periodic), _ptr(goff),
+                     _ptr(gidx), _ptr(nsum), _ptr(V), _ptr(N))
+    return nsum, V, N
+
+
+def nsum_at(x, y, z, i, Hi, L=1.0, periodic=True):
+    x, y, z = map(_f64, (x, y, z))
+    return lib().orc_nsum_at(x.shape[0], _ptr(x), _ptr(y), _ptr(z), L, int(periodic), int(i),
+                             float(Hi))
+
+
+def moments(x, y, z, H, V, goff, gidx, L=1.0, periodic=True):
+    """dict of m0 [n], m1 [3,n], m2 [6,n], gm0 [3,n], gm1 [9,n], gm2 [18,n]."""
+    x, y, z, H, V = map(_f64, (x, y, z, H, V))
+    n = x.shape[0]
+    out = dict(m0=np.empty(n), m1=np.empty((3, n)), m2=np.empty((6, n)), gm0=np.empty((3, n)),
+               gm1=np.empty((9, n)), gm2=np.empty((18, n)))
+    lib().orc_moments(n, _ptr(x), _ptr(y), _ptr(z), _ptr(H), _ptr(V), L, int(periodic),
+                      _ptr(goff), _ptr(gidx), *[_ptr(out[k]) for k in
+                                                ("m0", "m1", "m2", "gm0", "gm1", "gm2")])
+    return out
+
+
+def corrections(mom):
+    """dict of A [n], B [3,n], gA [3,n], gB [9,n], singular [n] int32, n_singular."""
+    n = mom["m0"].shape[0]
+    src = [_f64(mom[k]) for k in ("m0", "m1", "m2", "gm0", "gm1", "gm2")]
+    out = dict(A=np.empty(n), B=np.empty((3, n)), gA=np.empty((3, n)), gB=np.empty((9, n)),
+               singular=np.empty(n, dtype=np.int32))
+    ns = lib().orc_corrections(n, *[_ptr(a) for a in src],
+                               *[_ptr(out[k]) for k in ("A", "B", "gA", "gB", "singular")])
+    out["n_singular"] = int(ns)
+    return out
+
+
+def rk_pairs(x, y, z, H, corr, pi, pj, L=1.0, periodic=True):
+    """W^R_ij, grad W^R_ij [3,npair] and d_ij [3,npair] for ordered pairs (pi, pj)."""
+    x, y, z, H = map(_f64, (x, y, z, H))
+    pi = np.ascontiguousarray(pi, dtype=np.int32)
+    pj = np.ascontiguousarray(pj, dtype=np.int32)
+    npair = pi.shape[0]
+    WR, GR, d = np.empty(npair), np.empty((3, npair)), np.empty((3, npair))
+    c = [_f64(corr[k]) for k in ("A", "B", "gA", "gB")]
+    lib().orc_rk_pairs(x.shape[0], _ptr(x), _ptr(y), _ptr(z), _ptr(H), L, int(periodic),
+                       *[_ptr(a) for a in c], npair, _ptr(pi), _ptr(pj), _ptr(WR), _ptr(GR),
+                       _ptr(d))
+    return WR, GR, d
+
+
+def gradv(x, y, z, H, v, V, corr, goff, gidx, L=1.0, periodic=True):
+    x, y, z, H, v, V = map(_f64, (x, y, z, H, v, V))
+    n = x.shape[0]
+    out = np.empty((9, n))
+    c = [_f64(corr[k]) for k in ("A", "B", "gA", "gB")]
+    lib().orc_gradv(n, _ptr(x), _ptr(y), _ptr(z), _ptr(H), L, int(periodic), _ptr(v), _ptr(V),
+                    *[_ptr(a) for a in c], _ptr(goff), _ptr(gidx), _ptr(out))
+    return out
+
+
+def limiter(si, sj, eta, eta_c, eta_f):
+    return lib().orc_limiter(float(si), float(sj), float(eta), float(eta_c), float(eta_f))
+
+
+PARAM_KEYS = ("gamma", "Cl", "Cq", "eps", "nh", "eta_c", "eta_f", "a", "adot")
+
+
+def params(nres: float = 64.0, **over) -> dict:
+    """Solver parameters. n_h follows from the target neighbour count by
+    N_res = (4 pi / 3) n_h^3 (n_h = 4 <-> N_res = 268, Sec. 3.6), and the
+    limiter scales are (1/n_h, 0.2/n_h); the viscosity constants are
+    (C_l, C_q) = (2, 1) and eps = 0.1 (Sec. 2.2)."""
+    nh = (3.0 * nres / (4.0 * math.pi)) ** (1.0 / 3.0)
+    p = dict(gamma=5.0 / 3.0, Cl=2.0, Cq=1.0, eps=0.1, nh=nh, eta_c=1.0 / nh, eta_f=0.2 / nh,
+             a=1.0, adot=0.0)
+    p.update(over)
+    return p
+
+
+def derivatives(x, y, z, H, v, m, u, rho, V, corr, gv, soff, sidx, prm, L=1.0, periodic=True):
+    """(dp/dt [3,n], du/dt [n], SF [n], SE [n])."""
+    x, y, z, H, v, m, u, V, gv = map(_f64, (x, y, z, H, v, m, u, V, gv))
+    rho = None if rho is None else _f64(rho)
+    n = x.shape[0]
+    dv, du, SF, SE = np.empty((3, n)), np.empty(n), np.empty(n), np.empty(n)
+    c = [_f64(corr[k]) for k in ("A", "B", "gA", "gB")]
+    pa = np.array([prm[k] for k in PARAM_KEYS], dtype=np.float64)
+    lib().orc_derivatives(n, _ptr(x), _ptr(y), _ptr(z), _ptr(H), L, int(periodic), _ptr(v),
+                          _ptr(m), _ptr(u), _ptr(rho), _ptr(V), *[_ptr(a) for a in c], _ptr(gv),
+                          _ptr(pa), _ptr(soff), _ptr(sidx), _ptr(dv), _ptr(du), _ptr(SF),
+                          _ptr(SE))
+    return dv, du, SF, SE
+
+
+def thacker_step(H, N, Nres):
+    return lib().orc_thacker_step(float(H), float(N), float(Nres))
+
+
+def hsolve(x, y, z, H0, Nres, tol=1e-7, max_iter=100, L=1.0, periodic=True):
+    """(H [n], iterations [n] int32, n_not_converged)."""
+    x, y, z = map(_f64, (x, y, z))
+    H = _f64(H0).copy()
+    it = np.empty(x.shape[0], dtype=np.int32)
+    nf = lib().orc_hsolve(x.shape[0], _ptr(x), _ptr(y), _ptr(z), L, int(periodic), float(Nres),
+                          float(tol), int(max_iter), _ptr(H), _ptr(it))
+    return H, it, int(nf)
+
+
+def pipeline(ps, prm, periodic=True, method="auto"):
+    """Every pass in the paper's data order for one particle set:
+    neighbour sets -> volume -> moments -> corrections -> grad v -> derivatives.
+    Returns a dict with every intermediate (original particle order)."""
+    x, y, z, H = ps.x, ps.y, ps.z, ps.H
+    L = ps.L
+    goff, gidx = neighbors(x, y, z, H, L, periodic, 0, method)
+    soff, sidx = neighbors(x, y, z, H, L, periodic, 1, method)
+    nsum, V, N = volume(x, y, z, H, goff, gidx, L, periodic)
+    mom = moments(x, y, z, H, V, goff, gidx, L, periodic)
+    corr = corrections(mom)
+    gv = gradv(x, y, z, H, ps.v, V, corr, goff, gidx, L, periodic)
+    dv, du, SF, SE = derivatives(x, y, z, H, ps.v, ps.m, ps.u, ps.rho, V, corr, gv, soff, sidx,
+                                 prm, L, periodic)
+    out = dict(goff=goff, gidx=gidx, soff=soff, sidx=sidx, nsum=nsum, V=V, N=N, gradv=gv,
+               dvdt=dv, dudt=du, SF=SF, SE=SE, n_pairs=int(soff[-1]))
+    out.update(mom)
+    out.update(corr)
+    return out
