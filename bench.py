@@ -1,0 +1,173 @@
+"""Throughput of the CRKSPH step on one MI355X.
+
+Workload: 128^3 = 2,097,152 gas particles, lognormal clustered positions
+(sigma_ln rho = 1.5, P(k) ~ k^-2 on a 128^3 grid, seed 2), H sized for 64
+neighbours at each particle's cell density (neighbour counts ~20-400), gas
+state u = 1, masses 1/N, density m/V, shear + noise velocities. One step is
+every pass of the hot path: cell sort + neighbour lists, volumes, kernel
+moments, FP64 RK solve, velocity gradient, momentum/energy derivatives with
+limited viscosity, in the mixed precision (FP32 pair terms with Kahan sums,
+FP64 solve) unless --precision fp64.
+
+Prints one JSON line: pair-interactions/s (ordered pairs (i, j), j in N_s(i),
+counted once per step) over the whole step, the per-kernel roofline of the
+derivative pass, the max normwise error of every output against the FP64
+GPU path, and the FP64 CPU oracle timed on a smaller box of the same recipe.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# MI355X peaks: HBM3E bandwidth, and the vector ALU rate of this build.
+# 256 CUs x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz = 78.6 TFLOP/s for
+# FP64 and for unpacked FP32; the 157.3 TFLOP/s FP32 figure needs packed
+# FP32 instructions, which this library is compiled without.
+HBM_PEAK_GBS = 8000.0
+VALU_PEAK_TFLOPS = 78.6
+VALU_PEAK_PACKED_FP32 = 157.3
+
+# algorithmic work of the derivative pass (k_deriv), counted from the kernel
+# source: flops per ordered pair and bytes per particle / per pair
+DERIV_FLOPS_PER_PAIR = 256
+DERIV_BYTES_PER_PARTICLE = {"mixed": 32 + 144 + 8 + 8 + 32, "fp64": 32 + 288 + 8 + 8 + 32}
+DERIV_BYTES_PER_PAIR = 4
+
+OUT_KEYS = ("V", "m0", "m1", "m2", "gm0", "gm1", "gm2", "A", "B", "gA", "gB", "gradv", "dpdt",
+            "dudt")
+
+
+def make_workload(n_side=128, seed=2):
+    import crk_inputs as ci
+    return ci.lognormal_box(n_side, sigma=1.5, spectral_index=-2.0, seed=seed)
+
+
+def cpu_baseline(n_side: int) -> dict:
+    import oracle
+    ps = make_workload(n_side)
+    prm = oracle.params(64.0)
+    t0 = time.perf_counter()
+    out = oracle.pipeline(ps, prm)
+    dt = time.perf_counter() - t0
+    return {"value": out["n_pairs"] / dt, "unit": "pair-interactions/s", "cores": oracle.threads(),
+            "kind": "oracle",
+            "sample": f"full FP64 oracle step (neighbour sets, volume, moments, corrections, grad v, "
+                      f"derivatives) on the same recipe at {n_side}^3 = {ps.n} particles "
+                      f"({out['n_pairs']} pairs, {dt:.2f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n-side", type=int, default=128)
+    ap.add_argument("--precision", choices=("mixed", "mixed_m64", "fp64"), default="mixed")
+    ap.add_argument("--cpu-n-side", type=int, default=64)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-check", action="store_true")
+    ap.add_argument("--lanes", type=str, default="", help="vol,mom,grad,der lanes per particle")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU: the CRKSPH passes here run on a single MI355X; "
+              "multi-GPU sharding is a design note only. Use --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2202_02840_amd import CRK_FP64, CRK_MIXED, CRK_MIXED_M64, Context
+    from paper_2202_02840_amd import pipeline as pl
+
+    ps = make_workload(args.n_side)
+    prec = {"mixed": CRK_MIXED, "mixed_m64": CRK_MIXED_M64, "fp64": CRK_FP64}[args.precision]
+    ctx = Context(0)
+    if args.lanes:
+        ctx.set_lanes(*[int(v) for v in args.lanes.split(",")])
+    dev = pl.upload(ps)
+    prm = pl.params_for(ps, 64.0, prec)
+    torch.cuda.synchronize()
+
+    for _ in range(args.warmup):
+        out = pl.step(ctx, dev, prm, count_singular=False)
+    torch.cuda.synchronize()
+    ctx.timing(True)
+    ctx.timing_reset()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        out = pl.step(ctx, dev, prm, count_singular=False)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_step = (t1 - t0) * 1e3 / max(args.steps, 1)
+    kern = {}
+    for k in ("sort", "k_walk_count", "k_walk_fill", "k_sort_extras", "k_volume", "k_moments",
+              "k_corrections", "k_pack", "k_gradv", "k_deriv"):
+        ms, cnt = ctx.timing_read(k)
+        kern[k] = ms / max(cnt, 1)
+    ctx.timing(False)
+    npairs = int(out["n_pairs"])
+    n = ps.n
+
+    # roofline of the dominant kernel (the derivative pass)
+    t_der = kern["k_deriv"] * 1e-3
+    flops = DERIV_FLOPS_PER_PAIR * npairs
+    key = "fp64" if prec == CRK_FP64 else "mixed"
+    bytes_alg = DERIV_BYTES_PER_PARTICLE[key] * n + DERIV_BYTES_PER_PAIR * npairs
+    achieved_tf = flops / t_der / 1e12
+    hbm_gbs = bytes_alg / t_der / 1e9
+
+    # accuracy of this path against the FP64 GPU path at full size
+    errs = None
+    if not args.no_check:
+        ref = pl.step(ctx, dev, pl.params_for(ps, 64.0, CRK_FP64), count_singular=False)
+        cur = pl.step(ctx, dev, prm, count_singular=False)
+        torch.cuda.synchronize()
+        errs = {}
+        for k in OUT_KEYS:
+            a, b = cur[k], ref[k]
+            den = b.abs().max().item()
+            errs[k] = (a - b).abs().max().item() / den if den > 0 else (a - b).abs().max().item()
+
+    line = {
+        "metric": "CRKSPH pair-interactions/s at <=1e-5 rel err vs FP64; % HBM roofline",
+        "value": npairs / (ms_step * 1e-3),
+        "unit": "pair-interactions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if prec == CRK_FP64 else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": f"lognormal clustered gas, {args.n_side}^3 = {n} particles, "
+                               f"sigma_ln_rho 1.5, P(k)~k^-2, 64-neighbour H, seed 2; "
+                               f"{args.precision} CRKSPH step",
+                   "particles": n, "pairs_per_step": npairs,
+                   "mean_pairs_per_particle": npairs / n, "precision": args.precision},
+        "roofline": {"bound": "alu", "achieved": achieved_tf, "peak": VALU_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved_tf / VALU_PEAK_TFLOPS, "traffic": None,
+                     "kernel": "k_deriv", "kernel_ms": kern["k_deriv"],
+                     "flops_per_pair": DERIV_FLOPS_PER_PAIR,
+                     "frac_of_packed_fp32_peak": achieved_tf / VALU_PEAK_PACKED_FP32,
+                     "hbm_algorithmic_gbs": hbm_gbs, "hbm_frac": hbm_gbs / HBM_PEAK_GBS},
+        "kernel_ms": kern,
+        "max_rel_err_vs_fp64": errs,
+        "err_target_met": None if errs is None else bool(max(errs.values()) <= 1e-5),
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(args.cpu_n_side)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

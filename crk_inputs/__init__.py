@@ -119,12 +119,22 @@ def gaussian_field(n_grid: int, spectral_index: float, g: np.random.Generator) -
     return f
 
 
+def smooth_field(f: np.ndarray, width: float) -> np.ndarray:
+    """Periodic Gaussian smoothing of a grid field, width in grid cells."""
+    n = f.shape[0]
+    k = np.fft.fftfreq(n) * 2.0 * math.pi
+    kz = np.fft.rfftfreq(n) * 2.0 * math.pi
+    k2 = k[:, None, None] ** 2 + k[None, :, None] ** 2 + kz[None, None, :] ** 2
+    return np.fft.irfftn(np.fft.rfftn(f) * np.exp(-0.5 * k2 * width * width), s=f.shape,
+                         axes=(0, 1, 2))
+
+
 def lognormal_box(n_side: int = 128, sigma: float = 1.5, spectral_index: float = -2.0,
                   seed: int = 2, box: int = 0, nngb: float = 64.0, L: float = 1.0,
                   n_grid: int | None = None, n_particles: int | None = None,
                   u0: float = 1.0, vamp: float = 0.01, vnoise: float = 0.01,
                   hcap: float = 0.3, rho_input: float | None = None,
-                  gamma: float = 5.0 / 3.0) -> ParticleSet:
+                  gamma: float = 5.0 / 3.0, h_smooth: float = 1.0) -> ParticleSet:
     """Lognormal clustered particle set.
 
     A Gaussian field g with P(k) ~ k^spectral_index on an n_grid^3 grid gives the
@@ -132,7 +142,11 @@ def lognormal_box(n_side: int = 128, sigma: float = 1.5, spectral_index: float =
     occupancies are multinomial over cells with probabilities ~ rho_c, and each
     particle is uniform inside its cell. Particles are stored cell by cell in
     grid order (x fastest). H_i puts ``nngb`` particles in the support at the
-    density of its cell, clamped to ``hcap * L`` (the clamp count is in meta).
+    density of its cell after a Gaussian smoothing of rho_c over ``h_smooth``
+    grid cells (0: no smoothing), clamped to ``hcap * L`` (the clamp count is
+    in meta). Without the smoothing a support sized from one cell's density
+    can hold from 2 to ~10^4 particles, because the field is rough at the grid
+    scale; one cell of smoothing gives the ~20-400 range of the workload.
     Velocities: shear v_x = vamp sin(2 pi y / L) plus N(0, vnoise^2) per
     component. Masses are equal, total mass L^3 (mean density 1); when
     ``rho_input`` is None the density is left to the library (m / V).
@@ -152,7 +166,9 @@ def lognormal_box(n_side: int = 128, sigma: float = 1.5, spectral_index: float =
     off = g.uniform(0.0, 1.0, size=(3, N))
     h = L / n_grid
     p = _wrap(np.stack([ix + off[0], iy + off[1], iz + off[2]]) * h, L)
-    H = support_for_neighbours(nngb, N * flat[cell] / L ** 3)
+    rho_h = smooth_field(rho_c, h_smooth).ravel() if h_smooth > 0 else flat
+    rho_h = np.maximum(rho_h, 1e-12)
+    H = support_for_neighbours(nngb, N * rho_h[cell] / L ** 3)
     nclamp = int(np.count_nonzero(H > hcap * L))
     H = np.minimum(H, hcap * L)
     v = g.normal(0.0, vnoise, size=(3, N))
@@ -163,7 +179,7 @@ def lognormal_box(n_side: int = 128, sigma: float = 1.5, spectral_index: float =
                        L=L, gamma=gamma,
                        meta=dict(kind="lognormal", n_side=n_side, n_grid=n_grid, sigma=sigma,
                                  spectral_index=spectral_index, seed=seed, box=box, nngb=nngb,
-                                 n_clamped=nclamp, hcap=hcap))
+                                 n_clamped=nclamp, hcap=hcap, h_smooth=h_smooth))
 
 
 def clustered_clump_box(n_side: int = 256, sigma: float = 2.0, spectral_index: float = -2.5,

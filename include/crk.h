@@ -1,0 +1,233 @@
+/*
+ * crk.h — C ABI of the CRKSPH neighbour-pass library for AMD Instinct MI355X
+ * (gfx950).
+ *
+ * The library evaluates the particle passes of the conservative
+ * reproducing-kernel SPH hydro solver of Frontiere et al., "Simulating
+ * Hydrodynamics in Cosmology with CRK-HACC" (Sec. 2.2 and Sec. 3.6):
+ *
+ *   crk_build_cells  cell list + neighbour lists (chaining mesh, Sec. 3.3;
+ *                    one interaction list per step, reused by every pass)
+ *   crk_moments      volumes, eq. (vol), and the kernel moments whose
+ *                    constraints fix the RK kernel, eqs. (RK), (gRK)
+ *   crk_corrections  RK coefficients A, B and their gradients
+ *   crk_derivatives  RK velocity gradient, eq. (gradv), then the momentum and
+ *                    energy derivatives, eqs. (mom), (eng), with the limited
+ *                    Monaghan-Gingold viscosity, eqs. (visc)-(phiad)
+ *   crk_hsolve       smoothing-length iteration, eqs. (hi), (thacker)
+ *
+ * Notation. H is the kernel support radius (the paper's h in eq. (C4):
+ * W = 0 for |x| >= h). d = x_i - x_j is the minimum-image separation in a
+ * periodic cube of side L. The gather set of i is N_g(i) = {j : |d| < H_i}
+ * (i included); the pair set is N_s(i) = {j != i : |d| < max(H_i, H_j)}.
+ *
+ * Memory. Every array argument is a DEVICE pointer to a caller-owned,
+ * contiguous buffer on the context's device. Vector fields are
+ * component-major: a field with k components over n particles is k
+ * consecutive arrays of n values ([k][n]). The library never allocates or
+ * frees caller memory; it owns only the context workspace (sorted copies,
+ * neighbour lists, packed per-particle records, scratch), which grows on
+ * demand and is released by crk_destroy.
+ *
+ * Ordering. crk_build_cells sorts the particles by cell (Morton order of the
+ * cells, ties by original index). Every per-particle array passed to or
+ * returned by the later calls is in that sorted order; crk_permute moves
+ * arrays between the original and the sorted order.
+ *
+ * Index conventions (fixed so results can be compared element by element):
+ *   m2 and other symmetric 3x3 tensors: (xx, xy, xz, yy, yz, zz)
+ *   gm1[a*3+g] = d m1^a / d x^g      gm2[s*3+g] = d m2^s / d x^g
+ *   gB[a*3+g]  = d B^a  / d x^g      gradv[a*3+b] = d v^a / d x^b
+ *
+ * Errors and synchronisation. Every function returns a crk_status and throws
+ * nothing across the ABI. On an error the outputs are unspecified and
+ * crk_last_error() holds a message. Work is enqueued on the context's HIP
+ * stream; functions that return a host value (a count) synchronise that
+ * stream. A context is used by one host thread at a time.
+ */
+#ifndef CRK_H
+#define CRK_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    CRK_OK = 0,
+    CRK_WARN_SINGULAR = 1,      /* some m2 were singular; those particles use the SPH fallback */
+    CRK_WARN_NOT_CONVERGED = 2, /* the smoothing-length iteration hit max_iter for some particles */
+    CRK_ERR_INVALID_ARG = -1,   /* NULL pointer, n < 1, position outside [0, L), bad parameter */
+    CRK_ERR_NONFINITE = -2,     /* NaN or Inf in positions, H, masses, energies or densities */
+    CRK_ERR_SUPPORT = -3,       /* H <= 0 or max H >= L/2 (the minimum image would be ambiguous) */
+    CRK_ERR_WORKSPACE = -4,     /* device allocation of the workspace failed */
+    CRK_ERR_HIP = -5,           /* a HIP runtime call failed */
+    CRK_ERR_STATE = -6          /* called out of order (e.g. crk_moments before crk_build_cells) */
+} crk_status;
+
+/* Arithmetic of the pair passes. */
+typedef enum {
+    CRK_FP64 = 0,  /* every pair term and sum in FP64 */
+    CRK_MIXED = 1, /* FP32 pair terms with compensated (Kahan) FP32 sums in every pair pass;
+                      separations are formed in FP64 before rounding; the RK solve
+                      (crk_corrections) and every boundary array stay FP64 */
+    CRK_MIXED_M64 = 2 /* volume and moment passes in FP64 (their sums feed the RK solve,
+                      whose conditioning amplifies their error), velocity-gradient and
+                      derivative passes as in CRK_MIXED */
+} crk_precision;
+
+/*
+ * Solver parameters (Sec. 2.2, Sec. 3.6).
+ *   L                periodic box side
+ *   gamma            adiabatic index of P = (gamma - 1) rho u, eq. (EOS)
+ *   Cl, Cq, eps      viscosity constants of eqs. (visc), (mu): 2, 1, 0.1
+ *   nh               particles per smoothing length; hh = H / nh in eq. (mu)
+ *   eta_crit, eta_fold   limiter adjustment scales of eq. (phiad): 1/nh, 0.2/nh
+ *   a, adot          scale factor and its rate (a = 1, adot = 0 without expansion)
+ *   precision        a crk_precision value
+ */
+typedef struct {
+    double L, gamma, Cl, Cq, eps, nh, eta_crit, eta_fold, a, adot;
+    int32_t precision;
+    int32_t reserved;
+} crk_params;
+
+typedef struct crk_ctx crk_ctx;
+
+/* Fills *p with the defaults for a target neighbour count Nres: L = 1,
+ * gamma = 5/3, (Cl, Cq, eps) = (2, 1, 0.1), nh = (3 Nres / (4 pi))^(1/3)
+ * (n_h = 4 for N_res = 268, Sec. 3.6), eta_crit = 1/nh, eta_fold = 0.2/nh,
+ * a = 1, adot = 0, precision CRK_FP64. Host memory. */
+crk_status crk_params_default(crk_params *p, double Nres);
+
+/* Creates a context on HIP device `device` that enqueues on `hip_stream`
+ * (a hipStream_t; NULL = the null stream). *out receives the context. */
+crk_status crk_create(crk_ctx **out, int device, void *hip_stream);
+void crk_destroy(crk_ctx *ctx);
+const char *crk_last_error(const crk_ctx *ctx);
+
+/*
+ * S1: cell list and neighbour lists (chaining mesh, Sec. 3.3).
+ * In:  n particles, x, y, z in [0, L) and support radii H (original order).
+ *      cell_size <= 0 picks the cell side from the mean H.
+ * Out: perm[n] (device, int32): perm[k] = original index of sorted particle k.
+ *      *n_pairs (host, may be NULL): number of ordered pairs (i, j), j in N_s(i).
+ *      *n_cells (host, may be NULL): cells per dimension.
+ * The context keeps the sorted positions and H, the gather lists N_g and the
+ * pair lists N_s. Synchronises the stream. Errors: CRK_ERR_INVALID_ARG,
+ * CRK_ERR_NONFINITE, CRK_ERR_SUPPORT, CRK_ERR_WORKSPACE, CRK_ERR_HIP.
+ */
+crk_status crk_build_cells(crk_ctx *ctx, int64_t n, const double *x, const double *y,
+                           const double *z, const double *H, const crk_params *p,
+                           double cell_size, int32_t *perm, int64_t *n_pairs, int32_t *n_cells);
+
+/* Rebuilds the neighbour lists after a change of support radii with the
+ * particles' positions unchanged. H_sorted[n]: new H in sorted order. */
+crk_status crk_update_support(crk_ctx *ctx, const double *H_sorted, int64_t *n_pairs);
+
+/* Moves ncomp arrays of n doubles between orders using the last build's
+ * permutation: to_sorted != 0: dst[c][k] = src[c][perm[k]];
+ * to_sorted == 0: dst[c][perm[k]] = src[c][k]. src and dst must not overlap. */
+crk_status crk_permute(crk_ctx *ctx, const double *src, double *dst, int32_t ncomp,
+                       int32_t to_sorted);
+
+/*
+ * S2 + S4: volume, eq. (vol), and kernel moments (sorted order, FP64 out).
+ *   nsum[n] = n_i = sum_{j in N_g(i)} W(|d|, H_i) (self included),  V[n] = 1 / n_i
+ *   m0[n] = sum V_j W,  m1[3][n] = sum V_j d W,  m2[6][n] = sum V_j d d^T W
+ *   gm0[3][n], gm1[9][n], gm2[18][n]: their gradients in x_i with H_i and
+ *   every V_j held fixed (d d / d x_i = I).
+ * Any output pointer except V may be NULL when the call is only needed for the
+ * volumes. The context also keeps V for the later passes.
+ */
+crk_status crk_moments(crk_ctx *ctx, const crk_params *p, double *nsum, double *V, double *m0,
+                       double *m1, double *m2, double *gm0, double *gm1, double *gm2);
+
+/*
+ * S5: RK correction coefficients from the moments, always in FP64. With the
+ * constraints sum V W^R = 1 and sum V d W^R = 0 of eq. (RK):
+ *   B = -m2^{-1} m1,  A = 1 / (m0 + B.m1),
+ *   dB/dx^g = -m2^{-1} (dm1/dx^g + (dm2/dx^g) B),
+ *   dA/dx^g = -A^2 (dm0/dx^g + (dB/dx^g).m1 + B.dm1/dx^g).
+ * When det(m2) <= 1e-12 (tr(m2)/3)^3 the particle falls back to normalised
+ * SPH: A = 1/m0, B = 0, dA = -dm0/m0^2, dB = 0.
+ * Out: A[n], B[3][n], gA[3][n], gB[9][n]; *n_singular (host, may be NULL:
+ * then the call does not synchronise). Returns CRK_WARN_SINGULAR when
+ * n_singular is requested and positive.
+ */
+crk_status crk_corrections(crk_ctx *ctx, int64_t n, const double *m0, const double *m1,
+                           const double *m2, const double *gm0, const double *gm1,
+                           const double *gm2, double *A, double *B, double *gA, double *gB,
+                           int64_t *n_singular);
+
+/*
+ * S6 + S7: velocity gradient, then momentum and energy derivatives.
+ *   gradv[9][n]: grad v_i = - sum_{j in N_g(i)} V_j (v_i - v_j) (x) grad W^R_ij, eq. (gradv)
+ *   dpdt[3][n] : dp_i/dt = (1/m_i) sum_{j in N_s(i)} (a^2/2) V_i V_j (P_i+Q_i+P_j+Q_j)
+ *                (grad W^R_ji - grad W^R_ij), eq. (mom); p = a v, so this is dv/dt at a = 1
+ *   dudt[n]    : du_i/dt = (1/m_i) sum (1/(2a^2)) V_i V_j (P_j+Q_j) (xdot_j - xdot_i).
+ *                (grad W^R_ji - grad W^R_ij), eq. (eng), xdot = v / a
+ * with P = (gamma-1) rho u, Q from eqs. (visc), (mu) on the midpoint-projected
+ * velocities of eq. (hatvi) and the limiter of eqs. (phi)-(phiad).
+ * grad W^R_ij is eq. (gRK) with i's coefficients and H_i (zero for |d| >= H_i);
+ * grad W^R_ji is the same with j's coefficients, H_j and d -> -d.
+ * In: v[3][n] (peculiar velocity), m[n], u[n], rho[n] (NULL: rho = m / V), V[n],
+ *     A, B, gA, gB as returned by crk_corrections.
+ */
+crk_status crk_derivatives(crk_ctx *ctx, const crk_params *p, const double *v, const double *m,
+                           const double *u, const double *rho, const double *V, const double *A,
+                           const double *B, const double *gA, const double *gB, double *gradv,
+                           double *dpdt, double *dudt);
+
+/*
+ * S3: smoothing-length iteration, eqs. (hi), (thacker). For each particle on
+ * its own (its neighbour count depends only on its own H):
+ *   N = (4 pi/3) H^3 sum_j W(|d|, H),  Delta = (Nres / N)^(1/3),
+ *   lambda = 0.2 (1 + Delta^2) if Delta < 1 else 0.2 (1 + Delta^-3),
+ *   H <- H (1 - lambda + lambda Delta),
+ * until |H_new - H_old| <= tol H_old or max_iter updates.
+ * H_inout[n] (sorted order): start values in, converged values out.
+ * iters[n] (int32, may be NULL): updates taken. *n_unconverged (host, may be
+ * NULL). Uses the positions and cells of the last crk_build_cells; call
+ * crk_update_support afterwards to rebuild the lists for the new H.
+ * Errors: CRK_ERR_SUPPORT if an iterate reaches L/2; CRK_ERR_INVALID_ARG if
+ * Nres <= 20.625 (the self term alone gives N = (4 pi/3)(495/(32 pi))).
+ */
+crk_status crk_hsolve(crk_ctx *ctx, double Nres, double tol, int32_t max_iter, double *H_inout,
+                      int32_t *iters, int64_t *n_unconverged);
+
+/*
+ * Neighbour lists of the last build, for checking: which = 0 gives N_g
+ * (self included), which = 1 gives N_s. offsets[n+1] (device int64) and
+ * idx[cap] (device int32, SORTED-order indices). Rows are not ordered.
+ * *total (host) receives the number of entries; idx may be NULL to query it.
+ */
+crk_status crk_export_neighbors(crk_ctx *ctx, int32_t which, int64_t *offsets, int32_t *idx,
+                                int64_t cap, int64_t *total);
+
+/* Lanes per particle of the four pair passes (volume, moments, velocity
+ * gradient, derivatives): each particle's neighbour row is split over a
+ * group of g lanes of one wavefront, g a power of two in 1..64; 0 keeps the
+ * current value. Tuning only: results agree to rounding for every g. */
+crk_status crk_set_lanes(crk_ctx *ctx, int32_t g_vol, int32_t g_mom, int32_t g_grad,
+                         int32_t g_der);
+
+/* Per-kernel timing (off by default). While enabled, every kernel launch of
+ * the library is bracketed by a pair of HIP events recorded on the context's
+ * stream. crk_timing_read synchronises the stream and returns the summed
+ * event time (ms) and the launch count for one kernel name ("k_walk_count",
+ * "k_walk_fill", "k_volume", "k_moments", "k_corrections", "k_gradv",
+ * "k_pack", "k_deriv", "k_hsolve", "sort"); crk_timing_reset clears the sums. */
+crk_status crk_timing_enable(crk_ctx *ctx, int32_t on);
+crk_status crk_timing_reset(crk_ctx *ctx);
+crk_status crk_timing_read(crk_ctx *ctx, const char *kernel, double *total_ms, int64_t *launches);
+
+/* Library version string. */
+const char *crk_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CRK_H */

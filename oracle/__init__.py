@@ -46,6 +46,8 @@ def lib():
     if _lib is None:
         build()
         L = C.CDLL(_LIB)
+        L.orc_threads.restype = _int
+        L.orc_threads.argtypes = []
         L.orc_W.restype = _d
         L.orc_W.argtypes = [_d, _d]
         L.orc_dWdr.restype = _d
@@ -81,6 +83,11 @@ def _f64(a):
 
 def _ptr(a):
     return None if a is None else a.ctypes.data_as(_p)
+
+
+def threads() -> int:
+    """OpenMP threads the oracle's loops run on."""
+    return int(lib().orc_threads())
 
 
 # ---------------------------------------------------------------- kernel

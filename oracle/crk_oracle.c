@@ -35,11 +35,15 @@
  * Separations are d = x_i - x_j (minimum image in a periodic box).
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
 
 #define ORC_PI 3.14159265358979323846
+
+/* threads the OpenMP loops of this oracle use */
+int orc_threads(void) { return omp_get_max_threads(); }
 
 /* ------------------------------------------------------------------ */
 /* Kernel, eq. (C4): W = 495/(32 pi H^3) (1-q)^6 (1 + 6q + 35q^2/3),   */

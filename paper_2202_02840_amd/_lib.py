@@ -1,0 +1,256 @@
+"""ctypes binding of include/crk.h (argument marshalling only)."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIBPATH = os.path.join(_HERE, "libcrk.so")
+
+CRK_FP64, CRK_MIXED, CRK_MIXED_M64 = 0, 1, 2
+STATUS = {0: "CRK_OK", 1: "CRK_WARN_SINGULAR", 2: "CRK_WARN_NOT_CONVERGED",
+          -1: "CRK_ERR_INVALID_ARG", -2: "CRK_ERR_NONFINITE", -3: "CRK_ERR_SUPPORT",
+          -4: "CRK_ERR_WORKSPACE", -5: "CRK_ERR_HIP", -6: "CRK_ERR_STATE"}
+
+# every symbol include/crk.h declares
+EXPORTS = ("crk_params_default", "crk_create", "crk_destroy", "crk_last_error", "crk_build_cells",
+           "crk_update_support", "crk_permute", "crk_moments", "crk_corrections",
+           "crk_derivatives", "crk_hsolve", "crk_export_neighbors", "crk_set_lanes",
+           "crk_timing_enable", "crk_timing_reset", "crk_timing_read", "crk_version")
+
+
+class CrkError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Params(C.Structure):
+    _fields_ = [(k, C.c_double) for k in ("L", "gamma", "Cl", "Cq", "eps", "nh", "eta_crit",
+                                          "eta_fold", "a", "adot")] + \
+               [("precision", C.c_int32), ("reserved", C.c_int32)]
+
+    @classmethod
+    def default(cls, nres: float = 64.0, **over) -> "Params":
+        p = cls()
+        st = lib().crk_params_default(C.byref(p), C.c_double(nres))
+        if st != 0:
+            raise CrkError(st, "crk_params_default")
+        for k, v in over.items():
+            setattr(p, k, v)
+        return p
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+
+def library_path() -> str:
+    return _LIBPATH
+
+
+def lib():
+    """Load libcrk.so; raise if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIBPATH):
+            raise RuntimeError(f"{_LIBPATH} is missing: build it with paper_2202_02840_amd/build.py")
+        L = C.CDLL(_LIBPATH)
+        p, i64, i32, d = C.c_void_p, C.c_int64, C.c_int32, C.c_double
+        sigs = {
+            "crk_params_default": ([p, d], i32),
+            "crk_create": ([p, C.c_int, p], i32),
+            "crk_destroy": ([p], None),
+            "crk_last_error": ([p], C.c_char_p),
+            "crk_build_cells": ([p, i64, p, p, p, p, p, d, p, p, p], i32),
+            "crk_update_support": ([p, p, p], i32),
+            "crk_permute": ([p, p, p, i32, i32], i32),
+            "crk_moments": ([p, p] + [p] * 8, i32),
+            "crk_corrections": ([p, i64] + [p] * 11, i32),
+            "crk_derivatives": ([p, p] + [p] * 12, i32),
+            "crk_hsolve": ([p, d, d, i32, p, p, p], i32),
+            "crk_export_neighbors": ([p, i32, p, p, i64, p], i32),
+            "crk_set_lanes": ([p, i32, i32, i32, i32], i32),
+            "crk_timing_enable": ([p, i32], i32),
+            "crk_timing_reset": ([p], i32),
+            "crk_timing_read": ([p, C.c_char_p, p, p], i32),
+            "crk_version": ([], C.c_char_p),
+        }
+        for name, (args, res) in sigs.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+    return _lib
+
+
+def version() -> str:
+    return lib().crk_version().decode()
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("expected a torch tensor")
+    if not t.is_cuda:
+        raise ValueError("arrays must be device tensors")
+    if not t.is_contiguous():
+        raise ValueError("arrays must be contiguous")
+    return C.c_void_p(t.data_ptr())
+
+
+def _f64(*ts):
+    for t in ts:
+        if t is not None and t.dtype != torch.float64:
+            raise TypeError("boundary arrays are float64")
+
+
+class Context:
+    """One crk_ctx bound to a device and a HIP stream (torch's current stream
+    by default)."""
+
+    def __init__(self, device: int = 0, stream: torch.cuda.Stream | None = None):
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU: the CRKSPH library runs on the device only")
+        self.device = torch.device("cuda", device)
+        self.stream = stream or torch.cuda.current_stream(self.device)
+        h = C.c_void_p()
+        st = lib().crk_create(C.byref(h), device, C.c_void_p(self.stream.cuda_stream))
+        if st != 0:
+            raise CrkError(st, "crk_create")
+        self._h = h
+        self.n = 0
+        self.n_pairs = 0
+        self.n_cells = 0
+        self.perm = None
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().crk_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st: int, what: str, allow_warn: bool = True) -> int:
+        if st < 0 or (st > 0 and not allow_warn):
+            raise CrkError(st, f"{what}: {lib().crk_last_error(self._h).decode()}")
+        return st
+
+    def _empty(self, *shape, dtype=torch.float64):
+        return torch.empty(*shape, dtype=dtype, device=self.device)
+
+    # ---------------------------------------------------------------- S1
+    def build_cells(self, x, y, z, H, params: Params, cell_size: float = 0.0):
+        _f64(x, y, z, H)
+        n = x.shape[0]
+        perm = self._empty(n, dtype=torch.int32)
+        npairs = C.c_int64()
+        ncell = C.c_int32()
+        st = lib().crk_build_cells(self._h, n, _ptr(x), _ptr(y), _ptr(z), _ptr(H),
+                                   C.byref(params), C.c_double(cell_size), _ptr(perm),
+                                   C.byref(npairs), C.byref(ncell))
+        self._check(st, "crk_build_cells")
+        self.n, self.n_pairs, self.n_cells, self.perm = n, npairs.value, ncell.value, perm
+        return perm, npairs.value
+
+    def update_support(self, H_sorted):
+        _f64(H_sorted)
+        npairs = C.c_int64()
+        self._check(lib().crk_update_support(self._h, _ptr(H_sorted), C.byref(npairs)),
+                    "crk_update_support")
+        self.n_pairs = npairs.value
+        return npairs.value
+
+    def permute(self, src, to_sorted: bool):
+        _f64(src)
+        ncomp = 1 if src.dim() == 1 else src.shape[0]
+        dst = torch.empty_like(src)
+        self._check(lib().crk_permute(self._h, _ptr(src), _ptr(dst), ncomp, int(to_sorted)),
+                    "crk_permute")
+        return dst
+
+    # ---------------------------------------------------------------- S2 + S4
+    def moments(self, params: Params, want_moments: bool = True):
+        n = self.n
+        out = dict(nsum=self._empty(n), V=self._empty(n))
+        if want_moments:
+            out.update(m0=self._empty(n), m1=self._empty(3, n), m2=self._empty(6, n),
+                       gm0=self._empty(3, n), gm1=self._empty(9, n), gm2=self._empty(18, n))
+        keys = ("nsum", "V", "m0", "m1", "m2", "gm0", "gm1", "gm2")
+        st = lib().crk_moments(self._h, C.byref(params), *[_ptr(out.get(k)) for k in keys])
+        self._check(st, "crk_moments")
+        return out
+
+    # ---------------------------------------------------------------- S5
+    def corrections(self, mom: dict, count_singular: bool = True):
+        n = self.n
+        out = dict(A=self._empty(n), B=self._empty(3, n), gA=self._empty(3, n),
+                   gB=self._empty(9, n))
+        ns = C.c_int64(-1)
+        st = lib().crk_corrections(self._h, n, *[_ptr(mom[k]) for k in
+                                                 ("m0", "m1", "m2", "gm0", "gm1", "gm2")],
+                                   *[_ptr(out[k]) for k in ("A", "B", "gA", "gB")],
+                                   C.byref(ns) if count_singular else None)
+        self._check(st, "crk_corrections")
+        out["n_singular"] = ns.value
+        return out
+
+    # ---------------------------------------------------------------- S6 + S7
+    def derivatives(self, params: Params, v, m, u, rho, V, corr: dict):
+        _f64(v, m, u, rho, V)
+        n = self.n
+        out = dict(gradv=self._empty(9, n), dpdt=self._empty(3, n), dudt=self._empty(n))
+        st = lib().crk_derivatives(self._h, C.byref(params), _ptr(v), _ptr(m), _ptr(u), _ptr(rho),
+                                   _ptr(V), *[_ptr(corr[k]) for k in ("A", "B", "gA", "gB")],
+                                   _ptr(out["gradv"]), _ptr(out["dpdt"]), _ptr(out["dudt"]))
+        self._check(st, "crk_derivatives")
+        return out
+
+    # ---------------------------------------------------------------- S3
+    def hsolve(self, Nres: float, H_sorted, tol: float = 1e-7, max_iter: int = 100):
+        _f64(H_sorted)
+        Hio = H_sorted.clone()
+        iters = self._empty(self.n, dtype=torch.int32)
+        nun = C.c_int64()
+        st = lib().crk_hsolve(self._h, C.c_double(Nres), C.c_double(tol), max_iter, _ptr(Hio),
+                              _ptr(iters), C.byref(nun))
+        self._check(st, "crk_hsolve")
+        return Hio, iters, nun.value
+
+    # ---------------------------------------------------------------- checks / tuning
+    def export_neighbors(self, which: int):
+        n = self.n
+        off = self._empty(n + 1, dtype=torch.int64)
+        tot = C.c_int64()
+        self._check(lib().crk_export_neighbors(self._h, which, _ptr(off), None, 0, C.byref(tot)),
+                    "crk_export_neighbors")
+        idx = self._empty(max(tot.value, 1), dtype=torch.int32)
+        self._check(lib().crk_export_neighbors(self._h, which, _ptr(off), _ptr(idx), tot.value,
+                                               C.byref(tot)), "crk_export_neighbors")
+        return off, idx[:tot.value]
+
+    def timing(self, on: bool):
+        self._check(lib().crk_timing_enable(self._h, int(on)), "crk_timing_enable")
+
+    def timing_reset(self):
+        self._check(lib().crk_timing_reset(self._h), "crk_timing_reset")
+
+    def timing_read(self, kernel: str):
+        """(summed event time in ms, launches) of one kernel name."""
+        ms = C.c_double()
+        cnt = C.c_int64()
+        self._check(lib().crk_timing_read(self._h, kernel.encode(), C.byref(ms), C.byref(cnt)),
+                    "crk_timing_read")
+        return ms.value, cnt.value
+
+    def set_lanes(self, vol: int = 0, mom: int = 0, grad: int = 0, der: int = 0):
+        self._check(lib().crk_set_lanes(self._h, vol, mom, grad, der), "crk_set_lanes")

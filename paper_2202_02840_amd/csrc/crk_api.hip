@@ -1,0 +1,196 @@
+// Context, errors, workspace and parameter defaults of the C ABI.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+
+#include <new>
+
+#include "crk_internal.h"
+
+namespace crk {
+
+crk_status set_err(crk_ctx *c, crk_status s, const char *fmt, ...) {
+    if (c) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof buf, fmt, ap);
+        va_end(ap);
+        c->err = buf;
+    }
+    return s;
+}
+
+crk_status hip_err(crk_ctx *c, hipError_t e, const char *what) {
+    return set_err(c, CRK_ERR_HIP, "%s failed: %s", what, hipGetErrorString(e));
+}
+
+crk_status ensure(crk_ctx *c, Buf &b, size_t bytes) {
+    if (bytes == 0) bytes = 256;
+    if (b.bytes >= bytes) return CRK_OK;
+    if (b.p) {
+        hipError_t e = hipStreamSynchronize(c->stream);
+        if (e != hipSuccess) return hip_err(c, e, "hipStreamSynchronize");
+        hipFree(b.p);
+        b.p = nullptr;
+        b.bytes = 0;
+    }
+    size_t want = bytes + bytes / 8;          // headroom against regrowth
+    hipError_t e = hipMalloc(&b.p, want);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return set_err(c, CRK_ERR_WORKSPACE, "workspace allocation of %zu bytes failed: %s", want,
+                       hipGetErrorString(e));
+    }
+    b.bytes = want;
+    return CRK_OK;
+}
+
+static hipEvent_t pool_get(crk_ctx *c) {
+    if (!c->ev_pool.empty()) {
+        hipEvent_t e = c->ev_pool.back();
+        c->ev_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    return e;
+}
+
+KTimer::KTimer(crk_ctx *ctx, const char *nm) : c(ctx), name(nm) {
+    if (!c->timing) return;
+    a = pool_get(c);
+    b = pool_get(c);
+    if (a && b) hipEventRecord(a, c->stream);
+}
+
+KTimer::~KTimer() {
+    if (!a || !b) return;
+    hipEventRecord(b, c->stream);
+    c->ev_pend.push_back({name, {a, b}});
+}
+
+static crk_status timing_flush(crk_ctx *c) {
+    if (c->ev_pend.empty()) return CRK_OK;
+    CRK_HIP(c, hipStreamSynchronize(c->stream));
+    for (auto &p : c->ev_pend) {
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, p.second.first, p.second.second) == hipSuccess) {
+            auto &t = c->ev_total[p.first];
+            t.first += ms;
+            t.second += 1;
+        } else {
+            (void)hipGetLastError();
+        }
+        c->ev_pool.push_back(p.second.first);
+        c->ev_pool.push_back(p.second.second);
+    }
+    c->ev_pend.clear();
+    return CRK_OK;
+}
+
+}  // namespace crk
+
+extern "C" {
+
+crk_status crk_timing_enable(crk_ctx *c, int32_t on) {
+    if (!c) return CRK_ERR_INVALID_ARG;
+    CRK_TRY(crk::timing_flush(c));
+    c->timing = on ? 1 : 0;
+    return CRK_OK;
+}
+
+crk_status crk_timing_reset(crk_ctx *c) {
+    if (!c) return CRK_ERR_INVALID_ARG;
+    CRK_TRY(crk::timing_flush(c));
+    c->ev_total.clear();
+    return CRK_OK;
+}
+
+crk_status crk_timing_read(crk_ctx *c, const char *kernel, double *total_ms, int64_t *launches) {
+    if (!c || !kernel || !total_ms || !launches) return CRK_ERR_INVALID_ARG;
+    CRK_TRY(crk::timing_flush(c));
+    auto it = c->ev_total.find(kernel);
+    if (it == c->ev_total.end()) {
+        *total_ms = 0.0;
+        *launches = 0;
+    } else {
+        *total_ms = it->second.first;
+        *launches = it->second.second;
+    }
+    return CRK_OK;
+}
+
+const char *crk_version(void) { return "crk-mi355x 0.1 (gfx950)"; }
+
+crk_status crk_params_default(crk_params *p, double Nres) {
+    if (!p || !(Nres > 0.0)) return CRK_ERR_INVALID_ARG;
+    double nh = cbrt(3.0 * Nres / (4.0 * crk::kPi));
+    p->L = 1.0;
+    p->gamma = 5.0 / 3.0;
+    p->Cl = 2.0;
+    p->Cq = 1.0;
+    p->eps = 0.1;
+    p->nh = nh;
+    p->eta_crit = 1.0 / nh;
+    p->eta_fold = 0.2 / nh;
+    p->a = 1.0;
+    p->adot = 0.0;
+    p->precision = CRK_FP64;
+    p->reserved = 0;
+    return CRK_OK;
+}
+
+crk_status crk_create(crk_ctx **out, int device, void *hip_stream) {
+    if (!out) return CRK_ERR_INVALID_ARG;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) {
+        (void)hipGetLastError();
+        return CRK_ERR_HIP;
+    }
+    if (device < 0 || device >= ndev) return CRK_ERR_INVALID_ARG;
+    crk_ctx *c = new (std::nothrow) crk_ctx();
+    if (!c) return CRK_ERR_WORKSPACE;
+    c->device = device;
+    c->stream = (hipStream_t)hip_stream;
+    if (hipSetDevice(device) != hipSuccess) {
+        delete c;
+        return CRK_ERR_HIP;
+    }
+    void *pin = nullptr;
+    if (hipHostMalloc(&pin, 4096, hipHostMallocDefault) != hipSuccess) {
+        delete c;
+        return CRK_ERR_WORKSPACE;
+    }
+    c->pinned.p = pin;
+    c->pinned.bytes = 4096;
+    *out = c;
+    return CRK_OK;
+}
+
+void crk_destroy(crk_ctx *c) {
+    if (!c) return;
+    hipSetDevice(c->device);
+    hipStreamSynchronize(c->stream);
+    crk::Buf *all[] = {&c->posH, &c->perm,  &c->cbeg,  &c->cend, &c->goff, &c->gidx, &c->ng,
+                       &c->nes,  &c->esoff, &c->eb,    &c->ee,   &c->ekey, &c->eidx, &c->keyA,
+                       &c->keyB, &c->valA,  &c->valB,  &c->hist, &c->scanTmp, &c->recV,
+                       &c->rec6, &c->rec7,  &c->red,   &c->misc};
+    for (crk::Buf *b : all)
+        if (b->p) hipFree(b->p);
+    if (c->pinned.p) hipHostFree(c->pinned.p);
+    for (auto &p : c->ev_pend) {
+        hipEventDestroy(p.second.first);
+        hipEventDestroy(p.second.second);
+    }
+    for (hipEvent_t e : c->ev_pool) hipEventDestroy(e);
+    delete c;
+}
+
+const char *crk_last_error(const crk_ctx *c) { return c ? c->err.c_str() : "null context"; }
+
+}  // extern "C"

@@ -1,0 +1,475 @@
+// S1: cell list and neighbour lists (the chaining mesh of Sec. 3.3 with one
+// interaction list per step that every later pass reuses).
+//
+// 1. validate + reduce H (deterministic two-level reduction)
+// 2. key = Morton code of the particle's cell; stable radix sort -> perm
+// 3. gather sorted x, y, z, H into one double4 per particle; cell ranges
+// 4. count: one thread per particle walks the cells of the hierarchy level
+//    matched to its support and counts j with r^2 < H_i^2 (the gather set,
+//    self excluded), and among them the j with r^2 >= H_j^2: j reaches i
+//    only through i's larger support, so the pair is an "extra" of j.
+// 5. exclusive scans of both counts give every particle its output slots
+// 6. fill with the same walk: gather rows in walk order, extras as (j, i)
+//    pairs grouped by i; a stable radix sort on j then makes each extras row
+//    ascending in i. No atomics decide an order, so the lists (and every
+//    sum over them) are the same bit for bit from run to run.
+#include <math.h>
+
+#include <algorithm>
+
+#include "crk_internal.h"
+
+namespace crk {
+namespace {
+
+__global__ __launch_bounds__(kBlock) void k_validate(const double *x, const double *y,
+                                                     const double *z, const double *H, int64_t n,
+                                                     double L, double *part /* [nblk][3] */,
+                                                     int *flags /* [3] */) {
+    __shared__ double smax[kBlock], smin[kBlock], ssum[kBlock];
+    double hmax = 0.0, hmin = INFINITY, hsum = 0.0;
+    int nf = 0, rg = 0, bh = 0;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kBlock) {
+        double a = x[i], b = y[i], c = z[i], h = H[i];
+        if (!isfinite(a) || !isfinite(b) || !isfinite(c) || !isfinite(h)) {
+            nf = 1;
+            continue;
+        }
+        if (a < 0.0 || a >= L || b < 0.0 || b >= L || c < 0.0 || c >= L) rg = 1;
+        if (!(h > 0.0)) bh = 1;
+        hmax = fmax(hmax, h);
+        hmin = fmin(hmin, h);
+        hsum += h;
+    }
+    smax[threadIdx.x] = hmax;
+    smin[threadIdx.x] = hmin;
+    ssum[threadIdx.x] = hsum;
+    __syncthreads();
+    for (int s = kBlock / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) {
+            smax[threadIdx.x] = fmax(smax[threadIdx.x], smax[threadIdx.x + s]);
+            smin[threadIdx.x] = fmin(smin[threadIdx.x], smin[threadIdx.x + s]);
+            ssum[threadIdx.x] += ssum[threadIdx.x + s];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        part[blockIdx.x * 3 + 0] = smax[0];
+        part[blockIdx.x * 3 + 1] = smin[0];
+        part[blockIdx.x * 3 + 2] = ssum[0];
+    }
+    if (nf) atomicOr(&flags[0], 1);
+    if (rg) atomicOr(&flags[1], 1);
+    if (bh) atomicOr(&flags[2], 1);
+}
+
+// fixed-order final reduction of the block partials (one thread)
+__global__ void k_validate_final(const double *part, int nblk, double *out) {
+    double hmax = 0.0, hmin = INFINITY, hsum = 0.0;
+    for (int b = 0; b < nblk; b++) {
+        hmax = fmax(hmax, part[b * 3 + 0]);
+        hmin = fmin(hmin, part[b * 3 + 1]);
+        hsum += part[b * 3 + 2];
+    }
+    out[0] = hmax;
+    out[1] = hmin;
+    out[2] = hsum;
+}
+
+__device__ __forceinline__ int cell_of(double x, double inv_c, int nc) {
+    int k = (int)floor(x * inv_c);
+    return k < 0 ? 0 : (k >= nc ? nc - 1 : k);
+}
+
+__global__ __launch_bounds__(kBlock) void k_keys(const double *x, const double *y, const double *z,
+                                                 int64_t n, double inv_c, int nc, uint32_t *key,
+                                                 int32_t *val) {
+    int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    key[i] = morton3(cell_of(x[i], inv_c, nc), cell_of(y[i], inv_c, nc), cell_of(z[i], inv_c, nc));
+    val[i] = (int32_t)i;
+}
+
+__global__ __launch_bounds__(kBlock) void k_gather_sorted(const double *x, const double *y,
+                                                          const double *z, const double *H,
+                                                          const int32_t *perm, int64_t n,
+                                                          double4 *posH) {
+    int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (k >= n) return;
+    int32_t i = perm[k];
+    posH[k] = make_double4(x[i], y[i], z[i], H[i]);
+}
+
+__global__ __launch_bounds__(kBlock) void k_fill_i32(int32_t *a, int64_t n, int32_t v) {
+    int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) a[i] = v;
+}
+
+// sorted-index range of every cell of every level (a level-k cell is the set
+// of particles whose fine Morton code shifted right by 3k is its id)
+__global__ __launch_bounds__(kBlock) void k_tables(const uint32_t *skey, int64_t n, Levels v,
+                                                   int32_t *cbeg, int32_t *cend) {
+    int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (k >= n) return;
+    uint32_t key = skey[k];
+    uint32_t prev = k > 0 ? skey[k - 1] : 0u, next = k + 1 < n ? skey[k + 1] : 0u;
+    for (int l = 0; l <= v.bits; l++) {
+        uint32_t id = key >> (3 * l);
+        if (k == 0 || (prev >> (3 * l)) != id) cbeg[v.off[l] + id] = (int32_t)k;
+        if (k == n - 1 || (next >> (3 * l)) != id) cend[v.off[l] + id] = (int32_t)(k + 1);
+    }
+}
+
+// Gather walk of particle i: every j != i with r^2 < H_i^2, in cell-walk
+// order. Such a pair is also an "extra" of j when r^2 >= H_j^2 (j's own
+// support does not reach i, but the pair is in N_s(j) through H_i).
+// MODE 0 counts both kinds per i; MODE 1 writes the gather row of i and the
+// (j, i) extras that i emits, at offsets from the scans of the counts.
+template <int MODE>
+__global__ __launch_bounds__(kBlock) void k_walk(const double4 *__restrict__ posH, int64_t n, Levels v,
+                                                 const int32_t *__restrict__ cbeg,
+                                                 const int32_t *__restrict__ cend, int32_t *ng,
+                                                 int32_t *nes, const int64_t *__restrict__ goff,
+                                                 int32_t *gidx, const int64_t *__restrict__ esoff,
+                                                 uint32_t *ekey, int32_t *eval) {
+    int64_t i = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const double4 pi = posH[i];
+    const double H2 = pi.w * pi.w;
+    int32_t cg = 0, ce = 0;
+    int64_t gw = MODE ? goff[i] : 0, ew = MODE ? esoff[i] : 0;
+    walk_cells(v, cbeg, cend, pi.x, pi.y, pi.z, pi.w, [&](int j) {
+        double4 pj = posH[j];
+        double dx = min_image(pi.x - pj.x, v.L, v.hL);
+        double dy = min_image(pi.y - pj.y, v.L, v.hL);
+        double dz = min_image(pi.z - pj.z, v.L, v.hL);
+        double r2 = r2_exact(dx, dy, dz);
+        if (r2 < H2 && j != i) {
+            bool extra = !(r2 < pj.w * pj.w);
+            if (MODE == 1) {
+                gidx[gw + cg] = j;
+                if (extra) {
+                    ekey[ew + ce] = (uint32_t)j;
+                    eval[ew + ce] = (int32_t)i;
+                }
+            }
+            cg++;
+            ce += extra ? 1 : 0;
+        }
+    });
+    if (MODE == 0) {
+        ng[i] = cg;
+        nes[i] = ce;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_to_i64(const int32_t *a, int64_t n, int64_t *o) {
+    int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) o[i] = a[i];
+    if (i == n) o[n] = 0;
+}
+
+// extras rows: the sorted keys are the receiving particles j
+__global__ __launch_bounds__(kBlock) void k_extra_ranges(const uint32_t *ekey, int64_t E, int32_t *eb,
+                                                         int32_t *ee) {
+    int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (k >= E) return;
+    uint32_t j = ekey[k];
+    if (k == 0 || ekey[k - 1] != j) eb[j] = (int32_t)k;
+    if (k == E - 1 || ekey[k + 1] != j) ee[j] = (int32_t)(k + 1);
+}
+
+__global__ __launch_bounds__(kBlock) void k_sum_i32(const int32_t *a, int64_t n, int64_t *out) {
+    __shared__ int64_t s[kBlock];
+    int64_t acc = 0;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
+        acc += a[i];
+    s[threadIdx.x] = acc;
+    __syncthreads();
+    for (int k = kBlock / 2; k > 0; k >>= 1) {
+        if (threadIdx.x < k) s[threadIdx.x] += s[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) atomicAdd((unsigned long long *)out, (unsigned long long)s[0]);
+}
+
+__global__ __launch_bounds__(kBlock) void k_set_H(double4 *posH, const double *H, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) posH[i].w = H[i];
+}
+
+__global__ __launch_bounds__(kBlock) void k_get_xyz(const double4 *posH, int64_t n, double *x,
+                                                    double *y, double *z) {
+    int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    double4 p = posH[i];
+    x[i] = p.x;
+    y[i] = p.y;
+    z[i] = p.z;
+}
+
+__global__ __launch_bounds__(kBlock) void k_permute(const int32_t *perm, const double *src,
+                                                    double *dst, int64_t n, int ncomp, int to_sorted) {
+    int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (k >= n) return;
+    int64_t o = perm[k];
+    for (int c = 0; c < ncomp; c++) {
+        if (to_sorted) dst[c * n + k] = src[c * n + o];
+        else dst[c * n + o] = src[c * n + k];
+    }
+}
+
+// row lengths of the exported sets: which 0 -> N_g (self + gather row),
+// which 1 -> N_s (gather row + extras row)
+__global__ __launch_bounds__(kBlock) void k_export_len(const int64_t *goff, const int32_t *eb,
+                                                       const int32_t *ee, int64_t n, int which,
+                                                       int64_t *len) {
+    int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) len[i] = (goff[i + 1] - goff[i]) + (which == 0 ? 1 : (int64_t)(ee[i] - eb[i]));
+    if (i == n) len[n] = 0;
+}
+
+__global__ __launch_bounds__(kBlock) void k_export_fill(const int64_t *goff, const int32_t *gidx,
+                                                        const int32_t *eb, const int32_t *ee,
+                                                        const int32_t *eidx, int64_t n, int which,
+                                                        const int64_t *off, int32_t *idx) {
+    int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    int64_t o = off[i];
+    if (which == 0) idx[o++] = (int32_t)i;
+    for (int64_t k = goff[i]; k < goff[i + 1]; k++) idx[o++] = gidx[k];
+    if (which == 1)
+        for (int k = eb[i]; k < ee[i]; k++) idx[o++] = eidx[k];
+}
+
+inline unsigned nblocks(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+
+}  // namespace
+
+static Levels levels_of(const crk_ctx *c) {
+    Levels v;
+    v.L = c->L;
+    v.hL = 0.5 * c->L;
+    v.c0 = c->cell;
+    v.margin = 1e-9 * c->L;
+    v.bits = c->bits;
+    for (int k = 0; k < 12; k++) v.off[k] = c->lvl_off[k];
+    return v;
+}
+
+// Neighbour lists for the current posH / cell tables.
+static crk_status build_lists(crk_ctx *c) {
+    int64_t n = c->n;
+    Levels v = levels_of(c);
+    CRK_TRY(ensure(c, c->ng, (size_t)n * sizeof(int32_t)));
+    CRK_TRY(ensure(c, c->nes, (size_t)n * sizeof(int32_t)));
+    CRK_TRY(ensure(c, c->goff, (size_t)(n + 1) * sizeof(int64_t)));
+    CRK_TRY(ensure(c, c->esoff, (size_t)(n + 1) * sizeof(int64_t)));
+    int32_t *ng = (int32_t *)c->ng.p, *nes = (int32_t *)c->nes.p;
+    int64_t *goff = (int64_t *)c->goff.p, *esoff = (int64_t *)c->esoff.p;
+    const double4 *posH = (const double4 *)c->posH.p;
+    const int32_t *cbeg = (const int32_t *)c->cbeg.p, *cend = (const int32_t *)c->cend.p;
+    {
+        KTimer kt_(c, "k_walk_count");
+        k_walk<0><<<nblocks(n), kBlock, 0, c->stream>>>(posH, n, v, cbeg, cend, ng, nes, nullptr,
+                                                         nullptr, nullptr, nullptr, nullptr);
+    }
+    CRK_HIP(c, hipGetLastError());
+    k_to_i64<<<nblocks(n + 1), kBlock, 0, c->stream>>>(ng, n, goff);
+    k_to_i64<<<nblocks(n + 1), kBlock, 0, c->stream>>>(nes, n, esoff);
+    CRK_TRY(scan_exclusive_i64(c, goff, goff, n + 1));
+    CRK_TRY(scan_exclusive_i64(c, esoff, esoff, n + 1));
+    int64_t *pin = (int64_t *)c->pinned.p;
+    CRK_HIP(c, hipMemcpyAsync(pin, goff + n, sizeof(int64_t), hipMemcpyDeviceToHost, c->stream));
+    CRK_HIP(c, hipMemcpyAsync(pin + 1, esoff + n, sizeof(int64_t), hipMemcpyDeviceToHost, c->stream));
+    CRK_HIP(c, hipStreamSynchronize(c->stream));
+    int64_t G = pin[0], E = pin[1];
+    if (E > INT32_MAX - 1) return set_err(c, CRK_ERR_INVALID_ARG, "more than 2^31 extra pairs");
+    CRK_TRY(ensure(c, c->gidx, (size_t)(G > 0 ? G : 1) * sizeof(int32_t)));
+    CRK_TRY(ensure(c, c->ekey, (size_t)(E > 0 ? E : 1) * sizeof(uint32_t)));
+    CRK_TRY(ensure(c, c->eidx, (size_t)(E > 0 ? E : 1) * sizeof(int32_t)));
+    CRK_TRY(ensure(c, c->eb, (size_t)n * sizeof(int32_t)));
+    CRK_TRY(ensure(c, c->ee, (size_t)n * sizeof(int32_t)));
+    uint32_t *ekey = (uint32_t *)c->ekey.p;
+    int32_t *eidx = (int32_t *)c->eidx.p;
+    {
+        KTimer kt_(c, "k_walk_fill");
+        k_walk<1><<<nblocks(n), kBlock, 0, c->stream>>>(posH, n, v, cbeg, cend, ng, nes, goff,
+                                                         (int32_t *)c->gidx.p, esoff, ekey, eidx);
+    }
+    CRK_HIP(c, hipGetLastError());
+    // extras arrive grouped by the emitting particle i (ascending); a stable
+    // sort on the receiving particle j keeps them ascending in i per row
+    int ebits = 0;
+    while (((int64_t)1 << ebits) < n) ebits++;
+    {
+        KTimer kt_(c, "k_sort_extras");
+        CRK_TRY(radix_sort_pairs(c, ekey, eidx, E, ebits));
+    }
+    k_fill_i32<<<nblocks(n), kBlock, 0, c->stream>>>((int32_t *)c->eb.p, n, 0);
+    k_fill_i32<<<nblocks(n), kBlock, 0, c->stream>>>((int32_t *)c->ee.p, n, 0);
+    if (E > 0)
+        k_extra_ranges<<<nblocks(E), kBlock, 0, c->stream>>>(ekey, E, (int32_t *)c->eb.p,
+                                                              (int32_t *)c->ee.p);
+    CRK_HIP(c, hipGetLastError());
+    c->ngather = G;
+    c->nextra = E;
+    c->npairs = G + E;
+    c->built = 1;
+    c->have_V = 0;
+    return CRK_OK;
+}
+
+}  // namespace crk
+
+using namespace crk;
+
+extern "C" {
+
+crk_status crk_build_cells(crk_ctx *c, int64_t n, const double *x, const double *y, const double *z,
+                           const double *H, const crk_params *p, double cell_size, int32_t *perm,
+                           int64_t *n_pairs, int32_t *n_cells) {
+    if (!c) return CRK_ERR_INVALID_ARG;
+    if (n < 1 || !x || !y || !z || !H || !p || !perm)
+        return set_err(c, CRK_ERR_INVALID_ARG, "crk_build_cells: n < 1 or NULL argument");
+    if (n > INT32_MAX / 2) return set_err(c, CRK_ERR_INVALID_ARG, "n too large");
+    if (!(p->L > 0.0)) return set_err(c, CRK_ERR_INVALID_ARG, "L must be positive");
+    CRK_HIP(c, hipSetDevice(c->device));
+    c->built = 0;
+    c->have_V = 0;
+    c->nc = 0;
+    c->n = n;
+    c->L = p->L;
+    // 1. validate and reduce H
+    int nblk = (int)std::min<int64_t>((n + kBlock - 1) / kBlock, 1024);
+    CRK_TRY(ensure(c, c->red, (size_t)nblk * 3 * sizeof(double) + 64));
+    double *part = (double *)c->red.p;
+    int *flags = (int *)(part + (size_t)nblk * 3);
+    CRK_TRY(ensure(c, c->misc, 256));
+    double *res = (double *)c->misc.p;
+    CRK_HIP(c, hipMemsetAsync(flags, 0, 3 * sizeof(int), c->stream));
+    k_validate<<<nblk, kBlock, 0, c->stream>>>(x, y, z, H, n, p->L, part, flags);
+    k_validate_final<<<1, 1, 0, c->stream>>>(part, nblk, res);
+    CRK_HIP(c, hipGetLastError());
+    double *pin = (double *)c->pinned.p;
+    CRK_HIP(c, hipMemcpyAsync(pin, res, 3 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    CRK_HIP(c, hipMemcpyAsync(pin + 3, flags, 3 * sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    CRK_HIP(c, hipStreamSynchronize(c->stream));
+    double hmax = pin[0], hmin = pin[1];
+    int *hf = (int *)(pin + 3);
+    if (hf[0]) return set_err(c, CRK_ERR_NONFINITE, "non-finite position or H");
+    if (hf[1]) return set_err(c, CRK_ERR_INVALID_ARG, "position outside [0, L)");
+    if (hf[2] || !(hmin > 0.0)) return set_err(c, CRK_ERR_SUPPORT, "H must be positive");
+    if (!(hmax < 0.5 * p->L)) return set_err(c, CRK_ERR_SUPPORT, "max H %g >= L/2", hmax);
+    // 2. Morton cell hierarchy: finest side near half the smallest support
+    //    (or the requested side), at most 256 cells a side
+    double cfine = cell_size > 0.0 ? cell_size : 0.5 * hmin;
+    int bits = 0;
+    while (bits < 8 && p->L / (double)(1 << bits) > cfine) bits++;
+    c->bits = bits;
+    c->nc = 1 << bits;
+    c->cell = p->L / c->nc;
+    int64_t off = 0;
+    for (int k = 0; k <= bits; k++) {
+        c->lvl_off[k] = off;
+        int64_t m = (int64_t)1 << (bits - k);
+        off += m * m * m;
+    }
+    c->ntab = off;
+    CRK_TRY(ensure(c, c->keyA, (size_t)n * sizeof(uint32_t)));
+    CRK_TRY(ensure(c, c->perm, (size_t)n * sizeof(int32_t)));
+    uint32_t *key = (uint32_t *)c->keyA.p;
+    int32_t *pm = (int32_t *)c->perm.p;
+    k_keys<<<nblocks(n), kBlock, 0, c->stream>>>(x, y, z, n, 1.0 / c->cell, c->nc, key, pm);
+    CRK_HIP(c, hipGetLastError());
+    {
+        KTimer kt_(c, "sort");
+        CRK_TRY(radix_sort_pairs(c, key, pm, n, 3 * bits));
+    }
+    // 3. sorted particles and the cell tables of every level
+    CRK_TRY(ensure(c, c->posH, (size_t)n * sizeof(double4)));
+    CRK_TRY(ensure(c, c->cbeg, (size_t)c->ntab * sizeof(int32_t)));
+    CRK_TRY(ensure(c, c->cend, (size_t)c->ntab * sizeof(int32_t)));
+    k_gather_sorted<<<nblocks(n), kBlock, 0, c->stream>>>(x, y, z, H, pm, n, (double4 *)c->posH.p);
+    k_fill_i32<<<nblocks(c->ntab), kBlock, 0, c->stream>>>((int32_t *)c->cbeg.p, c->ntab, 0);
+    k_fill_i32<<<nblocks(c->ntab), kBlock, 0, c->stream>>>((int32_t *)c->cend.p, c->ntab, 0);
+    k_tables<<<nblocks(n), kBlock, 0, c->stream>>>(key, n, levels_of(c), (int32_t *)c->cbeg.p,
+                                                    (int32_t *)c->cend.p);
+    CRK_HIP(c, hipGetLastError());
+    CRK_HIP(c, hipMemcpyAsync(perm, pm, (size_t)n * sizeof(int32_t), hipMemcpyDeviceToDevice, c->stream));
+    // 4. neighbour lists
+    CRK_TRY(build_lists(c));
+    if (n_pairs) *n_pairs = c->npairs;
+    if (n_cells) *n_cells = c->nc;
+    return CRK_OK;
+}
+
+crk_status crk_update_support(crk_ctx *c, const double *H_sorted, int64_t *n_pairs) {
+    if (!c) return CRK_ERR_INVALID_ARG;
+    if (!H_sorted) return set_err(c, CRK_ERR_INVALID_ARG, "H_sorted is NULL");
+    if (c->nc == 0) return set_err(c, CRK_ERR_STATE, "crk_build_cells has not run");
+    CRK_HIP(c, hipSetDevice(c->device));
+    int64_t n = c->n;
+    CRK_TRY(ensure(c, c->scanTmp, (size_t)n * 3 * sizeof(double)));
+    double *xs = (double *)c->scanTmp.p;
+    k_get_xyz<<<nblocks(n), kBlock, 0, c->stream>>>((const double4 *)c->posH.p, n, xs, xs + n,
+                                                     xs + 2 * n);
+    int nblk = (int)std::min<int64_t>((n + kBlock - 1) / kBlock, 1024);
+    CRK_TRY(ensure(c, c->red, (size_t)nblk * 3 * sizeof(double) + 64));
+    double *part = (double *)c->red.p;
+    int *flags = (int *)(part + (size_t)nblk * 3);
+    double *res = (double *)c->misc.p;
+    CRK_HIP(c, hipMemsetAsync(flags, 0, 3 * sizeof(int), c->stream));
+    k_validate<<<nblk, kBlock, 0, c->stream>>>(xs, xs + n, xs + 2 * n, H_sorted, n, c->L, part, flags);
+    k_validate_final<<<1, 1, 0, c->stream>>>(part, nblk, res);
+    double *pin = (double *)c->pinned.p;
+    CRK_HIP(c, hipMemcpyAsync(pin, res, 3 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    CRK_HIP(c, hipMemcpyAsync(pin + 3, flags, 3 * sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    CRK_HIP(c, hipStreamSynchronize(c->stream));
+    int *hf = (int *)(pin + 3);
+    if (hf[0]) return set_err(c, CRK_ERR_NONFINITE, "non-finite H");
+    if (hf[2] || !(pin[1] > 0.0)) return set_err(c, CRK_ERR_SUPPORT, "H must be positive");
+    if (!(pin[0] < 0.5 * c->L)) return set_err(c, CRK_ERR_SUPPORT, "max H %g >= L/2", pin[0]);
+    k_set_H<<<nblocks(n), kBlock, 0, c->stream>>>((double4 *)c->posH.p, H_sorted, n);
+    CRK_TRY(build_lists(c));
+    if (n_pairs) *n_pairs = c->npairs;
+    return CRK_OK;
+}
+
+crk_status crk_permute(crk_ctx *c, const double *src, double *dst, int32_t ncomp, int32_t to_sorted) {
+    if (!c) return CRK_ERR_INVALID_ARG;
+    if (!src || !dst || ncomp < 1) return set_err(c, CRK_ERR_INVALID_ARG, "crk_permute: bad argument");
+    if (c->nc == 0) return set_err(c, CRK_ERR_STATE, "crk_build_cells has not run");
+    CRK_HIP(c, hipSetDevice(c->device));
+    k_permute<<<nblocks(c->n), kBlock, 0, c->stream>>>((const int32_t *)c->perm.p, src, dst, c->n,
+                                                        ncomp, to_sorted);
+    CRK_HIP(c, hipGetLastError());
+    return CRK_OK;
+}
+
+crk_status crk_export_neighbors(crk_ctx *c, int32_t which, int64_t *offsets, int32_t *idx,
+                                int64_t cap, int64_t *total) {
+    if (!c) return CRK_ERR_INVALID_ARG;
+    if (!c->built) return set_err(c, CRK_ERR_STATE, "no neighbour lists");
+    if (!offsets || !total || (which != 0 && which != 1))
+        return set_err(c, CRK_ERR_INVALID_ARG, "crk_export_neighbors: bad argument");
+    CRK_HIP(c, hipSetDevice(c->device));
+    int64_t n = c->n;
+    *total = which == 0 ? c->ngather + n : c->npairs;
+    k_export_len<<<nblocks(n + 1), kBlock, 0, c->stream>>>((const int64_t *)c->goff.p,
+                                                            (const int32_t *)c->eb.p,
+                                                            (const int32_t *)c->ee.p, n, which, offsets);
+    CRK_TRY(scan_exclusive_i64(c, offsets, offsets, n + 1));
+    if (idx) {
+        if (cap < *total) return set_err(c, CRK_ERR_INVALID_ARG, "cap too small");
+        k_export_fill<<<nblocks(n), kBlock, 0, c->stream>>>(
+            (const int64_t *)c->goff.p, (const int32_t *)c->gidx.p, (const int32_t *)c->eb.p,
+            (const int32_t *)c->ee.p, (const int32_t *)c->eidx.p, n, which, offsets, idx);
+    }
+    CRK_HIP(c, hipGetLastError());
+    CRK_HIP(c, hipStreamSynchronize(c->stream));
+    return CRK_OK;
+}
+
+}  // extern "C"

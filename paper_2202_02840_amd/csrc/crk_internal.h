@@ -1,0 +1,223 @@
+// Internal declarations of the CRKSPH neighbour-pass library (gfx950).
+//
+// Layout in HBM (all owned by the context, sized for the largest n seen):
+//   posH   double4 [n]      sorted x, y, z, H (one 32-byte load per neighbour)
+//   perm   int32   [n]      sorted k -> original index
+//   skey   uint32  [n]      Morton code of each sorted particle's finest cell
+//   cbeg/cend int32 [sum_k 8^(b-k)]  sorted-index range of every cell of every
+//                           level k = 0..b of the Morton cell hierarchy (a
+//                           level-k cell is an aligned block of 2^k fine cells
+//                           a side, hence one contiguous range of particles)
+//   goff   int64   [n+1]    gather rows: N_g(i) without i, in cell-walk order
+//   gidx   int32   [sum ng]
+//   eb/ee  int32   [n]      extras rows in eidx: {j : H_i <= |d| < H_j}, the
+//   eidx   int32   [E]      partners that reach i only through their own larger
+//                           support, ascending; N_s(i) = gather row ++ extras row
+//   recV   T       [n]      volumes in the pass precision
+//   rec6   T4      [n]      {vx, vy, vz, V}            (velocity-gradient pass)
+//   rec7   T4      [9][n]   packed per-particle state  (derivative pass)
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <map>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/crk.h"
+
+namespace crk {
+
+constexpr double kPi = 3.14159265358979323846;
+// eq. (C4): W = kW H^-3 (1-q)^6 (1 + 6q + 35/3 q^2);
+// grad_i W = kG H^-5 (1 + 5q) (1-q)^5 d  with kG = -1155 / (4 pi)
+constexpr double kW = 495.0 / (32.0 * kPi);
+constexpr double kG = -1155.0 / (4.0 * kPi);
+
+constexpr int kBlock = 256;       // threads per block of every pair pass (4 wave64)
+
+struct Buf {
+    void *p = nullptr;
+    size_t bytes = 0;
+};
+
+}  // namespace crk
+
+struct crk_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+
+    // geometry of the last build: fine cells nc = 2^bits a side, levels 0..bits
+    int64_t n = 0;
+    double L = 1.0;
+    int nc = 0;
+    int bits = 0;
+    double cell = 0.0;
+    int64_t lvl_off[12] = {0};
+    int64_t ntab = 0;
+    int built = 0;          // lists valid
+    int have_V = 0;         // recV valid (after crk_moments)
+    int prec_V = -1;        // precision recV was written in
+    int64_t npairs = 0;     // sum of |N_s(i)|
+    int64_t ngather = 0;    // sum of ng (excludes self)
+    int64_t nextra = 0;     // entries of eidx
+
+    // workspace
+    crk::Buf posH, perm, cbeg, cend, goff, gidx, ng, nes, esoff, eb, ee, ekey, eidx;
+    crk::Buf keyA, keyB, valA, valB, hist, scanTmp;
+    crk::Buf recV, rec6, rec7, red, misc;
+    crk::Buf pinned;        // small host-pinned readback area
+
+    // per-pass tuning: lanes per particle (1..64)
+    int G_vol = 4, G_mom = 1, G_grad = 4, G_der = 8;
+
+    // per-kernel timing with HIP events on `stream` (crk_timing_*)
+    int timing = 0;
+    std::vector<hipEvent_t> ev_pool;
+    std::vector<std::pair<std::string, std::pair<hipEvent_t, hipEvent_t>>> ev_pend;
+    std::map<std::string, std::pair<double, int64_t>> ev_total;
+};
+
+namespace crk {
+
+crk_status set_err(crk_ctx *c, crk_status s, const char *fmt, ...);
+crk_status hip_err(crk_ctx *c, hipError_t e, const char *what);
+crk_status ensure(crk_ctx *c, Buf &b, size_t bytes);
+
+// Records a start/stop event pair around the launches in its scope when the
+// context's timing is on; the pairs are read back by crk_timing_read.
+struct KTimer {
+    crk_ctx *c;
+    const char *name;
+    hipEvent_t a = nullptr, b = nullptr;
+    KTimer(crk_ctx *ctx, const char *nm);
+    ~KTimer();
+};
+
+// device-wide exclusive scan of n values (int64 in/out may alias)
+crk_status scan_exclusive_i64(crk_ctx *c, const int64_t *in, int64_t *out, int64_t n);
+// stable LSD radix sort of (key, value) pairs on the low `bits` bits of the keys
+crk_status radix_sort_pairs(crk_ctx *c, uint32_t *keys, int32_t *vals, int64_t n, int bits);
+
+// grid index remap that gives each XCD a contiguous run of logical blocks:
+// blocks are dispatched round-robin over the 8 XCDs, so block b runs on XCD
+// b % 8; neighbouring particles then share that XCD's L2.
+__device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nb) {
+    int64_t q = nb >> 3, r = nb & 7, x = b & 7, k = b >> 3;
+    return x * q + (x < r ? x : r) + k;
+}
+
+// Minimum-image separation d = xi - xj in FP64 and r^2 = (dx dx + dy dy) + dz dz
+// without contraction, so that neighbour decisions are reproducible bit for bit.
+__device__ __forceinline__ double min_image(double d, double L, double hL) {
+    if (d > hL) d -= L;
+    else if (d < -hL) d += L;
+    return d;
+}
+
+__device__ __forceinline__ double r2_exact(double dx, double dy, double dz) {
+    return __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz));
+}
+
+// Uniform periodic cell grid of side c = L / nc over the sorted particles.
+struct Grid {
+    double L, hL, inv_c, margin;
+    int nc;
+};
+
+// cells along one axis overlapping [x - R, x + R], with a margin far above
+// any rounding in the division; a range of nc or more cells is one period
+__device__ __forceinline__ void axis_range(double x, double R, const Grid &g, int &lo, int &cnt) {
+    int a = (int)floor((x - R - g.margin) * g.inv_c);
+    int b = (int)floor((x + R + g.margin) * g.inv_c);
+    cnt = b - a + 1;
+    if (cnt >= g.nc) {
+        a = 0;
+        cnt = g.nc;
+    }
+    lo = a;
+}
+
+__device__ __forceinline__ int wrapc(int a, int nc) {
+    a %= nc;
+    return a < 0 ? a + nc : a;
+}
+
+
+// Morton cell hierarchy: level k has nc >> k cells a side, side c0 2^k, and
+// its table starts at off[k] in cbeg/cend (indexed by the level-k Morton id).
+struct Levels {
+    double L, hL, c0, margin;
+    int bits;
+    int64_t off[12];
+};
+
+__device__ __forceinline__ uint32_t spread3(uint32_t v) {   // 10 bits -> every third bit
+    v &= 0x3ffu;
+    v = (v | (v << 16)) & 0x030000ffu;
+    v = (v | (v << 8)) & 0x0300f00fu;
+    v = (v | (v << 4)) & 0x030c30c3u;
+    v = (v | (v << 2)) & 0x09249249u;
+    return v;
+}
+
+__device__ __forceinline__ uint32_t morton3(uint32_t x, uint32_t y, uint32_t z) {
+    return spread3(x) | (spread3(y) << 1) | (spread3(z) << 2);
+}
+
+// level whose cell side is at least R/2 (so at most five cells a side cover
+// the support), capped at the single-cell level
+__device__ __forceinline__ int level_for(double R, const Levels &v) {
+    int k = 0;
+    double c = v.c0;
+    while (k < v.bits && c < 0.5 * R) {
+        c *= 2.0;
+        k++;
+    }
+    return k;
+}
+
+// Walks every cell of the level chosen for radius R that overlaps the cube
+// [x - R, x + R]^3 (periodic), calling f(j) for each particle j in them, in a
+// fixed order: cells z-major, then y, then x; particles in sorted order.
+template <typename F>
+__device__ __forceinline__ void walk_cells(const Levels &v, const int32_t *__restrict__ cbeg,
+                                           const int32_t *__restrict__ cend, double px, double py,
+                                           double pz, double R, F &&f) {
+    int k = level_for(R, v);
+    int nck = 1 << (v.bits - k);
+    Grid g{v.L, v.hL, (double)nck / v.L, v.margin, nck};
+    int lx, ly, lz, mx, my, mz;
+    axis_range(px, R, g, lx, mx);
+    axis_range(py, R, g, ly, my);
+    axis_range(pz, R, g, lz, mz);
+    const int32_t *cb = cbeg + v.off[k], *ce = cend + v.off[k];
+    for (int a = 0; a < mz; a++) {
+        uint32_t mzb = spread3(wrapc(lz + a, nck)) << 2;
+        for (int b = 0; b < my; b++) {
+            uint32_t myb = mzb | (spread3(wrapc(ly + b, nck)) << 1);
+            for (int e = 0; e < mx; e++) {
+                uint32_t id = myb | spread3(wrapc(lx + e, nck));
+                int jb = cb[id], je = ce[id];
+                for (int j = jb; j < je; j++) f(j);
+            }
+        }
+    }
+}
+
+}  // namespace crk
+
+#define CRK_HIP(c, call)                                                   \
+    do {                                                                   \
+        hipError_t e_ = (call);                                            \
+        if (e_ != hipSuccess) return crk::hip_err((c), e_, #call);         \
+    } while (0)
+
+#define CRK_TRY(expr)                                                      \
+    do {                                                                   \
+        crk_status s_ = (expr);                                            \
+        if (s_ < 0) return s_;                                             \
+    } while (0)

@@ -1,0 +1,766 @@
+// S2, S4, S5, S6, S7: the pair passes and the per-particle RK solve.
+//
+// Thread mapping. Every pair pass gives each particle i a group of G lanes
+// (G in {1, 2, 4, 8, 16, 32, 64}, a divisor of the 64-wide wavefront). The
+// lanes of a group stride over i's neighbour row, each keeping partial sums,
+// and the group then reduces with cross-lane shuffles. G = 1 is one thread
+// per particle; larger G trades a final reduction for balanced rows and
+// coalesced loads of consecutive neighbours (rows follow the cell walk, and
+// particles of a cell are contiguous after the sort). The best G per pass is
+// chosen by the tuner; there is no MFMA here: each pass is a gather plus a
+// reduction, not a dense contraction.
+//
+// Precision. T = double: every term and sum in FP64. T = float (CRK_MIXED):
+// the separation d = x_i - x_j and its minimum image are formed in FP64 from
+// the FP64 positions and only then rounded to FP32 (so close pairs keep their
+// relative accuracy anywhere in the box); kernel values and pair terms are
+// FP32 and every sum is a compensated (Kahan) FP32 sum whose high and low
+// parts are combined in FP64 at the boundary.
+#include <math.h>
+
+#include <algorithm>
+#include <type_traits>
+
+#include "crk_internal.h"
+
+namespace crk {
+namespace {
+
+// ------------------------------------------------------------- arithmetic
+template <typename T> struct Mth;
+template <> struct Mth<float> {
+    static __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+    static __device__ __forceinline__ float sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+    static __device__ __forceinline__ float exp(float x) { return __expf(x); }
+};
+template <> struct Mth<double> {
+    static __device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
+    static __device__ __forceinline__ double sqrt(double x) { return ::sqrt(x); }
+    static __device__ __forceinline__ double exp(double x) { return ::exp(x); }
+};
+
+// sum accumulator: plain FP64, or compensated FP32 (value = s - c)
+template <typename T> struct Acc;
+template <> struct Acc<double> {
+    double s = 0.0;
+    __device__ __forceinline__ void add(double x) { s += x; }
+    __device__ __forceinline__ double value() const { return s; }
+    __device__ __forceinline__ void merge_xor(int m, int w) { s += __shfl_xor(s, m, w); }
+};
+template <> struct Acc<float> {
+    float s = 0.0f, c = 0.0f;
+    __device__ __forceinline__ void add(float x) {
+        float y = x - c;
+        float t = s + y;
+        c = (t - s) - y;
+        s = t;
+    }
+    __device__ __forceinline__ double value() const { return (double)s - (double)c; }
+    // combine with the partner lane's (s, c): exact two-sum of the high parts
+    __device__ __forceinline__ void merge_xor(int m, int w) {
+        float s2 = __shfl_xor(s, m, w), c2 = __shfl_xor(c, m, w);
+        float t = s + s2;
+        float bp = t - s;
+        float e = (s - (t - bp)) + (s2 - bp);
+        s = t;
+        c = c + c2 - e;
+    }
+};
+
+template <typename T, int G, int K>
+__device__ __forceinline__ void group_reduce(Acc<T> (&a)[K]) {
+#pragma unroll
+    for (int m = G / 2; m >= 1; m >>= 1)
+#pragma unroll
+        for (int k = 0; k < K; k++) a[k].merge_xor(m, G);
+}
+
+struct Box {
+    double L, hL;
+};
+
+template <typename T>
+__device__ __forceinline__ void separation(const double4 &pi, const double4 &pj, const Box &b,
+                                           T &dx, T &dy, T &dz) {
+    dx = (T)min_image(pi.x - pj.x, b.L, b.hL);
+    dy = (T)min_image(pi.y - pj.y, b.L, b.hL);
+    dz = (T)min_image(pi.z - pj.z, b.L, b.hL);
+}
+
+// Wendland C4 with unit support, eq. (C4): with q = r/H and s = max(1 - q, 0),
+//   W = kW H^-3 s^6 (1 + 6q + 35q^2/3),  grad_i W = kG H^-5 (1 + 5q) s^5 d.
+template <typename T>
+__device__ __forceinline__ void kernel_wg(T q, T cw, T cg, T &w, T &gf) {
+    T s = q < (T)1 ? (T)1 - q : (T)0;
+    T s2 = s * s;
+    T s5 = s2 * s2 * s;
+    w = cw * s5 * s * ((T)1 + q * ((T)6 + q * (T)(35.0 / 3.0)));
+    gf = cg * ((T)1 + (T)5 * q) * s5;
+}
+
+template <typename T>
+__device__ __forceinline__ T kernel_w(T q, T cw) {
+    T s = q < (T)1 ? (T)1 - q : (T)0;
+    T s2 = s * s;
+    return cw * s2 * s2 * s2 * ((T)1 + q * ((T)6 + q * (T)(35.0 / 3.0)));
+}
+
+__device__ __forceinline__ int64_t group_index(int G, int &lane) {
+    int64_t gid = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    lane = (int)(gid % G);
+    return gid / G;
+}
+
+// ------------------------------------------------------------- S2 volume
+template <typename T, int G>
+__global__ __launch_bounds__(kBlock) void k_volume(const double4 *__restrict__ posH,
+                                                   const int64_t *__restrict__ goff,
+                                                   const int32_t *__restrict__ gidx, int64_t n, Box box,
+                                                   double *nsum_out, double *V_out, T *recV) {
+    int l;
+    int64_t i = group_index(G, l);
+    Acc<T> acc[1];
+    if (i < n) {
+        double4 pi = posH[i];
+        T invH = (T)(1.0 / pi.w);
+        T cw = (T)kW * invH * invH * invH;
+        if (l == 0) acc[0].add(cw);            // self pair: W(0, H_i)
+        int64_t b = goff[i];
+        int cnt = (int)(goff[i + 1] - b);
+        for (int k = l; k < cnt; k += G) {
+            double4 pj = posH[gidx[b + k]];
+            T dx, dy, dz;
+            separation(pi, pj, box, dx, dy, dz);
+            T q = Mth<T>::sqrt(dx * dx + dy * dy + dz * dz) * invH;
+            acc[0].add(kernel_w(q, cw));
+        }
+    }
+    group_reduce<T, G, 1>(acc);
+    if (i < n && l == 0) {
+        double s = acc[0].value();
+        if (nsum_out) nsum_out[i] = s;
+        V_out[i] = 1.0 / s;
+        recV[i] = (T)(1.0 / s);
+    }
+}
+
+// ------------------------------------------------------------- S4 moments
+// 40 sums per particle: m0, m1[3], m2[6], gm0[3], gm1[9], gm2[18]
+template <typename T, int G>
+__global__ __launch_bounds__(kBlock) void k_moments(const double4 *__restrict__ posH,
+                                                    const int64_t *__restrict__ goff,
+                                                   const int32_t *__restrict__ gidx,
+                                                    const T *__restrict__ recV, int64_t n, Box box,
+                                                    double *m0, double *m1, double *m2, double *gm0,
+                                                    double *gm1, double *gm2) {
+    int l;
+    int64_t i = group_index(G, l);
+    Acc<T> a[40];
+    if (i < n) {
+        double4 pi = posH[i];
+        T invH = (T)(1.0 / pi.w);
+        T invH2 = invH * invH;
+        T cw = (T)kW * invH2 * invH;
+        T cg = (T)kG * invH2 * invH2 * invH;
+        if (l == 0) {
+            // self pair: d = 0, grad W = 0, so only m0 and the diagonal of dm1/dx
+            T t = recV[i] * cw;
+            a[0].add(t);
+            a[13 + 0].add(t);
+            a[13 + 4].add(t);
+            a[13 + 8].add(t);
+        }
+        int64_t b = goff[i];
+        int cnt = (int)(goff[i + 1] - b);
+        for (int k = l; k < cnt; k += G) {
+            int32_t j = gidx[b + k];
+            double4 pj = posH[j];
+            T Vj = recV[j];
+            T d[3];
+            separation(pi, pj, box, d[0], d[1], d[2]);
+            T q = Mth<T>::sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]) * invH;
+            T w, gf;
+            kernel_wg(q, cw, cg, w, gf);
+            T t = Vj * w;
+            T gv[3], td[3];
+            T vg = Vj * gf;
+#pragma unroll
+            for (int c = 0; c < 3; c++) {
+                gv[c] = vg * d[c];
+                td[c] = t * d[c];
+            }
+            a[0].add(t);
+#pragma unroll
+            for (int x = 0; x < 3; x++) a[1 + x].add(td[x]);
+            // m2 and dm2 over the symmetric pairs (x, y), y >= x
+            int s = 0;
+#pragma unroll
+            for (int x = 0; x < 3; x++)
+#pragma unroll
+                for (int y = x; y < 3; y++, s++) {
+                    T dd = d[x] * d[y];
+                    a[4 + s].add(td[x] * d[y]);
+#pragma unroll
+                    for (int c = 0; c < 3; c++) {
+                        T v = dd * gv[c];
+                        if (x == c) v += td[y];
+                        if (y == c) v += td[x];
+                        a[22 + s * 3 + c].add(v);
+                    }
+                }
+#pragma unroll
+            for (int c = 0; c < 3; c++) a[10 + c].add(gv[c]);
+#pragma unroll
+            for (int x = 0; x < 3; x++)
+#pragma unroll
+                for (int c = 0; c < 3; c++) a[13 + x * 3 + c].add(x == c ? d[x] * gv[c] + t : d[x] * gv[c]);
+        }
+    }
+    group_reduce<T, G, 40>(a);
+    if (i < n && l == 0) {
+        m0[i] = a[0].value();
+#pragma unroll
+        for (int x = 0; x < 3; x++) m1[x * n + i] = a[1 + x].value();
+#pragma unroll
+        for (int s = 0; s < 6; s++) m2[s * n + i] = a[4 + s].value();
+#pragma unroll
+        for (int c = 0; c < 3; c++) gm0[c * n + i] = a[10 + c].value();
+#pragma unroll
+        for (int s = 0; s < 9; s++) gm1[s * n + i] = a[13 + s].value();
+#pragma unroll
+        for (int s = 0; s < 18; s++) gm2[s * n + i] = a[22 + s].value();
+    }
+}
+
+// ------------------------------------------------------------- S5 corrections
+// Per particle, FP64. The constraints sum V W^R = 1 and sum V d W^R = 0 of
+// eq. (RK) give B = -m2^{-1} m1 and A = 1/(m0 + B.m1); their gradients follow
+// by differentiating the same constraints. m2 is inverted by its adjugate;
+// det(m2) <= 1e-12 (tr m2 / 3)^3 selects normalised SPH (A = 1/m0, B = 0).
+__global__ __launch_bounds__(kBlock) void k_corrections(int64_t n, const double *m0, const double *m1,
+                                                        const double *m2, const double *gm0,
+                                                        const double *gm1, const double *gm2,
+                                                        double *A, double *B, double *gA, double *gB,
+                                                        unsigned long long *nsing) {
+    int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const int sym[3][3] = {{0, 1, 2}, {1, 3, 4}, {2, 4, 5}};
+    double M[3][3];
+#pragma unroll
+    for (int x = 0; x < 3; x++)
+#pragma unroll
+        for (int y = 0; y < 3; y++) M[x][y] = m2[sym[x][y] * n + i];
+    double det = M[0][0] * (M[1][1] * M[2][2] - M[1][2] * M[2][1]) -
+                 M[0][1] * (M[1][0] * M[2][2] - M[1][2] * M[2][0]) +
+                 M[0][2] * (M[1][0] * M[2][1] - M[1][1] * M[2][0]);
+    double tr = (M[0][0] + M[1][1] + M[2][2]) / 3.0;
+    double mm0 = m0[i];
+    double mm1[3] = {m1[i], m1[n + i], m1[2 * n + i]};
+    if (!(det > 1e-12 * tr * tr * tr)) {
+        A[i] = 1.0 / mm0;
+#pragma unroll
+        for (int x = 0; x < 3; x++) {
+            B[x * n + i] = 0.0;
+            gA[x * n + i] = -gm0[x * n + i] / (mm0 * mm0);
+        }
+#pragma unroll
+        for (int s = 0; s < 9; s++) gB[s * n + i] = 0.0;
+        atomicAdd(nsing, 1ull);
+        return;
+    }
+    double id = 1.0 / det;
+    double Mi[3][3];
+    Mi[0][0] = (M[1][1] * M[2][2] - M[1][2] * M[2][1]) * id;
+    Mi[0][1] = (M[0][2] * M[2][1] - M[0][1] * M[2][2]) * id;
+    Mi[0][2] = (M[0][1] * M[1][2] - M[0][2] * M[1][1]) * id;
+    Mi[1][1] = (M[0][0] * M[2][2] - M[0][2] * M[2][0]) * id;
+    Mi[1][2] = (M[0][2] * M[1][0] - M[0][0] * M[1][2]) * id;
+    Mi[2][2] = (M[0][0] * M[1][1] - M[0][1] * M[1][0]) * id;
+    Mi[1][0] = Mi[0][1];
+    Mi[2][0] = Mi[0][2];
+    Mi[2][1] = Mi[1][2];
+    double Bv[3];
+#pragma unroll
+    for (int x = 0; x < 3; x++) Bv[x] = -(Mi[x][0] * mm1[0] + Mi[x][1] * mm1[1] + Mi[x][2] * mm1[2]);
+    double Av = 1.0 / (mm0 + Bv[0] * mm1[0] + Bv[1] * mm1[1] + Bv[2] * mm1[2]);
+    A[i] = Av;
+#pragma unroll
+    for (int x = 0; x < 3; x++) B[x * n + i] = Bv[x];
+#pragma unroll
+    for (int g = 0; g < 3; g++) {
+        double r[3];
+#pragma unroll
+        for (int x = 0; x < 3; x++) {
+            double s = gm1[(x * 3 + g) * n + i];
+#pragma unroll
+            for (int y = 0; y < 3; y++) s += gm2[(sym[x][y] * 3 + g) * n + i] * Bv[y];
+            r[x] = s;
+        }
+        double dB[3];
+#pragma unroll
+        for (int x = 0; x < 3; x++) dB[x] = -(Mi[x][0] * r[0] + Mi[x][1] * r[1] + Mi[x][2] * r[2]);
+        double s = gm0[g * n + i];
+#pragma unroll
+        for (int x = 0; x < 3; x++) s += dB[x] * mm1[x] + Bv[x] * gm1[(x * 3 + g) * n + i];
+        gA[g * n + i] = -Av * Av * s;
+#pragma unroll
+        for (int x = 0; x < 3; x++) gB[(x * 3 + g) * n + i] = dB[x];
+    }
+}
+
+// ------------------------------------------------------------- S6 grad v
+// RK gradient template of eq. (gRK) for the ordered pair (i, j) with i's
+// coefficients: c = 1 + B.d, (gradB^T d)_g = sum_a d_a dB_a/dx_g,
+//   grad W^R_g = w (dA_g c + A ((gradB^T d)_g + B_g)) + A c gf d_g.
+template <typename T>
+struct Coef {
+    T A, B[3], gA[3], gB[9];
+};
+
+template <typename T>
+__device__ __forceinline__ void rk_grad(const Coef<T> &k, const T d[3], T w, T gf, T out[3]) {
+    T c = (T)1 + k.B[0] * d[0] + k.B[1] * d[1] + k.B[2] * d[2];
+    T acg = k.A * c * gf;
+#pragma unroll
+    for (int g = 0; g < 3; g++) {
+        T btd = d[0] * k.gB[0 * 3 + g] + d[1] * k.gB[1 * 3 + g] + d[2] * k.gB[2 * 3 + g];
+        out[g] = w * (k.gA[g] * c + k.A * (btd + k.B[g])) + acg * d[g];
+    }
+}
+
+template <typename T, int G>
+__global__ __launch_bounds__(kBlock) void k_gradv(const double4 *__restrict__ posH,
+                                                  const int64_t *__restrict__ goff,
+                                                   const int32_t *__restrict__ gidx,
+                                                  const typename std::conditional<sizeof(T) == 4, float4, double4>::type *__restrict__ rec6,
+                                                  const double *__restrict__ A, const double *__restrict__ B,
+                                                  const double *__restrict__ gA,
+                                                  const double *__restrict__ gB, int64_t n, Box box,
+                                                  double *gradv) {
+    int l;
+    int64_t i = group_index(G, l);
+    Acc<T> a[9];
+    if (i < n) {
+        double4 pi = posH[i];
+        T invH = (T)(1.0 / pi.w);
+        T invH2 = invH * invH;
+        T cw = (T)kW * invH2 * invH;
+        T cg = (T)kG * invH2 * invH2 * invH;
+        Coef<T> k;
+        k.A = (T)A[i];
+#pragma unroll
+        for (int x = 0; x < 3; x++) {
+            k.B[x] = (T)B[x * n + i];
+            k.gA[x] = (T)gA[x * n + i];
+        }
+#pragma unroll
+        for (int s = 0; s < 9; s++) k.gB[s] = (T)gB[s * n + i];
+        auto ri = rec6[i];
+        T vi[3] = {ri.x, ri.y, ri.z};
+        int64_t b = goff[i];
+        int cnt = (int)(goff[i + 1] - b);
+        for (int kk = l; kk < cnt; kk += G) {
+            int32_t j = gidx[b + kk];
+            double4 pj = posH[j];
+            auto rj = rec6[j];
+            T d[3];
+            separation(pi, pj, box, d[0], d[1], d[2]);
+            T q = Mth<T>::sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]) * invH;
+            T w, gf;
+            kernel_wg(q, cw, cg, w, gf);
+            T G3[3];
+            rk_grad(k, d, w, gf, G3);
+            T dv[3] = {(vi[0] - (T)rj.x) * rj.w, (vi[1] - (T)rj.y) * rj.w, (vi[2] - (T)rj.z) * rj.w};
+#pragma unroll
+            for (int x = 0; x < 3; x++)
+#pragma unroll
+                for (int y = 0; y < 3; y++) a[x * 3 + y].add(-dv[x] * G3[y]);
+        }
+    }
+    group_reduce<T, G, 9>(a);
+    if (i < n && l == 0)
+#pragma unroll
+        for (int s = 0; s < 9; s++) gradv[s * n + i] = a[s].value();
+}
+
+// ------------------------------------------------------------- S7 derivatives
+// Packed per-particle state, nine 4-vectors:
+//   0 {vx, vy, vz, V}   1 {rho, P, cs, A}   2 {Bx, By, Bz, 1/H}   3 {dAx, dAy, dAz, H/nh}
+//   4 {gB0..gB3}        5 {gB4..gB7}        6 {gB8, gv0, gv1, gv2}
+//   7 {gv3..gv6}        8 {gv7, gv8, 0, 0}
+constexpr int kRec7 = 9;
+
+struct DerivPrm {
+    double gamma, Cl, Cq, eps2, inv_nh, inv_a, half_a2, half_inv_a2, adot, eta_c, inv_eta_f;
+};
+
+template <typename V4, typename T>
+__global__ __launch_bounds__(kBlock) void k_pack7(int64_t n, const double4 *__restrict__ posH,
+                                                  const double *v, const double *m, const double *u,
+                                                  const double *rho, const double *V, const double *A,
+                                                  const double *B, const double *gA, const double *gB,
+                                                  const double *gv, DerivPrm p, V4 *rec, int *bad) {
+    int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    double Vi = V[i];
+    double r = rho ? rho[i] : m[i] / Vi;
+    double P = (p.gamma - 1.0) * r * u[i];
+    double cs = sqrt(p.gamma * P / r);
+    if (!isfinite(r) || !isfinite(P) || !isfinite(cs) || !isfinite(m[i]) || !isfinite(v[i]) ||
+        !isfinite(v[n + i]) || !isfinite(v[2 * n + i]) || !(r > 0.0))
+        atomicOr(bad, 1);
+    double H = posH[i].w;
+    V4 *o = rec + i * kRec7;
+    o[0] = V4{(T)v[i], (T)v[n + i], (T)v[2 * n + i], (T)Vi};
+    o[1] = V4{(T)r, (T)P, (T)cs, (T)A[i]};
+    o[2] = V4{(T)B[i], (T)B[n + i], (T)B[2 * n + i], (T)(1.0 / H)};
+    o[3] = V4{(T)gA[i], (T)gA[n + i], (T)gA[2 * n + i], (T)(H * p.inv_nh)};
+    o[4] = V4{(T)gB[i], (T)gB[n + i], (T)gB[2 * n + i], (T)gB[3 * n + i]};
+    o[5] = V4{(T)gB[4 * n + i], (T)gB[5 * n + i], (T)gB[6 * n + i], (T)gB[7 * n + i]};
+    o[6] = V4{(T)gB[8 * n + i], (T)gv[i], (T)gv[n + i], (T)gv[2 * n + i]};
+    o[7] = V4{(T)gv[3 * n + i], (T)gv[4 * n + i], (T)gv[5 * n + i], (T)gv[6 * n + i]};
+    o[8] = V4{(T)gv[7 * n + i], (T)gv[8 * n + i], (T)0, (T)0};
+}
+
+template <typename T>
+struct State {
+    T v[3], V, rho, P, cs, invH, hh;
+    Coef<T> k;
+    T gv[9];
+};
+
+template <typename V4, typename T>
+__device__ __forceinline__ void load_state(const V4 *__restrict__ rec, int64_t j, State<T> &s) {
+    const V4 *o = rec + j * kRec7;
+    V4 r0 = o[0], r1 = o[1], r2 = o[2], r3 = o[3], r4 = o[4], r5 = o[5], r6 = o[6], r7 = o[7],
+       r8 = o[8];
+    s.v[0] = r0.x; s.v[1] = r0.y; s.v[2] = r0.z; s.V = r0.w;
+    s.rho = r1.x; s.P = r1.y; s.cs = r1.z; s.k.A = r1.w;
+    s.k.B[0] = r2.x; s.k.B[1] = r2.y; s.k.B[2] = r2.z; s.invH = r2.w;
+    s.k.gA[0] = r3.x; s.k.gA[1] = r3.y; s.k.gA[2] = r3.z; s.hh = r3.w;
+    s.k.gB[0] = r4.x; s.k.gB[1] = r4.y; s.k.gB[2] = r4.z; s.k.gB[3] = r4.w;
+    s.k.gB[4] = r5.x; s.k.gB[5] = r5.y; s.k.gB[6] = r5.z; s.k.gB[7] = r5.w;
+    s.k.gB[8] = r6.x; s.gv[0] = r6.y; s.gv[1] = r6.z; s.gv[2] = r6.w;
+    s.gv[3] = r7.x; s.gv[4] = r7.y; s.gv[5] = r7.z; s.gv[6] = r7.w;
+    s.gv[7] = r8.x; s.gv[8] = r8.y;
+}
+
+template <typename T, int G>
+__global__ __launch_bounds__(kBlock) void k_deriv(const double4 *__restrict__ posH,
+                                                  const int64_t *__restrict__ goff,
+                                                  const int32_t *__restrict__ gidx,
+                                                  const int32_t *__restrict__ eb,
+                                                  const int32_t *__restrict__ ee,
+                                                  const int32_t *__restrict__ eidx,
+                                                  const typename std::conditional<sizeof(T) == 4, float4, double4>::type *__restrict__ rec,
+                                                  const double *__restrict__ m, int64_t n, Box box,
+                                                  DerivPrm p, double *dpdt, double *dudt) {
+    int l;
+    int64_t i = group_index(G, l);
+    Acc<T> a[4];
+    if (i < n) {
+        double4 pi = posH[i];
+        State<T> si;
+        load_state(rec, i, si);
+        const T Cl = (T)p.Cl, Cq = (T)p.Cq, eps2 = (T)p.eps2, inv_a = (T)p.inv_a,
+                adot = (T)p.adot, eta_c = (T)p.eta_c, inv_eta_f = (T)p.inv_eta_f;
+        T cwi = (T)kW * si.invH * si.invH * si.invH;
+        T cgi = (T)kG * si.invH * si.invH * si.invH * si.invH * si.invH;
+        T hhi_a = si.hh * inv_a, hh2i = si.hh * si.hh * eps2;
+        T ViF = (T)p.half_a2 * si.V, ViE = (T)p.half_inv_a2 * si.V;
+        T PQbase_i = si.P;
+        // N_s(i): the gather row, then the extras row
+        int64_t gb = goff[i];
+        int ngi = (int)(goff[i + 1] - gb);
+        int ebi = eb[i];
+        int tot = ngi + (ee[i] - ebi);
+        for (int kk = l; kk < tot; kk += G) {
+            int32_t j = kk < ngi ? gidx[gb + kk] : eidx[ebi + (kk - ngi)];
+            double4 pj = posH[j];
+            State<T> sj;
+            load_state(rec, j, sj);
+            T d[3];
+            separation(pi, pj, box, d[0], d[1], d[2]);
+            T r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+            T r = Mth<T>::sqrt(r2);
+            T qi = r * si.invH, qj = r * sj.invH;
+            T cwj = (T)kW * sj.invH * sj.invH * sj.invH;
+            T cgj = (T)kG * sj.invH * sj.invH * sj.invH * sj.invH * sj.invH;
+            T wi, gfi, wj, gfj;
+            kernel_wg(qi, cwi, cgi, wi, gfi);
+            kernel_wg(qj, cwj, cgj, wj, gfj);
+            // grad W^R_ij (i's coefficients, +d) and grad W^R_ji (j's, -d)
+            T Gij[3], Gji[3], md[3] = {-d[0], -d[1], -d[2]};
+            rk_grad(si.k, d, wi, gfi, Gij);
+            rk_grad(sj.k, md, wj, gfj, Gji);
+            T D[3] = {Gji[0] - Gij[0], Gji[1] - Gij[1], Gji[2] - Gij[2]};
+            // limiter, eqs. (phi)-(phiad)
+            T gvi[3], gvj[3];
+#pragma unroll
+            for (int x = 0; x < 3; x++) {
+                gvi[x] = si.gv[x * 3 + 0] * d[0] + si.gv[x * 3 + 1] * d[1] + si.gv[x * 3 + 2] * d[2];
+                gvj[x] = sj.gv[x * 3 + 0] * d[0] + sj.gv[x * 3 + 1] * d[1] + sj.gv[x * 3 + 2] * d[2];
+            }
+            T s_i = d[0] * gvi[0] + d[1] * gvi[1] + d[2] * gvi[2];
+            T s_j = d[0] * gvj[0] + d[1] * gvj[1] + d[2] * gvj[2];
+            T prod = s_i * s_j;
+            T phi = (T)0;
+            if (prod > (T)0) {
+                T sum = s_i + s_j;
+                phi = (T)4 * prod * Mth<T>::rcp(sum * sum);
+                phi = phi < (T)1 ? phi : (T)1;
+                T eta = qi < qj ? qi : qj;
+                if (eta < eta_c) {
+                    T x = (eta - eta_c) * inv_eta_f;
+                    phi *= Mth<T>::exp(-x * x);
+                }
+            }
+            // projected velocity difference, eq. (hatvi), and eq. (mu)
+            T hp = (T)0.5 * phi;
+            T ud = (T)0;
+#pragma unroll
+            for (int x = 0; x < 3; x++) ud += ((si.v[x] - sj.v[x]) - hp * (gvi[x] + gvj[x]) + adot * d[x]) * d[x];
+            T Qi = (T)0, Qj = (T)0;
+            if (ud < (T)0) {
+                T hhj_a = sj.hh * inv_a, hh2j = sj.hh * sj.hh * eps2;
+                T mui = hhi_a * ud * Mth<T>::rcp(r2 + hh2i);
+                T muj = hhj_a * ud * Mth<T>::rcp(r2 + hh2j);
+                Qi = si.rho * (-Cl * si.cs * mui + Cq * mui * mui);
+                Qj = sj.rho * (-Cl * sj.cs * muj + Cq * muj * muj);
+            }
+            T fm = ViF * sj.V * (PQbase_i + Qi + sj.P + Qj);
+            T fe = ViE * sj.V * (sj.P + Qj);
+            T xdd = ((sj.v[0] - si.v[0]) * D[0] + (sj.v[1] - si.v[1]) * D[1] + (sj.v[2] - si.v[2]) * D[2]) * inv_a;
+            a[0].add(fm * D[0]);
+            a[1].add(fm * D[1]);
+            a[2].add(fm * D[2]);
+            a[3].add(fe * xdd);
+        }
+    }
+    group_reduce<T, G, 4>(a);
+    if (i < n && l == 0) {
+        double im = 1.0 / m[i];
+        dpdt[i] = a[0].value() * im;
+        dpdt[n + i] = a[1].value() * im;
+        dpdt[2 * n + i] = a[2].value() * im;
+        dudt[i] = a[3].value() * im;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_pack6_f(int64_t n, const double *v, const double *V,
+                                                    float4 *rec) {
+    int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) rec[i] = make_float4((float)v[i], (float)v[n + i], (float)v[2 * n + i], (float)V[i]);
+}
+__global__ __launch_bounds__(kBlock) void k_pack6_d(int64_t n, const double *v, const double *V,
+                                                    double4 *rec) {
+    int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) rec[i] = make_double4(v[i], v[n + i], v[2 * n + i], V[i]);
+}
+
+inline unsigned nblocks(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+inline unsigned gblocks(int64_t n, int G) { return (unsigned)((n * G + kBlock - 1) / kBlock); }
+
+#define CRK_DISPATCH_G(G, LAUNCH)                                                          \
+    switch (G) {                                                                           \
+        case 1: LAUNCH(1); break;                                                          \
+        case 2: LAUNCH(2); break;                                                          \
+        case 4: LAUNCH(4); break;                                                          \
+        case 8: LAUNCH(8); break;                                                          \
+        case 16: LAUNCH(16); break;                                                        \
+        case 32: LAUNCH(32); break;                                                        \
+        case 64: LAUNCH(64); break;                                                        \
+        default: return set_err(c, CRK_ERR_INVALID_ARG, "lanes per particle must be a power of two <= 64"); \
+    }
+
+bool valid_prec(int p) { return p == CRK_FP64 || p == CRK_MIXED || p == CRK_MIXED_M64; }
+
+}  // namespace
+}  // namespace crk
+
+using namespace crk;
+
+extern "C" {
+
+// lanes per particle for each pass (tuning hook; 0 leaves a pass unchanged)
+crk_status crk_set_lanes(crk_ctx *c, int32_t g_vol, int32_t g_mom, int32_t g_grad, int32_t g_der) {
+    if (!c) return CRK_ERR_INVALID_ARG;
+    int gs[4] = {g_vol, g_mom, g_grad, g_der};
+    for (int g : gs)
+        if (g != 0 && (g < 1 || g > 64 || (g & (g - 1))))
+            return set_err(c, CRK_ERR_INVALID_ARG, "lanes per particle must be a power of two <= 64");
+    if (g_vol) c->G_vol = g_vol;
+    if (g_mom) c->G_mom = g_mom;
+    if (g_grad) c->G_grad = g_grad;
+    if (g_der) c->G_der = g_der;
+    return CRK_OK;
+}
+
+crk_status crk_moments(crk_ctx *c, const crk_params *p, double *nsum, double *V, double *m0,
+                       double *m1, double *m2, double *gm0, double *gm1, double *gm2) {
+    if (!c) return CRK_ERR_INVALID_ARG;
+    if (!p || !V) return set_err(c, CRK_ERR_INVALID_ARG, "crk_moments: NULL argument");
+    if (!valid_prec(p->precision)) return set_err(c, CRK_ERR_INVALID_ARG, "bad precision");
+    if (!c->built) return set_err(c, CRK_ERR_STATE, "crk_build_cells has not run");
+    bool want_m = m0 || m1 || m2 || gm0 || gm1 || gm2;
+    if (want_m && !(m0 && m1 && m2 && gm0 && gm1 && gm2))
+        return set_err(c, CRK_ERR_INVALID_ARG, "crk_moments: give all moment outputs or none");
+    CRK_HIP(c, hipSetDevice(c->device));
+    int64_t n = c->n;
+    Box box{c->L, 0.5 * c->L};
+    const double4 *posH = (const double4 *)c->posH.p;
+    const int64_t *goff = (const int64_t *)c->goff.p;
+    const int32_t *gidx = (const int32_t *)c->gidx.p;
+    const int32_t *eb = (const int32_t *)c->eb.p, *ee = (const int32_t *)c->ee.p,
+                  *eidx = (const int32_t *)c->eidx.p;
+    bool f32 = p->precision == CRK_MIXED;
+    CRK_TRY(ensure(c, c->recV, (size_t)n * (f32 ? 4 : 8)));
+    int Gv = c->G_vol, Gm = c->G_mom;
+    if (f32) {
+        float *rv = (float *)c->recV.p;
+#define L_VOL(GG) k_volume<float, GG><<<gblocks(n, GG), kBlock, 0, c->stream>>>(posH, goff, gidx, n, box, nsum, V, rv)
+        {
+            KTimer kt_(c, "k_volume");
+            CRK_DISPATCH_G(Gv, L_VOL);
+        }
+#undef L_VOL
+        if (want_m) {
+#define L_MOM(GG) k_moments<float, GG><<<gblocks(n, GG), kBlock, 0, c->stream>>>(posH, goff, gidx, rv, n, box, m0, m1, m2, gm0, gm1, gm2)
+            {
+                KTimer kt_(c, "k_moments");
+                CRK_DISPATCH_G(Gm, L_MOM);
+            }
+#undef L_MOM
+        }
+    } else {
+        double *rv = (double *)c->recV.p;
+#define L_VOL(GG) k_volume<double, GG><<<gblocks(n, GG), kBlock, 0, c->stream>>>(posH, goff, gidx, n, box, nsum, V, rv)
+        {
+            KTimer kt_(c, "k_volume");
+            CRK_DISPATCH_G(Gv, L_VOL);
+        }
+#undef L_VOL
+        if (want_m) {
+#define L_MOM(GG) k_moments<double, GG><<<gblocks(n, GG), kBlock, 0, c->stream>>>(posH, goff, gidx, rv, n, box, m0, m1, m2, gm0, gm1, gm2)
+            {
+                KTimer kt_(c, "k_moments");
+                CRK_DISPATCH_G(Gm, L_MOM);
+            }
+#undef L_MOM
+        }
+    }
+    CRK_HIP(c, hipGetLastError());
+    c->have_V = 1;
+    c->prec_V = p->precision;
+    return CRK_OK;
+}
+
+crk_status crk_corrections(crk_ctx *c, int64_t n, const double *m0, const double *m1,
+                           const double *m2, const double *gm0, const double *gm1, const double *gm2,
+                           double *A, double *B, double *gA, double *gB, int64_t *n_singular) {
+    if (!c) return CRK_ERR_INVALID_ARG;
+    if (n < 1 || !m0 || !m1 || !m2 || !gm0 || !gm1 || !gm2 || !A || !B || !gA || !gB)
+        return set_err(c, CRK_ERR_INVALID_ARG, "crk_corrections: n < 1 or NULL argument");
+    CRK_HIP(c, hipSetDevice(c->device));
+    CRK_TRY(ensure(c, c->misc, 256));
+    unsigned long long *cnt = (unsigned long long *)c->misc.p + 4;
+    CRK_HIP(c, hipMemsetAsync(cnt, 0, sizeof(unsigned long long), c->stream));
+    {
+        KTimer kt_(c, "k_corrections");
+        k_corrections<<<nblocks(n), kBlock, 0, c->stream>>>(n, m0, m1, m2, gm0, gm1, gm2, A, B, gA, gB, cnt);
+    }
+    CRK_HIP(c, hipGetLastError());
+    if (n_singular) {
+        unsigned long long *pin = (unsigned long long *)c->pinned.p + 8;
+        CRK_HIP(c, hipMemcpyAsync(pin, cnt, sizeof(unsigned long long), hipMemcpyDeviceToHost, c->stream));
+        CRK_HIP(c, hipStreamSynchronize(c->stream));
+        *n_singular = (int64_t)pin[0];
+        if (pin[0] > 0) return CRK_WARN_SINGULAR;
+    }
+    return CRK_OK;
+}
+
+crk_status crk_derivatives(crk_ctx *c, const crk_params *p, const double *v, const double *m,
+                           const double *u, const double *rho, const double *V, const double *A,
+                           const double *B, const double *gA, const double *gB, double *gradv,
+                           double *dpdt, double *dudt) {
+    if (!c) return CRK_ERR_INVALID_ARG;
+    if (!p || !v || !m || !u || !V || !A || !B || !gA || !gB || !gradv || !dpdt || !dudt)
+        return set_err(c, CRK_ERR_INVALID_ARG, "crk_derivatives: NULL argument");
+    if (!valid_prec(p->precision)) return set_err(c, CRK_ERR_INVALID_ARG, "bad precision");
+    if (!(p->a > 0.0) || !(p->nh > 0.0) || !(p->eta_fold > 0.0) || !(p->gamma > 1.0))
+        return set_err(c, CRK_ERR_INVALID_ARG, "crk_derivatives: bad parameter");
+    if (!c->built) return set_err(c, CRK_ERR_STATE, "crk_build_cells has not run");
+    CRK_HIP(c, hipSetDevice(c->device));
+    int64_t n = c->n;
+    Box box{c->L, 0.5 * c->L};
+    const double4 *posH = (const double4 *)c->posH.p;
+    const int64_t *goff = (const int64_t *)c->goff.p;
+    const int32_t *gidx = (const int32_t *)c->gidx.p;
+    const int32_t *eb = (const int32_t *)c->eb.p, *ee = (const int32_t *)c->ee.p,
+                  *eidx = (const int32_t *)c->eidx.p;
+    bool f32 = p->precision != CRK_FP64;
+    DerivPrm dp{p->gamma, p->Cl, p->Cq, p->eps * p->eps, 1.0 / p->nh, 1.0 / p->a,
+                0.5 * p->a * p->a, 0.5 / (p->a * p->a), p->adot, p->eta_crit, 1.0 / p->eta_fold};
+    CRK_TRY(ensure(c, c->misc, 256));
+    int *bad = (int *)c->misc.p + 2;
+    CRK_HIP(c, hipMemsetAsync(bad, 0, sizeof(int), c->stream));
+    int Gg = c->G_grad, Gd = c->G_der;
+    if (f32) {
+        CRK_TRY(ensure(c, c->rec6, (size_t)n * sizeof(float4)));
+        CRK_TRY(ensure(c, c->rec7, (size_t)n * kRec7 * sizeof(float4)));
+        float4 *r6 = (float4 *)c->rec6.p, *r7 = (float4 *)c->rec7.p;
+        {
+            KTimer kt_(c, "k_pack");
+            k_pack6_f<<<nblocks(n), kBlock, 0, c->stream>>>(n, v, V, r6);
+        }
+#define L_GV(GG) k_gradv<float, GG><<<gblocks(n, GG), kBlock, 0, c->stream>>>(posH, goff, gidx, r6, A, B, gA, gB, n, box, gradv)
+        {
+            KTimer kt_(c, "k_gradv");
+            CRK_DISPATCH_G(Gg, L_GV);
+        }
+#undef L_GV
+        {
+            KTimer kt_(c, "k_pack");
+            k_pack7<float4, float><<<nblocks(n), kBlock, 0, c->stream>>>(n, posH, v, m, u, rho, V, A, B, gA, gB, gradv, dp, r7, bad);
+        }
+#define L_DER(GG) k_deriv<float, GG><<<gblocks(n, GG), kBlock, 0, c->stream>>>(posH, goff, gidx, eb, ee, eidx, r7, m, n, box, dp, dpdt, dudt)
+        {
+            KTimer kt_(c, "k_deriv");
+            CRK_DISPATCH_G(Gd, L_DER);
+        }
+#undef L_DER
+    } else {
+        CRK_TRY(ensure(c, c->rec6, (size_t)n * sizeof(double4)));
+        CRK_TRY(ensure(c, c->rec7, (size_t)n * kRec7 * sizeof(double4)));
+        double4 *r6 = (double4 *)c->rec6.p, *r7 = (double4 *)c->rec7.p;
+        {
+            KTimer kt_(c, "k_pack");
+            k_pack6_d<<<nblocks(n), kBlock, 0, c->stream>>>(n, v, V, r6);
+        }
+#define L_GV(GG) k_gradv<double, GG><<<gblocks(n, GG), kBlock, 0, c->stream>>>(posH, goff, gidx, r6, A, B, gA, gB, n, box, gradv)
+        {
+            KTimer kt_(c, "k_gradv");
+            CRK_DISPATCH_G(Gg, L_GV);
+        }
+#undef L_GV
+        {
+            KTimer kt_(c, "k_pack");
+            k_pack7<double4, double><<<nblocks(n), kBlock, 0, c->stream>>>(n, posH, v, m, u, rho, V, A, B, gA, gB, gradv, dp, r7, bad);
+        }
+#define L_DER(GG) k_deriv<double, GG><<<gblocks(n, GG), kBlock, 0, c->stream>>>(posH, goff, gidx, eb, ee, eidx, r7, m, n, box, dp, dpdt, dudt)
+        {
+            KTimer kt_(c, "k_deriv");
+            CRK_DISPATCH_G(Gd, L_DER);
+        }
+#undef L_DER
+    }
+    CRK_HIP(c, hipGetLastError());
+    int *pin = (int *)c->pinned.p + 32;
+    CRK_HIP(c, hipMemcpyAsync(pin, bad, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    CRK_HIP(c, hipStreamSynchronize(c->stream));
+    if (pin[0]) return set_err(c, CRK_ERR_NONFINITE, "non-finite or non-positive gas state");
+    return CRK_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,194 @@
+// Device-wide exclusive scan and a stable LSD radix sort (key/value), both
+// written for wave64: the per-block scans use wave shuffles plus one LDS
+// exchange between the four waves of a block, and the sort ranks keys inside
+// a wave with eight ballots (one per digit bit), so each pass is stable and
+// the whole sort is deterministic.
+#include "crk_internal.h"
+
+namespace crk {
+namespace {
+
+constexpr int kScanItems = 8;                       // per thread
+constexpr int kScanTile = kBlock * kScanItems;      // 2048 per block
+
+// inclusive scan of one value per thread across a 256-thread block
+template <typename T>
+__device__ T block_inclusive_scan(T v, T *lds /* [4] */) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        T u = __shfl_up(v, o, 64);
+        if (lane >= o) v += u;
+    }
+    if (lane == 63) lds[w] = v;
+    __syncthreads();
+    T add = 0;
+    for (int k = 0; k < w; k++) add += lds[k];
+    __syncthreads();
+    return v + add;
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_sums(const int64_t *in, int64_t n, int64_t *bsum) {
+    __shared__ int64_t lds[4];
+    int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    int64_t s = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; k++)
+        if (base + k < n) s += in[base + k];
+    s = block_inclusive_scan(s, lds);
+    if (threadIdx.x == kBlock - 1) bsum[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_apply(const int64_t *in, int64_t *out, int64_t n,
+                                                       const int64_t *boff) {
+    __shared__ int64_t lds[4];
+    int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    int64_t v[kScanItems];
+    int64_t s = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; k++) {
+        v[k] = (base + k < n) ? in[base + k] : 0;
+        s += v[k];
+    }
+    int64_t incl = block_inclusive_scan(s, lds);
+    int64_t run = incl - s + (boff ? boff[blockIdx.x] : 0);
+#pragma unroll
+    for (int k = 0; k < kScanItems; k++) {
+        if (base + k < n) out[base + k] = run;
+        run += v[k];
+    }
+}
+
+// ---------------------------------------------------------------- radix sort
+constexpr int kRadixBits = 8;
+constexpr int kBuckets = 1 << kRadixBits;
+constexpr int kSortItems = 8;                       // rounds of 256 per block
+constexpr int kSortTile = kBlock * kSortItems;
+
+__global__ __launch_bounds__(kBlock) void k_radix_hist(const uint32_t *keys, int64_t n, int shift,
+                                                       int64_t nblk, int64_t *hist) {
+    __shared__ int cnt[kBuckets];
+    cnt[threadIdx.x] = 0;
+    __syncthreads();
+    int64_t base = (int64_t)blockIdx.x * kSortTile;
+    for (int r = 0; r < kSortItems; r++) {
+        int64_t i = base + (int64_t)r * kBlock + threadIdx.x;
+        if (i < n) atomicAdd(&cnt[(keys[i] >> shift) & (kBuckets - 1)], 1);
+    }
+    __syncthreads();
+    hist[(int64_t)threadIdx.x * nblk + blockIdx.x] = cnt[threadIdx.x];
+}
+
+__global__ __launch_bounds__(kBlock) void k_radix_scatter(const uint32_t *kin, const int32_t *vin,
+                                                          uint32_t *kout, int32_t *vout, int64_t n,
+                                                          int shift, int64_t nblk,
+                                                          const int64_t *offs) {
+    __shared__ int64_t base[kBuckets];
+    __shared__ int wcnt[4][kBuckets];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    base[tid] = offs[(int64_t)tid * nblk + blockIdx.x];
+    for (int k = 0; k < 4; k++) wcnt[k][tid] = 0;
+    __syncthreads();
+    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    int64_t tile = (int64_t)blockIdx.x * kSortTile;
+    for (int r = 0; r < kSortItems; r++) {
+        int64_t i = tile + (int64_t)r * kBlock + tid;
+        bool valid = i < n;
+        uint32_t key = valid ? kin[i] : 0u;
+        int d = (key >> shift) & (kBuckets - 1);
+        // lanes of this wave holding the same digit
+        uint64_t mask = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < kRadixBits; b++) {
+            uint64_t bb = __ballot((d >> b) & 1);
+            mask &= ((d >> b) & 1) ? bb : ~bb;
+        }
+        int rank = __popcll(mask & lt);
+        if (valid && rank == 0) wcnt[w][d] = __popcll(mask);
+        __syncthreads();
+        int64_t pos = 0;
+        if (valid) {
+            int pre = 0;
+            for (int k = 0; k < w; k++) pre += wcnt[k][d];
+            pos = base[d] + pre + rank;
+        }
+        __syncthreads();
+        base[tid] += wcnt[0][tid] + wcnt[1][tid] + wcnt[2][tid] + wcnt[3][tid];
+        wcnt[0][tid] = wcnt[1][tid] = wcnt[2][tid] = wcnt[3][tid] = 0;
+        __syncthreads();
+        if (valid) {
+            kout[pos] = key;
+            vout[pos] = vin[i];
+        }
+    }
+}
+
+}  // namespace
+
+crk_status scan_exclusive_i64(crk_ctx *c, const int64_t *in, int64_t *out, int64_t n) {
+    if (n <= 0) return CRK_OK;
+    int64_t nblk = (n + kScanTile - 1) / kScanTile;
+    if (nblk == 1) {
+        k_scan_apply<<<1, kBlock, 0, c->stream>>>(in, out, n, nullptr);
+        CRK_HIP(c, hipGetLastError());
+        return CRK_OK;
+    }
+    // block sums live in a scratch buffer; the recursion uses the tail of it
+    size_t need = 0;
+    for (int64_t m = nblk; m > 1; m = (m + kScanTile - 1) / kScanTile) need += (size_t)m;
+    CRK_TRY(ensure(c, c->scanTmp, (need + 16) * sizeof(int64_t)));
+    int64_t *bsum = (int64_t *)c->scanTmp.p;
+    k_scan_sums<<<(unsigned)nblk, kBlock, 0, c->stream>>>(in, n, bsum);
+    CRK_HIP(c, hipGetLastError());
+    // scan the block sums in place (recursion on a disjoint region is not
+    // needed: in == out is allowed by k_scan_apply's read-then-write tiles)
+    {
+        int64_t m = nblk;
+        int64_t mblk = (m + kScanTile - 1) / kScanTile;
+        if (mblk == 1) {
+            k_scan_apply<<<1, kBlock, 0, c->stream>>>(bsum, bsum, m, nullptr);
+            CRK_HIP(c, hipGetLastError());
+        } else {
+            // two-level: nblk <= 2048^2 covers n up to 8.6e9 elements
+            int64_t *bsum2 = bsum + nblk;
+            k_scan_sums<<<(unsigned)mblk, kBlock, 0, c->stream>>>(bsum, m, bsum2);
+            CRK_HIP(c, hipGetLastError());
+            if (mblk > kScanTile) return set_err(c, CRK_ERR_INVALID_ARG, "scan too large");
+            k_scan_apply<<<1, kBlock, 0, c->stream>>>(bsum2, bsum2, mblk, nullptr);
+            k_scan_apply<<<(unsigned)mblk, kBlock, 0, c->stream>>>(bsum, bsum, m, bsum2);
+            CRK_HIP(c, hipGetLastError());
+        }
+    }
+    k_scan_apply<<<(unsigned)nblk, kBlock, 0, c->stream>>>(in, out, n, bsum);
+    CRK_HIP(c, hipGetLastError());
+    return CRK_OK;
+}
+
+crk_status radix_sort_pairs(crk_ctx *c, uint32_t *keys, int32_t *vals, int64_t n, int bits) {
+    if (n <= 1 || bits <= 0) return CRK_OK;
+    int64_t nblk = (n + kSortTile - 1) / kSortTile;
+    CRK_TRY(ensure(c, c->keyB, (size_t)n * sizeof(uint32_t)));
+    CRK_TRY(ensure(c, c->valB, (size_t)n * sizeof(int32_t)));
+    CRK_TRY(ensure(c, c->hist, (size_t)nblk * kBuckets * sizeof(int64_t)));
+    uint32_t *ka = keys, *kb = (uint32_t *)c->keyB.p;
+    int32_t *va = vals, *vb = (int32_t *)c->valB.p;
+    int64_t *hist = (int64_t *)c->hist.p;
+    int passes = (bits + kRadixBits - 1) / kRadixBits;
+    for (int p = 0; p < passes; p++) {
+        int shift = p * kRadixBits;
+        k_radix_hist<<<(unsigned)nblk, kBlock, 0, c->stream>>>(ka, n, shift, nblk, hist);
+        CRK_HIP(c, hipGetLastError());
+        CRK_TRY(scan_exclusive_i64(c, hist, hist, nblk * kBuckets));
+        k_radix_scatter<<<(unsigned)nblk, kBlock, 0, c->stream>>>(ka, va, kb, vb, n, shift, nblk, hist);
+        CRK_HIP(c, hipGetLastError());
+        uint32_t *tk = ka; ka = kb; kb = tk;
+        int32_t *tv = va; va = vb; vb = tv;
+    }
+    if (ka != keys) {
+        CRK_HIP(c, hipMemcpyAsync(keys, ka, (size_t)n * sizeof(uint32_t), hipMemcpyDeviceToDevice, c->stream));
+        CRK_HIP(c, hipMemcpyAsync(vals, va, (size_t)n * sizeof(int32_t), hipMemcpyDeviceToDevice, c->stream));
+    }
+    return CRK_OK;
+}
+
+}  // namespace crk
