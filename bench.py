@@ -70,11 +70,14 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n-side", type=int, default=128)
-    ap.add_argument("--precision", choices=("mixed", "mixed_m64", "fp64"), default="mixed")
+    ap.add_argument("--precision", choices=("mixed", "adapt", "fp64"), default="mixed")
     ap.add_argument("--cpu-n-side", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true")
     ap.add_argument("--lanes", type=str, default="", help="vol,mom,grad,der lanes per particle")
+    ap.add_argument("--walk", type=str, default="", help="lanes,cap of the neighbour walk")
+    ap.add_argument("--kappa", type=float, default=1000.0,
+                    help="conditioning bound above which the adaptive mode runs a row in FP64")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -83,16 +86,18 @@ def main():
         sys.exit(2)
 
     import torch
-    from paper_2202_02840_amd import CRK_FP64, CRK_MIXED, CRK_MIXED_M64, Context
+    from paper_2202_02840_amd import CRK_FP64, CRK_MIXED, CRK_MIXED_ADAPT, Context
     from paper_2202_02840_amd import pipeline as pl
 
     ps = make_workload(args.n_side)
-    prec = {"mixed": CRK_MIXED, "mixed_m64": CRK_MIXED_M64, "fp64": CRK_FP64}[args.precision]
+    prec = {"mixed": CRK_MIXED, "adapt": CRK_MIXED_ADAPT, "fp64": CRK_FP64}[args.precision]
     ctx = Context(0)
     if args.lanes:
         ctx.set_lanes(*[int(v) for v in args.lanes.split(",")])
+    if args.walk:
+        ctx.set_walk(*[int(v) for v in args.walk.split(",")])
     dev = pl.upload(ps)
-    prm = pl.params_for(ps, 64.0, prec)
+    prm = pl.params_for(ps, 64.0, prec, kappa_max=args.kappa)
     torch.cuda.synchronize()
 
     for _ in range(args.warmup):
@@ -108,11 +113,13 @@ def main():
     t1 = time.perf_counter()
     ms_step = (t1 - t0) * 1e3 / max(args.steps, 1)
     kern = {}
-    for k in ("sort", "k_walk_count", "k_walk_fill", "k_sort_extras", "k_volume", "k_moments",
-              "k_corrections", "k_pack", "k_gradv", "k_deriv"):
+    for k in ("sort", "k_walk", "k_compact_rows", "k_walk_long", "k_sort_extras", "k_volume", "k_moments",
+              "k_corrections", "k_flag", "k_pack", "k_gradv", "k_gradv_fix", "k_deriv",
+              "k_deriv_fix"):
         ms, cnt = ctx.timing_read(k)
         kern[k] = ms / max(cnt, 1)
     ctx.timing(False)
+    fp64_rows = ctx.adaptive_rows() if prec == CRK_MIXED_ADAPT else (0, 0)
     npairs = int(out["n_pairs"])
     n = ps.n
 
@@ -153,7 +160,9 @@ def main():
                                f"sigma_ln_rho 1.5, P(k)~k^-2, 64-neighbour H, seed 2; "
                                f"{args.precision} CRKSPH step",
                    "particles": n, "pairs_per_step": npairs,
-                   "mean_pairs_per_particle": npairs / n, "precision": args.precision},
+                   "mean_pairs_per_particle": npairs / n, "precision": args.precision,
+                   "kappa_max": args.kappa if prec == CRK_MIXED_ADAPT else None,
+                   "fp64_rows": fp64_rows[0], "fp64_touched_rows": fp64_rows[1]},
         "roofline": {"bound": "alu", "achieved": achieved_tf, "peak": VALU_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved_tf / VALU_PEAK_TFLOPS, "traffic": None,
                      "kernel": "k_deriv", "kernel_ms": kern["k_deriv"],

@@ -72,9 +72,12 @@ typedef enum {
     CRK_MIXED = 1, /* FP32 pair terms with compensated (Kahan) FP32 sums in every pair pass;
                       separations are formed in FP64 before rounding; the RK solve
                       (crk_corrections) and every boundary array stay FP64 */
-    CRK_MIXED_M64 = 2 /* volume and moment passes in FP64 (their sums feed the RK solve,
-                      whose conditioning amplifies their error), velocity-gradient and
-                      derivative passes as in CRK_MIXED */
+    CRK_MIXED_ADAPT = 2 /* volume and moment passes in FP64 (their sums feed the RK solve,
+                      whose conditioning amplifies any rounding in them); velocity-gradient
+                      and derivative passes as in CRK_MIXED, except the rows of particles
+                      whose RK template is ill-conditioned, kappa_i = 1 + |B_i| H_i +
+                      |gradB_i| H_i^2 + |gradA_i| H_i / |A_i| > kappa_max: their velocity
+                      gradient and every derivative pair they take part in run in FP64 */
 } crk_precision;
 
 /*
@@ -85,10 +88,11 @@ typedef enum {
  *   nh               particles per smoothing length; hh = H / nh in eq. (mu)
  *   eta_crit, eta_fold   limiter adjustment scales of eq. (phiad): 1/nh, 0.2/nh
  *   a, adot          scale factor and its rate (a = 1, adot = 0 without expansion)
+ *   kappa_max        conditioning bound of CRK_MIXED_ADAPT (ignored otherwise)
  *   precision        a crk_precision value
  */
 typedef struct {
-    double L, gamma, Cl, Cq, eps, nh, eta_crit, eta_fold, a, adot;
+    double L, gamma, Cl, Cq, eps, nh, eta_crit, eta_fold, a, adot, kappa_max;
     int32_t precision;
     int32_t reserved;
 } crk_params;
@@ -98,7 +102,7 @@ typedef struct crk_ctx crk_ctx;
 /* Fills *p with the defaults for a target neighbour count Nres: L = 1,
  * gamma = 5/3, (Cl, Cq, eps) = (2, 1, 0.1), nh = (3 Nres / (4 pi))^(1/3)
  * (n_h = 4 for N_res = 268, Sec. 3.6), eta_crit = 1/nh, eta_fold = 0.2/nh,
- * a = 1, adot = 0, precision CRK_FP64. Host memory. */
+ * a = 1, adot = 0, kappa_max = 1000, precision CRK_FP64. Host memory. */
 crk_status crk_params_default(crk_params *p, double Nres);
 
 /* Creates a context on HIP device `device` that enqueues on `hip_stream`
@@ -198,6 +202,38 @@ crk_status crk_hsolve(crk_ctx *ctx, double Nres, double tol, int32_t max_iter, d
                       int32_t *iters, int64_t *n_unconverged);
 
 /*
+ * S9: smoothing-length network (an addition to the paper's method: a learned
+ * starting value for the iteration of eq. (thacker); the iteration stays the
+ * judge of the converged H). An 8 -> 64 -> 64 -> 1 MLP, exact-erf GELU, FP32:
+ *   z1 = W1 f + b1, a1 = gelu(z1), z2 = W2 a1 + b2, a2 = gelu(z2), y = w3.a2 + b3,
+ * y = ln(H_conv / H_prev). theta[4801] (device, float) holds W1 [64][8]
+ * (row-major), b1 [64], W2 [64][64], b2 [64], w3 [64], b3.
+ * Features (crk_hnet_features), feat[8][n] float, sorted order, at radius
+ * H = H_sorted[i], with N_w(h) = (4 pi/3) h^3 sum_{r<h} W(r, h) (eq. hi) and
+ * n_raw(h) = #{j : r < h} (self included in both):
+ *   f0 = ln(N_w(H)/Nres)   f1 = (Nres/N_w(H))^(1/3) - 1   f2 = ln(8 N_w(H/2)/Nres)
+ *   f3 = ln(64 N_w(H/4)/Nres)   f4 = ln(n_raw(H)/Nres)   f5 = ln(8 n_raw(H/2)/Nres)
+ *   f6 = ln(H n^(1/3) / L)      f7 = 1
+ * crk_hnet_forward: y[nb] for feat[8][nb]. crk_hnet_train_step: one step of
+ * mean-squared-error training on a batch (feat[8][nb], target[nb]): the batch
+ * gradient (reduced in a fixed order, so deterministic) goes to grad[4801]
+ * if non-NULL, and when lr > 0 one bias-corrected Adam step (0.9, 0.999,
+ * 1e-8; step counts from 1) updates theta, adam_m, adam_v in place;
+ * *loss (host, may be NULL: no synchronisation) receives the batch loss at
+ * the incoming theta. crk_hnet_seed: H_seed = H_prev exp(y) on the last
+ * build's particles, clamped to [H_prev/8, 8 H_prev] and below L/2 (a
+ * non-finite y keeps H_prev); H_prev and H_seed are sorted-order doubles.
+ */
+crk_status crk_hnet_features(crk_ctx *ctx, double Nres, const double *H_sorted, float *feat);
+crk_status crk_hnet_forward(crk_ctx *ctx, const float *theta, const float *feat, int64_t nb,
+                            float *y);
+crk_status crk_hnet_train_step(crk_ctx *ctx, float *theta, float *adam_m, float *adam_v,
+                               int64_t step, float lr, const float *feat, const float *target,
+                               int64_t nb, float *grad, float *loss);
+crk_status crk_hnet_seed(crk_ctx *ctx, const float *theta, double Nres, const double *H_prev,
+                         double *H_seed);
+
+/*
  * Neighbour lists of the last build, for checking: which = 0 gives N_g
  * (self included), which = 1 gives N_s. offsets[n+1] (device int64) and
  * idx[cap] (device int32, SORTED-order indices). Rows are not ordered.
@@ -213,6 +249,13 @@ crk_status crk_export_neighbors(crk_ctx *ctx, int32_t which, int64_t *offsets, i
 crk_status crk_set_lanes(crk_ctx *ctx, int32_t g_vol, int32_t g_mom, int32_t g_grad,
                          int32_t g_der);
 
+/* Neighbour walk of crk_build_cells / crk_update_support (tuning only: the
+ * lists do not depend on it): lanes (1, 2, 4, 8 or 16) of a wavefront share
+ * one particle's walk; each row is first written to a scratch row of cap
+ * slots, and rows longer than cap are walked again into place. 0 keeps the
+ * current value. */
+crk_status crk_set_walk(crk_ctx *ctx, int32_t lanes, int32_t cap);
+
 /* Per-kernel timing (off by default). While enabled, every kernel launch of
  * the library is bracketed by a pair of HIP events recorded on the context's
  * stream. crk_timing_read synchronises the stream and returns the summed
@@ -222,6 +265,10 @@ crk_status crk_set_lanes(crk_ctx *ctx, int32_t g_vol, int32_t g_mom, int32_t g_g
 crk_status crk_timing_enable(crk_ctx *ctx, int32_t on);
 crk_status crk_timing_reset(crk_ctx *ctx);
 crk_status crk_timing_read(crk_ctx *ctx, const char *kernel, double *total_ms, int64_t *launches);
+
+/* Rows the last CRK_MIXED_ADAPT crk_derivatives call ran in FP64: particles
+ * over kappa_max, and particles with such a partner (host values). */
+crk_status crk_adaptive_rows(crk_ctx *ctx, int64_t *n_fp64_rows, int64_t *n_touched_rows);
 
 /* Library version string. */
 const char *crk_version(void);

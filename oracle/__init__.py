@@ -71,6 +71,7 @@ def lib():
         L.orc_derivatives.argtypes = [_i64, _p, _p, _p, _p, _d, _int] + [_p] * 16
         L.orc_thacker_step.restype = _d
         L.orc_thacker_step.argtypes = [_d, _d, _d]
+        L.orc_hnet_features.argtypes = [_i64, _p, _p, _p, _p, _d, _d, _p]
         L.orc_hsolve.restype = _i64
         L.orc_hsolve.argtypes = [_i64, _p, _p, _p, _d, _int, _d, _d, _int, _p, _p]
         _lib = L
@@ -245,6 +246,15 @@ def hsolve(x, y, z, H0, Nres, tol=1e-7, max_iter=100, L=1.0, periodic=True):
     nf = lib().orc_hsolve(x.shape[0], _ptr(x), _ptr(y), _ptr(z), L, int(periodic), float(Nres),
                           float(tol), int(max_iter), _ptr(H), _ptr(it))
     return H, it, int(nf)
+
+
+def hnet_features(x, y, z, H, Nres, L=1.0):
+    """[8, n] input features of the smoothing-length network at radius H."""
+    x, y, z, H = map(_f64, (x, y, z, H))
+    n = x.shape[0]
+    out = np.empty((8, n))
+    lib().orc_hnet_features(n, _ptr(x), _ptr(y), _ptr(z), _ptr(H), float(L), float(Nres), _ptr(out))
+    return out
 
 
 def pipeline(ps, prm, periodic=True, method="auto"):

@@ -792,3 +792,67 @@ int64_t orc_hsolve(int64_t n, const double *x, const double *y, const double *z,
     if (use_grid) orc_grid_free(&g);
     return nfail;
 }
+
+/* ------------------------------------------------------------------ */
+/* Input features of the smoothing-length network (not in the paper;   */
+/* they feed a learned starting value for the iteration of eq. thacker).*/
+/* From one pass over the support of radius H = H_i, with              */
+/* N_w(h) = (4 pi / 3) h^3 sum_{r < h} W(r, h) (eq. hi, self included)  */
+/* and n_raw(h) = #{j : r < h} (self included):                         */
+/*   f0 = ln(N_w(H) / N_res)          f1 = (N_res / N_w(H))^(1/3) - 1   */
+/*   f2 = ln(8 N_w(H/2) / N_res)      f3 = ln(64 N_w(H/4) / N_res)      */
+/*   f4 = ln(n_raw(H) / N_res)        f5 = ln(8 n_raw(H/2) / N_res)     */
+/*   f6 = ln(H N_tot^(1/3) / L)       f7 = 1                            */
+/* feat is [8][n].                                                     */
+/* ------------------------------------------------------------------ */
+void orc_hnet_features(int64_t n, const double *x, const double *y, const double *z,
+                       const double *H, double L, double Nres, double *feat)
+{
+    orc_grid g;
+    int use_grid = n > 4096;
+    if (use_grid) orc_grid_build(&g, n, x, y, z, H, L);
+    #pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t i = 0; i < n; i++) {
+        double h = H[i];
+        double s1 = 0.0, s2 = 0.0, s4 = 0.0, c1 = 0.0, c2 = 0.0;
+        int64_t jb = 0, je = n;
+        int lx = 0, ly = 0, lz = 0, mx = 1, my = 1, mz = 1;
+        if (use_grid) {
+            orc_axis_range(x[i], h, &g, &lx, &mx);
+            orc_axis_range(y[i], h, &g, &ly, &my);
+            orc_axis_range(z[i], h, &g, &lz, &mz);
+        }
+        for (int a = 0; a < mz; a++)
+            for (int b = 0; b < my; b++)
+                for (int e = 0; e < mx; e++) {
+                    if (use_grid) {
+                        int64_t cell = ((int64_t)orc_mod(lz + a, g.nc) * g.nc + orc_mod(ly + b, g.nc)) * g.nc
+                                       + orc_mod(lx + e, g.nc);
+                        jb = g.start[cell];
+                        je = g.start[cell + 1];
+                    }
+                    for (int64_t k = jb; k < je; k++) {
+                        int64_t j = use_grid ? g.list[k] : k;
+                        double d[3];
+                        double r2 = orc_sep(x, y, z, i, j, L, 1, d);
+                        double r = sqrt(r2);
+                        if (r2 < h * h) { s1 += orc_W(r, h); c1 += 1.0; }
+                        if (r2 < 0.25 * h * h) { s2 += orc_W(r, 0.5 * h); c2 += 1.0; }
+                        if (r2 < 0.0625 * h * h) s4 += orc_W(r, 0.25 * h);
+                    }
+                }
+        double v = 4.0 / 3.0 * ORC_PI;
+        double N1 = v * h * h * h * s1;
+        double N2 = v * 0.125 * h * h * h * s2;
+        double N4 = v * h * h * h / 64.0 * s4;
+        feat[0 * n + i] = log(N1 / Nres);
+        feat[1 * n + i] = cbrt(Nres / N1) - 1.0;
+        feat[2 * n + i] = log(8.0 * N2 / Nres);
+        feat[3 * n + i] = log(64.0 * N4 / Nres);
+        feat[4 * n + i] = log(c1 / Nres);
+        feat[5 * n + i] = log(8.0 * c2 / Nres);
+        feat[6 * n + i] = log(h * cbrt((double)n) / L);
+        feat[7 * n + i] = 1.0;
+    }
+    if (use_grid) orc_grid_free(&g);
+}

@@ -6,8 +6,8 @@ arithmetic runs in the library's HIP kernels. Importing this package never
 falls back to anything else: if the library is missing or no GPU is present,
 the calls raise.
 """
-from ._lib import (CRK_FP64, CRK_MIXED, CRK_MIXED_M64, CrkError, Context, Params, lib, library_path,
+from ._lib import (CRK_FP64, CRK_MIXED, CRK_MIXED_ADAPT, CrkError, Context, Params, lib, library_path,
                    version)
 
-__all__ = ["CRK_FP64", "CRK_MIXED", "CRK_MIXED_M64", "CrkError", "Context", "Params", "lib", "library_path",
+__all__ = ["CRK_FP64", "CRK_MIXED", "CRK_MIXED_ADAPT", "CrkError", "Context", "Params", "lib", "library_path",
            "version"]

@@ -9,7 +9,7 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIBPATH = os.path.join(_HERE, "libcrk.so")
 
-CRK_FP64, CRK_MIXED, CRK_MIXED_M64 = 0, 1, 2
+CRK_FP64, CRK_MIXED, CRK_MIXED_ADAPT = 0, 1, 2
 STATUS = {0: "CRK_OK", 1: "CRK_WARN_SINGULAR", 2: "CRK_WARN_NOT_CONVERGED",
           -1: "CRK_ERR_INVALID_ARG", -2: "CRK_ERR_NONFINITE", -3: "CRK_ERR_SUPPORT",
           -4: "CRK_ERR_WORKSPACE", -5: "CRK_ERR_HIP", -6: "CRK_ERR_STATE"}
@@ -17,8 +17,10 @@ STATUS = {0: "CRK_OK", 1: "CRK_WARN_SINGULAR", 2: "CRK_WARN_NOT_CONVERGED",
 # every symbol include/crk.h declares
 EXPORTS = ("crk_params_default", "crk_create", "crk_destroy", "crk_last_error", "crk_build_cells",
            "crk_update_support", "crk_permute", "crk_moments", "crk_corrections",
-           "crk_derivatives", "crk_hsolve", "crk_export_neighbors", "crk_set_lanes",
-           "crk_timing_enable", "crk_timing_reset", "crk_timing_read", "crk_version")
+           "crk_derivatives", "crk_hsolve", "crk_export_neighbors", "crk_set_lanes", "crk_set_walk",
+           "crk_timing_enable", "crk_timing_reset", "crk_timing_read", "crk_adaptive_rows",
+           "crk_hnet_features", "crk_hnet_forward", "crk_hnet_train_step", "crk_hnet_seed",
+           "crk_version")
 
 
 class CrkError(RuntimeError):
@@ -29,7 +31,7 @@ class CrkError(RuntimeError):
 
 class Params(C.Structure):
     _fields_ = [(k, C.c_double) for k in ("L", "gamma", "Cl", "Cq", "eps", "nh", "eta_crit",
-                                          "eta_fold", "a", "adot")] + \
+                                          "eta_fold", "a", "adot", "kappa_max")] + \
                [("precision", C.c_int32), ("reserved", C.c_int32)]
 
     @classmethod
@@ -75,9 +77,15 @@ def lib():
             "crk_hsolve": ([p, d, d, i32, p, p, p], i32),
             "crk_export_neighbors": ([p, i32, p, p, i64, p], i32),
             "crk_set_lanes": ([p, i32, i32, i32, i32], i32),
+            "crk_set_walk": ([p, i32, i32], i32),
             "crk_timing_enable": ([p, i32], i32),
             "crk_timing_reset": ([p], i32),
             "crk_timing_read": ([p, C.c_char_p, p, p], i32),
+            "crk_adaptive_rows": ([p, p, p], i32),
+            "crk_hnet_features": ([p, d, p, p], i32),
+            "crk_hnet_forward": ([p, p, p, i64, p], i32),
+            "crk_hnet_train_step": ([p, p, p, p, i64, C.c_float, p, p, i64, p, p], i32),
+            "crk_hnet_seed": ([p, p, d, p, p], i32),
             "crk_version": ([], C.c_char_p),
         }
         for name, (args, res) in sigs.items():
@@ -251,6 +259,49 @@ class Context:
         self._check(lib().crk_timing_read(self._h, kernel.encode(), C.byref(ms), C.byref(cnt)),
                     "crk_timing_read")
         return ms.value, cnt.value
+
+    def adaptive_rows(self):
+        """(FP64 rows, touched rows) of the last adaptive derivative pass."""
+        a, b = C.c_int64(), C.c_int64()
+        self._check(lib().crk_adaptive_rows(self._h, C.byref(a), C.byref(b)), "crk_adaptive_rows")
+        return a.value, b.value
+
+    # ---------------------------------------------------------------- S9
+    def hnet_features(self, Nres: float, H_sorted):
+        _f64(H_sorted)
+        feat = self._empty(8, self.n, dtype=torch.float32)
+        self._check(lib().crk_hnet_features(self._h, C.c_double(Nres), _ptr(H_sorted), _ptr(feat)),
+                    "crk_hnet_features")
+        return feat
+
+    def hnet_forward(self, theta, feat):
+        nb = feat.shape[1]
+        y = self._empty(nb, dtype=torch.float32)
+        self._check(lib().crk_hnet_forward(self._h, _ptr(theta), _ptr(feat), nb, _ptr(y)),
+                    "crk_hnet_forward")
+        return y
+
+    def hnet_train_step(self, theta, m, v, step: int, lr: float, feat, target, want_grad=False,
+                        want_loss=False):
+        """One Adam step in place on theta/m/v (lr > 0); returns (grad, loss)."""
+        nb = feat.shape[1]
+        grad = self._empty(theta.shape[0], dtype=torch.float32) if want_grad else None
+        loss = C.c_float()
+        self._check(lib().crk_hnet_train_step(self._h, _ptr(theta), _ptr(m), _ptr(v), step,
+                                              C.c_float(lr), _ptr(feat), _ptr(target), nb,
+                                              _ptr(grad), C.byref(loss) if want_loss else None),
+                    "crk_hnet_train_step")
+        return grad, (loss.value if want_loss else None)
+
+    def hnet_seed(self, theta, Nres: float, H_prev_sorted):
+        _f64(H_prev_sorted)
+        out = torch.empty_like(H_prev_sorted)
+        self._check(lib().crk_hnet_seed(self._h, _ptr(theta), C.c_double(Nres),
+                                        _ptr(H_prev_sorted), _ptr(out)), "crk_hnet_seed")
+        return out
+
+    def set_walk(self, lanes: int = 0, cap: int = 0):
+        self._check(lib().crk_set_walk(self._h, lanes, cap), "crk_set_walk")
 
     def set_lanes(self, vol: int = 0, mom: int = 0, grad: int = 0, der: int = 0):
         self._check(lib().crk_set_lanes(self._h, vol, mom, grad, der), "crk_set_lanes")

@@ -139,6 +139,7 @@ crk_status crk_params_default(crk_params *p, double Nres) {
     p->eta_fold = 0.2 / nh;
     p->a = 1.0;
     p->adot = 0.0;
+    p->kappa_max = 1000.0;
     p->precision = CRK_FP64;
     p->reserved = 0;
     return CRK_OK;
@@ -179,7 +180,9 @@ void crk_destroy(crk_ctx *c) {
     crk::Buf *all[] = {&c->posH, &c->perm,  &c->cbeg,  &c->cend, &c->goff, &c->gidx, &c->ng,
                        &c->nes,  &c->esoff, &c->eb,    &c->ee,   &c->ekey, &c->eidx, &c->keyA,
                        &c->keyB, &c->valA,  &c->valB,  &c->hist, &c->scanTmp, &c->recV,
-                       &c->rec6, &c->rec7,  &c->red,   &c->misc};
+                       &c->rec6, &c->rec7,  &c->red,   &c->misc, &c->flag, &c->flist,
+                       &c->tlist, &c->fpos, &c->tpos,  &c->rec6d, &c->aux, &c->scratch,
+                       &c->hnet_part, &c->hnet_feat};
     for (crk::Buf *b : all)
         if (b->p) hipFree(b->p);
     if (c->pinned.p) hipHostFree(c->pinned.p);

@@ -121,46 +121,131 @@ __global__ __launch_bounds__(kBlock) void k_tables(const uint32_t *skey, int64_t
     }
 }
 
-// Gather walk of particle i: every j != i with r^2 < H_i^2, in cell-walk
-// order. Such a pair is also an "extra" of j when r^2 >= H_j^2 (j's own
-// support does not reach i, but the pair is in N_s(j) through H_i).
-// MODE 0 counts both kinds per i; MODE 1 writes the gather row of i and the
-// (j, i) extras that i emits, at offsets from the scans of the counts.
-template <int MODE>
-__global__ __launch_bounds__(kBlock) void k_walk(const double4 *__restrict__ posH, int64_t n, Levels v,
-                                                 const int32_t *__restrict__ cbeg,
-                                                 const int32_t *__restrict__ cend, int32_t *ng,
-                                                 int32_t *nes, const int64_t *__restrict__ goff,
-                                                 int32_t *gidx, const int64_t *__restrict__ esoff,
-                                                 uint32_t *ekey, int32_t *eval) {
-    int64_t i = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
-    if (i >= n) return;
+// Single-pass walk of particle i by a group of G lanes of one wavefront:
+// the group visits i's cells in order and takes each cell's particles G at a
+// time (consecutive, so the loads coalesce). A ballot over the group orders
+// the hits exactly as a serial walk would, so row i is the same list for
+// every G. Row entries go to a per-particle scratch of `cap` slots, with bit
+// 31 marking the pairs that are extras of j; ng/nes count every hit, so a
+// row longer than cap is detected and walked again (DIRECT) into its final
+// place.
+// DIRECT = true is the second walk of rows longer than cap: it writes the
+// gather row and the extras straight to their final places.
+template <int G, bool DIRECT>
+__global__ __launch_bounds__(kBlock) void k_walk_scratch(const double4 *__restrict__ posH, int64_t n,
+                                                         Levels v, const int32_t *__restrict__ cbeg,
+                                                         const int32_t *__restrict__ cend, int cap,
+                                                         uint32_t *scratch, int32_t *ng, int32_t *nes,
+                                                         const int64_t *__restrict__ goff, int32_t *gidx,
+                                                         const int64_t *__restrict__ esoff,
+                                                         uint32_t *ekey, int32_t *eval) {
+    int64_t gid = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    const int l = (int)(gid % G);
+    const int64_t i = gid / G;
+    if (i >= n) return;   // whole groups leave together (G divides the block)
+    if (DIRECT && ng[i] <= cap) return;
     const double4 pi = posH[i];
     const double H2 = pi.w * pi.w;
+    const int lane = threadIdx.x & 63;
+    const int gshift = lane - l;
+    const uint64_t below = (l == 0) ? 0ull : (((uint64_t)1 << l) - 1);
     int32_t cg = 0, ce = 0;
-    int64_t gw = MODE ? goff[i] : 0, ew = MODE ? esoff[i] : 0;
-    walk_cells(v, cbeg, cend, pi.x, pi.y, pi.z, pi.w, [&](int j) {
-        double4 pj = posH[j];
-        double dx = min_image(pi.x - pj.x, v.L, v.hL);
-        double dy = min_image(pi.y - pj.y, v.L, v.hL);
-        double dz = min_image(pi.z - pj.z, v.L, v.hL);
-        double r2 = r2_exact(dx, dy, dz);
-        if (r2 < H2 && j != i) {
-            bool extra = !(r2 < pj.w * pj.w);
-            if (MODE == 1) {
-                gidx[gw + cg] = j;
-                if (extra) {
-                    ekey[ew + ce] = (uint32_t)j;
-                    eval[ew + ce] = (int32_t)i;
+    uint32_t *row = scratch + (size_t)i * cap;
+    int k = level_for(pi.w, v);
+    int nck = 1 << (v.bits - k);
+    Grid g{v.L, v.hL, (double)nck / v.L, v.margin, nck};
+    int lx, ly, lz, mx, my, mz;
+    axis_range(pi.x, pi.w, g, lx, mx);
+    axis_range(pi.y, pi.w, g, ly, my);
+    axis_range(pi.z, pi.w, g, lz, mz);
+    const int32_t *cb = cbeg + v.off[k], *ce_ = cend + v.off[k];
+    for (int a = 0; a < mz; a++) {
+        uint32_t mzb = spread3(wrapc(lz + a, nck)) << 2;
+        for (int b = 0; b < my; b++) {
+            uint32_t myb = mzb | (spread3(wrapc(ly + b, nck)) << 1);
+            for (int e = 0; e < mx; e++) {
+                uint32_t id = myb | spread3(wrapc(lx + e, nck));
+                int jb = cb[id], je = ce_[id];
+                for (int j0 = jb; j0 < je; j0 += G) {
+                    int j = j0 + l;
+                    bool hit = false, extra = false;
+                    if (j < je) {
+                        double4 pj = posH[j];
+                        double dx = min_image(pi.x - pj.x, v.L, v.hL);
+                        double dy = min_image(pi.y - pj.y, v.L, v.hL);
+                        double dz = min_image(pi.z - pj.z, v.L, v.hL);
+                        double r2 = r2_exact(dx, dy, dz);
+                        hit = r2 < H2 && (int64_t)j != i;
+                        extra = hit && !(r2 < pj.w * pj.w);
+                    }
+                    uint32_t hm, em;
+                    if (G == 1) {
+                        hm = hit;
+                        em = extra;
+                    } else {
+                        uint64_t mh = __ballot(hit), mx_ = __ballot(extra);
+                        hm = (uint32_t)((mh >> gshift) & ((G == 64) ? ~0ull : (((uint64_t)1 << G) - 1)));
+                        em = (uint32_t)((mx_ >> gshift) & ((G == 64) ? ~0ull : (((uint64_t)1 << G) - 1)));
+                    }
+                    if (hit) {
+                        int pos = cg + (G == 1 ? 0 : __popc(hm & (uint32_t)below));
+                        if (DIRECT) {
+                            gidx[goff[i] + pos] = j;
+                            if (extra) {
+                                int ep = ce + (G == 1 ? 0 : __popc(em & (uint32_t)below));
+                                ekey[esoff[i] + ep] = (uint32_t)j;
+                                eval[esoff[i] + ep] = (int32_t)i;
+                            }
+                        } else if (pos < cap) {
+                            row[pos] = (uint32_t)j | (extra ? 0x80000000u : 0u);
+                        }
+                    }
+                    cg += __popc(hm);
+                    ce += __popc(em);
                 }
             }
-            cg++;
-            ce += extra ? 1 : 0;
         }
-    });
-    if (MODE == 0) {
+    }
+    if (!DIRECT && l == 0) {
         ng[i] = cg;
         nes[i] = ce;
+    }
+}
+
+// scratch rows -> gather rows and (j, i) extras, for rows that fit in cap;
+// G lanes per row read and write consecutive slots, and a ballot keeps the
+// extras in row order
+template <int G>
+__global__ __launch_bounds__(kBlock) void k_compact_rows(const uint32_t *__restrict__ scratch, int cap,
+                                                         int64_t n, const int32_t *__restrict__ ng,
+                                                         const int64_t *__restrict__ goff,
+                                                         const int64_t *__restrict__ esoff,
+                                                         int32_t *gidx, uint32_t *ekey, int32_t *eval) {
+    int64_t gid = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    const int l = (int)(gid % G);
+    const int64_t i = gid / G;
+    if (i >= n) return;
+    const int cnt = ng[i];
+    if (cnt > cap) return;
+    const int gshift = (threadIdx.x & 63) - l;
+    const uint32_t below = (l == 0) ? 0u : ((1u << l) - 1u);
+    const uint32_t *row = scratch + (size_t)i * cap;
+    const int64_t gw = goff[i], ew = esoff[i];
+    int e = 0;
+    for (int k0 = 0; k0 < cnt; k0 += G) {
+        int k = k0 + l;
+        bool valid = k < cnt;
+        uint32_t w = valid ? row[k] : 0u;
+        int32_t j = (int32_t)(w & 0x7fffffffu);
+        if (valid) gidx[gw + k] = j;
+        bool isx = valid && (w & 0x80000000u);
+        uint32_t gm = (uint32_t)((__ballot(isx) >> gshift) & ((1ull << G) - 1));
+        if (isx) {
+            int p = e + __popc(gm & below);
+            ekey[ew + p] = (uint32_t)j;
+            eval[ew + p] = (int32_t)i;
+        }
+        e += __popc(gm);
     }
 }
 
@@ -270,10 +355,23 @@ static crk_status build_lists(crk_ctx *c) {
     int64_t *goff = (int64_t *)c->goff.p, *esoff = (int64_t *)c->esoff.p;
     const double4 *posH = (const double4 *)c->posH.p;
     const int32_t *cbeg = (const int32_t *)c->cbeg.p, *cend = (const int32_t *)c->cend.p;
+    // one walk into a capped scratch row per particle; exact counts come with it
+    const int cap = c->walk_cap;
+    CRK_TRY(ensure(c, c->scratch, (size_t)n * cap * sizeof(uint32_t)));
+    uint32_t *scratch = (uint32_t *)c->scratch.p;
     {
-        KTimer kt_(c, "k_walk_count");
-        k_walk<0><<<nblocks(n), kBlock, 0, c->stream>>>(posH, n, v, cbeg, cend, ng, nes, nullptr,
-                                                         nullptr, nullptr, nullptr, nullptr);
+        KTimer kt_(c, "k_walk");
+        int G = c->G_walk;
+#define L_WALK(GG) k_walk_scratch<GG, false><<<(unsigned)((n * GG + kBlock - 1) / kBlock), kBlock, 0, c->stream>>>(posH, n, v, cbeg, cend, cap, scratch, ng, nes, nullptr, nullptr, nullptr, nullptr, nullptr)
+        switch (G) {
+            case 1: L_WALK(1); break;
+            case 2: L_WALK(2); break;
+            case 4: L_WALK(4); break;
+            case 8: L_WALK(8); break;
+            case 16: L_WALK(16); break;
+            default: return set_err(c, CRK_ERR_INVALID_ARG, "walk lanes must be 1, 2, 4, 8 or 16");
+        }
+#undef L_WALK
     }
     CRK_HIP(c, hipGetLastError());
     k_to_i64<<<nblocks(n + 1), kBlock, 0, c->stream>>>(ng, n, goff);
@@ -294,9 +392,24 @@ static crk_status build_lists(crk_ctx *c) {
     uint32_t *ekey = (uint32_t *)c->ekey.p;
     int32_t *eidx = (int32_t *)c->eidx.p;
     {
-        KTimer kt_(c, "k_walk_fill");
-        k_walk<1><<<nblocks(n), kBlock, 0, c->stream>>>(posH, n, v, cbeg, cend, ng, nes, goff,
-                                                         (int32_t *)c->gidx.p, esoff, ekey, eidx);
+        KTimer kt_(c, "k_compact_rows");
+        constexpr int GC = 16;
+        k_compact_rows<GC><<<(unsigned)((n * GC + kBlock - 1) / kBlock), kBlock, 0, c->stream>>>(
+            scratch, cap, n, ng, goff, esoff, (int32_t *)c->gidx.p, ekey, eidx);
+    }
+    {
+        KTimer kt_(c, "k_walk_long");
+        int G = c->G_walk;
+#define L_WALK(GG) k_walk_scratch<GG, true><<<(unsigned)((n * GG + kBlock - 1) / kBlock), kBlock, 0, c->stream>>>(posH, n, v, cbeg, cend, cap, nullptr, ng, nes, goff, (int32_t *)c->gidx.p, esoff, ekey, eidx)
+        switch (G) {
+            case 1: L_WALK(1); break;
+            case 2: L_WALK(2); break;
+            case 4: L_WALK(4); break;
+            case 8: L_WALK(8); break;
+            case 16: L_WALK(16); break;
+            default: return set_err(c, CRK_ERR_INVALID_ARG, "walk lanes must be 1, 2, 4, 8 or 16");
+        }
+#undef L_WALK
     }
     CRK_HIP(c, hipGetLastError());
     // extras arrive grouped by the emitting particle i (ascending); a stable

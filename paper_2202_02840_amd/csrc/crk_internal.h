@@ -69,10 +69,16 @@ struct crk_ctx {
     crk::Buf posH, perm, cbeg, cend, goff, gidx, ng, nes, esoff, eb, ee, ekey, eidx;
     crk::Buf keyA, keyB, valA, valB, hist, scanTmp;
     crk::Buf recV, rec6, rec7, red, misc;
+    crk::Buf flag, flist, tlist, fpos, tpos, rec6d, aux;   // adaptive-precision rows
+    crk::Buf scratch;                                     // walk rows before compaction
+    crk::Buf hnet_part, hnet_feat;                        // network gradients / features
+    int64_t last_nflag = 0, last_ntouch = 0;
     crk::Buf pinned;        // small host-pinned readback area
 
     // per-pass tuning: lanes per particle (1..64)
     int G_vol = 4, G_mom = 1, G_grad = 4, G_der = 8;
+    // neighbour walk: lanes per particle and scratch slots per row
+    int G_walk = 4, walk_cap = 192;
 
     // per-kernel timing with HIP events on `stream` (crk_timing_*)
     int timing = 0;

@@ -328,19 +328,28 @@ __device__ __forceinline__ void rk_grad(const Coef<T> &k, const T d[3], T w, T g
     }
 }
 
+// i = list[g] when a list is given (the FP64 rows of the adaptive mode),
+// else i = g; rows with skip[i] set are left to another launch.
 template <typename T, int G>
 __global__ __launch_bounds__(kBlock) void k_gradv(const double4 *__restrict__ posH,
                                                   const int64_t *__restrict__ goff,
-                                                   const int32_t *__restrict__ gidx,
+                                                  const int32_t *__restrict__ gidx,
                                                   const typename std::conditional<sizeof(T) == 4, float4, double4>::type *__restrict__ rec6,
                                                   const double *__restrict__ A, const double *__restrict__ B,
                                                   const double *__restrict__ gA,
                                                   const double *__restrict__ gB, int64_t n, Box box,
-                                                  double *gradv) {
+                                                  const int32_t *__restrict__ list, int64_t nlist,
+                                                  const int32_t *__restrict__ skip, double *gradv) {
     int l;
-    int64_t i = group_index(G, l);
+    int64_t g = group_index(G, l);
+    int64_t i = -1;
+    if (list) {
+        if (g < nlist) i = list[g];
+    } else if (g < n && !(skip && skip[g])) {
+        i = g;
+    }
     Acc<T> a[9];
-    if (i < n) {
+    if (i >= 0) {
         double4 pi = posH[i];
         T invH = (T)(1.0 / pi.w);
         T invH2 = invH * invH;
@@ -378,7 +387,7 @@ __global__ __launch_bounds__(kBlock) void k_gradv(const double4 *__restrict__ po
         }
     }
     group_reduce<T, G, 9>(a);
-    if (i < n && l == 0)
+    if (i >= 0 && l == 0)
 #pragma unroll
         for (int s = 0; s < 9; s++) gradv[s * n + i] = a[s].value();
 }
@@ -387,7 +396,7 @@ __global__ __launch_bounds__(kBlock) void k_gradv(const double4 *__restrict__ po
 // Packed per-particle state, nine 4-vectors:
 //   0 {vx, vy, vz, V}   1 {rho, P, cs, A}   2 {Bx, By, Bz, 1/H}   3 {dAx, dAy, dAz, H/nh}
 //   4 {gB0..gB3}        5 {gB4..gB7}        6 {gB8, gv0, gv1, gv2}
-//   7 {gv3..gv6}        8 {gv7, gv8, 0, 0}
+//   7 {gv3..gv6}        8 {gv7, gv8, fp64-row flag, 0}
 constexpr int kRec7 = 9;
 
 struct DerivPrm {
@@ -399,7 +408,8 @@ __global__ __launch_bounds__(kBlock) void k_pack7(int64_t n, const double4 *__re
                                                   const double *v, const double *m, const double *u,
                                                   const double *rho, const double *V, const double *A,
                                                   const double *B, const double *gA, const double *gB,
-                                                  const double *gv, DerivPrm p, V4 *rec, int *bad) {
+                                                  const double *gv, DerivPrm p, const int32_t *flag,
+                                                  V4 *rec, double4 *aux, int *bad) {
     int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i >= n) return;
     double Vi = V[i];
@@ -419,15 +429,46 @@ __global__ __launch_bounds__(kBlock) void k_pack7(int64_t n, const double4 *__re
     o[5] = V4{(T)gB[4 * n + i], (T)gB[5 * n + i], (T)gB[6 * n + i], (T)gB[7 * n + i]};
     o[6] = V4{(T)gB[8 * n + i], (T)gv[i], (T)gv[n + i], (T)gv[2 * n + i]};
     o[7] = V4{(T)gv[3 * n + i], (T)gv[4 * n + i], (T)gv[5 * n + i], (T)gv[6 * n + i]};
-    o[8] = V4{(T)gv[7 * n + i], (T)gv[8 * n + i], (T)0, (T)0};
+    o[8] = V4{(T)gv[7 * n + i], (T)gv[8 * n + i], (T)(flag ? flag[i] : 0), (T)0};
+    if (aux) aux[i] = make_double4(r, P, cs, H * p.inv_nh);
 }
 
 template <typename T>
 struct State {
-    T v[3], V, rho, P, cs, invH, hh;
+    T v[3], V, rho, P, cs, invH, hh, fl;
     Coef<T> k;
     T gv[9];
 };
+
+// FP64 state from the boundary arrays (rows of the adaptive mode's FP64 launch)
+struct Soa {
+    const double *v, *V, *A, *B, *gA, *gB, *gv;
+    const double4 *aux;
+};
+
+__device__ __forceinline__ void load_state_soa(const Soa &a, const double4 *__restrict__ posH, int64_t n,
+                                               int64_t j, State<double> &s) {
+#pragma unroll
+    for (int x = 0; x < 3; x++) {
+        s.v[x] = a.v[x * n + j];
+        s.k.B[x] = a.B[x * n + j];
+        s.k.gA[x] = a.gA[x * n + j];
+    }
+#pragma unroll
+    for (int q = 0; q < 9; q++) {
+        s.k.gB[q] = a.gB[q * n + j];
+        s.gv[q] = a.gv[q * n + j];
+    }
+    s.V = a.V[j];
+    s.k.A = a.A[j];
+    double4 x = a.aux[j];
+    s.rho = x.x;
+    s.P = x.y;
+    s.cs = x.z;
+    s.hh = x.w;
+    s.invH = 1.0 / posH[j].w;
+    s.fl = 0.0;
+}
 
 template <typename V4, typename T>
 __device__ __forceinline__ void load_state(const V4 *__restrict__ rec, int64_t j, State<T> &s) {
@@ -442,9 +483,83 @@ __device__ __forceinline__ void load_state(const V4 *__restrict__ rec, int64_t j
     s.k.gB[4] = r5.x; s.k.gB[5] = r5.y; s.k.gB[6] = r5.z; s.k.gB[7] = r5.w;
     s.k.gB[8] = r6.x; s.gv[0] = r6.y; s.gv[1] = r6.z; s.gv[2] = r6.w;
     s.gv[3] = r7.x; s.gv[4] = r7.y; s.gv[5] = r7.z; s.gv[6] = r7.w;
-    s.gv[7] = r8.x; s.gv[8] = r8.y;
+    s.gv[7] = r8.x; s.gv[8] = r8.y; s.fl = r8.z;
 }
 
+// One ordered pair of eqs. (mom) and (eng) with P -> P + Q: adds
+// (a^2/2) V_i V_j (P_i+Q_i+P_j+Q_j) D to F and (1/(2a^2)) V_i V_j (P_j+Q_j)
+// (xdot_j - xdot_i).D to E, D = grad W^R_ji - grad W^R_ij.
+template <typename T>
+struct PairConst {
+    T Cl, Cq, eps2, inv_a, adot, eta_c, inv_eta_f, half_a2, half_inv_a2;
+};
+
+template <typename T>
+__device__ __forceinline__ void deriv_pair(const State<T> &si, const State<T> &sj, const T d[3],
+                                           const PairConst<T> &pc, T cwi, T cgi, T F[3], T &E) {
+    T r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+    T r = Mth<T>::sqrt(r2);
+    T qi = r * si.invH, qj = r * sj.invH;
+    T cwj = (T)kW * sj.invH * sj.invH * sj.invH;
+    T cgj = (T)kG * sj.invH * sj.invH * sj.invH * sj.invH * sj.invH;
+    T wi, gfi, wj, gfj;
+    kernel_wg(qi, cwi, cgi, wi, gfi);
+    kernel_wg(qj, cwj, cgj, wj, gfj);
+    // grad W^R_ij (i's coefficients, +d) and grad W^R_ji (j's, -d)
+    T Gij[3], Gji[3], md[3] = {-d[0], -d[1], -d[2]};
+    rk_grad(si.k, d, wi, gfi, Gij);
+    rk_grad(sj.k, md, wj, gfj, Gji);
+    T D[3] = {Gji[0] - Gij[0], Gji[1] - Gij[1], Gji[2] - Gij[2]};
+    // limiter, eqs. (phi)-(phiad)
+    T gvi[3], gvj[3];
+#pragma unroll
+    for (int x = 0; x < 3; x++) {
+        gvi[x] = si.gv[x * 3 + 0] * d[0] + si.gv[x * 3 + 1] * d[1] + si.gv[x * 3 + 2] * d[2];
+        gvj[x] = sj.gv[x * 3 + 0] * d[0] + sj.gv[x * 3 + 1] * d[1] + sj.gv[x * 3 + 2] * d[2];
+    }
+    T s_i = d[0] * gvi[0] + d[1] * gvi[1] + d[2] * gvi[2];
+    T s_j = d[0] * gvj[0] + d[1] * gvj[1] + d[2] * gvj[2];
+    T prod = s_i * s_j;
+    T phi = (T)0;
+    if (prod > (T)0) {
+        T sum = s_i + s_j;
+        phi = (T)4 * prod * Mth<T>::rcp(sum * sum);
+        phi = phi < (T)1 ? phi : (T)1;
+        T eta = qi < qj ? qi : qj;
+        if (eta < pc.eta_c) {
+            T x = (eta - pc.eta_c) * pc.inv_eta_f;
+            phi *= Mth<T>::exp(-x * x);
+        }
+    }
+    // projected velocity difference, eq. (hatvi), and eq. (mu)
+    T hp = (T)0.5 * phi;
+    T ud = (T)0;
+#pragma unroll
+    for (int x = 0; x < 3; x++) ud += ((si.v[x] - sj.v[x]) - hp * (gvi[x] + gvj[x]) + pc.adot * d[x]) * d[x];
+    T Qi = (T)0, Qj = (T)0;
+    if (ud < (T)0) {
+        T mui = si.hh * pc.inv_a * ud * Mth<T>::rcp(r2 + si.hh * si.hh * pc.eps2);
+        T muj = sj.hh * pc.inv_a * ud * Mth<T>::rcp(r2 + sj.hh * sj.hh * pc.eps2);
+        Qi = si.rho * (-pc.Cl * si.cs * mui + pc.Cq * mui * mui);
+        Qj = sj.rho * (-pc.Cl * sj.cs * muj + pc.Cq * muj * muj);
+    }
+    T fm = pc.half_a2 * si.V * sj.V * (si.P + Qi + sj.P + Qj);
+    T fe = pc.half_inv_a2 * si.V * sj.V * (sj.P + Qj);
+    T xdd = ((sj.v[0] - si.v[0]) * D[0] + (sj.v[1] - si.v[1]) * D[1] + (sj.v[2] - si.v[2]) * D[2]) * pc.inv_a;
+    F[0] = fm * D[0];
+    F[1] = fm * D[1];
+    F[2] = fm * D[2];
+    E = fe * xdd;
+}
+
+template <typename T>
+__device__ __forceinline__ PairConst<T> pair_const(const DerivPrm &p) {
+    return PairConst<T>{(T)p.Cl, (T)p.Cq, (T)p.eps2, (T)p.inv_a, (T)p.adot, (T)p.eta_c,
+                        (T)p.inv_eta_f, (T)p.half_a2, (T)p.half_inv_a2};
+}
+
+// Pairs with an FP64-row flag on either side (adaptive mode) are skipped
+// here and summed by k_deriv_fix.
 template <typename T, int G>
 __global__ __launch_bounds__(kBlock) void k_deriv(const double4 *__restrict__ posH,
                                                   const int64_t *__restrict__ goff,
@@ -462,79 +577,28 @@ __global__ __launch_bounds__(kBlock) void k_deriv(const double4 *__restrict__ po
         double4 pi = posH[i];
         State<T> si;
         load_state(rec, i, si);
-        const T Cl = (T)p.Cl, Cq = (T)p.Cq, eps2 = (T)p.eps2, inv_a = (T)p.inv_a,
-                adot = (T)p.adot, eta_c = (T)p.eta_c, inv_eta_f = (T)p.inv_eta_f;
+        const PairConst<T> pc = pair_const<T>(p);
         T cwi = (T)kW * si.invH * si.invH * si.invH;
         T cgi = (T)kG * si.invH * si.invH * si.invH * si.invH * si.invH;
-        T hhi_a = si.hh * inv_a, hh2i = si.hh * si.hh * eps2;
-        T ViF = (T)p.half_a2 * si.V, ViE = (T)p.half_inv_a2 * si.V;
-        T PQbase_i = si.P;
         // N_s(i): the gather row, then the extras row
         int64_t gb = goff[i];
         int ngi = (int)(goff[i + 1] - gb);
         int ebi = eb[i];
-        int tot = ngi + (ee[i] - ebi);
+        int tot = si.fl != (T)0 ? 0 : ngi + (ee[i] - ebi);
         for (int kk = l; kk < tot; kk += G) {
             int32_t j = kk < ngi ? gidx[gb + kk] : eidx[ebi + (kk - ngi)];
             double4 pj = posH[j];
             State<T> sj;
             load_state(rec, j, sj);
+            if (sj.fl != (T)0) continue;
             T d[3];
             separation(pi, pj, box, d[0], d[1], d[2]);
-            T r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
-            T r = Mth<T>::sqrt(r2);
-            T qi = r * si.invH, qj = r * sj.invH;
-            T cwj = (T)kW * sj.invH * sj.invH * sj.invH;
-            T cgj = (T)kG * sj.invH * sj.invH * sj.invH * sj.invH * sj.invH;
-            T wi, gfi, wj, gfj;
-            kernel_wg(qi, cwi, cgi, wi, gfi);
-            kernel_wg(qj, cwj, cgj, wj, gfj);
-            // grad W^R_ij (i's coefficients, +d) and grad W^R_ji (j's, -d)
-            T Gij[3], Gji[3], md[3] = {-d[0], -d[1], -d[2]};
-            rk_grad(si.k, d, wi, gfi, Gij);
-            rk_grad(sj.k, md, wj, gfj, Gji);
-            T D[3] = {Gji[0] - Gij[0], Gji[1] - Gij[1], Gji[2] - Gij[2]};
-            // limiter, eqs. (phi)-(phiad)
-            T gvi[3], gvj[3];
-#pragma unroll
-            for (int x = 0; x < 3; x++) {
-                gvi[x] = si.gv[x * 3 + 0] * d[0] + si.gv[x * 3 + 1] * d[1] + si.gv[x * 3 + 2] * d[2];
-                gvj[x] = sj.gv[x * 3 + 0] * d[0] + sj.gv[x * 3 + 1] * d[1] + sj.gv[x * 3 + 2] * d[2];
-            }
-            T s_i = d[0] * gvi[0] + d[1] * gvi[1] + d[2] * gvi[2];
-            T s_j = d[0] * gvj[0] + d[1] * gvj[1] + d[2] * gvj[2];
-            T prod = s_i * s_j;
-            T phi = (T)0;
-            if (prod > (T)0) {
-                T sum = s_i + s_j;
-                phi = (T)4 * prod * Mth<T>::rcp(sum * sum);
-                phi = phi < (T)1 ? phi : (T)1;
-                T eta = qi < qj ? qi : qj;
-                if (eta < eta_c) {
-                    T x = (eta - eta_c) * inv_eta_f;
-                    phi *= Mth<T>::exp(-x * x);
-                }
-            }
-            // projected velocity difference, eq. (hatvi), and eq. (mu)
-            T hp = (T)0.5 * phi;
-            T ud = (T)0;
-#pragma unroll
-            for (int x = 0; x < 3; x++) ud += ((si.v[x] - sj.v[x]) - hp * (gvi[x] + gvj[x]) + adot * d[x]) * d[x];
-            T Qi = (T)0, Qj = (T)0;
-            if (ud < (T)0) {
-                T hhj_a = sj.hh * inv_a, hh2j = sj.hh * sj.hh * eps2;
-                T mui = hhi_a * ud * Mth<T>::rcp(r2 + hh2i);
-                T muj = hhj_a * ud * Mth<T>::rcp(r2 + hh2j);
-                Qi = si.rho * (-Cl * si.cs * mui + Cq * mui * mui);
-                Qj = sj.rho * (-Cl * sj.cs * muj + Cq * muj * muj);
-            }
-            T fm = ViF * sj.V * (PQbase_i + Qi + sj.P + Qj);
-            T fe = ViE * sj.V * (sj.P + Qj);
-            T xdd = ((sj.v[0] - si.v[0]) * D[0] + (sj.v[1] - si.v[1]) * D[1] + (sj.v[2] - si.v[2]) * D[2]) * inv_a;
-            a[0].add(fm * D[0]);
-            a[1].add(fm * D[1]);
-            a[2].add(fm * D[2]);
-            a[3].add(fe * xdd);
+            T F[3], E;
+            deriv_pair(si, sj, d, pc, cwi, cgi, F, E);
+            a[0].add(F[0]);
+            a[1].add(F[1]);
+            a[2].add(F[2]);
+            a[3].add(E);
         }
     }
     group_reduce<T, G, 4>(a);
@@ -545,6 +609,118 @@ __global__ __launch_bounds__(kBlock) void k_deriv(const double4 *__restrict__ po
         dpdt[2 * n + i] = a[2].value() * im;
         dudt[i] = a[3].value() * im;
     }
+}
+
+// FP64 rows of the adaptive mode: for each listed particle, every pair when
+// the particle itself is flagged, else only the pairs with a flagged
+// partner; the FP64 sums are added to the outputs of k_deriv.
+template <int G>
+__global__ __launch_bounds__(kBlock) void k_deriv_fix(const double4 *__restrict__ posH,
+                                                      const int64_t *__restrict__ goff,
+                                                      const int32_t *__restrict__ gidx,
+                                                      const int32_t *__restrict__ eb,
+                                                      const int32_t *__restrict__ ee,
+                                                      const int32_t *__restrict__ eidx, Soa s,
+                                                      const int32_t *__restrict__ flag,
+                                                      const int32_t *__restrict__ list, int64_t nlist,
+                                                      const double *__restrict__ m, int64_t n, Box box,
+                                                      DerivPrm p, double *dpdt, double *dudt) {
+    int l;
+    int64_t g = group_index(G, l);
+    int64_t i = g < nlist ? list[g] : -1;
+    Acc<double> a[4];
+    if (i >= 0) {
+        double4 pi = posH[i];
+        State<double> si;
+        load_state_soa(s, posH, n, i, si);
+        const PairConst<double> pc = pair_const<double>(p);
+        double cwi = kW * si.invH * si.invH * si.invH;
+        double cgi = kG * si.invH * si.invH * si.invH * si.invH * si.invH;
+        bool all = flag[i] != 0;
+        int64_t gb = goff[i];
+        int ngi = (int)(goff[i + 1] - gb);
+        int ebi = eb[i];
+        int tot = ngi + (ee[i] - ebi);
+        for (int kk = l; kk < tot; kk += G) {
+            int32_t j = kk < ngi ? gidx[gb + kk] : eidx[ebi + (kk - ngi)];
+            if (!all && flag[j] == 0) continue;
+            double4 pj = posH[j];
+            State<double> sj;
+            load_state_soa(s, posH, n, j, sj);
+            double d[3];
+            separation(pi, pj, box, d[0], d[1], d[2]);
+            double F[3], E;
+            deriv_pair(si, sj, d, pc, cwi, cgi, F, E);
+            a[0].add(F[0]);
+            a[1].add(F[1]);
+            a[2].add(F[2]);
+            a[3].add(E);
+        }
+    }
+    group_reduce<double, G, 4>(a);
+    if (i >= 0 && l == 0) {
+        double im = 1.0 / m[i];
+        dpdt[i] += a[0].value() * im;
+        dpdt[n + i] += a[1].value() * im;
+        dpdt[2 * n + i] += a[2].value() * im;
+        dudt[i] += a[3].value() * im;
+    }
+}
+
+// Conditioning of particle i's RK template: the pair terms of eq. (gRK)
+// carry B.d, (gradB)^T d and gradA / A, which reach |B| H, |gradB| H^2 and
+// |gradA| H / |A| relative to the O(1) part; their sum bounds how much a
+// rounding of the terms is amplified in the (cancelling) row sums.
+__global__ __launch_bounds__(kBlock) void k_flag(int64_t n, const double4 *__restrict__ posH,
+                                                 const double *A, const double *B, const double *gA,
+                                                 const double *gB, double kappa_max, int32_t *flag,
+                                                 int64_t *fl64) {
+    int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    double H = posH[i].w;
+    double b2 = 0.0, a2 = 0.0, g2 = 0.0;
+#pragma unroll
+    for (int x = 0; x < 3; x++) {
+        b2 += B[x * n + i] * B[x * n + i];
+        a2 += gA[x * n + i] * gA[x * n + i];
+    }
+#pragma unroll
+    for (int q = 0; q < 9; q++) g2 += gB[q * n + i] * gB[q * n + i];
+    double kap = 1.0 + sqrt(b2) * H + sqrt(g2) * H * H + sqrt(a2) * H / fabs(A[i]);
+    int f = !(kap <= kappa_max);
+    flag[i] = f;
+    fl64[i] = f;
+    if (i == 0) fl64[n] = 0;
+}
+
+// rows that need an FP64 launch in the derivative pass: the flagged
+// particles and their partners (N_s is symmetric, so the partners of a
+// flagged particle are exactly the particles with a flagged partner).
+// One thread per flagged particle; the count is read from the scan's end.
+__global__ __launch_bounds__(kBlock) void k_mark(const int32_t *__restrict__ flist,
+                                                 const int64_t *__restrict__ fpos, int64_t n,
+                                                 const int64_t *__restrict__ goff,
+                                                 const int32_t *__restrict__ gidx,
+                                                 const int32_t *__restrict__ eb,
+                                                 const int32_t *__restrict__ ee,
+                                                 const int32_t *__restrict__ eidx, int64_t *t64) {
+    int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (k >= fpos[n]) return;
+    int32_t i = flist[k];
+    t64[i] = 1;
+    for (int64_t q = goff[i]; q < goff[i + 1]; q++) t64[gidx[q]] = 1;
+    for (int q = eb[i]; q < ee[i]; q++) t64[eidx[q]] = 1;
+}
+
+__global__ __launch_bounds__(kBlock) void k_zero_i64(int64_t *a, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) a[i] = 0;
+}
+
+__global__ __launch_bounds__(kBlock) void k_compact(int64_t n, const int64_t *__restrict__ pos,
+                                                    int32_t *list) {
+    int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < n && pos[i + 1] != pos[i]) list[pos[i]] = (int32_t)i;
 }
 
 __global__ __launch_bounds__(kBlock) void k_pack6_f(int64_t n, const double *v, const double *V,
@@ -573,7 +749,7 @@ inline unsigned gblocks(int64_t n, int G) { return (unsigned)((n * G + kBlock - 
         default: return set_err(c, CRK_ERR_INVALID_ARG, "lanes per particle must be a power of two <= 64"); \
     }
 
-bool valid_prec(int p) { return p == CRK_FP64 || p == CRK_MIXED || p == CRK_MIXED_M64; }
+bool valid_prec(int p) { return p == CRK_FP64 || p == CRK_MIXED || p == CRK_MIXED_ADAPT; }
 
 }  // namespace
 }  // namespace crk
@@ -583,6 +759,16 @@ using namespace crk;
 extern "C" {
 
 // lanes per particle for each pass (tuning hook; 0 leaves a pass unchanged)
+crk_status crk_set_walk(crk_ctx *c, int32_t lanes, int32_t cap) {
+    if (!c) return CRK_ERR_INVALID_ARG;
+    if (lanes != 0 && lanes != 1 && lanes != 2 && lanes != 4 && lanes != 8 && lanes != 16)
+        return set_err(c, CRK_ERR_INVALID_ARG, "walk lanes must be 1, 2, 4, 8 or 16");
+    if (cap < 0 || cap > 65536) return set_err(c, CRK_ERR_INVALID_ARG, "walk cap out of range");
+    if (lanes) c->G_walk = lanes;
+    if (cap) c->walk_cap = cap;
+    return CRK_OK;
+}
+
 crk_status crk_set_lanes(crk_ctx *c, int32_t g_vol, int32_t g_mom, int32_t g_grad, int32_t g_der) {
     if (!c) return CRK_ERR_INVALID_ARG;
     int gs[4] = {g_vol, g_mom, g_grad, g_der};
@@ -699,30 +885,80 @@ crk_status crk_derivatives(crk_ctx *c, const crk_params *p, const double *v, con
     const int32_t *gidx = (const int32_t *)c->gidx.p;
     const int32_t *eb = (const int32_t *)c->eb.p, *ee = (const int32_t *)c->ee.p,
                   *eidx = (const int32_t *)c->eidx.p;
-    bool f32 = p->precision != CRK_FP64;
+    const bool f32 = p->precision != CRK_FP64;
+    const bool adapt = p->precision == CRK_MIXED_ADAPT;
     DerivPrm dp{p->gamma, p->Cl, p->Cq, p->eps * p->eps, 1.0 / p->nh, 1.0 / p->a,
                 0.5 * p->a * p->a, 0.5 / (p->a * p->a), p->adot, p->eta_crit, 1.0 / p->eta_fold};
     CRK_TRY(ensure(c, c->misc, 256));
     int *bad = (int *)c->misc.p + 2;
     CRK_HIP(c, hipMemsetAsync(bad, 0, sizeof(int), c->stream));
     int Gg = c->G_grad, Gd = c->G_der;
+
+    // adaptive mode: FP64 rows for ill-conditioned RK templates
+    int32_t *flag = nullptr, *flist = nullptr, *tlist = nullptr;
+    int64_t nflag = 0, ntouch = 0;
+    if (adapt) {
+        CRK_TRY(ensure(c, c->flag, (size_t)n * sizeof(int32_t)));
+        CRK_TRY(ensure(c, c->flist, (size_t)n * sizeof(int32_t)));
+        CRK_TRY(ensure(c, c->tlist, (size_t)n * sizeof(int32_t)));
+        CRK_TRY(ensure(c, c->fpos, (size_t)(n + 1) * sizeof(int64_t)));
+        CRK_TRY(ensure(c, c->tpos, (size_t)(n + 1) * sizeof(int64_t)));
+        flag = (int32_t *)c->flag.p;
+        flist = (int32_t *)c->flist.p;
+        tlist = (int32_t *)c->tlist.p;
+        int64_t *fpos = (int64_t *)c->fpos.p, *tpos = (int64_t *)c->tpos.p;
+        {
+            KTimer kt_(c, "k_flag");
+            k_flag<<<nblocks(n), kBlock, 0, c->stream>>>(n, posH, A, B, gA, gB, p->kappa_max, flag, fpos);
+            CRK_TRY(scan_exclusive_i64(c, fpos, fpos, n + 1));
+            k_compact<<<nblocks(n), kBlock, 0, c->stream>>>(n, fpos, flist);
+            k_zero_i64<<<nblocks(n + 1), kBlock, 0, c->stream>>>(tpos, n + 1);
+            k_mark<<<nblocks(n), kBlock, 0, c->stream>>>(flist, fpos, n, goff, gidx, eb, ee, eidx, tpos);
+            CRK_TRY(scan_exclusive_i64(c, tpos, tpos, n + 1));
+            k_compact<<<nblocks(n), kBlock, 0, c->stream>>>(n, tpos, tlist);
+        }
+        CRK_HIP(c, hipGetLastError());
+        int64_t *pin = (int64_t *)c->pinned.p + 40;
+        CRK_HIP(c, hipMemcpyAsync(pin, fpos + n, sizeof(int64_t), hipMemcpyDeviceToHost, c->stream));
+        CRK_HIP(c, hipMemcpyAsync(pin + 1, tpos + n, sizeof(int64_t), hipMemcpyDeviceToHost, c->stream));
+        CRK_HIP(c, hipStreamSynchronize(c->stream));
+        nflag = pin[0];
+        ntouch = pin[1];
+        c->last_nflag = nflag;
+        c->last_ntouch = ntouch;
+    }
+
     if (f32) {
         CRK_TRY(ensure(c, c->rec6, (size_t)n * sizeof(float4)));
         CRK_TRY(ensure(c, c->rec7, (size_t)n * kRec7 * sizeof(float4)));
         float4 *r6 = (float4 *)c->rec6.p, *r7 = (float4 *)c->rec7.p;
+        double4 *r6d = nullptr, *aux = nullptr;
+        if (adapt) {
+            CRK_TRY(ensure(c, c->rec6d, (size_t)n * sizeof(double4)));
+            CRK_TRY(ensure(c, c->aux, (size_t)n * sizeof(double4)));
+            r6d = (double4 *)c->rec6d.p;
+            aux = (double4 *)c->aux.p;
+        }
         {
             KTimer kt_(c, "k_pack");
             k_pack6_f<<<nblocks(n), kBlock, 0, c->stream>>>(n, v, V, r6);
+            if (adapt) k_pack6_d<<<nblocks(n), kBlock, 0, c->stream>>>(n, v, V, r6d);
         }
-#define L_GV(GG) k_gradv<float, GG><<<gblocks(n, GG), kBlock, 0, c->stream>>>(posH, goff, gidx, r6, A, B, gA, gB, n, box, gradv)
+#define L_GV(GG) k_gradv<float, GG><<<gblocks(n, GG), kBlock, 0, c->stream>>>(posH, goff, gidx, r6, A, B, gA, gB, n, box, nullptr, 0, flag, gradv)
         {
             KTimer kt_(c, "k_gradv");
             CRK_DISPATCH_G(Gg, L_GV);
         }
 #undef L_GV
+        if (adapt && nflag > 0) {
+#define L_GV(GG) k_gradv<double, GG><<<gblocks(nflag, GG), kBlock, 0, c->stream>>>(posH, goff, gidx, r6d, A, B, gA, gB, n, box, flist, nflag, nullptr, gradv)
+            KTimer kt_(c, "k_gradv_fix");
+            CRK_DISPATCH_G(Gg, L_GV);
+#undef L_GV
+        }
         {
             KTimer kt_(c, "k_pack");
-            k_pack7<float4, float><<<nblocks(n), kBlock, 0, c->stream>>>(n, posH, v, m, u, rho, V, A, B, gA, gB, gradv, dp, r7, bad);
+            k_pack7<float4, float><<<nblocks(n), kBlock, 0, c->stream>>>(n, posH, v, m, u, rho, V, A, B, gA, gB, gradv, dp, flag, r7, aux, bad);
         }
 #define L_DER(GG) k_deriv<float, GG><<<gblocks(n, GG), kBlock, 0, c->stream>>>(posH, goff, gidx, eb, ee, eidx, r7, m, n, box, dp, dpdt, dudt)
         {
@@ -730,6 +966,13 @@ crk_status crk_derivatives(crk_ctx *c, const crk_params *p, const double *v, con
             CRK_DISPATCH_G(Gd, L_DER);
         }
 #undef L_DER
+        if (adapt && ntouch > 0) {
+            Soa s{v, V, A, B, gA, gB, gradv, aux};
+#define L_FIX(GG) k_deriv_fix<GG><<<gblocks(ntouch, GG), kBlock, 0, c->stream>>>(posH, goff, gidx, eb, ee, eidx, s, flag, tlist, ntouch, m, n, box, dp, dpdt, dudt)
+            KTimer kt_(c, "k_deriv_fix");
+            CRK_DISPATCH_G(Gd, L_FIX);
+#undef L_FIX
+        }
     } else {
         CRK_TRY(ensure(c, c->rec6, (size_t)n * sizeof(double4)));
         CRK_TRY(ensure(c, c->rec7, (size_t)n * kRec7 * sizeof(double4)));
@@ -738,7 +981,7 @@ crk_status crk_derivatives(crk_ctx *c, const crk_params *p, const double *v, con
             KTimer kt_(c, "k_pack");
             k_pack6_d<<<nblocks(n), kBlock, 0, c->stream>>>(n, v, V, r6);
         }
-#define L_GV(GG) k_gradv<double, GG><<<gblocks(n, GG), kBlock, 0, c->stream>>>(posH, goff, gidx, r6, A, B, gA, gB, n, box, gradv)
+#define L_GV(GG) k_gradv<double, GG><<<gblocks(n, GG), kBlock, 0, c->stream>>>(posH, goff, gidx, r6, A, B, gA, gB, n, box, nullptr, 0, nullptr, gradv)
         {
             KTimer kt_(c, "k_gradv");
             CRK_DISPATCH_G(Gg, L_GV);
@@ -746,7 +989,7 @@ crk_status crk_derivatives(crk_ctx *c, const crk_params *p, const double *v, con
 #undef L_GV
         {
             KTimer kt_(c, "k_pack");
-            k_pack7<double4, double><<<nblocks(n), kBlock, 0, c->stream>>>(n, posH, v, m, u, rho, V, A, B, gA, gB, gradv, dp, r7, bad);
+            k_pack7<double4, double><<<nblocks(n), kBlock, 0, c->stream>>>(n, posH, v, m, u, rho, V, A, B, gA, gB, gradv, dp, nullptr, r7, nullptr, bad);
         }
 #define L_DER(GG) k_deriv<double, GG><<<gblocks(n, GG), kBlock, 0, c->stream>>>(posH, goff, gidx, eb, ee, eidx, r7, m, n, box, dp, dpdt, dudt)
         {
@@ -760,6 +1003,13 @@ crk_status crk_derivatives(crk_ctx *c, const crk_params *p, const double *v, con
     CRK_HIP(c, hipMemcpyAsync(pin, bad, sizeof(int), hipMemcpyDeviceToHost, c->stream));
     CRK_HIP(c, hipStreamSynchronize(c->stream));
     if (pin[0]) return set_err(c, CRK_ERR_NONFINITE, "non-finite or non-positive gas state");
+    return CRK_OK;
+}
+
+crk_status crk_adaptive_rows(crk_ctx *c, int64_t *n_fp64_rows, int64_t *n_touched_rows) {
+    if (!c || !n_fp64_rows || !n_touched_rows) return CRK_ERR_INVALID_ARG;
+    *n_fp64_rows = c->last_nflag;
+    *n_touched_rows = c->last_ntouch;
     return CRK_OK;
 }
 

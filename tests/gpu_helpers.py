@@ -19,11 +19,13 @@ def oracle_run(ps, nres=64.0, **over):
     return out
 
 
-def gpu_run(ps, precision=CRK_FP64, nres=64.0, lanes=None, ctx=None, **over):
+def gpu_run(ps, precision=CRK_FP64, nres=64.0, lanes=None, ctx=None, walk=None, **over):
     import torch
     ctx = ctx or Context(0)
     if lanes:
         ctx.set_lanes(*lanes)
+    if walk:
+        ctx.set_walk(*walk)
     dev = pl.upload(ps)
     p = pl.params_for(ps, nres, precision, **over)
     out = pl.step(ctx, dev, p)

@@ -1,0 +1,101 @@
+"""GPU parity of the smoothing-length network kernels (features, forward,
+batch gradient, Adam) against the FP64 oracles (oracle.hnet_features,
+oracle/hnet.py), from the same seeded weights and batches."""
+import numpy as np
+import pytest
+import torch
+
+import crk_inputs as ci
+import oracle
+from oracle import hnet
+from paper_2202_02840_amd import CRK_FP64, Context
+from paper_2202_02840_amd import pipeline as pl
+
+pytestmark = pytest.mark.gpu
+
+
+def _batch(seed, B):
+    g = np.random.default_rng(seed)
+    f = g.normal(0, 1, (B, 8))
+    f[:, 7] = 1.0
+    return f, g.normal(0, 0.3, B)
+
+
+def _dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float32), device="cuda")
+
+
+def test_features_match_oracle():
+    ps = ci.lognormal_box(16, sigma=1.5, seed=401)
+    print(f"[case] hnet features n={ps.n}", flush=True)
+    ctx = Context(0)
+    dev = pl.upload(ps)
+    ctx.build_cells(dev["x"], dev["y"], dev["z"], dev["H"], pl.params_for(ps, 64.0, CRK_FP64))
+    Hs = ctx.permute(dev["H"], True)
+    f = ctx.hnet_features(64.0, Hs).double()
+    perm = ctx.perm.long().cpu().numpy()
+    got = np.empty((8, ps.n))
+    got[:, perm] = f.cpu().numpy()
+    ref = oracle.hnet_features(ps.x, ps.y, ps.z, ps.H, 64.0)
+    # features are FP64 sums rounded to FP32
+    assert np.abs(got - ref).max() <= 1e-6 * max(1.0, np.abs(ref).max())
+
+
+def test_forward_matches_oracle():
+    th = ci.hnet_init(11)
+    f, _ = _batch(12, 1000)
+    ctx = Context(0)
+    y = ctx.hnet_forward(_dev(th), _dev(f.T)).double().cpu().numpy()
+    ref = hnet.forward(th.astype(np.float32).astype(np.float64), f.astype(np.float32).astype(np.float64))
+    assert np.abs(y - ref).max() <= 1e-5 * max(1.0, np.abs(ref).max())
+
+
+def test_gradient_matches_oracle():
+    th = ci.hnet_init(13)
+    f, t = _batch(14, 777)          # ragged: not a multiple of the 64-sample block
+    ctx = Context(0)
+    tht = _dev(th)
+    m = torch.zeros_like(tht)
+    v = torch.zeros_like(tht)
+    g, loss = ctx.hnet_train_step(tht, m, v, 1, 0.0, _dev(f.T), _dev(t), want_grad=True,
+                                  want_loss=True)
+    L, ref = hnet.backward(th.astype(np.float32).astype(np.float64),
+                           f.astype(np.float32).astype(np.float64), t.astype(np.float32))
+    g = g.double().cpu().numpy()
+    assert abs(loss - L) <= 1e-5 * L
+    assert np.abs(g - ref).max() <= 1e-4 * np.abs(ref).max()
+    # lr = 0 leaves the weights alone
+    assert torch.equal(tht, _dev(th))
+
+
+def test_adam_trajectory_matches_oracle():
+    th0 = ci.hnet_init(15)
+    ctx = Context(0)
+    tht = _dev(th0)
+    m = torch.zeros_like(tht)
+    v = torch.zeros_like(tht)
+    th = th0.astype(np.float32).astype(np.float64)
+    opt = hnet.Adam(hnet.N_PARAM, lr=1e-3)
+    for step in range(1, 31):
+        f, t = _batch(100 + step, 256)
+        ctx.hnet_train_step(tht, m, v, step, 1e-3, _dev(f.T), _dev(t))
+        _, gr = hnet.backward(th, f.astype(np.float32).astype(np.float64), t.astype(np.float32))
+        th = opt.step(th, gr)
+    got = tht.double().cpu().numpy()
+    # relative to the size of the total update
+    assert np.abs(got - th).max() <= 2e-3 * np.abs(th - th0).max()
+
+
+def test_training_is_deterministic():
+    th0 = ci.hnet_init(16)
+    f, t = _batch(17, 5000)
+    outs = []
+    for _ in range(2):
+        ctx = Context(0)
+        tht = _dev(th0)
+        m = torch.zeros_like(tht)
+        v = torch.zeros_like(tht)
+        for step in range(1, 6):
+            ctx.hnet_train_step(tht, m, v, step, 1e-3, _dev(f.T), _dev(t))
+        outs.append(tht.cpu().numpy())
+    assert np.array_equal(outs[0], outs[1])

@@ -10,7 +10,7 @@ import pytest
 import crk_inputs as ci
 import oracle
 from gpu_helpers import OUTPUTS, compare, gpu_run, oracle_run, rows_original
-from paper_2202_02840_amd import CRK_FP64, CRK_MIXED
+from paper_2202_02840_amd import CRK_FP64, CRK_MIXED, CRK_MIXED_ADAPT
 
 pytestmark = pytest.mark.gpu
 
@@ -27,10 +27,11 @@ def _print_case(name, ps):
 
 @pytest.mark.parametrize("name", list(CASES))
 @pytest.mark.parametrize("which", [0, 1])
-def test_neighbour_lists_bit_exact(name, which):
+@pytest.mark.parametrize("walk", [(4, 192), (1, 192), (8, 16), (16, 3)])
+def test_neighbour_lists_bit_exact(name, which, walk):
     ps = CASES[name]()
-    _print_case(name, ps)
-    res = gpu_run(ps)
+    _print_case(f"{name} walk {walk}", ps)
+    res = gpu_run(ps, walk=walk)
     ctx = res["ctx"]
     off, idx = ctx.export_neighbors(which)
     rows = rows_original(off, idx, ctx.perm)
@@ -55,11 +56,12 @@ def test_fp64_path_matches_oracle(name):
 
 
 @pytest.mark.parametrize("name", list(CASES))
-def test_mixed_path_matches_oracle(name):
+@pytest.mark.parametrize("prec", [CRK_MIXED, CRK_MIXED_ADAPT])
+def test_mixed_path_matches_oracle(name, prec):
     ps = CASES[name]()
     _print_case(name, ps)
     ref = oracle_run(ps)
-    res = gpu_run(ps, CRK_MIXED)
+    res = gpu_run(ps, prec)
     errs = compare(res, ref)
     print(errs)
     for k, e in errs.items():
@@ -71,7 +73,7 @@ def test_every_lane_split_agrees(lanes):
     ps = CASES["lognormal_ragged"]()
     _print_case(f"lanes {lanes}", ps)
     ref = oracle_run(ps)
-    for prec, tol in ((CRK_FP64, 1e-12), (CRK_MIXED, 1e-5)):
+    for prec, tol in ((CRK_FP64, 1e-12), (CRK_MIXED, 1e-5), (CRK_MIXED_ADAPT, 1e-5)):
         res = gpu_run(ps, prec, lanes=lanes)
         errs = compare(res, ref)
         for k, e in errs.items():
@@ -85,3 +87,16 @@ def test_bitwise_deterministic():
     b = gpu_run(ps, CRK_MIXED)
     for k in OUTPUTS:
         assert np.array_equal(a[k], b[k]), k
+
+
+def test_adaptive_mode_with_every_row_fp64_equals_fp64_path():
+    """kappa_max = 0 sends every row through the FP64 launches: the result then
+    matches the FP64 path to rounding."""
+    ps = CASES["lognormal20"]()
+    _print_case("adaptive kappa 0", ps)
+    a = gpu_run(ps, CRK_FP64)
+    b = gpu_run(ps, CRK_MIXED_ADAPT, kappa_max=0.0)
+    assert b["ctx"].adaptive_rows()[0] == ps.n
+    for k in OUTPUTS:
+        den = np.abs(a[k]).max()
+        assert np.abs(a[k] - b[k]).max() <= 1e-13 * max(den, 1e-300), k
