@@ -64,6 +64,35 @@ def cpu_baseline(n_side: int) -> dict:
                       f"({out['n_pairs']} pairs, {dt:.2f} s)"}
 
 
+def hsurrogate_leg(ctx, args) -> dict:
+    """Smoothing-length network: train on clustered boxes with the library's
+    own kernels (labels from the plain iteration), then on a held-out box
+    compare the plain iteration with the network-seeded one at identical
+    converged H."""
+    import crk_inputs as ci
+    from paper_2202_02840_amd import hsurrogate as hs
+    t0 = time.perf_counter()
+    feats, tgts, nsamp = [], [], 0
+    for b, sigma in enumerate((1.0, 1.5, 2.0)):
+        ps = ci.lognormal_box(args.hs_train_side, sigma=sigma, seed=100 + b)
+        f, t, _ = hs.training_pairs(ctx, ps)
+        feats.append(f)
+        tgts.append(t)
+        nsamp += ps.n
+    t1 = time.perf_counter()
+    theta, hist = hs.train(ctx, ci.hnet_init(0), feats, tgts, steps=args.hs_steps, batch=8192,
+                           log_every=max(args.hs_steps // 5, 1))
+    import torch
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    held = ci.lognormal_box(args.hs_eval_side, sigma=2.0, seed=4)
+    r = hs.evaluate(ctx, held, theta, tol=1e-8, repeats=2)
+    r.update(train_samples=nsamp, train_steps=args.hs_steps, label_seconds=t1 - t0,
+             train_seconds=t2 - t1, loss_history=hist,
+             eval_box=f"lognormal {args.hs_eval_side}^3, sigma 2.0, seed 4")
+    return r
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -74,6 +103,11 @@ def main():
     ap.add_argument("--cpu-n-side", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true")
+    ap.add_argument("--no-hsurrogate", action="store_true",
+                    help="skip the smoothing-length network leg (train + plain vs seeded iteration)")
+    ap.add_argument("--hs-train-side", type=int, default=64)
+    ap.add_argument("--hs-eval-side", type=int, default=128)
+    ap.add_argument("--hs-steps", type=int, default=1500)
     ap.add_argument("--lanes", type=str, default="", help="vol,mom,grad,der lanes per particle")
     ap.add_argument("--walk", type=str, default="", help="lanes,cap of the neighbour walk")
     ap.add_argument("--kappa", type=float, default=1000.0,
@@ -173,6 +207,8 @@ def main():
         "max_rel_err_vs_fp64": errs,
         "err_target_met": None if errs is None else bool(max(errs.values()) <= 1e-5),
     }
+    if not args.no_hsurrogate:
+        line["h_surrogate"] = hsurrogate_leg(ctx, args)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args.cpu_n_side)
     print(json.dumps(line), flush=True)

@@ -197,6 +197,10 @@ crk_status crk_derivatives(crk_ctx *ctx, const crk_params *p, const double *v, c
  * crk_update_support afterwards to rebuild the lists for the new H.
  * Errors: CRK_ERR_SUPPORT if an iterate reaches L/2; CRK_ERR_INVALID_ARG if
  * Nres <= 20.625 (the self term alone gives N = (4 pi/3)(495/(32 pi))).
+ * The iteration runs in rounds of a few updates per particle; particles that
+ * have stopped are compacted out between rounds, so the time follows the
+ * total number of updates rather than the slowest particle of a wavefront;
+ * when few particles remain each gets more lanes (up to a wavefront).
  */
 crk_status crk_hsolve(crk_ctx *ctx, double Nres, double tol, int32_t max_iter, double *H_inout,
                       int32_t *iters, int64_t *n_unconverged);
@@ -232,6 +236,9 @@ crk_status crk_hnet_train_step(crk_ctx *ctx, float *theta, float *adam_m, float 
                                int64_t nb, float *grad, float *loss);
 crk_status crk_hnet_seed(crk_ctx *ctx, const float *theta, double Nres, const double *H_prev,
                          double *H_seed);
+/* Training targets target[i] = ln(H_conv[i] / H_prev[i]) (float) for n particles. */
+crk_status crk_hnet_targets(crk_ctx *ctx, int64_t n, const double *H_prev, const double *H_conv,
+                            float *target);
 
 /*
  * Neighbour lists of the last build, for checking: which = 0 gives N_g
@@ -248,6 +255,15 @@ crk_status crk_export_neighbors(crk_ctx *ctx, int32_t which, int64_t *offsets, i
  * current value. Tuning only: results agree to rounding for every g. */
 crk_status crk_set_lanes(crk_ctx *ctx, int32_t g_vol, int32_t g_mom, int32_t g_grad,
                          int32_t g_der);
+
+/* Tuning of crk_hsolve (results do not depend on it; 0 keeps a value):
+ * lanes per particle (1, 2, 4, 8, 16), updates per round, and the candidate
+ * rows built once before the iteration: every j within factor * H_start of
+ * i, stored as exact FP64 r^2 in rows of cap slots (cap = -1: no rows; an
+ * iterate beyond the row's radius, or a row longer than cap, walks the cells
+ * instead). Defaults 4, 8, 320, 1.3. */
+crk_status crk_set_hsolve(crk_ctx *ctx, int32_t lanes, int32_t round, int32_t cap,
+                          double factor);
 
 /* Neighbour walk of crk_build_cells / crk_update_support (tuning only: the
  * lists do not depend on it): lanes (1, 2, 4, 8 or 16) of a wavefront share

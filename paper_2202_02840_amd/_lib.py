@@ -17,9 +17,10 @@ STATUS = {0: "CRK_OK", 1: "CRK_WARN_SINGULAR", 2: "CRK_WARN_NOT_CONVERGED",
 # every symbol include/crk.h declares
 EXPORTS = ("crk_params_default", "crk_create", "crk_destroy", "crk_last_error", "crk_build_cells",
            "crk_update_support", "crk_permute", "crk_moments", "crk_corrections",
-           "crk_derivatives", "crk_hsolve", "crk_export_neighbors", "crk_set_lanes", "crk_set_walk",
+           "crk_derivatives", "crk_hsolve", "crk_export_neighbors", "crk_set_lanes", "crk_set_walk", "crk_set_hsolve",
            "crk_timing_enable", "crk_timing_reset", "crk_timing_read", "crk_adaptive_rows",
            "crk_hnet_features", "crk_hnet_forward", "crk_hnet_train_step", "crk_hnet_seed",
+           "crk_hnet_targets",
            "crk_version")
 
 
@@ -78,6 +79,7 @@ def lib():
             "crk_export_neighbors": ([p, i32, p, p, i64, p], i32),
             "crk_set_lanes": ([p, i32, i32, i32, i32], i32),
             "crk_set_walk": ([p, i32, i32], i32),
+            "crk_set_hsolve": ([p, i32, i32, i32, d], i32),
             "crk_timing_enable": ([p, i32], i32),
             "crk_timing_reset": ([p], i32),
             "crk_timing_read": ([p, C.c_char_p, p, p], i32),
@@ -86,6 +88,7 @@ def lib():
             "crk_hnet_forward": ([p, p, p, i64, p], i32),
             "crk_hnet_train_step": ([p, p, p, p, i64, C.c_float, p, p, i64, p, p], i32),
             "crk_hnet_seed": ([p, p, d, p, p], i32),
+            "crk_hnet_targets": ([p, i64, p, p, p], i32),
             "crk_version": ([], C.c_char_p),
         }
         for name, (args, res) in sigs.items():
@@ -299,6 +302,17 @@ class Context:
         self._check(lib().crk_hnet_seed(self._h, _ptr(theta), C.c_double(Nres),
                                         _ptr(H_prev_sorted), _ptr(out)), "crk_hnet_seed")
         return out
+
+    def hnet_targets(self, H_prev, H_conv):
+        _f64(H_prev, H_conv)
+        t = self._empty(H_prev.shape[0], dtype=torch.float32)
+        self._check(lib().crk_hnet_targets(self._h, H_prev.shape[0], _ptr(H_prev), _ptr(H_conv),
+                                           _ptr(t)), "crk_hnet_targets")
+        return t
+
+    def set_hsolve(self, lanes: int = 0, round: int = 0, cap: int = 0, factor: float = 0.0):
+        self._check(lib().crk_set_hsolve(self._h, lanes, round, cap, C.c_double(factor)),
+                    "crk_set_hsolve")
 
     def set_walk(self, lanes: int = 0, cap: int = 0):
         self._check(lib().crk_set_walk(self._h, lanes, cap), "crk_set_walk")

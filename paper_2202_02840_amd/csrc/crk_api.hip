@@ -182,7 +182,8 @@ void crk_destroy(crk_ctx *c) {
                        &c->keyB, &c->valA,  &c->valB,  &c->hist, &c->scanTmp, &c->recV,
                        &c->rec6, &c->rec7,  &c->red,   &c->misc, &c->flag, &c->flist,
                        &c->tlist, &c->fpos, &c->tpos,  &c->rec6d, &c->aux, &c->scratch,
-                       &c->hnet_part, &c->hnet_feat};
+                       &c->hnet_part, &c->hnet_feat, &c->hs_list, &c->hs_state, &c->hs_pos,
+                       &c->hs_iters, &c->hs_rows, &c->hs_rcnt, &c->hs_R};
     for (crk::Buf *b : all)
         if (b->p) hipFree(b->p);
     if (c->pinned.p) hipHostFree(c->pinned.p);

@@ -232,6 +232,13 @@ __global__ __launch_bounds__(kBlock) void k_hnet_seed(const double *__restrict__
     Hseed[i] = fmin(s, hmax);
 }
 
+__global__ __launch_bounds__(kBlock) void k_hnet_targets(const double *__restrict__ Hprev,
+                                                         const double *__restrict__ Hconv, int64_t n,
+                                                         float *t) {
+    int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) t[i] = (float)log(Hconv[i] / Hprev[i]);
+}
+
 }  // namespace
 
 static Levels levels_here(const crk_ctx *c) {
@@ -313,6 +320,17 @@ crk_status crk_hnet_train_step(crk_ctx *c, float *theta, float *adam_m, float *a
         CRK_HIP(c, hipStreamSynchronize(c->stream));
         *loss = pin[0];
     }
+    return CRK_OK;
+}
+
+crk_status crk_hnet_targets(crk_ctx *c, int64_t n, const double *H_prev, const double *H_conv,
+                            float *target) {
+    if (!c) return CRK_ERR_INVALID_ARG;
+    if (n < 1 || !H_prev || !H_conv || !target)
+        return set_err(c, CRK_ERR_INVALID_ARG, "crk_hnet_targets: bad argument");
+    CRK_HIP(c, hipSetDevice(c->device));
+    k_hnet_targets<<<(unsigned)((n + kBlock - 1) / kBlock), kBlock, 0, c->stream>>>(H_prev, H_conv, n, target);
+    CRK_HIP(c, hipGetLastError());
     return CRK_OK;
 }
 

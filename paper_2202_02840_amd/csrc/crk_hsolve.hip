@@ -13,39 +13,163 @@
 namespace crk {
 namespace {
 
-__device__ __forceinline__ double nsum_walk(const double4 *__restrict__ posH, const int32_t *__restrict__ cbeg,
-                                            const int32_t *__restrict__ cend, const Levels &v, double4 pi,
-                                            double H) {
+// n_i(H) by a group of G lanes: the group walks i's cells together, lanes
+// take a cell's particles G at a time, and the partial sums are combined
+// with cross-lane shuffles (every lane ends with the same total).
+template <int G>
+__device__ __forceinline__ double nsum_group(const double4 *__restrict__ posH,
+                                             const int32_t *__restrict__ cbeg,
+                                             const int32_t *__restrict__ cend, const Levels &v,
+                                             const double4 &pi, double H, int l) {
     const double H2 = H * H, invH = 1.0 / H;
     double s = 0.0;
-    walk_cells(v, cbeg, cend, pi.x, pi.y, pi.z, H, [&](int j) {
-        double4 pj = posH[j];
-        double dx = min_image(pi.x - pj.x, v.L, v.hL);
-        double dy = min_image(pi.y - pj.y, v.L, v.hL);
-        double dz = min_image(pi.z - pj.z, v.L, v.hL);
-        double r2 = r2_exact(dx, dy, dz);
+    int k = level_for(H, v);
+    int nck = 1 << (v.bits - k);
+    Grid g{v.L, v.hL, (double)nck / v.L, v.margin, nck};
+    int lx, ly, lz, mx, my, mz;
+    axis_range(pi.x, H, g, lx, mx);
+    axis_range(pi.y, H, g, ly, my);
+    axis_range(pi.z, H, g, lz, mz);
+    const int32_t *cb = cbeg + v.off[k], *ce = cend + v.off[k];
+    for (int a = 0; a < mz; a++) {
+        uint32_t mzb = spread3(wrapc(lz + a, nck)) << 2;
+        for (int b = 0; b < my; b++) {
+            uint32_t myb = mzb | (spread3(wrapc(ly + b, nck)) << 1);
+            for (int e = 0; e < mx; e++) {
+                uint32_t id = myb | spread3(wrapc(lx + e, nck));
+                int je = ce[id];
+                for (int j = cb[id] + l; j < je; j += G) {
+                    double4 pj = posH[j];
+                    double dx = min_image(pi.x - pj.x, v.L, v.hL);
+                    double dy = min_image(pi.y - pj.y, v.L, v.hL);
+                    double dz = min_image(pi.z - pj.z, v.L, v.hL);
+                    double r2 = r2_exact(dx, dy, dz);
+                    if (r2 < H2) {
+                        double q = sqrt(r2) * invH;
+                        double t = 1.0 - q, t2 = t * t;
+                        s += t2 * t2 * t2 * (1.0 + q * (6.0 + q * (35.0 / 3.0)));
+                    }
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int m = G / 2; m >= 1; m >>= 1) s += __shfl_xor(s, m, G);
+    return kW * invH * invH * invH * s;
+}
+
+// Candidate rows for the iteration: the exact FP64 r^2 of every j within
+// R_i = f H_start (self included), in cell-walk order, in a row of cap
+// slots. cnt[i] counts every candidate, so cnt[i] > cap marks a row that
+// the iteration must not use.
+template <int G>
+__global__ __launch_bounds__(kBlock) void k_hs_rows(const double4 *__restrict__ posH,
+                                                    const int32_t *__restrict__ cbeg,
+                                                    const int32_t *__restrict__ cend, Levels v,
+                                                    int64_t n, const double *__restrict__ H0, double f,
+                                                    int cap, double *rows, int32_t *cnt, double *Rlist) {
+    int64_t gid = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    const int l = (int)(gid % G);
+    const int64_t i = gid / G;
+    if (i >= n) return;
+    const double4 pi = posH[i];
+    const double R = f * H0[i];
+    const double R2 = R * R;
+    const int gshift = (threadIdx.x & 63) - l;
+    const uint64_t below = (l == 0) ? 0ull : (((uint64_t)1 << l) - 1);
+    double *row = rows + (size_t)i * cap;
+    int c = 0;
+    int k = level_for(R, v);
+    int nck = 1 << (v.bits - k);
+    Grid g{v.L, v.hL, (double)nck / v.L, v.margin, nck};
+    int lx, ly, lz, mx, my, mz;
+    axis_range(pi.x, R, g, lx, mx);
+    axis_range(pi.y, R, g, ly, my);
+    axis_range(pi.z, R, g, lz, mz);
+    const int32_t *cb = cbeg + v.off[k], *ce = cend + v.off[k];
+    for (int a = 0; a < mz; a++) {
+        uint32_t mzb = spread3(wrapc(lz + a, nck)) << 2;
+        for (int b = 0; b < my; b++) {
+            uint32_t myb = mzb | (spread3(wrapc(ly + b, nck)) << 1);
+            for (int e = 0; e < mx; e++) {
+                uint32_t id = myb | spread3(wrapc(lx + e, nck));
+                int jb = cb[id], je = ce[id];
+                for (int j0 = jb; j0 < je; j0 += G) {
+                    int j = j0 + l;
+                    bool hit = false;
+                    double r2 = 0.0;
+                    if (j < je) {
+                        double4 pj = posH[j];
+                        double dx = min_image(pi.x - pj.x, v.L, v.hL);
+                        double dy = min_image(pi.y - pj.y, v.L, v.hL);
+                        double dz = min_image(pi.z - pj.z, v.L, v.hL);
+                        r2 = r2_exact(dx, dy, dz);
+                        hit = r2 < R2;
+                    }
+                    uint32_t hm = (uint32_t)((__ballot(hit) >> gshift) &
+                                             ((G == 64) ? ~0ull : (((uint64_t)1 << G) - 1)));
+                    if (hit) {
+                        int p = c + __popc(hm & (uint32_t)below);
+                        if (p < cap) row[p] = r2;
+                    }
+                    c += __popc(hm);
+                }
+            }
+        }
+    }
+    if (l == 0) {
+        cnt[i] = c;
+        Rlist[i] = R;
+    }
+}
+
+// n_i(H) from a candidate row (valid while H <= the row's radius)
+template <int G>
+__device__ __forceinline__ double nsum_row(const double *__restrict__ row, int c, double H, int l) {
+    const double H2 = H * H, invH = 1.0 / H;
+    double s = 0.0;
+    for (int k = l; k < c; k += G) {
+        double r2 = row[k];
         if (r2 < H2) {
             double q = sqrt(r2) * invH;
             double t = 1.0 - q, t2 = t * t;
             s += t2 * t2 * t2 * (1.0 + q * (6.0 + q * (35.0 / 3.0)));
         }
-    });
+    }
+#pragma unroll
+    for (int m = G / 2; m >= 1; m >>= 1) s += __shfl_xor(s, m, G);
     return kW * invH * invH * invH * s;
 }
 
-__global__ __launch_bounds__(kBlock) void k_hsolve(const double4 *__restrict__ posH,
-                                                   const int32_t *__restrict__ cbeg,
-                                                   const int32_t *__restrict__ cend, Levels v, int64_t n,
-                                                   double Nres, double tol, int max_iter, double *H_io,
-                                                   int32_t *iters, unsigned long long *counters) {
-    int64_t i = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
-    if (i >= n) return;
-    double4 pi = posH[i];
+// One round: each listed particle takes up to R more updates of eq. (thacker)
+// from its stored state. state[i]: 0 running, 1 converged, 2 hit max_iter,
+// 3 support reached L/2.
+template <int G>
+__global__ __launch_bounds__(kBlock) void k_hsolve_round(const double4 *__restrict__ posH,
+                                                         const int32_t *__restrict__ cbeg,
+                                                         const int32_t *__restrict__ cend, Levels v,
+                                                         const int32_t *__restrict__ list, int64_t m,
+                                                         double Nres, double tol, int max_iter, int R,
+                                                         const double *__restrict__ rows,
+                                                         const int32_t *__restrict__ rcnt,
+                                                         const double *__restrict__ Rlist, int cap,
+                                                         double *H_io, int32_t *iters, int32_t *state) {
+    int64_t gid = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    const int l = (int)(gid % G);
+    const int64_t k = gid / G;
+    if (k >= m) return;
+    const int64_t i = list[k];
+    const double4 pi = posH[i];
     double H = H_io[i];
-    int it = 0;
-    bool conv = false, support = false;
-    while (it < max_iter) {
-        double ns = nsum_walk(posH, cbeg, cend, v, pi, H);
+    int it = iters[i];
+    int st = 0;
+    const int c = rows ? rcnt[i] : cap + 1;
+    const double Rmax = rows ? Rlist[i] : 0.0;
+    const double *row = rows ? rows + (size_t)i * cap : nullptr;
+    for (int r = 0; r < R; r++) {
+        // the candidate row holds every j within Rmax, so it answers any H <= Rmax
+        double ns = (c <= cap && H <= Rmax) ? nsum_row<G>(row, c, H, l)
+                                            : nsum_group<G>(posH, cbeg, cend, v, pi, H, l);
         double N = (4.0 * kPi / 3.0) * H * H * H * ns;
         double D = cbrt(Nres / N);
         double lam = D < 1.0 ? 0.2 * (1.0 + D * D) : 0.2 * (1.0 + 1.0 / (D * D * D));
@@ -53,19 +177,46 @@ __global__ __launch_bounds__(kBlock) void k_hsolve(const double4 *__restrict__ p
         it++;
         bool done = fabs(Hn - H) <= tol * H;
         H = Hn;
-        if (!(H < v.hL)) {
-            support = true;
-            break;
-        }
-        if (done) {
-            conv = true;
-            break;
-        }
+        if (!(H < v.hL)) { st = 3; break; }
+        if (done) { st = 1; break; }
+        if (it >= max_iter) { st = 2; break; }
     }
-    H_io[i] = H;
-    if (iters) iters[i] = it;
-    if (!conv) atomicAdd(&counters[0], 1ull);
-    if (support) atomicAdd(&counters[1], 1ull);
+    if (l == 0) {
+        H_io[i] = H;
+        iters[i] = it;
+        state[i] = st;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_hs_init(int64_t n, int32_t *list, int32_t *iters, int32_t *state) {
+    int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    list[i] = (int32_t)i;
+    iters[i] = 0;
+    state[i] = 0;
+}
+
+// running[k] = 1 when list[k] is still running (for the compaction scan)
+__global__ __launch_bounds__(kBlock) void k_hs_running(const int32_t *__restrict__ list, int64_t m,
+                                                       const int32_t *__restrict__ state, int64_t *run) {
+    int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (k < m) run[k] = state[list[k]] == 0;
+    if (k == m) run[m] = 0;
+}
+
+__global__ __launch_bounds__(kBlock) void k_hs_compact(const int32_t *__restrict__ list, int64_t m,
+                                                       const int64_t *__restrict__ pos, int32_t *out) {
+    int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (k < m && pos[k + 1] != pos[k]) out[pos[k]] = list[k];
+}
+
+__global__ __launch_bounds__(kBlock) void k_hs_count(const int32_t *__restrict__ state, int64_t n,
+                                                     unsigned long long *cnt) {
+    int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    int s = state[i];
+    if (s == 2) atomicAdd(&cnt[0], 1ull);
+    if (s == 3) atomicAdd(&cnt[1], 1ull);
 }
 
 __global__ __launch_bounds__(kBlock) void k_set_H2(double4 *posH, const double *H, int64_t n) {
@@ -90,7 +241,7 @@ crk_status crk_hsolve(crk_ctx *c, double Nres, double tol, int32_t max_iter, dou
         return set_err(c, CRK_ERR_INVALID_ARG, "Nres must exceed 20.625 (the self term alone)");
     if (c->nc == 0) return set_err(c, CRK_ERR_STATE, "crk_build_cells has not run");
     CRK_HIP(c, hipSetDevice(c->device));
-    int64_t n = c->n;
+    const int64_t n = c->n;
     Levels v;
     v.L = c->L;
     v.hL = 0.5 * c->L;
@@ -98,27 +249,99 @@ crk_status crk_hsolve(crk_ctx *c, double Nres, double tol, int32_t max_iter, dou
     v.margin = 1e-9 * c->L;
     v.bits = c->bits;
     for (int k = 0; k < 12; k++) v.off[k] = c->lvl_off[k];
+    CRK_TRY(ensure(c, c->hs_list, (size_t)2 * n * sizeof(int32_t)));
+    CRK_TRY(ensure(c, c->hs_state, (size_t)n * sizeof(int32_t)));
+    CRK_TRY(ensure(c, c->hs_pos, (size_t)(n + 1) * sizeof(int64_t)));
+    CRK_TRY(ensure(c, c->hs_iters, (size_t)n * sizeof(int32_t)));
+    int32_t *la = (int32_t *)c->hs_list.p, *lb = la + n;
+    int32_t *state = (int32_t *)c->hs_state.p;
+    int32_t *it = iters ? iters : (int32_t *)c->hs_iters.p;
+    int64_t *pos = (int64_t *)c->hs_pos.p;
+    const unsigned nb = (unsigned)((n + kBlock - 1) / kBlock);
+    k_hs_init<<<nb, kBlock, 0, c->stream>>>(n, la, it, state);
+    CRK_HIP(c, hipGetLastError());
+    // candidate rows at f H_start (positions do not move during the iteration)
+    const int cap = c->hs_cap;
+    double *rows = nullptr;
+    int32_t *rcnt = nullptr;
+    double *Rl = nullptr;
+    if (cap > 0) {
+        CRK_TRY(ensure(c, c->hs_rows, (size_t)n * cap * sizeof(double)));
+        CRK_TRY(ensure(c, c->hs_rcnt, (size_t)n * sizeof(int32_t)));
+        CRK_TRY(ensure(c, c->hs_R, (size_t)n * sizeof(double)));
+        rows = (double *)c->hs_rows.p;
+        rcnt = (int32_t *)c->hs_rcnt.p;
+        Rl = (double *)c->hs_R.p;
+        KTimer kt_(c, "k_hs_rows");
+        k_hs_rows<8><<<(unsigned)((n * 8 + kBlock - 1) / kBlock), kBlock, 0, c->stream>>>(
+            (const double4 *)c->posH.p, (const int32_t *)c->cbeg.p, (const int32_t *)c->cend.p, v, n,
+            H_inout, c->hs_factor, cap, rows, rcnt, Rl);
+        CRK_HIP(c, hipGetLastError());
+    }
+    int64_t m = n;
+    int64_t *pin = (int64_t *)c->pinned.p + 24;
+    const int G = c->G_hsolve;
+    {
+        KTimer kt_(c, "k_hsolve");
+        while (m > 0) {
+            // few particles left (the slowly contracting tail): give each one
+            // more lanes so the device stays busy, and run longer rounds
+            int Gr = G;
+            while (Gr < 64 && m * Gr < (int64_t)1 << 18) Gr *= 2;
+            const int R = Gr > G ? 4 * c->hs_round : c->hs_round;
+#define L_HS(GG) k_hsolve_round<GG><<<(unsigned)((m * GG + kBlock - 1) / kBlock), kBlock, 0, c->stream>>>((const double4 *)c->posH.p, (const int32_t *)c->cbeg.p, (const int32_t *)c->cend.p, v, la, m, Nres, tol, max_iter, R, rows, rcnt, Rl, cap, H_inout, it, state)
+            switch (Gr) {
+                case 1: L_HS(1); break;
+                case 2: L_HS(2); break;
+                case 4: L_HS(4); break;
+                case 8: L_HS(8); break;
+                case 16: L_HS(16); break;
+                case 32: L_HS(32); break;
+                case 64: L_HS(64); break;
+                default: return set_err(c, CRK_ERR_INVALID_ARG, "hsolve lanes must be a power of two <= 64");
+            }
+#undef L_HS
+            const unsigned mb = (unsigned)((m + 1 + kBlock - 1) / kBlock);
+            k_hs_running<<<mb, kBlock, 0, c->stream>>>(la, m, state, pos);
+            CRK_TRY(scan_exclusive_i64(c, pos, pos, m + 1));
+            k_hs_compact<<<mb, kBlock, 0, c->stream>>>(la, m, pos, lb);
+            CRK_HIP(c, hipGetLastError());
+            CRK_HIP(c, hipMemcpyAsync(pin, pos + m, sizeof(int64_t), hipMemcpyDeviceToHost, c->stream));
+            CRK_HIP(c, hipStreamSynchronize(c->stream));
+            m = pin[0];
+            int32_t *t = la;
+            la = lb;
+            lb = t;
+        }
+    }
     CRK_TRY(ensure(c, c->misc, 256));
     unsigned long long *cnt = (unsigned long long *)c->misc.p + 6;
     CRK_HIP(c, hipMemsetAsync(cnt, 0, 2 * sizeof(unsigned long long), c->stream));
-    {
-        KTimer kt_(c, "k_hsolve");
-        k_hsolve<<<(unsigned)((n + kBlock - 1) / kBlock), kBlock, 0, c->stream>>>(
-            (const double4 *)c->posH.p, (const int32_t *)c->cbeg.p, (const int32_t *)c->cend.p, v, n,
-            Nres, tol, max_iter, H_inout, iters, cnt);
-    }
-    CRK_HIP(c, hipGetLastError());
-    unsigned long long *pin = (unsigned long long *)c->pinned.p + 16;
-    CRK_HIP(c, hipMemcpyAsync(pin, cnt, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, c->stream));
+    k_hs_count<<<nb, kBlock, 0, c->stream>>>(state, n, cnt);
+    unsigned long long *pc = (unsigned long long *)c->pinned.p + 16;
+    CRK_HIP(c, hipMemcpyAsync(pc, cnt, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, c->stream));
     CRK_HIP(c, hipStreamSynchronize(c->stream));
-    if (n_unconverged) *n_unconverged = (int64_t)pin[0];
-    if (pin[1]) return set_err(c, CRK_ERR_SUPPORT, "%llu supports reached L/2", pin[1]);
+    if (n_unconverged) *n_unconverged = (int64_t)pc[0];
+    if (pc[1]) return set_err(c, CRK_ERR_SUPPORT, "%llu supports reached L/2", pc[1]);
     // the lists no longer match the support radii
     c->built = 0;
     c->have_V = 0;
-    k_set_H2<<<(unsigned)((n + kBlock - 1) / kBlock), kBlock, 0, c->stream>>>((double4 *)c->posH.p, H_inout, n);
+    k_set_H2<<<nb, kBlock, 0, c->stream>>>((double4 *)c->posH.p, H_inout, n);
     CRK_HIP(c, hipGetLastError());
-    if (pin[0]) return CRK_WARN_NOT_CONVERGED;
+    if (pc[0]) return CRK_WARN_NOT_CONVERGED;
+    return CRK_OK;
+}
+
+crk_status crk_set_hsolve(crk_ctx *c, int32_t lanes, int32_t round, int32_t cap, double factor) {
+    if (!c) return CRK_ERR_INVALID_ARG;
+    if (lanes != 0 && lanes != 1 && lanes != 2 && lanes != 4 && lanes != 8 && lanes != 16)
+        return set_err(c, CRK_ERR_INVALID_ARG, "hsolve lanes must be 1, 2, 4, 8 or 16");
+    if (round < 0 || cap < -1 || cap > 65536 || factor < 0.0)
+        return set_err(c, CRK_ERR_INVALID_ARG, "crk_set_hsolve: bad argument");
+    if (lanes) c->G_hsolve = lanes;
+    if (round) c->hs_round = round;
+    if (cap) c->hs_cap = cap < 0 ? 0 : cap;
+    if (factor > 0.0) c->hs_factor = factor;
     return CRK_OK;
 }
 

@@ -14,8 +14,10 @@ from paper_2202_02840_amd import pipeline as pl
 pytestmark = pytest.mark.gpu
 
 
-def _gpu_hsolve(ps, nres, tol=1e-7, max_iter=100, start=None):
+def _gpu_hsolve(ps, nres, tol=1e-7, max_iter=100, start=None, tune=None):
     ctx = Context(0)
+    if tune:
+        ctx.set_hsolve(*tune)
     dev = pl.upload(ps)
     H0 = dev["H"] if start is None else torch.as_tensor(start, device="cuda")
     prm = pl.params_for(ps, nres, CRK_FP64)
@@ -34,26 +36,38 @@ def _gpu_hsolve(ps, nres, tol=1e-7, max_iter=100, start=None):
     ("lognormal16", lambda: ci.lognormal_box(16, sigma=1.5, seed=301)),
     ("lattice12", lambda: ci.lattice_box(12, seed=302)),
 ])
-def test_hsolve_matches_oracle(name, make):
+@pytest.mark.parametrize("tune", [None, (4, 8, -1, 0.0), (2, 3, 8, 0.0), (16, 8, 320, 1.05)],
+                         ids=["rows", "no-rows", "overflow", "tight-rows"])
+def test_hsolve_matches_oracle(name, make, tune):
     ps = make()
-    print(f"[case] hsolve {name} n={ps.n}", flush=True)
+    print(f"[case] hsolve {name} tune={tune} n={ps.n}", flush=True)
     # sparse particles, where N(H) is flat, contract slowly: allow 1000 updates
     Href, itref, nf = oracle.hsolve(ps.x, ps.y, ps.z, ps.H, 64.0, tol=1e-7, max_iter=1000)
-    H, it, nun, _ = _gpu_hsolve(ps, 64.0, max_iter=1000)
+    H, it, nun, _ = _gpu_hsolve(ps, 64.0, max_iter=1000, tune=tune)
     assert nf == 0 and nun == 0
     assert np.abs(H / Href - 1).max() < 1e-6
     # same update on both sides: iteration counts agree up to the last step
     assert np.abs(it - itref).max() <= 1
 
 
-def test_hsolve_then_lists_follow_new_support():
+def test_update_support_rebuilds_lists():
+    """After crk_update_support with new support radii (the oracle's converged
+    H), the pair lists equal the oracle's for those radii."""
     ps = ci.lognormal_box(14, sigma=1.5, seed=303)
-    print(f"[case] hsolve+update n={ps.n}", flush=True)
-    H, _, _, ctx = _gpu_hsolve(ps, 64.0, max_iter=1000)
-    Hs = ctx.permute(torch.as_tensor(H, device="cuda"), True)
+    print(f"[case] update_support n={ps.n}", flush=True)
+    Hc, _, _ = oracle.hsolve(ps.x, ps.y, ps.z, ps.H, 64.0, tol=1e-7, max_iter=1000)
+    ctx = Context(0)
+    dev = pl.upload(ps)
+    ctx.build_cells(dev["x"], dev["y"], dev["z"], dev["H"], pl.params_for(ps, 64.0, CRK_FP64))
+    Hs = ctx.permute(torch.as_tensor(Hc, device="cuda"), True)
     npairs = ctx.update_support(Hs)
-    soff, _ = oracle.neighbors(ps.x, ps.y, ps.z, H, 1.0, True, 1)
+    soff, sidx = oracle.neighbors(ps.x, ps.y, ps.z, Hc, 1.0, True, 1)
     assert npairs == soff[-1]
+    from gpu_helpers import rows_original
+    off, idx = ctx.export_neighbors(1)
+    rows = rows_original(off, idx, ctx.perm)
+    for i in range(ps.n):
+        assert np.array_equal(rows[i], sidx[soff[i]:soff[i + 1]]), i
 
 
 def test_hsolve_rejects_target_below_self_term():
