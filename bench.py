@@ -45,6 +45,24 @@ OUT_KEYS = ("V", "m0", "m1", "m2", "gm0", "gm1", "gm2", "A", "B", "gA", "gB", "g
             "dudt")
 
 
+COUNTERS = os.path.join(ROOT, "profiles", "k_deriv_counters.json")
+DERIV_SOURCE = os.path.join(ROOT, "paper_2202_02840_amd", "csrc", "crk_pairs.hip")
+
+
+def deriv_traffic(precision: str, lanes: int):
+    """HBM bytes per k_deriv launch from the committed rocprofv3 counter runs
+    (FETCH_SIZE and WRITE_SIZE scaled by the copy-probe factors), or None when
+    the kernel source or its launch shape differs from the one measured."""
+    import hashlib
+    if not os.path.exists(COUNTERS):
+        return None
+    rec = json.load(open(COUNTERS))
+    sha = hashlib.sha256(open(DERIV_SOURCE, "rb").read()).hexdigest()
+    if rec.get("source_sha256") != sha or rec.get("precision") != precision or rec.get("lanes") != lanes:
+        return None
+    return (rec["fetch_kib"] * rec["fetch_scale"] + rec["write_kib"] * rec["write_scale"]) * 1024.0
+
+
 def make_workload(n_side=128, seed=2):
     import crk_inputs as ci
     return ci.lognormal_box(n_side, sigma=1.5, spectral_index=-2.0, seed=seed)
@@ -99,7 +117,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n-side", type=int, default=128)
-    ap.add_argument("--precision", choices=("mixed", "adapt", "fp64"), default="mixed")
+    ap.add_argument("--precision", choices=("mixed", "adapt", "fp64"), default="adapt")
     ap.add_argument("--cpu-n-side", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true")
@@ -110,6 +128,12 @@ def main():
     ap.add_argument("--hs-steps", type=int, default=1500)
     ap.add_argument("--lanes", type=str, default="", help="vol,mom,grad,der lanes per particle")
     ap.add_argument("--walk", type=str, default="", help="lanes,cap of the neighbour walk")
+    ap.add_argument("--autotune", action="store_true",
+                    help="tune lanes per pass on this workload before timing")
+    ap.add_argument("--tune-out", type=str, default="",
+                    help="write the tuned table to this path (with --autotune)")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a plain 2 GiB device-to-device copy three times (scales HBM counters)")
     ap.add_argument("--kappa", type=float, default=1000.0,
                     help="conditioning bound above which the adaptive mode runs a row in FP64")
     args = ap.parse_args()
@@ -120,6 +144,14 @@ def main():
         sys.exit(2)
 
     import torch
+    if args.copy_probe:
+        a = torch.ones(1 << 28, dtype=torch.float64, device="cuda")
+        c = torch.empty_like(a)
+        for _ in range(3):
+            c.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_per_launch": (1 << 28) * 8}), flush=True)
+        return
     from paper_2202_02840_amd import CRK_FP64, CRK_MIXED, CRK_MIXED_ADAPT, Context
     from paper_2202_02840_amd import pipeline as pl
 
@@ -133,6 +165,20 @@ def main():
     dev = pl.upload(ps)
     prm = pl.params_for(ps, 64.0, prec, kappa_max=args.kappa)
     torch.cuda.synchronize()
+
+    # lanes per pass: tuned now, or from the stored table for this workload class
+    from paper_2202_02840_amd import autotune as at
+    first = pl.step(ctx, dev, prm, count_singular=False)
+    ppp = first["n_pairs"] / ps.n
+    tuned = None
+    if args.autotune:
+        tuned, tune_ms = at.tune(ctx, dev, prm, log=lambda s: print(s, file=sys.stderr, flush=True))
+        if args.tune_out:
+            at.save(prec, ppp, tuned, tune_ms, f"lognormal {args.n_side}^3 sigma 1.5", args.tune_out)
+    elif not (args.lanes or args.walk):
+        tuned = at.load(prec, ppp)
+        if tuned:
+            at.apply(ctx, tuned)
 
     for _ in range(args.warmup):
         out = pl.step(ctx, dev, prm, count_singular=False)
@@ -196,9 +242,12 @@ def main():
                    "particles": n, "pairs_per_step": npairs,
                    "mean_pairs_per_particle": npairs / n, "precision": args.precision,
                    "kappa_max": args.kappa if prec == CRK_MIXED_ADAPT else None,
-                   "fp64_rows": fp64_rows[0], "fp64_touched_rows": fp64_rows[1]},
+                   "fp64_rows": fp64_rows[0], "fp64_touched_rows": fp64_rows[1],
+                   "lanes": tuned},
         "roofline": {"bound": "alu", "achieved": achieved_tf, "peak": VALU_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved_tf / VALU_PEAK_TFLOPS, "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved_tf / VALU_PEAK_TFLOPS,
+                     "traffic": deriv_traffic(args.precision, (tuned or {}).get("der")),
+                     "traffic_unit": "bytes per launch", "algorithmic_bytes": bytes_alg,
                      "kernel": "k_deriv", "kernel_ms": kern["k_deriv"],
                      "flops_per_pair": DERIV_FLOPS_PER_PAIR,
                      "frac_of_packed_fp32_peak": achieved_tf / VALU_PEAK_PACKED_FP32,

@@ -126,6 +126,21 @@ crk_status crk_build_cells(crk_ctx *ctx, int64_t n, const double *x, const doubl
                            const double *z, const double *H, const crk_params *p,
                            double cell_size, int32_t *perm, int64_t *n_pairs, int32_t *n_cells);
 
+/*
+ * S10: many independent periodic boxes (same L) in one build. Particles are
+ * concatenated box by box: box b owns [box_offsets[b], box_offsets[b+1]) of
+ * the n particles (box_offsets: HOST int64 [nboxes+1], 0 .. n). The sort
+ * groups particles by (box, Morton cell), each box gets its own cell
+ * hierarchy, and a particle only ever pairs with particles of its own box.
+ * Every later call (moments, corrections, derivatives, h iteration, network)
+ * then runs over all boxes in one launch per pass, on the concatenated
+ * arrays in the sorted order. crk_build_cells is this call with one box.
+ */
+crk_status crk_build_cells_batch(crk_ctx *ctx, int32_t nboxes, const int64_t *box_offsets,
+                                 int64_t n, const double *x, const double *y, const double *z,
+                                 const double *H, const crk_params *p, double cell_size,
+                                 int32_t *perm, int64_t *n_pairs, int32_t *n_cells);
+
 /* Rebuilds the neighbour lists after a change of support radii with the
  * particles' positions unchanged. H_sorted[n]: new H in sorted order. */
 crk_status crk_update_support(crk_ctx *ctx, const double *H_sorted, int64_t *n_pairs);
@@ -257,7 +272,7 @@ crk_status crk_set_lanes(crk_ctx *ctx, int32_t g_vol, int32_t g_mom, int32_t g_g
                          int32_t g_der);
 
 /* Tuning of crk_hsolve (results do not depend on it; 0 keeps a value):
- * lanes per particle (1, 2, 4, 8, 16), updates per round, and the candidate
+ * lanes per particle (a power of two <= 64), updates per round, and the candidate
  * rows built once before the iteration: every j within factor * H_start of
  * i, stored as exact FP64 r^2 in rows of cap slots (cap = -1: no rows; an
  * iterate beyond the row's radius, or a row longer than cap, walks the cells

@@ -16,6 +16,7 @@ STATUS = {0: "CRK_OK", 1: "CRK_WARN_SINGULAR", 2: "CRK_WARN_NOT_CONVERGED",
 
 # every symbol include/crk.h declares
 EXPORTS = ("crk_params_default", "crk_create", "crk_destroy", "crk_last_error", "crk_build_cells",
+           "crk_build_cells_batch",
            "crk_update_support", "crk_permute", "crk_moments", "crk_corrections",
            "crk_derivatives", "crk_hsolve", "crk_export_neighbors", "crk_set_lanes", "crk_set_walk", "crk_set_hsolve",
            "crk_timing_enable", "crk_timing_reset", "crk_timing_read", "crk_adaptive_rows",
@@ -70,6 +71,7 @@ def lib():
             "crk_destroy": ([p], None),
             "crk_last_error": ([p], C.c_char_p),
             "crk_build_cells": ([p, i64, p, p, p, p, p, d, p, p, p], i32),
+            "crk_build_cells_batch": ([p, i32, p, i64, p, p, p, p, p, d, p, p, p], i32),
             "crk_update_support": ([p, p, p], i32),
             "crk_permute": ([p, p, p, i32, i32], i32),
             "crk_moments": ([p, p] + [p] * 8, i32),
@@ -170,6 +172,23 @@ class Context:
                                    C.byref(params), C.c_double(cell_size), _ptr(perm),
                                    C.byref(npairs), C.byref(ncell))
         self._check(st, "crk_build_cells")
+        self.n, self.n_pairs, self.n_cells, self.perm = n, npairs.value, ncell.value, perm
+        return perm, npairs.value
+
+    def build_cells_batch(self, box_offsets, x, y, z, H, params: Params, cell_size: float = 0.0):
+        """box_offsets: host sequence of nboxes+1 particle offsets (0 .. n)."""
+        import numpy as np
+        _f64(x, y, z, H)
+        n = x.shape[0]
+        off = np.ascontiguousarray(box_offsets, dtype=np.int64)
+        perm = self._empty(n, dtype=torch.int32)
+        npairs = C.c_int64()
+        ncell = C.c_int32()
+        st = lib().crk_build_cells_batch(self._h, len(off) - 1, off.ctypes.data_as(C.c_void_p), n,
+                                         _ptr(x), _ptr(y), _ptr(z), _ptr(H), C.byref(params),
+                                         C.c_double(cell_size), _ptr(perm), C.byref(npairs),
+                                         C.byref(ncell))
+        self._check(st, "crk_build_cells_batch")
         self.n, self.n_pairs, self.n_cells, self.perm = n, npairs.value, ncell.value, perm
         return perm, npairs.value
 

@@ -1,0 +1,122 @@
+"""Autotuner for the lanes-per-particle of every pass.
+
+Each pair pass, the neighbour walk and the smoothing-length iteration split a
+particle's work over a group of G lanes of a wave64 (crk_set_lanes,
+crk_set_walk, crk_set_hsolve). The best G depends on the neighbour counts
+and on the precision, so the tuner times every candidate on the actual
+workload with the library's own per-kernel HIP-event timers, one knob at a
+time (coordinate descent from the current setting), and keeps the fastest.
+Results are stored in a JSON table keyed by precision and mean pairs per
+particle, which bench.py and callers apply with :func:`apply`.
+"""
+from __future__ import annotations
+
+import json
+import os
+
+import torch
+
+from ._lib import Context
+from . import pipeline as pl
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+TABLE = os.path.join(HERE, "tune_table.json")
+
+DEFAULT = {"walk": 8, "vol": 4, "mom": 1, "grad": 4, "der": 8, "hsolve": 8}
+CANDIDATES = {
+    "walk": (2, 4, 8, 16),
+    "vol": (1, 2, 4, 8, 16),
+    "mom": (1, 2, 4, 8),
+    "grad": (2, 4, 8, 16),
+    "der": (4, 8, 16, 32),
+    "hsolve": (4, 8, 16, 32),
+}
+KERNEL = {"walk": "k_walk", "vol": "k_volume", "mom": "k_moments", "grad": "k_gradv",
+          "der": "k_deriv"}
+
+
+def key_for(precision: int, pairs_per_particle: float) -> str:
+    """Table key: precision and mean pairs per particle rounded to 16."""
+    return f"p{precision}/n{int(round(pairs_per_particle / 16.0)) * 16}"
+
+
+def apply(ctx: Context, cfg: dict) -> None:
+    ctx.set_lanes(cfg["vol"], cfg["mom"], cfg["grad"], cfg["der"])
+    ctx.set_walk(cfg["walk"], 0)
+    ctx.set_hsolve(cfg["hsolve"], 0, 0, 0.0)
+
+
+def load(precision: int, pairs_per_particle: float) -> dict | None:
+    if not os.path.exists(TABLE):
+        return None
+    tab = json.load(open(TABLE))
+    k = key_for(precision, pairs_per_particle)
+    if k in tab:
+        return dict(tab[k]["config"])
+    # nearest neighbour-count class of the same precision
+    same = [(abs(int(kk.split("/n")[1]) - pairs_per_particle), kk) for kk in tab
+            if kk.startswith(f"p{precision}/")]
+    return dict(tab[min(same)[1]]["config"]) if same else None
+
+
+def _time_step(ctx, dev, prm, kernel: str, reps: int) -> float:
+    pl.step(ctx, dev, prm, count_singular=False)          # settle allocations
+    ctx.timing(True)
+    ctx.timing_reset()
+    for _ in range(reps):
+        pl.step(ctx, dev, prm, count_singular=False)
+    torch.cuda.synchronize()
+    ms, cnt = ctx.timing_read(kernel)
+    ctx.timing(False)
+    return ms / max(cnt, 1)
+
+
+def _time_hsolve(ctx, dev, prm, nres: float, reps: int) -> float:
+    ctx.build_cells(dev["x"], dev["y"], dev["z"], dev["H"], prm)
+    Hs = ctx.permute(dev["H"], True)
+    best = None
+    for _ in range(reps):
+        ctx.timing(True)
+        ctx.timing_reset()
+        ctx.hsolve(nres, Hs, 1e-8, 1000)
+        torch.cuda.synchronize()
+        ms, _ = ctx.timing_read("k_hsolve")
+        ctx.timing(False)
+        ctx.update_support(Hs)
+        best = ms if best is None else min(best, ms)
+    return best
+
+
+def tune(ctx: Context, dev: dict, prm, nres: float = 64.0, start: dict | None = None,
+         reps: int = 3, with_hsolve: bool = True, log=print) -> tuple[dict, dict]:
+    """Coordinate descent over the knobs; returns (best config, timings)."""
+    cfg = dict(start or DEFAULT)
+    timings = {}
+    for knob, cands in CANDIDATES.items():
+        if knob == "hsolve" and not with_hsolve:
+            continue
+        res = {}
+        for g in cands:
+            trial = dict(cfg)
+            trial[knob] = g
+            apply(ctx, trial)
+            if knob == "hsolve":
+                res[g] = _time_hsolve(ctx, dev, prm, nres, max(1, reps - 1))
+            else:
+                res[g] = _time_step(ctx, dev, prm, KERNEL[knob], reps)
+        best = min(res, key=res.get)
+        cfg[knob] = best
+        timings[knob] = {str(k): v for k, v in res.items()}
+        if log:
+            log(f"tune {knob}: {res} -> {best}")
+    apply(ctx, cfg)
+    return cfg, timings
+
+
+def save(precision: int, pairs_per_particle: float, cfg: dict, timings: dict, workload: str,
+         path: str = TABLE) -> None:
+    tab = json.load(open(path)) if os.path.exists(path) else {}
+    tab[key_for(precision, pairs_per_particle)] = {"config": cfg, "timings_ms": timings,
+                                                   "workload": workload}
+    with open(path, "w") as f:
+        json.dump(tab, f, indent=1, sort_keys=True)

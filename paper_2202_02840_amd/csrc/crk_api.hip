@@ -46,6 +46,18 @@ crk_status ensure(crk_ctx *c, Buf &b, size_t bytes) {
     return CRK_OK;
 }
 
+__global__ void k_zero_words(uint32_t *p, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0u;
+}
+
+crk_status zero_async(crk_ctx *c, void *p, int64_t words) {
+    if (words <= 0) return CRK_OK;
+    k_zero_words<<<(unsigned)((words + kBlock - 1) / kBlock), kBlock, 0, c->stream>>>((uint32_t *)p, words);
+    CRK_HIP(c, hipGetLastError());
+    return CRK_OK;
+}
+
 static hipEvent_t pool_get(crk_ctx *c) {
     if (!c->ev_pool.empty()) {
         hipEvent_t e = c->ev_pool.back();
@@ -175,15 +187,15 @@ crk_status crk_create(crk_ctx **out, int device, void *hip_stream) {
 
 void crk_destroy(crk_ctx *c) {
     if (!c) return;
-    hipSetDevice(c->device);
-    hipStreamSynchronize(c->stream);
+    (void)hipSetDevice(c->device);
+    (void)hipStreamSynchronize(c->stream);
     crk::Buf *all[] = {&c->posH, &c->perm,  &c->cbeg,  &c->cend, &c->goff, &c->gidx, &c->ng,
                        &c->nes,  &c->esoff, &c->eb,    &c->ee,   &c->ekey, &c->eidx, &c->keyA,
                        &c->keyB, &c->valA,  &c->valB,  &c->hist, &c->scanTmp, &c->recV,
                        &c->rec6, &c->rec7,  &c->red,   &c->misc, &c->flag, &c->flist,
                        &c->tlist, &c->fpos, &c->tpos,  &c->rec6d, &c->aux, &c->scratch,
                        &c->hnet_part, &c->hnet_feat, &c->hs_list, &c->hs_state, &c->hs_pos,
-                       &c->hs_iters, &c->hs_rows, &c->hs_rcnt, &c->hs_R};
+                       &c->hs_iters, &c->hs_rows, &c->hs_rcnt, &c->hs_R, &c->boff};
     for (crk::Buf *b : all)
         if (b->p) hipFree(b->p);
     if (c->pinned.p) hipHostFree(c->pinned.p);

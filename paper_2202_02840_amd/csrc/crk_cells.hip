@@ -82,12 +82,22 @@ __device__ __forceinline__ int cell_of(double x, double inv_c, int nc) {
     return k < 0 ? 0 : (k >= nc ? nc - 1 : k);
 }
 
+// key = (box << 3 bits) | Morton code of the particle's finest cell; the box
+// is found by bisection of the batch's particle offsets
 __global__ __launch_bounds__(kBlock) void k_keys(const double *x, const double *y, const double *z,
-                                                 int64_t n, double inv_c, int nc, uint32_t *key,
-                                                 int32_t *val) {
+                                                 int64_t n, double inv_c, int nc, int bits,
+                                                 const int64_t *__restrict__ boff, int nboxes,
+                                                 uint32_t *key, int32_t *val) {
     int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i >= n) return;
-    key[i] = morton3(cell_of(x[i], inv_c, nc), cell_of(y[i], inv_c, nc), cell_of(z[i], inv_c, nc));
+    int lo = 0, hi = nboxes - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (boff[mid] <= i) lo = mid;
+        else hi = mid - 1;
+    }
+    uint32_t m = morton3(cell_of(x[i], inv_c, nc), cell_of(y[i], inv_c, nc), cell_of(z[i], inv_c, nc));
+    key[i] = ((uint32_t)lo << (3 * bits)) | m;
     val[i] = (int32_t)i;
 }
 
@@ -114,10 +124,14 @@ __global__ __launch_bounds__(kBlock) void k_tables(const uint32_t *skey, int64_t
     if (k >= n) return;
     uint32_t key = skey[k];
     uint32_t prev = k > 0 ? skey[k - 1] : 0u, next = k + 1 < n ? skey[k + 1] : 0u;
+    const int64_t base = box_base(v, k);
+    const uint32_t mort = key & (uint32_t)(((uint64_t)1 << (3 * v.bits)) - 1);
     for (int l = 0; l <= v.bits; l++) {
+        // a cell of level l is identified by key >> 3l (box bits included)
         uint32_t id = key >> (3 * l);
-        if (k == 0 || (prev >> (3 * l)) != id) cbeg[v.off[l] + id] = (int32_t)k;
-        if (k == n - 1 || (next >> (3 * l)) != id) cend[v.off[l] + id] = (int32_t)(k + 1);
+        uint32_t loc = mort >> (3 * l);
+        if (k == 0 || (prev >> (3 * l)) != id) cbeg[base + v.off[l] + loc] = (int32_t)k;
+        if (k == n - 1 || (next >> (3 * l)) != id) cend[base + v.off[l] + loc] = (int32_t)(k + 1);
     }
 }
 
@@ -158,7 +172,8 @@ __global__ __launch_bounds__(kBlock) void k_walk_scratch(const double4 *__restri
     axis_range(pi.x, pi.w, g, lx, mx);
     axis_range(pi.y, pi.w, g, ly, my);
     axis_range(pi.z, pi.w, g, lz, mz);
-    const int32_t *cb = cbeg + v.off[k], *ce_ = cend + v.off[k];
+    const int64_t base = box_base(v, i) + v.off[k];
+    const int32_t *cb = cbeg + base, *ce_ = cend + base;
     for (int a = 0; a < mz; a++) {
         uint32_t mzb = spread3(wrapc(lz + a, nck)) << 2;
         for (int b = 0; b < my; b++) {
@@ -332,7 +347,7 @@ inline unsigned nblocks(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock
 
 }  // namespace
 
-static Levels levels_of(const crk_ctx *c) {
+Levels levels(const crk_ctx *c) {
     Levels v;
     v.L = c->L;
     v.hL = 0.5 * c->L;
@@ -340,13 +355,15 @@ static Levels levels_of(const crk_ctx *c) {
     v.margin = 1e-9 * c->L;
     v.bits = c->bits;
     for (int k = 0; k < 12; k++) v.off[k] = c->lvl_off[k];
+    v.skey = (const uint32_t *)c->keyA.p;
+    v.box_stride = c->ntab;
     return v;
 }
 
 // Neighbour lists for the current posH / cell tables.
 static crk_status build_lists(crk_ctx *c) {
     int64_t n = c->n;
-    Levels v = levels_of(c);
+    Levels v = levels(c);
     CRK_TRY(ensure(c, c->ng, (size_t)n * sizeof(int32_t)));
     CRK_TRY(ensure(c, c->nes, (size_t)n * sizeof(int32_t)));
     CRK_TRY(ensure(c, c->goff, (size_t)(n + 1) * sizeof(int64_t)));
@@ -440,20 +457,27 @@ using namespace crk;
 
 extern "C" {
 
-crk_status crk_build_cells(crk_ctx *c, int64_t n, const double *x, const double *y, const double *z,
-                           const double *H, const crk_params *p, double cell_size, int32_t *perm,
-                           int64_t *n_pairs, int32_t *n_cells) {
+crk_status crk_build_cells_batch(crk_ctx *c, int32_t nboxes, const int64_t *box_offsets, int64_t n,
+                                 const double *x, const double *y, const double *z, const double *H,
+                                 const crk_params *p, double cell_size, int32_t *perm,
+                                 int64_t *n_pairs, int32_t *n_cells) {
     if (!c) return CRK_ERR_INVALID_ARG;
-    if (n < 1 || !x || !y || !z || !H || !p || !perm)
+    if (n < 1 || !x || !y || !z || !H || !p || !perm || nboxes < 1 || !box_offsets)
         return set_err(c, CRK_ERR_INVALID_ARG, "crk_build_cells: n < 1 or NULL argument");
     if (n > INT32_MAX / 2) return set_err(c, CRK_ERR_INVALID_ARG, "n too large");
     if (!(p->L > 0.0)) return set_err(c, CRK_ERR_INVALID_ARG, "L must be positive");
+    if (box_offsets[0] != 0 || box_offsets[nboxes] != n)
+        return set_err(c, CRK_ERR_INVALID_ARG, "box offsets must run from 0 to n");
+    for (int b = 0; b < nboxes; b++)
+        if (box_offsets[b + 1] < box_offsets[b])
+            return set_err(c, CRK_ERR_INVALID_ARG, "box offsets must not decrease");
     CRK_HIP(c, hipSetDevice(c->device));
     c->built = 0;
     c->have_V = 0;
     c->nc = 0;
     c->n = n;
     c->L = p->L;
+    c->nboxes = nboxes;
     // 1. validate and reduce H
     int nblk = (int)std::min<int64_t>((n + kBlock - 1) / kBlock, 1024);
     CRK_TRY(ensure(c, c->red, (size_t)nblk * 3 * sizeof(double) + 64));
@@ -461,7 +485,7 @@ crk_status crk_build_cells(crk_ctx *c, int64_t n, const double *x, const double 
     int *flags = (int *)(part + (size_t)nblk * 3);
     CRK_TRY(ensure(c, c->misc, 256));
     double *res = (double *)c->misc.p;
-    CRK_HIP(c, hipMemsetAsync(flags, 0, 3 * sizeof(int), c->stream));
+    k_fill_i32<<<1, kBlock, 0, c->stream>>>(flags, 3, 0);
     k_validate<<<nblk, kBlock, 0, c->stream>>>(x, y, z, H, n, p->L, part, flags);
     k_validate_final<<<1, 1, 0, c->stream>>>(part, nblk, res);
     CRK_HIP(c, hipGetLastError());
@@ -476,10 +500,16 @@ crk_status crk_build_cells(crk_ctx *c, int64_t n, const double *x, const double 
     if (hf[2] || !(hmin > 0.0)) return set_err(c, CRK_ERR_SUPPORT, "H must be positive");
     if (!(hmax < 0.5 * p->L)) return set_err(c, CRK_ERR_SUPPORT, "max H %g >= L/2", hmax);
     // 2. Morton cell hierarchy: finest side near half the smallest support
-    //    (or the requested side), at most 256 cells a side
+    //    (or the requested side), at most 256 cells a side and at most about
+    //    2^26 table entries over all boxes; box id above the Morton bits
     double cfine = cell_size > 0.0 ? cell_size : 0.5 * hmin;
     int bits = 0;
-    while (bits < 8 && p->L / (double)(1 << bits) > cfine) bits++;
+    while (bits < 8 && p->L / (double)(1 << bits) > cfine &&
+           (double)nboxes * (double)((int64_t)1 << (3 * (bits + 1))) * 8.0 / 7.0 <= (double)(1 << 26))
+        bits++;
+    int boxbits = 0;
+    while ((1 << boxbits) < nboxes) boxbits++;
+    if (3 * bits + boxbits > 32) return set_err(c, CRK_ERR_INVALID_ARG, "too many boxes for the key width");
     c->bits = bits;
     c->nc = 1 << bits;
     c->cell = p->L / c->nc;
@@ -490,24 +520,29 @@ crk_status crk_build_cells(crk_ctx *c, int64_t n, const double *x, const double 
         off += m * m * m;
     }
     c->ntab = off;
+    int64_t ntot = off * nboxes;
     CRK_TRY(ensure(c, c->keyA, (size_t)n * sizeof(uint32_t)));
     CRK_TRY(ensure(c, c->perm, (size_t)n * sizeof(int32_t)));
+    CRK_TRY(ensure(c, c->boff, (size_t)(nboxes + 1) * sizeof(int64_t)));
+    CRK_HIP(c, hipMemcpyAsync(c->boff.p, box_offsets, (size_t)(nboxes + 1) * sizeof(int64_t),
+                              hipMemcpyHostToDevice, c->stream));
     uint32_t *key = (uint32_t *)c->keyA.p;
     int32_t *pm = (int32_t *)c->perm.p;
-    k_keys<<<nblocks(n), kBlock, 0, c->stream>>>(x, y, z, n, 1.0 / c->cell, c->nc, key, pm);
+    k_keys<<<nblocks(n), kBlock, 0, c->stream>>>(x, y, z, n, 1.0 / c->cell, c->nc, bits,
+                                                  (const int64_t *)c->boff.p, nboxes, key, pm);
     CRK_HIP(c, hipGetLastError());
     {
         KTimer kt_(c, "sort");
-        CRK_TRY(radix_sort_pairs(c, key, pm, n, 3 * bits));
+        CRK_TRY(radix_sort_pairs(c, key, pm, n, 3 * bits + boxbits));
     }
-    // 3. sorted particles and the cell tables of every level
+    // 3. sorted particles and the cell tables of every level of every box
     CRK_TRY(ensure(c, c->posH, (size_t)n * sizeof(double4)));
-    CRK_TRY(ensure(c, c->cbeg, (size_t)c->ntab * sizeof(int32_t)));
-    CRK_TRY(ensure(c, c->cend, (size_t)c->ntab * sizeof(int32_t)));
+    CRK_TRY(ensure(c, c->cbeg, (size_t)ntot * sizeof(int32_t)));
+    CRK_TRY(ensure(c, c->cend, (size_t)ntot * sizeof(int32_t)));
     k_gather_sorted<<<nblocks(n), kBlock, 0, c->stream>>>(x, y, z, H, pm, n, (double4 *)c->posH.p);
-    k_fill_i32<<<nblocks(c->ntab), kBlock, 0, c->stream>>>((int32_t *)c->cbeg.p, c->ntab, 0);
-    k_fill_i32<<<nblocks(c->ntab), kBlock, 0, c->stream>>>((int32_t *)c->cend.p, c->ntab, 0);
-    k_tables<<<nblocks(n), kBlock, 0, c->stream>>>(key, n, levels_of(c), (int32_t *)c->cbeg.p,
+    k_fill_i32<<<nblocks(ntot), kBlock, 0, c->stream>>>((int32_t *)c->cbeg.p, ntot, 0);
+    k_fill_i32<<<nblocks(ntot), kBlock, 0, c->stream>>>((int32_t *)c->cend.p, ntot, 0);
+    k_tables<<<nblocks(n), kBlock, 0, c->stream>>>(key, n, levels(c), (int32_t *)c->cbeg.p,
                                                     (int32_t *)c->cend.p);
     CRK_HIP(c, hipGetLastError());
     CRK_HIP(c, hipMemcpyAsync(perm, pm, (size_t)n * sizeof(int32_t), hipMemcpyDeviceToDevice, c->stream));
@@ -516,6 +551,13 @@ crk_status crk_build_cells(crk_ctx *c, int64_t n, const double *x, const double 
     if (n_pairs) *n_pairs = c->npairs;
     if (n_cells) *n_cells = c->nc;
     return CRK_OK;
+}
+
+crk_status crk_build_cells(crk_ctx *c, int64_t n, const double *x, const double *y, const double *z,
+                           const double *H, const crk_params *p, double cell_size, int32_t *perm,
+                           int64_t *n_pairs, int32_t *n_cells) {
+    int64_t off[2] = {0, n};
+    return crk_build_cells_batch(c, 1, off, n, x, y, z, H, p, cell_size, perm, n_pairs, n_cells);
 }
 
 crk_status crk_update_support(crk_ctx *c, const double *H_sorted, int64_t *n_pairs) {
@@ -533,7 +575,7 @@ crk_status crk_update_support(crk_ctx *c, const double *H_sorted, int64_t *n_pai
     double *part = (double *)c->red.p;
     int *flags = (int *)(part + (size_t)nblk * 3);
     double *res = (double *)c->misc.p;
-    CRK_HIP(c, hipMemsetAsync(flags, 0, 3 * sizeof(int), c->stream));
+    k_fill_i32<<<1, kBlock, 0, c->stream>>>(flags, 3, 0);
     k_validate<<<nblk, kBlock, 0, c->stream>>>(xs, xs + n, xs + 2 * n, H_sorted, n, c->L, part, flags);
     k_validate_final<<<1, 1, 0, c->stream>>>(part, nblk, res);
     double *pin = (double *)c->pinned.p;

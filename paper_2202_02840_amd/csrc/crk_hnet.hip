@@ -183,7 +183,7 @@ __global__ __launch_bounds__(kBlock) void k_hnet_features(const double4 *__restr
     const double h = H[i];
     double s1 = 0.0, s2 = 0.0, s4 = 0.0, c1 = 0.0, c2 = 0.0;
     const double h2 = h * h, ih = 1.0 / h;
-    walk_cells(v, cbeg, cend, pi.x, pi.y, pi.z, h, [&](int j) {
+    walk_cells(v, cbeg, cend, i, pi.x, pi.y, pi.z, h, [&](int j) {
         double4 pj = posH[j];
         double dx = min_image(pi.x - pj.x, v.L, v.hL);
         double dy = min_image(pi.y - pj.y, v.L, v.hL);
@@ -241,16 +241,6 @@ __global__ __launch_bounds__(kBlock) void k_hnet_targets(const double *__restric
 
 }  // namespace
 
-static Levels levels_here(const crk_ctx *c) {
-    Levels v;
-    v.L = c->L;
-    v.hL = 0.5 * c->L;
-    v.c0 = c->cell;
-    v.margin = 1e-9 * c->L;
-    v.bits = c->bits;
-    for (int k = 0; k < 12; k++) v.off[k] = c->lvl_off[k];
-    return v;
-}
 
 }  // namespace crk
 
@@ -268,7 +258,7 @@ crk_status crk_hnet_features(crk_ctx *c, double Nres, const double *H_sorted, fl
         KTimer kt_(c, "k_hnet_features");
         k_hnet_features<<<(unsigned)((n + kBlock - 1) / kBlock), kBlock, 0, c->stream>>>(
             (const double4 *)c->posH.p, (const int32_t *)c->cbeg.p, (const int32_t *)c->cend.p,
-            levels_here(c), n, H_sorted, Nres, feat);
+            levels(c), n, H_sorted, Nres, feat);
     }
     CRK_HIP(c, hipGetLastError());
     return CRK_OK;

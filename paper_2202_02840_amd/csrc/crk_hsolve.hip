@@ -20,7 +20,7 @@ template <int G>
 __device__ __forceinline__ double nsum_group(const double4 *__restrict__ posH,
                                              const int32_t *__restrict__ cbeg,
                                              const int32_t *__restrict__ cend, const Levels &v,
-                                             const double4 &pi, double H, int l) {
+                                             int64_t i, const double4 &pi, double H, int l) {
     const double H2 = H * H, invH = 1.0 / H;
     double s = 0.0;
     int k = level_for(H, v);
@@ -30,7 +30,8 @@ __device__ __forceinline__ double nsum_group(const double4 *__restrict__ posH,
     axis_range(pi.x, H, g, lx, mx);
     axis_range(pi.y, H, g, ly, my);
     axis_range(pi.z, H, g, lz, mz);
-    const int32_t *cb = cbeg + v.off[k], *ce = cend + v.off[k];
+    const int64_t base = box_base(v, i) + v.off[k];
+    const int32_t *cb = cbeg + base, *ce = cend + base;
     for (int a = 0; a < mz; a++) {
         uint32_t mzb = spread3(wrapc(lz + a, nck)) << 2;
         for (int b = 0; b < my; b++) {
@@ -86,7 +87,8 @@ __global__ __launch_bounds__(kBlock) void k_hs_rows(const double4 *__restrict__ 
     axis_range(pi.x, R, g, lx, mx);
     axis_range(pi.y, R, g, ly, my);
     axis_range(pi.z, R, g, lz, mz);
-    const int32_t *cb = cbeg + v.off[k], *ce = cend + v.off[k];
+    const int64_t base = box_base(v, i) + v.off[k];
+    const int32_t *cb = cbeg + base, *ce = cend + base;
     for (int a = 0; a < mz; a++) {
         uint32_t mzb = spread3(wrapc(lz + a, nck)) << 2;
         for (int b = 0; b < my; b++) {
@@ -128,7 +130,20 @@ template <int G>
 __device__ __forceinline__ double nsum_row(const double *__restrict__ row, int c, double H, int l) {
     const double H2 = H * H, invH = 1.0 / H;
     double s = 0.0;
-    for (int k = l; k < c; k += G) {
+    // four loads in flight per lane: the row streams from memory, so the
+    // latency, not the arithmetic, sets the pace
+    int k = l;
+    for (; k + 3 * G < c; k += 4 * G) {
+        double r[4] = {row[k], row[k + G], row[k + 2 * G], row[k + 3 * G]};
+#pragma unroll
+        for (int u = 0; u < 4; u++)
+            if (r[u] < H2) {
+                double q = sqrt(r[u]) * invH;
+                double t = 1.0 - q, t2 = t * t;
+                s += t2 * t2 * t2 * (1.0 + q * (6.0 + q * (35.0 / 3.0)));
+            }
+    }
+    for (; k < c; k += G) {
         double r2 = row[k];
         if (r2 < H2) {
             double q = sqrt(r2) * invH;
@@ -169,7 +184,7 @@ __global__ __launch_bounds__(kBlock) void k_hsolve_round(const double4 *__restri
     for (int r = 0; r < R; r++) {
         // the candidate row holds every j within Rmax, so it answers any H <= Rmax
         double ns = (c <= cap && H <= Rmax) ? nsum_row<G>(row, c, H, l)
-                                            : nsum_group<G>(posH, cbeg, cend, v, pi, H, l);
+                                            : nsum_group<G>(posH, cbeg, cend, v, i, pi, H, l);
         double N = (4.0 * kPi / 3.0) * H * H * H * ns;
         double D = cbrt(Nres / N);
         double lam = D < 1.0 ? 0.2 * (1.0 + D * D) : 0.2 * (1.0 + 1.0 / (D * D * D));
@@ -242,13 +257,7 @@ crk_status crk_hsolve(crk_ctx *c, double Nres, double tol, int32_t max_iter, dou
     if (c->nc == 0) return set_err(c, CRK_ERR_STATE, "crk_build_cells has not run");
     CRK_HIP(c, hipSetDevice(c->device));
     const int64_t n = c->n;
-    Levels v;
-    v.L = c->L;
-    v.hL = 0.5 * c->L;
-    v.c0 = c->cell;
-    v.margin = 1e-9 * c->L;
-    v.bits = c->bits;
-    for (int k = 0; k < 12; k++) v.off[k] = c->lvl_off[k];
+    Levels v = levels(c);
     CRK_TRY(ensure(c, c->hs_list, (size_t)2 * n * sizeof(int32_t)));
     CRK_TRY(ensure(c, c->hs_state, (size_t)n * sizeof(int32_t)));
     CRK_TRY(ensure(c, c->hs_pos, (size_t)(n + 1) * sizeof(int64_t)));
@@ -287,7 +296,7 @@ crk_status crk_hsolve(crk_ctx *c, double Nres, double tol, int32_t max_iter, dou
             // few particles left (the slowly contracting tail): give each one
             // more lanes so the device stays busy, and run longer rounds
             int Gr = G;
-            while (Gr < 64 && m * Gr < (int64_t)1 << 18) Gr *= 2;
+            while (Gr < 64 && m * Gr < (int64_t)1 << 19) Gr *= 2;
             const int R = Gr > G ? 4 * c->hs_round : c->hs_round;
 #define L_HS(GG) k_hsolve_round<GG><<<(unsigned)((m * GG + kBlock - 1) / kBlock), kBlock, 0, c->stream>>>((const double4 *)c->posH.p, (const int32_t *)c->cbeg.p, (const int32_t *)c->cend.p, v, la, m, Nres, tol, max_iter, R, rows, rcnt, Rl, cap, H_inout, it, state)
             switch (Gr) {
@@ -316,7 +325,7 @@ crk_status crk_hsolve(crk_ctx *c, double Nres, double tol, int32_t max_iter, dou
     }
     CRK_TRY(ensure(c, c->misc, 256));
     unsigned long long *cnt = (unsigned long long *)c->misc.p + 6;
-    CRK_HIP(c, hipMemsetAsync(cnt, 0, 2 * sizeof(unsigned long long), c->stream));
+    CRK_TRY(zero_async(c, cnt, 4));
     k_hs_count<<<nb, kBlock, 0, c->stream>>>(state, n, cnt);
     unsigned long long *pc = (unsigned long long *)c->pinned.p + 16;
     CRK_HIP(c, hipMemcpyAsync(pc, cnt, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, c->stream));
@@ -334,8 +343,8 @@ crk_status crk_hsolve(crk_ctx *c, double Nres, double tol, int32_t max_iter, dou
 
 crk_status crk_set_hsolve(crk_ctx *c, int32_t lanes, int32_t round, int32_t cap, double factor) {
     if (!c) return CRK_ERR_INVALID_ARG;
-    if (lanes != 0 && lanes != 1 && lanes != 2 && lanes != 4 && lanes != 8 && lanes != 16)
-        return set_err(c, CRK_ERR_INVALID_ARG, "hsolve lanes must be 1, 2, 4, 8 or 16");
+    if (lanes < 0 || lanes > 64 || (lanes & (lanes - 1)))
+        return set_err(c, CRK_ERR_INVALID_ARG, "hsolve lanes must be a power of two <= 64");
     if (round < 0 || cap < -1 || cap > 65536 || factor < 0.0)
         return set_err(c, CRK_ERR_INVALID_ARG, "crk_set_hsolve: bad argument");
     if (lanes) c->G_hsolve = lanes;

@@ -57,7 +57,8 @@ struct crk_ctx {
     int bits = 0;
     double cell = 0.0;
     int64_t lvl_off[12] = {0};
-    int64_t ntab = 0;
+    int64_t ntab = 0;        // table entries of one box
+    int64_t nboxes = 1;
     int built = 0;          // lists valid
     int have_V = 0;         // recV valid (after crk_moments)
     int prec_V = -1;        // precision recV was written in
@@ -74,6 +75,7 @@ struct crk_ctx {
     crk::Buf hnet_part, hnet_feat;                        // network gradients / features
     crk::Buf hs_list, hs_state, hs_pos, hs_iters;         // smoothing-length rounds
     crk::Buf hs_rows, hs_rcnt, hs_R;                      // candidate rows (r^2)
+    crk::Buf boff;                                        // batch box offsets
     int G_hsolve = 4, hs_round = 8, hs_cap = 320;
     double hs_factor = 1.3;
     int64_t last_nflag = 0, last_ntouch = 0;
@@ -159,11 +161,19 @@ __device__ __forceinline__ int wrapc(int a, int nc) {
 
 // Morton cell hierarchy: level k has nc >> k cells a side, side c0 2^k, and
 // its table starts at off[k] in cbeg/cend (indexed by the level-k Morton id).
+// Boxes of a batch share one sort: a particle's key is (box << 3 bits) |
+// Morton code, and box b's tables start at b * box_stride.
 struct Levels {
     double L, hL, c0, margin;
     int bits;
     int64_t off[12];
+    const uint32_t *skey;   // sorted keys (box id in the bits above 3 * bits)
+    int64_t box_stride;     // table entries per box
 };
+
+__device__ __forceinline__ int64_t box_base(const Levels &v, int64_t i) {
+    return (int64_t)(v.skey[i] >> (3 * v.bits)) * v.box_stride;
+}
 
 __device__ __forceinline__ uint32_t spread3(uint32_t v) {   // 10 bits -> every third bit
     v &= 0x3ffu;
@@ -195,8 +205,8 @@ __device__ __forceinline__ int level_for(double R, const Levels &v) {
 // fixed order: cells z-major, then y, then x; particles in sorted order.
 template <typename F>
 __device__ __forceinline__ void walk_cells(const Levels &v, const int32_t *__restrict__ cbeg,
-                                           const int32_t *__restrict__ cend, double px, double py,
-                                           double pz, double R, F &&f) {
+                                           const int32_t *__restrict__ cend, int64_t i, double px,
+                                           double py, double pz, double R, F &&f) {
     int k = level_for(R, v);
     int nck = 1 << (v.bits - k);
     Grid g{v.L, v.hL, (double)nck / v.L, v.margin, nck};
@@ -204,7 +214,8 @@ __device__ __forceinline__ void walk_cells(const Levels &v, const int32_t *__res
     axis_range(px, R, g, lx, mx);
     axis_range(py, R, g, ly, my);
     axis_range(pz, R, g, lz, mz);
-    const int32_t *cb = cbeg + v.off[k], *ce = cend + v.off[k];
+    const int64_t base = box_base(v, i) + v.off[k];
+    const int32_t *cb = cbeg + base, *ce = cend + base;
     for (int a = 0; a < mz; a++) {
         uint32_t mzb = spread3(wrapc(lz + a, nck)) << 2;
         for (int b = 0; b < my; b++) {
@@ -217,6 +228,13 @@ __device__ __forceinline__ void walk_cells(const Levels &v, const int32_t *__res
         }
     }
 }
+
+// geometry of the last build as seen by the walks (host side)
+Levels levels(const crk_ctx *c);
+
+// zero `words` 32-bit words on the context's stream with a kernel (not a
+// memset node, so the call can sit inside a captured graph)
+crk_status zero_async(crk_ctx *c, void *p, int64_t words);
 
 }  // namespace crk
 

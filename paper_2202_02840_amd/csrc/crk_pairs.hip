@@ -850,7 +850,7 @@ crk_status crk_corrections(crk_ctx *c, int64_t n, const double *m0, const double
     CRK_HIP(c, hipSetDevice(c->device));
     CRK_TRY(ensure(c, c->misc, 256));
     unsigned long long *cnt = (unsigned long long *)c->misc.p + 4;
-    CRK_HIP(c, hipMemsetAsync(cnt, 0, sizeof(unsigned long long), c->stream));
+    CRK_TRY(zero_async(c, cnt, 2));
     {
         KTimer kt_(c, "k_corrections");
         k_corrections<<<nblocks(n), kBlock, 0, c->stream>>>(n, m0, m1, m2, gm0, gm1, gm2, A, B, gA, gB, cnt);
@@ -891,7 +891,7 @@ crk_status crk_derivatives(crk_ctx *c, const crk_params *p, const double *v, con
                 0.5 * p->a * p->a, 0.5 / (p->a * p->a), p->adot, p->eta_crit, 1.0 / p->eta_fold};
     CRK_TRY(ensure(c, c->misc, 256));
     int *bad = (int *)c->misc.p + 2;
-    CRK_HIP(c, hipMemsetAsync(bad, 0, sizeof(int), c->stream));
+    CRK_TRY(zero_async(c, bad, 1));
     int Gg = c->G_grad, Gd = c->G_der;
 
     // adaptive mode: FP64 rows for ill-conditioned RK templates

@@ -26,10 +26,27 @@ def params_for(ps, nres: float = 64.0, precision: int = CRK_FP64, **over) -> Par
     return p
 
 
+def concat(boxes) -> tuple:
+    """Particle sets of a batch -> one concatenated set and the box offsets."""
+    import crk_inputs as ci
+    off = np.concatenate([[0], np.cumsum([b.n for b in boxes])]).astype(np.int64)
+    cat = lambda k: np.concatenate([getattr(b, k) for b in boxes])
+    rho = None if any(b.rho is None for b in boxes) else cat("rho")
+    ps = ci.ParticleSet(cat("x"), cat("y"), cat("z"), cat("H"), cat("m"), cat("u"),
+                        np.concatenate([b.v for b in boxes], axis=1), rho, L=boxes[0].L,
+                        gamma=boxes[0].gamma, meta=dict(kind="batch", boxes=len(boxes)))
+    return ps, off
+
+
 def step(ctx: Context, dev: dict, params: Params, cell_size: float = 0.0,
-         count_singular: bool = True) -> dict:
-    """All passes of one step; every returned array is in cell-sorted order."""
-    perm, npairs = ctx.build_cells(dev["x"], dev["y"], dev["z"], dev["H"], params, cell_size)
+         count_singular: bool = True, box_offsets=None) -> dict:
+    """All passes of one step; every returned array is in cell-sorted order.
+    With box_offsets (host, nboxes+1) the arrays hold a batch of boxes."""
+    if box_offsets is None:
+        perm, npairs = ctx.build_cells(dev["x"], dev["y"], dev["z"], dev["H"], params, cell_size)
+    else:
+        perm, npairs = ctx.build_cells_batch(box_offsets, dev["x"], dev["y"], dev["z"], dev["H"],
+                                             params, cell_size)
     mom = ctx.moments(params)
     corr = ctx.corrections(mom, count_singular=count_singular)
     v = ctx.permute(dev["v"], True)
@@ -59,4 +76,4 @@ def to_original(out: dict, perm: torch.Tensor) -> dict:
     return res
 
 
-__all__ = ["upload", "params_for", "step", "to_original", "CRK_FP64", "CRK_MIXED"]
+__all__ = ["upload", "params_for", "step", "to_original", "concat", "CRK_FP64", "CRK_MIXED"]
