@@ -63,7 +63,8 @@ typedef enum {
     CRK_ERR_SUPPORT = -3,       /* H <= 0 or max H >= L/2 (the minimum image would be ambiguous) */
     CRK_ERR_WORKSPACE = -4,     /* device allocation of the workspace failed */
     CRK_ERR_HIP = -5,           /* a HIP runtime call failed */
-    CRK_ERR_STATE = -6          /* called out of order (e.g. crk_moments before crk_build_cells) */
+    CRK_ERR_STATE = -6,         /* called out of order (e.g. crk_moments before crk_build_cells) */
+    CRK_ERR_CAPACITY = -7       /* a replayed step's lists outgrew the capacity recorded in the graph */
 } crk_status;
 
 /* Arithmetic of the pair passes. */
@@ -200,6 +201,74 @@ crk_status crk_derivatives(crk_ctx *ctx, const crk_params *p, const double *v, c
                            double *dpdt, double *dudt);
 
 /*
+ * One whole step: S1 build (all boxes of a batch), S2 volumes, S4 moments,
+ * S5 corrections, S6 velocity gradient and S7 derivatives, i.e. the calls
+ * crk_build_cells_batch, crk_moments, crk_corrections, crk_derivatives in
+ * that order (Sec. 3.3: one interaction list per step, reused by every pass).
+ * Inputs are in the original particle order, outputs in the sorted order;
+ * every pointer is a caller-owned DEVICE array. rho may be NULL (rho = m/V);
+ * every other member must be set.
+ */
+typedef struct {
+    const double *x, *y, *z, *H; /* [n] positions in [0, L), support radii   */
+    const double *v;             /* [3][n] peculiar velocity                  */
+    const double *m, *u;         /* [n] masses, specific internal energies    */
+    const double *rho;           /* [n] densities or NULL                     */
+    int32_t *perm;               /* [n] sorted k -> original index            */
+    double *V;                   /* [n] volumes                               */
+    double *m0, *m1, *m2, *gm0, *gm1, *gm2; /* as crk_moments                 */
+    double *A, *B, *gA, *gB;     /* as crk_corrections                        */
+    double *gradv, *dpdt, *dudt; /* as crk_derivatives                        */
+} crk_step_io;
+
+/* The step, eagerly. box_offsets: HOST int64 [nboxes+1] as in
+ * crk_build_cells_batch. *n_pairs, *n_singular: host, may be NULL.
+ * Synchronises the stream. Returns CRK_WARN_SINGULAR as crk_corrections. */
+crk_status crk_step(crk_ctx *ctx, int32_t nboxes, const int64_t *box_offsets, int64_t n,
+                    const crk_step_io *io, const crk_params *p, double cell_size,
+                    int64_t *n_pairs, int64_t *n_singular);
+
+/* Device-side status of a replayed step (filled by crk_graph_replay). */
+typedef struct {
+    int64_t n_pairs;        /* ordered pairs of the replayed lists           */
+    int64_t n_singular;     /* particles on the singular-m2 fallback         */
+    int64_t n_fp64_rows;    /* CRK_MIXED_ADAPT: particles over kappa_max     */
+    int64_t n_touched_rows; /* CRK_MIXED_ADAPT: particles with an FP64 pair  */
+    int32_t input_error;    /* bit 0 non-finite, 1 outside [0, L), 2 H <= 0, 3 H >= L/2 */
+    int32_t overflow;       /* 1: lists outgrew the recorded capacity        */
+    int32_t state_error;    /* 1: non-finite or non-positive gas state       */
+    int32_t reserved;
+} crk_graph_status;
+
+/*
+ * S10: record the step once as a HIP graph, then replay it.
+ * crk_graph_capture runs the step eagerly (checks the input, fixes the cell
+ * geometry: box layout, L and the finest cell side), sizes the neighbour
+ * lists at (1 + headroom) times the measured counts plus 1024, runs the
+ * graph form of the step once, and records it (on a stream of its own, so
+ * the context's stream may be the null stream). The outputs then hold the
+ * step's results. The graph keeps every pointer of *io and every value of *p
+ * and box_offsets: a replay re-reads the same input arrays (update them in
+ * place between replays) and rewrites the same outputs; n and the boxes are
+ * fixed. crk_graph_replay launches the graph on the context's stream; with
+ * st == NULL it returns at once (no synchronisation), else it waits, fills
+ * *st and returns: CRK_ERR_NONFINITE / CRK_ERR_INVALID_ARG / CRK_ERR_SUPPORT
+ * for invalid positions or H (the offending particles were moved to stand-in
+ * points with a vanishing support, so the replay itself stays in bounds),
+ * CRK_ERR_CAPACITY when the lists outgrew the capacity (every row was
+ * emptied; capture again), CRK_ERR_NONFINITE for a bad gas state,
+ * CRK_WARN_SINGULAR as crk_corrections. On any error the outputs are not
+ * valid. A workspace reallocation by a later call (e.g. a larger build on
+ * the same context) discards the graph (replay then gives CRK_ERR_STATE).
+ * One recorded step per context; crk_graph_destroy releases it.
+ */
+crk_status crk_graph_capture(crk_ctx *ctx, int32_t nboxes, const int64_t *box_offsets, int64_t n,
+                             const crk_step_io *io, const crk_params *p, double cell_size,
+                             double headroom);
+crk_status crk_graph_replay(crk_ctx *ctx, crk_graph_status *st);
+crk_status crk_graph_destroy(crk_ctx *ctx);
+
+/*
  * S3: smoothing-length iteration, eqs. (hi), (thacker). For each particle on
  * its own (its neighbour count depends only on its own H):
  *   N = (4 pi/3) H^3 sum_j W(|d|, H),  Delta = (Nres / N)^(1/3),
@@ -289,10 +358,12 @@ crk_status crk_set_walk(crk_ctx *ctx, int32_t lanes, int32_t cap);
 
 /* Per-kernel timing (off by default). While enabled, every kernel launch of
  * the library is bracketed by a pair of HIP events recorded on the context's
- * stream. crk_timing_read synchronises the stream and returns the summed
- * event time (ms) and the launch count for one kernel name ("k_walk_count",
- * "k_walk_fill", "k_volume", "k_moments", "k_corrections", "k_gradv",
- * "k_pack", "k_deriv", "k_hsolve", "sort"); crk_timing_reset clears the sums. */
+ * stream (graph replays are not timed). crk_timing_read synchronises the
+ * stream and returns the summed event time (ms) and the launch count for one
+ * kernel name ("sort", "k_walk", "k_compact_rows", "k_walk_long",
+ * "k_sort_extras", "k_volume", "k_moments", "k_corrections", "k_flag",
+ * "k_pack", "k_gradv", "k_gradv_fix", "k_deriv", "k_deriv_fix", "k_hsolve",
+ * ...); crk_timing_reset clears the sums. */
 crk_status crk_timing_enable(crk_ctx *ctx, int32_t on);
 crk_status crk_timing_reset(crk_ctx *ctx);
 crk_status crk_timing_read(crk_ctx *ctx, const char *kernel, double *total_ms, int64_t *launches);

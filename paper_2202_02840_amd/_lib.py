@@ -12,7 +12,8 @@ _LIBPATH = os.path.join(_HERE, "libcrk.so")
 CRK_FP64, CRK_MIXED, CRK_MIXED_ADAPT = 0, 1, 2
 STATUS = {0: "CRK_OK", 1: "CRK_WARN_SINGULAR", 2: "CRK_WARN_NOT_CONVERGED",
           -1: "CRK_ERR_INVALID_ARG", -2: "CRK_ERR_NONFINITE", -3: "CRK_ERR_SUPPORT",
-          -4: "CRK_ERR_WORKSPACE", -5: "CRK_ERR_HIP", -6: "CRK_ERR_STATE"}
+          -4: "CRK_ERR_WORKSPACE", -5: "CRK_ERR_HIP", -6: "CRK_ERR_STATE",
+          -7: "CRK_ERR_CAPACITY"}
 
 # every symbol include/crk.h declares
 EXPORTS = ("crk_params_default", "crk_create", "crk_destroy", "crk_last_error", "crk_build_cells",
@@ -21,8 +22,27 @@ EXPORTS = ("crk_params_default", "crk_create", "crk_destroy", "crk_last_error", 
            "crk_derivatives", "crk_hsolve", "crk_export_neighbors", "crk_set_lanes", "crk_set_walk", "crk_set_hsolve",
            "crk_timing_enable", "crk_timing_reset", "crk_timing_read", "crk_adaptive_rows",
            "crk_hnet_features", "crk_hnet_forward", "crk_hnet_train_step", "crk_hnet_seed",
-           "crk_hnet_targets",
+           "crk_hnet_targets", "crk_step", "crk_graph_capture", "crk_graph_replay",
+           "crk_graph_destroy",
            "crk_version")
+
+# members of crk_step_io, in order
+STEP_INPUTS = ("x", "y", "z", "H", "v", "m", "u", "rho")
+STEP_OUTPUTS = ("perm", "V", "m0", "m1", "m2", "gm0", "gm1", "gm2", "A", "B", "gA", "gB", "gradv",
+                "dpdt", "dudt")
+
+
+class StepIO(C.Structure):
+    _fields_ = [(k, C.c_void_p) for k in STEP_INPUTS + STEP_OUTPUTS]
+
+
+class GraphStatus(C.Structure):
+    _fields_ = [(k, C.c_int64) for k in ("n_pairs", "n_singular", "n_fp64_rows",
+                                         "n_touched_rows")] + \
+               [(k, C.c_int32) for k in ("input_error", "overflow", "state_error", "reserved")]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
 
 
 class CrkError(RuntimeError):
@@ -91,6 +111,10 @@ def lib():
             "crk_hnet_train_step": ([p, p, p, p, i64, C.c_float, p, p, i64, p, p], i32),
             "crk_hnet_seed": ([p, p, d, p, p], i32),
             "crk_hnet_targets": ([p, i64, p, p, p], i32),
+            "crk_step": ([p, i32, p, i64, p, p, d, p, p], i32),
+            "crk_graph_capture": ([p, i32, p, i64, p, p, d, d], i32),
+            "crk_graph_replay": ([p, p], i32),
+            "crk_graph_destroy": ([p], i32),
             "crk_version": ([], C.c_char_p),
         }
         for name, (args, res) in sigs.items():
@@ -244,6 +268,72 @@ class Context:
                                    _ptr(out["gradv"]), _ptr(out["dpdt"]), _ptr(out["dudt"]))
         self._check(st, "crk_derivatives")
         return out
+
+    # ---------------------------------------------------------------- whole step / S10 graph
+    def step_buffers(self, dev: dict) -> dict:
+        """Inputs of `dev` (original order) plus freshly allocated outputs."""
+        n = dev["x"].shape[0]
+        e = self._empty
+        io = {k: dev.get(k) for k in STEP_INPUTS}
+        io.update(perm=e(n, dtype=torch.int32), V=e(n), m0=e(n), m1=e(3, n), m2=e(6, n),
+                  gm0=e(3, n), gm1=e(9, n), gm2=e(18, n), A=e(n), B=e(3, n), gA=e(3, n),
+                  gB=e(9, n), gradv=e(9, n), dpdt=e(3, n), dudt=e(n))
+        return io
+
+    def _io(self, io: dict):
+        _f64(*[io[k] for k in STEP_INPUTS + STEP_OUTPUTS if k != "perm"])
+        s = StepIO()
+        for k in STEP_INPUTS + STEP_OUTPUTS:
+            setattr(s, k, None if io.get(k) is None else io[k].data_ptr())
+            if io.get(k) is not None:
+                _ptr(io[k])
+        return s
+
+    def step(self, io: dict, params: Params, box_offsets=None, cell_size: float = 0.0):
+        """crk_step on the buffers of `io` (see step_buffers); returns
+        (n_pairs, n_singular)."""
+        import numpy as np
+        n = io["x"].shape[0]
+        off = np.ascontiguousarray([0, n] if box_offsets is None else box_offsets, dtype=np.int64)
+        s = self._io(io)
+        npairs, ns = C.c_int64(), C.c_int64()
+        st = lib().crk_step(self._h, len(off) - 1, off.ctypes.data_as(C.c_void_p), n, C.byref(s),
+                            C.byref(params), C.c_double(cell_size), C.byref(npairs), C.byref(ns))
+        self._check(st, "crk_step")
+        self.n, self.n_pairs, self.perm = n, npairs.value, io["perm"]
+        return npairs.value, ns.value
+
+    def graph_capture(self, io: dict, params: Params, box_offsets=None, cell_size: float = 0.0,
+                      headroom: float = 0.25):
+        """Record the step on the buffers of `io` as a graph (the buffers are
+        kept alive with the graph); the outputs hold the step's results."""
+        import numpy as np
+        n = io["x"].shape[0]
+        off = np.ascontiguousarray([0, n] if box_offsets is None else box_offsets, dtype=np.int64)
+        s = self._io(io)
+        st = lib().crk_graph_capture(self._h, len(off) - 1, off.ctypes.data_as(C.c_void_p), n,
+                                     C.byref(s), C.byref(params), C.c_double(cell_size),
+                                     C.c_double(headroom))
+        self._check(st, "crk_graph_capture")
+        self._graph_io = io
+        self.n, self.perm = n, io["perm"]
+
+    def graph_replay(self, status: bool = True, check: bool = True):
+        """Replay the recorded step; with status, wait and return (status
+        code, status dict). check raises on an error code."""
+        if not status:
+            self._check(lib().crk_graph_replay(self._h, None), "crk_graph_replay")
+            return 0, None
+        gs = GraphStatus()
+        st = lib().crk_graph_replay(self._h, C.byref(gs))
+        if check:
+            self._check(st, "crk_graph_replay")
+        self.n_pairs = gs.n_pairs
+        return st, gs.as_dict()
+
+    def graph_destroy(self):
+        self._check(lib().crk_graph_destroy(self._h), "crk_graph_destroy")
+        self._graph_io = None
 
     # ---------------------------------------------------------------- S3
     def hsolve(self, Nres: float, H_sorted, tol: float = 1e-7, max_iter: int = 100):

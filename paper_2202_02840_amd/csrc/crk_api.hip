@@ -28,7 +28,10 @@ crk_status hip_err(crk_ctx *c, hipError_t e, const char *what) {
 crk_status ensure(crk_ctx *c, Buf &b, size_t bytes) {
     if (bytes == 0) bytes = 256;
     if (b.bytes >= bytes) return CRK_OK;
+    if (c->capturing)
+        return set_err(c, CRK_ERR_STATE, "workspace of %zu bytes needed while recording a graph", bytes);
     if (b.p) {
+        graph_release(c);                     // a recorded graph holds the old address
         hipError_t e = hipStreamSynchronize(c->stream);
         if (e != hipSuccess) return hip_err(c, e, "hipStreamSynchronize");
         hipFree(b.p);
@@ -73,7 +76,7 @@ static hipEvent_t pool_get(crk_ctx *c) {
 }
 
 KTimer::KTimer(crk_ctx *ctx, const char *nm) : c(ctx), name(nm) {
-    if (!c->timing) return;
+    if (!c->timing || c->capturing) return;
     a = pool_get(c);
     b = pool_get(c);
     if (a && b) hipEventRecord(a, c->stream);
@@ -195,7 +198,9 @@ void crk_destroy(crk_ctx *c) {
                        &c->rec6, &c->rec7,  &c->red,   &c->misc, &c->flag, &c->flist,
                        &c->tlist, &c->fpos, &c->tpos,  &c->rec6d, &c->aux, &c->scratch,
                        &c->hnet_part, &c->hnet_feat, &c->hs_list, &c->hs_state, &c->hs_pos,
-                       &c->hs_iters, &c->hs_rows, &c->hs_rcnt, &c->hs_R, &c->boff};
+                       &c->hs_iters, &c->hs_rows, &c->hs_rcnt, &c->hs_R, &c->boff,
+                       &c->sv, &c->sm, &c->su, &c->srho, &c->gstat, &c->gboff};
+    crk::graph_release(c);
     for (crk::Buf *b : all)
         if (b->p) hipFree(b->p);
     if (c->pinned.p) hipHostFree(c->pinned.p);

@@ -77,6 +77,21 @@ __global__ void k_validate_final(const double *part, int nblk, double *out) {
     out[2] = hsum;
 }
 
+// Graph mode cannot stop on invalid input before the walk, so such a
+// particle is moved to a fixed in-box point (the R3 low-discrepancy sequence
+// of its index) with a vanishing support: every later access stays in
+// bounds, and the step's status reports the error.
+__device__ __forceinline__ bool invalid_particle(double x, double y, double z, double h, double L) {
+    return !(x >= 0.0 && x < L && y >= 0.0 && y < L && z >= 0.0 && z < L && h > 0.0 && h < 0.5 * L);
+}
+
+__device__ __forceinline__ double4 stand_in(int64_t i, double L) {
+    double t = (double)i;
+    return make_double4(L * (t * 0.8191725133961645 - floor(t * 0.8191725133961645)),
+                        L * (t * 0.6710436067037893 - floor(t * 0.6710436067037893)),
+                        L * (t * 0.5497004779019703 - floor(t * 0.5497004779019703)), 1e-9 * L);
+}
+
 __device__ __forceinline__ int cell_of(double x, double inv_c, int nc) {
     int k = (int)floor(x * inv_c);
     return k < 0 ? 0 : (k >= nc ? nc - 1 : k);
@@ -87,7 +102,7 @@ __device__ __forceinline__ int cell_of(double x, double inv_c, int nc) {
 __global__ __launch_bounds__(kBlock) void k_keys(const double *x, const double *y, const double *z,
                                                  int64_t n, double inv_c, int nc, int bits,
                                                  const int64_t *__restrict__ boff, int nboxes,
-                                                 uint32_t *key, int32_t *val) {
+                                                 const double *H, double L, uint32_t *key, int32_t *val) {
     int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i >= n) return;
     int lo = 0, hi = nboxes - 1;
@@ -96,7 +111,14 @@ __global__ __launch_bounds__(kBlock) void k_keys(const double *x, const double *
         if (boff[mid] <= i) lo = mid;
         else hi = mid - 1;
     }
-    uint32_t m = morton3(cell_of(x[i], inv_c, nc), cell_of(y[i], inv_c, nc), cell_of(z[i], inv_c, nc));
+    double px = x[i], py = y[i], pz = z[i];
+    if (H && invalid_particle(px, py, pz, H[i], L)) {
+        double4 s = stand_in(i, L);
+        px = s.x;
+        py = s.y;
+        pz = s.z;
+    }
+    uint32_t m = morton3(cell_of(px, inv_c, nc), cell_of(py, inv_c, nc), cell_of(pz, inv_c, nc));
     key[i] = ((uint32_t)lo << (3 * bits)) | m;
     val[i] = (int32_t)i;
 }
@@ -104,11 +126,57 @@ __global__ __launch_bounds__(kBlock) void k_keys(const double *x, const double *
 __global__ __launch_bounds__(kBlock) void k_gather_sorted(const double *x, const double *y,
                                                           const double *z, const double *H,
                                                           const int32_t *perm, int64_t n,
-                                                          double4 *posH) {
+                                                          int stand_ins, double L, double4 *posH) {
     int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (k >= n) return;
     int32_t i = perm[k];
-    posH[k] = make_double4(x[i], y[i], z[i], H[i]);
+    double4 p = make_double4(x[i], y[i], z[i], H[i]);
+    if (stand_ins && invalid_particle(p.x, p.y, p.z, p.w, L)) p = stand_in(i, L);
+    posH[k] = p;
+}
+
+// graph mode: the input checks of the eager build, as a status word
+// (bit 0 non-finite, bit 1 outside [0, L), bit 2 H <= 0, bit 3 H >= L/2)
+__global__ void k_graph_inputs(const double *res, const int *flags, double L, GraphStat *st) {
+    int e = (flags[0] ? 1 : 0) | (flags[1] ? 2 : 0) | (flags[2] || !(res[1] > 0.0) ? 4 : 0);
+    if (!flags[0] && !(res[0] < 0.5 * L)) e |= 8;
+    st->input_error = e;
+    st->overflow = 0;
+    st->clear = 0;
+}
+
+// graph mode: lists longer than the recorded capacity empty every row (so
+// that the fills below stay in bounds) and raise the overflow flag
+__global__ void k_graph_cap(const int64_t *goff, const int64_t *esoff, int64_t n, int64_t gcap,
+                            int64_t ecap, GraphStat *st) {
+    int64_t G = goff[n], E = esoff[n];
+    int o = (G > gcap || E > ecap) ? 1 : 0;
+    st->overflow = o;
+    st->clear = o;
+    st->n_gather = o ? 0 : G;
+    st->n_extra = o ? 0 : E;
+}
+
+__global__ __launch_bounds__(kBlock) void k_graph_clear(const GraphStat *st, int64_t n, int64_t *goff,
+                                                        int64_t *esoff, int32_t *ng, int32_t *nes) {
+    int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i > n || !st->clear) return;
+    goff[i] = 0;
+    esoff[i] = 0;
+    if (i < n) {
+        ng[i] = 0;
+        nes[i] = 0;
+    }
+}
+
+// graph mode: the extras are sorted over the whole capacity; slots past the
+// device count get a key above every particle index, so they sort last
+__global__ __launch_bounds__(kBlock) void k_pad_extras(const int64_t *esoff, int64_t n, int64_t cap,
+                                                       uint32_t pad, uint32_t *ekey, int32_t *eval) {
+    int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (k >= cap || k < esoff[n]) return;
+    ekey[k] = pad;
+    eval[k] = 0;
 }
 
 __global__ __launch_bounds__(kBlock) void k_fill_i32(int32_t *a, int64_t n, int32_t v) {
@@ -271,11 +339,12 @@ __global__ __launch_bounds__(kBlock) void k_to_i64(const int32_t *a, int64_t n, 
 }
 
 // extras rows: the sorted keys are the receiving particles j
-__global__ __launch_bounds__(kBlock) void k_extra_ranges(const uint32_t *ekey, int64_t E, int32_t *eb,
-                                                         int32_t *ee) {
+__global__ __launch_bounds__(kBlock) void k_extra_ranges(const uint32_t *ekey, int64_t E, int64_t n,
+                                                         int32_t *eb, int32_t *ee) {
     int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (k >= E) return;
     uint32_t j = ekey[k];
+    if ((int64_t)j >= n) return;   // graph-mode padding
     if (k == 0 || ekey[k - 1] != j) eb[j] = (int32_t)k;
     if (k == E - 1 || ekey[k + 1] != j) ee[j] = (int32_t)(k + 1);
 }
@@ -395,11 +464,23 @@ static crk_status build_lists(crk_ctx *c) {
     k_to_i64<<<nblocks(n + 1), kBlock, 0, c->stream>>>(nes, n, esoff);
     CRK_TRY(scan_exclusive_i64(c, goff, goff, n + 1));
     CRK_TRY(scan_exclusive_i64(c, esoff, esoff, n + 1));
-    int64_t *pin = (int64_t *)c->pinned.p;
-    CRK_HIP(c, hipMemcpyAsync(pin, goff + n, sizeof(int64_t), hipMemcpyDeviceToHost, c->stream));
-    CRK_HIP(c, hipMemcpyAsync(pin + 1, esoff + n, sizeof(int64_t), hipMemcpyDeviceToHost, c->stream));
-    CRK_HIP(c, hipStreamSynchronize(c->stream));
-    int64_t G = pin[0], E = pin[1];
+    int64_t G, E;
+    GraphStat *gst = (GraphStat *)c->gstat.p;
+    if (c->graph_mode) {
+        // fixed capacities; the counts stay on the device
+        G = c->gcap;
+        E = c->ecap;
+        k_graph_cap<<<1, 1, 0, c->stream>>>(goff, esoff, n, G, E, gst);
+        k_graph_clear<<<nblocks(n + 1), kBlock, 0, c->stream>>>(gst, n, goff, esoff, ng, nes);
+        CRK_HIP(c, hipGetLastError());
+    } else {
+        int64_t *pin = (int64_t *)c->pinned.p;
+        CRK_HIP(c, hipMemcpyAsync(pin, goff + n, sizeof(int64_t), hipMemcpyDeviceToHost, c->stream));
+        CRK_HIP(c, hipMemcpyAsync(pin + 1, esoff + n, sizeof(int64_t), hipMemcpyDeviceToHost, c->stream));
+        CRK_HIP(c, hipStreamSynchronize(c->stream));
+        G = pin[0];
+        E = pin[1];
+    }
     if (E > INT32_MAX - 1) return set_err(c, CRK_ERR_INVALID_ARG, "more than 2^31 extra pairs");
     CRK_TRY(ensure(c, c->gidx, (size_t)(G > 0 ? G : 1) * sizeof(int32_t)));
     CRK_TRY(ensure(c, c->ekey, (size_t)(E > 0 ? E : 1) * sizeof(uint32_t)));
@@ -432,7 +513,14 @@ static crk_status build_lists(crk_ctx *c) {
     // extras arrive grouped by the emitting particle i (ascending); a stable
     // sort on the receiving particle j keeps them ascending in i per row
     int ebits = 0;
-    while (((int64_t)1 << ebits) < n) ebits++;
+    if (c->graph_mode) {
+        // padding key n must sort after every particle index
+        while (((int64_t)1 << ebits) <= n) ebits++;
+        if (E > 0)
+            k_pad_extras<<<nblocks(E), kBlock, 0, c->stream>>>(esoff, n, E, (uint32_t)n, ekey, eidx);
+    } else {
+        while (((int64_t)1 << ebits) < n) ebits++;
+    }
     {
         KTimer kt_(c, "k_sort_extras");
         CRK_TRY(radix_sort_pairs(c, ekey, eidx, E, ebits));
@@ -440,14 +528,61 @@ static crk_status build_lists(crk_ctx *c) {
     k_fill_i32<<<nblocks(n), kBlock, 0, c->stream>>>((int32_t *)c->eb.p, n, 0);
     k_fill_i32<<<nblocks(n), kBlock, 0, c->stream>>>((int32_t *)c->ee.p, n, 0);
     if (E > 0)
-        k_extra_ranges<<<nblocks(E), kBlock, 0, c->stream>>>(ekey, E, (int32_t *)c->eb.p,
+        k_extra_ranges<<<nblocks(E), kBlock, 0, c->stream>>>(ekey, E, n, (int32_t *)c->eb.p,
                                                               (int32_t *)c->ee.p);
     CRK_HIP(c, hipGetLastError());
-    c->ngather = G;
-    c->nextra = E;
-    c->npairs = G + E;
+    if (c->graph_mode) {
+        // counts are on the device (crk_graph_replay reads them)
+        c->ngather = c->nextra = c->npairs = -1;
+    } else {
+        c->ngather = G;
+        c->nextra = E;
+        c->npairs = G + E;
+    }
     c->built = 1;
     c->have_V = 0;
+    return CRK_OK;
+}
+
+// Steps 2-4 of the build for the geometry held in the context (box offsets
+// already on the device). stand_ins: graph mode (see stand_in).
+crk_status build_sorted(crk_ctx *c, const double *x, const double *y, const double *z,
+                               const double *H, int32_t *perm, bool stand_ins, int64_t *n_pairs,
+                               int32_t *n_cells) {
+    const int64_t n = c->n;
+    const int bits = c->bits;
+    const int nboxes = (int)c->nboxes;
+    int boxbits = 0;
+    while ((1 << boxbits) < nboxes) boxbits++;
+    int64_t ntot = c->ntab * nboxes;
+    CRK_TRY(ensure(c, c->keyA, (size_t)n * sizeof(uint32_t)));
+    CRK_TRY(ensure(c, c->perm, (size_t)n * sizeof(int32_t)));
+    uint32_t *key = (uint32_t *)c->keyA.p;
+    int32_t *pm = (int32_t *)c->perm.p;
+    k_keys<<<nblocks(n), kBlock, 0, c->stream>>>(x, y, z, n, 1.0 / c->cell, c->nc, bits,
+                                                  (const int64_t *)(c->graph_mode ? c->gboff.p : c->boff.p),
+                                                  nboxes, stand_ins ? H : nullptr, c->L, key, pm);
+    CRK_HIP(c, hipGetLastError());
+    {
+        KTimer kt_(c, "sort");
+        CRK_TRY(radix_sort_pairs(c, key, pm, n, 3 * bits + boxbits));
+    }
+    // 3. sorted particles and the cell tables of every level of every box
+    CRK_TRY(ensure(c, c->posH, (size_t)n * sizeof(double4)));
+    CRK_TRY(ensure(c, c->cbeg, (size_t)ntot * sizeof(int32_t)));
+    CRK_TRY(ensure(c, c->cend, (size_t)ntot * sizeof(int32_t)));
+    k_gather_sorted<<<nblocks(n), kBlock, 0, c->stream>>>(x, y, z, H, pm, n, stand_ins ? 1 : 0, c->L,
+                                                           (double4 *)c->posH.p);
+    k_fill_i32<<<nblocks(ntot), kBlock, 0, c->stream>>>((int32_t *)c->cbeg.p, ntot, 0);
+    k_fill_i32<<<nblocks(ntot), kBlock, 0, c->stream>>>((int32_t *)c->cend.p, ntot, 0);
+    k_tables<<<nblocks(n), kBlock, 0, c->stream>>>(key, n, levels(c), (int32_t *)c->cbeg.p,
+                                                    (int32_t *)c->cend.p);
+    CRK_HIP(c, hipGetLastError());
+    CRK_HIP(c, hipMemcpyAsync(perm, pm, (size_t)n * sizeof(int32_t), hipMemcpyDeviceToDevice, c->stream));
+    // 4. neighbour lists
+    CRK_TRY(build_lists(c));
+    if (n_pairs) *n_pairs = c->npairs;
+    if (n_cells) *n_cells = c->nc;
     return CRK_OK;
 }
 
@@ -472,12 +607,17 @@ crk_status crk_build_cells_batch(crk_ctx *c, int32_t nboxes, const int64_t *box_
         if (box_offsets[b + 1] < box_offsets[b])
             return set_err(c, CRK_ERR_INVALID_ARG, "box offsets must not decrease");
     CRK_HIP(c, hipSetDevice(c->device));
-    c->built = 0;
+    const bool gm = c->graph_mode != 0;
+    if (gm && (n != c->n || nboxes != c->nboxes || p->L != c->L || !c->built))
+        return set_err(c, CRK_ERR_STATE, "graph mode needs the geometry of the last build");
+    if (!gm) {
+        c->built = 0;
+        c->nc = 0;
+        c->n = n;
+        c->L = p->L;
+        c->nboxes = nboxes;
+    }
     c->have_V = 0;
-    c->nc = 0;
-    c->n = n;
-    c->L = p->L;
-    c->nboxes = nboxes;
     // 1. validate and reduce H
     int nblk = (int)std::min<int64_t>((n + kBlock - 1) / kBlock, 1024);
     CRK_TRY(ensure(c, c->red, (size_t)nblk * 3 * sizeof(double) + 64));
@@ -489,6 +629,12 @@ crk_status crk_build_cells_batch(crk_ctx *c, int32_t nboxes, const int64_t *box_
     k_validate<<<nblk, kBlock, 0, c->stream>>>(x, y, z, H, n, p->L, part, flags);
     k_validate_final<<<1, 1, 0, c->stream>>>(part, nblk, res);
     CRK_HIP(c, hipGetLastError());
+    if (gm) {
+        CRK_TRY(ensure(c, c->gstat, sizeof(GraphStat)));
+        k_graph_inputs<<<1, 1, 0, c->stream>>>(res, flags, p->L, (GraphStat *)c->gstat.p);
+        CRK_HIP(c, hipGetLastError());
+        return build_sorted(c, x, y, z, H, perm, true, n_pairs, n_cells);
+    }
     double *pin = (double *)c->pinned.p;
     CRK_HIP(c, hipMemcpyAsync(pin, res, 3 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
     CRK_HIP(c, hipMemcpyAsync(pin + 3, flags, 3 * sizeof(int), hipMemcpyDeviceToHost, c->stream));
@@ -520,37 +666,10 @@ crk_status crk_build_cells_batch(crk_ctx *c, int32_t nboxes, const int64_t *box_
         off += m * m * m;
     }
     c->ntab = off;
-    int64_t ntot = off * nboxes;
-    CRK_TRY(ensure(c, c->keyA, (size_t)n * sizeof(uint32_t)));
-    CRK_TRY(ensure(c, c->perm, (size_t)n * sizeof(int32_t)));
     CRK_TRY(ensure(c, c->boff, (size_t)(nboxes + 1) * sizeof(int64_t)));
     CRK_HIP(c, hipMemcpyAsync(c->boff.p, box_offsets, (size_t)(nboxes + 1) * sizeof(int64_t),
                               hipMemcpyHostToDevice, c->stream));
-    uint32_t *key = (uint32_t *)c->keyA.p;
-    int32_t *pm = (int32_t *)c->perm.p;
-    k_keys<<<nblocks(n), kBlock, 0, c->stream>>>(x, y, z, n, 1.0 / c->cell, c->nc, bits,
-                                                  (const int64_t *)c->boff.p, nboxes, key, pm);
-    CRK_HIP(c, hipGetLastError());
-    {
-        KTimer kt_(c, "sort");
-        CRK_TRY(radix_sort_pairs(c, key, pm, n, 3 * bits + boxbits));
-    }
-    // 3. sorted particles and the cell tables of every level of every box
-    CRK_TRY(ensure(c, c->posH, (size_t)n * sizeof(double4)));
-    CRK_TRY(ensure(c, c->cbeg, (size_t)ntot * sizeof(int32_t)));
-    CRK_TRY(ensure(c, c->cend, (size_t)ntot * sizeof(int32_t)));
-    k_gather_sorted<<<nblocks(n), kBlock, 0, c->stream>>>(x, y, z, H, pm, n, (double4 *)c->posH.p);
-    k_fill_i32<<<nblocks(ntot), kBlock, 0, c->stream>>>((int32_t *)c->cbeg.p, ntot, 0);
-    k_fill_i32<<<nblocks(ntot), kBlock, 0, c->stream>>>((int32_t *)c->cend.p, ntot, 0);
-    k_tables<<<nblocks(n), kBlock, 0, c->stream>>>(key, n, levels(c), (int32_t *)c->cbeg.p,
-                                                    (int32_t *)c->cend.p);
-    CRK_HIP(c, hipGetLastError());
-    CRK_HIP(c, hipMemcpyAsync(perm, pm, (size_t)n * sizeof(int32_t), hipMemcpyDeviceToDevice, c->stream));
-    // 4. neighbour lists
-    CRK_TRY(build_lists(c));
-    if (n_pairs) *n_pairs = c->npairs;
-    if (n_cells) *n_cells = c->nc;
-    return CRK_OK;
+    return build_sorted(c, x, y, z, H, perm, false, n_pairs, n_cells);
 }
 
 crk_status crk_build_cells(crk_ctx *c, int64_t n, const double *x, const double *y, const double *z,

@@ -76,6 +76,24 @@ struct crk_ctx {
     crk::Buf hs_list, hs_state, hs_pos, hs_iters;         // smoothing-length rounds
     crk::Buf hs_rows, hs_rcnt, hs_R;                      // candidate rows (r^2)
     crk::Buf boff;                                        // batch box offsets
+    crk::Buf sv, sm, su, srho;                            // sorted gas state (crk_step)
+    crk::Buf gstat;                                       // device status of a graph step
+    crk::Buf gboff;                                       // box offsets the graph was recorded with
+
+    // graph mode (crk_graph_capture): the build keeps the geometry of the
+    // last eager build, lists are bounded by fixed capacities, and no call
+    // reads device values back on the host; `capturing` forbids workspace growth
+    int graph_mode = 0;
+    int capturing = 0;
+    int64_t gcap = 0, ecap = 0;           // gather / extras capacity
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    int graph_prec = -1;
+    struct Geo {
+        int64_t n, ntab, nboxes, lvl_off[12];
+        double L, cell;
+        int nc, bits;
+    } geo{};                              // geometry the graph was recorded with
     int G_hsolve = 4, hs_round = 8, hs_cap = 320;
     double hs_factor = 1.3;
     int64_t last_nflag = 0, last_ntouch = 0;
@@ -98,6 +116,20 @@ namespace crk {
 crk_status set_err(crk_ctx *c, crk_status s, const char *fmt, ...);
 crk_status hip_err(crk_ctx *c, hipError_t e, const char *what);
 crk_status ensure(crk_ctx *c, Buf &b, size_t bytes);
+void graph_release(crk_ctx *c);
+// steps 2-4 of crk_build_cells_batch for the geometry held in the context
+crk_status build_sorted(crk_ctx *c, const double *x, const double *y, const double *z,
+                        const double *H, int32_t *perm, bool stand_ins, int64_t *n_pairs,
+                        int32_t *n_cells);
+
+// Device status of a graph-mode step (written by the step's own kernels and
+// read back by crk_graph_replay).
+struct GraphStat {
+    int64_t n_gather, n_extra;
+    uint64_t n_singular;
+    int64_t n_flag, n_touch;
+    int32_t input_error, overflow, clear, state_error;
+};
 
 // Records a start/stop event pair around the launches in its scope when the
 // context's timing is on; the pairs are read back by crk_timing_read.

@@ -339,9 +339,14 @@ __global__ __launch_bounds__(kBlock) void k_gradv(const double4 *__restrict__ po
                                                   const double *__restrict__ gA,
                                                   const double *__restrict__ gB, int64_t n, Box box,
                                                   const int32_t *__restrict__ list, int64_t nlist,
+                                                  const int64_t *__restrict__ nlist_dev,
                                                   const int32_t *__restrict__ skip, double *gradv) {
     int l;
     int64_t g = group_index(G, l);
+    if (nlist_dev) nlist = *nlist_dev;
+    const int64_t gstride = (int64_t)gridDim.x * (kBlock / G);
+    // a list launch may cover its rows with fewer groups than rows
+    for (;; g += gstride) {
     int64_t i = -1;
     if (list) {
         if (g < nlist) i = list[g];
@@ -390,6 +395,8 @@ __global__ __launch_bounds__(kBlock) void k_gradv(const double4 *__restrict__ po
     if (i >= 0 && l == 0)
 #pragma unroll
         for (int s = 0; s < 9; s++) gradv[s * n + i] = a[s].value();
+    if (!list || g + gstride >= nlist) break;
+    }
 }
 
 // ------------------------------------------------------------- S7 derivatives
@@ -623,11 +630,15 @@ __global__ __launch_bounds__(kBlock) void k_deriv_fix(const double4 *__restrict_
                                                       const int32_t *__restrict__ eidx, Soa s,
                                                       const int32_t *__restrict__ flag,
                                                       const int32_t *__restrict__ list, int64_t nlist,
+                                                      const int64_t *__restrict__ nlist_dev,
                                                       const double *__restrict__ m, int64_t n, Box box,
                                                       DerivPrm p, double *dpdt, double *dudt) {
     int l;
     int64_t g = group_index(G, l);
-    int64_t i = g < nlist ? list[g] : -1;
+    if (nlist_dev) nlist = *nlist_dev;
+    const int64_t gstride = (int64_t)gridDim.x * (kBlock / G);
+    for (; g < nlist; g += gstride) {
+    const int64_t i = list[g];
     Acc<double> a[4];
     if (i >= 0) {
         double4 pi = posH[i];
@@ -658,12 +669,13 @@ __global__ __launch_bounds__(kBlock) void k_deriv_fix(const double4 *__restrict_
         }
     }
     group_reduce<double, G, 4>(a);
-    if (i >= 0 && l == 0) {
+    if (l == 0) {
         double im = 1.0 / m[i];
         dpdt[i] += a[0].value() * im;
         dpdt[n + i] += a[1].value() * im;
         dpdt[2 * n + i] += a[2].value() * im;
         dudt[i] += a[3].value() * im;
+    }
     }
 }
 
@@ -736,6 +748,12 @@ __global__ __launch_bounds__(kBlock) void k_pack6_d(int64_t n, const double *v, 
 
 inline unsigned nblocks(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 inline unsigned gblocks(int64_t n, int G) { return (unsigned)((n * G + kBlock - 1) / kBlock); }
+// list launches of graph mode do not know their row count on the host: a
+// bounded grid loops over the rows (the flagged rows are a small fraction)
+inline unsigned fix_blocks(int64_t rows, int G, bool graph) {
+    unsigned b = gblocks(rows, G);
+    return graph ? std::min(b, 2048u) : b;
+}
 
 #define CRK_DISPATCH_G(G, LAUNCH)                                                          \
     switch (G) {                                                                           \
@@ -897,6 +915,8 @@ crk_status crk_derivatives(crk_ctx *c, const crk_params *p, const double *v, con
     // adaptive mode: FP64 rows for ill-conditioned RK templates
     int32_t *flag = nullptr, *flist = nullptr, *tlist = nullptr;
     int64_t nflag = 0, ntouch = 0;
+    const bool gm = c->graph_mode != 0;
+    const int64_t *nflag_dev = nullptr, *ntouch_dev = nullptr;
     if (adapt) {
         CRK_TRY(ensure(c, c->flag, (size_t)n * sizeof(int32_t)));
         CRK_TRY(ensure(c, c->flist, (size_t)n * sizeof(int32_t)));
@@ -918,14 +938,22 @@ crk_status crk_derivatives(crk_ctx *c, const crk_params *p, const double *v, con
             k_compact<<<nblocks(n), kBlock, 0, c->stream>>>(n, tpos, tlist);
         }
         CRK_HIP(c, hipGetLastError());
-        int64_t *pin = (int64_t *)c->pinned.p + 40;
-        CRK_HIP(c, hipMemcpyAsync(pin, fpos + n, sizeof(int64_t), hipMemcpyDeviceToHost, c->stream));
-        CRK_HIP(c, hipMemcpyAsync(pin + 1, tpos + n, sizeof(int64_t), hipMemcpyDeviceToHost, c->stream));
-        CRK_HIP(c, hipStreamSynchronize(c->stream));
-        nflag = pin[0];
-        ntouch = pin[1];
-        c->last_nflag = nflag;
-        c->last_ntouch = ntouch;
+        if (gm) {
+            // row counts stay on the device; the fix launches loop over them
+            nflag_dev = fpos + n;
+            ntouch_dev = tpos + n;
+            nflag = ntouch = n;
+            c->last_nflag = c->last_ntouch = -1;
+        } else {
+            int64_t *pin = (int64_t *)c->pinned.p + 40;
+            CRK_HIP(c, hipMemcpyAsync(pin, fpos + n, sizeof(int64_t), hipMemcpyDeviceToHost, c->stream));
+            CRK_HIP(c, hipMemcpyAsync(pin + 1, tpos + n, sizeof(int64_t), hipMemcpyDeviceToHost, c->stream));
+            CRK_HIP(c, hipStreamSynchronize(c->stream));
+            nflag = pin[0];
+            ntouch = pin[1];
+            c->last_nflag = nflag;
+            c->last_ntouch = ntouch;
+        }
     }
 
     if (f32) {
@@ -944,14 +972,14 @@ crk_status crk_derivatives(crk_ctx *c, const crk_params *p, const double *v, con
             k_pack6_f<<<nblocks(n), kBlock, 0, c->stream>>>(n, v, V, r6);
             if (adapt) k_pack6_d<<<nblocks(n), kBlock, 0, c->stream>>>(n, v, V, r6d);
         }
-#define L_GV(GG) k_gradv<float, GG><<<gblocks(n, GG), kBlock, 0, c->stream>>>(posH, goff, gidx, r6, A, B, gA, gB, n, box, nullptr, 0, flag, gradv)
+#define L_GV(GG) k_gradv<float, GG><<<gblocks(n, GG), kBlock, 0, c->stream>>>(posH, goff, gidx, r6, A, B, gA, gB, n, box, nullptr, 0, nullptr, flag, gradv)
         {
             KTimer kt_(c, "k_gradv");
             CRK_DISPATCH_G(Gg, L_GV);
         }
 #undef L_GV
         if (adapt && nflag > 0) {
-#define L_GV(GG) k_gradv<double, GG><<<gblocks(nflag, GG), kBlock, 0, c->stream>>>(posH, goff, gidx, r6d, A, B, gA, gB, n, box, flist, nflag, nullptr, gradv)
+#define L_GV(GG) k_gradv<double, GG><<<fix_blocks(nflag, GG, gm), kBlock, 0, c->stream>>>(posH, goff, gidx, r6d, A, B, gA, gB, n, box, flist, nflag, nflag_dev, nullptr, gradv)
             KTimer kt_(c, "k_gradv_fix");
             CRK_DISPATCH_G(Gg, L_GV);
 #undef L_GV
@@ -968,7 +996,7 @@ crk_status crk_derivatives(crk_ctx *c, const crk_params *p, const double *v, con
 #undef L_DER
         if (adapt && ntouch > 0) {
             Soa s{v, V, A, B, gA, gB, gradv, aux};
-#define L_FIX(GG) k_deriv_fix<GG><<<gblocks(ntouch, GG), kBlock, 0, c->stream>>>(posH, goff, gidx, eb, ee, eidx, s, flag, tlist, ntouch, m, n, box, dp, dpdt, dudt)
+#define L_FIX(GG) k_deriv_fix<GG><<<fix_blocks(ntouch, GG, gm), kBlock, 0, c->stream>>>(posH, goff, gidx, eb, ee, eidx, s, flag, tlist, ntouch, ntouch_dev, m, n, box, dp, dpdt, dudt)
             KTimer kt_(c, "k_deriv_fix");
             CRK_DISPATCH_G(Gd, L_FIX);
 #undef L_FIX
@@ -981,7 +1009,7 @@ crk_status crk_derivatives(crk_ctx *c, const crk_params *p, const double *v, con
             KTimer kt_(c, "k_pack");
             k_pack6_d<<<nblocks(n), kBlock, 0, c->stream>>>(n, v, V, r6);
         }
-#define L_GV(GG) k_gradv<double, GG><<<gblocks(n, GG), kBlock, 0, c->stream>>>(posH, goff, gidx, r6, A, B, gA, gB, n, box, nullptr, 0, nullptr, gradv)
+#define L_GV(GG) k_gradv<double, GG><<<gblocks(n, GG), kBlock, 0, c->stream>>>(posH, goff, gidx, r6, A, B, gA, gB, n, box, nullptr, 0, nullptr, nullptr, gradv)
         {
             KTimer kt_(c, "k_gradv");
             CRK_DISPATCH_G(Gg, L_GV);
@@ -999,6 +1027,7 @@ crk_status crk_derivatives(crk_ctx *c, const crk_params *p, const double *v, con
 #undef L_DER
     }
     CRK_HIP(c, hipGetLastError());
+    if (gm) return CRK_OK;   // the graph's status kernel reads `bad`
     int *pin = (int *)c->pinned.p + 32;
     CRK_HIP(c, hipMemcpyAsync(pin, bad, sizeof(int), hipMemcpyDeviceToHost, c->stream));
     CRK_HIP(c, hipStreamSynchronize(c->stream));
