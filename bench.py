@@ -13,6 +13,10 @@ Prints one JSON line: pair-interactions/s (ordered pairs (i, j), j in N_s(i),
 counted once per step) over the whole step, the per-kernel roofline of the
 derivative pass, the max normwise error of every output against the FP64
 GPU path, and the FP64 CPU oracle timed on a smaller box of the same recipe.
+Further legs: the same step recorded once as a HIP graph and replayed
+(graph_replay), the smoothing-length network against the plain iteration
+(h_surrogate), and 512 independent boxes of 8^3..48^3 particles in one
+batched, graph-recorded step (batch).
 """
 from __future__ import annotations
 
@@ -111,6 +115,91 @@ def hsurrogate_leg(ctx, args) -> dict:
     return r
 
 
+def graph_replay_ms(ctx, io, prm, steps: int, warmup: int, box_offsets=None) -> tuple:
+    """Record the step as one HIP graph on the buffers of io and time its
+    replays (synchronised wall clock); returns (ms per replay, status)."""
+    import torch
+    ctx.graph_capture(io, prm, box_offsets=box_offsets, headroom=0.25)
+    for _ in range(warmup):
+        ctx.graph_replay(status=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ctx.graph_replay(status=False)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / max(steps, 1)
+    st, info = ctx.graph_replay()
+    return ms, st, info
+
+
+def batch_leg(args, prec, precision_name: str) -> dict:
+    """Many independent boxes of uneven size in one build and one launch per
+    pass, the whole step recorded once as a HIP graph and replayed."""
+    import crk_inputs as ci
+    import torch
+    from paper_2202_02840_amd import CRK_FP64, Context
+    from paper_2202_02840_amd import autotune as at
+    from paper_2202_02840_amd import pipeline as pl
+    t0 = time.perf_counter()
+    boxes = ci.batch_boxes(args.batch_boxes, seed=3)
+    ps, off = pl.concat(boxes)
+    gen_s = time.perf_counter() - t0
+    ctx = Context(0)
+    dev = pl.upload(ps)
+    prm = pl.params_for(ps, 64.0, prec, kappa_max=args.kappa)
+    io = ctx.step_buffers(dev)
+    npairs, _ = ctx.step(io, prm, box_offsets=off)
+    ppp = npairs / ps.n
+    if args.autotune_batch:
+        tuned, tune_ms = at.tune(ctx, dev, prm, with_hsolve=False, box_offsets=off,
+                                 log=lambda m: print(m, file=sys.stderr, flush=True))
+        if args.tune_out:
+            at.save(prec, ppp, tuned, tune_ms, f"{args.batch_boxes} boxes, sides 8..48",
+                    args.tune_out, kind="batch")
+    else:
+        tuned = at.load(prec, ppp, kind="batch")
+        if tuned:
+            at.apply(ctx, tuned)
+    # eager steps (per-kernel event times), then the recorded step
+    for _ in range(args.warmup):
+        ctx.step(io, prm, box_offsets=off)
+    ctx.timing(True)
+    ctx.timing_reset()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(args.steps):
+        ctx.step(io, prm, box_offsets=off)
+    torch.cuda.synchronize()
+    eager_ms = (time.perf_counter() - t1) * 1e3 / max(args.steps, 1)
+    kern = {}
+    for k in ("sort", "k_walk", "k_compact_rows", "k_walk_long", "k_sort_extras", "k_volume",
+              "k_moments", "k_corrections", "k_gradv", "k_deriv", "k_deriv_fix"):
+        ms, cnt = ctx.timing_read(k)
+        kern[k] = ms / max(cnt, 1)
+    ctx.timing(False)
+    g_ms, st, info = graph_replay_ms(ctx, io, prm, args.steps, args.warmup, box_offsets=off)
+    ctx.graph_destroy()
+    out = {"workload": f"{args.batch_boxes} periodic boxes, side n_b = round(exp U(ln 8, ln 48)), "
+                       f"half jittered lattice, half lognormal (sigma 1.5, P(k)~k^-2, H <= 0.3 L), "
+                       f"gamma-law gas rho, u log-uniform in [0.1, 10], seed 3; {precision_name}",
+           "boxes": args.batch_boxes, "particles": ps.n, "pairs_per_step": int(info["n_pairs"]),
+           "graph_ms_per_step": g_ms, "graph_pairs_per_s": info["n_pairs"] / (g_ms * 1e-3),
+           "eager_ms_per_step": eager_ms, "graph_status": st, "graph_info": info,
+           "lanes": tuned, "kernel_ms": kern, "generate_seconds": gen_s}
+    if not args.no_check:
+        ref = ctx.step_buffers(dev)
+        ctx.step(ref, pl.params_for(ps, 64.0, CRK_FP64), box_offsets=off)
+        torch.cuda.synchronize()
+        errs = {}
+        for k in OUT_KEYS:
+            a, b = io[k], ref[k]
+            den = b.abs().max().item()
+            errs[k] = (a - b).abs().max().item() / den if den > 0 else (a - b).abs().max().item()
+        out["max_rel_err_vs_fp64"] = errs
+        out["err_target_met"] = bool(max(errs.values()) <= 1e-5)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -134,6 +223,12 @@ def main():
                     help="write the tuned table to this path (with --autotune)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 2 GiB device-to-device copy three times (scales HBM counters)")
+    ap.add_argument("--no-graph", action="store_true",
+                    help="skip the HIP-graph replay timing of the step")
+    ap.add_argument("--no-batch", action="store_true", help="skip the many-box batch leg")
+    ap.add_argument("--batch-boxes", type=int, default=512)
+    ap.add_argument("--autotune-batch", action="store_true",
+                    help="tune the lanes on the batch workload (stored with --tune-out)")
     ap.add_argument("--kappa", type=float, default=1000.0,
                     help="conditioning bound above which the adaptive mode runs a row in FP64")
     args = ap.parse_args()
@@ -211,6 +306,17 @@ def main():
     achieved_tf = flops / t_der / 1e12
     hbm_gbs = bytes_alg / t_der / 1e9
 
+    # the same step recorded as one HIP graph and replayed
+    graph = None
+    if not args.no_graph:
+        io = ctx.step_buffers(dev)
+        g_ms, g_st, g_info = graph_replay_ms(ctx, io, prm, args.steps, args.warmup)
+        ctx.graph_destroy()
+        same = all(torch.equal(io[k], out[k]) for k in OUT_KEYS)
+        graph = {"ms_per_step": g_ms, "pairs_per_s": g_info["n_pairs"] / (g_ms * 1e-3),
+                 "status": g_st, "n_pairs": g_info["n_pairs"], "bitwise_equal_to_eager": same}
+        del io
+
     # accuracy of this path against the FP64 GPU path at full size
     errs = None
     if not args.no_check:
@@ -255,7 +361,10 @@ def main():
         "kernel_ms": kern,
         "max_rel_err_vs_fp64": errs,
         "err_target_met": None if errs is None else bool(max(errs.values()) <= 1e-5),
+        "graph_replay": graph,
     }
+    if not args.no_batch:
+        line["batch"] = batch_leg(args, prec, args.precision)
     if not args.no_hsurrogate:
         line["h_surrogate"] = hsurrogate_leg(ctx, args)
     if not args.no_cpu_baseline:

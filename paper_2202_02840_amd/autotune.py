@@ -35,9 +35,16 @@ KERNEL = {"walk": "k_walk", "vol": "k_volume", "mom": "k_moments", "grad": "k_gr
           "der": "k_deriv"}
 
 
-def key_for(precision: int, pairs_per_particle: float) -> str:
-    """Table key: precision and mean pairs per particle rounded to 16."""
-    return f"p{precision}/n{int(round(pairs_per_particle / 16.0)) * 16}"
+def key_for(precision: int, pairs_per_particle: float, kind: str = "") -> str:
+    """Table key: precision, mean pairs per particle rounded to 16, and the
+    workload kind ("" for one box, "batch" for many small boxes)."""
+    k = f"p{precision}/n{int(round(pairs_per_particle / 16.0)) * 16}"
+    return f"{k}/{kind}" if kind else k
+
+
+def _kind(key: str) -> str:
+    parts = key.split("/")
+    return parts[2] if len(parts) > 2 else ""
 
 
 def apply(ctx: Context, cfg: dict) -> None:
@@ -46,25 +53,29 @@ def apply(ctx: Context, cfg: dict) -> None:
     ctx.set_hsolve(cfg["hsolve"], 0, 0, 0.0)
 
 
-def load(precision: int, pairs_per_particle: float) -> dict | None:
+def load(precision: int, pairs_per_particle: float, kind: str = "") -> dict | None:
     if not os.path.exists(TABLE):
         return None
     tab = json.load(open(TABLE))
-    k = key_for(precision, pairs_per_particle)
+    k = key_for(precision, pairs_per_particle, kind)
     if k in tab:
         return dict(tab[k]["config"])
-    # nearest neighbour-count class of the same precision
-    same = [(abs(int(kk.split("/n")[1]) - pairs_per_particle), kk) for kk in tab
-            if kk.startswith(f"p{precision}/")]
-    return dict(tab[min(same)[1]]["config"]) if same else None
+    # nearest neighbour-count class of the same precision (and kind, if any)
+    same = [kk for kk in tab if kk.startswith(f"p{precision}/")]
+    if any(_kind(kk) == kind for kk in same):
+        same = [kk for kk in same if _kind(kk) == kind]
+    if not same:
+        return None
+    best = min(same, key=lambda kk: abs(int(kk.split("/")[1][1:]) - pairs_per_particle))
+    return dict(tab[best]["config"])
 
 
-def _time_step(ctx, dev, prm, kernel: str, reps: int) -> float:
-    pl.step(ctx, dev, prm, count_singular=False)          # settle allocations
+def _time_step(ctx, dev, prm, kernel: str, reps: int, box_offsets=None) -> float:
+    pl.step(ctx, dev, prm, count_singular=False, box_offsets=box_offsets)   # settle allocations
     ctx.timing(True)
     ctx.timing_reset()
     for _ in range(reps):
-        pl.step(ctx, dev, prm, count_singular=False)
+        pl.step(ctx, dev, prm, count_singular=False, box_offsets=box_offsets)
     torch.cuda.synchronize()
     ms, cnt = ctx.timing_read(kernel)
     ctx.timing(False)
@@ -88,7 +99,7 @@ def _time_hsolve(ctx, dev, prm, nres: float, reps: int) -> float:
 
 
 def tune(ctx: Context, dev: dict, prm, nres: float = 64.0, start: dict | None = None,
-         reps: int = 3, with_hsolve: bool = True, log=print) -> tuple[dict, dict]:
+         reps: int = 3, with_hsolve: bool = True, log=print, box_offsets=None) -> tuple[dict, dict]:
     """Coordinate descent over the knobs; returns (best config, timings)."""
     cfg = dict(start or DEFAULT)
     timings = {}
@@ -103,7 +114,7 @@ def tune(ctx: Context, dev: dict, prm, nres: float = 64.0, start: dict | None = 
             if knob == "hsolve":
                 res[g] = _time_hsolve(ctx, dev, prm, nres, max(1, reps - 1))
             else:
-                res[g] = _time_step(ctx, dev, prm, KERNEL[knob], reps)
+                res[g] = _time_step(ctx, dev, prm, KERNEL[knob], reps, box_offsets)
         best = min(res, key=res.get)
         cfg[knob] = best
         timings[knob] = {str(k): v for k, v in res.items()}
@@ -114,9 +125,9 @@ def tune(ctx: Context, dev: dict, prm, nres: float = 64.0, start: dict | None = 
 
 
 def save(precision: int, pairs_per_particle: float, cfg: dict, timings: dict, workload: str,
-         path: str = TABLE) -> None:
+         path: str = TABLE, kind: str = "") -> None:
     tab = json.load(open(path)) if os.path.exists(path) else {}
-    tab[key_for(precision, pairs_per_particle)] = {"config": cfg, "timings_ms": timings,
-                                                   "workload": workload}
+    tab[key_for(precision, pairs_per_particle, kind)] = {"config": cfg, "timings_ms": timings,
+                                                         "workload": workload}
     with open(path, "w") as f:
         json.dump(tab, f, indent=1, sort_keys=True)

@@ -242,11 +242,25 @@ __global__ __launch_bounds__(kBlock) void k_walk_scratch(const double4 *__restri
     axis_range(pi.z, pi.w, g, lz, mz);
     const int64_t base = box_base(v, i) + v.off[k];
     const int32_t *cb = cbeg + base, *ce_ = cend + base;
+    // cells wholly outside the support are skipped (conservatively: the
+    // bound is widened by twice the axis margin, far above any rounding);
+    // only when the walked range stays within half a period of i
+    const double cs = v.L / (double)nck;
+    const double Hc = pi.w + 2.0 * v.margin;
+    const bool cull = 2.0 * (Hc + cs) < v.L;
+    const double Hc2 = cull ? Hc * Hc : INFINITY;
     for (int a = 0; a < mz; a++) {
         uint32_t mzb = spread3(wrapc(lz + a, nck)) << 2;
+        const double gz = cull ? cell_gap(pi.z, lz + a, cs) : 0.0;
+        const double gz2 = gz * gz;
         for (int b = 0; b < my; b++) {
             uint32_t myb = mzb | (spread3(wrapc(ly + b, nck)) << 1);
+            const double gy = cull ? cell_gap(pi.y, ly + b, cs) : 0.0;
+            const double gzy = gz2 + gy * gy;
+            if (gzy > Hc2) continue;
             for (int e = 0; e < mx; e++) {
+                const double gx = cull ? cell_gap(pi.x, lx + e, cs) : 0.0;
+                if (gzy + gx * gx > Hc2) continue;
                 uint32_t id = myb | spread3(wrapc(lx + e, nck));
                 int jb = cb[id], je = ce_[id];
                 for (int j0 = jb; j0 < je; j0 += G) {

@@ -185,6 +185,15 @@ __device__ __forceinline__ void axis_range(double x, double R, const Grid &g, in
     lo = a;
 }
 
+// Distance along one axis from p to the unwrapped cell k of side cs (0 when
+// p is inside). Used to skip cells that lie wholly outside a support sphere;
+// a walk only does so while its whole range stays within half a period of p
+// (then the unwrapped cell is the nearest image of every particle in it).
+__device__ __forceinline__ double cell_gap(double p, int k, double cs) {
+    double lo = (double)k * cs, hi = lo + cs;
+    return fmax(0.0, fmax(lo - p, p - hi));
+}
+
 __device__ __forceinline__ int wrapc(int a, int nc) {
     a %= nc;
     return a < 0 ? a + nc : a;
