@@ -203,6 +203,92 @@ __global__ __launch_bounds__(kBlock) void k_tables(const uint32_t *skey, int64_t
     }
 }
 
+// The cells of one particle's walk. CULL: the walked range lies within half
+// a period of i, so every particle of an (unwrapped) cell has its nearest
+// image in that cell's image: the separation is (x_i - x_j) + c with c in
+// {-L, 0, L} fixed per cell, the same two roundings the minimum-image rule
+// makes, and cells wholly outside the (slightly widened) support are
+// skipped. Otherwise each separation takes the minimum-image rule.
+template <int G, bool DIRECT, bool CULL>
+__device__ __forceinline__ void walk_row(const double4 *__restrict__ posH, int64_t i, const double4 &pi,
+                                         int l, int gshift, uint32_t below, const Levels &v,
+                                         const int32_t *__restrict__ cb, const int32_t *__restrict__ ce_,
+                                         int nck, int lx, int ly, int lz, int mx, int my, int mz,
+                                         double cs, double Hc2, int cap, uint32_t *row,
+                                         const int64_t *__restrict__ goff, int32_t *gidx,
+                                         const int64_t *__restrict__ esoff, uint32_t *ekey,
+                                         int32_t *eval, int32_t &cg, int32_t &ce) {
+    const double H2 = pi.w * pi.w;
+    const double L = v.L;
+    for (int a = 0; a < mz; a++) {
+        const int kz = lz + a;
+        uint32_t mzb = spread3(wrapc(kz, nck)) << 2;
+        const double cz = kz < 0 ? L : (kz >= nck ? -L : 0.0);
+        const double gz = CULL ? cell_gap(pi.z, kz, cs) : 0.0;
+        const double gz2 = gz * gz;
+        for (int b = 0; b < my; b++) {
+            const int ky = ly + b;
+            uint32_t myb = mzb | (spread3(wrapc(ky, nck)) << 1);
+            const double cy = ky < 0 ? L : (ky >= nck ? -L : 0.0);
+            const double gy = CULL ? cell_gap(pi.y, ky, cs) : 0.0;
+            const double gzy = gz2 + gy * gy;
+            if (CULL && gzy > Hc2) continue;
+            for (int e = 0; e < mx; e++) {
+                const int kx = lx + e;
+                const double gx = CULL ? cell_gap(pi.x, kx, cs) : 0.0;
+                if (CULL && gzy + gx * gx > Hc2) continue;
+                const double cx = kx < 0 ? L : (kx >= nck ? -L : 0.0);
+                uint32_t id = myb | spread3(wrapc(kx, nck));
+                int jb = cb[id], je = ce_[id];
+                for (int j0 = jb; j0 < je; j0 += G) {
+                    int j = j0 + l;
+                    bool hit = false, extra = false;
+                    if (j < je) {
+                        double4 pj = posH[j];
+                        double dx, dy, dz;
+                        if (CULL) {
+                            dx = (pi.x - pj.x) + cx;
+                            dy = (pi.y - pj.y) + cy;
+                            dz = (pi.z - pj.z) + cz;
+                        } else {
+                            dx = min_image(pi.x - pj.x, v.L, v.hL);
+                            dy = min_image(pi.y - pj.y, v.L, v.hL);
+                            dz = min_image(pi.z - pj.z, v.L, v.hL);
+                        }
+                        double r2 = r2_exact(dx, dy, dz);
+                        hit = r2 < H2 && (int64_t)j != i;
+                        extra = hit && !(r2 < pj.w * pj.w);
+                    }
+                    uint32_t hm, em;
+                    if (G == 1) {
+                        hm = hit;
+                        em = extra;
+                    } else {
+                        uint64_t mh = __ballot(hit), mx_ = __ballot(extra);
+                        hm = (uint32_t)((mh >> gshift) & ((G == 64) ? ~0ull : (((uint64_t)1 << G) - 1)));
+                        em = (uint32_t)((mx_ >> gshift) & ((G == 64) ? ~0ull : (((uint64_t)1 << G) - 1)));
+                    }
+                    if (hit) {
+                        int pos = cg + (G == 1 ? 0 : __popc(hm & below));
+                        if (DIRECT) {
+                            gidx[goff[i] + pos] = j;
+                            if (extra) {
+                                int ep = ce + (G == 1 ? 0 : __popc(em & below));
+                                ekey[esoff[i] + ep] = (uint32_t)j;
+                                eval[esoff[i] + ep] = (int32_t)i;
+                            }
+                        } else if (pos < cap) {
+                            row[pos] = (uint32_t)j | (extra ? 0x80000000u : 0u);
+                        }
+                    }
+                    cg += __popc(hm);
+                    ce += __popc(em);
+                }
+            }
+        }
+    }
+}
+
 // Single-pass walk of particle i by a group of G lanes of one wavefront:
 // the group visits i's cells in order and takes each cell's particles G at a
 // time (consecutive, so the loads coalesce). A ballot over the group orders
@@ -227,10 +313,9 @@ __global__ __launch_bounds__(kBlock) void k_walk_scratch(const double4 *__restri
     if (i >= n) return;   // whole groups leave together (G divides the block)
     if (DIRECT && ng[i] <= cap) return;
     const double4 pi = posH[i];
-    const double H2 = pi.w * pi.w;
     const int lane = threadIdx.x & 63;
     const int gshift = lane - l;
-    const uint64_t below = (l == 0) ? 0ull : (((uint64_t)1 << l) - 1);
+    const uint32_t below = (l == 0) ? 0u : ((1u << l) - 1u);
     int32_t cg = 0, ce = 0;
     uint32_t *row = scratch + (size_t)i * cap;
     int k = level_for(pi.w, v);
@@ -242,67 +327,15 @@ __global__ __launch_bounds__(kBlock) void k_walk_scratch(const double4 *__restri
     axis_range(pi.z, pi.w, g, lz, mz);
     const int64_t base = box_base(v, i) + v.off[k];
     const int32_t *cb = cbeg + base, *ce_ = cend + base;
-    // cells wholly outside the support are skipped (conservatively: the
-    // bound is widened by twice the axis margin, far above any rounding);
-    // only when the walked range stays within half a period of i
+    // the support widened by twice the axis margin (far above any rounding)
     const double cs = v.L / (double)nck;
     const double Hc = pi.w + 2.0 * v.margin;
-    const bool cull = 2.0 * (Hc + cs) < v.L;
-    const double Hc2 = cull ? Hc * Hc : INFINITY;
-    for (int a = 0; a < mz; a++) {
-        uint32_t mzb = spread3(wrapc(lz + a, nck)) << 2;
-        const double gz = cull ? cell_gap(pi.z, lz + a, cs) : 0.0;
-        const double gz2 = gz * gz;
-        for (int b = 0; b < my; b++) {
-            uint32_t myb = mzb | (spread3(wrapc(ly + b, nck)) << 1);
-            const double gy = cull ? cell_gap(pi.y, ly + b, cs) : 0.0;
-            const double gzy = gz2 + gy * gy;
-            if (gzy > Hc2) continue;
-            for (int e = 0; e < mx; e++) {
-                const double gx = cull ? cell_gap(pi.x, lx + e, cs) : 0.0;
-                if (gzy + gx * gx > Hc2) continue;
-                uint32_t id = myb | spread3(wrapc(lx + e, nck));
-                int jb = cb[id], je = ce_[id];
-                for (int j0 = jb; j0 < je; j0 += G) {
-                    int j = j0 + l;
-                    bool hit = false, extra = false;
-                    if (j < je) {
-                        double4 pj = posH[j];
-                        double dx = min_image(pi.x - pj.x, v.L, v.hL);
-                        double dy = min_image(pi.y - pj.y, v.L, v.hL);
-                        double dz = min_image(pi.z - pj.z, v.L, v.hL);
-                        double r2 = r2_exact(dx, dy, dz);
-                        hit = r2 < H2 && (int64_t)j != i;
-                        extra = hit && !(r2 < pj.w * pj.w);
-                    }
-                    uint32_t hm, em;
-                    if (G == 1) {
-                        hm = hit;
-                        em = extra;
-                    } else {
-                        uint64_t mh = __ballot(hit), mx_ = __ballot(extra);
-                        hm = (uint32_t)((mh >> gshift) & ((G == 64) ? ~0ull : (((uint64_t)1 << G) - 1)));
-                        em = (uint32_t)((mx_ >> gshift) & ((G == 64) ? ~0ull : (((uint64_t)1 << G) - 1)));
-                    }
-                    if (hit) {
-                        int pos = cg + (G == 1 ? 0 : __popc(hm & (uint32_t)below));
-                        if (DIRECT) {
-                            gidx[goff[i] + pos] = j;
-                            if (extra) {
-                                int ep = ce + (G == 1 ? 0 : __popc(em & (uint32_t)below));
-                                ekey[esoff[i] + ep] = (uint32_t)j;
-                                eval[esoff[i] + ep] = (int32_t)i;
-                            }
-                        } else if (pos < cap) {
-                            row[pos] = (uint32_t)j | (extra ? 0x80000000u : 0u);
-                        }
-                    }
-                    cg += __popc(hm);
-                    ce += __popc(em);
-                }
-            }
-        }
-    }
+    if (2.0 * (Hc + cs) < v.L)
+        walk_row<G, DIRECT, true>(posH, i, pi, l, gshift, below, v, cb, ce_, nck, lx, ly, lz, mx, my,
+                                  mz, cs, Hc * Hc, cap, row, goff, gidx, esoff, ekey, eval, cg, ce);
+    else
+        walk_row<G, DIRECT, false>(posH, i, pi, l, gshift, below, v, cb, ce_, nck, lx, ly, lz, mx, my,
+                                   mz, cs, INFINITY, cap, row, goff, gidx, esoff, ekey, eval, cg, ce);
     if (!DIRECT && l == 0) {
         ng[i] = cg;
         nes[i] = ce;

@@ -156,14 +156,15 @@ __device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nb) {
 
 // Minimum-image separation d = xi - xj in FP64 and r^2 = (dx dx + dy dy) + dz dz
 // without contraction, so that neighbour decisions are reproducible bit for bit.
+// (selects rather than branches: the wrapped value is d - L or d + L either way)
 __device__ __forceinline__ double min_image(double d, double L, double hL) {
-    if (d > hL) d -= L;
-    else if (d < -hL) d += L;
-    return d;
+    const double up = d - L, dn = d + L;
+    return d > hL ? up : (d < -hL ? dn : d);
 }
 
 __device__ __forceinline__ double r2_exact(double dx, double dy, double dz) {
-    return __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz));
+#pragma clang fp contract(off)
+    return (dx * dx + dy * dy) + dz * dz;
 }
 
 // Uniform periodic cell grid of side c = L / nc over the sorted particles.

@@ -127,8 +127,12 @@ __global__ __launch_bounds__(kBlock) void k_volume(const double4 *__restrict__ p
         if (l == 0) acc[0].add(cw);            // self pair: W(0, H_i)
         int64_t b = goff[i];
         int cnt = (int)(goff[i + 1] - b);
+        // the next neighbour index is fetched one step ahead
+        int32_t jn = l < cnt ? gidx[b + l] : 0;
         for (int k = l; k < cnt; k += G) {
-            double4 pj = posH[gidx[b + k]];
+            const int32_t j = jn;
+            if (k + G < cnt) jn = gidx[b + k + G];
+            double4 pj = posH[j];
             T dx, dy, dz;
             separation(pi, pj, box, dx, dy, dz);
             T q = Mth<T>::sqrt(dx * dx + dy * dy + dz * dz) * invH;
@@ -172,8 +176,10 @@ __global__ __launch_bounds__(kBlock) void k_moments(const double4 *__restrict__ 
         }
         int64_t b = goff[i];
         int cnt = (int)(goff[i + 1] - b);
+        int32_t jn = l < cnt ? gidx[b + l] : 0;
         for (int k = l; k < cnt; k += G) {
-            int32_t j = gidx[b + k];
+            const int32_t j = jn;
+            if (k + G < cnt) jn = gidx[b + k + G];
             double4 pj = posH[j];
             T Vj = recV[j];
             T d[3];
@@ -373,8 +379,10 @@ __global__ __launch_bounds__(kBlock) void k_gradv(const double4 *__restrict__ po
         T vi[3] = {ri.x, ri.y, ri.z};
         int64_t b = goff[i];
         int cnt = (int)(goff[i + 1] - b);
+        int32_t jn = l < cnt ? gidx[b + l] : 0;
         for (int kk = l; kk < cnt; kk += G) {
-            int32_t j = gidx[b + kk];
+            const int32_t j = jn;
+            if (kk + G < cnt) jn = gidx[b + kk + G];
             double4 pj = posH[j];
             auto rj = rec6[j];
             T d[3];
@@ -592,20 +600,27 @@ __global__ __launch_bounds__(kBlock) void k_deriv(const double4 *__restrict__ po
         int ngi = (int)(goff[i + 1] - gb);
         int ebi = eb[i];
         int tot = si.fl != (T)0 ? 0 : ngi + (ee[i] - ebi);
+        // the next partner index is fetched one step ahead; a partner's record
+        // is loaded before its FP64-row flag is looked at, so the loads of one
+        // step go out together
+        int32_t jn = l < tot ? (l < ngi ? gidx[gb + l] : eidx[ebi + (l - ngi)]) : 0;
         for (int kk = l; kk < tot; kk += G) {
-            int32_t j = kk < ngi ? gidx[gb + kk] : eidx[ebi + (kk - ngi)];
+            const int32_t j = jn;
+            const int kn = kk + G;
+            if (kn < tot) jn = kn < ngi ? gidx[gb + kn] : eidx[ebi + (kn - ngi)];
             double4 pj = posH[j];
             State<T> sj;
             load_state(rec, j, sj);
-            if (sj.fl != (T)0) continue;
             T d[3];
             separation(pi, pj, box, d[0], d[1], d[2]);
             T F[3], E;
             deriv_pair(si, sj, d, pc, cwi, cgi, F, E);
-            a[0].add(F[0]);
-            a[1].add(F[1]);
-            a[2].add(F[2]);
-            a[3].add(E);
+            if (sj.fl == (T)0) {
+                a[0].add(F[0]);
+                a[1].add(F[1]);
+                a[2].add(F[2]);
+                a[3].add(E);
+            }
         }
     }
     group_reduce<T, G, 4>(a);
