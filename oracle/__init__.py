@@ -74,6 +74,10 @@ def lib():
         L.orc_hnet_features.argtypes = [_i64, _p, _p, _p, _p, _d, _d, _p]
         L.orc_hsolve.restype = _i64
         L.orc_hsolve.argtypes = [_i64, _p, _p, _p, _d, _int, _d, _d, _int, _p, _p]
+        L.orc_rows_for.restype = _i64
+        L.orc_rows_for.argtypes = [_i64, _p, _p, _p, _p, _d, _int, _i64, _p, _p, _p, _i64]
+        L.orc_hsolve_for.restype = _i64
+        L.orc_hsolve_for.argtypes = [_i64, _p, _p, _p, _d, _p, _d, _d, _int, _i64, _p, _p, _p, _p]
         _lib = L
     return _lib
 
@@ -275,4 +279,94 @@ def pipeline(ps, prm, periodic=True, method="auto"):
                dvdt=dv, dudt=du, SF=SF, SE=SE, n_pairs=int(soff[-1]))
     out.update(mom)
     out.update(corr)
+    return out
+
+
+# ------------------------------------------------------ sampled evaluation
+def rows_for(x, y, z, H, which, targets, L=1.0):
+    """CSR rows of N_g (which 0, self included) or N_s (which 1) for the
+    listed particles only, over the whole periodic set; rows ascending."""
+    x, y, z, H = map(_f64, (x, y, z, H))
+    t = np.ascontiguousarray(targets, dtype=np.int64)
+    off = np.zeros(t.shape[0] + 1, dtype=np.int64)
+    args = (x.shape[0], _ptr(x), _ptr(y), _ptr(z), _ptr(H), float(L), int(which), t.shape[0], _ptr(t),
+            _ptr(off))
+    tot = lib().orc_rows_for(*args, None, 0)
+    idx = np.empty(max(tot, 1), dtype=np.int32)
+    lib().orc_rows_for(*args, _ptr(idx), tot)
+    return off, idx[:tot]
+
+
+def hsolve_for(x, y, z, targets, H0, Nres, tol=1e-7, max_iter=100, L=1.0, H_grid=None):
+    """The iteration of ``hsolve`` for the listed particles only, over every
+    position. H0: starting radii of the targets. H_grid (all particles) only
+    sizes the search grid. Returns (H, iterations, n_not_converged)."""
+    x, y, z = map(_f64, (x, y, z))
+    t = np.ascontiguousarray(targets, dtype=np.int64)
+    H0 = _f64(H0)
+    Hg = _f64(H_grid) if H_grid is not None else np.full(x.shape[0], float(np.mean(H0)))
+    H = np.empty(t.shape[0])
+    it = np.empty(t.shape[0], dtype=np.int32)
+    nf = lib().orc_hsolve_for(x.shape[0], _ptr(x), _ptr(y), _ptr(z), float(L), _ptr(Hg), float(Nres),
+                              float(tol), int(max_iter), t.shape[0], _ptr(t), _ptr(H0), _ptr(H),
+                              _ptr(it))
+    return H, it, int(nf)
+
+
+def _sub_rows(S, owners, off, idx):
+    """CSR over the sorted index set S: the rows of `owners` (sorted, a subset
+    of S, row data off/idx in original indices) remapped into S, empty rows
+    for the rest of S."""
+    lens = np.zeros(S.shape[0], dtype=np.int64)
+    lens[np.searchsorted(S, owners)] = np.diff(off)
+    o = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    return o, np.searchsorted(S, idx).astype(np.int32)
+
+
+def spot_check(ps, targets, prm, H=None):
+    """Every pass for the listed particles only, exactly as ``pipeline``
+    computes it on the whole set: the targets' pair sets (1-hop ring R1),
+    the gather sets of R1 (2-hop ring R2) and those of R2 (R3) are found over
+    all particles; volumes are evaluated on R2, moments, corrections and
+    grad v on R1, and the derivatives on the targets, each with the same
+    rows (ascending) as the whole-set oracle. Returns a dict of the outputs
+    of ``pipeline`` at the sorted unique targets (key "targets")."""
+    x, y, z = map(_f64, (ps.x, ps.y, ps.z))
+    H = _f64(ps.H if H is None else H)
+    L = ps.L
+    T = np.unique(np.asarray(targets, dtype=np.int64))
+    soff, sidx = rows_for(x, y, z, H, 1, T, L)
+    R1 = np.union1d(T, sidx)
+    g1off, g1idx = rows_for(x, y, z, H, 0, R1, L)
+    R2 = np.union1d(R1, g1idx)
+    g2off, g2idx = rows_for(x, y, z, H, 0, R2, L)
+    R3 = np.union1d(R2, g2idx)
+    # volumes on R2, over the positions of R3
+    oA, iA = _sub_rows(R3, R2, g2off, g2idx)
+    _, VA, NA = volume(x[R3], y[R3], z[R3], H[R3], oA, iA, L)
+    pB = np.searchsorted(R3, R2)
+    V2 = VA[pB]
+    # moments, corrections and grad v on R1, over R2
+    oB, iB = _sub_rows(R2, R1, g1off, g1idx)
+    xb, yb, zb, hb = x[R2], y[R2], z[R2], H[R2]
+    with np.errstate(all="ignore"):
+        mom = moments(xb, yb, zb, hb, V2, oB, iB, L)
+        corr = corrections(mom)
+        gv = gradv(xb, yb, zb, hb, ps.v[:, R2], V2, corr, oB, iB, L)
+    # derivatives on the targets, over R1
+    pC = np.searchsorted(R2, R1)
+    oC, iC = _sub_rows(R1, T, soff, sidx)
+    cC = {k: corr[k][..., pC] for k in ("A", "B", "gA", "gB")}
+    rho = None if ps.rho is None else _f64(ps.rho)[R1]
+    dv, du, SF, SE = derivatives(x[R1], y[R1], z[R1], H[R1], ps.v[:, R1], _f64(ps.m)[R1],
+                                 _f64(ps.u)[R1], rho, V2[pC], cC, gv[:, pC], oC, iC, prm, L)
+    pT1 = np.searchsorted(R1, T)          # targets within R1
+    pT2 = pC[pT1]                          # targets within R2
+    out = dict(targets=T, V=V2[pT2], N=NA[np.searchsorted(R3, T)], gradv=gv[:, pT2],
+               dvdt=dv[:, pT1], dudt=du[pT1], SF=SF[pT1], SE=SE[pT1],
+               n_pairs=int(soff[-1]), rings=(T.shape[0], R1.shape[0], R2.shape[0], R3.shape[0]))
+    for k, a in mom.items():
+        out[k] = a[..., pT2]
+    for k in ("A", "B", "gA", "gB", "singular"):
+        out[k] = corr[k][..., pT2]
     return out

@@ -856,3 +856,208 @@ void orc_hnet_features(int64_t n, const double *x, const double *y, const double
     }
     if (use_grid) orc_grid_free(&g);
 }
+
+/* ------------------------------------------------------------------ */
+/* Evaluation for listed particles only (sampled checks on large sets). */
+/* A fine periodic grid over all n particles (up to 256 cells a side)  */
+/* restricts the candidates; every decision is the same r^2 test as     */
+/* the brute-force path, so the rows are the same sets.                 */
+/* ------------------------------------------------------------------ */
+typedef struct {
+    int nc;
+    double c;
+    int64_t *start;   /* [nc^3 + 1] */
+    int32_t *list;    /* particles cell by cell */
+    double *hmax;     /* [nc^3] largest H of each cell */
+} orc_fgrid;
+
+static void orc_fgrid_build(orc_fgrid *g, int64_t n, const double *x, const double *y,
+                            const double *z, const double *H, double L)
+{
+    double mean = 0.0;
+    for (int64_t i = 0; i < n; i++) mean += H[i];
+    mean /= (double)(n > 0 ? n : 1);
+    int nc = (int)floor(2.0 * L / mean);
+    if (nc < 1) nc = 1;
+    if (nc > 256) nc = 256;
+    g->nc = nc;
+    g->c = L / nc;
+    int64_t ncell = (int64_t)nc * nc * nc;
+    g->start = (int64_t *)calloc((size_t)ncell + 1, sizeof(int64_t));
+    g->hmax = (double *)calloc((size_t)ncell, sizeof(double));
+    g->list = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    int64_t *cellof = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    for (int64_t i = 0; i < n; i++) {
+        int cx = orc_cell_of(x[i], g->c, nc), cy = orc_cell_of(y[i], g->c, nc),
+            cz = orc_cell_of(z[i], g->c, nc);
+        cellof[i] = ((int64_t)cz * nc + cy) * nc + cx;
+        g->start[cellof[i] + 1]++;
+        if (H[i] > g->hmax[cellof[i]]) g->hmax[cellof[i]] = H[i];
+    }
+    for (int64_t k = 0; k < ncell; k++) g->start[k + 1] += g->start[k];
+    int64_t *fill = (int64_t *)malloc(sizeof(int64_t) * (size_t)ncell);
+    memcpy(fill, g->start, sizeof(int64_t) * (size_t)ncell);
+    for (int64_t i = 0; i < n; i++) g->list[fill[cellof[i]]++] = (int32_t)i;
+    free(fill);
+    free(cellof);
+}
+
+static void orc_fgrid_free(orc_fgrid *g)
+{
+    free(g->start);
+    free(g->list);
+    free(g->hmax);
+}
+
+static void orc_faxis(double xi, double R, const orc_fgrid *g, int *lo, int *cnt)
+{
+    int a = (int)floor((xi - R) / g->c) - 1;
+    int b = (int)floor((xi + R) / g->c) + 1;
+    int m = b - a + 1;
+    if (m >= g->nc) { a = 0; m = g->nc; }
+    *lo = a;
+    *cnt = m;
+}
+
+/* shortest periodic distance along one axis from xi to the cell of     */
+/* (unwrapped) index k, 0 inside; used only to skip cells, with a whole */
+/* extra cell of slack around the support                              */
+static double orc_cell_gap(double xi, int k, const orc_fgrid *g, double L)
+{
+    double lo = k * g->c, hi = lo + g->c, best = INFINITY;
+    for (int s = -1; s <= 1; s++) {
+        double a = lo + s * L, b = hi + s * L;
+        double d = xi < a ? a - xi : (xi > b ? xi - b : 0.0);
+        if (d < best) best = d;
+    }
+    return best;
+}
+
+static int orc_cmp_i32(const void *a, const void *b)
+{
+    int32_t u = *(const int32_t *)a, v = *(const int32_t *)b;
+    return (u > v) - (u < v);
+}
+
+/* One row for particle i: which 0 -> N_g(i) (i included), which 1 ->   */
+/* N_s(i). Writes at most cap entries to row (if row != NULL) and       */
+/* returns the row length; the row is ascending.                        */
+static int64_t orc_row_one(int64_t i, const double *x, const double *y, const double *z,
+                           const double *H, double L, int which, double Hall, const orc_fgrid *g,
+                           int32_t *row, int64_t cap)
+{
+    double R = which == 0 ? H[i] : (H[i] > Hall ? H[i] : Hall);
+    int lx, ly, lz, mx, my, mz;
+    orc_faxis(x[i], R, g, &lx, &mx);
+    orc_faxis(y[i], R, g, &ly, &my);
+    orc_faxis(z[i], R, g, &lz, &mz);
+    int64_t c = 0;
+    for (int a = 0; a < mz; a++) {
+        int kz = orc_mod(lz + a, g->nc);
+        double gz = orc_cell_gap(z[i], kz, g, L);
+        for (int b = 0; b < my; b++) {
+            int ky = orc_mod(ly + b, g->nc);
+            double gy = orc_cell_gap(y[i], ky, g, L);
+            for (int e = 0; e < mx; e++) {
+                int kx = orc_mod(lx + e, g->nc);
+                int64_t cell = ((int64_t)kz * g->nc + ky) * g->nc + kx;
+                if (which == 1) {
+                    /* no j of this cell can reach i, nor i reach it */
+                    double gx = orc_cell_gap(x[i], kx, g, L);
+                    double reach = H[i] > g->hmax[cell] ? H[i] : g->hmax[cell];
+                    reach += g->c;
+                    if (gx * gx + gy * gy + gz * gz > reach * reach) continue;
+                }
+                for (int64_t k = g->start[cell]; k < g->start[cell + 1]; k++) {
+                    int64_t j = g->list[k];
+                    double d[3];
+                    double r2 = orc_sep(x, y, z, i, j, L, 1, d);
+                    int in = which == 0 ? r2 < H[i] * H[i]
+                                        : (j != i && (r2 < H[i] * H[i] || r2 < H[j] * H[j]));
+                    if (in) {
+                        if (row && c < cap) row[c] = (int32_t)j;
+                        c++;
+                    }
+                }
+            }
+        }
+    }
+    if (row && c <= cap) qsort(row, (size_t)c, sizeof(int32_t), orc_cmp_i32);
+    return c;
+}
+
+/* Rows of N_g (which 0) or N_s (which 1) for the m particles in list,  */
+/* over all n particles of a periodic box, ascending. off[m+1] always;  */
+/* idx (cap entries) is filled when it holds the total. Returns the     */
+/* total.                                                               */
+int64_t orc_rows_for(int64_t n, const double *x, const double *y, const double *z,
+                     const double *H, double L, int which, int64_t m, const int64_t *list,
+                     int64_t *off, int32_t *idx, int64_t cap)
+{
+    orc_fgrid g;
+    orc_fgrid_build(&g, n, x, y, z, H, L);
+    double Hall = 0.0;
+    for (int64_t i = 0; i < n; i++)
+        if (H[i] > Hall) Hall = H[i];
+    int64_t *cnt = (int64_t *)malloc(sizeof(int64_t) * (size_t)(m > 0 ? m : 1));
+    #pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t t = 0; t < m; t++)
+        cnt[t] = orc_row_one(list[t], x, y, z, H, L, which, Hall, &g, NULL, 0);
+    off[0] = 0;
+    for (int64_t t = 0; t < m; t++) off[t + 1] = off[t] + cnt[t];
+    if (idx && cap >= off[m]) {
+        #pragma omp parallel for schedule(dynamic, 16)
+        for (int64_t t = 0; t < m; t++)
+            orc_row_one(list[t], x, y, z, H, L, which, Hall, &g, idx + off[t], cnt[t]);
+    }
+    free(cnt);
+    orc_fgrid_free(&g);
+    return off[m];
+}
+
+/* The iteration of orc_hsolve for the m listed particles only, over all */
+/* n positions; H0 and H are [m] (start and result), iters [m].         */
+int64_t orc_hsolve_for(int64_t n, const double *x, const double *y, const double *z, double L,
+                       const double *Hgrid, double Nres, double tol, int max_iter, int64_t m,
+                       const int64_t *list, const double *H0, double *H, int32_t *iters)
+{
+    orc_fgrid g;
+    orc_fgrid_build(&g, n, x, y, z, Hgrid, L);
+    int64_t nfail = 0;
+    #pragma omp parallel for schedule(dynamic, 4) reduction(+ : nfail)
+    for (int64_t t = 0; t < m; t++) {
+        int64_t i = list[t];
+        double h = H0[t];
+        int it = 0, conv = 0;
+        while (it < max_iter) {
+            double s = 0.0;
+            int lx, ly, lz, mx, my, mz;
+            orc_faxis(x[i], h, &g, &lx, &mx);
+            orc_faxis(y[i], h, &g, &ly, &my);
+            orc_faxis(z[i], h, &g, &lz, &mz);
+            for (int a = 0; a < mz; a++)
+                for (int b = 0; b < my; b++)
+                    for (int e = 0; e < mx; e++) {
+                        int64_t cell = ((int64_t)orc_mod(lz + a, g.nc) * g.nc + orc_mod(ly + b, g.nc)) * g.nc
+                                       + orc_mod(lx + e, g.nc);
+                        for (int64_t k = g.start[cell]; k < g.start[cell + 1]; k++) {
+                            double d[3];
+                            double r2 = orc_sep(x, y, z, i, g.list[k], L, 1, d);
+                            if (r2 < h * h) s += orc_W(sqrt(r2), h);
+                        }
+                    }
+            double N = 4.0 / 3.0 * ORC_PI * h * h * h * s;
+            double hn = orc_thacker_step(h, N, Nres);
+            it++;
+            double dh = fabs(hn - h);
+            double hold = h;
+            h = hn;
+            if (dh <= tol * hold) { conv = 1; break; }
+        }
+        H[t] = h;
+        if (iters) iters[t] = it;
+        if (!conv) nfail++;
+    }
+    orc_fgrid_free(&g);
+    return nfail;
+}

@@ -4,15 +4,17 @@
 // 1. validate + reduce H (deterministic two-level reduction)
 // 2. key = Morton code of the particle's cell; stable radix sort -> perm
 // 3. gather sorted x, y, z, H into one double4 per particle; cell ranges
-// 4. count: one thread per particle walks the cells of the hierarchy level
-//    matched to its support and counts j with r^2 < H_i^2 (the gather set,
-//    self excluded), and among them the j with r^2 >= H_j^2: j reaches i
-//    only through i's larger support, so the pair is an "extra" of j.
-// 5. exclusive scans of both counts give every particle its output slots
-// 6. fill with the same walk: gather rows in walk order, extras as (j, i)
-//    pairs grouped by i; a stable radix sort on j then makes each extras row
-//    ascending in i. No atomics decide an order, so the lists (and every
-//    sum over them) are the same bit for bit from run to run.
+// 4. walk: a group of lanes per particle visits the cells of the hierarchy
+//    level matched to its support and finds the j with r^2 < H_i^2 (the
+//    gather set, self excluded), and among them the j with r^2 >= H_j^2: j
+//    reaches i only through i's larger support, so the pair is an "extra"
+//    of j. Hits go to a capped scratch row, with exact counts.
+// 5. exclusive scans of both counts give every particle its output slots;
+//    the scratch rows are compacted, and rows past the cap walked again
+// 6. the extras, grouped by i, are transposed into rows per j, each row
+//    ascending in i (placed by rank, so the atomic slot counters of the
+//    scatter decide nothing). The lists, and every sum over them, are the
+//    same bit for bit from run to run.
 #include <math.h>
 
 #include <algorithm>
@@ -167,16 +169,6 @@ __global__ __launch_bounds__(kBlock) void k_graph_clear(const GraphStat *st, int
         ng[i] = 0;
         nes[i] = 0;
     }
-}
-
-// graph mode: the extras are sorted over the whole capacity; slots past the
-// device count get a key above every particle index, so they sort last
-__global__ __launch_bounds__(kBlock) void k_pad_extras(const int64_t *esoff, int64_t n, int64_t cap,
-                                                       uint32_t pad, uint32_t *ekey, int32_t *eval) {
-    int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (k >= cap || k < esoff[n]) return;
-    ekey[k] = pad;
-    eval[k] = 0;
 }
 
 __global__ __launch_bounds__(kBlock) void k_fill_i32(int32_t *a, int64_t n, int32_t v) {
@@ -385,15 +377,52 @@ __global__ __launch_bounds__(kBlock) void k_to_i64(const int32_t *a, int64_t n, 
     if (i == n) o[n] = 0;
 }
 
-// extras rows: the sorted keys are the receiving particles j
-__global__ __launch_bounds__(kBlock) void k_extra_ranges(const uint32_t *ekey, int64_t E, int64_t n,
-                                                         int32_t *eb, int32_t *ee) {
+// Transpose of the extras, which arrive grouped by the emitting particle i:
+// rows per receiving particle j, each ascending in i. Counts per j, a scan
+// for the row offsets, a scatter into arbitrary slots of the row (atomic
+// slot counters), then every entry moves to the place given by its rank in
+// its row, which fixes the order whatever the scatter did.
+__global__ __launch_bounds__(kBlock) void k_extra_count(const uint32_t *__restrict__ ekey, int64_t cap,
+                                                        const int64_t *__restrict__ E_dev, int32_t *cnt) {
     int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (k >= E) return;
+    if (k >= cap || k >= *E_dev) return;
+    atomicAdd(&cnt[ekey[k]], 1);
+}
+
+__global__ __launch_bounds__(kBlock) void k_extra_scatter(const uint32_t *__restrict__ ekey,
+                                                          const int32_t *__restrict__ eval, int64_t cap,
+                                                          const int64_t *__restrict__ E_dev,
+                                                          const int64_t *__restrict__ eoff, int32_t *fill,
+                                                          int32_t *tmp) {
+    int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (k >= cap || k >= *E_dev) return;
     uint32_t j = ekey[k];
-    if ((int64_t)j >= n) return;   // graph-mode padding
-    if (k == 0 || ekey[k - 1] != j) eb[j] = (int32_t)k;
-    if (k == E - 1 || ekey[k + 1] != j) ee[j] = (int32_t)(k + 1);
+    int slot = atomicAdd(&fill[j], 1);
+    tmp[eoff[j] + slot] = eval[k];
+}
+
+// G lanes per row; entries of a row are distinct emitters, so the ranks are
+// a permutation of the row's slots
+template <int G>
+__global__ __launch_bounds__(kBlock) void k_extra_rank(const int64_t *__restrict__ eoff,
+                                                       const int32_t *__restrict__ tmp, int64_t n,
+                                                       int32_t *out, int32_t *eb, int32_t *ee) {
+    int64_t gid = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    const int l = (int)(gid % G);
+    const int64_t j = gid / G;
+    if (j >= n) return;
+    const int64_t b = eoff[j];
+    const int c = (int)(eoff[j + 1] - b);
+    if (l == 0) {
+        eb[j] = (int32_t)b;
+        ee[j] = (int32_t)(b + c);
+    }
+    for (int t = l; t < c; t += G) {
+        const int32_t v = tmp[b + t];
+        int r = 0;
+        for (int u = 0; u < c; u++) r += tmp[b + u] < v ? 1 : 0;
+        out[b + r] = v;
+    }
 }
 
 __global__ __launch_bounds__(kBlock) void k_sum_i32(const int32_t *a, int64_t n, int64_t *out) {
@@ -559,24 +588,35 @@ static crk_status build_lists(crk_ctx *c) {
     CRK_HIP(c, hipGetLastError());
     // extras arrive grouped by the emitting particle i (ascending); a stable
     // sort on the receiving particle j keeps them ascending in i per row
-    int ebits = 0;
-    if (c->graph_mode) {
-        // padding key n must sort after every particle index
-        while (((int64_t)1 << ebits) <= n) ebits++;
-        if (E > 0)
-            k_pad_extras<<<nblocks(E), kBlock, 0, c->stream>>>(esoff, n, E, (uint32_t)n, ekey, eidx);
-    } else {
-        while (((int64_t)1 << ebits) < n) ebits++;
-    }
+    // transpose to rows per receiving particle j, ascending in i (the
+    // extras count is read on the device: in graph mode E is the capacity)
     {
         KTimer kt_(c, "k_sort_extras");
-        CRK_TRY(radix_sort_pairs(c, ekey, eidx, E, ebits));
+        CRK_TRY(ensure(c, c->ecnt, (size_t)n * sizeof(int32_t)));
+        CRK_TRY(ensure(c, c->efill, (size_t)n * sizeof(int32_t)));
+        CRK_TRY(ensure(c, c->eoff, (size_t)(n + 1) * sizeof(int64_t)));
+        CRK_TRY(ensure(c, c->etmp, (size_t)(E > 0 ? E : 1) * sizeof(int32_t)));
+        int32_t *ecnt = (int32_t *)c->ecnt.p, *efill = (int32_t *)c->efill.p;
+        int32_t *etmp = (int32_t *)c->etmp.p;
+        int64_t *eoff = (int64_t *)c->eoff.p;
+        k_fill_i32<<<nblocks(n), kBlock, 0, c->stream>>>(ecnt, n, 0);
+        k_fill_i32<<<nblocks(n), kBlock, 0, c->stream>>>(efill, n, 0);
+        if (E > 0) {
+            KTimer kt2_(c, "k_extra_count");
+            k_extra_count<<<nblocks(E), kBlock, 0, c->stream>>>(ekey, E, esoff + n, ecnt);
+        }
+        k_to_i64<<<nblocks(n + 1), kBlock, 0, c->stream>>>(ecnt, n, eoff);
+        CRK_TRY(scan_exclusive_i64(c, eoff, eoff, n + 1));
+        if (E > 0) {
+            KTimer kt2_(c, "k_extra_scatter");
+            k_extra_scatter<<<nblocks(E), kBlock, 0, c->stream>>>(ekey, eidx, E, esoff + n, eoff, efill,
+                                                                   etmp);
+        }
+        constexpr int GR = 8;
+        KTimer kt3_(c, "k_extra_rank");
+        k_extra_rank<GR><<<(unsigned)((n * GR + kBlock - 1) / kBlock), kBlock, 0, c->stream>>>(
+            eoff, etmp, n, eidx, (int32_t *)c->eb.p, (int32_t *)c->ee.p);
     }
-    k_fill_i32<<<nblocks(n), kBlock, 0, c->stream>>>((int32_t *)c->eb.p, n, 0);
-    k_fill_i32<<<nblocks(n), kBlock, 0, c->stream>>>((int32_t *)c->ee.p, n, 0);
-    if (E > 0)
-        k_extra_ranges<<<nblocks(E), kBlock, 0, c->stream>>>(ekey, E, n, (int32_t *)c->eb.p,
-                                                              (int32_t *)c->ee.p);
     CRK_HIP(c, hipGetLastError());
     if (c->graph_mode) {
         // counts are on the device (crk_graph_replay reads them)

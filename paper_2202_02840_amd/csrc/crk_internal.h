@@ -79,6 +79,7 @@ struct crk_ctx {
     crk::Buf sv, sm, su, srho;                            // sorted gas state (crk_step)
     crk::Buf gstat;                                       // device status of a graph step
     crk::Buf gboff;                                       // box offsets the graph was recorded with
+    crk::Buf ecnt, efill, eoff, etmp;                     // transpose of the extras
 
     // graph mode (crk_graph_capture): the build keeps the geometry of the
     // last eager build, lists are bounded by fixed capacities, and no call
