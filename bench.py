@@ -15,8 +15,9 @@ derivative pass, the max normwise error of every output against the FP64
 GPU path, and the FP64 CPU oracle timed on a smaller box of the same recipe.
 Further legs: the same step recorded once as a HIP graph and replayed
 (graph_replay), the smoothing-length network against the plain iteration
-(h_surrogate), and 512 independent boxes of 8^3..48^3 particles in one
-batched, graph-recorded step (batch).
+(h_surrogate), 512 independent boxes of 8^3..48^3 particles in one
+batched, graph-recorded step (batch), and one complete step of the
+256^3 clumped set with its smoothing-length iteration (full_size).
 """
 from __future__ import annotations
 
@@ -112,7 +113,84 @@ def hsurrogate_leg(ctx, args) -> dict:
     r.update(train_samples=nsamp, train_steps=args.hs_steps, label_seconds=t1 - t0,
              train_seconds=t2 - t1, loss_history=hist,
              eval_box=f"lognormal {args.hs_eval_side}^3, sigma 2.0, seed 4")
-    return r
+    return r, theta
+
+
+def full_size_leg(args, prec, theta=None) -> dict:
+    """The largest single-GPU set: 256^3 particles, lognormal (sigma 2.0,
+    P(k) ~ k^-2.5) with 1% of them in 64 dense clumps (seed 5). One complete
+    step: the smoothing-length iteration from the generator's supports
+    (plain, and seeded by the trained network when one is given), then the
+    build and every pass at the converged supports; mixed against the FP64
+    GPU path."""
+    import crk_inputs as ci
+    import torch
+    from paper_2202_02840_amd import CRK_FP64, Context
+    from paper_2202_02840_amd import autotune as at
+    from paper_2202_02840_amd import pipeline as pl
+    t0 = time.perf_counter()
+    ps = ci.clustered_clump_box(args.full_side)
+    gen_s = time.perf_counter() - t0
+    ctx = Context(0)
+    dev = pl.upload(ps)
+    prm = pl.params_for(ps, 64.0, prec, kappa_max=args.kappa)
+    ctx.build_cells(dev["x"], dev["y"], dev["z"], dev["H"], prm)
+    Hs = ctx.permute(dev["H"], True)
+    hres = {}
+    for name in ("plain", "surrogate"):
+        if name == "surrogate" and theta is None:
+            continue
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        start = Hs if name == "plain" else ctx.hnet_seed(theta, 64.0, Hs)
+        Hc, it, nun = ctx.hsolve(64.0, start, 1e-8, 1000)
+        torch.cuda.synchronize()
+        hres[name] = dict(seconds=time.perf_counter() - t1, mean_iters=float(it.double().mean()),
+                          max_iters=int(it.max()), unconverged=int(nun), H=Hc)
+        ctx.update_support(Hs)
+    use = "surrogate" if "surrogate" in hres else "plain"
+    Hconv = hres[use]["H"]
+    if "surrogate" in hres:
+        hres["max_rel_dH"] = float((hres["surrogate"]["H"] / hres["plain"]["H"] - 1).abs().max())
+        hres["speedup"] = hres["plain"]["seconds"] / hres["surrogate"]["seconds"]
+    # the converged supports in the original order
+    dev["H"] = ctx.permute(Hconv, False)
+    for k in ("plain", "surrogate"):
+        if k in hres:
+            hres[k].pop("H")
+    out = pl.step(ctx, dev, prm, count_singular=False)
+    cfg = at.load(prec, out["n_pairs"] / ps.n)
+    if cfg:
+        at.apply(ctx, cfg)
+    for _ in range(args.warmup):
+        out = pl.step(ctx, dev, prm, count_singular=False)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    for _ in range(args.steps):
+        out = pl.step(ctx, dev, prm, count_singular=False)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t2) * 1e3 / max(args.steps, 1)
+    npairs = int(out["n_pairs"])
+    res = {"workload": f"lognormal {args.full_side}^3 sigma 2.0, P(k)~k^-2.5, 1% in 64 clumps at "
+                       f"100x mean density, seed 5; h iteration from the generator's H to 1e-8, "
+                       f"then the {args.precision} step at the converged H",
+           "particles": ps.n, "pairs_per_step": npairs, "step_ms": ms,
+           "step_pairs_per_s": npairs / (ms * 1e-3), "h_iteration": hres,
+           "h_iteration_used": use,
+           "full_step_ms": ms + hres[use]["seconds"] * 1e3, "lanes": cfg,
+           "generate_seconds": gen_s}
+    if not args.no_check:
+        ref = pl.step(ctx, dev, pl.params_for(ps, 64.0, CRK_FP64), count_singular=False)
+        cur = pl.step(ctx, dev, prm, count_singular=False)
+        torch.cuda.synchronize()
+        errs = {}
+        for k in OUT_KEYS:
+            a, b = cur[k], ref[k]
+            den = b.abs().max().item()
+            errs[k] = (a - b).abs().max().item() / den if den > 0 else (a - b).abs().max().item()
+        res["max_rel_err_vs_fp64"] = errs
+        res["err_target_met"] = bool(max(errs.values()) <= 1e-5)
+    return res
 
 
 def graph_replay_ms(ctx, io, prm, steps: int, warmup: int, box_offsets=None) -> tuple:
@@ -207,7 +285,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n-side", type=int, default=128)
     ap.add_argument("--precision", choices=("mixed", "adapt", "fp64"), default="adapt")
-    ap.add_argument("--cpu-n-side", type=int, default=64)
+    ap.add_argument("--cpu-n-side", type=int, default=128)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true")
     ap.add_argument("--no-hsurrogate", action="store_true",
@@ -226,6 +304,8 @@ def main():
     ap.add_argument("--no-graph", action="store_true",
                     help="skip the HIP-graph replay timing of the step")
     ap.add_argument("--no-batch", action="store_true", help="skip the many-box batch leg")
+    ap.add_argument("--no-full-size", action="store_true", help="skip the 256^3 full-step leg")
+    ap.add_argument("--full-side", type=int, default=256)
     ap.add_argument("--batch-boxes", type=int, default=512)
     ap.add_argument("--autotune-batch", action="store_true",
                     help="tune the lanes on the batch workload (stored with --tune-out)")
@@ -363,12 +443,23 @@ def main():
         "err_target_met": None if errs is None else bool(max(errs.values()) <= 1e-5),
         "graph_replay": graph,
     }
+    log = lambda m: print(f"[bench] {m}", file=sys.stderr, flush=True)
+    log(f"main step {ms_step:.3f} ms")
     if not args.no_batch:
         line["batch"] = batch_leg(args, prec, args.precision)
+        log(f"batch leg {line['batch']['graph_ms_per_step']:.3f} ms per replay")
+    theta = None
     if not args.no_hsurrogate:
-        line["h_surrogate"] = hsurrogate_leg(ctx, args)
+        line["h_surrogate"], theta = hsurrogate_leg(ctx, args)
+        log(f"h-surrogate leg speedup {line['h_surrogate']['speedup']:.3f}")
+    if not args.no_full_size:
+        del ctx, dev, out
+        torch.cuda.empty_cache()
+        line["full_size"] = full_size_leg(args, prec, theta)
+        log(f"full-size leg step {line['full_size']['step_ms']:.3f} ms")
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args.cpu_n_side)
+        log("cpu baseline done")
     print(json.dumps(line), flush=True)
 
 
