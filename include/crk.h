@@ -350,11 +350,14 @@ crk_status crk_set_hsolve(crk_ctx *ctx, int32_t lanes, int32_t round, int32_t ca
                           double factor);
 
 /* Neighbour walk of crk_build_cells / crk_update_support (tuning only: the
- * lists do not depend on it): lanes (1, 2, 4, 8 or 16) of a wavefront share
- * one particle's walk; each row is first written to a scratch row of cap
- * slots, and rows longer than cap are walked again into place. 0 keeps the
- * current value. */
-crk_status crk_set_walk(crk_ctx *ctx, int32_t lanes, int32_t cap);
+ * neighbour sets do not depend on it): lanes (1, 2, 4, 8 or 16) of a
+ * wavefront share one particle's walk; each row is first written to a
+ * scratch row of cap slots, and rows longer than cap are walked again into
+ * place (0 keeps either value). level_shift s (0..3; -1 keeps) walks the
+ * first hierarchy level whose cell side is at least 2^(s-1) H: larger cells
+ * mean fewer cells and more candidates per particle. The order of a gather
+ * row is the walk order, so it follows the walked level. */
+crk_status crk_set_walk(crk_ctx *ctx, int32_t lanes, int32_t cap, int32_t level_shift);
 
 /* Per-kernel timing (off by default). While enabled, every kernel launch of
  * the library is bracketed by a pair of HIP events recorded on the context's

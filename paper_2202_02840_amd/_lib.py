@@ -100,7 +100,7 @@ def lib():
             "crk_hsolve": ([p, d, d, i32, p, p, p], i32),
             "crk_export_neighbors": ([p, i32, p, p, i64, p], i32),
             "crk_set_lanes": ([p, i32, i32, i32, i32], i32),
-            "crk_set_walk": ([p, i32, i32], i32),
+            "crk_set_walk": ([p, i32, i32, i32], i32),
             "crk_set_hsolve": ([p, i32, i32, i32, d], i32),
             "crk_timing_enable": ([p, i32], i32),
             "crk_timing_reset": ([p], i32),
@@ -423,8 +423,8 @@ class Context:
         self._check(lib().crk_set_hsolve(self._h, lanes, round, cap, C.c_double(factor)),
                     "crk_set_hsolve")
 
-    def set_walk(self, lanes: int = 0, cap: int = 0):
-        self._check(lib().crk_set_walk(self._h, lanes, cap), "crk_set_walk")
+    def set_walk(self, lanes: int = 0, cap: int = 0, level_shift: int = -1):
+        self._check(lib().crk_set_walk(self._h, lanes, cap, level_shift), "crk_set_walk")
 
     def set_lanes(self, vol: int = 0, mom: int = 0, grad: int = 0, der: int = 0):
         self._check(lib().crk_set_lanes(self._h, vol, mom, grad, der), "crk_set_lanes")

@@ -2,7 +2,8 @@
 
 Each pair pass, the neighbour walk and the smoothing-length iteration split a
 particle's work over a group of G lanes of a wave64 (crk_set_lanes,
-crk_set_walk, crk_set_hsolve). The best G depends on the neighbour counts
+crk_set_walk, crk_set_hsolve); the walk also picks how coarse a cell level
+it walks (fewer cells against more candidates). The best G depends on the neighbour counts
 and on the precision, so the tuner times every candidate on the actual
 workload with the library's own per-kernel HIP-event timers, one knob at a
 time (coordinate descent from the current setting), and keeps the fastest.
@@ -22,16 +23,17 @@ from . import pipeline as pl
 HERE = os.path.dirname(os.path.abspath(__file__))
 TABLE = os.path.join(HERE, "tune_table.json")
 
-DEFAULT = {"walk": 8, "vol": 4, "mom": 1, "grad": 4, "der": 8, "hsolve": 8}
+DEFAULT = {"walk": 8, "walk_level": 0, "vol": 4, "mom": 1, "grad": 4, "der": 8, "hsolve": 8}
 CANDIDATES = {
     "walk": (2, 4, 8, 16),
+    "walk_level": (0, 1, 2),
     "vol": (1, 2, 4, 8, 16),
     "mom": (1, 2, 4, 8),
     "grad": (2, 4, 8, 16),
     "der": (4, 8, 16, 32),
     "hsolve": (4, 8, 16, 32),
 }
-KERNEL = {"walk": "k_walk", "vol": "k_volume", "mom": "k_moments", "grad": "k_gradv",
+KERNEL = {"walk": "k_walk", "walk_level": "k_walk", "vol": "k_volume", "mom": "k_moments", "grad": "k_gradv",
           "der": "k_deriv"}
 
 
@@ -49,7 +51,7 @@ def _kind(key: str) -> str:
 
 def apply(ctx: Context, cfg: dict) -> None:
     ctx.set_lanes(cfg["vol"], cfg["mom"], cfg["grad"], cfg["der"])
-    ctx.set_walk(cfg["walk"], 0)
+    ctx.set_walk(cfg["walk"], 0, cfg.get("walk_level", 0))
     ctx.set_hsolve(cfg["hsolve"], 0, 0, 0.0)
 
 

@@ -281,6 +281,150 @@ __device__ __forceinline__ void walk_row(const double4 *__restrict__ posH, int64
     }
 }
 
+// Flattened form of the same walk. The cells of a wavefront's groups hold
+// different numbers of particles, so a cell-by-cell loop keeps most lanes
+// idle; here a group first lists its non-empty, non-skipped cells as ranges
+// of sorted particles (in walk order, up to kRanges at a time, in LDS) and
+// then takes the concatenated candidates G at a time across cell
+// boundaries. The candidate order, hence every row, is the same as the
+// cell-by-cell walk's.
+constexpr int kRanges = 32;
+
+template <int G>
+__device__ __forceinline__ int group_excl_scan(int x, int l, int &total) {
+    int inc = x;
+#pragma unroll
+    for (int o = 1; o < G; o <<= 1) {
+        int t = __shfl_up(inc, o, G);
+        if (l >= o) inc += t;
+    }
+    total = __shfl(inc, G - 1, G);
+    return inc - x;
+}
+
+template <int G, bool DIRECT, bool CULL>
+__device__ __forceinline__ void walk_row_flat(const double4 *__restrict__ posH, int64_t i,
+                                              const double4 &pi, int l, int gshift, uint32_t below,
+                                              const Levels &v, const int32_t *__restrict__ cb,
+                                              const int32_t *__restrict__ ce_, int nck, int lx, int ly,
+                                              int lz, int mx, int my, int mz, double cs, double Hc2,
+                                              int cap, uint32_t *row, const int64_t *__restrict__ goff,
+                                              int32_t *gidx, const int64_t *__restrict__ esoff,
+                                              uint32_t *ekey, int32_t *eval, int32_t &cg, int32_t &ce,
+                                              int32_t *sb, int32_t *sc, int32_t *so) {
+    const double H2 = pi.w * pi.w;
+    const double L = v.L;
+    const int ncell = mx * my * mz;
+    int c0 = 0;
+    while (c0 < ncell) {
+        // 1. list up to kRanges non-empty cells, G cells per step
+        int nr = 0, cum = 0;
+        while (c0 < ncell && nr + G <= kRanges) {
+            const int cidx = c0 + l;
+            int jb = 0, len = 0, code = 0;
+            if (cidx < ncell) {
+                const int e = cidx % mx, t = cidx / mx;
+                const int b = t % my, a = t / my;
+                const int kx = lx + e, ky = ly + b, kz = lz + a;
+                bool keep = true;
+                if (CULL) {
+                    const double gz = cell_gap(pi.z, kz, cs), gy = cell_gap(pi.y, ky, cs),
+                                 gx = cell_gap(pi.x, kx, cs);
+                    keep = (gz * gz + gy * gy) + gx * gx <= Hc2;
+                    code = (kx < 0 ? 1 : (kx >= nck ? 2 : 0)) | (ky < 0 ? 4 : (ky >= nck ? 8 : 0)) |
+                           (kz < 0 ? 16 : (kz >= nck ? 32 : 0));
+                }
+                if (keep) {
+                    const uint32_t id = (spread3(wrapc(kz, nck)) << 2) | (spread3(wrapc(ky, nck)) << 1) |
+                                        spread3(wrapc(kx, nck));
+                    jb = cb[id];
+                    len = ce_[id] - jb;
+                }
+            }
+            int tot;
+            const int pre = group_excl_scan<G>(len, l, tot);
+            const bool has = len > 0;
+            uint32_t hm;
+            if (G == 1) {
+                hm = has;
+            } else {
+                uint64_t m = __ballot(has);
+                hm = (uint32_t)((m >> gshift) & ((G == 64) ? ~0ull : (((uint64_t)1 << G) - 1)));
+            }
+            if (has) {
+                const int pos = nr + (G == 1 ? 0 : __popc(hm & below));
+                sb[pos] = jb;
+                sc[pos] = cum + pre;
+                so[pos] = code;
+            }
+            nr += __popc(hm);
+            cum += tot;
+            c0 += G;
+        }
+        if (l == 0) sc[nr] = cum;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        // 2. the listed candidates, G at a time
+        int r = 0;
+        for (int f0 = 0; f0 < cum; f0 += G) {
+            const int f = f0 + l;
+            bool hit = false, extra = false;
+            int j = 0;
+            if (f < cum) {
+                while (sc[r + 1] <= f) r++;
+                j = sb[r] + (f - sc[r]);
+                const double4 pj = posH[j];
+                double dx, dy, dz;
+                if (CULL) {
+                    const int code = so[r];
+                    const double cx = (code & 1) ? L : ((code & 2) ? -L : 0.0);
+                    const double cy = (code & 4) ? L : ((code & 8) ? -L : 0.0);
+                    const double cz = (code & 16) ? L : ((code & 32) ? -L : 0.0);
+                    dx = (pi.x - pj.x) + cx;
+                    dy = (pi.y - pj.y) + cy;
+                    dz = (pi.z - pj.z) + cz;
+                } else {
+                    dx = min_image(pi.x - pj.x, v.L, v.hL);
+                    dy = min_image(pi.y - pj.y, v.L, v.hL);
+                    dz = min_image(pi.z - pj.z, v.L, v.hL);
+                }
+                const double r2 = r2_exact(dx, dy, dz);
+                hit = r2 < H2 && (int64_t)j != i;
+                extra = hit && !(r2 < pj.w * pj.w);
+            }
+            uint32_t hm, em;
+            if (G == 1) {
+                hm = hit;
+                em = extra;
+            } else {
+                uint64_t mh = __ballot(hit), mx_ = __ballot(extra);
+                hm = (uint32_t)((mh >> gshift) & ((G == 64) ? ~0ull : (((uint64_t)1 << G) - 1)));
+                em = (uint32_t)((mx_ >> gshift) & ((G == 64) ? ~0ull : (((uint64_t)1 << G) - 1)));
+            }
+            if (hit) {
+                const int pos = cg + (G == 1 ? 0 : __popc(hm & below));
+                if (DIRECT) {
+                    gidx[goff[i] + pos] = j;
+                    if (extra) {
+                        const int ep = ce + (G == 1 ? 0 : __popc(em & below));
+                        ekey[esoff[i] + ep] = (uint32_t)j;
+                        eval[esoff[i] + ep] = (int32_t)i;
+                    }
+                } else if (pos < cap) {
+                    row[pos] = (uint32_t)j | (extra ? 0x80000000u : 0u);
+                }
+            }
+            cg += __popc(hm);
+            ce += __popc(em);
+        }
+        // the list is rewritten by the next batch only after every lane read it
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+}
+
 // Single-pass walk of particle i by a group of G lanes of one wavefront:
 // the group visits i's cells in order and takes each cell's particles G at a
 // time (consecutive, so the loads coalesce). A ballot over the group orders
@@ -298,7 +442,7 @@ __global__ __launch_bounds__(kBlock) void k_walk_scratch(const double4 *__restri
                                                          uint32_t *scratch, int32_t *ng, int32_t *nes,
                                                          const int64_t *__restrict__ goff, int32_t *gidx,
                                                          const int64_t *__restrict__ esoff,
-                                                         uint32_t *ekey, int32_t *eval) {
+                                                         uint32_t *ekey, int32_t *eval, int shift) {
     int64_t gid = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
     const int l = (int)(gid % G);
     const int64_t i = gid / G;
@@ -310,7 +454,7 @@ __global__ __launch_bounds__(kBlock) void k_walk_scratch(const double4 *__restri
     const uint32_t below = (l == 0) ? 0u : ((1u << l) - 1u);
     int32_t cg = 0, ce = 0;
     uint32_t *row = scratch + (size_t)i * cap;
-    int k = level_for(pi.w, v);
+    int k = level_for(pi.w * (double)(1 << shift), v);
     int nck = 1 << (v.bits - k);
     Grid g{v.L, v.hL, (double)nck / v.L, v.margin, nck};
     int lx, ly, lz, mx, my, mz;
@@ -322,12 +466,34 @@ __global__ __launch_bounds__(kBlock) void k_walk_scratch(const double4 *__restri
     // the support widened by twice the axis margin (far above any rounding)
     const double cs = v.L / (double)nck;
     const double Hc = pi.w + 2.0 * v.margin;
-    if (2.0 * (Hc + cs) < v.L)
+    const bool cull = 2.0 * (Hc + cs) < v.L;
+    bool done = false;
+    if constexpr (G >= 4) {
+        // the flattened walk (narrower groups would need too much LDS for
+        // their range lists, and walk cell by cell)
+        {
+            constexpr int NG = kBlock / G;
+            __shared__ int32_t s_b[NG][kRanges], s_c[NG][kRanges + 1], s_o[NG][kRanges];
+            const int grp = threadIdx.x / G;
+            if (cull)
+                walk_row_flat<G, DIRECT, true>(posH, i, pi, l, gshift, below, v, cb, ce_, nck, lx, ly, lz,
+                                               mx, my, mz, cs, Hc * Hc, cap, row, goff, gidx, esoff, ekey,
+                                               eval, cg, ce, s_b[grp], s_c[grp], s_o[grp]);
+            else
+                walk_row_flat<G, DIRECT, false>(posH, i, pi, l, gshift, below, v, cb, ce_, nck, lx, ly, lz,
+                                                mx, my, mz, cs, INFINITY, cap, row, goff, gidx, esoff, ekey,
+                                                eval, cg, ce, s_b[grp], s_c[grp], s_o[grp]);
+            done = true;
+        }
+    }
+    if (done) {
+    } else if (cull) {
         walk_row<G, DIRECT, true>(posH, i, pi, l, gshift, below, v, cb, ce_, nck, lx, ly, lz, mx, my,
                                   mz, cs, Hc * Hc, cap, row, goff, gidx, esoff, ekey, eval, cg, ce);
-    else
+    } else {
         walk_row<G, DIRECT, false>(posH, i, pi, l, gshift, below, v, cb, ce_, nck, lx, ly, lz, mx, my,
                                    mz, cs, INFINITY, cap, row, goff, gidx, esoff, ekey, eval, cg, ce);
+    }
     if (!DIRECT && l == 0) {
         ng[i] = cg;
         nes[i] = ce;
@@ -524,7 +690,7 @@ static crk_status build_lists(crk_ctx *c) {
     {
         KTimer kt_(c, "k_walk");
         int G = c->G_walk;
-#define L_WALK(GG) k_walk_scratch<GG, false><<<(unsigned)((n * GG + kBlock - 1) / kBlock), kBlock, 0, c->stream>>>(posH, n, v, cbeg, cend, cap, scratch, ng, nes, nullptr, nullptr, nullptr, nullptr, nullptr)
+#define L_WALK(GG) k_walk_scratch<GG, false><<<(unsigned)((n * GG + kBlock - 1) / kBlock), kBlock, 0, c->stream>>>(posH, n, v, cbeg, cend, cap, scratch, ng, nes, nullptr, nullptr, nullptr, nullptr, nullptr, c->walk_shift)
         switch (G) {
             case 1: L_WALK(1); break;
             case 2: L_WALK(2); break;
@@ -574,7 +740,7 @@ static crk_status build_lists(crk_ctx *c) {
     {
         KTimer kt_(c, "k_walk_long");
         int G = c->G_walk;
-#define L_WALK(GG) k_walk_scratch<GG, true><<<(unsigned)((n * GG + kBlock - 1) / kBlock), kBlock, 0, c->stream>>>(posH, n, v, cbeg, cend, cap, nullptr, ng, nes, goff, (int32_t *)c->gidx.p, esoff, ekey, eidx)
+#define L_WALK(GG) k_walk_scratch<GG, true><<<(unsigned)((n * GG + kBlock - 1) / kBlock), kBlock, 0, c->stream>>>(posH, n, v, cbeg, cend, cap, nullptr, ng, nes, goff, (int32_t *)c->gidx.p, esoff, ekey, eidx, c->walk_shift)
         switch (G) {
             case 1: L_WALK(1); break;
             case 2: L_WALK(2); break;

@@ -103,7 +103,9 @@ struct crk_ctx {
     // per-pass tuning: lanes per particle (1..64)
     int G_vol = 4, G_mom = 1, G_grad = 4, G_der = 8;
     // neighbour walk: lanes per particle and scratch slots per row
-    int G_walk = 4, walk_cap = 192;
+    int G_walk = 8, walk_cap = 192;
+    // walked level: the first whose cell side is at least 2^(walk_shift-1) H
+    int walk_shift = 0;
 
     // per-kernel timing with HIP events on `stream` (crk_timing_*)
     int timing = 0;

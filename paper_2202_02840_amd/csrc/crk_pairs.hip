@@ -792,13 +792,16 @@ using namespace crk;
 extern "C" {
 
 // lanes per particle for each pass (tuning hook; 0 leaves a pass unchanged)
-crk_status crk_set_walk(crk_ctx *c, int32_t lanes, int32_t cap) {
+crk_status crk_set_walk(crk_ctx *c, int32_t lanes, int32_t cap, int32_t level_shift) {
     if (!c) return CRK_ERR_INVALID_ARG;
     if (lanes != 0 && lanes != 1 && lanes != 2 && lanes != 4 && lanes != 8 && lanes != 16)
         return set_err(c, CRK_ERR_INVALID_ARG, "walk lanes must be 1, 2, 4, 8 or 16");
     if (cap < 0 || cap > 65536) return set_err(c, CRK_ERR_INVALID_ARG, "walk cap out of range");
+    if (level_shift < -1 || level_shift > 3)
+        return set_err(c, CRK_ERR_INVALID_ARG, "walk level shift must be -1 (keep) or 0..3");
     if (lanes) c->G_walk = lanes;
     if (cap) c->walk_cap = cap;
+    if (level_shift >= 0) c->walk_shift = level_shift;
     return CRK_OK;
 }
 

@@ -27,7 +27,7 @@ def _print_case(name, ps):
 
 @pytest.mark.parametrize("name", list(CASES))
 @pytest.mark.parametrize("which", [0, 1])
-@pytest.mark.parametrize("walk", [(4, 192), (1, 192), (8, 16), (16, 3)])
+@pytest.mark.parametrize("walk", [(4, 192, 0), (1, 192, 0), (8, 16, 0), (16, 3, 0), (4, 192, 1), (8, 16, 2)])
 def test_neighbour_lists_bit_exact(name, which, walk):
     ps = CASES[name]()
     _print_case(f"{name} walk {walk}", ps)
