@@ -59,26 +59,18 @@ __device__ __forceinline__ double nsum_group(const double4 *__restrict__ posH,
     return kW * invH * invH * invH * s;
 }
 
-// Candidate rows for the iteration: the exact FP64 r^2 of every j within
-// R_i = f H_start (self included), in cell-walk order, in a row of cap
-// slots. cnt[i] counts every candidate, so cnt[i] > cap marks a row that
-// the iteration must not use.
+// Candidate row of particle i: the exact FP64 r^2 of every j within R (self
+// included), in cell-walk order, in a row of cap slots, by a group of G
+// lanes (a ballot orders the hits). Returns the number of candidates, which
+// exceeds cap when the row could not hold them all.
 template <int G>
-__global__ __launch_bounds__(kBlock) void k_hs_rows(const double4 *__restrict__ posH,
-                                                    const int32_t *__restrict__ cbeg,
-                                                    const int32_t *__restrict__ cend, Levels v,
-                                                    int64_t n, const double *__restrict__ H0, double f,
-                                                    int cap, double *rows, int32_t *cnt, double *Rlist) {
-    int64_t gid = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
-    const int l = (int)(gid % G);
-    const int64_t i = gid / G;
-    if (i >= n) return;
-    const double4 pi = posH[i];
-    const double R = f * H0[i];
+__device__ __forceinline__ int build_row(const double4 *__restrict__ posH,
+                                         const int32_t *__restrict__ cbeg,
+                                         const int32_t *__restrict__ cend, const Levels &v, int64_t i,
+                                         const double4 &pi, double R, int cap, double *row, int l) {
     const double R2 = R * R;
     const int gshift = (threadIdx.x & 63) - l;
     const uint64_t below = (l == 0) ? 0ull : (((uint64_t)1 << l) - 1);
-    double *row = rows + (size_t)i * cap;
     int c = 0;
     int k = level_for(R, v);
     int nck = 1 << (v.bits - k);
@@ -108,21 +100,19 @@ __global__ __launch_bounds__(kBlock) void k_hs_rows(const double4 *__restrict__ 
                         r2 = r2_exact(dx, dy, dz);
                         hit = r2 < R2;
                     }
-                    uint32_t hm = (uint32_t)((__ballot(hit) >> gshift) &
-                                             ((G == 64) ? ~0ull : (((uint64_t)1 << G) - 1)));
+                    // 64-bit masks: a group may be a whole wavefront
+                    const uint64_t hm = (__ballot(hit) >> gshift) &
+                                        ((G == 64) ? ~0ull : (((uint64_t)1 << G) - 1));
                     if (hit) {
-                        int p = c + __popc(hm & (uint32_t)below);
+                        int p = c + __popcll(hm & below);
                         if (p < cap) row[p] = r2;
                     }
-                    c += __popc(hm);
+                    c += __popcll(hm);
                 }
             }
         }
     }
-    if (l == 0) {
-        cnt[i] = c;
-        Rlist[i] = R;
-    }
+    return c;
 }
 
 // n_i(H) from a candidate row (valid while H <= the row's radius)
@@ -165,10 +155,9 @@ __global__ __launch_bounds__(kBlock) void k_hsolve_round(const double4 *__restri
                                                          const int32_t *__restrict__ cend, Levels v,
                                                          const int32_t *__restrict__ list, int64_t m,
                                                          double Nres, double tol, int max_iter, int R,
-                                                         const double *__restrict__ rows,
-                                                         const int32_t *__restrict__ rcnt,
-                                                         const double *__restrict__ Rlist, int cap,
-                                                         double *H_io, int32_t *iters, int32_t *state) {
+                                                         double *rows, int32_t *rcnt, double *Rlist,
+                                                         int cap, double f, double *H_io,
+                                                         int32_t *iters, int32_t *state) {
     int64_t gid = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
     const int l = (int)(gid % G);
     const int64_t k = gid / G;
@@ -178,9 +167,25 @@ __global__ __launch_bounds__(kBlock) void k_hsolve_round(const double4 *__restri
     double H = H_io[i];
     int it = iters[i];
     int st = 0;
-    const int c = rows ? rcnt[i] : cap + 1;
-    const double Rmax = rows ? Rlist[i] : 0.0;
-    const double *row = rows ? rows + (size_t)i * cap : nullptr;
+    int c = rows ? rcnt[i] : cap + 1;
+    double Rmax = rows ? Rlist[i] : 0.0;
+    double *row = rows ? rows + (size_t)i * cap : nullptr;
+    // a support that left its candidate row (or has none yet) gets a new
+    // row at f H, which serves every later update with H <= f H without a
+    // cell walk; when f H holds more candidates than the row, a row just
+    // past H is tried (it still serves the updates that shrink H)
+    if (rows && !(c <= cap && H <= Rmax)) {
+        Rmax = f * H;
+        c = build_row<G>(posH, cbeg, cend, v, i, pi, Rmax, cap, row, l);
+        if (c > cap && f > 1.02) {
+            Rmax = 1.02 * H;
+            c = build_row<G>(posH, cbeg, cend, v, i, pi, Rmax, cap, row, l);
+        }
+        if (l == 0) {
+            rcnt[i] = c;
+            Rlist[i] = Rmax;
+        }
+    }
     for (int r = 0; r < R; r++) {
         // the candidate row holds every j within Rmax, so it answers any H <= Rmax
         double ns = (c <= cap && H <= Rmax) ? nsum_row<G>(row, c, H, l)
@@ -203,12 +208,14 @@ __global__ __launch_bounds__(kBlock) void k_hsolve_round(const double4 *__restri
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_hs_init(int64_t n, int32_t *list, int32_t *iters, int32_t *state) {
+__global__ __launch_bounds__(kBlock) void k_hs_init(int64_t n, int32_t *list, int32_t *iters, int32_t *state,
+                                                    int32_t *rcnt, int cap) {
     int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i >= n) return;
     list[i] = (int32_t)i;
     iters[i] = 0;
     state[i] = 0;
+    if (rcnt) rcnt[i] = cap + 1;   // no candidate row yet
 }
 
 // running[k] = 1 when list[k] is still running (for the compaction scan)
@@ -267,9 +274,8 @@ crk_status crk_hsolve(crk_ctx *c, double Nres, double tol, int32_t max_iter, dou
     int32_t *it = iters ? iters : (int32_t *)c->hs_iters.p;
     int64_t *pos = (int64_t *)c->hs_pos.p;
     const unsigned nb = (unsigned)((n + kBlock - 1) / kBlock);
-    k_hs_init<<<nb, kBlock, 0, c->stream>>>(n, la, it, state);
-    CRK_HIP(c, hipGetLastError());
-    // candidate rows at f H_start (positions do not move during the iteration)
+    // candidate rows (positions do not move during the iteration); each
+    // particle's first round builds its row
     const int cap = c->hs_cap;
     double *rows = nullptr;
     int32_t *rcnt = nullptr;
@@ -281,12 +287,9 @@ crk_status crk_hsolve(crk_ctx *c, double Nres, double tol, int32_t max_iter, dou
         rows = (double *)c->hs_rows.p;
         rcnt = (int32_t *)c->hs_rcnt.p;
         Rl = (double *)c->hs_R.p;
-        KTimer kt_(c, "k_hs_rows");
-        k_hs_rows<8><<<(unsigned)((n * 8 + kBlock - 1) / kBlock), kBlock, 0, c->stream>>>(
-            (const double4 *)c->posH.p, (const int32_t *)c->cbeg.p, (const int32_t *)c->cend.p, v, n,
-            H_inout, c->hs_factor, cap, rows, rcnt, Rl);
-        CRK_HIP(c, hipGetLastError());
     }
+    k_hs_init<<<nb, kBlock, 0, c->stream>>>(n, la, it, state, rcnt, cap);
+    CRK_HIP(c, hipGetLastError());
     int64_t m = n;
     int64_t *pin = (int64_t *)c->pinned.p + 24;
     const int G = c->G_hsolve;
@@ -298,7 +301,7 @@ crk_status crk_hsolve(crk_ctx *c, double Nres, double tol, int32_t max_iter, dou
             int Gr = G;
             while (Gr < 64 && m * Gr < (int64_t)1 << 19) Gr *= 2;
             const int R = Gr > G ? 4 * c->hs_round : c->hs_round;
-#define L_HS(GG) k_hsolve_round<GG><<<(unsigned)((m * GG + kBlock - 1) / kBlock), kBlock, 0, c->stream>>>((const double4 *)c->posH.p, (const int32_t *)c->cbeg.p, (const int32_t *)c->cend.p, v, la, m, Nres, tol, max_iter, R, rows, rcnt, Rl, cap, H_inout, it, state)
+#define L_HS(GG) k_hsolve_round<GG><<<(unsigned)((m * GG + kBlock - 1) / kBlock), kBlock, 0, c->stream>>>((const double4 *)c->posH.p, (const int32_t *)c->cbeg.p, (const int32_t *)c->cend.p, v, la, m, Nres, tol, max_iter, R, rows, rcnt, Rl, cap, c->hs_factor, H_inout, it, state)
             switch (Gr) {
                 case 1: L_HS(1); break;
                 case 2: L_HS(2); break;

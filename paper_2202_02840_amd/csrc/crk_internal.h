@@ -95,7 +95,7 @@ struct crk_ctx {
         double L, cell;
         int nc, bits;
     } geo{};                              // geometry the graph was recorded with
-    int G_hsolve = 4, hs_round = 8, hs_cap = 320;
+    int G_hsolve = 8, hs_round = 8, hs_cap = 320;
     double hs_factor = 1.3;
     int64_t last_nflag = 0, last_ntouch = 0;
     crk::Buf pinned;        // small host-pinned readback area
