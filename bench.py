@@ -250,7 +250,7 @@ def batch_leg(args, prec, precision_name: str) -> dict:
     torch.cuda.synchronize()
     eager_ms = (time.perf_counter() - t1) * 1e3 / max(args.steps, 1)
     kern = {}
-    for k in ("sort", "k_walk", "k_compact_rows", "k_walk_long", "k_sort_extras", "k_volume",
+    for k in ("sort", "k_walk", "k_compact_rows", "k_walk_long", "k_extra_rank", "k_volume",
               "k_moments", "k_corrections", "k_gradv", "k_deriv", "k_deriv_fix"):
         ms, cnt = ctx.timing_read(k)
         kern[k] = ms / max(cnt, 1)
@@ -368,7 +368,7 @@ def main():
     t1 = time.perf_counter()
     ms_step = (t1 - t0) * 1e3 / max(args.steps, 1)
     kern = {}
-    for k in ("sort", "k_walk", "k_compact_rows", "k_walk_long", "k_sort_extras", "k_volume", "k_moments",
+    for k in ("sort", "k_walk", "k_compact_rows", "k_walk_long", "k_extra_rank", "k_volume", "k_moments",
               "k_corrections", "k_flag", "k_pack", "k_gradv", "k_gradv_fix", "k_deriv",
               "k_deriv_fix"):
         ms, cnt = ctx.timing_read(k)

@@ -193,7 +193,7 @@ void crk_destroy(crk_ctx *c) {
     (void)hipSetDevice(c->device);
     (void)hipStreamSynchronize(c->stream);
     crk::Buf *all[] = {&c->posH, &c->perm,  &c->cbeg,  &c->cend, &c->goff, &c->gidx, &c->ng,
-                       &c->nes,  &c->esoff, &c->eb,    &c->ee,   &c->ekey, &c->eidx, &c->keyA,
+                       &c->eb,    &c->ee,   &c->eidx, &c->keyA,
                        &c->keyB, &c->valA,  &c->valB,  &c->hist, &c->scanTmp, &c->recV,
                        &c->rec6, &c->rec7,  &c->red,   &c->misc, &c->flag, &c->flist,
                        &c->tlist, &c->fpos, &c->tpos,  &c->rec6d, &c->aux, &c->scratch,

@@ -149,9 +149,9 @@ __global__ void k_graph_inputs(const double *res, const int *flags, double L, Gr
 
 // graph mode: lists longer than the recorded capacity empty every row (so
 // that the fills below stay in bounds) and raise the overflow flag
-__global__ void k_graph_cap(const int64_t *goff, const int64_t *esoff, int64_t n, int64_t gcap,
+__global__ void k_graph_cap(const int64_t *goff, const int64_t *eoff, int64_t n, int64_t gcap,
                             int64_t ecap, GraphStat *st) {
-    int64_t G = goff[n], E = esoff[n];
+    int64_t G = goff[n], E = eoff[n];
     int o = (G > gcap || E > ecap) ? 1 : 0;
     st->overflow = o;
     st->clear = o;
@@ -160,15 +160,12 @@ __global__ void k_graph_cap(const int64_t *goff, const int64_t *esoff, int64_t n
 }
 
 __global__ __launch_bounds__(kBlock) void k_graph_clear(const GraphStat *st, int64_t n, int64_t *goff,
-                                                        int64_t *esoff, int32_t *ng, int32_t *nes) {
+                                                        int64_t *eoff, int32_t *ng) {
     int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i > n || !st->clear) return;
     goff[i] = 0;
-    esoff[i] = 0;
-    if (i < n) {
-        ng[i] = 0;
-        nes[i] = 0;
-    }
+    eoff[i] = 0;
+    if (i < n) ng[i] = 0;
 }
 
 __global__ __launch_bounds__(kBlock) void k_fill_i32(int32_t *a, int64_t n, int32_t v) {
@@ -208,8 +205,8 @@ __device__ __forceinline__ void walk_row(const double4 *__restrict__ posH, int64
                                          int nck, int lx, int ly, int lz, int mx, int my, int mz,
                                          double cs, double Hc2, int cap, uint32_t *row,
                                          const int64_t *__restrict__ goff, int32_t *gidx,
-                                         const int64_t *__restrict__ esoff, uint32_t *ekey,
-                                         int32_t *eval, int32_t &cg, int32_t &ce) {
+                                         int32_t *rcnt, const int64_t *__restrict__ eoff,
+                                         int32_t *efill, int32_t *etmp, int32_t &cg) {
     const double H2 = pi.w * pi.w;
     const double L = v.L;
     for (int a = 0; a < mz; a++) {
@@ -251,30 +248,24 @@ __device__ __forceinline__ void walk_row(const double4 *__restrict__ posH, int64
                         hit = r2 < H2 && (int64_t)j != i;
                         extra = hit && !(r2 < pj.w * pj.w);
                     }
-                    uint32_t hm, em;
+                    uint32_t hm;
                     if (G == 1) {
                         hm = hit;
-                        em = extra;
                     } else {
-                        uint64_t mh = __ballot(hit), mx_ = __ballot(extra);
+                        uint64_t mh = __ballot(hit);
                         hm = (uint32_t)((mh >> gshift) & ((G == 64) ? ~0ull : (((uint64_t)1 << G) - 1)));
-                        em = (uint32_t)((mx_ >> gshift) & ((G == 64) ? ~0ull : (((uint64_t)1 << G) - 1)));
                     }
                     if (hit) {
                         int pos = cg + (G == 1 ? 0 : __popc(hm & below));
                         if (DIRECT) {
                             gidx[goff[i] + pos] = j;
-                            if (extra) {
-                                int ep = ce + (G == 1 ? 0 : __popc(em & below));
-                                ekey[esoff[i] + ep] = (uint32_t)j;
-                                eval[esoff[i] + ep] = (int32_t)i;
-                            }
-                        } else if (pos < cap) {
-                            row[pos] = (uint32_t)j | (extra ? 0x80000000u : 0u);
+                            if (extra) etmp[eoff[j] + atomicAdd(&efill[j], 1)] = (int32_t)i;
+                        } else {
+                            if (pos < cap) row[pos] = (uint32_t)j | (extra ? 0x80000000u : 0u);
+                            if (extra) atomicAdd(&rcnt[j], 1);
                         }
                     }
                     cg += __popc(hm);
-                    ce += __popc(em);
                 }
             }
         }
@@ -309,9 +300,10 @@ __device__ __forceinline__ void walk_row_flat(const double4 *__restrict__ posH, 
                                               const int32_t *__restrict__ ce_, int nck, int lx, int ly,
                                               int lz, int mx, int my, int mz, double cs, double Hc2,
                                               int cap, uint32_t *row, const int64_t *__restrict__ goff,
-                                              int32_t *gidx, const int64_t *__restrict__ esoff,
-                                              uint32_t *ekey, int32_t *eval, int32_t &cg, int32_t &ce,
-                                              int32_t *sb, int32_t *sc, int32_t *so) {
+                                              int32_t *gidx, int32_t *rcnt,
+                                              const int64_t *__restrict__ eoff, int32_t *efill,
+                                              int32_t *etmp, int32_t &cg, int32_t *sb, int32_t *sc,
+                                              int32_t *so) {
     const double H2 = pi.w * pi.w;
     const double L = v.L;
     const int ncell = mx * my * mz;
@@ -393,30 +385,24 @@ __device__ __forceinline__ void walk_row_flat(const double4 *__restrict__ posH, 
                 hit = r2 < H2 && (int64_t)j != i;
                 extra = hit && !(r2 < pj.w * pj.w);
             }
-            uint32_t hm, em;
+            uint32_t hm;
             if (G == 1) {
                 hm = hit;
-                em = extra;
             } else {
-                uint64_t mh = __ballot(hit), mx_ = __ballot(extra);
+                uint64_t mh = __ballot(hit);
                 hm = (uint32_t)((mh >> gshift) & ((G == 64) ? ~0ull : (((uint64_t)1 << G) - 1)));
-                em = (uint32_t)((mx_ >> gshift) & ((G == 64) ? ~0ull : (((uint64_t)1 << G) - 1)));
             }
             if (hit) {
                 const int pos = cg + (G == 1 ? 0 : __popc(hm & below));
                 if (DIRECT) {
                     gidx[goff[i] + pos] = j;
-                    if (extra) {
-                        const int ep = ce + (G == 1 ? 0 : __popc(em & below));
-                        ekey[esoff[i] + ep] = (uint32_t)j;
-                        eval[esoff[i] + ep] = (int32_t)i;
-                    }
-                } else if (pos < cap) {
-                    row[pos] = (uint32_t)j | (extra ? 0x80000000u : 0u);
+                    if (extra) etmp[eoff[j] + atomicAdd(&efill[j], 1)] = (int32_t)i;
+                } else {
+                    if (pos < cap) row[pos] = (uint32_t)j | (extra ? 0x80000000u : 0u);
+                    if (extra) atomicAdd(&rcnt[j], 1);
                 }
             }
             cg += __popc(hm);
-            ce += __popc(em);
         }
         // the list is rewritten by the next batch only after every lane read it
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -439,10 +425,10 @@ template <int G, bool DIRECT>
 __global__ __launch_bounds__(kBlock) void k_walk_scratch(const double4 *__restrict__ posH, int64_t n,
                                                          Levels v, const int32_t *__restrict__ cbeg,
                                                          const int32_t *__restrict__ cend, int cap,
-                                                         uint32_t *scratch, int32_t *ng, int32_t *nes,
+                                                         uint32_t *scratch, int32_t *ng, int32_t *rcnt,
                                                          const int64_t *__restrict__ goff, int32_t *gidx,
-                                                         const int64_t *__restrict__ esoff,
-                                                         uint32_t *ekey, int32_t *eval, int shift) {
+                                                         const int64_t *__restrict__ eoff, int32_t *efill,
+                                                         int32_t *etmp, int shift) {
     int64_t gid = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
     const int l = (int)(gid % G);
     const int64_t i = gid / G;
@@ -452,7 +438,7 @@ __global__ __launch_bounds__(kBlock) void k_walk_scratch(const double4 *__restri
     const int lane = threadIdx.x & 63;
     const int gshift = lane - l;
     const uint32_t below = (l == 0) ? 0u : ((1u << l) - 1u);
-    int32_t cg = 0, ce = 0;
+    int32_t cg = 0;
     uint32_t *row = scratch + (size_t)i * cap;
     int k = level_for(pi.w * (double)(1 << shift), v);
     int nck = 1 << (v.bits - k);
@@ -477,63 +463,48 @@ __global__ __launch_bounds__(kBlock) void k_walk_scratch(const double4 *__restri
             const int grp = threadIdx.x / G;
             if (cull)
                 walk_row_flat<G, DIRECT, true>(posH, i, pi, l, gshift, below, v, cb, ce_, nck, lx, ly, lz,
-                                               mx, my, mz, cs, Hc * Hc, cap, row, goff, gidx, esoff, ekey,
-                                               eval, cg, ce, s_b[grp], s_c[grp], s_o[grp]);
+                                               mx, my, mz, cs, Hc * Hc, cap, row, goff, gidx, rcnt, eoff,
+                                               efill, etmp, cg, s_b[grp], s_c[grp], s_o[grp]);
             else
                 walk_row_flat<G, DIRECT, false>(posH, i, pi, l, gshift, below, v, cb, ce_, nck, lx, ly, lz,
-                                                mx, my, mz, cs, INFINITY, cap, row, goff, gidx, esoff, ekey,
-                                                eval, cg, ce, s_b[grp], s_c[grp], s_o[grp]);
+                                                mx, my, mz, cs, INFINITY, cap, row, goff, gidx, rcnt, eoff,
+                                                efill, etmp, cg, s_b[grp], s_c[grp], s_o[grp]);
             done = true;
         }
     }
     if (done) {
     } else if (cull) {
         walk_row<G, DIRECT, true>(posH, i, pi, l, gshift, below, v, cb, ce_, nck, lx, ly, lz, mx, my,
-                                  mz, cs, Hc * Hc, cap, row, goff, gidx, esoff, ekey, eval, cg, ce);
+                                  mz, cs, Hc * Hc, cap, row, goff, gidx, rcnt, eoff, efill, etmp, cg);
     } else {
         walk_row<G, DIRECT, false>(posH, i, pi, l, gshift, below, v, cb, ce_, nck, lx, ly, lz, mx, my,
-                                   mz, cs, INFINITY, cap, row, goff, gidx, esoff, ekey, eval, cg, ce);
+                                   mz, cs, INFINITY, cap, row, goff, gidx, rcnt, eoff, efill, etmp, cg);
     }
-    if (!DIRECT && l == 0) {
-        ng[i] = cg;
-        nes[i] = ce;
-    }
+    if (!DIRECT && l == 0) ng[i] = cg;
 }
 
-// scratch rows -> gather rows and (j, i) extras, for rows that fit in cap;
-// G lanes per row read and write consecutive slots, and a ballot keeps the
-// extras in row order
+// scratch rows -> gather rows, for rows that fit in cap (G lanes per row
+// read and write consecutive slots); each extra (j, i) goes to a slot of
+// row j of the transposed lists (slot order is fixed later by rank)
 template <int G>
 __global__ __launch_bounds__(kBlock) void k_compact_rows(const uint32_t *__restrict__ scratch, int cap,
                                                          int64_t n, const int32_t *__restrict__ ng,
-                                                         const int64_t *__restrict__ goff,
-                                                         const int64_t *__restrict__ esoff,
-                                                         int32_t *gidx, uint32_t *ekey, int32_t *eval) {
+                                                         const int64_t *__restrict__ goff, int32_t *gidx,
+                                                         const int64_t *__restrict__ eoff, int32_t *efill,
+                                                         int32_t *etmp) {
     int64_t gid = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
     const int l = (int)(gid % G);
     const int64_t i = gid / G;
     if (i >= n) return;
     const int cnt = ng[i];
     if (cnt > cap) return;
-    const int gshift = (threadIdx.x & 63) - l;
-    const uint32_t below = (l == 0) ? 0u : ((1u << l) - 1u);
     const uint32_t *row = scratch + (size_t)i * cap;
-    const int64_t gw = goff[i], ew = esoff[i];
-    int e = 0;
-    for (int k0 = 0; k0 < cnt; k0 += G) {
-        int k = k0 + l;
-        bool valid = k < cnt;
-        uint32_t w = valid ? row[k] : 0u;
-        int32_t j = (int32_t)(w & 0x7fffffffu);
-        if (valid) gidx[gw + k] = j;
-        bool isx = valid && (w & 0x80000000u);
-        uint32_t gm = (uint32_t)((__ballot(isx) >> gshift) & ((1ull << G) - 1));
-        if (isx) {
-            int p = e + __popc(gm & below);
-            ekey[ew + p] = (uint32_t)j;
-            eval[ew + p] = (int32_t)i;
-        }
-        e += __popc(gm);
+    const int64_t gw = goff[i];
+    for (int k = l; k < cnt; k += G) {
+        const uint32_t w = row[k];
+        const int32_t j = (int32_t)(w & 0x7fffffffu);
+        gidx[gw + k] = j;
+        if (w & 0x80000000u) etmp[eoff[j] + atomicAdd(&efill[j], 1)] = (int32_t)i;
     }
 }
 
@@ -543,32 +514,13 @@ __global__ __launch_bounds__(kBlock) void k_to_i64(const int32_t *a, int64_t n, 
     if (i == n) o[n] = 0;
 }
 
-// Transpose of the extras, which arrive grouped by the emitting particle i:
-// rows per receiving particle j, each ascending in i. Counts per j, a scan
-// for the row offsets, a scatter into arbitrary slots of the row (atomic
-// slot counters), then every entry moves to the place given by its rank in
-// its row, which fixes the order whatever the scatter did.
-__global__ __launch_bounds__(kBlock) void k_extra_count(const uint32_t *__restrict__ ekey, int64_t cap,
-                                                        const int64_t *__restrict__ E_dev, int32_t *cnt) {
-    int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (k >= cap || k >= *E_dev) return;
-    atomicAdd(&cnt[ekey[k]], 1);
-}
-
-__global__ __launch_bounds__(kBlock) void k_extra_scatter(const uint32_t *__restrict__ ekey,
-                                                          const int32_t *__restrict__ eval, int64_t cap,
-                                                          const int64_t *__restrict__ E_dev,
-                                                          const int64_t *__restrict__ eoff, int32_t *fill,
-                                                          int32_t *tmp) {
-    int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (k >= cap || k >= *E_dev) return;
-    uint32_t j = ekey[k];
-    int slot = atomicAdd(&fill[j], 1);
-    tmp[eoff[j] + slot] = eval[k];
-}
-
-// G lanes per row; entries of a row are distinct emitters, so the ranks are
-// a permutation of the row's slots
+// Extras rows (per receiving particle j): the walk counts them per j, a
+// scan gives the row offsets, the compaction and the second walk drop each
+// (j, i) into some slot of row j (atomic slot counters), and here every
+// entry moves to the place given by its rank in its row, so each row is
+// ascending in i whatever order the slots were taken in. G lanes per row;
+// entries of a row are distinct emitters, so the ranks are a permutation of
+// the row's slots.
 template <int G>
 __global__ __launch_bounds__(kBlock) void k_extra_rank(const int64_t *__restrict__ eoff,
                                                        const int32_t *__restrict__ tmp, int64_t n,
@@ -676,21 +628,27 @@ static crk_status build_lists(crk_ctx *c) {
     int64_t n = c->n;
     Levels v = levels(c);
     CRK_TRY(ensure(c, c->ng, (size_t)n * sizeof(int32_t)));
-    CRK_TRY(ensure(c, c->nes, (size_t)n * sizeof(int32_t)));
     CRK_TRY(ensure(c, c->goff, (size_t)(n + 1) * sizeof(int64_t)));
-    CRK_TRY(ensure(c, c->esoff, (size_t)(n + 1) * sizeof(int64_t)));
-    int32_t *ng = (int32_t *)c->ng.p, *nes = (int32_t *)c->nes.p;
-    int64_t *goff = (int64_t *)c->goff.p, *esoff = (int64_t *)c->esoff.p;
+    CRK_TRY(ensure(c, c->ecnt, (size_t)n * sizeof(int32_t)));
+    CRK_TRY(ensure(c, c->efill, (size_t)n * sizeof(int32_t)));
+    CRK_TRY(ensure(c, c->eoff, (size_t)(n + 1) * sizeof(int64_t)));
+    int32_t *ng = (int32_t *)c->ng.p;
+    int64_t *goff = (int64_t *)c->goff.p;
+    int32_t *ecnt = (int32_t *)c->ecnt.p, *efill = (int32_t *)c->efill.p;
+    int64_t *eoff = (int64_t *)c->eoff.p;
     const double4 *posH = (const double4 *)c->posH.p;
     const int32_t *cbeg = (const int32_t *)c->cbeg.p, *cend = (const int32_t *)c->cend.p;
-    // one walk into a capped scratch row per particle; exact counts come with it
+    // one walk into a capped scratch row per particle; exact counts come
+    // with it, and the extras are counted per receiving particle
     const int cap = c->walk_cap;
     CRK_TRY(ensure(c, c->scratch, (size_t)n * cap * sizeof(uint32_t)));
     uint32_t *scratch = (uint32_t *)c->scratch.p;
+    k_fill_i32<<<nblocks(n), kBlock, 0, c->stream>>>(ecnt, n, 0);
+    k_fill_i32<<<nblocks(n), kBlock, 0, c->stream>>>(efill, n, 0);
     {
         KTimer kt_(c, "k_walk");
         int G = c->G_walk;
-#define L_WALK(GG) k_walk_scratch<GG, false><<<(unsigned)((n * GG + kBlock - 1) / kBlock), kBlock, 0, c->stream>>>(posH, n, v, cbeg, cend, cap, scratch, ng, nes, nullptr, nullptr, nullptr, nullptr, nullptr, c->walk_shift)
+#define L_WALK(GG) k_walk_scratch<GG, false><<<(unsigned)((n * GG + kBlock - 1) / kBlock), kBlock, 0, c->stream>>>(posH, n, v, cbeg, cend, cap, scratch, ng, ecnt, nullptr, nullptr, nullptr, nullptr, nullptr, c->walk_shift)
         switch (G) {
             case 1: L_WALK(1); break;
             case 2: L_WALK(2); break;
@@ -703,44 +661,43 @@ static crk_status build_lists(crk_ctx *c) {
     }
     CRK_HIP(c, hipGetLastError());
     k_to_i64<<<nblocks(n + 1), kBlock, 0, c->stream>>>(ng, n, goff);
-    k_to_i64<<<nblocks(n + 1), kBlock, 0, c->stream>>>(nes, n, esoff);
+    k_to_i64<<<nblocks(n + 1), kBlock, 0, c->stream>>>(ecnt, n, eoff);
     CRK_TRY(scan_exclusive_i64(c, goff, goff, n + 1));
-    CRK_TRY(scan_exclusive_i64(c, esoff, esoff, n + 1));
+    CRK_TRY(scan_exclusive_i64(c, eoff, eoff, n + 1));
     int64_t G, E;
     GraphStat *gst = (GraphStat *)c->gstat.p;
     if (c->graph_mode) {
         // fixed capacities; the counts stay on the device
         G = c->gcap;
         E = c->ecap;
-        k_graph_cap<<<1, 1, 0, c->stream>>>(goff, esoff, n, G, E, gst);
-        k_graph_clear<<<nblocks(n + 1), kBlock, 0, c->stream>>>(gst, n, goff, esoff, ng, nes);
+        k_graph_cap<<<1, 1, 0, c->stream>>>(goff, eoff, n, G, E, gst);
+        k_graph_clear<<<nblocks(n + 1), kBlock, 0, c->stream>>>(gst, n, goff, eoff, ng);
         CRK_HIP(c, hipGetLastError());
     } else {
         int64_t *pin = (int64_t *)c->pinned.p;
         CRK_HIP(c, hipMemcpyAsync(pin, goff + n, sizeof(int64_t), hipMemcpyDeviceToHost, c->stream));
-        CRK_HIP(c, hipMemcpyAsync(pin + 1, esoff + n, sizeof(int64_t), hipMemcpyDeviceToHost, c->stream));
+        CRK_HIP(c, hipMemcpyAsync(pin + 1, eoff + n, sizeof(int64_t), hipMemcpyDeviceToHost, c->stream));
         CRK_HIP(c, hipStreamSynchronize(c->stream));
         G = pin[0];
         E = pin[1];
     }
     if (E > INT32_MAX - 1) return set_err(c, CRK_ERR_INVALID_ARG, "more than 2^31 extra pairs");
     CRK_TRY(ensure(c, c->gidx, (size_t)(G > 0 ? G : 1) * sizeof(int32_t)));
-    CRK_TRY(ensure(c, c->ekey, (size_t)(E > 0 ? E : 1) * sizeof(uint32_t)));
+    CRK_TRY(ensure(c, c->etmp, (size_t)(E > 0 ? E : 1) * sizeof(int32_t)));
     CRK_TRY(ensure(c, c->eidx, (size_t)(E > 0 ? E : 1) * sizeof(int32_t)));
     CRK_TRY(ensure(c, c->eb, (size_t)n * sizeof(int32_t)));
     CRK_TRY(ensure(c, c->ee, (size_t)n * sizeof(int32_t)));
-    uint32_t *ekey = (uint32_t *)c->ekey.p;
-    int32_t *eidx = (int32_t *)c->eidx.p;
+    int32_t *etmp = (int32_t *)c->etmp.p, *eidx = (int32_t *)c->eidx.p;
     {
         KTimer kt_(c, "k_compact_rows");
         constexpr int GC = 16;
         k_compact_rows<GC><<<(unsigned)((n * GC + kBlock - 1) / kBlock), kBlock, 0, c->stream>>>(
-            scratch, cap, n, ng, goff, esoff, (int32_t *)c->gidx.p, ekey, eidx);
+            scratch, cap, n, ng, goff, (int32_t *)c->gidx.p, eoff, efill, etmp);
     }
     {
         KTimer kt_(c, "k_walk_long");
         int G = c->G_walk;
-#define L_WALK(GG) k_walk_scratch<GG, true><<<(unsigned)((n * GG + kBlock - 1) / kBlock), kBlock, 0, c->stream>>>(posH, n, v, cbeg, cend, cap, nullptr, ng, nes, goff, (int32_t *)c->gidx.p, esoff, ekey, eidx, c->walk_shift)
+#define L_WALK(GG) k_walk_scratch<GG, true><<<(unsigned)((n * GG + kBlock - 1) / kBlock), kBlock, 0, c->stream>>>(posH, n, v, cbeg, cend, cap, nullptr, ng, nullptr, goff, (int32_t *)c->gidx.p, eoff, efill, etmp, c->walk_shift)
         switch (G) {
             case 1: L_WALK(1); break;
             case 2: L_WALK(2); break;
@@ -752,34 +709,10 @@ static crk_status build_lists(crk_ctx *c) {
 #undef L_WALK
     }
     CRK_HIP(c, hipGetLastError());
-    // extras arrive grouped by the emitting particle i (ascending); a stable
-    // sort on the receiving particle j keeps them ascending in i per row
-    // transpose to rows per receiving particle j, ascending in i (the
-    // extras count is read on the device: in graph mode E is the capacity)
+    // each extras row ascending in the emitting particle
     {
-        KTimer kt_(c, "k_sort_extras");
-        CRK_TRY(ensure(c, c->ecnt, (size_t)n * sizeof(int32_t)));
-        CRK_TRY(ensure(c, c->efill, (size_t)n * sizeof(int32_t)));
-        CRK_TRY(ensure(c, c->eoff, (size_t)(n + 1) * sizeof(int64_t)));
-        CRK_TRY(ensure(c, c->etmp, (size_t)(E > 0 ? E : 1) * sizeof(int32_t)));
-        int32_t *ecnt = (int32_t *)c->ecnt.p, *efill = (int32_t *)c->efill.p;
-        int32_t *etmp = (int32_t *)c->etmp.p;
-        int64_t *eoff = (int64_t *)c->eoff.p;
-        k_fill_i32<<<nblocks(n), kBlock, 0, c->stream>>>(ecnt, n, 0);
-        k_fill_i32<<<nblocks(n), kBlock, 0, c->stream>>>(efill, n, 0);
-        if (E > 0) {
-            KTimer kt2_(c, "k_extra_count");
-            k_extra_count<<<nblocks(E), kBlock, 0, c->stream>>>(ekey, E, esoff + n, ecnt);
-        }
-        k_to_i64<<<nblocks(n + 1), kBlock, 0, c->stream>>>(ecnt, n, eoff);
-        CRK_TRY(scan_exclusive_i64(c, eoff, eoff, n + 1));
-        if (E > 0) {
-            KTimer kt2_(c, "k_extra_scatter");
-            k_extra_scatter<<<nblocks(E), kBlock, 0, c->stream>>>(ekey, eidx, E, esoff + n, eoff, efill,
-                                                                   etmp);
-        }
+        KTimer kt_(c, "k_extra_rank");
         constexpr int GR = 8;
-        KTimer kt3_(c, "k_extra_rank");
         k_extra_rank<GR><<<(unsigned)((n * GR + kBlock - 1) / kBlock), kBlock, 0, c->stream>>>(
             eoff, etmp, n, eidx, (int32_t *)c->eb.p, (int32_t *)c->ee.p);
     }

@@ -13,6 +13,7 @@
 //   eb/ee  int32   [n]      extras rows in eidx: {j : H_i <= |d| < H_j}, the
 //   eidx   int32   [E]      partners that reach i only through their own larger
 //                           support, ascending; N_s(i) = gather row ++ extras row
+//                           (eoff [n+1] int64 holds the same row offsets)
 //   recV   T       [n]      volumes in the pass precision
 //   rec6   T4      [n]      {vx, vy, vz, V}            (velocity-gradient pass)
 //   rec7   T4      [9][n]   packed per-particle state  (derivative pass)
@@ -67,7 +68,7 @@ struct crk_ctx {
     int64_t nextra = 0;     // entries of eidx
 
     // workspace
-    crk::Buf posH, perm, cbeg, cend, goff, gidx, ng, nes, esoff, eb, ee, ekey, eidx;
+    crk::Buf posH, perm, cbeg, cend, goff, gidx, ng, eb, ee, eidx;
     crk::Buf keyA, keyB, valA, valB, hist, scanTmp;
     crk::Buf recV, rec6, rec7, red, misc;
     crk::Buf flag, flist, tlist, fpos, tpos, rec6d, aux;   // adaptive-precision rows
@@ -79,7 +80,7 @@ struct crk_ctx {
     crk::Buf sv, sm, su, srho;                            // sorted gas state (crk_step)
     crk::Buf gstat;                                       // device status of a graph step
     crk::Buf gboff;                                       // box offsets the graph was recorded with
-    crk::Buf ecnt, efill, eoff, etmp;                     // transpose of the extras
+    crk::Buf ecnt, efill, eoff, etmp;                     // extras rows: counts, slots, offsets, unordered rows
 
     // graph mode (crk_graph_capture): the build keeps the geometry of the
     // last eager build, lists are bounded by fixed capacities, and no call
