@@ -76,15 +76,23 @@ __device__ __forceinline__ void group_reduce(Acc<T> (&a)[K]) {
 }
 
 struct Box {
-    double L, hL;
+    double L, invL;
 };
+
+// Minimum image of a listed pair: d - L rint(d / L), one fused rounding,
+// so the value equals d, d - L or d + L exactly as the branch form gives;
+// a listed pair has |d| < H < L/2 per component, far from the tie at L/2
+// (neighbour decisions themselves use the branch form).
+__device__ __forceinline__ double pair_image(double d, const Box &b) {
+    return fma(-b.L, rint(d * b.invL), d);
+}
 
 template <typename T>
 __device__ __forceinline__ void separation(const double4 &pi, const double4 &pj, const Box &b,
                                            T &dx, T &dy, T &dz) {
-    dx = (T)min_image(pi.x - pj.x, b.L, b.hL);
-    dy = (T)min_image(pi.y - pj.y, b.L, b.hL);
-    dz = (T)min_image(pi.z - pj.z, b.L, b.hL);
+    dx = (T)pair_image(pi.x - pj.x, b);
+    dy = (T)pair_image(pi.y - pj.y, b);
+    dz = (T)pair_image(pi.z - pj.z, b);
 }
 
 // Wendland C4 with unit support, eq. (C4): with q = r/H and s = max(1 - q, 0),
@@ -829,7 +837,7 @@ crk_status crk_moments(crk_ctx *c, const crk_params *p, double *nsum, double *V,
         return set_err(c, CRK_ERR_INVALID_ARG, "crk_moments: give all moment outputs or none");
     CRK_HIP(c, hipSetDevice(c->device));
     int64_t n = c->n;
-    Box box{c->L, 0.5 * c->L};
+    Box box{c->L, 1.0 / c->L};
     const double4 *posH = (const double4 *)c->posH.p;
     const int64_t *goff = (const int64_t *)c->goff.p;
     const int32_t *gidx = (const int32_t *)c->gidx.p;
@@ -915,7 +923,7 @@ crk_status crk_derivatives(crk_ctx *c, const crk_params *p, const double *v, con
     if (!c->built) return set_err(c, CRK_ERR_STATE, "crk_build_cells has not run");
     CRK_HIP(c, hipSetDevice(c->device));
     int64_t n = c->n;
-    Box box{c->L, 0.5 * c->L};
+    Box box{c->L, 1.0 / c->L};
     const double4 *posH = (const double4 *)c->posH.p;
     const int64_t *goff = (const int64_t *)c->goff.p;
     const int32_t *gidx = (const int32_t *)c->gidx.p;
