@@ -307,6 +307,9 @@ __device__ __forceinline__ void walk_row_flat(const double4 *__restrict__ posH, 
     const double H2 = pi.w * pi.w;
     const double L = v.L;
     const int ncell = mx * my * mz;
+    // cell index -> (a, b, e) without integer division: the quotients are
+    // taken in FP64, exact for these small integers
+    const double inv_mx = 1.0 / (double)mx, inv_my = 1.0 / (double)my;
     int c0 = 0;
     while (c0 < ncell) {
         // 1. list up to kRanges non-empty cells, G cells per step
@@ -315,8 +318,10 @@ __device__ __forceinline__ void walk_row_flat(const double4 *__restrict__ posH, 
             const int cidx = c0 + l;
             int jb = 0, len = 0, code = 0;
             if (cidx < ncell) {
-                const int e = cidx % mx, t = cidx / mx;
-                const int b = t % my, a = t / my;
+                const int t = (int)(((double)cidx + 0.5) * inv_mx);
+                const int e = cidx - t * mx;
+                const int a = (int)(((double)t + 0.5) * inv_my);
+                const int b = t - a * my;
                 const int kx = lx + e, ky = ly + b, kz = lz + a;
                 bool keep = true;
                 if (CULL) {

@@ -199,10 +199,9 @@ __device__ __forceinline__ double cell_gap(double p, int k, double cs) {
     return fmax(0.0, fmax(lo - p, p - hi));
 }
 
-__device__ __forceinline__ int wrapc(int a, int nc) {
-    a %= nc;
-    return a < 0 ? a + nc : a;
-}
+// periodic cell index: every level has a power-of-two number of cells a
+// side, so the wrap is a mask (two's complement keeps it right for a < 0)
+__device__ __forceinline__ int wrapc(int a, int nc) { return a & (nc - 1); }
 
 
 // Morton cell hierarchy: level k has nc >> k cells a side, side c0 2^k, and
