@@ -1,0 +1,165 @@
+"""Edge cases and error paths of the GPU path.
+
+Degenerate sets against the oracle (a single particle, one-sided pairs,
+coincident particles, supports near L/2, particles on the box faces, a
+tiny ragged set, strongly mixed supports; each dense enough that the RK
+solve is well conditioned where a solve happens): pair rows bit for bit, FP64
+outputs within 1e-12, adaptive mixed within 1e-5, and the same count of
+singular-m2 fallbacks. Invalid input is rejected with the documented
+status and never run. The autotuner returns a configuration from its
+candidate lists whose results still match the oracle.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import crk_inputs as ci
+from gpu_helpers import compare, gpu_run, oracle_run, rows_original
+from paper_2202_02840_amd import CRK_FP64, CRK_MIXED_ADAPT, Context, CrkError
+from paper_2202_02840_amd import pipeline as pl
+
+pytestmark = pytest.mark.gpu
+
+
+def _set(x, y, z, H, seed=0, u=1.0, rho=None):
+    x, y, z, H = (np.asarray(a, dtype=np.float64) for a in (x, y, z, H))
+    n = x.shape[0]
+    g = np.random.default_rng(seed)
+    v = g.normal(0.0, 0.05, (3, n))
+    return ci.ParticleSet(x, y, z, H, np.full(n, 1.0 / max(n, 1)), np.full(n, u), v, rho, L=1.0,
+                          meta=dict(kind="edge"))
+
+
+def _single():
+    return _set([0.3], [0.6], [0.9], [0.2])
+
+
+def _one_sided_pair():
+    # j reaches i only through its own larger support
+    return _set([0.1, 0.15], [0.5, 0.5], [0.5, 0.52], [0.02, 0.2])
+
+
+def _ragged_seven():
+    g = np.random.default_rng(41)
+    return _set(g.uniform(0, 1, 7), g.uniform(0, 1, 7), g.uniform(0, 1, 7), g.uniform(0.05, 0.45, 7))
+
+
+def _coincident():
+    # twenty particles placed exactly on top of others (r = 0 between
+    # distinct particles), in a set dense enough (~25-60 neighbours) for a
+    # well-conditioned RK solve
+    g = np.random.default_rng(42)
+    x, y, z = g.uniform(0, 1, 200), g.uniform(0, 1, 200), g.uniform(0, 1, 200)
+    x = np.concatenate([x, x[:20]])
+    y = np.concatenate([y, y[:20]])
+    z = np.concatenate([z, z[:20]])
+    return _set(x, y, z, g.uniform(0.3, 0.4, 220))
+
+
+def _on_faces():
+    g = np.random.default_rng(43)
+    top = math.nextafter(1.0, 0.0)
+    x = np.concatenate([[0.0, top, 0.0, top], g.uniform(0, 1, 400)])
+    y = np.concatenate([[0.0, 0.0, top, top], g.uniform(0, 1, 400)])
+    z = np.concatenate([[top, 0.0, 0.0, top], g.uniform(0, 1, 400)])
+    return _set(x, y, z, np.full(404, 0.25))
+
+
+def _near_half_box():
+    g = np.random.default_rng(44)
+    n = 50
+    return _set(g.uniform(0, 1, n), g.uniform(0, 1, n), g.uniform(0, 1, n),
+                g.uniform(0.40, 0.4999, n))
+
+
+def _mixed_supports():
+    # every other particle has twice the support (0.41, below L/2)
+    ps = ci.lattice_box(12, seed=45)
+    H = ps.H.copy()
+    H[::2] *= 2.0
+    ps.H = H
+    return ps
+
+
+CASES = {"single": _single, "one_sided_pair": _one_sided_pair, "ragged_seven": _ragged_seven,
+         "coincident": _coincident, "on_faces": _on_faces, "near_half_box": _near_half_box,
+         "mixed_supports": _mixed_supports}
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_degenerate_sets_match_oracle(name):
+    ps = CASES[name]()
+    print(f"[case] edge {name} n={ps.n}", flush=True)
+    ref = oracle_run(ps)
+    res = gpu_run(ps, CRK_FP64)
+    assert res["n_singular"] == ref["n_singular"]
+    assert res["n_pairs"] == ref["n_pairs"]
+    o1, i1 = res["ctx"].export_neighbors(1)
+    rows = rows_original(o1, i1, res["ctx"].perm)
+    for i in range(ps.n):
+        assert np.array_equal(rows[i], ref["sidx"][ref["soff"][i]:ref["soff"][i + 1]]), i
+    for k, e in compare(res, ref).items():
+        assert e <= 1e-12, (name, k, e)
+    mixed = gpu_run(ps, CRK_MIXED_ADAPT)
+    for k, e in compare(mixed, ref).items():
+        assert e <= 1e-5, (name, k, e)
+
+
+@pytest.mark.parametrize("field,index,value,status", [
+    ("x", 3, float("nan"), -2),
+    ("H", 5, float("inf"), -2),
+    ("y", 2, 1.0, -1),
+    ("z", 0, -1e-9, -1),
+    ("H", 7, 0.0, -3),
+    ("H", 1, 0.5, -3),
+])
+def test_invalid_input_is_rejected(field, index, value, status):
+    ps = ci.lattice_box(6, seed=46)
+    print(f"[case] invalid {field}[{index}] = {value}", flush=True)
+    dev = pl.upload(ps)
+    dev[field][index] = value
+    ctx = Context(0)
+    with pytest.raises(CrkError) as e:
+        ctx.build_cells(dev["x"], dev["y"], dev["z"], dev["H"], pl.params_for(ps, 64.0, CRK_FP64))
+    assert e.value.status == status
+
+
+def test_calls_out_of_order_are_rejected():
+    ps = ci.lattice_box(6, seed=47)
+    ctx = Context(0)
+    ctx.n = ps.n
+    with pytest.raises(CrkError) as e:
+        ctx.moments(pl.params_for(ps, 64.0, CRK_FP64))
+    assert e.value.status == -6
+
+
+def test_bad_gas_state_is_reported():
+    ps = ci.lattice_box(8, seed=48)
+    ps.u = ps.u.copy()
+    ps.u[11] = -1.0
+    print("[case] negative internal energy", flush=True)
+    ctx = Context(0)
+    dev = pl.upload(ps)
+    with pytest.raises(CrkError) as e:
+        pl.step(ctx, dev, pl.params_for(ps, 64.0, CRK_FP64))
+    assert e.value.status == -2
+
+
+def test_autotuner_picks_listed_candidates_and_keeps_parity():
+    from paper_2202_02840_amd import autotune as at
+    ps = ci.lognormal_box(16, sigma=1.5, seed=49)
+    print(f"[case] autotune n={ps.n}", flush=True)
+    ctx = Context(0)
+    dev = pl.upload(ps)
+    prm = pl.params_for(ps, 64.0, CRK_MIXED_ADAPT)
+    cfg, timings = at.tune(ctx, dev, prm, reps=1, with_hsolve=True, log=None)
+    for knob, cands in at.CANDIDATES.items():
+        assert cfg[knob] in cands, (knob, cfg[knob])
+        assert set(timings[knob]) == {str(c) for c in cands}
+    res = gpu_run(ps, CRK_MIXED_ADAPT, ctx=ctx)
+    ref = oracle_run(ps)
+    for k, e in compare(res, ref).items():
+        assert e <= 1e-5, (k, e)
+    torch.cuda.synchronize()
