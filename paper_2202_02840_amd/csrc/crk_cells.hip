@@ -66,17 +66,28 @@ __global__ __launch_bounds__(kBlock) void k_validate(const double *x, const doub
     if (bh) atomicOr(&flags[2], 1);
 }
 
-// fixed-order final reduction of the block partials (one thread)
-__global__ void k_validate_final(const double *part, int nblk, double *out) {
-    double hmax = 0.0, hmin = INFINITY, hsum = 0.0;
-    for (int b = 0; b < nblk; b++) {
-        hmax = fmax(hmax, part[b * 3 + 0]);
-        hmin = fmin(hmin, part[b * 3 + 1]);
-        hsum += part[b * 3 + 2];
+// final reduction of the (at most 1024) block partials by one block, in a
+// fixed tree order
+__global__ __launch_bounds__(1024) void k_validate_final(const double *part, int nblk, double *out) {
+    __shared__ double smax[1024], smin[1024], ssum[1024];
+    const int t = threadIdx.x;
+    smax[t] = t < nblk ? part[t * 3 + 0] : 0.0;
+    smin[t] = t < nblk ? part[t * 3 + 1] : INFINITY;
+    ssum[t] = t < nblk ? part[t * 3 + 2] : 0.0;
+    __syncthreads();
+    for (int s = 512; s > 0; s >>= 1) {
+        if (t < s) {
+            smax[t] = fmax(smax[t], smax[t + s]);
+            smin[t] = fmin(smin[t], smin[t + s]);
+            ssum[t] += ssum[t + s];
+        }
+        __syncthreads();
     }
-    out[0] = hmax;
-    out[1] = hmin;
-    out[2] = hsum;
+    if (t == 0) {
+        out[0] = smax[0];
+        out[1] = smin[0];
+        out[2] = ssum[0];
+    }
 }
 
 // Graph mode cannot stop on invalid input before the walk, so such a
@@ -818,7 +829,7 @@ crk_status crk_build_cells_batch(crk_ctx *c, int32_t nboxes, const int64_t *box_
     double *res = (double *)c->misc.p;
     k_fill_i32<<<1, kBlock, 0, c->stream>>>(flags, 3, 0);
     k_validate<<<nblk, kBlock, 0, c->stream>>>(x, y, z, H, n, p->L, part, flags);
-    k_validate_final<<<1, 1, 0, c->stream>>>(part, nblk, res);
+    k_validate_final<<<1, 1024, 0, c->stream>>>(part, nblk, res);
     CRK_HIP(c, hipGetLastError());
     if (gm) {
         CRK_TRY(ensure(c, c->gstat, sizeof(GraphStat)));
@@ -887,7 +898,7 @@ crk_status crk_update_support(crk_ctx *c, const double *H_sorted, int64_t *n_pai
     double *res = (double *)c->misc.p;
     k_fill_i32<<<1, kBlock, 0, c->stream>>>(flags, 3, 0);
     k_validate<<<nblk, kBlock, 0, c->stream>>>(xs, xs + n, xs + 2 * n, H_sorted, n, c->L, part, flags);
-    k_validate_final<<<1, 1, 0, c->stream>>>(part, nblk, res);
+    k_validate_final<<<1, 1024, 0, c->stream>>>(part, nblk, res);
     double *pin = (double *)c->pinned.p;
     CRK_HIP(c, hipMemcpyAsync(pin, res, 3 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
     CRK_HIP(c, hipMemcpyAsync(pin + 3, flags, 3 * sizeof(int), hipMemcpyDeviceToHost, c->stream));
