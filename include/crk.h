@@ -364,7 +364,7 @@ crk_status crk_set_walk(crk_ctx *ctx, int32_t lanes, int32_t cap, int32_t level_
  * stream (graph replays are not timed). crk_timing_read synchronises the
  * stream and returns the summed event time (ms) and the launch count for one
  * kernel name ("sort", "k_walk", "k_compact_rows", "k_walk_long",
- * "k_sort_extras", "k_volume", "k_moments", "k_corrections", "k_flag",
+ * "k_extra_rank", "k_volume", "k_moments", "k_corrections", "k_flag",
  * "k_pack", "k_gradv", "k_gradv_fix", "k_deriv", "k_deriv_fix", "k_hsolve",
  * ...); crk_timing_reset clears the sums. */
 crk_status crk_timing_enable(crk_ctx *ctx, int32_t on);
