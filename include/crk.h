@@ -285,6 +285,11 @@ crk_status crk_graph_destroy(crk_ctx *ctx);
  * have stopped are compacted out between rounds, so the time follows the
  * total number of updates rather than the slowest particle of a wavefront;
  * when few particles remain each gets more lanes (up to a wavefront).
+ * Each update sums W over a candidate row (the distances of every j within
+ * a radius above H, rebuilt when H leaves it). A particle whose row does not
+ * fit its slots is moved to a wide pass with a wavefront per particle and
+ * rows of max(4096, 8 cap) slots (up to 65536 particles per launch; that
+ * pool, 2 GiB at most, is part of the context workspace).
  */
 crk_status crk_hsolve(crk_ctx *ctx, double Nres, double tol, int32_t max_iter, double *H_inout,
                       int32_t *iters, int64_t *n_unconverged);
@@ -340,12 +345,12 @@ crk_status crk_export_neighbors(crk_ctx *ctx, int32_t which, int64_t *offsets, i
 crk_status crk_set_lanes(crk_ctx *ctx, int32_t g_vol, int32_t g_mom, int32_t g_grad,
                          int32_t g_der);
 
-/* Tuning of crk_hsolve (results do not depend on it; 0 keeps a value):
- * lanes per particle (a power of two <= 64), updates per round, and the candidate
- * rows built once before the iteration: every j within factor * H_start of
- * i, stored as exact FP64 r^2 in rows of cap slots (cap = -1: no rows; an
- * iterate beyond the row's radius, or a row longer than cap, walks the cells
- * instead). Defaults 4, 8, 320, 1.3. */
+/* Tuning of crk_hsolve (results do not depend on it beyond rounding; 0 keeps
+ * a value): lanes per particle (a power of two <= 64), updates per round, and
+ * the candidate rows: every j within factor * H of i (membership decided on
+ * the exact FP64 r^2), stored as FP64 distances in rows of cap slots, built
+ * again whenever H leaves the row (cap = -1: no rows, every update walks the
+ * cells). Defaults 16, 8, 320, 1.3. */
 crk_status crk_set_hsolve(crk_ctx *ctx, int32_t lanes, int32_t round, int32_t cap,
                           double factor);
 

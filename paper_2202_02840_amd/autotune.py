@@ -23,7 +23,7 @@ from . import pipeline as pl
 HERE = os.path.dirname(os.path.abspath(__file__))
 TABLE = os.path.join(HERE, "tune_table.json")
 
-DEFAULT = {"walk": 8, "walk_level": 0, "vol": 4, "mom": 1, "grad": 4, "der": 8, "hsolve": 8}
+DEFAULT = {"walk": 8, "walk_level": 0, "vol": 4, "mom": 1, "grad": 4, "der": 8, "hsolve": 16}
 CANDIDATES = {
     "walk": (2, 4, 8, 16),
     "walk_level": (0, 1, 2),

@@ -198,7 +198,7 @@ void crk_destroy(crk_ctx *c) {
                        &c->rec6, &c->rec7,  &c->red,   &c->misc, &c->flag, &c->flist,
                        &c->tlist, &c->fpos, &c->tpos,  &c->rec6d, &c->aux, &c->scratch,
                        &c->hnet_part, &c->hnet_feat, &c->hs_list, &c->hs_state, &c->hs_pos,
-                       &c->hs_iters, &c->hs_rows, &c->hs_rcnt, &c->hs_R, &c->boff,
+                       &c->hs_iters, &c->hs_pool, &c->hs_rows, &c->hs_rcnt, &c->hs_R, &c->boff,
                        &c->sv, &c->sm, &c->su, &c->srho, &c->gstat, &c->gboff,
                        &c->ecnt, &c->efill, &c->eoff, &c->etmp};
     crk::graph_release(c);

@@ -172,39 +172,72 @@ __global__ void k_hnet_loss(const float *__restrict__ ploss, int64_t nblk, float
 // Features at radius H (one walk over the support): kernel-weighted counts
 // N_w(h) = (4 pi/3) h^3 sum W(r, h) at h = H, H/2, H/4 and raw counts within
 // H and H/2 (self included), see crk.h for the eight definitions.
+template <int G>
 __global__ __launch_bounds__(kBlock) void k_hnet_features(const double4 *__restrict__ posH,
                                                           const int32_t *__restrict__ cbeg,
                                                           const int32_t *__restrict__ cend, Levels v,
                                                           int64_t n, const double *__restrict__ H,
                                                           double Nres, float *feat) {
-    int64_t i = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
-    if (i >= n) return;
+    // G lanes per particle take each cell's particles G at a time; the five
+    // sums are combined across the group at the end
+    const int64_t gid = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    const int l = (int)(gid % G);
+    const int64_t i = gid / G;
+    if (i >= n) return;   // whole groups leave together
     const double4 pi = posH[i];
     const double h = H[i];
     double s1 = 0.0, s2 = 0.0, s4 = 0.0, c1 = 0.0, c2 = 0.0;
     const double h2 = h * h, ih = 1.0 / h;
-    walk_cells(v, cbeg, cend, i, pi.x, pi.y, pi.z, h, [&](int j) {
-        double4 pj = posH[j];
-        double dx = min_image(pi.x - pj.x, v.L, v.hL);
-        double dy = min_image(pi.y - pj.y, v.L, v.hL);
-        double dz = min_image(pi.z - pj.z, v.L, v.hL);
-        double r2 = r2_exact(dx, dy, dz);
-        if (r2 < h2) {
-            double q = sqrt(r2) * ih;
-            double w1 = 1.0 - q, w1_2 = w1 * w1;
-            s1 += w1_2 * w1_2 * w1_2 * (1.0 + q * (6.0 + q * (35.0 / 3.0)));
-            c1 += 1.0;
-            if (r2 < 0.25 * h2) {
-                double q2 = 2.0 * q, w2 = 1.0 - q2, w2_2 = w2 * w2;
-                s2 += w2_2 * w2_2 * w2_2 * (1.0 + q2 * (6.0 + q2 * (35.0 / 3.0)));
-                c2 += 1.0;
-                if (r2 < 0.0625 * h2) {
-                    double q4 = 4.0 * q, w4 = 1.0 - q4, w4_2 = w4 * w4;
-                    s4 += w4_2 * w4_2 * w4_2 * (1.0 + q4 * (6.0 + q4 * (35.0 / 3.0)));
+    const int k = level_for(h, v);
+    const int nck = 1 << (v.bits - k);
+    Grid g{v.L, v.hL, (double)nck / v.L, v.margin, nck};
+    int lx, ly, lz, mx, my, mz;
+    axis_range(pi.x, h, g, lx, mx);
+    axis_range(pi.y, h, g, ly, my);
+    axis_range(pi.z, h, g, lz, mz);
+    const int64_t base = box_base(v, i) + v.off[k];
+    const int32_t *cb = cbeg + base, *ce = cend + base;
+    for (int a = 0; a < mz; a++) {
+        const uint32_t mzb = spread3(wrapc(lz + a, nck)) << 2;
+        for (int b = 0; b < my; b++) {
+            const uint32_t myb = mzb | (spread3(wrapc(ly + b, nck)) << 1);
+            for (int e = 0; e < mx; e++) {
+                const uint32_t id = myb | spread3(wrapc(lx + e, nck));
+                const int je = ce[id];
+                for (int j = cb[id] + l; j < je; j += G) {
+                    const double4 pj = posH[j];
+                    const double dx = min_image(pi.x - pj.x, v.L, v.hL);
+                    const double dy = min_image(pi.y - pj.y, v.L, v.hL);
+                    const double dz = min_image(pi.z - pj.z, v.L, v.hL);
+                    const double r2 = r2_exact(dx, dy, dz);
+                    if (r2 < h2) {
+                        double q = sqrt(r2) * ih;
+                        double w1 = 1.0 - q, w1_2 = w1 * w1;
+                        s1 += w1_2 * w1_2 * w1_2 * (1.0 + q * (6.0 + q * (35.0 / 3.0)));
+                        c1 += 1.0;
+                        if (r2 < 0.25 * h2) {
+                            double q2 = 2.0 * q, w2 = 1.0 - q2, w2_2 = w2 * w2;
+                            s2 += w2_2 * w2_2 * w2_2 * (1.0 + q2 * (6.0 + q2 * (35.0 / 3.0)));
+                            c2 += 1.0;
+                            if (r2 < 0.0625 * h2) {
+                                double q4 = 4.0 * q, w4 = 1.0 - q4, w4_2 = w4 * w4;
+                                s4 += w4_2 * w4_2 * w4_2 * (1.0 + q4 * (6.0 + q4 * (35.0 / 3.0)));
+                            }
+                        }
+                    }
                 }
             }
         }
-    });
+    }
+#pragma unroll
+    for (int m = G / 2; m >= 1; m >>= 1) {
+        s1 += __shfl_xor(s1, m, G);
+        s2 += __shfl_xor(s2, m, G);
+        s4 += __shfl_xor(s4, m, G);
+        c1 += __shfl_xor(c1, m, G);
+        c2 += __shfl_xor(c2, m, G);
+    }
+    if (l != 0) return;
     // (4 pi/3) h^3 * kW h^-3 sum = (4 pi/3) kW sum, the same at every radius
     const double c = 4.0 / 3.0 * kPi * kW;
     double N1 = c * s1, N2 = c * s2, N4 = c * s4;
@@ -256,7 +289,8 @@ crk_status crk_hnet_features(crk_ctx *c, double Nres, const double *H_sorted, fl
     int64_t n = c->n;
     {
         KTimer kt_(c, "k_hnet_features");
-        k_hnet_features<<<(unsigned)((n + kBlock - 1) / kBlock), kBlock, 0, c->stream>>>(
+        constexpr int GF = 8;
+        k_hnet_features<GF><<<(unsigned)((n * GF + kBlock - 1) / kBlock), kBlock, 0, c->stream>>>(
             (const double4 *)c->posH.p, (const int32_t *)c->cbeg.p, (const int32_t *)c->cend.p,
             levels(c), n, H_sorted, Nres, feat);
     }

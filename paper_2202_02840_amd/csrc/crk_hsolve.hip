@@ -13,6 +13,13 @@
 namespace crk {
 namespace {
 
+// wide-pass rows: up to kPoolRows particles per launch, kPoolCap slots each
+constexpr int64_t kPoolRows = 65536;
+constexpr int kPoolCap = 4096;
+// row slots per lane held in registers by the narrow pass (8 and 16 lanes)
+constexpr int kRegSlots8 = 40;
+constexpr int kRegSlots16 = 20;
+
 // n_i(H) by a group of G lanes: the group walks i's cells together, lanes
 // take a cell's particles G at a time, and the partial sums are combined
 // with cross-lane shuffles (every lane ends with the same total).
@@ -59,10 +66,12 @@ __device__ __forceinline__ double nsum_group(const double4 *__restrict__ posH,
     return kW * invH * invH * invH * s;
 }
 
-// Candidate row of particle i: the exact FP64 r^2 of every j within R (self
-// included), in cell-walk order, in a row of cap slots, by a group of G
-// lanes (a ballot orders the hits). Returns the number of candidates, which
-// exceeds cap when the row could not hold them all.
+// Candidate row of particle i: the distance r of every j within R (self
+// included; membership decided on the exact FP64 r^2), in cell-walk order,
+// in a row of cap slots, by a group of G lanes (a ballot orders the hits).
+// The square root is taken here once, not at every update. Returns the
+// number of candidates, or a number above cap as soon as the row cannot hold
+// them all (the walk stops there).
 template <int G>
 __device__ __forceinline__ int build_row(const double4 *__restrict__ posH,
                                          const int32_t *__restrict__ cbeg,
@@ -105,9 +114,10 @@ __device__ __forceinline__ int build_row(const double4 *__restrict__ posH,
                                         ((G == 64) ? ~0ull : (((uint64_t)1 << G) - 1));
                     if (hit) {
                         int p = c + __popcll(hm & below);
-                        if (p < cap) row[p] = r2;
+                        if (p < cap) row[p] = sqrt(r2);
                     }
                     c += __popcll(hm);
+                    if (c > cap) return c;   // the same for every lane of the group
                 }
             }
         }
@@ -115,97 +125,245 @@ __device__ __forceinline__ int build_row(const double4 *__restrict__ posH,
     return c;
 }
 
-// n_i(H) from a candidate row (valid while H <= the row's radius)
+// Unnormalised C4 weight (1-q)^6 (1 + 6q + 35q^2/3), zero for q >= 1 without
+// a branch (the clamp makes the first factor vanish)
+__device__ __forceinline__ double w_c4(double q) {
+    const double t = fmax(1.0 - q, 0.0), t2 = t * t;
+    return t2 * t2 * t2 * (1.0 + q * (6.0 + q * (35.0 / 3.0)));
+}
+
+// n_i(H) from a candidate row of distances (valid while H <= the row's
+// radius); rows that are not a multiple of 4G long finish one slot at a time
 template <int G>
 __device__ __forceinline__ double nsum_row(const double *__restrict__ row, int c, double H, int l) {
-    const double H2 = H * H, invH = 1.0 / H;
+    const double invH = 1.0 / H;
     double s = 0.0;
-    // four loads in flight per lane: the row streams from memory, so the
-    // latency, not the arithmetic, sets the pace
     int k = l;
     for (; k + 3 * G < c; k += 4 * G) {
-        double r[4] = {row[k], row[k + G], row[k + 2 * G], row[k + 3 * G]};
-#pragma unroll
-        for (int u = 0; u < 4; u++)
-            if (r[u] < H2) {
-                double q = sqrt(r[u]) * invH;
-                double t = 1.0 - q, t2 = t * t;
-                s += t2 * t2 * t2 * (1.0 + q * (6.0 + q * (35.0 / 3.0)));
-            }
+        const double r0 = row[k], r1 = row[k + G], r2 = row[k + 2 * G], r3 = row[k + 3 * G];
+        s += (w_c4(r0 * invH) + w_c4(r1 * invH)) + (w_c4(r2 * invH) + w_c4(r3 * invH));
     }
-    for (; k < c; k += G) {
-        double r2 = row[k];
-        if (r2 < H2) {
-            double q = sqrt(r2) * invH;
-            double t = 1.0 - q, t2 = t * t;
-            s += t2 * t2 * t2 * (1.0 + q * (6.0 + q * (35.0 / 3.0)));
-        }
-    }
+    for (; k < c; k += G) s += w_c4(row[k] * invH);
 #pragma unroll
     for (int m = G / 2; m >= 1; m >>= 1) s += __shfl_xor(s, m, G);
     return kW * invH * invH * invH * s;
 }
 
-// One round: each listed particle takes up to R more updates of eq. (thacker)
-// from its stored state. state[i]: 0 running, 1 converged, 2 hit max_iter,
-// 3 support reached L/2.
-template <int G>
-__global__ __launch_bounds__(kBlock) void k_hsolve_round(const double4 *__restrict__ posH,
-                                                         const int32_t *__restrict__ cbeg,
-                                                         const int32_t *__restrict__ cend, Levels v,
-                                                         const int32_t *__restrict__ list, int64_t m,
-                                                         double Nres, double tol, int max_iter, int R,
-                                                         double *rows, int32_t *rcnt, double *Rlist,
-                                                         int cap, double f, double *H_io,
-                                                         int32_t *iters, int32_t *state) {
-    int64_t gid = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
-    const int l = (int)(gid % G);
-    const int64_t k = gid / G;
-    if (k >= m) return;
-    const int64_t i = list[k];
-    const double4 pi = posH[i];
-    double H = H_io[i];
-    int it = iters[i];
-    int st = 0;
-    int c = rows ? rcnt[i] : cap + 1;
-    double Rmax = rows ? Rlist[i] : 0.0;
-    double *row = rows ? rows + (size_t)i * cap : nullptr;
-    // a support that left its candidate row (or has none yet) gets a new
-    // row at f H, which serves every later update with H <= f H without a
-    // cell walk; when f H holds more candidates than the row, a row just
-    // past H is tried (it still serves the updates that shrink H)
-    if (rows && !(c <= cap && H <= Rmax)) {
-        Rmax = f * H;
-        c = build_row<G>(posH, cbeg, cend, v, i, pi, Rmax, cap, row, l);
-        if (c > cap && f > 1.02) {
-            Rmax = 1.02 * H;
-            c = build_row<G>(posH, cbeg, cend, v, i, pi, Rmax, cap, row, l);
-        }
-        if (l == 0) {
-            rcnt[i] = c;
-            Rlist[i] = Rmax;
-        }
-    }
+// Everything a round needs besides its list (kernel argument by value)
+struct HsArgs {
+    const double4 *posH;
+    const int32_t *cbeg, *cend;
+    Levels v;
+    double Nres, tol, f;
+    int max_iter, cap;
+    double *rows;   // n rows of cap slots (nullptr: no rows, every update walks)
+    int32_t *rcnt;
+    double *Rlist;
+    double *H;
+    int32_t *iters, *state;
+};
+
+// Takes updates of eq. (thacker) from H until stop or R updates; returns the
+// state (0 running, 1 converged, 2 hit max_iter, 3 support reached L/2).
+// NS(H) gives n_i(H) and is the only part that differs between passes.
+template <typename NSum>
+__device__ __forceinline__ int thacker_updates(const HsArgs &a, double &H, int &it, int R,
+                                               double Rmax, bool stop_outside, NSum &&NS) {
     for (int r = 0; r < R; r++) {
-        // the candidate row holds every j within Rmax, so it answers any H <= Rmax
-        double ns = (c <= cap && H <= Rmax) ? nsum_row<G>(row, c, H, l)
-                                            : nsum_group<G>(posH, cbeg, cend, v, i, pi, H, l);
-        double N = (4.0 * kPi / 3.0) * H * H * H * ns;
-        double D = cbrt(Nres / N);
-        double lam = D < 1.0 ? 0.2 * (1.0 + D * D) : 0.2 * (1.0 + 1.0 / (D * D * D));
-        double Hn = H * (1.0 - lam + lam * D);
+        if (stop_outside && !(H <= Rmax)) return 0;   // a new row next round
+        const double ns = NS(H);
+        const double N = (4.0 * kPi / 3.0) * H * H * H * ns;
+        const double D = cbrt(a.Nres / N);
+        const double lam = D < 1.0 ? 0.2 * (1.0 + D * D) : 0.2 * (1.0 + 1.0 / (D * D * D));
+        const double Hn = H * (1.0 - lam + lam * D);
         it++;
-        bool done = fabs(Hn - H) <= tol * H;
+        const bool done = fabs(Hn - H) <= a.tol * H;
         H = Hn;
-        if (!(H < v.hL)) { st = 3; break; }
-        if (done) { st = 1; break; }
-        if (it >= max_iter) { st = 2; break; }
+        if (!(H < a.v.hL)) return 3;
+        if (done) return 1;
+        if (it >= a.max_iter) return 2;
     }
+    return 0;
+}
+
+// A row at f H for particle i (which then serves every update with H <= f H
+// without a cell walk); when f H holds more candidates than the row, a row
+// just past H is tried (it still serves the updates that shrink H).
+template <int G>
+__device__ __forceinline__ int make_row(const HsArgs &a, int64_t i, const double4 &pi, double H,
+                                        int rcap, double *row, double &Rmax, int l) {
+    Rmax = a.f * H;
+    int c = build_row<G>(a.posH, a.cbeg, a.cend, a.v, i, pi, Rmax, rcap, row, l);
+    if (c > rcap && a.f > 1.02) {
+        Rmax = 1.02 * H;
+        c = build_row<G>(a.posH, a.cbeg, a.cend, a.v, i, pi, Rmax, rcap, row, l);
+    }
+    return c;
+}
+
+// One round of list[k] with G lanes per particle (state 4: running, but its
+// support holds more candidates than a row of cap slots).
+//
+// Narrow pass (pool == nullptr, defer set): rows of cap slots kept per
+// particle across rounds. A particle never walks the cells here: when its
+// row cannot be built it is handed to the wide pass (state 4), and when H
+// leaves its row it stops for this round (the next round rebuilds the row),
+// so no group holds up the launch with a long walk.
+// Wide pass (pool set, 64 lanes): a row of pcap slots per listed particle,
+// built at the start of every round in pool[k]; a support beyond even that
+// row walks the cells at every update. A particle goes back to the narrow
+// pass once its row fits cap slots.
+// Neither (no rows, or the tail where a particle has a wavefront): rows kept
+// as in the narrow pass, cell walks where a row does not serve.
+template <int G>
+__device__ __forceinline__ void round_body(const HsArgs &a, const int32_t *__restrict__ list,
+                                           int64_t k, int l, int R, double *pool, int pcap,
+                                           int defer) {
+    const int64_t i = list[k];
+    const double4 pi = a.posH[i];
+    double H = a.H[i];
+    int it = a.iters[i];
+    int c, rcap;
+    double Rmax;
+    double *row;
+    if (pool) {
+        rcap = pcap;
+        row = pool + (size_t)k * pcap;
+        c = rcap + 1;
+        Rmax = 0.0;
+    } else {
+        rcap = a.cap;
+        row = a.rows ? a.rows + (size_t)i * a.cap : nullptr;
+        c = a.rows ? a.rcnt[i] : a.cap + 1;
+        Rmax = a.rows ? a.Rlist[i] : 0.0;
+    }
+    if (row && !(c <= rcap && H <= Rmax)) {
+        c = make_row<G>(a, i, pi, H, rcap, row, Rmax, l);
+        if (l == 0 && !pool) {
+            a.rcnt[i] = c;
+            a.Rlist[i] = Rmax;
+        }
+    }
+    if (defer && c > rcap) {
+        if (l == 0) a.state[i] = 4;
+        return;
+    }
+    int st = thacker_updates(a, H, it, R, Rmax, defer != 0, [&](double h) {
+        // the candidate row holds every j within Rmax, so it answers any h <= Rmax
+        return (c <= rcap && h <= Rmax) ? nsum_row<G>(row, c, h, l)
+                                        : nsum_group<G>(a.posH, a.cbeg, a.cend, a.v, i, pi, h, l);
+    });
+    // still running: the wide pass keeps a support that a narrow row cannot hold
+    if (a.rows && st == 0 && c > a.cap) st = 4;
     if (l == 0) {
-        H_io[i] = H;
-        iters[i] = it;
-        state[i] = st;
+        a.H[i] = H;
+        a.iters[i] = it;
+        a.state[i] = st;
     }
+}
+
+// One lane's FP64 value from lane CTRL-selected within its DPP row (both
+// 32-bit halves moved; every source lane lies in the row)
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double x) {
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(x), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(x), CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
+// Sum over an aligned group of G = 8 or 16 lanes; every lane ends with the
+// same total (each step adds commuting pairs): swap neighbours, swap pairs,
+// mirror the 8-lane halves, mirror the 16-lane row
+template <int G>
+__device__ __forceinline__ double group_sum(double s) {
+    static_assert(G == 8 || G == 16, "DPP group sum covers 8 or 16 lanes");
+    s += dpp_f64<0xB1>(s);   // quad_perm(1,0,3,2)
+    s += dpp_f64<0x4E>(s);   // quad_perm(2,3,0,1)
+    s += dpp_f64<0x141>(s);  // row_half_mirror
+    if constexpr (G == 16) s += dpp_f64<0x140>(s);  // row_mirror
+    return s;
+}
+
+// Narrow pass with the row held in registers: the round loads each
+// particle's row once (slot s of lane l holds candidate s G + l, empty slots
+// a distance of 2 Rmax, whose weight is zero) and every update sums from
+// registers; the same hand-over rules as the narrow pass of round_body.
+template <int G, int S>
+__device__ __forceinline__ void narrow_body(const HsArgs &a, const int32_t *__restrict__ list,
+                                            int64_t k, int l, int R) {
+    const int64_t i = list[k];
+    const double4 pi = a.posH[i];
+    double H = a.H[i];
+    int it = a.iters[i];
+    int c = a.rcnt[i];
+    double Rmax = a.Rlist[i];
+    double *row = a.rows + (size_t)i * a.cap;
+    if (!(c <= a.cap && H <= Rmax)) {
+        c = make_row<G>(a, i, pi, H, a.cap, row, Rmax, l);
+        if (l == 0) {
+            a.rcnt[i] = c;
+            a.Rlist[i] = Rmax;
+        }
+    }
+    if (c > a.cap) {
+        if (l == 0) a.state[i] = 4;
+        return;
+    }
+    double rr[S];
+    const double pad = 2.0 * Rmax;
+#pragma unroll
+    for (int s = 0; s < S; s++) {
+        const int q = s * G + l;
+        rr[s] = q < c ? row[q] : pad;
+    }
+    const int st = thacker_updates(a, H, it, R, Rmax, true, [&](double h) {
+        const double invH = 1.0 / h;
+        double acc = 0.0;
+#pragma unroll
+        for (int s = 0; s < S; s++) {
+            if (!__any(s * G < c)) break;
+            acc += w_c4(rr[s] * invH);
+        }
+        return kW * invH * invH * invH * group_sum<G>(acc);
+    });
+    if (l == 0) {
+        a.H[i] = H;
+        a.iters[i] = it;
+        a.state[i] = st;
+    }
+}
+
+template <int G>
+__global__ __launch_bounds__(kBlock) void k_hsolve_round(HsArgs a, const int32_t *__restrict__ list,
+                                                         int64_t m, int R, double *pool, int pcap,
+                                                         int defer) {
+    const int64_t gid = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    const int64_t k = gid / G;
+    if (k >= m) return;   // whole groups leave together
+    round_body<G>(a, list, k, (int)(gid % G), R, pool, pcap, defer);
+}
+
+// One launch for both passes: the first nbw blocks (a multiple of 8, so the
+// XCD of a narrow block is the one xcd_block assumes) take the wide list with
+// a wavefront per particle and are dispatched first, since their particles
+// are the slow ones; the other blocks take the narrow list with register
+// rows. The two lists hold different particles.
+template <int G, int S>
+__global__ __launch_bounds__(kBlock) void k_hsolve_both(HsArgs a, const int32_t *__restrict__ ln,
+                                                        int64_t mn, int Rn, const int32_t *__restrict__ lw,
+                                                        int64_t mw, int Rw, int64_t nbw, double *pool,
+                                                        int pcap) {
+    if ((int64_t)blockIdx.x < nbw) {
+        const int64_t gid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+        const int64_t k = gid / 64;
+        if (k >= mw) return;
+        round_body<64>(a, lw, k, (int)(gid % 64), Rw, pool, pcap, 0);
+        return;
+    }
+    const int64_t gid = xcd_block(blockIdx.x - nbw, gridDim.x - nbw) * kBlock + threadIdx.x;
+    const int64_t k = gid / G;
+    if (k >= mn) return;
+    narrow_body<G, S>(a, ln, k, (int)(gid % G), Rn);
 }
 
 __global__ __launch_bounds__(kBlock) void k_hs_init(int64_t n, int32_t *list, int32_t *iters, int32_t *state,
@@ -218,18 +376,26 @@ __global__ __launch_bounds__(kBlock) void k_hs_init(int64_t n, int32_t *list, in
     if (rcnt) rcnt[i] = cap + 1;   // no candidate row yet
 }
 
-// running[k] = 1 when list[k] is still running (for the compaction scan)
+// run[k]: 1 when list[k] runs on in the narrow pass, 1 << 32 when it runs on
+// in the wide pass (one scan then counts both classes)
 __global__ __launch_bounds__(kBlock) void k_hs_running(const int32_t *__restrict__ list, int64_t m,
                                                        const int32_t *__restrict__ state, int64_t *run) {
     int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (k < m) run[k] = state[list[k]] == 0;
+    if (k < m) {
+        const int s = state[list[k]];
+        run[k] = s == 0 ? 1 : (s == 4 ? ((int64_t)1 << 32) : 0);
+    }
     if (k == m) run[m] = 0;
 }
 
+// running particles to out: the narrow ones first, then the wide ones
 __global__ __launch_bounds__(kBlock) void k_hs_compact(const int32_t *__restrict__ list, int64_t m,
                                                        const int64_t *__restrict__ pos, int32_t *out) {
     int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (k < m && pos[k + 1] != pos[k]) out[pos[k]] = list[k];
+    if (k >= m) return;
+    const int64_t d = pos[k + 1] - pos[k];
+    if (d == 1) out[pos[k] & 0xffffffff] = list[k];
+    else if (d != 0) out[(pos[m] & 0xffffffff) + (pos[k] >> 32)] = list[k];
 }
 
 __global__ __launch_bounds__(kBlock) void k_hs_count(const int32_t *__restrict__ state, int64_t n,
@@ -247,6 +413,38 @@ __global__ __launch_bounds__(kBlock) void k_set_H2(double4 *posH, const double *
 }
 
 }  // namespace
+
+// one round over list[0..m) with G lanes per particle
+static crk_status hsolve_round(crk_ctx *c, const HsArgs &a, int G, const int32_t *list, int64_t m,
+                               int R, double *pool, int pcap, int defer) {
+    const unsigned nb = (unsigned)((m * G + kBlock - 1) / kBlock);
+    switch (G) {
+        case 1: k_hsolve_round<1><<<nb, kBlock, 0, c->stream>>>(a, list, m, R, pool, pcap, defer); break;
+        case 2: k_hsolve_round<2><<<nb, kBlock, 0, c->stream>>>(a, list, m, R, pool, pcap, defer); break;
+        case 4: k_hsolve_round<4><<<nb, kBlock, 0, c->stream>>>(a, list, m, R, pool, pcap, defer); break;
+        case 8: k_hsolve_round<8><<<nb, kBlock, 0, c->stream>>>(a, list, m, R, pool, pcap, defer); break;
+        case 16: k_hsolve_round<16><<<nb, kBlock, 0, c->stream>>>(a, list, m, R, pool, pcap, defer); break;
+        case 32: k_hsolve_round<32><<<nb, kBlock, 0, c->stream>>>(a, list, m, R, pool, pcap, defer); break;
+        case 64: k_hsolve_round<64><<<nb, kBlock, 0, c->stream>>>(a, list, m, R, pool, pcap, defer); break;
+        default: return set_err(c, CRK_ERR_INVALID_ARG, "hsolve lanes must be a power of two <= 64");
+    }
+    CRK_HIP(c, hipGetLastError());
+    return CRK_OK;
+}
+
+// both passes of a round in one launch (register rows of S slots for the
+// narrow one); mw <= kPoolRows
+template <int G, int S>
+static crk_status hsolve_both(crk_ctx *c, const HsArgs &a, const int32_t *ln, int64_t mn, int Rn,
+                              const int32_t *lw, int64_t mw, int Rw, double *pool, int pcap) {
+    const int64_t nbw = (mw * 64 + kBlock - 1) / kBlock;
+    const int64_t nbw8 = (nbw + 7) / 8 * 8;
+    const int64_t nbn = (mn * G + kBlock - 1) / kBlock;
+    k_hsolve_both<G, S><<<(unsigned)(nbw8 + nbn), kBlock, 0, c->stream>>>(a, ln, mn, Rn, lw, mw, Rw,
+                                                                         nbw8, pool, pcap);
+    CRK_HIP(c, hipGetLastError());
+    return CRK_OK;
+}
 }  // namespace crk
 
 using namespace crk;
@@ -290,29 +488,41 @@ crk_status crk_hsolve(crk_ctx *c, double Nres, double tol, int32_t max_iter, dou
     }
     k_hs_init<<<nb, kBlock, 0, c->stream>>>(n, la, it, state, rcnt, cap);
     CRK_HIP(c, hipGetLastError());
-    int64_t m = n;
+    int64_t mn = n, mw = 0;   // narrow and wide particles still running
+    const int pcap = kPoolCap < 8 * cap ? 8 * cap : kPoolCap;
+    const HsArgs a{(const double4 *)c->posH.p, (const int32_t *)c->cbeg.p, (const int32_t *)c->cend.p,
+                   v, Nres, tol, c->hs_factor, max_iter, cap, rows, rcnt, Rl, H_inout, it, state};
     int64_t *pin = (int64_t *)c->pinned.p + 24;
     const int G = c->G_hsolve;
     {
         KTimer kt_(c, "k_hsolve");
-        while (m > 0) {
+        while (mn + mw > 0) {
             // few particles left (the slowly contracting tail): give each one
             // more lanes so the device stays busy, and run longer rounds
             int Gr = G;
-            while (Gr < 64 && m * Gr < (int64_t)1 << 19) Gr *= 2;
-            const int R = Gr > G ? 4 * c->hs_round : c->hs_round;
-#define L_HS(GG) k_hsolve_round<GG><<<(unsigned)((m * GG + kBlock - 1) / kBlock), kBlock, 0, c->stream>>>((const double4 *)c->posH.p, (const int32_t *)c->cbeg.p, (const int32_t *)c->cend.p, v, la, m, Nres, tol, max_iter, R, rows, rcnt, Rl, cap, c->hs_factor, H_inout, it, state)
-            switch (Gr) {
-                case 1: L_HS(1); break;
-                case 2: L_HS(2); break;
-                case 4: L_HS(4); break;
-                case 8: L_HS(8); break;
-                case 16: L_HS(16); break;
-                case 32: L_HS(32); break;
-                case 64: L_HS(64); break;
-                default: return set_err(c, CRK_ERR_INVALID_ARG, "hsolve lanes must be a power of two <= 64");
+            while (Gr < 64 && mn * Gr < (int64_t)1 << 19) Gr *= 2;
+            const int Rn = Gr > G ? 4 * c->hs_round : c->hs_round;
+            // the wide pass runs longer rounds: its particles are few and slow
+            const int Rw = 4 * c->hs_round;
+            const int64_t mw0 = mw < kPoolRows ? mw : kPoolRows;   // wide particles in the first launch
+            if (mw0 > 0) CRK_TRY(ensure(c, c->hs_pool, (size_t)mw0 * pcap * sizeof(double)));
+            double *pool = (double *)c->hs_pool.p;
+            const bool reg8 = rows && Gr == 8 && cap <= 8 * kRegSlots8;
+            const bool reg16 = rows && Gr == 16 && cap <= 16 * kRegSlots16;
+            if (mn > 0 && reg8)
+                CRK_TRY((hsolve_both<8, kRegSlots8>(c, a, la, mn, Rn, la + mn, mw0, Rw, pool, pcap)));
+            else if (mn > 0 && reg16)
+                CRK_TRY((hsolve_both<16, kRegSlots16>(c, a, la, mn, Rn, la + mn, mw0, Rw, pool, pcap)));
+            else {
+                if (mn > 0) CRK_TRY(hsolve_round(c, a, Gr, la, mn, Rn, nullptr, 0, rows && Gr < 64));
+                if (mw0 > 0) CRK_TRY(hsolve_round(c, a, 64, la + mn, mw0, Rw, pool, pcap, 0));
             }
-#undef L_HS
+            // wide particles beyond the pool: further launches reusing it
+            for (int64_t w0 = mw0; w0 < mw; w0 += kPoolRows) {
+                const int64_t mc = mw - w0 < kPoolRows ? mw - w0 : kPoolRows;
+                CRK_TRY(hsolve_round(c, a, 64, la + mn + w0, mc, Rw, pool, pcap, 0));
+            }
+            const int64_t m = mn + mw;
             const unsigned mb = (unsigned)((m + 1 + kBlock - 1) / kBlock);
             k_hs_running<<<mb, kBlock, 0, c->stream>>>(la, m, state, pos);
             CRK_TRY(scan_exclusive_i64(c, pos, pos, m + 1));
@@ -320,7 +530,8 @@ crk_status crk_hsolve(crk_ctx *c, double Nres, double tol, int32_t max_iter, dou
             CRK_HIP(c, hipGetLastError());
             CRK_HIP(c, hipMemcpyAsync(pin, pos + m, sizeof(int64_t), hipMemcpyDeviceToHost, c->stream));
             CRK_HIP(c, hipStreamSynchronize(c->stream));
-            m = pin[0];
+            mn = pin[0] & 0xffffffff;
+            mw = pin[0] >> 32;
             int32_t *t = la;
             la = lb;
             lb = t;

@@ -74,7 +74,7 @@ struct crk_ctx {
     crk::Buf flag, flist, tlist, fpos, tpos, rec6d, aux;   // adaptive-precision rows
     crk::Buf scratch;                                     // walk rows before compaction
     crk::Buf hnet_part, hnet_feat;                        // network gradients / features
-    crk::Buf hs_list, hs_state, hs_pos, hs_iters;         // smoothing-length rounds
+    crk::Buf hs_list, hs_state, hs_pos, hs_iters, hs_pool;   // smoothing-length rounds
     crk::Buf hs_rows, hs_rcnt, hs_R;                      // candidate rows (r^2)
     crk::Buf boff;                                        // batch box offsets
     crk::Buf sv, sm, su, srho;                            // sorted gas state (crk_step)
@@ -96,7 +96,7 @@ struct crk_ctx {
         double L, cell;
         int nc, bits;
     } geo{};                              // geometry the graph was recorded with
-    int G_hsolve = 8, hs_round = 8, hs_cap = 320;
+    int G_hsolve = 16, hs_round = 8, hs_cap = 320;
     double hs_factor = 1.3;
     int64_t last_nflag = 0, last_ntouch = 0;
     crk::Buf pinned;        // small host-pinned readback area

@@ -50,6 +50,25 @@ def test_hsolve_matches_oracle(name, make, tune):
     assert np.abs(it - itref).max() <= 1
 
 
+def test_hsolve_narrow_and_wide_passes_match_oracle():
+    """A clustered set large enough that the iteration starts with 8 lanes per
+    particle: particles whose candidate row overflows are handed to the wide
+    pass (a wavefront per particle, pool rows) and back; with a short row
+    (cap 96) most of them go through it. Register rows (16 and 8 lanes, one
+    launch for both passes) and memory rows (32 lanes, two launches) all
+    match the oracle."""
+    ps = ci.lognormal_box(48, sigma=2.0, seed=305)
+    print(f"[case] hsolve narrow/wide n={ps.n}", flush=True)
+    Href, itref, nf = oracle.hsolve(ps.x, ps.y, ps.z, ps.H, 64.0, tol=1e-7, max_iter=1000)
+    assert nf == 0
+    for tune in (None, (8, 8, 96, 1.3), (32, 8, 320, 1.3)):
+        H, it, nun, _ = _gpu_hsolve(ps, 64.0, max_iter=1000, tune=tune)
+        print(tune, "max rel", float(np.abs(H / Href - 1).max()), flush=True)
+        assert nun == 0
+        assert np.abs(H / Href - 1).max() < 1e-6
+        assert np.abs(it - itref).max() <= 1
+
+
 def test_update_support_rebuilds_lists():
     """After crk_update_support with new support radii (the oracle's converged
     H), the pair lists equal the oracle's for those radii."""
