@@ -290,19 +290,6 @@ __device__ __forceinline__ void walk_row(const double4 *__restrict__ posH, int64
 // then takes the concatenated candidates G at a time across cell
 // boundaries. The candidate order, hence every row, is the same as the
 // cell-by-cell walk's.
-constexpr int kRanges = 32;
-
-template <int G>
-__device__ __forceinline__ int group_excl_scan(int x, int l, int &total) {
-    int inc = x;
-#pragma unroll
-    for (int o = 1; o < G; o <<= 1) {
-        int t = __shfl_up(inc, o, G);
-        if (l >= o) inc += t;
-    }
-    total = __shfl(inc, G - 1, G);
-    return inc - x;
-}
 
 template <int G, bool DIRECT, bool CULL>
 __device__ __forceinline__ void walk_row_flat(const double4 *__restrict__ posH, int64_t i,

@@ -178,7 +178,7 @@ __global__ __launch_bounds__(kBlock) void k_hnet_features(const double4 *__restr
                                                           const int32_t *__restrict__ cend, Levels v,
                                                           int64_t n, const double *__restrict__ H,
                                                           double Nres, float *feat) {
-    // G lanes per particle take each cell's particles G at a time; the five
+    // G lanes per particle share a flattened walk of the support; the five
     // sums are combined across the group at the end
     const int64_t gid = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
     const int l = (int)(gid % G);
@@ -188,47 +188,27 @@ __global__ __launch_bounds__(kBlock) void k_hnet_features(const double4 *__restr
     const double h = H[i];
     double s1 = 0.0, s2 = 0.0, s4 = 0.0, c1 = 0.0, c2 = 0.0;
     const double h2 = h * h, ih = 1.0 / h;
-    const int k = level_for(h, v);
-    const int nck = 1 << (v.bits - k);
-    Grid g{v.L, v.hL, (double)nck / v.L, v.margin, nck};
-    int lx, ly, lz, mx, my, mz;
-    axis_range(pi.x, h, g, lx, mx);
-    axis_range(pi.y, h, g, ly, my);
-    axis_range(pi.z, h, g, lz, mz);
-    const int64_t base = box_base(v, i) + v.off[k];
-    const int32_t *cb = cbeg + base, *ce = cend + base;
-    for (int a = 0; a < mz; a++) {
-        const uint32_t mzb = spread3(wrapc(lz + a, nck)) << 2;
-        for (int b = 0; b < my; b++) {
-            const uint32_t myb = mzb | (spread3(wrapc(ly + b, nck)) << 1);
-            for (int e = 0; e < mx; e++) {
-                const uint32_t id = myb | spread3(wrapc(lx + e, nck));
-                const int je = ce[id];
-                for (int j = cb[id] + l; j < je; j += G) {
-                    const double4 pj = posH[j];
-                    const double dx = min_image(pi.x - pj.x, v.L, v.hL);
-                    const double dy = min_image(pi.y - pj.y, v.L, v.hL);
-                    const double dz = min_image(pi.z - pj.z, v.L, v.hL);
-                    const double r2 = r2_exact(dx, dy, dz);
-                    if (r2 < h2) {
-                        double q = sqrt(r2) * ih;
-                        double w1 = 1.0 - q, w1_2 = w1 * w1;
-                        s1 += w1_2 * w1_2 * w1_2 * (1.0 + q * (6.0 + q * (35.0 / 3.0)));
-                        c1 += 1.0;
-                        if (r2 < 0.25 * h2) {
-                            double q2 = 2.0 * q, w2 = 1.0 - q2, w2_2 = w2 * w2;
-                            s2 += w2_2 * w2_2 * w2_2 * (1.0 + q2 * (6.0 + q2 * (35.0 / 3.0)));
-                            c2 += 1.0;
-                            if (r2 < 0.0625 * h2) {
-                                double q4 = 4.0 * q, w4 = 1.0 - q4, w4_2 = w4 * w4;
-                                s4 += w4_2 * w4_2 * w4_2 * (1.0 + q4 * (6.0 + q4 * (35.0 / 3.0)));
-                            }
-                        }
-                    }
+    __shared__ int32_t s_b[kBlock / G][kRanges], s_c[kBlock / G][kRanges + 1], s_o[kBlock / G][kRanges];
+    const int grp = threadIdx.x / G;
+    flat_candidates<G>(posH, cbeg, cend, v, i, pi, h, l, s_b[grp], s_c[grp], s_o[grp],
+                       [&](bool valid, double r2) {
+        if (valid && r2 < h2) {
+            double q = sqrt(r2) * ih;
+            double w1 = 1.0 - q, w1_2 = w1 * w1;
+            s1 += w1_2 * w1_2 * w1_2 * (1.0 + q * (6.0 + q * (35.0 / 3.0)));
+            c1 += 1.0;
+            if (r2 < 0.25 * h2) {
+                double q2 = 2.0 * q, w2 = 1.0 - q2, w2_2 = w2 * w2;
+                s2 += w2_2 * w2_2 * w2_2 * (1.0 + q2 * (6.0 + q2 * (35.0 / 3.0)));
+                c2 += 1.0;
+                if (r2 < 0.0625 * h2) {
+                    double q4 = 4.0 * q, w4 = 1.0 - q4, w4_2 = w4 * w4;
+                    s4 += w4_2 * w4_2 * w4_2 * (1.0 + q4 * (6.0 + q4 * (35.0 / 3.0)));
                 }
             }
         }
-    }
+        return false;
+    });
 #pragma unroll
     for (int m = G / 2; m >= 1; m >>= 1) {
         s1 += __shfl_xor(s1, m, G);

@@ -125,6 +125,34 @@ __device__ __forceinline__ int build_row(const double4 *__restrict__ posH,
     return c;
 }
 
+// The same row by the flattened walk (flat_candidates): the loads of
+// different cells overlap. Candidate order differs from build_row; the rows
+// hold the same set.
+template <int G>
+__device__ __forceinline__ int build_row_flat(const double4 *__restrict__ posH,
+                                              const int32_t *__restrict__ cbeg,
+                                              const int32_t *__restrict__ cend, const Levels &v,
+                                              int64_t i, const double4 &pi, double R, int cap,
+                                              double *row, int l, int32_t *sb, int32_t *sc,
+                                              int32_t *so) {
+    const double R2 = R * R;
+    const int gshift = (threadIdx.x & 63) - l;
+    const uint64_t gmask = ((uint64_t)1 << G) - 1;
+    const uint64_t below = ((uint64_t)1 << l) - 1;
+    int c = 0;
+    flat_candidates<G>(posH, cbeg, cend, v, i, pi, R, l, sb, sc, so, [&](bool valid, double r2) {
+        const bool hit = valid && r2 < R2;
+        const uint64_t hm = (__ballot(hit) >> gshift) & gmask;
+        if (hit) {
+            const int p = c + __popcll(hm & below);
+            if (p < cap) row[p] = sqrt(r2);
+        }
+        c += __popcll(hm);
+        return c > cap;   // the same for every lane of the group
+    });
+    return c;
+}
+
 // Unnormalised C4 weight (1-q)^6 (1 + 6q + 35q^2/3), zero for q >= 1 without
 // a branch (the clamp makes the first factor vanish)
 __device__ __forceinline__ double w_c4(double q) {
@@ -189,14 +217,23 @@ __device__ __forceinline__ int thacker_updates(const HsArgs &a, double &H, int &
 // A row at f H for particle i (which then serves every update with H <= f H
 // without a cell walk); when f H holds more candidates than the row, a row
 // just past H is tried (it still serves the updates that shrink H).
-template <int G>
+// (FLAT: the flattened walk, with the group's LDS lists sb, sc, so)
+template <int G, bool FLAT = false>
 __device__ __forceinline__ int make_row(const HsArgs &a, int64_t i, const double4 &pi, double H,
-                                        int rcap, double *row, double &Rmax, int l) {
+                                        int rcap, double *row, double &Rmax, int l,
+                                        int32_t *sb = nullptr, int32_t *sc = nullptr,
+                                        int32_t *so = nullptr) {
+    auto build = [&](double R) {
+        if constexpr (FLAT)
+            return build_row_flat<G>(a.posH, a.cbeg, a.cend, a.v, i, pi, R, rcap, row, l, sb, sc, so);
+        else
+            return build_row<G>(a.posH, a.cbeg, a.cend, a.v, i, pi, R, rcap, row, l);
+    };
     Rmax = a.f * H;
-    int c = build_row<G>(a.posH, a.cbeg, a.cend, a.v, i, pi, Rmax, rcap, row, l);
+    int c = build(Rmax);
     if (c > rcap && a.f > 1.02) {
         Rmax = 1.02 * H;
-        c = build_row<G>(a.posH, a.cbeg, a.cend, a.v, i, pi, Rmax, rcap, row, l);
+        c = build(Rmax);
     }
     return c;
 }
@@ -299,7 +336,10 @@ __device__ __forceinline__ void narrow_body(const HsArgs &a, const int32_t *__re
     double Rmax = a.Rlist[i];
     double *row = a.rows + (size_t)i * a.cap;
     if (!(c <= a.cap && H <= Rmax)) {
-        c = make_row<G>(a, i, pi, H, a.cap, row, Rmax, l);
+        __shared__ int32_t s_b[kBlock / G][kRanges], s_c[kBlock / G][kRanges + 1],
+            s_o[kBlock / G][kRanges];
+        const int grp = (threadIdx.x & (kBlock - 1)) / G;
+        c = make_row<G, true>(a, i, pi, H, a.cap, row, Rmax, l, s_b[grp], s_c[grp], s_o[grp]);
         if (l == 0) {
             a.rcnt[i] = c;
             a.Rlist[i] = Rmax;

@@ -97,7 +97,7 @@ struct crk_ctx {
         int nc, bits;
     } geo{};                              // geometry the graph was recorded with
     int G_hsolve = 16, hs_round = 8, hs_cap = 320;
-    double hs_factor = 1.3;
+    double hs_factor = 1.15;
     int64_t last_nflag = 0, last_ntouch = 0;
     crk::Buf pinned;        // small host-pinned readback area
 
@@ -199,6 +199,22 @@ __device__ __forceinline__ double cell_gap(double p, int k, double cs) {
     return fmax(0.0, fmax(lo - p, p - hi));
 }
 
+// cell ranges a lane group lists in LDS at a time in the flattened walks
+constexpr int kRanges = 32;
+
+// exclusive prefix sum of x over a group of G lanes (total to every lane)
+template <int G>
+__device__ __forceinline__ int group_excl_scan(int x, int l, int &total) {
+    int inc = x;
+#pragma unroll
+    for (int o = 1; o < G; o <<= 1) {
+        int t = __shfl_up(inc, o, G);
+        if (l >= o) inc += t;
+    }
+    total = __shfl(inc, G - 1, G);
+    return inc - x;
+}
+
 // periodic cell index: every level has a power-of-two number of cells a
 // side, so the wrap is a mask (two's complement keeps it right for a < 0)
 __device__ __forceinline__ int wrapc(int a, int nc) { return a & (nc - 1); }
@@ -244,6 +260,126 @@ __device__ __forceinline__ int level_for(double R, const Levels &v) {
     }
     return k;
 }
+
+// Flattened walk of the cells that a sphere of radius R about particle i
+// overlaps, by an aligned group of G lanes (4 <= G <= kRanges) of one
+// wavefront. The group lists its cells as ranges of sorted particles in
+// LDS (sb: first particle, sc: offset in the concatenation, so: image
+// code; kRanges at a time), skipping cells wholly outside R when the range
+// stays within half a period (then each listed cell carries the image shift
+// of all its particles), and then takes the concatenated candidates G at a
+// time across cell boundaries, so the loads of different cells overlap.
+// visit(valid, r2) sees every batch on every lane (valid false past the
+// end; r2 the exact FP64 minimum-image r^2 with i itself included) and
+// returns true to stop the walk; its value must be the same on every lane
+// of the group.
+template <int G, typename Visit>
+__device__ __forceinline__ void flat_candidates(const double4 *__restrict__ posH,
+                                                const int32_t *__restrict__ cbeg,
+                                                const int32_t *__restrict__ cend, const Levels &v,
+                                                int64_t i, const double4 &pi, double R, int l,
+                                                int32_t *sb, int32_t *sc, int32_t *so,
+                                                Visit &&visit) {
+    static_assert(G >= 4 && G <= kRanges, "the flattened walk needs 4..kRanges lanes");
+    const int gshift = (threadIdx.x & 63) - l;
+    const uint64_t gmask = ((uint64_t)1 << G) - 1;
+    const uint64_t below = ((uint64_t)1 << l) - 1;
+    const int k = level_for(R, v);
+    const int nck = 1 << (v.bits - k);
+    Grid g{v.L, v.hL, (double)nck / v.L, v.margin, nck};
+    int lx, ly, lz, mx, my, mz;
+    axis_range(pi.x, R, g, lx, mx);
+    axis_range(pi.y, R, g, ly, my);
+    axis_range(pi.z, R, g, lz, mz);
+    const int64_t base = box_base(v, i) + v.off[k];
+    const int32_t *cb = cbeg + base, *ce = cend + base;
+    const double cs = v.L / (double)nck;
+    const double Rc = R + 2.0 * v.margin;   // far above any rounding of the gaps
+    const bool cull = 2.0 * (Rc + cs) < v.L;
+    const double Rc2 = Rc * Rc;
+    const double L = v.L;
+    const int ncell = mx * my * mz;
+    const double inv_mx = 1.0 / (double)mx, inv_my = 1.0 / (double)my;
+    int c0 = 0;
+    bool stop = false;
+    while (c0 < ncell && !stop) {
+        int nr = 0, cum = 0;
+        while (c0 < ncell && nr + G <= kRanges) {
+            const int cidx = c0 + l;
+            int jb = 0, len = 0, code = 0;
+            if (cidx < ncell) {
+                // cell index -> (a, b, e); FP64 quotients, exact for these small integers
+                const int t = (int)(((double)cidx + 0.5) * inv_mx);
+                const int e = cidx - t * mx;
+                const int a = (int)(((double)t + 0.5) * inv_my);
+                const int b = t - a * my;
+                const int kx = lx + e, ky = ly + b, kz = lz + a;
+                bool keep = true;
+                if (cull) {
+                    const double gz = cell_gap(pi.z, kz, cs), gy = cell_gap(pi.y, ky, cs),
+                                 gx = cell_gap(pi.x, kx, cs);
+                    keep = (gz * gz + gy * gy) + gx * gx <= Rc2;
+                    code = (kx < 0 ? 1 : (kx >= nck ? 2 : 0)) | (ky < 0 ? 4 : (ky >= nck ? 8 : 0)) |
+                           (kz < 0 ? 16 : (kz >= nck ? 32 : 0));
+                }
+                if (keep) {
+                    const uint32_t id = (spread3(wrapc(kz, nck)) << 2) | (spread3(wrapc(ky, nck)) << 1) |
+                                        spread3(wrapc(kx, nck));
+                    jb = cb[id];
+                    len = ce[id] - jb;
+                }
+            }
+            int tot;
+            const int pre = group_excl_scan<G>(len, l, tot);
+            const bool has = len > 0;
+            const uint64_t hm = (__ballot(has) >> gshift) & gmask;
+            if (has) {
+                const int p = nr + __popcll(hm & below);
+                sb[p] = jb;
+                sc[p] = cum + pre;
+                so[p] = code;
+            }
+            nr += __popcll(hm);
+            cum += tot;
+            c0 += G;
+        }
+        if (l == 0) sc[nr] = cum;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        int r = 0;
+        for (int f0 = 0; f0 < cum; f0 += G) {
+            const int f = f0 + l;
+            double r2 = 0.0;
+            if (f < cum) {
+                while (sc[r + 1] <= f) r++;
+                const int j = sb[r] + (f - sc[r]);
+                const double4 pj = posH[j];
+                double dx, dy, dz;
+                if (cull) {
+                    const int code = so[r];
+                    dx = (pi.x - pj.x) + ((code & 1) ? L : ((code & 2) ? -L : 0.0));
+                    dy = (pi.y - pj.y) + ((code & 4) ? L : ((code & 8) ? -L : 0.0));
+                    dz = (pi.z - pj.z) + ((code & 16) ? L : ((code & 32) ? -L : 0.0));
+                } else {
+                    dx = min_image(pi.x - pj.x, v.L, v.hL);
+                    dy = min_image(pi.y - pj.y, v.L, v.hL);
+                    dz = min_image(pi.z - pj.z, v.L, v.hL);
+                }
+                r2 = r2_exact(dx, dy, dz);
+            }
+            if (visit(f < cum, r2)) {
+                stop = true;
+                break;
+            }
+        }
+        // the lists are rewritten by the next batch only after every lane read them
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+}
+
 
 // Walks every cell of the level chosen for radius R that overlaps the cube
 // [x - R, x + R]^3 (periodic), calling f(j) for each particle j in them, in a
