@@ -523,11 +523,17 @@ __global__ __launch_bounds__(kBlock) void k_to_i64(const int32_t *a, int64_t n, 
 // entry moves to the place given by its rank in its row, so each row is
 // ascending in i whatever order the slots were taken in. G lanes per row;
 // entries of a row are distinct emitters, so the ranks are a permutation of
-// the row's slots.
-template <int G>
+// the row's slots. A row of up to CAP entries is first staged in LDS (row
+// stride CAP + 4 words, so the groups of a wavefront read different banks)
+// and every rank is counted from there, four entries per read; longer rows
+// count from global memory.
+template <int G, int CAP>
 __global__ __launch_bounds__(kBlock) void k_extra_rank(const int64_t *__restrict__ eoff,
                                                        const int32_t *__restrict__ tmp, int64_t n,
                                                        int32_t *out, int32_t *eb, int32_t *ee) {
+    static_assert(CAP % 4 == 0, "rows are read four entries at a time");
+    constexpr int S = CAP + 4;
+    __shared__ __align__(16) int32_t srow[kBlock / G][S];
     int64_t gid = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
     const int l = (int)(gid % G);
     const int64_t j = gid / G;
@@ -537,6 +543,26 @@ __global__ __launch_bounds__(kBlock) void k_extra_rank(const int64_t *__restrict
     if (l == 0) {
         eb[j] = (int32_t)b;
         ee[j] = (int32_t)(b + c);
+    }
+    if (c <= CAP) {
+        int32_t *sr = srow[threadIdx.x / G];
+        // padded to a multiple of four with values above every index
+        const int c4 = (c + 3) & ~3;
+        for (int t = l; t < c4; t += G) sr[t] = t < c ? tmp[b + t] : INT32_MAX;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const int4 *s4 = reinterpret_cast<const int4 *>(sr);
+        for (int t = l; t < c; t += G) {
+            const int32_t v = sr[t];
+            int r = 0;
+            for (int u = 0; u < c4 / 4; u++) {
+                const int4 q = s4[u];
+                r += (q.x < v) + (q.y < v) + (q.z < v) + (q.w < v);
+            }
+            out[b + r] = v;
+        }
+        return;
     }
     for (int t = l; t < c; t += G) {
         const int32_t v = tmp[b + t];
@@ -716,7 +742,7 @@ static crk_status build_lists(crk_ctx *c) {
     {
         KTimer kt_(c, "k_extra_rank");
         constexpr int GR = 8;
-        k_extra_rank<GR><<<(unsigned)((n * GR + kBlock - 1) / kBlock), kBlock, 0, c->stream>>>(
+        k_extra_rank<GR, 128><<<(unsigned)((n * GR + kBlock - 1) / kBlock), kBlock, 0, c->stream>>>(
             eoff, etmp, n, eidx, (int32_t *)c->eb.p, (int32_t *)c->ee.p);
     }
     CRK_HIP(c, hipGetLastError());
