@@ -19,6 +19,7 @@ constexpr int kIn = 8, kHid = 64;
 constexpr int oW1 = 0, ob1 = oW1 + kHid * kIn, oW2 = ob1 + kHid, ob2 = oW2 + kHid * kHid,
               ow3 = ob2 + kHid, ob3 = ow3 + kHid, kNP = ob3 + 1;   // kNP = 4801
 constexpr int kGradBlock = 64;                                      // samples per gradient block
+constexpr int kAdamLanes = 8;                                       // lanes summing one parameter's partials
 
 __device__ __forceinline__ float gelu(float x) { return 0.5f * x * (1.0f + erff(x * 0.70710678118654752f)); }
 __device__ __forceinline__ float gelu_d(float x) {
@@ -88,12 +89,14 @@ __global__ __launch_bounds__(kGradBlock) void k_hnet_grad(const float *__restric
     load_theta(theta, s);
     const int t = threadIdx.x;
     const int64_t b = (int64_t)blockIdx.x * kGradBlock + t;
-    float z1[kHid], z2[kHid];
+    // z1 and z2 are parked in this sample's LDS rows of dz1 and dz2 (each is
+    // overwritten by its gradient once read), so no per-thread array is
+    // indexed at run time
     float f[kIn];
     bool act = b < nb;
 #pragma unroll
     for (int q = 0; q < kIn; q++) f[q] = act ? feat[q * nb + b] : 0.0f;
-    float y = mlp_forward<true>(s, f, z1, sa1[t], z2);
+    float y = mlp_forward<true>(s, f, sdz1[t], sa1[t], sdz2[t]);
     float r = act ? (y - target[b]) : 0.0f;
     float dy = 2.0f * r * inv_b;
     sl[t] = r * r;
@@ -103,19 +106,48 @@ __global__ __launch_bounds__(kGradBlock) void k_hnet_grad(const float *__restric
     float dz2[kHid];
 #pragma unroll
     for (int k = 0; k < kHid; k++) {
-        dz2[k] = dy * s[ow3 + k] * gelu_d(z2[k]);
+        const float z2 = sdz2[t][k];
+        dz2[k] = dy * s[ow3 + k] * gelu_d(z2);
         sdz2[t][k] = dz2[k];
-        sa2[t][k] = gelu(z2[k]);
+        sa2[t][k] = gelu(z2);
     }
     for (int j = 0; j < kHid; j++) {
         float da = 0.0f;
 #pragma unroll
         for (int k = 0; k < kHid; k++) da += s[oW2 + k * kHid + j] * dz2[k];
-        sdz1[t][j] = da * gelu_d(z1[j]);
+        sdz1[t][j] = da * gelu_d(sdz1[t][j]);
     }
     __syncthreads();
     float *out = partial + (int64_t)blockIdx.x * kNP;
+    // dW2: each thread an 8 x 8 tile of rows k0.. and columns j0.., summed
+    // over the samples in order (the same order as every other entry)
+    static_assert(kGradBlock == 64 && kHid == 64, "one 8 x 8 tile of dW2 per thread");
+    {
+        const int k0 = (t / 8) * 8, j0 = (t % 8) * 8;
+        float acc[8][8];
+#pragma unroll
+        for (int a = 0; a < 8; a++)
+#pragma unroll
+            for (int c = 0; c < 8; c++) acc[a][c] = 0.0f;
+        for (int u = 0; u < kGradBlock; u++) {
+            float dk[8], aj[8];
+#pragma unroll
+            for (int a = 0; a < 8; a++) {
+                dk[a] = sdz2[u][k0 + a];
+                aj[a] = sa1[u][j0 + a];
+            }
+#pragma unroll
+            for (int a = 0; a < 8; a++)
+#pragma unroll
+                for (int c = 0; c < 8; c++) acc[a][c] += dk[a] * aj[c];
+        }
+#pragma unroll
+        for (int a = 0; a < 8; a++)
+#pragma unroll
+            for (int c = 0; c < 8; c++) out[oW2 + (k0 + a) * kHid + j0 + c] = acc[a][c];
+    }
     for (int e = t; e < kNP; e += kGradBlock) {
+        if (e >= oW2 && e < ob2) continue;   // the tiles above
         float acc = 0.0f;
         if (e < ob1) {
             int j = e / kIn, q = e % kIn;
@@ -123,9 +155,6 @@ __global__ __launch_bounds__(kGradBlock) void k_hnet_grad(const float *__restric
         } else if (e < oW2) {
             int j = e - ob1;
             for (int u = 0; u < kGradBlock; u++) acc += sdz1[u][j];
-        } else if (e < ob2) {
-            int k = (e - oW2) / kHid, j = (e - oW2) % kHid;
-            for (int u = 0; u < kGradBlock; u++) acc += sdz2[u][k] * sa1[u][j];
         } else if (e < ow3) {
             int k = e - ob2;
             for (int u = 0; u < kGradBlock; u++) acc += sdz2[u][k];
@@ -144,15 +173,21 @@ __global__ __launch_bounds__(kGradBlock) void k_hnet_grad(const float *__restric
     }
 }
 
-// fixed-order sum of the block partials, then one Adam step per parameter
-// (bias-corrected, beta1 0.9, beta2 0.999, eps 1e-8)
+// fixed-order sum of the block partials (kAdamLanes lanes per parameter,
+// lane c takes blocks c, c + kAdamLanes, ...; the lanes combine in a fixed
+// butterfly), then one Adam step per parameter (bias-corrected, beta1 0.9,
+// beta2 0.999, eps 1e-8)
 __global__ __launch_bounds__(kBlock) void k_hnet_adam(const float *__restrict__ partial, int64_t nblk,
                                                       float *theta, float *m, float *v, float lr,
                                                       float bc1, float bc2, float *grad_out) {
-    int e = blockIdx.x * kBlock + threadIdx.x;
-    if (e >= kNP) return;
+    const int t = blockIdx.x * kBlock + threadIdx.x;
+    const int e = t / kAdamLanes, c = t % kAdamLanes;
+    if (e >= kNP) return;   // whole lane groups leave together
     float g = 0.0f;
-    for (int64_t b = 0; b < nblk; b++) g += partial[b * kNP + e];
+    for (int64_t b = c; b < nblk; b += kAdamLanes) g += partial[b * kNP + e];
+#pragma unroll
+    for (int o = 1; o < kAdamLanes; o <<= 1) g += __shfl_xor(g, o, kAdamLanes);
+    if (c != 0) return;
     if (grad_out) grad_out[e] = g;
     if (!theta) return;
     float mm = 0.9f * m[e] + 0.1f * g;
@@ -311,7 +346,7 @@ crk_status crk_hnet_train_step(crk_ctx *c, float *theta, float *adam_m, float *a
     float bc1 = 1.0f - powf(0.9f, (float)step), bc2 = 1.0f - powf(0.999f, (float)step);
     {
         KTimer kt_(c, "k_hnet_adam");
-        k_hnet_adam<<<(kNP + kBlock - 1) / kBlock, kBlock, 0, c->stream>>>(
+        k_hnet_adam<<<(kNP * kAdamLanes + kBlock - 1) / kBlock, kBlock, 0, c->stream>>>(
             part, nblk, lr > 0.0f ? theta : nullptr, adam_m, adam_v, lr, bc1, bc2, grad);
     }
     CRK_HIP(c, hipGetLastError());
