@@ -288,8 +288,9 @@ crk_status crk_graph_destroy(crk_ctx *ctx);
  * Each update sums W over a candidate row (the distances of every j within
  * a radius above H, rebuilt when H leaves it). A particle whose row does not
  * fit its slots is moved to a wide pass with a wavefront per particle and
- * rows of max(4096, 8 cap) slots (up to 65536 particles per launch; that
- * pool, 2 GiB at most, is part of the context workspace).
+ * rows of max(4096, 8 cap) slots (as many particles per launch as 8 GiB of
+ * rows hold; that pool, sized to the particles it serves, is part of the
+ * context workspace).
  */
 crk_status crk_hsolve(crk_ctx *ctx, double Nres, double tol, int32_t max_iter, double *H_inout,
                       int32_t *iters, int64_t *n_unconverged);

@@ -13,8 +13,9 @@
 namespace crk {
 namespace {
 
-// wide-pass rows: up to kPoolRows particles per launch, kPoolCap slots each
-constexpr int64_t kPoolRows = 65536;
+// wide-pass rows: kPoolCap slots each (or 8 cap), for at most kPoolBytes of
+// rows per launch (262144 particles at 4096 slots)
+constexpr int64_t kPoolBytes = (int64_t)8 << 30;
 constexpr int kPoolCap = 4096;
 // row slots per lane held in registers by the narrow pass (8 and 16 lanes)
 constexpr int kRegSlots8 = 40;
@@ -473,7 +474,7 @@ static crk_status hsolve_round(crk_ctx *c, const HsArgs &a, int G, const int32_t
 }
 
 // both passes of a round in one launch (register rows of S slots for the
-// narrow one); mw <= kPoolRows
+// narrow one); mw at most the pool's rows
 template <int G, int S>
 static crk_status hsolve_both(crk_ctx *c, const HsArgs &a, const int32_t *ln, int64_t mn, int Rn,
                               const int32_t *lw, int64_t mw, int Rw, double *pool, int pcap) {
@@ -530,6 +531,7 @@ crk_status crk_hsolve(crk_ctx *c, double Nres, double tol, int32_t max_iter, dou
     CRK_HIP(c, hipGetLastError());
     int64_t mn = n, mw = 0;   // narrow and wide particles still running
     const int pcap = kPoolCap < 8 * cap ? 8 * cap : kPoolCap;
+    const int64_t prow = kPoolBytes / ((int64_t)pcap * (int64_t)sizeof(double));   // >= 2048
     const HsArgs a{(const double4 *)c->posH.p, (const int32_t *)c->cbeg.p, (const int32_t *)c->cend.p,
                    v, Nres, tol, c->hs_factor, max_iter, cap, rows, rcnt, Rl, H_inout, it, state};
     int64_t *pin = (int64_t *)c->pinned.p + 24;
@@ -544,7 +546,7 @@ crk_status crk_hsolve(crk_ctx *c, double Nres, double tol, int32_t max_iter, dou
             const int Rn = Gr > G ? 4 * c->hs_round : c->hs_round;
             // the wide pass runs longer rounds: its particles are few and slow
             const int Rw = 4 * c->hs_round;
-            const int64_t mw0 = mw < kPoolRows ? mw : kPoolRows;   // wide particles in the first launch
+            const int64_t mw0 = mw < prow ? mw : prow;   // wide particles in the first launch
             if (mw0 > 0) CRK_TRY(ensure(c, c->hs_pool, (size_t)mw0 * pcap * sizeof(double)));
             double *pool = (double *)c->hs_pool.p;
             const bool reg8 = rows && Gr == 8 && cap <= 8 * kRegSlots8;
@@ -558,8 +560,8 @@ crk_status crk_hsolve(crk_ctx *c, double Nres, double tol, int32_t max_iter, dou
                 if (mw0 > 0) CRK_TRY(hsolve_round(c, a, 64, la + mn, mw0, Rw, pool, pcap, 0));
             }
             // wide particles beyond the pool: further launches reusing it
-            for (int64_t w0 = mw0; w0 < mw; w0 += kPoolRows) {
-                const int64_t mc = mw - w0 < kPoolRows ? mw - w0 : kPoolRows;
+            for (int64_t w0 = mw0; w0 < mw; w0 += prow) {
+                const int64_t mc = mw - w0 < prow ? mw - w0 : prow;
                 CRK_TRY(hsolve_round(c, a, 64, la + mn + w0, mc, Rw, pool, pcap, 0));
             }
             const int64_t m = mn + mw;
