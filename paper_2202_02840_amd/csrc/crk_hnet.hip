@@ -4,10 +4,11 @@
 // backward, Adam) are all kernels here.
 //
 // Parameter vector (4801 floats): W1 [64][8], b1 [64], W2 [64][64], b2 [64],
-// w3 [64], b3. Every kernel stages it in LDS (19 KB) and reads it with
-// wave-wide broadcasts; one thread evaluates one sample. The batch gradient
-// is reduced deterministically: per-block partial sums in a fixed sample
-// order, then a fixed-order sum over blocks (no float atomics).
+// w3 [64], b3. Every kernel stages it in LDS (19 KB). The dense products of
+// the forward and backward passes run on the matrix cores (FP32 MFMA), 16
+// samples per wavefront. The batch gradient is reduced deterministically:
+// one partial row per 16-sample tile, then a fixed-order sum over the rows
+// (no float atomics).
 #include <math.h>
 
 #include "crk_internal.h"
@@ -18,8 +19,7 @@ namespace {
 constexpr int kIn = 8, kHid = 64;
 constexpr int oW1 = 0, ob1 = oW1 + kHid * kIn, oW2 = ob1 + kHid, ob2 = oW2 + kHid * kHid,
               ow3 = ob2 + kHid, ob3 = ow3 + kHid, kNP = ob3 + 1;   // kNP = 4801
-constexpr int kGradBlock = 64;                                      // samples per gradient block
-constexpr int kAdamLanes = 8;                                       // lanes summing one parameter's partials
+constexpr int kAdamLanes = 32;                                      // lanes summing one parameter's partials
 
 __device__ __forceinline__ float gelu(float x) { return 0.5f * x * (1.0f + erff(x * 0.70710678118654752f)); }
 __device__ __forceinline__ float gelu_d(float x) {
@@ -31,145 +31,239 @@ __device__ __forceinline__ void load_theta(const float *__restrict__ th, float *
     __syncthreads();
 }
 
-// forward of one sample; keeps z1, a1, z2 when asked
-template <bool KEEP>
-__device__ __forceinline__ float mlp_forward(const float *__restrict__ s, const float f[kIn], float *z1k,
-                                             float *a1k, float *z2k) {
-    float a1[kHid];
-#pragma unroll
-    for (int j = 0; j < kHid; j++) {
-        float z = s[ob1 + j];
-#pragma unroll
-        for (int q = 0; q < kIn; q++) z += s[oW1 + j * kIn + q] * f[q];
-        if (KEEP) z1k[j] = z;
-        a1[j] = gelu(z);
-        if (KEEP) a1k[j] = a1[j];
-    }
-    float y = s[ob3];
-    for (int k = 0; k < kHid; k++) {
-        float z = s[ob2 + k];
-#pragma unroll
-        for (int j = 0; j < kHid; j++) z += s[oW2 + k * kHid + j] * a1[j];
-        if (KEEP) z2k[k] = z;
-        y += s[ow3 + k] * gelu(z);
-    }
-    return y;
+// ---------------------------------------------------------------- matrix cores
+// v_mfma_f32_16x16x4_f32: D[16x16] = A[16x4] B[4x16] + C with, for lane l,
+// c = l % 16 and g = l / 16: A[c][g], B[g][c] and D[4g + r][c] (r = 0..3).
+typedef float f4v __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ f4v mfma4(float a, float b, f4v c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
+// Forward on the matrix cores, 16 samples (the columns) per wavefront step.
+// Layer 1: Z1 = W1 F as four 16-row tiles over two k-steps. Layer 2: Z2 = W2
+// A1, where the k-step (mt, r) takes the hidden units 16 mt + 4 g + r, i.e.
+// the values each lane already holds in register r of tile mt (the sum over
+// k runs in a permuted order, so no data moves between lanes); the matching
+// W2 entries are per-lane constants. Output: each lane's share of w3.a2,
+// then a sum over the four lane groups of a column.
 __global__ __launch_bounds__(kBlock) void k_hnet_fwd(const float *__restrict__ theta,
                                                      const float *__restrict__ feat, int64_t nb,
                                                      float *y) {
     __shared__ float s[kNP];
     load_theta(theta, s);
-    int64_t b = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (b >= nb) return;
-    float f[kIn];
+    const int lane = threadIdx.x & 63;
+    const int c = lane & 15, g = lane >> 4;
+    float w1a[4][2], w2a[4][4][4], b1r[4][4], b2r[4][4], w3r[4][4];
 #pragma unroll
-    for (int q = 0; q < kIn; q++) f[q] = feat[q * nb + b];
-    y[b] = mlp_forward<false>(s, f, nullptr, nullptr, nullptr);
+    for (int mt = 0; mt < 4; mt++) {
+#pragma unroll
+        for (int ks = 0; ks < 2; ks++) w1a[mt][ks] = s[oW1 + (16 * mt + c) * kIn + 4 * ks + g];
+#pragma unroll
+        for (int r = 0; r < 4; r++) {
+            const int h = 16 * mt + 4 * g + r;   // the hidden unit of register r of tile mt
+            b1r[mt][r] = s[ob1 + h];
+            b2r[mt][r] = s[ob2 + h];
+            w3r[mt][r] = s[ow3 + h];
+#pragma unroll
+            for (int m2 = 0; m2 < 4; m2++) w2a[m2][mt][r] = s[oW2 + (16 * m2 + c) * kHid + h];
+        }
+    }
+    const float b3 = s[ob3];
+    const int64_t wstep = (int64_t)gridDim.x * (kBlock / 64) * 16;
+    for (int64_t t0 = ((int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6)) * 16; t0 < nb; t0 += wstep) {
+        const int64_t smp = t0 + c;
+        const bool act = smp < nb;
+        f4v z1[4];
+#pragma unroll
+        for (int mt = 0; mt < 4; mt++) z1[mt] = f4v{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int ks = 0; ks < 2; ks++) {
+            const float bf = act ? feat[(int64_t)(4 * ks + g) * nb + smp] : 0.0f;
+#pragma unroll
+            for (int mt = 0; mt < 4; mt++) z1[mt] = mfma4(w1a[mt][ks], bf, z1[mt]);
+        }
+        float a1[4][4];
+#pragma unroll
+        for (int mt = 0; mt < 4; mt++)
+#pragma unroll
+            for (int r = 0; r < 4; r++) a1[mt][r] = gelu(z1[mt][r] + b1r[mt][r]);
+        f4v z2[4];
+#pragma unroll
+        for (int m2 = 0; m2 < 4; m2++) z2[m2] = f4v{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int mt = 0; mt < 4; mt++)
+#pragma unroll
+            for (int r = 0; r < 4; r++)
+#pragma unroll
+                for (int m2 = 0; m2 < 4; m2++) z2[m2] = mfma4(w2a[m2][mt][r], a1[mt][r], z2[m2]);
+        float part = 0.0f;
+#pragma unroll
+        for (int m2 = 0; m2 < 4; m2++)
+#pragma unroll
+            for (int r = 0; r < 4; r++) part += w3r[m2][r] * gelu(z2[m2][r] + b2r[m2][r]);
+        part += __shfl_xor(part, 16);
+        part += __shfl_xor(part, 32);
+        if (g == 0 && act) y[smp] = part + b3;
+    }
 }
 
-// One block = kGradBlock samples. Phase 1: each thread runs its sample
-// forward and backward (dL/dy = 2 (y - t) / B) and parks the per-sample
-// factors in LDS. Phase 2: the block's threads sum the outer products of
-// those factors over the block's samples in sample order and write one
-// partial gradient row per block.
-__global__ __launch_bounds__(kGradBlock) void k_hnet_grad(const float *__restrict__ theta,
-                                                          const float *__restrict__ feat,
-                                                          const float *__restrict__ target, int64_t nb,
-                                                          float inv_b, float *partial, float *ploss) {
+// Sum over the 16 lanes of a DPP row (every lane gets the total)
+template <int CTRL>
+__device__ __forceinline__ float dpp_f32(float x) {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), CTRL, 0xF, 0xF, false));
+}
+__device__ __forceinline__ float row_sum16(float x) {
+    x += dpp_f32<0xB1>(x);    // quad_perm(1,0,3,2)
+    x += dpp_f32<0x4E>(x);    // quad_perm(2,3,0,1)
+    x += dpp_f32<0x141>(x);   // row_half_mirror
+    x += dpp_f32<0x140>(x);   // row_mirror
+    return x;
+}
+
+// Gradient on the matrix cores: a wavefront takes a tile of 16 samples (the
+// columns; lane c = l % 16 is a sample, g = l / 16 picks four hidden units
+// per register tile) and writes one partial gradient row. Forward as in
+// k_hnet_fwd. Backward: dZ2 = dy w3 gelu'(z2) in the same layout; dA1 =
+// W2^T dZ2 on the matrix cores with the permuted k order of the forward;
+// dZ1 = dA1 gelu'(z1). Weight gradients are sums over the tile's samples,
+// so the sample index becomes the k of the product: dZ2, A1 and dZ1 are
+// transposed through LDS (row stride 17), and dW2 = dZ2 A1^T, db2 (a column
+// of ones), dW1 = dZ1 F^T and db1 (F padded with a row of ones) run on the
+// matrix cores; dw3 and db3 are row sums over the 16 sample lanes.
+constexpr int kTS = 17;   // LDS row stride of the transposed 64 x 16 tiles
+__global__ __launch_bounds__(kBlock) void k_hnet_grad(const float *__restrict__ theta,
+                                                      const float *__restrict__ feat,
+                                                      const float *__restrict__ target, int64_t nb,
+                                                      float inv_b, float *partial, float *ploss) {
     __shared__ float s[kNP];
-    __shared__ float sf[kGradBlock][kIn];
-    __shared__ float sa1[kGradBlock][kHid + 1];
-    __shared__ float sa2[kGradBlock][kHid + 1];
-    __shared__ float sdz1[kGradBlock][kHid + 1];
-    __shared__ float sdz2[kGradBlock][kHid + 1];
-    __shared__ float sdy[kGradBlock];
-    __shared__ float sl[kGradBlock];
+    __shared__ float tr[kBlock / 64][3][kHid * kTS];
     load_theta(theta, s);
-    const int t = threadIdx.x;
-    const int64_t b = (int64_t)blockIdx.x * kGradBlock + t;
-    // z1 and z2 are parked in this sample's LDS rows of dz1 and dz2 (each is
-    // overwritten by its gradient once read), so no per-thread array is
-    // indexed at run time
-    float f[kIn];
-    bool act = b < nb;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int c = lane & 15, g = lane >> 4;
+    const int64_t tile = (int64_t)blockIdx.x * (kBlock / 64) + wv;
+    if (tile * 16 >= nb) return;   // the whole wavefront: no samples left
+    const int64_t smp = tile * 16 + c;
+    const bool act = smp < nb;
+    float *Ta1 = tr[wv][0], *Tdz2 = tr[wv][1], *Tdz1 = tr[wv][2];
+    // forward
+    f4v z1[4], z2[4];
 #pragma unroll
-    for (int q = 0; q < kIn; q++) f[q] = act ? feat[q * nb + b] : 0.0f;
-    float y = mlp_forward<true>(s, f, sdz1[t], sa1[t], sdz2[t]);
-    float r = act ? (y - target[b]) : 0.0f;
-    float dy = 2.0f * r * inv_b;
-    sl[t] = r * r;
-    sdy[t] = dy;
+    for (int mt = 0; mt < 4; mt++) z1[mt] = f4v{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-    for (int q = 0; q < kIn; q++) sf[t][q] = f[q];
-    float dz2[kHid];
+    for (int ks = 0; ks < 2; ks++) {
+        const float bf = act ? feat[(int64_t)(4 * ks + g) * nb + smp] : 0.0f;
 #pragma unroll
-    for (int k = 0; k < kHid; k++) {
-        const float z2 = sdz2[t][k];
-        dz2[k] = dy * s[ow3 + k] * gelu_d(z2);
-        sdz2[t][k] = dz2[k];
-        sa2[t][k] = gelu(z2);
+        for (int mt = 0; mt < 4; mt++) z1[mt] = mfma4(s[oW1 + (16 * mt + c) * kIn + 4 * ks + g], bf, z1[mt]);
     }
-    for (int j = 0; j < kHid; j++) {
-        float da = 0.0f;
+    float a1[4][4];
 #pragma unroll
-        for (int k = 0; k < kHid; k++) da += s[oW2 + k * kHid + j] * dz2[k];
-        sdz1[t][j] = da * gelu_d(sdz1[t][j]);
-    }
-    __syncthreads();
-    float *out = partial + (int64_t)blockIdx.x * kNP;
-    // dW2: each thread an 8 x 8 tile of rows k0.. and columns j0.., summed
-    // over the samples in order (the same order as every other entry)
-    static_assert(kGradBlock == 64 && kHid == 64, "one 8 x 8 tile of dW2 per thread");
-    {
-        const int k0 = (t / 8) * 8, j0 = (t % 8) * 8;
-        float acc[8][8];
+    for (int mt = 0; mt < 4; mt++)
 #pragma unroll
-        for (int a = 0; a < 8; a++)
-#pragma unroll
-            for (int c = 0; c < 8; c++) acc[a][c] = 0.0f;
-        for (int u = 0; u < kGradBlock; u++) {
-            float dk[8], aj[8];
-#pragma unroll
-            for (int a = 0; a < 8; a++) {
-                dk[a] = sdz2[u][k0 + a];
-                aj[a] = sa1[u][j0 + a];
-            }
-#pragma unroll
-            for (int a = 0; a < 8; a++)
-#pragma unroll
-                for (int c = 0; c < 8; c++) acc[a][c] += dk[a] * aj[c];
+        for (int r = 0; r < 4; r++) {
+            z1[mt][r] += s[ob1 + 16 * mt + 4 * g + r];
+            a1[mt][r] = gelu(z1[mt][r]);
         }
 #pragma unroll
-        for (int a = 0; a < 8; a++)
+    for (int m2 = 0; m2 < 4; m2++) z2[m2] = f4v{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-            for (int c = 0; c < 8; c++) out[oW2 + (k0 + a) * kHid + j0 + c] = acc[a][c];
-    }
-    for (int e = t; e < kNP; e += kGradBlock) {
-        if (e >= oW2 && e < ob2) continue;   // the tiles above
-        float acc = 0.0f;
-        if (e < ob1) {
-            int j = e / kIn, q = e % kIn;
-            for (int u = 0; u < kGradBlock; u++) acc += sdz1[u][j] * sf[u][q];
-        } else if (e < oW2) {
-            int j = e - ob1;
-            for (int u = 0; u < kGradBlock; u++) acc += sdz1[u][j];
-        } else if (e < ow3) {
-            int k = e - ob2;
-            for (int u = 0; u < kGradBlock; u++) acc += sdz2[u][k];
-        } else if (e < ob3) {
-            int k = e - ow3;
-            for (int u = 0; u < kGradBlock; u++) acc += sdy[u] * sa2[u][k];
-        } else {
-            for (int u = 0; u < kGradBlock; u++) acc += sdy[u];
+    for (int mt = 0; mt < 4; mt++)
+#pragma unroll
+        for (int r = 0; r < 4; r++)
+#pragma unroll
+            for (int m2 = 0; m2 < 4; m2++)
+                z2[m2] = mfma4(s[oW2 + (16 * m2 + c) * kHid + 16 * mt + 4 * g + r], a1[mt][r], z2[m2]);
+    float part = 0.0f;
+#pragma unroll
+    for (int m2 = 0; m2 < 4; m2++)
+#pragma unroll
+        for (int r = 0; r < 4; r++) {
+            z2[m2][r] += s[ob2 + 16 * m2 + 4 * g + r];
+            part += s[ow3 + 16 * m2 + 4 * g + r] * gelu(z2[m2][r]);
         }
-        out[e] = acc;
+    part += __shfl_xor(part, 16);
+    part += __shfl_xor(part, 32);
+    const float res = act ? part + s[ob3] - target[smp] : 0.0f;
+    const float dy = 2.0f * res * inv_b;
+    float *out = partial + tile * kNP;
+    // loss and db3: sums over the tile's samples
+    const float lsum = row_sum16(res * res), dysum = row_sum16(dy);
+    if (lane == 0) {
+        ploss[tile] = lsum;
+        out[ob3] = dysum;
     }
-    if (t == 0) {
-        float L = 0.0f;
-        for (int u = 0; u < kGradBlock; u++) L += sl[u];
-        ploss[blockIdx.x] = L;
+    // dZ2 (and dw3 from the same registers)
+    float dz2[4][4];
+#pragma unroll
+    for (int m2 = 0; m2 < 4; m2++)
+#pragma unroll
+        for (int r = 0; r < 4; r++) {
+            const int h = 16 * m2 + 4 * g + r;
+            dz2[m2][r] = dy * s[ow3 + h] * gelu_d(z2[m2][r]);
+            const float dw3 = row_sum16(dy * gelu(z2[m2][r]));
+            if (c == 0) out[ow3 + h] = dw3;
+            Tdz2[h * kTS + c] = dz2[m2][r];
+        }
+    // dA1 = W2^T dZ2, then dZ1
+    f4v da1[4];
+#pragma unroll
+    for (int mt = 0; mt < 4; mt++) {
+        da1[mt] = f4v{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int m2 = 0; m2 < 4; m2++)
+#pragma unroll
+            for (int r = 0; r < 4; r++)
+                da1[mt] = mfma4(s[oW2 + (16 * m2 + 4 * g + r) * kHid + 16 * mt + c], dz2[m2][r], da1[mt]);
+    }
+#pragma unroll
+    for (int mt = 0; mt < 4; mt++)
+#pragma unroll
+        for (int r = 0; r < 4; r++) {
+            const int h = 16 * mt + 4 * g + r;
+            Ta1[h * kTS + c] = a1[mt][r];
+            Tdz1[h * kTS + c] = da1[mt][r] * gelu_d(z1[mt][r]);
+        }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // dW2 and db2: k = the tile's samples
+    float fb[4];   // B of dW1: F[c][s] for c < 8, ones for c == 8 (db1), else 0
+#pragma unroll
+    for (int ks = 0; ks < 4; ks++) {
+        const int64_t sk = tile * 16 + 4 * ks + g;
+        fb[ks] = c < kIn ? (sk < nb ? feat[(int64_t)c * nb + sk] : 0.0f) : (c == kIn ? 1.0f : 0.0f);
+    }
+#pragma unroll
+    for (int m2 = 0; m2 < 4; m2++) {
+        float av[4];
+#pragma unroll
+        for (int ks = 0; ks < 4; ks++) av[ks] = Tdz2[(16 * m2 + c) * kTS + 4 * ks + g];
+#pragma unroll
+        for (int mt = 0; mt < 4; mt++) {
+            f4v acc = f4v{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+            for (int ks = 0; ks < 4; ks++) acc = mfma4(av[ks], Ta1[(16 * mt + c) * kTS + 4 * ks + g], acc);
+#pragma unroll
+            for (int r = 0; r < 4; r++) out[oW2 + (16 * m2 + 4 * g + r) * kHid + 16 * mt + c] = acc[r];
+        }
+        f4v acc = f4v{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int ks = 0; ks < 4; ks++) acc = mfma4(av[ks], c == 0 ? 1.0f : 0.0f, acc);
+        if (c == 0)
+#pragma unroll
+            for (int r = 0; r < 4; r++) out[ob2 + 16 * m2 + 4 * g + r] = acc[r];
+    }
+    // dW1 (columns 0..7) and db1 (column 8)
+#pragma unroll
+    for (int mt = 0; mt < 4; mt++) {
+        f4v acc = f4v{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int ks = 0; ks < 4; ks++) acc = mfma4(Tdz1[(16 * mt + c) * kTS + 4 * ks + g], fb[ks], acc);
+#pragma unroll
+        for (int r = 0; r < 4; r++) {
+            const int h = 16 * mt + 4 * g + r;
+            if (c < kIn) out[oW1 + h * kIn + c] = acc[r];
+            else if (c == kIn) out[ob1 + h] = acc[r];
+        }
     }
 }
 
@@ -319,7 +413,12 @@ crk_status crk_hnet_forward(crk_ctx *c, const float *theta, const float *feat, i
     CRK_HIP(c, hipSetDevice(c->device));
     {
         KTimer kt_(c, "k_hnet_fwd");
-        k_hnet_fwd<<<(unsigned)((nb + kBlock - 1) / kBlock), kBlock, 0, c->stream>>>(theta, feat, nb, y);
+        // 16 samples per wavefront step; enough blocks to fill the device, each
+        // wavefront striding over the batch
+        const int64_t tiles = (nb + 15) / 16;
+        int64_t nbk = (tiles + kBlock / 64 - 1) / (kBlock / 64);
+        if (nbk > 4096) nbk = 4096;
+        k_hnet_fwd<<<(unsigned)nbk, kBlock, 0, c->stream>>>(theta, feat, nb, y);
     }
     CRK_HIP(c, hipGetLastError());
     return CRK_OK;
@@ -332,7 +431,7 @@ crk_status crk_hnet_train_step(crk_ctx *c, float *theta, float *adam_m, float *a
     if (!feat || !target || nb < 1 || (theta && (!adam_m || !adam_v || step < 1)) || (!theta && !grad))
         return set_err(c, CRK_ERR_INVALID_ARG, "crk_hnet_train_step: bad argument");
     CRK_HIP(c, hipSetDevice(c->device));
-    int64_t nblk = (nb + kGradBlock - 1) / kGradBlock;
+    int64_t nblk = (nb + 15) / 16;   // one partial row per 16-sample tile
     CRK_TRY(ensure(c, c->hnet_part, (size_t)nblk * (kNP + 1) * sizeof(float) + 64));
     float *part = (float *)c->hnet_part.p;
     float *ploss = part + nblk * kNP;
@@ -340,7 +439,7 @@ crk_status crk_hnet_train_step(crk_ctx *c, float *theta, float *adam_m, float *a
     if (!theta) return set_err(c, CRK_ERR_INVALID_ARG, "theta is NULL");
     {
         KTimer kt_(c, "k_hnet_grad");
-        k_hnet_grad<<<(unsigned)nblk, kGradBlock, 0, c->stream>>>(th_in, feat, target, nb, 1.0f / (float)nb,
+        k_hnet_grad<<<(unsigned)((nblk + kBlock / 64 - 1) / (kBlock / 64)), kBlock, 0, c->stream>>>(th_in, feat, target, nb, 1.0f / (float)nb,
                                                                    part, ploss);
     }
     float bc1 = 1.0f - powf(0.9f, (float)step), bc2 = 1.0f - powf(0.999f, (float)step);
