@@ -157,31 +157,37 @@ __global__ __launch_bounds__(kBlock) void k_volume(const double4 *__restrict__ p
 }
 
 // ------------------------------------------------------------- S4 moments
-// 40 sums per particle: m0, m1[3], m2[6], gm0[3], gm1[9], gm2[18]
+// The 40 outputs per particle (m0, m1[3], m2[6], gm0[3], gm1[9], gm2[18])
+// come from 29 sums. With t = V_j W and u = V_j gf (grad_i W = gf d, the
+// kernel being radial):
+//   m0 = sum t, m1_a = sum t d_a, m2_ab = sum t d_a d_b, gm0_g = sum u d_g,
+//   gm1_ag = Q2_ag + delta_ag m0,  gm2_abg = Q3_abg + delta_ag m1_b + delta_bg m1_a,
+// with Q2_ag = sum u d_a d_g and Q3_abg = sum u d_a d_b d_g, both symmetric
+// in their indices (6 and 10 distinct sums), since d/dx_i (d_a W) = delta W +
+// d_a grad W. Same sums as the term-by-term form, grouped differently.
+// index of the symmetric pair (a, b) among (0,0),(0,1),(0,2),(1,1),(1,2),(2,2),
+// and of the sorted triple (a, b, c) among the ten triples in lexicographic order
+__device__ constexpr int kSym2[3][3] = {{0, 1, 2}, {1, 3, 4}, {2, 4, 5}};
+__device__ constexpr int kSym3[3][3][3] = {{{0, 1, 2}, {1, 3, 4}, {2, 4, 5}}, {{1, 3, 4}, {3, 6, 7}, {4, 7, 8}}, {{2, 4, 5}, {4, 7, 8}, {5, 8, 9}}};
+
 template <typename T, int G>
 __global__ __launch_bounds__(kBlock) void k_moments(const double4 *__restrict__ posH,
                                                     const int64_t *__restrict__ goff,
-                                                   const int32_t *__restrict__ gidx,
+                                                    const int32_t *__restrict__ gidx,
                                                     const T *__restrict__ recV, int64_t n, Box box,
                                                     double *m0, double *m1, double *m2, double *gm0,
                                                     double *gm1, double *gm2) {
+    // sums: 0 m0 | 1-3 m1 | 4-9 m2 | 10-12 gm0 | 13-18 Q2 | 19-28 Q3
     int l;
     int64_t i = group_index(G, l);
-    Acc<T> a[40];
+    Acc<T> a[29];
     if (i < n) {
         double4 pi = posH[i];
         T invH = (T)(1.0 / pi.w);
         T invH2 = invH * invH;
         T cw = (T)kW * invH2 * invH;
         T cg = (T)kG * invH2 * invH2 * invH;
-        if (l == 0) {
-            // self pair: d = 0, grad W = 0, so only m0 and the diagonal of dm1/dx
-            T t = recV[i] * cw;
-            a[0].add(t);
-            a[13 + 0].add(t);
-            a[13 + 4].add(t);
-            a[13 + 8].add(t);
-        }
+        if (l == 0) a[0].add(recV[i] * cw);   // self pair: d = 0, so m0 only
         int64_t b = goff[i];
         int cnt = (int)(goff[i + 1] - b);
         int32_t jn = l < cnt ? gidx[b + l] : 0;
@@ -195,54 +201,57 @@ __global__ __launch_bounds__(kBlock) void k_moments(const double4 *__restrict__ 
             T q = Mth<T>::sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]) * invH;
             T w, gf;
             kernel_wg(q, cw, cg, w, gf);
-            T t = Vj * w;
-            T gv[3], td[3];
-            T vg = Vj * gf;
-#pragma unroll
-            for (int c = 0; c < 3; c++) {
-                gv[c] = vg * d[c];
-                td[c] = t * d[c];
-            }
+            const T t = Vj * w, u = Vj * gf;
             a[0].add(t);
+            T dd[6];
 #pragma unroll
-            for (int x = 0; x < 3; x++) a[1 + x].add(td[x]);
-            // m2 and dm2 over the symmetric pairs (x, y), y >= x
-            int s = 0;
+            for (int x = 0; x < 3; x++) {
+                a[1 + x].add(t * d[x]);
+                a[10 + x].add(u * d[x]);
 #pragma unroll
-            for (int x = 0; x < 3; x++)
+                for (int y = x; y < 3; y++) dd[kSym2[x][y]] = d[x] * d[y];
+            }
 #pragma unroll
-                for (int y = x; y < 3; y++, s++) {
-                    T dd = d[x] * d[y];
-                    a[4 + s].add(td[x] * d[y]);
-#pragma unroll
-                    for (int c = 0; c < 3; c++) {
-                        T v = dd * gv[c];
-                        if (x == c) v += td[y];
-                        if (y == c) v += td[x];
-                        a[22 + s * 3 + c].add(v);
-                    }
-                }
-#pragma unroll
-            for (int c = 0; c < 3; c++) a[10 + c].add(gv[c]);
+            for (int e = 0; e < 6; e++) {
+                a[4 + e].add(t * dd[e]);
+                a[13 + e].add(u * dd[e]);
+            }
 #pragma unroll
             for (int x = 0; x < 3; x++)
 #pragma unroll
-                for (int c = 0; c < 3; c++) a[13 + x * 3 + c].add(x == c ? d[x] * gv[c] + t : d[x] * gv[c]);
+                for (int y = x; y < 3; y++)
+#pragma unroll
+                    for (int z = y; z < 3; z++) a[19 + kSym3[x][y][z]].add(u * dd[kSym2[x][y]] * d[z]);
         }
     }
-    group_reduce<T, G, 40>(a);
+    group_reduce<T, G, 29>(a);
     if (i < n && l == 0) {
-        m0[i] = a[0].value();
+        const double p0 = a[0].value();
+        double p1[3];
 #pragma unroll
-        for (int x = 0; x < 3; x++) m1[x * n + i] = a[1 + x].value();
+        for (int x = 0; x < 3; x++) p1[x] = a[1 + x].value();
+        m0[i] = p0;
 #pragma unroll
-        for (int s = 0; s < 6; s++) m2[s * n + i] = a[4 + s].value();
+        for (int x = 0; x < 3; x++) {
+            m1[x * n + i] = p1[x];
+            gm0[x * n + i] = a[10 + x].value();
+        }
 #pragma unroll
-        for (int c = 0; c < 3; c++) gm0[c * n + i] = a[10 + c].value();
+        for (int e = 0; e < 6; e++) m2[e * n + i] = a[4 + e].value();
 #pragma unroll
-        for (int s = 0; s < 9; s++) gm1[s * n + i] = a[13 + s].value();
+        for (int x = 0; x < 3; x++)
 #pragma unroll
-        for (int s = 0; s < 18; s++) gm2[s * n + i] = a[22 + s].value();
+            for (int c = 0; c < 3; c++)
+                gm1[(x * 3 + c) * n + i] = a[13 + kSym2[x][c]].value() + (x == c ? p0 : 0.0);
+        int s = 0;
+#pragma unroll
+        for (int x = 0; x < 3; x++)
+#pragma unroll
+            for (int y = x; y < 3; y++, s++)
+#pragma unroll
+                for (int c = 0; c < 3; c++)
+                    gm2[(s * 3 + c) * n + i] = a[19 + kSym3[x][y][c]].value() + (x == c ? p1[y] : 0.0) +
+                                               (y == c ? p1[x] : 0.0);
     }
 }
 
