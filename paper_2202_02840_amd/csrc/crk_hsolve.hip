@@ -178,12 +178,21 @@ __device__ __forceinline__ double nsum_row(const double *__restrict__ row, int c
     return kW * invH * invH * invH * s;
 }
 
+// Delta = x^(1/3) for x > 0 (x = Nres / N lies between ~1e-6 and ~3): an FP32
+// seed from the hardware log2/exp2, then one Newton step in FP64, which
+// squares the seed's ~1e-7 relative error to ~1e-14; the step's divisor
+// 3 y^2 needs only the seed's accuracy, so a hardware reciprocal serves.
+__device__ __forceinline__ double cube_root(double x) {
+    const double y = (double)__builtin_amdgcn_exp2f(__builtin_amdgcn_logf((float)x) * (1.0f / 3.0f));
+    return y - (y * y * y - x) * __builtin_amdgcn_rcp(3.0 * y * y);
+}
+
 // Everything a round needs besides its list (kernel argument by value)
 struct HsArgs {
     const double4 *posH;
     const int32_t *cbeg, *cend;
     Levels v;
-    double Nres, tol, f;
+    double Nres, inv_Nres, tol, f;
     int max_iter, cap;
     double *rows;   // n rows of cap slots (nullptr: no rows, every update walks)
     int32_t *rcnt;
@@ -202,8 +211,9 @@ __device__ __forceinline__ int thacker_updates(const HsArgs &a, double &H, int &
         if (stop_outside && !(H <= Rmax)) return 0;   // a new row next round
         const double ns = NS(H);
         const double N = (4.0 * kPi / 3.0) * H * H * H * ns;
-        const double D = cbrt(a.Nres / N);
-        const double lam = D < 1.0 ? 0.2 * (1.0 + D * D) : 0.2 * (1.0 + 1.0 / (D * D * D));
+        const double x = a.Nres / N;   // Delta^3
+        const double D = cube_root(x);
+        const double lam = D < 1.0 ? 0.2 * (1.0 + D * D) : 0.2 * (1.0 + N * a.inv_Nres);
         const double Hn = H * (1.0 - lam + lam * D);
         it++;
         const bool done = fabs(Hn - H) <= a.tol * H;
@@ -533,7 +543,8 @@ crk_status crk_hsolve(crk_ctx *c, double Nres, double tol, int32_t max_iter, dou
     const int pcap = kPoolCap < 8 * cap ? 8 * cap : kPoolCap;
     const int64_t prow = kPoolBytes / ((int64_t)pcap * (int64_t)sizeof(double));   // >= 2048
     const HsArgs a{(const double4 *)c->posH.p, (const int32_t *)c->cbeg.p, (const int32_t *)c->cend.p,
-                   v, Nres, tol, c->hs_factor, max_iter, cap, rows, rcnt, Rl, H_inout, it, state};
+                   v, Nres, 1.0 / Nres, tol, c->hs_factor, max_iter, cap, rows, rcnt, Rl, H_inout, it,
+                   state};
     int64_t *pin = (int64_t *)c->pinned.p + 24;
     const int G = c->G_hsolve;
     {
