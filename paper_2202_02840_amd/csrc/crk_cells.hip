@@ -286,10 +286,18 @@ __device__ __forceinline__ void walk_row(const double4 *__restrict__ posH, int64
 // Flattened form of the same walk. The cells of a wavefront's groups hold
 // different numbers of particles, so a cell-by-cell loop keeps most lanes
 // idle; here a group first lists its non-empty, non-skipped cells as ranges
-// of sorted particles (in walk order, up to kRanges at a time, in LDS) and
+// of sorted particles (in walk order, up to walk_ranges<G>() at a time, in
+// LDS, each with the image shift of its particles) and
 // then takes the concatenated candidates G at a time across cell
 // boundaries. The candidate order, hence every row, is the same as the
 // cell-by-cell walk's.
+
+// ranges a group lists per batch: two steps of G cells (at least 8), so the
+// LDS lists of a block stay near 16 KB whatever G
+template <int G>
+__host__ __device__ constexpr int walk_ranges() {
+    return 2 * G < 8 ? 8 : (2 * G > kRanges ? kRanges : 2 * G);
+}
 
 template <int G, bool DIRECT, bool CULL>
 __device__ __forceinline__ void walk_row_flat(const double4 *__restrict__ posH, int64_t i,
@@ -301,7 +309,7 @@ __device__ __forceinline__ void walk_row_flat(const double4 *__restrict__ posH, 
                                               int32_t *gidx, int32_t *rcnt,
                                               const int64_t *__restrict__ eoff, int32_t *efill,
                                               int32_t *etmp, int32_t &cg, int32_t *sb, int32_t *sc,
-                                              int32_t *so) {
+                                              double *sx) {
     const double H2 = pi.w * pi.w;
     const double L = v.L;
     const int ncell = mx * my * mz;
@@ -310,11 +318,12 @@ __device__ __forceinline__ void walk_row_flat(const double4 *__restrict__ posH, 
     const double inv_mx = 1.0 / (double)mx, inv_my = 1.0 / (double)my;
     int c0 = 0;
     while (c0 < ncell) {
-        // 1. list up to kRanges non-empty cells, G cells per step
+        // 1. list up to walk_ranges<G>() non-empty cells, G cells per step
         int nr = 0, cum = 0;
-        while (c0 < ncell && nr + G <= kRanges) {
+        while (c0 < ncell && nr + G <= walk_ranges<G>()) {
             const int cidx = c0 + l;
-            int jb = 0, len = 0, code = 0;
+            int jb = 0, len = 0;
+            double cx = 0.0, cy = 0.0, cz = 0.0;
             if (cidx < ncell) {
                 const int t = (int)(((double)cidx + 0.5) * inv_mx);
                 const int e = cidx - t * mx;
@@ -326,8 +335,10 @@ __device__ __forceinline__ void walk_row_flat(const double4 *__restrict__ posH, 
                     const double gz = cell_gap(pi.z, kz, cs), gy = cell_gap(pi.y, ky, cs),
                                  gx = cell_gap(pi.x, kx, cs);
                     keep = (gz * gz + gy * gy) + gx * gx <= Hc2;
-                    code = (kx < 0 ? 1 : (kx >= nck ? 2 : 0)) | (ky < 0 ? 4 : (ky >= nck ? 8 : 0)) |
-                           (kz < 0 ? 16 : (kz >= nck ? 32 : 0));
+                    // image shift of the cell's particles (0, L or -L per axis)
+                    cx = kx < 0 ? L : (kx >= nck ? -L : 0.0);
+                    cy = ky < 0 ? L : (ky >= nck ? -L : 0.0);
+                    cz = kz < 0 ? L : (kz >= nck ? -L : 0.0);
                 }
                 if (keep) {
                     const uint32_t id = (spread3(wrapc(kz, nck)) << 2) | (spread3(wrapc(ky, nck)) << 1) |
@@ -350,7 +361,9 @@ __device__ __forceinline__ void walk_row_flat(const double4 *__restrict__ posH, 
                 const int pos = nr + (G == 1 ? 0 : __popc(hm & below));
                 sb[pos] = jb;
                 sc[pos] = cum + pre;
-                so[pos] = code;
+                sx[3 * pos + 0] = cx;
+                sx[3 * pos + 1] = cy;
+                sx[3 * pos + 2] = cz;
             }
             nr += __popc(hm);
             cum += tot;
@@ -372,13 +385,9 @@ __device__ __forceinline__ void walk_row_flat(const double4 *__restrict__ posH, 
                 const double4 pj = posH[j];
                 double dx, dy, dz;
                 if (CULL) {
-                    const int code = so[r];
-                    const double cx = (code & 1) ? L : ((code & 2) ? -L : 0.0);
-                    const double cy = (code & 4) ? L : ((code & 8) ? -L : 0.0);
-                    const double cz = (code & 16) ? L : ((code & 32) ? -L : 0.0);
-                    dx = (pi.x - pj.x) + cx;
-                    dy = (pi.y - pj.y) + cy;
-                    dz = (pi.z - pj.z) + cz;
+                    dx = (pi.x - pj.x) + sx[3 * r + 0];
+                    dy = (pi.y - pj.y) + sx[3 * r + 1];
+                    dz = (pi.z - pj.z) + sx[3 * r + 2];
                 } else {
                     dx = min_image(pi.x - pj.x, v.L, v.hL);
                     dy = min_image(pi.y - pj.y, v.L, v.hL);
@@ -462,16 +471,18 @@ __global__ __launch_bounds__(kBlock) void k_walk_scratch(const double4 *__restri
         // their range lists, and walk cell by cell)
         {
             constexpr int NG = kBlock / G;
-            __shared__ int32_t s_b[NG][kRanges], s_c[NG][kRanges + 1], s_o[NG][kRanges];
+            constexpr int NR = walk_ranges<G>();
+            __shared__ int32_t s_b[NG][NR], s_c[NG][NR + 1];
+            __shared__ double s_x[NG][3 * NR];
             const int grp = threadIdx.x / G;
             if (cull)
                 walk_row_flat<G, DIRECT, true>(posH, i, pi, l, gshift, below, v, cb, ce_, nck, lx, ly, lz,
                                                mx, my, mz, cs, Hc * Hc, cap, row, goff, gidx, rcnt, eoff,
-                                               efill, etmp, cg, s_b[grp], s_c[grp], s_o[grp]);
+                                               efill, etmp, cg, s_b[grp], s_c[grp], s_x[grp]);
             else
                 walk_row_flat<G, DIRECT, false>(posH, i, pi, l, gshift, below, v, cb, ce_, nck, lx, ly, lz,
                                                 mx, my, mz, cs, INFINITY, cap, row, goff, gidx, rcnt, eoff,
-                                                efill, etmp, cg, s_b[grp], s_c[grp], s_o[grp]);
+                                                efill, etmp, cg, s_b[grp], s_c[grp], s_x[grp]);
             done = true;
         }
     }
