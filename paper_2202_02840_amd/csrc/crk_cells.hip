@@ -286,18 +286,11 @@ __device__ __forceinline__ void walk_row(const double4 *__restrict__ posH, int64
 // Flattened form of the same walk. The cells of a wavefront's groups hold
 // different numbers of particles, so a cell-by-cell loop keeps most lanes
 // idle; here a group first lists its non-empty, non-skipped cells as ranges
-// of sorted particles (in walk order, up to walk_ranges<G>() at a time, in
+// of sorted particles (in walk order, up to flat_ranges<G>() at a time, in
 // LDS, each with the image shift of its particles) and
 // then takes the concatenated candidates G at a time across cell
 // boundaries. The candidate order, hence every row, is the same as the
 // cell-by-cell walk's.
-
-// ranges a group lists per batch: two steps of G cells (at least 8), so the
-// LDS lists of a block stay near 16 KB whatever G
-template <int G>
-__host__ __device__ constexpr int walk_ranges() {
-    return 2 * G < 8 ? 8 : (2 * G > kRanges ? kRanges : 2 * G);
-}
 
 template <int G, bool DIRECT, bool CULL>
 __device__ __forceinline__ void walk_row_flat(const double4 *__restrict__ posH, int64_t i,
@@ -318,9 +311,9 @@ __device__ __forceinline__ void walk_row_flat(const double4 *__restrict__ posH, 
     const double inv_mx = 1.0 / (double)mx, inv_my = 1.0 / (double)my;
     int c0 = 0;
     while (c0 < ncell) {
-        // 1. list up to walk_ranges<G>() non-empty cells, G cells per step
+        // 1. list up to flat_ranges<G>() non-empty cells, G cells per step
         int nr = 0, cum = 0;
-        while (c0 < ncell && nr + G <= walk_ranges<G>()) {
+        while (c0 < ncell && nr + G <= flat_ranges<G>()) {
             const int cidx = c0 + l;
             int jb = 0, len = 0;
             double cx = 0.0, cy = 0.0, cz = 0.0;
@@ -471,7 +464,7 @@ __global__ __launch_bounds__(kBlock) void k_walk_scratch(const double4 *__restri
         // their range lists, and walk cell by cell)
         {
             constexpr int NG = kBlock / G;
-            constexpr int NR = walk_ranges<G>();
+            constexpr int NR = flat_ranges<G>();
             __shared__ int32_t s_b[NG][NR], s_c[NG][NR + 1];
             __shared__ double s_x[NG][3 * NR];
             const int grp = threadIdx.x / G;

@@ -317,9 +317,11 @@ __global__ __launch_bounds__(kBlock) void k_hnet_features(const double4 *__restr
     const double h = H[i];
     double s1 = 0.0, s2 = 0.0, s4 = 0.0, c1 = 0.0, c2 = 0.0;
     const double h2 = h * h, ih = 1.0 / h;
-    __shared__ int32_t s_b[kBlock / G][kRanges], s_c[kBlock / G][kRanges + 1], s_o[kBlock / G][kRanges];
+    constexpr int NR = flat_ranges<G>();
+    __shared__ int32_t s_b[kBlock / G][NR], s_c[kBlock / G][NR + 1];
+    __shared__ double s_x[kBlock / G][3 * NR];
     const int grp = threadIdx.x / G;
-    flat_candidates<G>(posH, cbeg, cend, v, i, pi, h, l, s_b[grp], s_c[grp], s_o[grp],
+    flat_candidates<G, NR>(posH, cbeg, cend, v, i, pi, h, l, s_b[grp], s_c[grp], s_x[grp],
                        [&](bool valid, double r2) {
         if (valid && r2 < h2) {
             double q = sqrt(r2) * ih;

@@ -135,13 +135,14 @@ __device__ __forceinline__ int build_row_flat(const double4 *__restrict__ posH,
                                               const int32_t *__restrict__ cend, const Levels &v,
                                               int64_t i, const double4 &pi, double R, int cap,
                                               double *row, int l, int32_t *sb, int32_t *sc,
-                                              int32_t *so) {
+                                              double *sx) {
     const double R2 = R * R;
     const int gshift = (threadIdx.x & 63) - l;
     const uint64_t gmask = ((uint64_t)1 << G) - 1;
     const uint64_t below = ((uint64_t)1 << l) - 1;
     int c = 0;
-    flat_candidates<G>(posH, cbeg, cend, v, i, pi, R, l, sb, sc, so, [&](bool valid, double r2) {
+    flat_candidates<G, flat_ranges<G>()>(posH, cbeg, cend, v, i, pi, R, l, sb, sc, sx,
+                                         [&](bool valid, double r2) {
         const bool hit = valid && r2 < R2;
         const uint64_t hm = (__ballot(hit) >> gshift) & gmask;
         if (hit) {
@@ -228,15 +229,15 @@ __device__ __forceinline__ int thacker_updates(const HsArgs &a, double &H, int &
 // A row at f H for particle i (which then serves every update with H <= f H
 // without a cell walk); when f H holds more candidates than the row, a row
 // just past H is tried (it still serves the updates that shrink H).
-// (FLAT: the flattened walk, with the group's LDS lists sb, sc, so)
+// (FLAT: the flattened walk, with the group's LDS lists sb, sc, sx)
 template <int G, bool FLAT = false>
 __device__ __forceinline__ int make_row(const HsArgs &a, int64_t i, const double4 &pi, double H,
                                         int rcap, double *row, double &Rmax, int l,
                                         int32_t *sb = nullptr, int32_t *sc = nullptr,
-                                        int32_t *so = nullptr) {
+                                        double *sx = nullptr) {
     auto build = [&](double R) {
         if constexpr (FLAT)
-            return build_row_flat<G>(a.posH, a.cbeg, a.cend, a.v, i, pi, R, rcap, row, l, sb, sc, so);
+            return build_row_flat<G>(a.posH, a.cbeg, a.cend, a.v, i, pi, R, rcap, row, l, sb, sc, sx);
         else
             return build_row<G>(a.posH, a.cbeg, a.cend, a.v, i, pi, R, rcap, row, l);
     };
@@ -347,10 +348,11 @@ __device__ __forceinline__ void narrow_body(const HsArgs &a, const int32_t *__re
     double Rmax = a.Rlist[i];
     double *row = a.rows + (size_t)i * a.cap;
     if (!(c <= a.cap && H <= Rmax)) {
-        __shared__ int32_t s_b[kBlock / G][kRanges], s_c[kBlock / G][kRanges + 1],
-            s_o[kBlock / G][kRanges];
+        constexpr int NR = flat_ranges<G>();
+        __shared__ int32_t s_b[kBlock / G][NR], s_c[kBlock / G][NR + 1];
+        __shared__ double s_x[kBlock / G][3 * NR];
         const int grp = (threadIdx.x & (kBlock - 1)) / G;
-        c = make_row<G, true>(a, i, pi, H, a.cap, row, Rmax, l, s_b[grp], s_c[grp], s_o[grp]);
+        c = make_row<G, true>(a, i, pi, H, a.cap, row, Rmax, l, s_b[grp], s_c[grp], s_x[grp]);
         if (l == 0) {
             a.rcnt[i] = c;
             a.Rlist[i] = Rmax;

@@ -200,7 +200,13 @@ __device__ __forceinline__ double cell_gap(double p, int k, double cs) {
 }
 
 // cell ranges a lane group lists in LDS at a time in the flattened walks
+// (at most; flat_ranges<G>() is two steps of G cells, at least 8, so the
+// lists of a 256-thread block stay near 16 KB whatever G)
 constexpr int kRanges = 32;
+template <int G>
+__host__ __device__ constexpr int flat_ranges() {
+    return 2 * G < 8 ? 8 : (2 * G > kRanges ? kRanges : 2 * G);
+}
 
 // exclusive prefix sum of x over a group of G lanes (total to every lane)
 template <int G>
@@ -262,25 +268,26 @@ __device__ __forceinline__ int level_for(double R, const Levels &v) {
 }
 
 // Flattened walk of the cells that a sphere of radius R about particle i
-// overlaps, by an aligned group of G lanes (4 <= G <= kRanges) of one
-// wavefront. The group lists its cells as ranges of sorted particles in
-// LDS (sb: first particle, sc: offset in the concatenation, so: image
-// code; kRanges at a time), skipping cells wholly outside R when the range
-// stays within half a period (then each listed cell carries the image shift
-// of all its particles), and then takes the concatenated candidates G at a
-// time across cell boundaries, so the loads of different cells overlap.
+// overlaps, by an aligned group of G lanes (4 <= G <= NR) of one wavefront.
+// The group lists its cells as ranges of sorted particles in LDS (sb: first
+// particle, sc[NR + 1]: offset in the concatenation, sx[3 NR]: the FP64
+// image shift of the cell's particles; NR at a time), skipping cells wholly
+// outside R when the range stays within half a period (then each listed
+// cell carries the image shift of all its particles), and then takes the
+// concatenated candidates G at a time across cell boundaries, so the loads
+// of different cells overlap.
 // visit(valid, r2) sees every batch on every lane (valid false past the
 // end; r2 the exact FP64 minimum-image r^2 with i itself included) and
 // returns true to stop the walk; its value must be the same on every lane
 // of the group.
-template <int G, typename Visit>
+template <int G, int NR, typename Visit>
 __device__ __forceinline__ void flat_candidates(const double4 *__restrict__ posH,
                                                 const int32_t *__restrict__ cbeg,
                                                 const int32_t *__restrict__ cend, const Levels &v,
                                                 int64_t i, const double4 &pi, double R, int l,
-                                                int32_t *sb, int32_t *sc, int32_t *so,
+                                                int32_t *sb, int32_t *sc, double *sx,
                                                 Visit &&visit) {
-    static_assert(G >= 4 && G <= kRanges, "the flattened walk needs 4..kRanges lanes");
+    static_assert(G >= 4 && G <= NR, "the flattened walk needs 4..NR lanes");
     const int gshift = (threadIdx.x & 63) - l;
     const uint64_t gmask = ((uint64_t)1 << G) - 1;
     const uint64_t below = ((uint64_t)1 << l) - 1;
@@ -304,9 +311,10 @@ __device__ __forceinline__ void flat_candidates(const double4 *__restrict__ posH
     bool stop = false;
     while (c0 < ncell && !stop) {
         int nr = 0, cum = 0;
-        while (c0 < ncell && nr + G <= kRanges) {
+        while (c0 < ncell && nr + G <= NR) {
             const int cidx = c0 + l;
-            int jb = 0, len = 0, code = 0;
+            int jb = 0, len = 0;
+            double cx = 0.0, cy = 0.0, cz = 0.0;
             if (cidx < ncell) {
                 // cell index -> (a, b, e); FP64 quotients, exact for these small integers
                 const int t = (int)(((double)cidx + 0.5) * inv_mx);
@@ -319,8 +327,9 @@ __device__ __forceinline__ void flat_candidates(const double4 *__restrict__ posH
                     const double gz = cell_gap(pi.z, kz, cs), gy = cell_gap(pi.y, ky, cs),
                                  gx = cell_gap(pi.x, kx, cs);
                     keep = (gz * gz + gy * gy) + gx * gx <= Rc2;
-                    code = (kx < 0 ? 1 : (kx >= nck ? 2 : 0)) | (ky < 0 ? 4 : (ky >= nck ? 8 : 0)) |
-                           (kz < 0 ? 16 : (kz >= nck ? 32 : 0));
+                    cx = kx < 0 ? L : (kx >= nck ? -L : 0.0);
+                    cy = ky < 0 ? L : (ky >= nck ? -L : 0.0);
+                    cz = kz < 0 ? L : (kz >= nck ? -L : 0.0);
                 }
                 if (keep) {
                     const uint32_t id = (spread3(wrapc(kz, nck)) << 2) | (spread3(wrapc(ky, nck)) << 1) |
@@ -337,7 +346,9 @@ __device__ __forceinline__ void flat_candidates(const double4 *__restrict__ posH
                 const int p = nr + __popcll(hm & below);
                 sb[p] = jb;
                 sc[p] = cum + pre;
-                so[p] = code;
+                sx[3 * p + 0] = cx;
+                sx[3 * p + 1] = cy;
+                sx[3 * p + 2] = cz;
             }
             nr += __popcll(hm);
             cum += tot;
@@ -357,10 +368,9 @@ __device__ __forceinline__ void flat_candidates(const double4 *__restrict__ posH
                 const double4 pj = posH[j];
                 double dx, dy, dz;
                 if (cull) {
-                    const int code = so[r];
-                    dx = (pi.x - pj.x) + ((code & 1) ? L : ((code & 2) ? -L : 0.0));
-                    dy = (pi.y - pj.y) + ((code & 4) ? L : ((code & 8) ? -L : 0.0));
-                    dz = (pi.z - pj.z) + ((code & 16) ? L : ((code & 32) ? -L : 0.0));
+                    dx = (pi.x - pj.x) + sx[3 * r + 0];
+                    dy = (pi.y - pj.y) + sx[3 * r + 1];
+                    dz = (pi.z - pj.z) + sx[3 * r + 2];
                 } else {
                     dx = min_image(pi.x - pj.x, v.L, v.hL);
                     dy = min_image(pi.y - pj.y, v.L, v.hL);
