@@ -308,6 +308,10 @@ crk_status crk_hsolve(crk_ctx *ctx, double Nres, double tol, int32_t max_iter, d
  *   f0 = ln(N_w(H)/Nres)   f1 = (Nres/N_w(H))^(1/3) - 1   f2 = ln(8 N_w(H/2)/Nres)
  *   f3 = ln(64 N_w(H/4)/Nres)   f4 = ln(n_raw(H)/Nres)   f5 = ln(8 n_raw(H/2)/Nres)
  *   f6 = ln(H n^(1/3) / L)      f7 = 1
+ * A particle whose H_sorted[i] is the support of the last crk_build_cells /
+ * crk_update_support (lists not made stale since) takes its candidates from
+ * its gather row; any other walks the cells (same values up to summation
+ * order).
  * crk_hnet_forward: y[nb] for feat[8][nb]. crk_hnet_train_step: one step of
  * mean-squared-error training on a batch (feat[8][nb], target[nb]): the batch
  * gradient (reduced in a fixed order, so deterministic) goes to grad[4801]

@@ -298,17 +298,21 @@ __global__ void k_hnet_loss(const float *__restrict__ ploss, int64_t nblk, float
     out[0] = L * inv_b;
 }
 
-// Features at radius H (one walk over the support): kernel-weighted counts
-// N_w(h) = (4 pi/3) h^3 sum W(r, h) at h = H, H/2, H/4 and raw counts within
-// H and H/2 (self included), see crk.h for the eight definitions.
+// Features at radius H: kernel-weighted counts N_w(h) = (4 pi/3) h^3 sum
+// W(r, h) at h = H, H/2, H/4 and raw counts within H and H/2 (self
+// included), see crk.h for the eight definitions. G lanes per particle
+// share the candidates and combine their five sums at the end. When the
+// last build's gather rows are given and the particle's H is the support
+// they were built with, the row is the candidate set (it holds every j with
+// r < H, self aside); otherwise a flattened walk of the support.
 template <int G>
 __global__ __launch_bounds__(kBlock) void k_hnet_features(const double4 *__restrict__ posH,
                                                           const int32_t *__restrict__ cbeg,
                                                           const int32_t *__restrict__ cend, Levels v,
                                                           int64_t n, const double *__restrict__ H,
+                                                          const int64_t *__restrict__ goff,
+                                                          const int32_t *__restrict__ gidx,
                                                           double Nres, float *feat) {
-    // G lanes per particle share a flattened walk of the support; the five
-    // sums are combined across the group at the end
     const int64_t gid = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
     const int l = (int)(gid % G);
     const int64_t i = gid / G;
@@ -317,13 +321,8 @@ __global__ __launch_bounds__(kBlock) void k_hnet_features(const double4 *__restr
     const double h = H[i];
     double s1 = 0.0, s2 = 0.0, s4 = 0.0, c1 = 0.0, c2 = 0.0;
     const double h2 = h * h, ih = 1.0 / h;
-    constexpr int NR = flat_ranges<G>();
-    __shared__ int32_t s_b[kBlock / G][NR], s_c[kBlock / G][NR + 1];
-    __shared__ double s_x[kBlock / G][3 * NR];
-    const int grp = threadIdx.x / G;
-    flat_candidates<G, NR>(posH, cbeg, cend, v, i, pi, h, l, s_b[grp], s_c[grp], s_x[grp],
-                       [&](bool valid, double r2) {
-        if (valid && r2 < h2) {
+    auto add = [&](double r2) {
+        if (r2 < h2) {
             double q = sqrt(r2) * ih;
             double w1 = 1.0 - q, w1_2 = w1 * w1;
             s1 += w1_2 * w1_2 * w1_2 * (1.0 + q * (6.0 + q * (35.0 / 3.0)));
@@ -338,8 +337,25 @@ __global__ __launch_bounds__(kBlock) void k_hnet_features(const double4 *__restr
                 }
             }
         }
-        return false;
-    });
+    };
+    constexpr int NR = flat_ranges<G>();
+    __shared__ int32_t s_b[kBlock / G][NR], s_c[kBlock / G][NR + 1];
+    __shared__ double s_x[kBlock / G][3 * NR];
+    if (goff && h == pi.w) {
+        if (l == 0) add(0.0);   // self
+        for (int64_t k = goff[i] + l; k < goff[i + 1]; k += G) {
+            const double4 pj = posH[gidx[k]];
+            add(r2_exact(min_image(pi.x - pj.x, v.L, v.hL), min_image(pi.y - pj.y, v.L, v.hL),
+                         min_image(pi.z - pj.z, v.L, v.hL)));
+        }
+    } else {
+        const int grp = threadIdx.x / G;
+        flat_candidates<G, NR>(posH, cbeg, cend, v, i, pi, h, l, s_b[grp], s_c[grp], s_x[grp],
+                               [&](bool valid, double r2) {
+                                   if (valid) add(r2);
+                                   return false;
+                               });
+    }
 #pragma unroll
     for (int m = G / 2; m >= 1; m >>= 1) {
         s1 += __shfl_xor(s1, m, G);
@@ -401,9 +417,13 @@ crk_status crk_hnet_features(crk_ctx *c, double Nres, const double *H_sorted, fl
     {
         KTimer kt_(c, "k_hnet_features");
         constexpr int GF = 8;
+        // the gather rows serve the particles whose H is the one they were
+        // built with (graph-mode lists are capacity-bound, so never those)
+        const bool rows = c->built && !c->graph_mode;
         k_hnet_features<GF><<<(unsigned)((n * GF + kBlock - 1) / kBlock), kBlock, 0, c->stream>>>(
             (const double4 *)c->posH.p, (const int32_t *)c->cbeg.p, (const int32_t *)c->cend.p,
-            levels(c), n, H_sorted, Nres, feat);
+            levels(c), n, H_sorted, rows ? (const int64_t *)c->goff.p : nullptr,
+            rows ? (const int32_t *)c->gidx.p : nullptr, Nres, feat);
     }
     CRK_HIP(c, hipGetLastError());
     return CRK_OK;

@@ -32,13 +32,18 @@ def test_features_match_oracle():
     dev = pl.upload(ps)
     ctx.build_cells(dev["x"], dev["y"], dev["z"], dev["H"], pl.params_for(ps, 64.0, CRK_FP64))
     Hs = ctx.permute(dev["H"], True)
-    f = ctx.hnet_features(64.0, Hs).double()
     perm = ctx.perm.long().cpu().numpy()
-    got = np.empty((8, ps.n))
-    got[:, perm] = f.cpu().numpy()
-    ref = oracle.hnet_features(ps.x, ps.y, ps.z, ps.H, 64.0)
-    # features are FP64 sums rounded to FP32
-    assert np.abs(got - ref).max() <= 1e-6 * max(1.0, np.abs(ref).max())
+    # at the build's supports the gather rows are the candidates; at other
+    # supports (scaled, and after the lists went stale) the cells are walked
+    for scale, stale in ((1.0, False), (1.03, False), (1.0, True)):
+        if stale:
+            ctx.hsolve(64.0, Hs.clone(), 1e-7, 5)   # leaves the lists stale
+        f = ctx.hnet_features(64.0, Hs * scale).double()
+        got = np.empty((8, ps.n))
+        got[:, perm] = f.cpu().numpy()
+        ref = oracle.hnet_features(ps.x, ps.y, ps.z, ps.H * scale, 64.0)
+        # features are FP64 sums rounded to FP32
+        assert np.abs(got - ref).max() <= 1e-6 * max(1.0, np.abs(ref).max()), (scale, stale)
 
 
 def test_forward_matches_oracle():
