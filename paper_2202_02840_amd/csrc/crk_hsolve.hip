@@ -1,11 +1,14 @@
 // S3: smoothing-length iteration, eqs. (hi) and (thacker).
 //
 // Each particle's neighbour count depends only on its own H and the fixed
-// positions, so every particle iterates on its own inside one launch: no host
-// round trip per iteration. Each iteration re-walks the cells that the
-// current support overlaps (the cell grid is fixed, the walk range follows H),
-// so H may grow past the cell side. FP64 throughout: the converged H is
-// compared across implementations at 1e-6.
+// positions, so every particle iterates on its own: a round launch takes up
+// to R updates per listed particle, stopped particles are compacted out
+// between rounds. Each particle keeps a candidate row (the distances of
+// every j within a radius a little above H), so an update re-sums W from the
+// row instead of walking the cells; a row is rebuilt when H leaves it, and a
+// support whose row would overflow goes to a wide pass (a wavefront per
+// particle, larger rows, cell walks as the last resort). FP64 throughout:
+// the converged H is compared across implementations at 1e-6.
 #include <math.h>
 
 #include "crk_internal.h"
