@@ -728,18 +728,13 @@ static crk_status build_lists(crk_ctx *c) {
             scratch, cap, n, ng, goff, (int32_t *)c->gidx.p, eoff, efill, etmp);
     }
     {
+        // the rows over the cap are few and long: 32 lanes each (the row is
+        // the same list for any lane count)
         KTimer kt_(c, "k_walk_long");
-        int G = c->G_walk;
-#define L_WALK(GG) k_walk_scratch<GG, true><<<(unsigned)((n * GG + kBlock - 1) / kBlock), kBlock, 0, c->stream>>>(posH, n, v, cbeg, cend, cap, nullptr, ng, nullptr, goff, (int32_t *)c->gidx.p, eoff, efill, etmp, c->walk_shift)
-        switch (G) {
-            case 1: L_WALK(1); break;
-            case 2: L_WALK(2); break;
-            case 4: L_WALK(4); break;
-            case 8: L_WALK(8); break;
-            case 16: L_WALK(16); break;
-            default: return set_err(c, CRK_ERR_INVALID_ARG, "walk lanes must be 1, 2, 4, 8 or 16");
-        }
-#undef L_WALK
+        constexpr int GL = 32;
+        k_walk_scratch<GL, true><<<(unsigned)((n * GL + kBlock - 1) / kBlock), kBlock, 0, c->stream>>>(
+            posH, n, v, cbeg, cend, cap, nullptr, ng, nullptr, goff, (int32_t *)c->gidx.p, eoff, efill,
+            etmp, c->walk_shift);
     }
     CRK_HIP(c, hipGetLastError());
     // each extras row ascending in the emitting particle
