@@ -68,7 +68,7 @@ def lib():
         L.orc_gradv.argtypes = [_i64, _p, _p, _p, _p, _d, _int, _p, _p, _p, _p, _p, _p, _p, _p, _p]
         L.orc_limiter.restype = _d
         L.orc_limiter.argtypes = [_d, _d, _d, _d, _d]
-        L.orc_derivatives.argtypes = [_i64, _p, _p, _p, _p, _d, _int] + [_p] * 16
+        L.orc_derivatives.argtypes = [_i64, _p, _p, _p, _p, _d, _int] + [_p] * 18
         L.orc_thacker_step.restype = _d
         L.orc_thacker_step.argtypes = [_d, _d, _d]
         L.orc_hnet_features.argtypes = [_i64, _p, _p, _p, _p, _d, _d, _p]
@@ -223,19 +223,42 @@ def params(nres: float = 64.0, **over) -> dict:
     return p
 
 
-def derivatives(x, y, z, H, v, m, u, rho, V, corr, gv, soff, sidx, prm, L=1.0, periodic=True):
-    """(dp/dt [3,n], du/dt [n], SF [n], SE [n])."""
+def derivatives(x, y, z, H, v, m, u, rho, V, corr, gv, soff, sidx, prm, L=1.0, periodic=True,
+                ts=None):
+    """(dp/dt [3,n], du/dt [n], SF [n], SE [n]); with a dict ``ts`` also the
+    time-step terms ts["vsig"] (closing speed, max over the pair set) and
+    ts["qrho"] (max over the pairs of Q_i / rho_i)."""
     x, y, z, H, v, m, u, V, gv = map(_f64, (x, y, z, H, v, m, u, V, gv))
     rho = None if rho is None else _f64(rho)
     n = x.shape[0]
     dv, du, SF, SE = np.empty((3, n)), np.empty(n), np.empty(n), np.empty(n)
+    VS, QR = (np.empty(n), np.empty(n)) if ts is not None else (None, None)
     c = [_f64(corr[k]) for k in ("A", "B", "gA", "gB")]
     pa = np.array([prm[k] for k in PARAM_KEYS], dtype=np.float64)
     lib().orc_derivatives(n, _ptr(x), _ptr(y), _ptr(z), _ptr(H), L, int(periodic), _ptr(v),
                           _ptr(m), _ptr(u), _ptr(rho), _ptr(V), *[_ptr(a) for a in c], _ptr(gv),
                           _ptr(pa), _ptr(soff), _ptr(sidx), _ptr(dv), _ptr(du), _ptr(SF),
-                          _ptr(SE))
+                          _ptr(SE), _ptr(VS), _ptr(QR))
+    if ts is not None:
+        ts["vsig"], ts["qrho"] = VS, QR
     return dv, du, SF, SE
+
+
+def timestep(H, u, m, rho, V, gv, vsig, qrho, prm, zeta=4.0, c_cfl=0.25):
+    """Courant criterion of Sec. 2.4 per particle: (v_max [n], dt_hyd [n]) with
+    v_max = max(v_sig, c_s, c_sq, (h_hat / a) |div u|), c_sq = sqrt(zeta Q/rho),
+    |div u| = |Tr grad v + 3 adot|, h_hat = H / n_h, and dt_hyd = C_CFL h_hat /
+    v_max in time (the caller applies dy/dt)."""
+    H, u, m, V = map(_f64, (H, u, m, V))
+    gv = _f64(gv).reshape(9, -1)
+    rho = m / V if rho is None else _f64(rho)
+    P = (prm["gamma"] - 1.0) * rho * u
+    cs = np.sqrt(prm["gamma"] * P / rho)
+    csq = np.sqrt(zeta * _f64(qrho))
+    hh = H / prm["nh"]
+    divu = np.abs(gv[0] + gv[4] + gv[8] + 3.0 * prm["adot"])
+    vmax = np.maximum(np.maximum(_f64(vsig), cs), np.maximum(csq, hh / prm["a"] * divu))
+    return vmax, c_cfl * hh / vmax
 
 
 def thacker_step(H, N, Nres):
@@ -273,10 +296,13 @@ def pipeline(ps, prm, periodic=True, method="auto"):
     mom = moments(x, y, z, H, V, goff, gidx, L, periodic)
     corr = corrections(mom)
     gv = gradv(x, y, z, H, ps.v, V, corr, goff, gidx, L, periodic)
+    ts = {}
     dv, du, SF, SE = derivatives(x, y, z, H, ps.v, ps.m, ps.u, ps.rho, V, corr, gv, soff, sidx,
-                                 prm, L, periodic)
+                                 prm, L, periodic, ts=ts)
+    vmax, dt = timestep(H, ps.u, ps.m, ps.rho, V, gv, ts["vsig"], ts["qrho"], prm)
     out = dict(goff=goff, gidx=gidx, soff=soff, sidx=sidx, nsum=nsum, V=V, N=N, gradv=gv,
-               dvdt=dv, dudt=du, SF=SF, SE=SE, n_pairs=int(soff[-1]))
+               dvdt=dv, dudt=du, SF=SF, SE=SE, n_pairs=int(soff[-1]), vsig=ts["vsig"],
+               qrho=ts["qrho"], vmax=vmax, dt_hyd=dt)
     out.update(mom)
     out.update(corr)
     return out

@@ -650,13 +650,18 @@ typedef struct {
 /* du_i/dt = E_i / m_i, and the conditioning sums                       */
 /*   SF_i = sum |(a^2/2) V_i V_j (P_i+Q_i+P_j+Q_j)| |D|,  SE_i = sum |E term|. */
 /* rho == NULL means rho = m / V.                                       */
+/* Time-step terms (Sec. 2.4, the signal velocity and viscous sound     */
+/* speed of the Courant criterion), when VS / QR are non-NULL:          */
+/*   w_ij = (xdot_ij + (adot/a) x_ij).x_ij / |x_ij|,                     */
+/*   VS_i = max_j max(-w_ij, 0)  (the closing speed of approaching pairs),*/
+/*   QR_i = max_j Q_i / rho_i    (Q_i of the pair, as above).            */
 /* ------------------------------------------------------------------ */
 void orc_derivatives(int64_t n, const double *x, const double *y, const double *z,
                      const double *H, double L, int periodic, const double *v, const double *m,
                      const double *u, const double *rho, const double *V, const double *A,
                      const double *B, const double *gA, const double *gB, const double *gradv,
                      const double *prm, const int64_t *soff, const int32_t *sidx,
-                     double *dvdt, double *dudt, double *SF, double *SE)
+                     double *dvdt, double *dudt, double *SF, double *SE, double *VS, double *QR)
 {
     orc_params p;
     p.gamma = prm[0]; p.Cl = prm[1]; p.Cq = prm[2]; p.eps = prm[3]; p.nh = prm[4];
@@ -668,7 +673,7 @@ void orc_derivatives(int64_t n, const double *x, const double *y, const double *
         double rhoi = rho ? rho[i] : m[i] / V[i];
         double Pi = (p.gamma - 1.0) * rhoi * u[i];
         double ci = sqrt(p.gamma * Pi / rhoi);
-        double F[3] = {0, 0, 0}, E = 0.0, sf = 0.0, se = 0.0;
+        double F[3] = {0, 0, 0}, E = 0.0, sf = 0.0, se = 0.0, vs = 0.0, qr = 0.0;
         for (int64_t k = soff[i]; k < soff[i + 1]; k++) {
             int64_t j = sidx[k];
             double d[3], md[3], Gij[3] = {0, 0, 0}, Gji[3] = {0, 0, 0};
@@ -721,11 +726,20 @@ void orc_derivatives(int64_t n, const double *x, const double *y, const double *
             E += fe * xdd;
             sf += fabs(fm) * sqrt(D[0] * D[0] + D[1] * D[1] + D[2] * D[2]);
             se += fabs(fe * xdd);
+            /* time-step terms */
+            double xd[3];
+            for (int a = 0; a < 3; a++)
+                xd[a] = (v[a * n + i] - v[a * n + j]) / p.a + (p.adot / p.a) * d[a];
+            double w = (xd[0] * d[0] + xd[1] * d[1] + xd[2] * d[2]) / r;
+            if (-w > vs) vs = -w;
+            if (Qi / rhoi > qr) qr = Qi / rhoi;
         }
         for (int a = 0; a < 3; a++) dvdt[a * n + i] = F[a] / m[i];
         dudt[i] = E / m[i];
         if (SF) SF[i] = sf;
         if (SE) SE[i] = se;
+        if (VS) VS[i] = vs;
+        if (QR) QR[i] = qr;
     }
 }
 
