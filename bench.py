@@ -193,6 +193,31 @@ def full_size_leg(args, prec, theta=None) -> dict:
     return res
 
 
+def timestep_leg(ctx, dev, prm, args, deriv_ms_plain: float) -> dict:
+    """The Courant terms of Sec. 2.4 fused into the derivative pass: the same
+    step with the terms on, the derivative pass's event time against the
+    plain one, and the per-particle combination (crk_timestep)."""
+    import torch
+    from paper_2202_02840_amd import pipeline as pl
+    for _ in range(max(args.warmup, 1)):
+        pl.step(ctx, dev, prm, count_singular=False, timestep=True)
+    torch.cuda.synchronize()
+    ctx.timing(True)
+    ctx.timing_reset()
+    for _ in range(args.steps):
+        out = pl.step(ctx, dev, prm, count_singular=False, timestep=True)
+    torch.cuda.synchronize()
+    ms, cnt = ctx.timing_read("k_deriv")
+    ctx.timing(False)
+    der = ms / max(cnt, 1)
+    vmax, dt = out["vmax"], out["dt_hyd"]
+    return {"k_deriv_ms": der, "k_deriv_ms_without": deriv_ms_plain,
+            "overhead": der / deriv_ms_plain - 1.0,
+            "vmax_range": [float(vmax.min()), float(vmax.max())],
+            "dt_hyd_range": [float(dt.min()), float(dt.max())],
+            "terms": "v_sig, c_sq (zeta 4), c_s, h_hat |div u| / a; dt_hyd = 0.25 h_hat / v_max"}
+
+
 def graph_replay_ms(ctx, io, prm, steps: int, warmup: int, box_offsets=None) -> tuple:
     """Record the step as one HIP graph on the buffers of io and time its
     replays (synchronised wall clock); returns (ms per replay, status)."""
@@ -305,6 +330,8 @@ def main():
                     help="skip the HIP-graph replay timing of the step")
     ap.add_argument("--no-batch", action="store_true", help="skip the many-box batch leg")
     ap.add_argument("--no-full-size", action="store_true", help="skip the 256^3 full-step leg")
+    ap.add_argument("--no-timestep", action="store_true",
+                    help="skip the leg timing the Courant terms fused into the derivative pass")
     ap.add_argument("--full-side", type=int, default=256)
     ap.add_argument("--batch-boxes", type=int, default=512)
     ap.add_argument("--autotune-batch", action="store_true",
@@ -445,6 +472,9 @@ def main():
     }
     log = lambda m: print(f"[bench] {m}", file=sys.stderr, flush=True)
     log(f"main step {ms_step:.3f} ms")
+    if not args.no_timestep:
+        line["timestep"] = timestep_leg(ctx, dev, prm, args, kern["k_deriv"])
+        log(f"timestep leg: derivative pass {line['timestep']['k_deriv_ms']:.3f} ms with the terms")
     if not args.no_batch:
         line["batch"] = batch_leg(args, prec, args.precision)
         log(f"batch leg {line['batch']['graph_ms_per_step']:.3f} ms per replay")

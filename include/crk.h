@@ -201,6 +201,29 @@ crk_status crk_derivatives(crk_ctx *ctx, const crk_params *p, const double *v, c
                            double *dpdt, double *dudt);
 
 /*
+ * Time-step terms of the Courant criterion (Sec. 2.4; an extension beyond
+ * the pair passes). crk_set_timestep(ctx, 1) makes every later
+ * crk_derivatives call (and a step recorded after it) also keep, per
+ * particle, the largest closing speed over its pair set, max_j max(-w_ij, 0)
+ * with w_ij = (xdot_ij + (adot/a) x_ij).x_ij / |x_ij| and xdot = v / a, and
+ * the largest Q_i / rho_i over its pairs (Q_i the pair's viscous pressure of
+ * eq. (visc)); 0 turns it off. crk_timestep then forms, in sorted order,
+ *   c_s = sqrt(gamma P / rho), c_sq = sqrt(zeta max Q_i / rho_i),
+ *   |div u| = |Tr grad v + 3 adot|, h_hat = H / n_h,
+ *   v_max = max(v_sig, c_s, c_sq, h_hat |div u| / a),
+ *   dt_hyd = C_CFL h_hat / v_max   (in time: the caller applies dy/dt),
+ * with the paper's zeta = 4 and C_CFL = 0.25 passed in. u, m, rho (NULL:
+ * rho = m/V), V and gradv are the arrays the derivative call used (gradv as
+ * it returned). vsig, csq and dt_hyd may be NULL; vmax may not. The
+ * acceleration criterion needs gravity and is not computed.
+ * Errors: CRK_ERR_STATE when the last crk_derivatives ran without the terms.
+ */
+crk_status crk_set_timestep(crk_ctx *ctx, int32_t on);
+crk_status crk_timestep(crk_ctx *ctx, const crk_params *p, const double *u, const double *m,
+                        const double *rho, const double *V, const double *gradv, double zeta,
+                        double c_cfl, double *vsig, double *csq, double *vmax, double *dt_hyd);
+
+/*
  * One whole step: S1 build (all boxes of a batch), S2 volumes, S4 moments,
  * S5 corrections, S6 velocity gradient and S7 derivatives, i.e. the calls
  * crk_build_cells_batch, crk_moments, crk_corrections, crk_derivatives in

@@ -23,7 +23,7 @@ EXPORTS = ("crk_params_default", "crk_create", "crk_destroy", "crk_last_error", 
            "crk_timing_enable", "crk_timing_reset", "crk_timing_read", "crk_adaptive_rows",
            "crk_hnet_features", "crk_hnet_forward", "crk_hnet_train_step", "crk_hnet_seed",
            "crk_hnet_targets", "crk_step", "crk_graph_capture", "crk_graph_replay",
-           "crk_graph_destroy",
+           "crk_graph_destroy", "crk_set_timestep", "crk_timestep",
            "crk_version")
 
 # members of crk_step_io, in order
@@ -97,6 +97,8 @@ def lib():
             "crk_moments": ([p, p] + [p] * 8, i32),
             "crk_corrections": ([p, i64] + [p] * 11, i32),
             "crk_derivatives": ([p, p] + [p] * 12, i32),
+            "crk_set_timestep": ([p, i32], i32),
+            "crk_timestep": ([p, p, p, p, p, p, p, d, d, p, p, p, p], i32),
             "crk_hsolve": ([p, d, d, i32, p, p, p], i32),
             "crk_export_neighbors": ([p, i32, p, p, i64, p], i32),
             "crk_set_lanes": ([p, i32, i32, i32, i32], i32),
@@ -267,6 +269,21 @@ class Context:
                                    _ptr(V), *[_ptr(corr[k]) for k in ("A", "B", "gA", "gB")],
                                    _ptr(out["gradv"]), _ptr(out["dpdt"]), _ptr(out["dudt"]))
         self._check(st, "crk_derivatives")
+        return out
+
+    def set_timestep(self, on: bool = True):
+        self._check(lib().crk_set_timestep(self._h, int(bool(on))), "crk_set_timestep")
+
+    def timestep(self, params: Params, u, m, rho, V, gradv, zeta: float = 4.0, c_cfl: float = 0.25):
+        """Courant terms after a crk_derivatives call made with set_timestep
+        on (sorted order): dict of vsig, csq, vmax, dt_hyd."""
+        _f64(u, m, rho, V, gradv)
+        n = self.n
+        out = dict(vsig=self._empty(n), csq=self._empty(n), vmax=self._empty(n), dt_hyd=self._empty(n))
+        st = lib().crk_timestep(self._h, C.byref(params), _ptr(u), _ptr(m), _ptr(rho), _ptr(V),
+                                _ptr(gradv), C.c_double(zeta), C.c_double(c_cfl), _ptr(out["vsig"]),
+                                _ptr(out["csq"]), _ptr(out["vmax"]), _ptr(out["dt_hyd"]))
+        self._check(st, "crk_timestep")
         return out
 
     # ---------------------------------------------------------------- whole step / S10 graph

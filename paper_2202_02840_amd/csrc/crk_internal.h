@@ -75,6 +75,8 @@ struct crk_ctx {
     crk::Buf scratch;                                     // walk rows before compaction
     crk::Buf hnet_part, hnet_feat;                        // network gradients / features
     crk::Buf hs_list, hs_state, hs_pos, hs_iters, hs_pool;   // smoothing-length rounds
+    crk::Buf ts_vs, ts_qr;                                   // time-step maxima per particle
+    int ts_on = 0, ts_valid = 0;
     crk::Buf hs_rows, hs_rcnt, hs_R;                      // candidate rows (r^2)
     crk::Buf boff;                                        // batch box offsets
     crk::Buf sv, sm, su, srho;                            // sorted gas state (crk_step)

@@ -526,11 +526,20 @@ struct PairConst {
     T Cl, Cq, eps2, inv_a, adot, eta_c, inv_eta_f, half_a2, half_inv_a2;
 };
 
-template <typename T>
+// With TS also the pair's time-step terms (Sec. 2.4): vs = the closing speed
+// max(-w, 0), w = (xdot_ij + (adot/a) x_ij).x_ij / r, and qr = Q_i / rho_i.
+template <typename T, bool TS = false>
 __device__ __forceinline__ void deriv_pair(const State<T> &si, const State<T> &sj, const T d[3],
-                                           const PairConst<T> &pc, T cwi, T cgi, T F[3], T &E) {
+                                           const PairConst<T> &pc, T cwi, T cgi, T F[3], T &E,
+                                           T &vs, T &qr) {
     T r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
     T r = Mth<T>::sqrt(r2);
+    if constexpr (TS) {
+        const T w = ((si.v[0] - sj.v[0]) * d[0] + (si.v[1] - sj.v[1]) * d[1] +
+                     (si.v[2] - sj.v[2]) * d[2] + pc.adot * r2) * pc.inv_a;
+        vs = w < (T)0 ? -w * Mth<T>::rcp(r) : (T)0;
+        qr = (T)0;
+    }
     T qi = r * si.invH, qj = r * sj.invH;
     T cwj = (T)kW * sj.invH * sj.invH * sj.invH;
     T cgj = (T)kG * sj.invH * sj.invH * sj.invH * sj.invH * sj.invH;
@@ -572,8 +581,10 @@ __device__ __forceinline__ void deriv_pair(const State<T> &si, const State<T> &s
     if (ud < (T)0) {
         T mui = si.hh * pc.inv_a * ud * Mth<T>::rcp(r2 + si.hh * si.hh * pc.eps2);
         T muj = sj.hh * pc.inv_a * ud * Mth<T>::rcp(r2 + sj.hh * sj.hh * pc.eps2);
-        Qi = si.rho * (-pc.Cl * si.cs * mui + pc.Cq * mui * mui);
+        const T qi = -pc.Cl * si.cs * mui + pc.Cq * mui * mui;
+        Qi = si.rho * qi;
         Qj = sj.rho * (-pc.Cl * sj.cs * muj + pc.Cq * muj * muj);
+        if constexpr (TS) qr = qi;
     }
     T fm = pc.half_a2 * si.V * sj.V * (si.P + Qi + sj.P + Qj);
     T fe = pc.half_inv_a2 * si.V * sj.V * (sj.P + Qj);
@@ -592,7 +603,7 @@ __device__ __forceinline__ PairConst<T> pair_const(const DerivPrm &p) {
 
 // Pairs with an FP64-row flag on either side (adaptive mode) are skipped
 // here and summed by k_deriv_fix.
-template <typename T, int G>
+template <typename T, int G, bool TS = false>
 __global__ __launch_bounds__(kBlock) void k_deriv(const double4 *__restrict__ posH,
                                                   const int64_t *__restrict__ goff,
                                                   const int32_t *__restrict__ gidx,
@@ -601,10 +612,12 @@ __global__ __launch_bounds__(kBlock) void k_deriv(const double4 *__restrict__ po
                                                   const int32_t *__restrict__ eidx,
                                                   const typename std::conditional<sizeof(T) == 4, float4, double4>::type *__restrict__ rec,
                                                   const double *__restrict__ m, int64_t n, Box box,
-                                                  DerivPrm p, double *dpdt, double *dudt) {
+                                                  DerivPrm p, double *dpdt, double *dudt,
+                                                  double *ts_vs = nullptr, double *ts_qr = nullptr) {
     int l;
     int64_t i = group_index(G, l);
     Acc<T> a[4];
+    T vs = (T)0, qr = (T)0;   // time-step terms: maxima over the pairs (TS)
     if (i < n) {
         double4 pi = posH[i];
         State<T> si;
@@ -630,30 +643,46 @@ __global__ __launch_bounds__(kBlock) void k_deriv(const double4 *__restrict__ po
             load_state(rec, j, sj);
             T d[3];
             separation(pi, pj, box, d[0], d[1], d[2]);
-            T F[3], E;
-            deriv_pair(si, sj, d, pc, cwi, cgi, F, E);
+            T F[3], E, pvs, pqr;
+            deriv_pair<T, TS>(si, sj, d, pc, cwi, cgi, F, E, pvs, pqr);
             if (sj.fl == (T)0) {
                 a[0].add(F[0]);
                 a[1].add(F[1]);
                 a[2].add(F[2]);
                 a[3].add(E);
+                if constexpr (TS) {
+                    vs = pvs > vs ? pvs : vs;
+                    qr = pqr > qr ? pqr : qr;
+                }
             }
         }
     }
     group_reduce<T, G, 4>(a);
+    if constexpr (TS) {
+#pragma unroll
+        for (int o = G / 2; o >= 1; o >>= 1) {
+            const T v2 = __shfl_xor(vs, o, G), q2 = __shfl_xor(qr, o, G);
+            vs = v2 > vs ? v2 : vs;
+            qr = q2 > qr ? q2 : qr;
+        }
+    }
     if (i < n && l == 0) {
         double im = 1.0 / m[i];
         dpdt[i] = a[0].value() * im;
         dpdt[n + i] = a[1].value() * im;
         dpdt[2 * n + i] = a[2].value() * im;
         dudt[i] = a[3].value() * im;
+        if constexpr (TS) {
+            ts_vs[i] = (double)vs;
+            ts_qr[i] = (double)qr;
+        }
     }
 }
 
 // FP64 rows of the adaptive mode: for each listed particle, every pair when
 // the particle itself is flagged, else only the pairs with a flagged
 // partner; the FP64 sums are added to the outputs of k_deriv.
-template <int G>
+template <int G, bool TS = false>
 __global__ __launch_bounds__(kBlock) void k_deriv_fix(const double4 *__restrict__ posH,
                                                       const int64_t *__restrict__ goff,
                                                       const int32_t *__restrict__ gidx,
@@ -664,7 +693,8 @@ __global__ __launch_bounds__(kBlock) void k_deriv_fix(const double4 *__restrict_
                                                       const int32_t *__restrict__ list, int64_t nlist,
                                                       const int64_t *__restrict__ nlist_dev,
                                                       const double *__restrict__ m, int64_t n, Box box,
-                                                      DerivPrm p, double *dpdt, double *dudt) {
+                                                      DerivPrm p, double *dpdt, double *dudt,
+                                                      double *ts_vs = nullptr, double *ts_qr = nullptr) {
     int l;
     int64_t g = group_index(G, l);
     if (nlist_dev) nlist = *nlist_dev;
@@ -672,6 +702,7 @@ __global__ __launch_bounds__(kBlock) void k_deriv_fix(const double4 *__restrict_
     for (; g < nlist; g += gstride) {
     const int64_t i = list[g];
     Acc<double> a[4];
+    double vs = 0.0, qr = 0.0;
     if (i >= 0) {
         double4 pi = posH[i];
         State<double> si;
@@ -692,23 +723,70 @@ __global__ __launch_bounds__(kBlock) void k_deriv_fix(const double4 *__restrict_
             load_state_soa(s, posH, n, j, sj);
             double d[3];
             separation(pi, pj, box, d[0], d[1], d[2]);
-            double F[3], E;
-            deriv_pair(si, sj, d, pc, cwi, cgi, F, E);
+            double F[3], E, pvs, pqr;
+            deriv_pair<double, TS>(si, sj, d, pc, cwi, cgi, F, E, pvs, pqr);
             a[0].add(F[0]);
             a[1].add(F[1]);
             a[2].add(F[2]);
             a[3].add(E);
+            if constexpr (TS) {
+                vs = fmax(vs, pvs);
+                qr = fmax(qr, pqr);
+            }
         }
     }
     group_reduce<double, G, 4>(a);
-    if (l == 0) {
+    if constexpr (TS) {
+#pragma unroll
+        for (int o = G / 2; o >= 1; o >>= 1) {
+            vs = fmax(vs, __shfl_xor(vs, o, G));
+            qr = fmax(qr, __shfl_xor(qr, o, G));
+        }
+    }
+    if (l == 0 && i >= 0) {
         double im = 1.0 / m[i];
         dpdt[i] += a[0].value() * im;
         dpdt[n + i] += a[1].value() * im;
         dpdt[2 * n + i] += a[2].value() * im;
         dudt[i] += a[3].value() * im;
+        if constexpr (TS) {
+            // the pairs k_deriv skipped: the maximum over both launches
+            ts_vs[i] = fmax(ts_vs[i], vs);
+            ts_qr[i] = fmax(ts_qr[i], qr);
+        }
     }
     }
+}
+
+// Courant criterion (Sec. 2.4) per particle from the derivative pass's
+// maxima: c_s from the gas state, c_sq = sqrt(zeta max Q/rho), |div u| =
+// |Tr grad v + 3 adot|, h_hat = H / n_h; v_max = max(v_sig, c_s, c_sq,
+// h_hat |div u| / a) and dt_hyd = C_CFL h_hat / v_max (time; the caller
+// applies dy/dt).
+__global__ __launch_bounds__(kBlock) void k_timestep(int64_t n, const double4 *__restrict__ posH,
+                                                     const double *__restrict__ u,
+                                                     const double *__restrict__ m,
+                                                     const double *__restrict__ rho,
+                                                     const double *__restrict__ V,
+                                                     const double *__restrict__ gradv,
+                                                     const double *__restrict__ tvs,
+                                                     const double *__restrict__ tqr, double gamma,
+                                                     double inv_nh, double a, double adot, double zeta,
+                                                     double c_cfl, double *vsig, double *csq,
+                                                     double *vmax, double *dt) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const double r = rho ? rho[i] : m[i] / V[i];
+    const double P = (gamma - 1.0) * r * u[i];
+    const double cs = sqrt(gamma * P / r);
+    const double cq = sqrt(zeta * tqr[i]);
+    const double hh = posH[i].w * inv_nh;
+    const double divu = fabs(gradv[i] + gradv[4 * n + i] + gradv[8 * n + i] + 3.0 * adot);
+    const double vm = fmax(fmax(tvs[i], cs), fmax(cq, hh / a * divu));
+    if (vsig) vsig[i] = tvs[i];
+    if (csq) csq[i] = cq;
+    vmax[i] = vm;
+    if (dt) dt[i] = c_cfl * hh / vm;
 }
 
 // Conditioning of particle i's RK template: the pair terms of eq. (gRK)
@@ -932,6 +1010,16 @@ crk_status crk_derivatives(crk_ctx *c, const crk_params *p, const double *v, con
     if (!c->built) return set_err(c, CRK_ERR_STATE, "crk_build_cells has not run");
     CRK_HIP(c, hipSetDevice(c->device));
     int64_t n = c->n;
+    // time-step terms (crk_set_timestep): per-particle maxima kept for crk_timestep
+    const bool ts = c->ts_on != 0;
+    double *tvs = nullptr, *tqr = nullptr;
+    if (ts) {
+        CRK_TRY(ensure(c, c->ts_vs, (size_t)n * sizeof(double)));
+        CRK_TRY(ensure(c, c->ts_qr, (size_t)n * sizeof(double)));
+        tvs = (double *)c->ts_vs.p;
+        tqr = (double *)c->ts_qr.p;
+    }
+    c->ts_valid = 0;
     Box box{c->L, 1.0 / c->L};
     const double4 *posH = (const double4 *)c->posH.p;
     const int64_t *goff = (const int64_t *)c->goff.p;
@@ -1023,7 +1111,7 @@ crk_status crk_derivatives(crk_ctx *c, const crk_params *p, const double *v, con
             KTimer kt_(c, "k_pack");
             k_pack7<float4, float><<<nblocks(n), kBlock, 0, c->stream>>>(n, posH, v, m, u, rho, V, A, B, gA, gB, gradv, dp, flag, r7, aux, bad);
         }
-#define L_DER(GG) k_deriv<float, GG><<<gblocks(n, GG), kBlock, 0, c->stream>>>(posH, goff, gidx, eb, ee, eidx, r7, m, n, box, dp, dpdt, dudt)
+#define L_DER(GG) if (ts) k_deriv<float, GG, true><<<gblocks(n, GG), kBlock, 0, c->stream>>>(posH, goff, gidx, eb, ee, eidx, r7, m, n, box, dp, dpdt, dudt, tvs, tqr); else k_deriv<float, GG><<<gblocks(n, GG), kBlock, 0, c->stream>>>(posH, goff, gidx, eb, ee, eidx, r7, m, n, box, dp, dpdt, dudt)
         {
             KTimer kt_(c, "k_deriv");
             CRK_DISPATCH_G(Gd, L_DER);
@@ -1031,7 +1119,7 @@ crk_status crk_derivatives(crk_ctx *c, const crk_params *p, const double *v, con
 #undef L_DER
         if (adapt && ntouch > 0) {
             Soa s{v, V, A, B, gA, gB, gradv, aux};
-#define L_FIX(GG) k_deriv_fix<GG><<<fix_blocks(ntouch, GG, gm), kBlock, 0, c->stream>>>(posH, goff, gidx, eb, ee, eidx, s, flag, tlist, ntouch, ntouch_dev, m, n, box, dp, dpdt, dudt)
+#define L_FIX(GG) if (ts) k_deriv_fix<GG, true><<<fix_blocks(ntouch, GG, gm), kBlock, 0, c->stream>>>(posH, goff, gidx, eb, ee, eidx, s, flag, tlist, ntouch, ntouch_dev, m, n, box, dp, dpdt, dudt, tvs, tqr); else k_deriv_fix<GG><<<fix_blocks(ntouch, GG, gm), kBlock, 0, c->stream>>>(posH, goff, gidx, eb, ee, eidx, s, flag, tlist, ntouch, ntouch_dev, m, n, box, dp, dpdt, dudt)
             KTimer kt_(c, "k_deriv_fix");
             CRK_DISPATCH_G(Gd, L_FIX);
 #undef L_FIX
@@ -1054,7 +1142,7 @@ crk_status crk_derivatives(crk_ctx *c, const crk_params *p, const double *v, con
             KTimer kt_(c, "k_pack");
             k_pack7<double4, double><<<nblocks(n), kBlock, 0, c->stream>>>(n, posH, v, m, u, rho, V, A, B, gA, gB, gradv, dp, nullptr, r7, nullptr, bad);
         }
-#define L_DER(GG) k_deriv<double, GG><<<gblocks(n, GG), kBlock, 0, c->stream>>>(posH, goff, gidx, eb, ee, eidx, r7, m, n, box, dp, dpdt, dudt)
+#define L_DER(GG) if (ts) k_deriv<double, GG, true><<<gblocks(n, GG), kBlock, 0, c->stream>>>(posH, goff, gidx, eb, ee, eidx, r7, m, n, box, dp, dpdt, dudt, tvs, tqr); else k_deriv<double, GG><<<gblocks(n, GG), kBlock, 0, c->stream>>>(posH, goff, gidx, eb, ee, eidx, r7, m, n, box, dp, dpdt, dudt)
         {
             KTimer kt_(c, "k_deriv");
             CRK_DISPATCH_G(Gd, L_DER);
@@ -1062,11 +1150,37 @@ crk_status crk_derivatives(crk_ctx *c, const crk_params *p, const double *v, con
 #undef L_DER
     }
     CRK_HIP(c, hipGetLastError());
+    c->ts_valid = ts;
     if (gm) return CRK_OK;   // the graph's status kernel reads `bad`
     int *pin = (int *)c->pinned.p + 32;
     CRK_HIP(c, hipMemcpyAsync(pin, bad, sizeof(int), hipMemcpyDeviceToHost, c->stream));
     CRK_HIP(c, hipStreamSynchronize(c->stream));
     if (pin[0]) return set_err(c, CRK_ERR_NONFINITE, "non-finite or non-positive gas state");
+    return CRK_OK;
+}
+
+crk_status crk_set_timestep(crk_ctx *c, int32_t on) {
+    if (!c) return CRK_ERR_INVALID_ARG;
+    c->ts_on = on != 0;
+    return CRK_OK;
+}
+
+crk_status crk_timestep(crk_ctx *c, const crk_params *p, const double *u, const double *m,
+                        const double *rho, const double *V, const double *gradv, double zeta,
+                        double c_cfl, double *vsig, double *csq, double *vmax, double *dt_hyd) {
+    if (!c) return CRK_ERR_INVALID_ARG;
+    if (!p || !u || !m || !V || !gradv || !vmax)
+        return set_err(c, CRK_ERR_INVALID_ARG, "crk_timestep: NULL argument");
+    if (!(zeta >= 0.0) || !(c_cfl > 0.0) || !(p->a > 0.0) || !(p->nh > 0.0) || !(p->gamma > 1.0))
+        return set_err(c, CRK_ERR_INVALID_ARG, "crk_timestep: bad parameter");
+    if (!c->ts_valid)
+        return set_err(c, CRK_ERR_STATE, "crk_timestep needs a crk_derivatives call made with crk_set_timestep on");
+    CRK_HIP(c, hipSetDevice(c->device));
+    k_timestep<<<nblocks(c->n), kBlock, 0, c->stream>>>(
+        c->n, (const double4 *)c->posH.p, u, m, rho, V, gradv, (const double *)c->ts_vs.p,
+        (const double *)c->ts_qr.p, p->gamma, 1.0 / p->nh, p->a, p->adot, zeta, c_cfl, vsig, csq, vmax,
+        dt_hyd);
+    CRK_HIP(c, hipGetLastError());
     return CRK_OK;
 }
 

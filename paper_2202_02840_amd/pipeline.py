@@ -39,9 +39,10 @@ def concat(boxes) -> tuple:
 
 
 def step(ctx: Context, dev: dict, params: Params, cell_size: float = 0.0,
-         count_singular: bool = True, box_offsets=None) -> dict:
+         count_singular: bool = True, box_offsets=None, timestep: bool = False) -> dict:
     """All passes of one step; every returned array is in cell-sorted order.
-    With box_offsets (host, nboxes+1) the arrays hold a batch of boxes."""
+    With box_offsets (host, nboxes+1) the arrays hold a batch of boxes. With
+    timestep the Courant terms (vsig, csq, vmax, dt_hyd) come along."""
     if box_offsets is None:
         perm, npairs = ctx.build_cells(dev["x"], dev["y"], dev["z"], dev["H"], params, cell_size)
     else:
@@ -53,11 +54,16 @@ def step(ctx: Context, dev: dict, params: Params, cell_size: float = 0.0,
     m = ctx.permute(dev["m"], True)
     u = ctx.permute(dev["u"], True)
     rho = None if dev.get("rho") is None else ctx.permute(dev["rho"], True)
+    if timestep:
+        ctx.set_timestep(True)
     der = ctx.derivatives(params, v, m, u, rho, mom["V"], corr)
     out = dict(perm=perm, n_pairs=npairs)
     out.update(mom)
     out.update(corr)
     out.update(der)
+    if timestep:
+        out.update(ctx.timestep(params, u, m, rho, mom["V"], der["gradv"]))
+        ctx.set_timestep(False)
     return out
 
 
