@@ -69,6 +69,8 @@ def lib():
         L.orc_limiter.restype = _d
         L.orc_limiter.argtypes = [_d, _d, _d, _d, _d]
         L.orc_derivatives.argtypes = [_i64, _p, _p, _p, _p, _d, _int] + [_p] * 18
+        L.orc_compatible_energy.argtypes = [_i64, _p, _p, _p, _p, _d, _int] + [_p] * 14 + [_d, _p]
+        L.orc_compatible_energy.restype = None
         L.orc_thacker_step.restype = _d
         L.orc_thacker_step.argtypes = [_d, _d, _d]
         L.orc_hnet_features.argtypes = [_i64, _p, _p, _p, _p, _d, _d, _p]
@@ -244,6 +246,24 @@ def derivatives(x, y, z, H, v, m, u, rho, V, corr, gv, soff, sidx, prm, L=1.0, p
     return dv, du, SF, SE
 
 
+def compatible_energy(x, y, z, H, v, m, u, rho, V, corr, gv, soff, sidx, prm, dpdt, dt, L=1.0,
+                      periodic=True):
+    """Delta u [n] of the compatible energy update over the time step dt
+    (eqs. compEng, compEng2, Eij, ptdt, fij), from the state the derivative
+    pass saw and its dp/dt [3, n]."""
+    x, y, z, H, v, m, u, V, gv, dpdt = map(_f64, (x, y, z, H, v, m, u, V, gv, dpdt))
+    rho = None if rho is None else _f64(rho)
+    n = x.shape[0]
+    du = np.empty(n)
+    c = [_f64(corr[k]) for k in ("A", "B", "gA", "gB")]
+    pa = np.array([prm[k] for k in PARAM_KEYS], dtype=np.float64)
+    lib().orc_compatible_energy(n, _ptr(x), _ptr(y), _ptr(z), _ptr(H), L, int(periodic), _ptr(v),
+                                _ptr(m), _ptr(u), _ptr(rho), _ptr(V), *[_ptr(a) for a in c],
+                                _ptr(gv), _ptr(pa), _ptr(soff), _ptr(sidx), _ptr(dpdt), float(dt),
+                                _ptr(du))
+    return du
+
+
 def timestep(H, u, m, rho, V, gv, vsig, qrho, prm, zeta=4.0, c_cfl=0.25):
     """Courant criterion of Sec. 2.4 per particle: (v_max [n], dt_hyd [n]) with
     v_max = max(v_sig, c_s, c_sq, (h_hat / a) |div u|), c_sq = sqrt(zeta Q/rho),
@@ -284,9 +304,10 @@ def hnet_features(x, y, z, H, Nres, L=1.0):
     return out
 
 
-def pipeline(ps, prm, periodic=True, method="auto"):
+def pipeline(ps, prm, periodic=True, method="auto", dt=None):
     """Every pass in the paper's data order for one particle set:
-    neighbour sets -> volume -> moments -> corrections -> grad v -> derivatives.
+    neighbour sets -> volume -> moments -> corrections -> grad v -> derivatives
+    (-> the compatible energy update over dt, when dt is given).
     Returns a dict with every intermediate (original particle order)."""
     x, y, z, H = ps.x, ps.y, ps.z, ps.H
     L = ps.L
@@ -299,10 +320,13 @@ def pipeline(ps, prm, periodic=True, method="auto"):
     ts = {}
     dv, du, SF, SE = derivatives(x, y, z, H, ps.v, ps.m, ps.u, ps.rho, V, corr, gv, soff, sidx,
                                  prm, L, periodic, ts=ts)
-    vmax, dt = timestep(H, ps.u, ps.m, ps.rho, V, gv, ts["vsig"], ts["qrho"], prm)
+    vmax, dt_hyd = timestep(H, ps.u, ps.m, ps.rho, V, gv, ts["vsig"], ts["qrho"], prm)
     out = dict(goff=goff, gidx=gidx, soff=soff, sidx=sidx, nsum=nsum, V=V, N=N, gradv=gv,
                dvdt=dv, dudt=du, SF=SF, SE=SE, n_pairs=int(soff[-1]), vsig=ts["vsig"],
-               qrho=ts["qrho"], vmax=vmax, dt_hyd=dt)
+               qrho=ts["qrho"], vmax=vmax, dt_hyd=dt_hyd)
+    if dt is not None:
+        out["du_compat"] = compatible_energy(x, y, z, H, ps.v, ps.m, ps.u, ps.rho, V, corr, gv, soff,
+                                             sidx, prm, dv, dt, L, periodic)
     out.update(mom)
     out.update(corr)
     return out

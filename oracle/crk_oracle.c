@@ -656,6 +656,116 @@ typedef struct {
 /*   VS_i = max_j max(-w_ij, 0)  (the closing speed of approaching pairs),*/
 /*   QR_i = max_j Q_i / rho_i    (Q_i of the pair, as above).            */
 /* ------------------------------------------------------------------ */
+/* The state every pair of N_s(i) reads (see orc_derivatives).         */
+typedef struct {
+    int64_t n;
+    const double *x, *y, *z, *H;
+    double L;
+    int periodic;
+    const double *v, *m, *u, *rho, *V, *A, *B, *gA, *gB, *gradv;
+    orc_params p;
+} orc_gas;
+
+/* Particle i's own terms: RK coefficients, rho, P (eq. EOS), c_s.      */
+typedef struct {
+    int64_t i;
+    double A, B[3], gA[3], gB[9], rho, P, c;
+} orc_row;
+
+static void orc_gas_init(orc_gas *g, int64_t n, const double *x, const double *y, const double *z,
+                         const double *H, double L, int periodic, const double *v, const double *m,
+                         const double *u, const double *rho, const double *V, const double *A,
+                         const double *B, const double *gA, const double *gB, const double *gradv,
+                         const double *prm)
+{
+    g->n = n; g->x = x; g->y = y; g->z = z; g->H = H; g->L = L; g->periodic = periodic;
+    g->v = v; g->m = m; g->u = u; g->rho = rho; g->V = V;
+    g->A = A; g->B = B; g->gA = gA; g->gB = gB; g->gradv = gradv;
+    g->p.gamma = prm[0]; g->p.Cl = prm[1]; g->p.Cq = prm[2]; g->p.eps = prm[3]; g->p.nh = prm[4];
+    g->p.eta_c = prm[5]; g->p.eta_f = prm[6]; g->p.a = prm[7]; g->p.adot = prm[8];
+}
+
+static void orc_row_init(const orc_gas *g, int64_t i, orc_row *ri)
+{
+    ri->i = i;
+    orc_coeffs(g->n, i, g->A, g->B, g->gA, g->gB, &ri->A, ri->B, ri->gA, ri->gB);
+    ri->rho = g->rho ? g->rho[i] : g->m[i] / g->V[i];
+    ri->P = (g->p.gamma - 1.0) * ri->rho * g->u[i];
+    ri->c = sqrt(g->p.gamma * ri->P / ri->rho);
+}
+
+/* The terms of one ordered pair (i, j), j in N_s(i):                   */
+/*   F  = (a^2/2) V_i V_j (P_i+Q_i+P_j+Q_j) D  (= m_i dp_ij/dt, eq. mom),*/
+/*   E  = (1/(2a^2)) V_i V_j (P_j+Q_j) (xdot_j - xdot_i).D  (eq. eng),   */
+/*   sf = |(a^2/2) V_i V_j (P_i+Q_i+P_j+Q_j)| |D|,                        */
+/*   w  = (xdot_ij + (adot/a) x_ij).x_ij / |x_ij|,  qr = Q_i / rho_i.     */
+typedef struct {
+    double F[3], E, sf, w, qr;
+} orc_pair_terms;
+
+static void orc_pair(const orc_gas *g, const orc_row *ri, int64_t j, orc_pair_terms *t)
+{
+    const int64_t n = g->n, i = ri->i;
+    const double *v = g->v, *gradv = g->gradv, *H = g->H, *V = g->V;
+    const orc_params p = g->p;
+    double d[3], md[3], Gij[3] = {0, 0, 0}, Gji[3] = {0, 0, 0};
+    double r2 = orc_sep(g->x, g->y, g->z, i, j, g->L, g->periodic, d);
+    double r = sqrt(r2);
+    md[0] = -d[0]; md[1] = -d[1]; md[2] = -d[2];
+    if (r2 < H[i] * H[i]) orc_rk(d, r, H[i], ri->A, ri->B, ri->gA, ri->gB, NULL, Gij);
+    if (r2 < H[j] * H[j]) {
+        double Aj, Bj[3], gAj[3], gBj[9];
+        orc_coeffs(n, j, g->A, g->B, g->gA, g->gB, &Aj, Bj, gAj, gBj);
+        orc_rk(md, r, H[j], Aj, Bj, gAj, gBj, NULL, Gji);
+    }
+    double D[3] = {Gji[0] - Gij[0], Gji[1] - Gij[1], Gji[2] - Gij[2]};
+    double rhoi = ri->rho, Pi = ri->P, ci = ri->c;
+    double rhoj = g->rho ? g->rho[j] : g->m[j] / V[j];
+    double Pj = (p.gamma - 1.0) * rhoj * g->u[j];
+    double cj = sqrt(p.gamma * Pj / rhoj);
+    /* limiter */
+    double gvi_d[3], gvj_d[3];
+    for (int a = 0; a < 3; a++) {
+        gvi_d[a] = gradv[(a * 3 + 0) * n + i] * d[0] + gradv[(a * 3 + 1) * n + i] * d[1]
+                 + gradv[(a * 3 + 2) * n + i] * d[2];
+        gvj_d[a] = gradv[(a * 3 + 0) * n + j] * d[0] + gradv[(a * 3 + 1) * n + j] * d[1]
+                 + gradv[(a * 3 + 2) * n + j] * d[2];
+    }
+    double si = d[0] * gvi_d[0] + d[1] * gvi_d[1] + d[2] * gvi_d[2];
+    double sj = d[0] * gvj_d[0] + d[1] * gvj_d[1] + d[2] * gvj_d[2];
+    double qi = r / H[i], qj = r / H[j];
+    double eta = qi < qj ? qi : qj;
+    double phi = orc_limiter(si, sj, eta, p.eta_c, p.eta_f);
+    /* projected velocity difference, eq. (hatvi) */
+    double uh[3];
+    for (int a = 0; a < 3; a++)
+        uh[a] = (v[a * n + i] - 0.5 * phi * gvi_d[a]) - (v[a * n + j] + 0.5 * phi * gvj_d[a])
+                + p.adot * d[a];
+    double ud = uh[0] * d[0] + uh[1] * d[1] + uh[2] * d[2];
+    /* viscous pressures, eqs. (visc), (mu) */
+    double hi = H[i] / p.nh, hj = H[j] / p.nh;
+    double mui = (hi / p.a) * ud / (r2 + hi * hi * p.eps * p.eps);
+    double muj = (hj / p.a) * ud / (r2 + hj * hj * p.eps * p.eps);
+    if (mui > 0.0) mui = 0.0;
+    if (muj > 0.0) muj = 0.0;
+    double Qi = rhoi * (-p.Cl * ci * mui + p.Cq * mui * mui);
+    double Qj = rhoj * (-p.Cl * cj * muj + p.Cq * muj * muj);
+    /* eq. (mom), eq. (eng) */
+    double fm = 0.5 * p.a * p.a * V[i] * V[j] * (Pi + Qi + Pj + Qj);
+    double fe = 0.5 / (p.a * p.a) * V[i] * V[j] * (Pj + Qj);
+    double xdd = ((v[0 * n + j] - v[0 * n + i]) * D[0] + (v[1 * n + j] - v[1 * n + i]) * D[1]
+                  + (v[2 * n + j] - v[2 * n + i]) * D[2]) / p.a;
+    for (int a = 0; a < 3; a++) t->F[a] = fm * D[a];
+    t->E = fe * xdd;
+    t->sf = fabs(fm) * sqrt(D[0] * D[0] + D[1] * D[1] + D[2] * D[2]);
+    /* time-step terms */
+    double xd[3];
+    for (int a = 0; a < 3; a++)
+        xd[a] = (v[a * n + i] - v[a * n + j]) / p.a + (p.adot / p.a) * d[a];
+    t->w = (xd[0] * d[0] + xd[1] * d[1] + xd[2] * d[2]) / r;
+    t->qr = Qi / rhoi;
+}
+
 void orc_derivatives(int64_t n, const double *x, const double *y, const double *z,
                      const double *H, double L, int periodic, const double *v, const double *m,
                      const double *u, const double *rho, const double *V, const double *A,
@@ -663,76 +773,22 @@ void orc_derivatives(int64_t n, const double *x, const double *y, const double *
                      const double *prm, const int64_t *soff, const int32_t *sidx,
                      double *dvdt, double *dudt, double *SF, double *SE, double *VS, double *QR)
 {
-    orc_params p;
-    p.gamma = prm[0]; p.Cl = prm[1]; p.Cq = prm[2]; p.eps = prm[3]; p.nh = prm[4];
-    p.eta_c = prm[5]; p.eta_f = prm[6]; p.a = prm[7]; p.adot = prm[8];
+    orc_gas g;
+    orc_gas_init(&g, n, x, y, z, H, L, periodic, v, m, u, rho, V, A, B, gA, gB, gradv, prm);
     #pragma omp parallel for schedule(dynamic, 64)
     for (int64_t i = 0; i < n; i++) {
-        double Ai, Bi[3], gAi[3], gBi[9];
-        orc_coeffs(n, i, A, B, gA, gB, &Ai, Bi, gAi, gBi);
-        double rhoi = rho ? rho[i] : m[i] / V[i];
-        double Pi = (p.gamma - 1.0) * rhoi * u[i];
-        double ci = sqrt(p.gamma * Pi / rhoi);
+        orc_row ri;
+        orc_row_init(&g, i, &ri);
         double F[3] = {0, 0, 0}, E = 0.0, sf = 0.0, se = 0.0, vs = 0.0, qr = 0.0;
         for (int64_t k = soff[i]; k < soff[i + 1]; k++) {
-            int64_t j = sidx[k];
-            double d[3], md[3], Gij[3] = {0, 0, 0}, Gji[3] = {0, 0, 0};
-            double r2 = orc_sep(x, y, z, i, j, L, periodic, d);
-            double r = sqrt(r2);
-            md[0] = -d[0]; md[1] = -d[1]; md[2] = -d[2];
-            if (r2 < H[i] * H[i]) orc_rk(d, r, H[i], Ai, Bi, gAi, gBi, NULL, Gij);
-            if (r2 < H[j] * H[j]) {
-                double Aj, Bj[3], gAj[3], gBj[9];
-                orc_coeffs(n, j, A, B, gA, gB, &Aj, Bj, gAj, gBj);
-                orc_rk(md, r, H[j], Aj, Bj, gAj, gBj, NULL, Gji);
-            }
-            double D[3] = {Gji[0] - Gij[0], Gji[1] - Gij[1], Gji[2] - Gij[2]};
-            double rhoj = rho ? rho[j] : m[j] / V[j];
-            double Pj = (p.gamma - 1.0) * rhoj * u[j];
-            double cj = sqrt(p.gamma * Pj / rhoj);
-            /* limiter */
-            double gvi_d[3], gvj_d[3];
-            for (int a = 0; a < 3; a++) {
-                gvi_d[a] = gradv[(a * 3 + 0) * n + i] * d[0] + gradv[(a * 3 + 1) * n + i] * d[1]
-                         + gradv[(a * 3 + 2) * n + i] * d[2];
-                gvj_d[a] = gradv[(a * 3 + 0) * n + j] * d[0] + gradv[(a * 3 + 1) * n + j] * d[1]
-                         + gradv[(a * 3 + 2) * n + j] * d[2];
-            }
-            double si = d[0] * gvi_d[0] + d[1] * gvi_d[1] + d[2] * gvi_d[2];
-            double sj = d[0] * gvj_d[0] + d[1] * gvj_d[1] + d[2] * gvj_d[2];
-            double ri = r / H[i], rj = r / H[j];
-            double eta = ri < rj ? ri : rj;
-            double phi = orc_limiter(si, sj, eta, p.eta_c, p.eta_f);
-            /* projected velocity difference, eq. (hatvi) */
-            double uh[3];
-            for (int a = 0; a < 3; a++)
-                uh[a] = (v[a * n + i] - 0.5 * phi * gvi_d[a]) - (v[a * n + j] + 0.5 * phi * gvj_d[a])
-                        + p.adot * d[a];
-            double ud = uh[0] * d[0] + uh[1] * d[1] + uh[2] * d[2];
-            /* viscous pressures, eqs. (visc), (mu) */
-            double hi = H[i] / p.nh, hj = H[j] / p.nh;
-            double mui = (hi / p.a) * ud / (r2 + hi * hi * p.eps * p.eps);
-            double muj = (hj / p.a) * ud / (r2 + hj * hj * p.eps * p.eps);
-            if (mui > 0.0) mui = 0.0;
-            if (muj > 0.0) muj = 0.0;
-            double Qi = rhoi * (-p.Cl * ci * mui + p.Cq * mui * mui);
-            double Qj = rhoj * (-p.Cl * cj * muj + p.Cq * muj * muj);
-            /* eq. (mom), eq. (eng) */
-            double fm = 0.5 * p.a * p.a * V[i] * V[j] * (Pi + Qi + Pj + Qj);
-            double fe = 0.5 / (p.a * p.a) * V[i] * V[j] * (Pj + Qj);
-            double xdd = ((v[0 * n + j] - v[0 * n + i]) * D[0] + (v[1 * n + j] - v[1 * n + i]) * D[1]
-                          + (v[2 * n + j] - v[2 * n + i]) * D[2]) / p.a;
-            for (int a = 0; a < 3; a++) F[a] += fm * D[a];
-            E += fe * xdd;
-            sf += fabs(fm) * sqrt(D[0] * D[0] + D[1] * D[1] + D[2] * D[2]);
-            se += fabs(fe * xdd);
-            /* time-step terms */
-            double xd[3];
-            for (int a = 0; a < 3; a++)
-                xd[a] = (v[a * n + i] - v[a * n + j]) / p.a + (p.adot / p.a) * d[a];
-            double w = (xd[0] * d[0] + xd[1] * d[1] + xd[2] * d[2]) / r;
-            if (-w > vs) vs = -w;
-            if (Qi / rhoi > qr) qr = Qi / rhoi;
+            orc_pair_terms t;
+            orc_pair(&g, &ri, sidx[k], &t);
+            for (int a = 0; a < 3; a++) F[a] += t.F[a];
+            E += t.E;
+            sf += t.sf;
+            se += fabs(t.E);
+            if (-t.w > vs) vs = -t.w;
+            if (t.qr > qr) qr = t.qr;
         }
         for (int a = 0; a < 3; a++) dvdt[a * n + i] = F[a] / m[i];
         dudt[i] = E / m[i];
@@ -740,6 +796,68 @@ void orc_derivatives(int64_t n, const double *x, const double *y, const double *
         if (SE) SE[i] = se;
         if (VS) VS[i] = vs;
         if (QR) QR[i] = qr;
+    }
+}
+
+/* ------------------------------------------------------------------ */
+/* Compatible energy update over one time step dt, eqs. (compEng),      */
+/* (compEng2), (Eij), (ptdt) and (fij), for every particle i:           */
+/*   p = a v, p'_k = p_k + dt dp_k/dt (eq. ptdt; dp/dt as returned by    */
+/*   orc_derivatives for the same state);                               */
+/*   for every j in N_s(i): dp_ij/dt = F_ij / m_i, the pair's term of   */
+/*   eq. (mom) with P -> P+Q, and                                       */
+/*     c_ij = (p_j + p'_j - p_i - p'_i).dp_ij/dt;                       */
+/*   Delta E_ij = m_i c_ij / (2 a^4): eq. (Eij) for any partition with  */
+/*   f_ij + f_ji = 1, because m_i dp_ij/dt = -m_j dp_ji/dt;              */
+/*   s = P / rho^gamma (thermal pressure of eq. EOS) and f_ij from the  */
+/*   four cases of eq. (fij) on the sign of Delta E_ij;                 */
+/*   Delta u_ij = f_ij c_ij / (2 a^4) (eq. compEng2);                    */
+/*   Delta u_i = dt sum_j Delta u_ij - dt (adot/a) (3(gamma-1)+2) u_i.   */
+/* The last term is the expansion term of the comoving energy equation  */
+/* taken over dt, with that equation's sign.                            */
+/* ------------------------------------------------------------------ */
+void orc_compatible_energy(int64_t n, const double *x, const double *y, const double *z,
+                           const double *H, double L, int periodic, const double *v,
+                           const double *m, const double *u, const double *rho, const double *V,
+                           const double *A, const double *B, const double *gA, const double *gB,
+                           const double *gradv, const double *prm, const int64_t *soff,
+                           const int32_t *sidx, const double *dpdt, double dt, double *du)
+{
+    orc_gas g;
+    orc_gas_init(&g, n, x, y, z, H, L, periodic, v, m, u, rho, V, A, B, gA, gB, gradv, prm);
+    const double a = g.p.a, gam = g.p.gamma;
+    const double a4 = a * a * a * a;
+    #pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t i = 0; i < n; i++) {
+        orc_row ri;
+        orc_row_init(&g, i, &ri);
+        double s_i = ri.P / pow(ri.rho, gam);
+        double pi[3], ppi[3];
+        for (int c = 0; c < 3; c++) {
+            pi[c] = a * v[c * n + i];
+            ppi[c] = pi[c] + dt * dpdt[c * n + i];
+        }
+        double sum = 0.0;
+        for (int64_t k = soff[i]; k < soff[i + 1]; k++) {
+            int64_t j = sidx[k];
+            orc_pair_terms t;
+            orc_pair(&g, &ri, j, &t);
+            double rhoj = rho ? rho[j] : m[j] / V[j];
+            double s_j = (gam - 1.0) * rhoj * u[j] / pow(rhoj, gam);
+            double cij = 0.0;
+            for (int c = 0; c < 3; c++) {
+                double pj = a * v[c * n + j];
+                double ppj = pj + dt * dpdt[c * n + j];
+                cij += (pj + ppj - pi[c] - ppi[c]) * (t.F[c] / m[i]);
+            }
+            double dE = m[i] * cij / (2.0 * a4);
+            double smin = s_i < s_j ? s_i : s_j, smax = s_i < s_j ? s_j : s_i;
+            double f;
+            if ((dE >= 0.0 && s_i >= s_j) || (dE < 0.0 && s_i < s_j)) f = smin / (s_i + s_j);
+            else f = smax / (s_i + s_j);
+            sum += f * cij / (2.0 * a4);
+        }
+        du[i] = dt * sum - dt * (g.p.adot / a) * (3.0 * (gam - 1.0) + 2.0) * u[i];
     }
 }
 
