@@ -218,6 +218,52 @@ def timestep_leg(ctx, dev, prm, args, deriv_ms_plain: float) -> dict:
             "terms": "v_sig, c_sq (zeta 4), c_s, h_hat |div u| / a; dt_hyd = 0.25 h_hat / v_max"}
 
 
+def compat_leg(ctx, dev, prm, args, deriv_ms_plain: float, dt: float = 1e-3) -> dict:
+    """The compatible energy update over a step dt (a second pair pass that
+    recomputes each pair's dp_ij/dt): its event time, its energy balance on
+    the whole workload (the thermal energy the pairs hand out against the
+    kinetic change, which cancel exactly for the method), and its error
+    against the FP64 path of the same pass on the same state."""
+    import torch
+    from paper_2202_02840_amd import CRK_FP64
+    from paper_2202_02840_amd import pipeline as pl
+    for _ in range(max(args.warmup, 1)):
+        pl.step(ctx, dev, prm, count_singular=False, compat_dt=dt)
+    torch.cuda.synchronize()
+    ctx.timing(True)
+    ctx.timing_reset()
+    for _ in range(args.steps):
+        out = pl.step(ctx, dev, prm, count_singular=False, compat_dt=dt)
+    torch.cuda.synchronize()
+    ms, cnt = ctx.timing_read("k_compat")
+    fms, fcnt = ctx.timing_read("k_compat_fix")
+    ctx.timing(False)
+    perm = out["perm"].long()
+    m = dev["m"].index_select(0, perm)
+    u = dev["u"].index_select(0, perm)
+    v = dev["v"].index_select(1, perm)
+    a = prm.a
+    p0 = a * v
+    p1 = p0 + dt * out["dpdt"]
+    dkin = (m * ((p1 * p1).sum(0) - (p0 * p0).sum(0))).sum() / (2.0 * a ** 4)
+    pair = m * (out["du_compat"] + dt * (prm.adot / a) * (3.0 * (prm.gamma - 1.0) + 2.0) * u)
+    balance = (pair.sum() + dkin).abs().item() / pair.abs().sum().item()
+    res = {"dt": dt, "k_compat_ms": ms / max(cnt, 1),
+           "k_compat_fix_ms": fms / max(fcnt, 1) if fcnt else 0.0,
+           "k_deriv_ms": deriv_ms_plain,
+           "energy_balance_rel": balance}
+    if not args.no_check:
+        p64 = type(prm).from_buffer_copy(prm)
+        p64.precision = CRK_FP64
+        from paper_2202_02840_amd import Context
+        ref = pl.step(Context(0), dev, p64, count_singular=False, compat_dt=dt)
+        torch.cuda.synchronize()
+        a_ = out["du_compat"]
+        b_ = ref["du_compat"]
+        res["max_rel_err_vs_fp64"] = (a_ - b_).abs().max().item() / b_.abs().max().item()
+    return res
+
+
 def graph_replay_ms(ctx, io, prm, steps: int, warmup: int, box_offsets=None) -> tuple:
     """Record the step as one HIP graph on the buffers of io and time its
     replays (synchronised wall clock); returns (ms per replay, status)."""
@@ -332,6 +378,8 @@ def main():
     ap.add_argument("--no-full-size", action="store_true", help="skip the 256^3 full-step leg")
     ap.add_argument("--no-timestep", action="store_true",
                     help="skip the leg timing the Courant terms fused into the derivative pass")
+    ap.add_argument("--no-compat", action="store_true",
+                    help="skip the leg timing the compatible energy pass")
     ap.add_argument("--full-side", type=int, default=256)
     ap.add_argument("--batch-boxes", type=int, default=512)
     ap.add_argument("--autotune-batch", action="store_true",
@@ -475,6 +523,9 @@ def main():
     if not args.no_timestep:
         line["timestep"] = timestep_leg(ctx, dev, prm, args, kern["k_deriv"])
         log(f"timestep leg: derivative pass {line['timestep']['k_deriv_ms']:.3f} ms with the terms")
+    if not args.no_compat:
+        line["compatible_energy"] = compat_leg(ctx, dev, prm, args, kern["k_deriv"])
+        log(f"compatible energy leg: {line['compatible_energy']['k_compat_ms']:.3f} ms")
     if not args.no_batch:
         line["batch"] = batch_leg(args, prec, args.precision)
         log(f"batch leg {line['batch']['graph_ms_per_step']:.3f} ms per replay")

@@ -224,6 +224,36 @@ crk_status crk_timestep(crk_ctx *ctx, const crk_params *p, const double *u, cons
                         double c_cfl, double *vsig, double *csq, double *vmax, double *dt_hyd);
 
 /*
+ * Compatible energy update over one time step dt (eqs. compEng, compEng2,
+ * Eij, ptdt, fij; an extension beyond the pair passes). After
+ * crk_derivatives, with the same lists and the same state arrays (v, m, u,
+ * rho, V, A, B, gA, gB, and gradv and dpdt as that call returned), writes
+ * in sorted order
+ *   du[i] = dt sum_{j in N_s(i)} f_ij c_ij / (2 a^4)
+ *           - dt (adot/a)(3(gamma-1)+2) u_i,
+ *   c_ij = (p_j + p'_j - p_i - p'_i).dp_ij/dt,  p = a v,  p' = p + dt dp/dt,
+ * where dp_ij/dt is the pair's term of eq. (mom) with P -> P+Q (recomputed
+ * pair by pair, with the same limiter and viscosity as crk_derivatives) and
+ * f_ij is the entropy partition of eq. (fij), s = P / rho^gamma: the pair's
+ * energy Delta E_ij = m_i c_ij / (2 a^4) goes to i in the share s_j/(s_i+s_j)
+ * when Delta E_ij >= 0 and s_i/(s_i+s_j) otherwise, so that f_ij + f_ji = 1
+ * and sum_i m_i du_i plus the kinetic change sum_i m_i (|p'_i|^2 - |p_i|^2) /
+ * (2 a^4) is the expansion term alone. The last term is the comoving
+ * energy equation's expansion term over dt, with that equation's sign.
+ * Precision as crk_derivatives (p->precision; the adaptive mode sums the
+ * pairs of flagged rows in FP64). Every pointer is a DEVICE array; du[n] is
+ * written. Synchronises the stream.
+ * Errors: CRK_ERR_INVALID_ARG (NULL, bad parameter, non-finite dt),
+ * CRK_ERR_STATE (no build, or called while a step is being recorded),
+ * CRK_ERR_NONFINITE (non-finite or non-positive gas state).
+ */
+crk_status crk_compatible_energy(crk_ctx *ctx, const crk_params *p, const double *v,
+                                 const double *m, const double *u, const double *rho,
+                                 const double *V, const double *A, const double *B,
+                                 const double *gA, const double *gB, const double *gradv,
+                                 const double *dpdt, double dt, double *du);
+
+/*
  * One whole step: S1 build (all boxes of a batch), S2 volumes, S4 moments,
  * S5 corrections, S6 velocity gradient and S7 derivatives, i.e. the calls
  * crk_build_cells_batch, crk_moments, crk_corrections, crk_derivatives in

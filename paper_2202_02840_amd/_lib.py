@@ -23,7 +23,7 @@ EXPORTS = ("crk_params_default", "crk_create", "crk_destroy", "crk_last_error", 
            "crk_timing_enable", "crk_timing_reset", "crk_timing_read", "crk_adaptive_rows",
            "crk_hnet_features", "crk_hnet_forward", "crk_hnet_train_step", "crk_hnet_seed",
            "crk_hnet_targets", "crk_step", "crk_graph_capture", "crk_graph_replay",
-           "crk_graph_destroy", "crk_set_timestep", "crk_timestep",
+           "crk_graph_destroy", "crk_set_timestep", "crk_timestep", "crk_compatible_energy",
            "crk_version")
 
 # members of crk_step_io, in order
@@ -99,6 +99,7 @@ def lib():
             "crk_derivatives": ([p, p] + [p] * 12, i32),
             "crk_set_timestep": ([p, i32], i32),
             "crk_timestep": ([p, p, p, p, p, p, p, d, d, p, p, p, p], i32),
+            "crk_compatible_energy": ([p, p] + [p] * 11 + [d, p], i32),
             "crk_hsolve": ([p, d, d, i32, p, p, p], i32),
             "crk_export_neighbors": ([p, i32, p, p, i64, p], i32),
             "crk_set_lanes": ([p, i32, i32, i32, i32], i32),
@@ -285,6 +286,19 @@ class Context:
                                 _ptr(out["csq"]), _ptr(out["vmax"]), _ptr(out["dt_hyd"]))
         self._check(st, "crk_timestep")
         return out
+
+    def compatible_energy(self, params: Params, v, m, u, rho, V, corr: dict, gradv, dpdt,
+                          dt: float):
+        """Delta u of the compatible energy update over dt (sorted order),
+        from the state and outputs of the preceding derivative call."""
+        _f64(v, m, u, rho, V, gradv, dpdt)
+        du = self._empty(self.n)
+        st = lib().crk_compatible_energy(self._h, C.byref(params), _ptr(v), _ptr(m), _ptr(u),
+                                         _ptr(rho), _ptr(V),
+                                         *[_ptr(corr[k]) for k in ("A", "B", "gA", "gB")],
+                                         _ptr(gradv), _ptr(dpdt), C.c_double(dt), _ptr(du))
+        self._check(st, "crk_compatible_energy")
+        return du
 
     # ---------------------------------------------------------------- whole step / S10 graph
     def step_buffers(self, dev: dict) -> dict:

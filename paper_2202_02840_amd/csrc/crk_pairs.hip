@@ -758,6 +758,136 @@ __global__ __launch_bounds__(kBlock) void k_deriv_fix(const double4 *__restrict_
     }
 }
 
+// Compatible energy update (eqs. compEng, compEng2, Eij, ptdt, fij): per
+// particle q = p + p' = 2 a v + dt dp/dt (p = a v, eq. ptdt) and the specific
+// entropy s = P / rho^gamma, FP64, then rounded to the pass's type.
+template <typename V4, typename T>
+__global__ __launch_bounds__(kBlock) void k_pack_ce(int64_t n, const double *v, const double *dpdt,
+                                                    const double *m, const double *u,
+                                                    const double *rho, const double *V, double gamma,
+                                                    double a, double dt, V4 *ce, double4 *ced) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const double r = rho ? rho[i] : m[i] / V[i];
+    const double sp = (gamma - 1.0) * u[i] * pow(r, 1.0 - gamma);
+    const double qx = 2.0 * a * v[i] + dt * dpdt[i];
+    const double qy = 2.0 * a * v[n + i] + dt * dpdt[n + i];
+    const double qz = 2.0 * a * v[2 * n + i] + dt * dpdt[2 * n + i];
+    ce[i] = V4{(T)qx, (T)qy, (T)qz, (T)sp};
+    if (ced) ced[i] = make_double4(qx, qy, qz, sp);
+}
+
+// One ordered pair of the compatible update: c = (q_j - q_i).F with F =
+// m_i dp_ij/dt of eq. (mom), so Delta E_ij = c / (2 a^4) and, from the four
+// cases of eq. (fij), f_ij = s_j / (s_i + s_j) when Delta E_ij >= 0 and
+// s_i / (s_i + s_j) otherwise; returns f_ij c.
+template <typename T, typename V4>
+__device__ __forceinline__ T compat_term(const V4 &ci, const V4 &cj, const T F[3]) {
+    const T c = (cj.x - ci.x) * F[0] + (cj.y - ci.y) * F[1] + (cj.z - ci.z) * F[2];
+    const T sh = c >= (T)0 ? cj.w : ci.w;
+    return sh * Mth<T>::rcp(ci.w + cj.w) * c;
+}
+
+// Delta u_i = dt / (2 a^4 m_i) sum_j f_ij c_ij - dt (adot/a)(3(gamma-1)+2) u_i.
+// Pairs with an FP64-row flag on either side are left to k_compat_fix.
+template <typename T, int G>
+__global__ __launch_bounds__(kBlock) void k_compat(const double4 *__restrict__ posH,
+                                                   const int64_t *__restrict__ goff,
+                                                   const int32_t *__restrict__ gidx,
+                                                   const int32_t *__restrict__ eb,
+                                                   const int32_t *__restrict__ ee,
+                                                   const int32_t *__restrict__ eidx,
+                                                   const typename std::conditional<sizeof(T) == 4, float4, double4>::type *__restrict__ rec,
+                                                   const typename std::conditional<sizeof(T) == 4, float4, double4>::type *__restrict__ ce,
+                                                   const double *__restrict__ m,
+                                                   const double *__restrict__ u, int64_t n, Box box,
+                                                   DerivPrm p, double scale, double cool, double *du) {
+    int l;
+    int64_t i = group_index(G, l);
+    Acc<T> a[1];
+    if (i < n) {
+        double4 pi = posH[i];
+        State<T> si;
+        load_state(rec, i, si);
+        const auto cei = ce[i];
+        const PairConst<T> pc = pair_const<T>(p);
+        T cwi = (T)kW * si.invH * si.invH * si.invH;
+        T cgi = (T)kG * si.invH * si.invH * si.invH * si.invH * si.invH;
+        int64_t gb = goff[i];
+        int ngi = (int)(goff[i + 1] - gb);
+        int ebi = eb[i];
+        int tot = si.fl != (T)0 ? 0 : ngi + (ee[i] - ebi);
+        int32_t jn = l < tot ? (l < ngi ? gidx[gb + l] : eidx[ebi + (l - ngi)]) : 0;
+        for (int kk = l; kk < tot; kk += G) {
+            const int32_t j = jn;
+            const int kn = kk + G;
+            if (kn < tot) jn = kn < ngi ? gidx[gb + kn] : eidx[ebi + (kn - ngi)];
+            double4 pj = posH[j];
+            State<T> sj;
+            load_state(rec, j, sj);
+            const auto cej = ce[j];
+            T d[3];
+            separation(pi, pj, box, d[0], d[1], d[2]);
+            T F[3], E, pvs, pqr;
+            deriv_pair<T, false>(si, sj, d, pc, cwi, cgi, F, E, pvs, pqr);
+            if (sj.fl == (T)0) a[0].add(compat_term<T>(cei, cej, F));
+        }
+    }
+    group_reduce<T, G, 1>(a);
+    if (i < n && l == 0) du[i] = a[0].value() * (scale / m[i]) - cool * u[i];
+}
+
+// FP64 pairs of the adaptive mode (as k_deriv_fix): adds their share of
+// the sum to the output of k_compat.
+template <int G>
+__global__ __launch_bounds__(kBlock) void k_compat_fix(const double4 *__restrict__ posH,
+                                                       const int64_t *__restrict__ goff,
+                                                       const int32_t *__restrict__ gidx,
+                                                       const int32_t *__restrict__ eb,
+                                                       const int32_t *__restrict__ ee,
+                                                       const int32_t *__restrict__ eidx, Soa s,
+                                                       const double4 *__restrict__ ced,
+                                                       const int32_t *__restrict__ flag,
+                                                       const int32_t *__restrict__ list, int64_t nlist,
+                                                       const double *__restrict__ m, int64_t n, Box box,
+                                                       DerivPrm p, double scale, double *du) {
+    int l;
+    int64_t g = group_index(G, l);
+    const int64_t gstride = (int64_t)gridDim.x * (kBlock / G);
+    for (; g < nlist; g += gstride) {
+        const int64_t i = list[g];
+        Acc<double> a[1];
+        if (i >= 0) {
+            double4 pi = posH[i];
+            State<double> si;
+            load_state_soa(s, posH, n, i, si);
+            const double4 cei = ced[i];
+            const PairConst<double> pc = pair_const<double>(p);
+            double cwi = kW * si.invH * si.invH * si.invH;
+            double cgi = kG * si.invH * si.invH * si.invH * si.invH * si.invH;
+            bool all = flag[i] != 0;
+            int64_t gb = goff[i];
+            int ngi = (int)(goff[i + 1] - gb);
+            int ebi = eb[i];
+            int tot = ngi + (ee[i] - ebi);
+            for (int kk = l; kk < tot; kk += G) {
+                int32_t j = kk < ngi ? gidx[gb + kk] : eidx[ebi + (kk - ngi)];
+                if (!all && flag[j] == 0) continue;
+                double4 pj = posH[j];
+                State<double> sj;
+                load_state_soa(s, posH, n, j, sj);
+                double d[3];
+                separation(pi, pj, box, d[0], d[1], d[2]);
+                double F[3], E, pvs, pqr;
+                deriv_pair<double, false>(si, sj, d, pc, cwi, cgi, F, E, pvs, pqr);
+                a[0].add(compat_term<double>(cei, ced[j], F));
+            }
+        }
+        group_reduce<double, G, 1>(a);
+        if (l == 0 && i >= 0) du[i] += a[0].value() * (scale / m[i]);
+    }
+}
+
 // Courant criterion (Sec. 2.4) per particle from the derivative pass's
 // maxima: c_s from the gas state, c_sq = sqrt(zeta max Q/rho), |div u| =
 // |Tr grad v + 3 adot|, h_hat = H / n_h; v_max = max(v_sig, c_s, c_sq,
@@ -997,6 +1127,62 @@ crk_status crk_corrections(crk_ctx *c, int64_t n, const double *m0, const double
     return CRK_OK;
 }
 
+// FP64 rows of the adaptive mode: flags the particles whose RK template is
+// ill-conditioned (flist) and lists every particle with a flagged pair side
+// (tlist). In graph mode the counts stay on the device.
+struct AdaptRows {
+    int32_t *flag = nullptr, *flist = nullptr, *tlist = nullptr;
+    int64_t nflag = 0, ntouch = 0;
+    const int64_t *nflag_dev = nullptr, *ntouch_dev = nullptr;
+};
+
+static crk_status adapt_rows(crk_ctx *c, const crk_params *p, const double *A, const double *B,
+                             const double *gA, const double *gB, bool gm, AdaptRows &r) {
+    const int64_t n = c->n;
+    const double4 *posH = (const double4 *)c->posH.p;
+    const int64_t *goff = (const int64_t *)c->goff.p;
+    const int32_t *gidx = (const int32_t *)c->gidx.p;
+    const int32_t *eb = (const int32_t *)c->eb.p, *ee = (const int32_t *)c->ee.p,
+                  *eidx = (const int32_t *)c->eidx.p;
+    CRK_TRY(ensure(c, c->flag, (size_t)n * sizeof(int32_t)));
+    CRK_TRY(ensure(c, c->flist, (size_t)n * sizeof(int32_t)));
+    CRK_TRY(ensure(c, c->tlist, (size_t)n * sizeof(int32_t)));
+    CRK_TRY(ensure(c, c->fpos, (size_t)(n + 1) * sizeof(int64_t)));
+    CRK_TRY(ensure(c, c->tpos, (size_t)(n + 1) * sizeof(int64_t)));
+    r.flag = (int32_t *)c->flag.p;
+    r.flist = (int32_t *)c->flist.p;
+    r.tlist = (int32_t *)c->tlist.p;
+    int64_t *fpos = (int64_t *)c->fpos.p, *tpos = (int64_t *)c->tpos.p;
+    {
+        KTimer kt_(c, "k_flag");
+        k_flag<<<nblocks(n), kBlock, 0, c->stream>>>(n, posH, A, B, gA, gB, p->kappa_max, r.flag, fpos);
+        CRK_TRY(scan_exclusive_i64(c, fpos, fpos, n + 1));
+        k_compact<<<nblocks(n), kBlock, 0, c->stream>>>(n, fpos, r.flist);
+        k_zero_i64<<<nblocks(n + 1), kBlock, 0, c->stream>>>(tpos, n + 1);
+        k_mark<<<nblocks(n), kBlock, 0, c->stream>>>(r.flist, fpos, n, goff, gidx, eb, ee, eidx, tpos);
+        CRK_TRY(scan_exclusive_i64(c, tpos, tpos, n + 1));
+        k_compact<<<nblocks(n), kBlock, 0, c->stream>>>(n, tpos, r.tlist);
+    }
+    CRK_HIP(c, hipGetLastError());
+    if (gm) {
+        // row counts stay on the device; the fix launches loop over them
+        r.nflag_dev = fpos + n;
+        r.ntouch_dev = tpos + n;
+        r.nflag = r.ntouch = n;
+        c->last_nflag = c->last_ntouch = -1;
+    } else {
+        int64_t *pin = (int64_t *)c->pinned.p + 40;
+        CRK_HIP(c, hipMemcpyAsync(pin, fpos + n, sizeof(int64_t), hipMemcpyDeviceToHost, c->stream));
+        CRK_HIP(c, hipMemcpyAsync(pin + 1, tpos + n, sizeof(int64_t), hipMemcpyDeviceToHost, c->stream));
+        CRK_HIP(c, hipStreamSynchronize(c->stream));
+        r.nflag = pin[0];
+        r.ntouch = pin[1];
+        c->last_nflag = r.nflag;
+        c->last_ntouch = r.ntouch;
+    }
+    return CRK_OK;
+}
+
 crk_status crk_derivatives(crk_ctx *c, const crk_params *p, const double *v, const double *m,
                            const double *u, const double *rho, const double *V, const double *A,
                            const double *B, const double *gA, const double *gB, double *gradv,
@@ -1036,48 +1222,12 @@ crk_status crk_derivatives(crk_ctx *c, const crk_params *p, const double *v, con
     int Gg = c->G_grad, Gd = c->G_der;
 
     // adaptive mode: FP64 rows for ill-conditioned RK templates
-    int32_t *flag = nullptr, *flist = nullptr, *tlist = nullptr;
-    int64_t nflag = 0, ntouch = 0;
     const bool gm = c->graph_mode != 0;
-    const int64_t *nflag_dev = nullptr, *ntouch_dev = nullptr;
-    if (adapt) {
-        CRK_TRY(ensure(c, c->flag, (size_t)n * sizeof(int32_t)));
-        CRK_TRY(ensure(c, c->flist, (size_t)n * sizeof(int32_t)));
-        CRK_TRY(ensure(c, c->tlist, (size_t)n * sizeof(int32_t)));
-        CRK_TRY(ensure(c, c->fpos, (size_t)(n + 1) * sizeof(int64_t)));
-        CRK_TRY(ensure(c, c->tpos, (size_t)(n + 1) * sizeof(int64_t)));
-        flag = (int32_t *)c->flag.p;
-        flist = (int32_t *)c->flist.p;
-        tlist = (int32_t *)c->tlist.p;
-        int64_t *fpos = (int64_t *)c->fpos.p, *tpos = (int64_t *)c->tpos.p;
-        {
-            KTimer kt_(c, "k_flag");
-            k_flag<<<nblocks(n), kBlock, 0, c->stream>>>(n, posH, A, B, gA, gB, p->kappa_max, flag, fpos);
-            CRK_TRY(scan_exclusive_i64(c, fpos, fpos, n + 1));
-            k_compact<<<nblocks(n), kBlock, 0, c->stream>>>(n, fpos, flist);
-            k_zero_i64<<<nblocks(n + 1), kBlock, 0, c->stream>>>(tpos, n + 1);
-            k_mark<<<nblocks(n), kBlock, 0, c->stream>>>(flist, fpos, n, goff, gidx, eb, ee, eidx, tpos);
-            CRK_TRY(scan_exclusive_i64(c, tpos, tpos, n + 1));
-            k_compact<<<nblocks(n), kBlock, 0, c->stream>>>(n, tpos, tlist);
-        }
-        CRK_HIP(c, hipGetLastError());
-        if (gm) {
-            // row counts stay on the device; the fix launches loop over them
-            nflag_dev = fpos + n;
-            ntouch_dev = tpos + n;
-            nflag = ntouch = n;
-            c->last_nflag = c->last_ntouch = -1;
-        } else {
-            int64_t *pin = (int64_t *)c->pinned.p + 40;
-            CRK_HIP(c, hipMemcpyAsync(pin, fpos + n, sizeof(int64_t), hipMemcpyDeviceToHost, c->stream));
-            CRK_HIP(c, hipMemcpyAsync(pin + 1, tpos + n, sizeof(int64_t), hipMemcpyDeviceToHost, c->stream));
-            CRK_HIP(c, hipStreamSynchronize(c->stream));
-            nflag = pin[0];
-            ntouch = pin[1];
-            c->last_nflag = nflag;
-            c->last_ntouch = ntouch;
-        }
-    }
+    AdaptRows ar;
+    if (adapt) CRK_TRY(adapt_rows(c, p, A, B, gA, gB, gm, ar));
+    int32_t *flag = ar.flag, *flist = ar.flist, *tlist = ar.tlist;
+    const int64_t nflag = ar.nflag, ntouch = ar.ntouch;
+    const int64_t *nflag_dev = ar.nflag_dev, *ntouch_dev = ar.ntouch_dev;
 
     if (f32) {
         CRK_TRY(ensure(c, c->rec6, (size_t)n * sizeof(float4)));
@@ -1181,6 +1331,94 @@ crk_status crk_timestep(crk_ctx *c, const crk_params *p, const double *u, const 
         (const double *)c->ts_qr.p, p->gamma, 1.0 / p->nh, p->a, p->adot, zeta, c_cfl, vsig, csq, vmax,
         dt_hyd);
     CRK_HIP(c, hipGetLastError());
+    return CRK_OK;
+}
+
+crk_status crk_compatible_energy(crk_ctx *c, const crk_params *p, const double *v, const double *m,
+                                 const double *u, const double *rho, const double *V,
+                                 const double *A, const double *B, const double *gA,
+                                 const double *gB, const double *gradv, const double *dpdt,
+                                 double dt, double *du) {
+    if (!c) return CRK_ERR_INVALID_ARG;
+    if (!p || !v || !m || !u || !V || !A || !B || !gA || !gB || !gradv || !dpdt || !du)
+        return set_err(c, CRK_ERR_INVALID_ARG, "crk_compatible_energy: NULL argument");
+    if (!valid_prec(p->precision)) return set_err(c, CRK_ERR_INVALID_ARG, "bad precision");
+    if (!(p->a > 0.0) || !(p->nh > 0.0) || !(p->eta_fold > 0.0) || !(p->gamma > 1.0) ||
+        !isfinite(dt) || !isfinite(p->adot))
+        return set_err(c, CRK_ERR_INVALID_ARG, "crk_compatible_energy: bad parameter");
+    if (!c->built) return set_err(c, CRK_ERR_STATE, "crk_build_cells has not run");
+    if (c->capturing) return set_err(c, CRK_ERR_STATE, "crk_compatible_energy is not recorded in a graph");
+    CRK_HIP(c, hipSetDevice(c->device));
+    const int64_t n = c->n;
+    Box box{c->L, 1.0 / c->L};
+    const double4 *posH = (const double4 *)c->posH.p;
+    const int64_t *goff = (const int64_t *)c->goff.p;
+    const int32_t *gidx = (const int32_t *)c->gidx.p;
+    const int32_t *eb = (const int32_t *)c->eb.p, *ee = (const int32_t *)c->ee.p,
+                  *eidx = (const int32_t *)c->eidx.p;
+    const bool f32 = p->precision != CRK_FP64;
+    const bool adapt = p->precision == CRK_MIXED_ADAPT;
+    DerivPrm dp{p->gamma, p->Cl, p->Cq, p->eps * p->eps, 1.0 / p->nh, 1.0 / p->a,
+                0.5 * p->a * p->a, 0.5 / (p->a * p->a), p->adot, p->eta_crit, 1.0 / p->eta_fold};
+    const double a4 = p->a * p->a * p->a * p->a;
+    const double scale = dt / (2.0 * a4);
+    const double cool = dt * (p->adot / p->a) * (3.0 * (p->gamma - 1.0) + 2.0);
+    CRK_TRY(ensure(c, c->misc, 256));
+    int *bad = (int *)c->misc.p + 2;
+    CRK_TRY(zero_async(c, bad, 1));
+    const int Gd = c->G_der;
+    AdaptRows ar;
+    if (adapt) CRK_TRY(adapt_rows(c, p, A, B, gA, gB, false, ar));
+    if (f32) {
+        CRK_TRY(ensure(c, c->rec7, (size_t)n * kRec7 * sizeof(float4)));
+        CRK_TRY(ensure(c, c->ce, (size_t)n * sizeof(float4)));
+        float4 *r7 = (float4 *)c->rec7.p, *ce = (float4 *)c->ce.p;
+        double4 *aux = nullptr, *ced = nullptr;
+        if (adapt) {
+            CRK_TRY(ensure(c, c->aux, (size_t)n * sizeof(double4)));
+            CRK_TRY(ensure(c, c->ced, (size_t)n * sizeof(double4)));
+            aux = (double4 *)c->aux.p;
+            ced = (double4 *)c->ced.p;
+        }
+        {
+            KTimer kt_(c, "k_pack");
+            k_pack7<float4, float><<<nblocks(n), kBlock, 0, c->stream>>>(n, posH, v, m, u, rho, V, A, B, gA, gB, gradv, dp, ar.flag, r7, aux, bad);
+            k_pack_ce<float4, float><<<nblocks(n), kBlock, 0, c->stream>>>(n, v, dpdt, m, u, rho, V, p->gamma, p->a, dt, ce, ced);
+        }
+#define L_CE(GG) k_compat<float, GG><<<gblocks(n, GG), kBlock, 0, c->stream>>>(posH, goff, gidx, eb, ee, eidx, r7, ce, m, u, n, box, dp, scale, cool, du)
+        {
+            KTimer kt_(c, "k_compat");
+            CRK_DISPATCH_G(Gd, L_CE);
+        }
+#undef L_CE
+        if (adapt && ar.ntouch > 0) {
+            Soa s{v, V, A, B, gA, gB, gradv, aux};
+#define L_CEF(GG) k_compat_fix<GG><<<fix_blocks(ar.ntouch, GG, false), kBlock, 0, c->stream>>>(posH, goff, gidx, eb, ee, eidx, s, ced, ar.flag, ar.tlist, ar.ntouch, m, n, box, dp, scale, du)
+            KTimer kt_(c, "k_compat_fix");
+            CRK_DISPATCH_G(Gd, L_CEF);
+#undef L_CEF
+        }
+    } else {
+        CRK_TRY(ensure(c, c->rec7, (size_t)n * kRec7 * sizeof(double4)));
+        CRK_TRY(ensure(c, c->ce, (size_t)n * sizeof(double4)));
+        double4 *r7 = (double4 *)c->rec7.p, *ce = (double4 *)c->ce.p;
+        {
+            KTimer kt_(c, "k_pack");
+            k_pack7<double4, double><<<nblocks(n), kBlock, 0, c->stream>>>(n, posH, v, m, u, rho, V, A, B, gA, gB, gradv, dp, nullptr, r7, nullptr, bad);
+            k_pack_ce<double4, double><<<nblocks(n), kBlock, 0, c->stream>>>(n, v, dpdt, m, u, rho, V, p->gamma, p->a, dt, ce, nullptr);
+        }
+#define L_CE(GG) k_compat<double, GG><<<gblocks(n, GG), kBlock, 0, c->stream>>>(posH, goff, gidx, eb, ee, eidx, r7, ce, m, u, n, box, dp, scale, cool, du)
+        {
+            KTimer kt_(c, "k_compat");
+            CRK_DISPATCH_G(Gd, L_CE);
+        }
+#undef L_CE
+    }
+    CRK_HIP(c, hipGetLastError());
+    int *pin = (int *)c->pinned.p + 32;
+    CRK_HIP(c, hipMemcpyAsync(pin, bad, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    CRK_HIP(c, hipStreamSynchronize(c->stream));
+    if (pin[0]) return set_err(c, CRK_ERR_NONFINITE, "non-finite or non-positive gas state");
     return CRK_OK;
 }
 

@@ -39,10 +39,12 @@ def concat(boxes) -> tuple:
 
 
 def step(ctx: Context, dev: dict, params: Params, cell_size: float = 0.0,
-         count_singular: bool = True, box_offsets=None, timestep: bool = False) -> dict:
+         count_singular: bool = True, box_offsets=None, timestep: bool = False,
+         compat_dt: float = None) -> dict:
     """All passes of one step; every returned array is in cell-sorted order.
     With box_offsets (host, nboxes+1) the arrays hold a batch of boxes. With
-    timestep the Courant terms (vsig, csq, vmax, dt_hyd) come along."""
+    timestep the Courant terms (vsig, csq, vmax, dt_hyd) come along; with
+    compat_dt the compatible energy update over that step (du_compat)."""
     if box_offsets is None:
         perm, npairs = ctx.build_cells(dev["x"], dev["y"], dev["z"], dev["H"], params, cell_size)
     else:
@@ -64,6 +66,9 @@ def step(ctx: Context, dev: dict, params: Params, cell_size: float = 0.0,
     if timestep:
         out.update(ctx.timestep(params, u, m, rho, mom["V"], der["gradv"]))
         ctx.set_timestep(False)
+    if compat_dt is not None:
+        out["du_compat"] = ctx.compatible_energy(params, v, m, u, rho, mom["V"], corr, der["gradv"],
+                                                 der["dpdt"], compat_dt)
     return out
 
 

@@ -46,3 +46,24 @@ def test_no_gpu_fails_loudly():
         pytest.skip("a GPU is present")
     with pytest.raises(RuntimeError):
         crk.Context(0)
+
+
+def _prototypes():
+    """name -> number of parameters of each function include/crk.h declares."""
+    src = open(os.path.join(ROOT, "include", "crk.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    out = {}
+    for name, args in re.findall(r"\b(crk_[a-z_]+)\s*\(([^;{]*?)\)\s*;", src, flags=re.S):
+        args = args.strip()
+        out[name] = 0 if args in ("", "void") else args.count(",") + 1
+    return out
+
+
+def test_binding_signatures_match_the_header():
+    """The ctypes binding passes as many arguments as each prototype takes."""
+    import paper_2202_02840_amd as crk
+    L = crk._lib.lib()
+    protos = _prototypes()
+    assert set(protos) == set(_declared())
+    for name, nargs in protos.items():
+        assert len(getattr(L, name).argtypes) == nargs, name
