@@ -332,6 +332,47 @@ def pipeline(ps, prm, periodic=True, method="auto", dt=None):
     return out
 
 
+# ------------------------------------------------------ velocity Verlet
+def verlet_step(ps, prm, dt, d0=None, periodic=True):
+    """One step of the velocity-Verlet hydro operator, eq. verletOP, with the
+    time step dt = (dt/dy) Delta y and a, adot held over the step. With
+    p = a v and D = (dp/dt, du/dt) from the derivative pass (eqs. mom, eng):
+      p^1/2 = p^0 + dt/2 dp/dt(0),      u^1/2 = u^0 + dt/2 du/dt(0),
+      x^1   = x^0 + p^1/2 dt / a^2      (wrapped into [0, L) when periodic),
+      p_p   = p^1/2 + dt/2 dp/dt(0),    u_p   = u^1/2 + dt/2 du/dt(0),
+      D(1)  = D at (x^1, p_p, u_p) with the same H, m (and rho if given),
+      p^1   = p^1/2 + dt/2 dp/dt(1),    u^1   = u^1/2 + dt/2 du/dt(1).
+    d0 is D at the start state (dict with dvdt, dudt); None evaluates it.
+    Returns (state, D(1)): state is a namespace like ps at the end of the
+    step (v = p / a); D(1) is the derivative pass's output there."""
+    from types import SimpleNamespace
+    a = prm["a"]
+    L = ps.L
+    if d0 is None:
+        d0 = pipeline(ps, prm, periodic)
+    k = 0.5 * dt
+    c = dt / (a * a)
+    ph = a * np.asarray(ps.v, dtype=np.float64) + k * d0["dvdt"]
+    uh = np.asarray(ps.u, dtype=np.float64) + k * d0["dudt"]
+    x1 = []
+    for q, comp in ((ps.x, 0), (ps.y, 1), (ps.z, 2)):
+        xn = np.asarray(q, dtype=np.float64) + ph[comp] * c
+        if periodic:
+            xn = np.where(xn < 0.0, xn + L, xn)
+            xn = np.where(xn >= L, xn - L, xn)
+        x1.append(xn)
+    pp = ph + k * d0["dvdt"]
+    up = uh + k * d0["dudt"]
+    mid = SimpleNamespace(x=x1[0], y=x1[1], z=x1[2], H=ps.H, m=ps.m, u=up, v=pp / a,
+                          rho=ps.rho, L=L, gamma=getattr(ps, "gamma", prm["gamma"]))
+    d1 = pipeline(mid, prm, periodic)
+    p1 = ph + k * d1["dvdt"]
+    u1 = uh + k * d1["dudt"]
+    end = SimpleNamespace(x=x1[0], y=x1[1], z=x1[2], H=ps.H, m=ps.m, u=u1, v=p1 / a,
+                          rho=ps.rho, L=L, gamma=mid.gamma)
+    return end, d1
+
+
 # ------------------------------------------------------ sampled evaluation
 def rows_for(x, y, z, H, which, targets, L=1.0):
     """CSR rows of N_g (which 0, self included) or N_s (which 1) for the
