@@ -264,6 +264,40 @@ def compat_leg(ctx, dev, prm, args, deriv_ms_plain: float, dt: float = 1e-3) -> 
     return res
 
 
+def verlet_leg(ctx, dev, prm, args, dt: float = 1e-4) -> dict:
+    """Velocity-Verlet hydro steps (eq. verletOP) on the workload: each step
+    is the half kicks and drift around one whole evaluation at the predicted
+    state; reports the wall time per step, the elementwise kernels' share and
+    the change of the total energy sum m (u + |p|^2 / (2 a^4)) over the run."""
+    import torch
+    n = dev["x"].shape[0]
+    st = {k: dev[k].clone() for k in ("x", "y", "z", "H", "v", "m", "u")}
+    st["rho"] = None if dev.get("rho") is None else dev["rho"]
+    st["dpdt"] = torch.zeros(3, n, dtype=torch.float64, device="cuda")
+    st["dudt"] = torch.zeros(n, dtype=torch.float64, device="cuda")
+    a = prm.a
+
+    def energy():
+        return (st["m"] * (st["u"] + (a * st["v"]).pow(2).sum(0) / (2.0 * a ** 4))).sum().item()
+
+    ctx.verlet_step(st, prm, dt, start_eval=True)
+    e0 = energy()
+    torch.cuda.synchronize()
+    ctx.timing(True)
+    ctx.timing_reset()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ctx.verlet_step(st, prm, dt)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / max(args.steps, 1)
+    vms, vcnt = ctx.timing_read("k_verlet")
+    ctx.timing(False)
+    e1 = energy()
+    return {"dt": dt, "steps": args.steps, "ms_per_step": ms,
+            "k_verlet_ms_per_step": vms / max(args.steps, 1),
+            "energy_rel_change": abs(e1 - e0) / abs(e0)}
+
+
 def graph_replay_ms(ctx, io, prm, steps: int, warmup: int, box_offsets=None) -> tuple:
     """Record the step as one HIP graph on the buffers of io and time its
     replays (synchronised wall clock); returns (ms per replay, status)."""
@@ -380,6 +414,8 @@ def main():
                     help="skip the leg timing the Courant terms fused into the derivative pass")
     ap.add_argument("--no-compat", action="store_true",
                     help="skip the leg timing the compatible energy pass")
+    ap.add_argument("--no-verlet", action="store_true",
+                    help="skip the leg timing velocity-Verlet hydro steps")
     ap.add_argument("--full-side", type=int, default=256)
     ap.add_argument("--batch-boxes", type=int, default=512)
     ap.add_argument("--autotune-batch", action="store_true",
@@ -526,6 +562,9 @@ def main():
     if not args.no_compat:
         line["compatible_energy"] = compat_leg(ctx, dev, prm, args, kern["k_deriv"])
         log(f"compatible energy leg: {line['compatible_energy']['k_compat_ms']:.3f} ms")
+    if not args.no_verlet:
+        line["verlet"] = verlet_leg(ctx, dev, prm, args)
+        log(f"verlet leg: {line['verlet']['ms_per_step']:.3f} ms per step")
     if not args.no_batch:
         line["batch"] = batch_leg(args, prec, args.precision)
         log(f"batch leg {line['batch']['graph_ms_per_step']:.3f} ms per replay")

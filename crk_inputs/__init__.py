@@ -24,7 +24,7 @@ import numpy as np
 
 __all__ = [
     "ParticleSet", "philox", "lattice_box", "lognormal_box", "clustered_clump_box",
-    "batch_boxes", "support_for_neighbours", "hnet_init",
+    "batch_boxes", "support_for_neighbours", "hnet_init", "sod_tube",
 ]
 
 
@@ -269,3 +269,34 @@ def hnet_init(seed: int = 0, n_in: int = 8, n_hidden: int = 64) -> np.ndarray:
         else:
             parts.append(np.zeros(int(np.prod(shp))))
     return np.concatenate(parts)
+
+
+def sod_tube(n_high: int = 20, nngb: float = 64.0, gamma: float = 5.0 / 3.0) -> ParticleSet:
+    """Shock tube with two Riemann interfaces in the periodic cube [0, 2)^3.
+
+    High state (rho = 1, P = 1) in x in [0, 0.5) and [1.5, 2), low state
+    (rho = 1/8, P = 1/8) in [0.5, 1.5): the same temperature on both sides,
+    so u = P / ((gamma - 1) rho) is uniform. Equal-mass particles on cubic
+    lattices of spacing d = 0.5 / n_high (high) and 2 d (low), so the 3D
+    density ratio is 8 and the tube is n_high + n_high/2 particles long over
+    [0, 1). The interfaces are sharp (a step function); the gas is at rest.
+    H holds ``nngb`` lattice neighbours of each side.
+    """
+    L = 2.0
+    d = 0.5 / n_high
+    parts = []
+    for x0, x1, sp in ((0.0, 0.5, d), (0.5, 1.5, 2.0 * d), (1.5, 2.0, d)):
+        nx = int(round((x1 - x0) / sp))
+        ny = int(round(L / sp))
+        gx = x0 + (np.arange(nx) + 0.5) * sp
+        gy = (np.arange(ny) + 0.5) * sp
+        X, Y, Z = np.meshgrid(gx, gy, gy, indexing="ij")
+        Hs = support_for_neighbours(nngb, 1.0 / sp ** 3)
+        parts.append((X.ravel(), Y.ravel(), Z.ravel(), np.full(X.size, float(Hs))))
+    x, y, z, H = (np.concatenate([q[k] for q in parts]) for k in range(4))
+    n = x.shape[0]
+    m = np.full(n, d ** 3)
+    u = np.full(n, 1.0 / (gamma - 1.0))
+    v = np.zeros((3, n))
+    return ParticleSet(x, y, z, H, m, u, v, None, L=L, gamma=gamma,
+                       meta=dict(kind="sod", n_high=n_high, spacing=d))

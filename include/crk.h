@@ -281,6 +281,40 @@ crk_status crk_step(crk_ctx *ctx, int32_t nboxes, const int64_t *box_offsets, in
                     const crk_step_io *io, const crk_params *p, double cell_size,
                     int64_t *n_pairs, int64_t *n_singular);
 
+/*
+ * Velocity-Verlet hydro step, eq. (verletOP) (an extension beyond the pair
+ * passes). With p = a v, D = (dp/dt, du/dt) of crk_derivatives and the time
+ * step dt = (dt/dy) Delta y (a and adot held over the step):
+ *   p^1/2 = p + dt/2 dp/dt(0),   u^1/2 = u + dt/2 du/dt(0),
+ *   x^1   = x + p^1/2 dt / a^2   (wrapped once into [0, L)),
+ *   p_p   = p^1/2 + dt/2 dp/dt(0), u_p = u^1/2 + dt/2 du/dt(0),
+ *   D(1)  = the whole step (crk_step) at (x^1, p_p / a, u_p) with H, m, rho,
+ *   p^1   = p^1/2 + dt/2 dp/dt(1), u^1 = u^1/2 + dt/2 du/dt(1).
+ * Every array is a caller-owned DEVICE array in the caller's particle order;
+ * x, y, z, v, u are advanced in place. dpdt/dudt hold D at the start state
+ * on entry (start_eval = 0; with start_eval = 1 the library evaluates it
+ * first) and D at the end state on return, ready for the next step. The
+ * products and sums of the kicks and the drift are rounded one by one (no
+ * fused multiply-add). box_offsets: HOST int64 [nboxes+1] as in
+ * crk_build_cells_batch. *n_pairs (host, may be NULL): pairs of the end
+ * evaluation. Synchronises the stream. Errors: those of crk_step (a particle
+ * that moves more than L in one step fails its position check), and
+ * CRK_ERR_STATE while a step is being recorded.
+ */
+typedef struct {
+    double *x, *y, *z;    /* [n] in/out positions in [0, L)                    */
+    const double *H;      /* [n] support radii, held over the step              */
+    double *v;            /* [3][n] in/out peculiar velocity (p = a v)          */
+    const double *m;      /* [n] masses                                         */
+    double *u;            /* [n] in/out specific internal energies              */
+    const double *rho;    /* [n] densities or NULL (rho = m / V at evaluation)  */
+    double *dpdt, *dudt;  /* [3][n], [n] in/out: D at the start / at the end     */
+} crk_verlet_io;
+
+crk_status crk_verlet_step(crk_ctx *ctx, int32_t nboxes, const int64_t *box_offsets, int64_t n,
+                           const crk_verlet_io *io, const crk_params *p, double cell_size,
+                           double dt, int32_t start_eval, int64_t *n_pairs);
+
 /* Device-side status of a replayed step (filled by crk_graph_replay). */
 typedef struct {
     int64_t n_pairs;        /* ordered pairs of the replayed lists           */

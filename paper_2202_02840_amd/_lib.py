@@ -24,6 +24,7 @@ EXPORTS = ("crk_params_default", "crk_create", "crk_destroy", "crk_last_error", 
            "crk_hnet_features", "crk_hnet_forward", "crk_hnet_train_step", "crk_hnet_seed",
            "crk_hnet_targets", "crk_step", "crk_graph_capture", "crk_graph_replay",
            "crk_graph_destroy", "crk_set_timestep", "crk_timestep", "crk_compatible_energy",
+           "crk_verlet_step",
            "crk_version")
 
 # members of crk_step_io, in order
@@ -34,6 +35,13 @@ STEP_OUTPUTS = ("perm", "V", "m0", "m1", "m2", "gm0", "gm1", "gm2", "A", "B", "g
 
 class StepIO(C.Structure):
     _fields_ = [(k, C.c_void_p) for k in STEP_INPUTS + STEP_OUTPUTS]
+
+
+VERLET_FIELDS = ("x", "y", "z", "H", "v", "m", "u", "rho", "dpdt", "dudt")
+
+
+class VerletIO(C.Structure):
+    _fields_ = [(k, C.c_void_p) for k in VERLET_FIELDS]
 
 
 class GraphStatus(C.Structure):
@@ -100,6 +108,7 @@ def lib():
             "crk_set_timestep": ([p, i32], i32),
             "crk_timestep": ([p, p, p, p, p, p, p, d, d, p, p, p, p], i32),
             "crk_compatible_energy": ([p, p] + [p] * 11 + [d, p], i32),
+            "crk_verlet_step": ([p, i32, p, i64, p, p, d, d, i32, p], i32),
             "crk_hsolve": ([p, d, d, i32, p, p, p], i32),
             "crk_export_neighbors": ([p, i32, p, p, i64, p], i32),
             "crk_set_lanes": ([p, i32, i32, i32, i32], i32),
@@ -333,6 +342,24 @@ class Context:
         self._check(st, "crk_step")
         self.n, self.n_pairs, self.perm = n, npairs.value, io["perm"]
         return npairs.value, ns.value
+
+    def verlet_step(self, state: dict, params: Params, dt: float, start_eval: bool = False,
+                    box_offsets=None, cell_size: float = 0.0) -> int:
+        """One velocity-Verlet step (crk_verlet_step) on the device arrays of
+        `state` (x, y, z, H, v, m, u, optional rho, dpdt, dudt; the caller's
+        order), advanced in place; returns the end evaluation's pair count."""
+        import numpy as np
+        n = state["x"].shape[0]
+        _f64(*[state.get(k) for k in VERLET_FIELDS])
+        off = np.ascontiguousarray([0, n] if box_offsets is None else box_offsets, dtype=np.int64)
+        s = VerletIO(*[_ptr(state.get(k)) for k in VERLET_FIELDS])
+        npairs = C.c_int64()
+        st = lib().crk_verlet_step(self._h, len(off) - 1, off.ctypes.data_as(C.c_void_p), n,
+                                   C.byref(s), C.byref(params), C.c_double(cell_size),
+                                   C.c_double(dt), int(bool(start_eval)), C.byref(npairs))
+        self._check(st, "crk_verlet_step")
+        self.n, self.n_pairs = n, npairs.value
+        return npairs.value
 
     def graph_capture(self, io: dict, params: Params, box_offsets=None, cell_size: float = 0.0,
                       headroom: float = 0.25):

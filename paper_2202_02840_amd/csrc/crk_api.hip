@@ -200,7 +200,7 @@ void crk_destroy(crk_ctx *c) {
                        &c->hnet_part, &c->hnet_feat, &c->hs_list, &c->hs_state, &c->hs_pos,
                        &c->hs_iters, &c->hs_pool, &c->hs_rows, &c->hs_rcnt, &c->hs_R, &c->boff,
                        &c->sv, &c->sm, &c->su, &c->srho, &c->gstat, &c->gboff,
-                       &c->ecnt, &c->efill, &c->eoff, &c->etmp, &c->ts_vs, &c->ts_qr, &c->ce, &c->ced};
+                       &c->ecnt, &c->efill, &c->eoff, &c->etmp, &c->ts_vs, &c->ts_qr, &c->ce, &c->ced, &c->vstep};
     crk::graph_release(c);
     for (crk::Buf *b : all)
         if (b->p) hipFree(b->p);

@@ -78,6 +78,7 @@ struct crk_ctx {
     crk::Buf ts_vs, ts_qr;                                   // time-step maxima per particle
     int ts_on = 0, ts_valid = 0;
     crk::Buf ce, ced;                                     // compatible-energy records (q, s)
+    crk::Buf vstep;                                       // Verlet step: half-step state, evaluation outputs
     crk::Buf hs_rows, hs_rcnt, hs_R;                      // candidate rows (r^2)
     crk::Buf boff;                                        // batch box offsets
     crk::Buf sv, sm, su, srho;                            // sorted gas state (crk_step)

@@ -1,0 +1,187 @@
+// Velocity-Verlet hydro step, eq. (verletOP): half kick and drift from the
+// derivatives of the start state, a predicted momentum and energy at the
+// end of the step, one whole derivative evaluation there (the step of
+// crk_step: build, volumes, moments, corrections, velocity gradient,
+// derivatives), and the closing half kick. The time step dt is the paper's
+// (dt/dy) Delta y; a and adot are held over the step.
+//
+// The state stays in the caller's (original) particle order; the
+// evaluation's outputs come back in cell-sorted order and the closing kick
+// gathers them through the sort permutation. The elementwise kernels are
+// HBM-bound; the evaluation is the step itself.
+#include <math.h>
+
+#include "crk_internal.h"
+
+// the kicks and the drift are written operation by operation; no product is
+// fused into the following sum (hipcc contracts by default)
+#pragma clang fp contract(off)
+
+namespace crk {
+namespace {
+
+constexpr int kVB = 256;
+
+// p^1/2 = a v + dt/2 dp/dt(0), u^1/2 = u + dt/2 du/dt(0),
+// x^1 = x + p^1/2 dt / a^2 wrapped into [0, L), p_p = p^1/2 + dt/2 dp/dt(0),
+// u_p = u^1/2 + dt/2 du/dt(0); the products and sums are rounded one by one
+// (no fused multiply-add, see the pragma above), so a drift reproduces
+// x + p dt / a^2 exactly as written.
+__global__ __launch_bounds__(kVB) void k_kick_drift(int64_t n, double a, double k, double c, double L,
+                                                    double *x, double *y, double *z,
+                                                    const double *__restrict__ v,
+                                                    const double *__restrict__ u,
+                                                    const double *__restrict__ dpdt,
+                                                    const double *__restrict__ dudt,
+                                                    double *__restrict__ ph, double *__restrict__ uh,
+                                                    double *__restrict__ vp, double *__restrict__ up) {
+    const int64_t i = (int64_t)blockIdx.x * kVB + threadIdx.x;
+    if (i >= n) return;
+    double *pos[3] = {x, y, z};
+#pragma unroll
+    for (int q = 0; q < 3; q++) {
+        const int64_t j = q * n + i;
+        const double kd = k * dpdt[j];
+        const double h = a * v[j] + kd;
+        ph[j] = h;
+        const double dx = h * c;
+        double xn = pos[q][i] + dx;
+        if (xn < 0.0) xn = xn + L;
+        if (xn >= L) xn = xn - L;
+        pos[q][i] = xn;
+        vp[j] = (h + kd) / a;
+    }
+    const double kd = k * dudt[i];
+    const double hu = u[i] + kd;
+    uh[i] = hu;
+    up[i] = hu + kd;
+}
+
+// p^1 = p^1/2 + dt/2 dp/dt(1), u^1 = u^1/2 + dt/2 du/dt(1) with the end
+// derivatives in sorted order (perm: sorted -> original); the end
+// derivatives are also returned in the original order for the next step.
+__global__ __launch_bounds__(kVB) void k_kick_close(int64_t n, const int32_t *__restrict__ perm,
+                                                    double a, double k,
+                                                    const double *__restrict__ ph,
+                                                    const double *__restrict__ uh,
+                                                    const double *__restrict__ sdp,
+                                                    const double *__restrict__ sdu, double *v,
+                                                    double *u, double *dpdt, double *dudt) {
+    const int64_t s = (int64_t)blockIdx.x * kVB + threadIdx.x;
+    if (s >= n) return;
+    const int64_t i = perm[s];
+#pragma unroll
+    for (int q = 0; q < 3; q++) {
+        const double d = sdp[q * n + s];
+        v[q * n + i] = (ph[q * n + i] + k * d) / a;
+        dpdt[q * n + i] = d;
+    }
+    const double du = sdu[s];
+    u[i] = uh[i] + k * du;
+    dudt[i] = du;
+}
+
+// sorted derivatives -> original order
+__global__ __launch_bounds__(kVB) void k_unsort_d(int64_t n, const int32_t *__restrict__ perm,
+                                                  const double *__restrict__ sdp,
+                                                  const double *__restrict__ sdu, double *dpdt,
+                                                  double *dudt) {
+    const int64_t s = (int64_t)blockIdx.x * kVB + threadIdx.x;
+    if (s >= n) return;
+    const int64_t i = perm[s];
+#pragma unroll
+    for (int q = 0; q < 3; q++) dpdt[q * n + i] = sdp[q * n + s];
+    dudt[i] = sdu[s];
+}
+
+inline unsigned vblocks(int64_t n) { return (unsigned)((n + kVB - 1) / kVB); }
+
+// doubles per particle of the step's sorted outputs, in crk_step_io order
+constexpr int kOutDoubles = 1 + 1 + 3 + 6 + 3 + 9 + 18 + 1 + 3 + 3 + 9 + 9 + 3 + 1;
+
+// points the sorted outputs of the evaluation into the workspace
+void carve(double *w, int64_t n, int32_t *perm, crk_step_io &io) {
+    io.perm = perm;
+    io.V = w;        w += n;
+    io.m0 = w;       w += n;
+    io.m1 = w;       w += 3 * n;
+    io.m2 = w;       w += 6 * n;
+    io.gm0 = w;      w += 3 * n;
+    io.gm1 = w;      w += 9 * n;
+    io.gm2 = w;      w += 18 * n;
+    io.A = w;        w += n;
+    io.B = w;        w += 3 * n;
+    io.gA = w;       w += 3 * n;
+    io.gB = w;       w += 9 * n;
+    io.gradv = w;    w += 9 * n;
+    io.dpdt = w;     w += 3 * n;
+    io.dudt = w;
+}
+
+}  // namespace
+}  // namespace crk
+
+using namespace crk;
+
+extern "C" {
+
+crk_status crk_verlet_step(crk_ctx *c, int32_t nboxes, const int64_t *box_offsets, int64_t n,
+                           const crk_verlet_io *io, const crk_params *p, double cell_size,
+                           double dt, int32_t start_eval, int64_t *n_pairs) {
+    if (!c) return CRK_ERR_INVALID_ARG;
+    if (!io || !p || !box_offsets || nboxes < 1 || n < 1 || !io->x || !io->y || !io->z || !io->H ||
+        !io->v || !io->m || !io->u || !io->dpdt || !io->dudt)
+        return set_err(c, CRK_ERR_INVALID_ARG, "crk_verlet_step: bad argument");
+    if (!isfinite(dt) || !(p->a > 0.0) || !(p->L > 0.0))
+        return set_err(c, CRK_ERR_INVALID_ARG, "crk_verlet_step: bad parameter");
+    if (c->graph_mode || c->capturing)
+        return set_err(c, CRK_ERR_STATE, "crk_verlet_step is not recorded in a graph");
+    CRK_HIP(c, hipSetDevice(c->device));
+    // workspace: p^1/2, u^1/2, p_p / a, u_p, then the evaluation's outputs
+    const size_t nd = (size_t)(8 + kOutDoubles) * n;
+    CRK_TRY(ensure(c, c->vstep, nd * sizeof(double) + (size_t)n * sizeof(int32_t)));
+    double *w = (double *)c->vstep.p;
+    double *ph = w, *uh = w + 3 * n, *vp = w + 4 * n, *up = w + 7 * n;
+    int32_t *perm = (int32_t *)(w + nd);
+    crk_step_io sio{};
+    carve(w + 8 * n, n, perm, sio);
+    sio.H = io->H;
+    sio.m = io->m;
+    sio.rho = io->rho;
+    if (start_eval) {
+        sio.x = io->x;
+        sio.y = io->y;
+        sio.z = io->z;
+        sio.v = io->v;
+        sio.u = io->u;
+        crk_status st = crk_step(c, nboxes, box_offsets, n, &sio, p, cell_size, nullptr, nullptr);
+        if (st < 0) return st;
+        KTimer kt_(c, "k_verlet");
+        k_unsort_d<<<vblocks(n), kVB, 0, c->stream>>>(n, perm, sio.dpdt, sio.dudt, io->dpdt, io->dudt);
+        CRK_HIP(c, hipGetLastError());
+    }
+    const double a = p->a, k = 0.5 * dt, cd = dt / (a * a);
+    {
+        KTimer kt_(c, "k_verlet");
+        k_kick_drift<<<vblocks(n), kVB, 0, c->stream>>>(n, a, k, cd, p->L, io->x, io->y, io->z, io->v,
+                                                         io->u, io->dpdt, io->dudt, ph, uh, vp, up);
+        CRK_HIP(c, hipGetLastError());
+    }
+    sio.x = io->x;
+    sio.y = io->y;
+    sio.z = io->z;
+    sio.v = vp;
+    sio.u = up;
+    crk_status st = crk_step(c, nboxes, box_offsets, n, &sio, p, cell_size, n_pairs, nullptr);
+    if (st < 0) return st;
+    {
+        KTimer kt_(c, "k_verlet");
+        k_kick_close<<<vblocks(n), kVB, 0, c->stream>>>(n, perm, a, k, ph, uh, sio.dpdt, sio.dudt, io->v,
+                                                         io->u, io->dpdt, io->dudt);
+        CRK_HIP(c, hipGetLastError());
+    }
+    CRK_HIP(c, hipStreamSynchronize(c->stream));
+    return st;
+}
+
+}  // extern "C"
