@@ -264,15 +264,19 @@ def compat_leg(ctx, dev, prm, args, deriv_ms_plain: float, dt: float = 1e-3) -> 
     return res
 
 
-def verlet_leg(ctx, dev, prm, args, dt: float = 1e-4) -> dict:
+def verlet_leg(ctx, dev, prm, args) -> dict:
     """Velocity-Verlet hydro steps (eq. verletOP) on the workload: each step
     is the half kicks and drift around one whole evaluation at the predicted
     state; reports the wall time per step, the elementwise kernels' share and
-    the change of the total energy sum m (u + |p|^2 / (2 a^4)) over the run."""
+    the change of the total energy sum m (u + |p|^2 / (2 a^4)) over the run.
+    The step is the smallest Courant step dt_hyd of the start state (Sec. 2.4,
+    C_CFL = 0.25)."""
     import torch
+    from paper_2202_02840_amd import pipeline as pl
+    dt = float(pl.step(ctx, dev, prm, count_singular=False, timestep=True)["dt_hyd"].min())
     n = dev["x"].shape[0]
     st = {k: dev[k].clone() for k in ("x", "y", "z", "H", "v", "m", "u")}
-    st["rho"] = None if dev.get("rho") is None else dev["rho"]
+    st["rho"] = None          # density follows the particles: rho = m / V
     st["dpdt"] = torch.zeros(3, n, dtype=torch.float64, device="cuda")
     st["dudt"] = torch.zeros(n, dtype=torch.float64, device="cuda")
     a = prm.a
