@@ -69,7 +69,7 @@ def lib():
         L.orc_limiter.restype = _d
         L.orc_limiter.argtypes = [_d, _d, _d, _d, _d]
         L.orc_derivatives.argtypes = [_i64, _p, _p, _p, _p, _d, _int] + [_p] * 18
-        L.orc_compatible_energy.argtypes = [_i64, _p, _p, _p, _p, _d, _int] + [_p] * 14 + [_d, _p]
+        L.orc_compatible_energy.argtypes = [_i64, _p, _p, _p, _p, _d, _int] + [_p] * 15 + [_d, _p]
         L.orc_compatible_energy.restype = None
         L.orc_thacker_step.restype = _d
         L.orc_thacker_step.argtypes = [_d, _d, _d]
@@ -247,11 +247,13 @@ def derivatives(x, y, z, H, v, m, u, rho, V, corr, gv, soff, sidx, prm, L=1.0, p
 
 
 def compatible_energy(x, y, z, H, v, m, u, rho, V, corr, gv, soff, sidx, prm, dpdt, dt, L=1.0,
-                      periodic=True):
+                      periodic=True, pk=None):
     """Delta u [n] of the compatible energy update over the time step dt
     (eqs. compEng, compEng2, Eij, ptdt, fij), from the state the derivative
-    pass saw and its dp/dt [3, n]."""
+    pass saw and its dp/dt [3, n]; pk [3, n], when given, is the momentum at
+    the start of the kick (else a v)."""
     x, y, z, H, v, m, u, V, gv, dpdt = map(_f64, (x, y, z, H, v, m, u, V, gv, dpdt))
+    pk = None if pk is None else _f64(pk)
     rho = None if rho is None else _f64(rho)
     n = x.shape[0]
     du = np.empty(n)
@@ -259,8 +261,8 @@ def compatible_energy(x, y, z, H, v, m, u, rho, V, corr, gv, soff, sidx, prm, dp
     pa = np.array([prm[k] for k in PARAM_KEYS], dtype=np.float64)
     lib().orc_compatible_energy(n, _ptr(x), _ptr(y), _ptr(z), _ptr(H), L, int(periodic), _ptr(v),
                                 _ptr(m), _ptr(u), _ptr(rho), _ptr(V), *[_ptr(a) for a in c],
-                                _ptr(gv), _ptr(pa), _ptr(soff), _ptr(sidx), _ptr(dpdt), float(dt),
-                                _ptr(du))
+                                _ptr(gv), _ptr(pa), _ptr(soff), _ptr(sidx), _ptr(dpdt), _ptr(pk),
+                                float(dt), _ptr(du))
     return du
 
 
@@ -333,7 +335,15 @@ def pipeline(ps, prm, periodic=True, method="auto", dt=None):
 
 
 # ------------------------------------------------------ velocity Verlet
-def verlet_step(ps, prm, dt, d0=None, periodic=True):
+def _compat_half(st, d, prm, k, pk, periodic):
+    """Delta u of a half kick of length k with the pair forces of the
+    evaluation d at state st, starting from the momenta pk."""
+    return compatible_energy(st.x, st.y, st.z, st.H, st.v, st.m, st.u, st.rho, d["V"], d,
+                             d["gradv"], d["soff"], d["sidx"], prm, d["dvdt"], k, st.L, periodic,
+                             pk=pk)
+
+
+def verlet_step(ps, prm, dt, d0=None, periodic=True, energy="eng"):
     """One step of the velocity-Verlet hydro operator, eq. verletOP, with the
     time step dt = (dt/dy) Delta y and a, adot held over the step. With
     p = a v and D = (dp/dt, du/dt) from the derivative pass (eqs. mom, eng):
@@ -342,18 +352,31 @@ def verlet_step(ps, prm, dt, d0=None, periodic=True):
       p_p   = p^1/2 + dt/2 dp/dt(0),    u_p   = u^1/2 + dt/2 du/dt(0),
       D(1)  = D at (x^1, p_p, u_p) with the same H, m (and rho if given),
       p^1   = p^1/2 + dt/2 dp/dt(1),    u^1   = u^1/2 + dt/2 du/dt(1).
-    d0 is D at the start state (dict with dvdt, dudt); None evaluates it.
-    Returns (state, D(1)): state is a namespace like ps at the end of the
-    step (v = p / a); D(1) is the derivative pass's output there."""
+    With energy="compat" each half kick's energy change is instead the
+    compatible update (eqs. compEng-fij) of that kick: the pair forces of
+    the evaluation the kick uses, the momenta the kick starts from, length
+    dt/2; the opening kick's change is carried as a rate in D["dudt_kick"]
+    (taken for a next step of the same dt), which also predicts u_p.
+    d0 is D at the start state (dict with dvdt, dudt, and dudt_kick for
+    "compat"); None evaluates it. Returns (state, D(1)): state is a
+    namespace like ps at the end of the step (v = p / a); D(1) is the
+    derivative pass's output there."""
     from types import SimpleNamespace
     a = prm["a"]
     L = ps.L
+    k = 0.5 * dt
+    compat = energy == "compat"
+    gam = getattr(ps, "gamma", prm["gamma"])
     if d0 is None:
         d0 = pipeline(ps, prm, periodic)
-    k = 0.5 * dt
+        if compat:
+            st0 = SimpleNamespace(x=ps.x, y=ps.y, z=ps.z, H=ps.H, m=ps.m, u=ps.u, v=ps.v,
+                                  rho=ps.rho, L=L)
+            d0["dudt_kick"] = _compat_half(st0, d0, prm, k, a * np.asarray(ps.v), periodic) / k
+    rate0 = d0["dudt_kick"] if compat else d0["dudt"]
     c = dt / (a * a)
     ph = a * np.asarray(ps.v, dtype=np.float64) + k * d0["dvdt"]
-    uh = np.asarray(ps.u, dtype=np.float64) + k * d0["dudt"]
+    uh = np.asarray(ps.u, dtype=np.float64) + k * rate0
     x1 = []
     for q, comp in ((ps.x, 0), (ps.y, 1), (ps.z, 2)):
         xn = np.asarray(q, dtype=np.float64) + ph[comp] * c
@@ -362,14 +385,18 @@ def verlet_step(ps, prm, dt, d0=None, periodic=True):
             xn = np.where(xn >= L, xn - L, xn)
         x1.append(xn)
     pp = ph + k * d0["dvdt"]
-    up = uh + k * d0["dudt"]
+    up = uh + k * rate0
     mid = SimpleNamespace(x=x1[0], y=x1[1], z=x1[2], H=ps.H, m=ps.m, u=up, v=pp / a,
-                          rho=ps.rho, L=L, gamma=getattr(ps, "gamma", prm["gamma"]))
+                          rho=ps.rho, L=L, gamma=gam)
     d1 = pipeline(mid, prm, periodic)
     p1 = ph + k * d1["dvdt"]
-    u1 = uh + k * d1["dudt"]
+    if compat:
+        u1 = uh + _compat_half(mid, d1, prm, k, ph, periodic)
+        d1["dudt_kick"] = _compat_half(mid, d1, prm, k, p1, periodic) / k
+    else:
+        u1 = uh + k * d1["dudt"]
     end = SimpleNamespace(x=x1[0], y=x1[1], z=x1[2], H=ps.H, m=ps.m, u=u1, v=p1 / a,
-                          rho=ps.rho, L=L, gamma=mid.gamma)
+                          rho=ps.rho, L=L, gamma=gam)
     return end, d1
 
 

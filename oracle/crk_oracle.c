@@ -803,7 +803,10 @@ void orc_derivatives(int64_t n, const double *x, const double *y, const double *
 /* Compatible energy update over one time step dt, eqs. (compEng),      */
 /* (compEng2), (Eij), (ptdt) and (fij), for every particle i:           */
 /*   p = a v, p'_k = p_k + dt dp_k/dt (eq. ptdt; dp/dt as returned by    */
-/*   orc_derivatives for the same state);                               */
+/*   orc_derivatives for the same state); when PK is given, p = PK is    */
+/*   the momentum at the start of the kick instead (the pair forces stay */
+/*   those of the state v: a kick that starts elsewhere, as in a         */
+/*   velocity-Verlet half step);                                        */
 /*   for every j in N_s(i): dp_ij/dt = F_ij / m_i, the pair's term of   */
 /*   eq. (mom) with P -> P+Q, and                                       */
 /*     c_ij = (p_j + p'_j - p_i - p'_i).dp_ij/dt;                       */
@@ -821,7 +824,8 @@ void orc_compatible_energy(int64_t n, const double *x, const double *y, const do
                            const double *m, const double *u, const double *rho, const double *V,
                            const double *A, const double *B, const double *gA, const double *gB,
                            const double *gradv, const double *prm, const int64_t *soff,
-                           const int32_t *sidx, const double *dpdt, double dt, double *du)
+                           const int32_t *sidx, const double *dpdt, const double *PK, double dt,
+                           double *du)
 {
     orc_gas g;
     orc_gas_init(&g, n, x, y, z, H, L, periodic, v, m, u, rho, V, A, B, gA, gB, gradv, prm);
@@ -834,7 +838,7 @@ void orc_compatible_energy(int64_t n, const double *x, const double *y, const do
         double s_i = ri.P / pow(ri.rho, gam);
         double pi[3], ppi[3];
         for (int c = 0; c < 3; c++) {
-            pi[c] = a * v[c * n + i];
+            pi[c] = PK ? PK[c * n + i] : a * v[c * n + i];
             ppi[c] = pi[c] + dt * dpdt[c * n + i];
         }
         double sum = 0.0;
@@ -846,7 +850,7 @@ void orc_compatible_energy(int64_t n, const double *x, const double *y, const do
             double s_j = (gam - 1.0) * rhoj * u[j] / pow(rhoj, gam);
             double cij = 0.0;
             for (int c = 0; c < 3; c++) {
-                double pj = a * v[c * n + j];
+                double pj = PK ? PK[c * n + j] : a * v[c * n + j];
                 double ppj = pj + dt * dpdt[c * n + j];
                 cij += (pj + ppj - pi[c] - ppi[c]) * (t.F[c] / m[i]);
             }

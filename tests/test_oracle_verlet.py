@@ -79,3 +79,47 @@ def test_second_order_convergence(over):
     print(errs, r1, r2)
     assert errs[0] > 1e-9
     assert 3.0 < r1 < 5.5 and 3.0 < r2 < 5.5
+
+
+def _energy(st, a):
+    return (st.m * (st.u + ((a * st.v) ** 2).sum(0) / (2.0 * a ** 4))).sum()
+
+
+@pytest.mark.parametrize("over", [{}, dict(a=1.3)], ids=["static", "a=1.3"])
+def test_compatible_mode_conserves_energy_exactly(over):
+    """With each half kick's energy from the compatible update, the total
+    energy sum m (u + |p|^2 / (2 a^4)) is conserved to rounding over many
+    steps, shocks and viscosity included (adot = 0); the du/dt mode drifts."""
+    ps = ci.lognormal_box(8, sigma=1.5, seed=904)
+    ps.v = ps.v * 20.0
+    prm = oracle.params(64.0, gamma=ps.gamma, **over)
+    a, dt = prm["a"], 2e-3
+    e0 = _energy(ps, a)
+    drift = {}
+    for mode in ("compat", "eng"):
+        st, d = ps, None
+        for _ in range(6):
+            st, d = oracle.verlet_step(st, prm, dt, d0=d, energy=mode)
+        drift[mode] = abs(_energy(st, a) - e0) / e0
+    print(drift)
+    assert drift["compat"] < 1e-13
+    assert drift["eng"] > 1e3 * drift["compat"]
+
+
+def test_compatible_mode_is_second_order():
+    ps = ci.lognormal_box(6, sigma=0.8, seed=905)
+    ps.v = ps.v * 2.0
+    prm = oracle.params(64.0, gamma=ps.gamma, Cl=0.0, Cq=0.0)
+    T = 0.02
+
+    def run(nsteps):
+        st, d = ps, None
+        for _ in range(nsteps):
+            st, d = oracle.verlet_step(st, prm, T / nsteps, d0=d, energy="compat")
+        return st
+
+    ref = run(64)
+    errs = [_err(run(k), ref) for k in (4, 8, 16)]
+    r1, r2 = errs[0] / errs[1], errs[1] / errs[2]
+    print(errs, r1, r2)
+    assert 3.0 < r1 < 5.5 and 3.0 < r2 < 5.5
