@@ -232,6 +232,9 @@ crk_status crk_timestep(crk_ctx *ctx, const crk_params *p, const double *u, cons
  *   du[i] = dt sum_{j in N_s(i)} f_ij c_ij / (2 a^4)
  *           - dt (adot/a)(3(gamma-1)+2) u_i,
  *   c_ij = (p_j + p'_j - p_i - p'_i).dp_ij/dt,  p = a v,  p' = p + dt dp/dt,
+ * (p = pk instead when pk is not NULL: the momenta a kick starts from, as in
+ * a velocity-Verlet half step, while the pair forces stay those of the
+ * state v; [3][n] sorted),
  * where dp_ij/dt is the pair's term of eq. (mom) with P -> P+Q (recomputed
  * pair by pair, with the same limiter and viscosity as crk_derivatives) and
  * f_ij is the entropy partition of eq. (fij), s = P / rho^gamma: the pair's
@@ -251,7 +254,7 @@ crk_status crk_compatible_energy(crk_ctx *ctx, const crk_params *p, const double
                                  const double *m, const double *u, const double *rho,
                                  const double *V, const double *A, const double *B,
                                  const double *gA, const double *gB, const double *gradv,
-                                 const double *dpdt, double dt, double *du);
+                                 const double *dpdt, const double *pk, double dt, double *du);
 
 /*
  * One whole step: S1 build (all boxes of a batch), S2 volumes, S4 moments,
@@ -290,6 +293,15 @@ crk_status crk_step(crk_ctx *ctx, int32_t nboxes, const int64_t *box_offsets, in
  *   p_p   = p^1/2 + dt/2 dp/dt(0), u_p = u^1/2 + dt/2 du/dt(0),
  *   D(1)  = the whole step (crk_step) at (x^1, p_p / a, u_p) with H, m, rho,
  *   p^1   = p^1/2 + dt/2 dp/dt(1), u^1 = u^1/2 + dt/2 du/dt(1).
+ * energy = 0 uses du/dt of eq. (eng) as above. energy = 1 takes each half
+ * kick's energy change from the compatible update instead (as
+ * crk_compatible_energy over dt/2, with the pair forces of the evaluation the
+ * kick uses and the momenta the kick starts from): the closing kick from
+ * p^1/2, and the next step's opening kick from p^1, whose change is returned
+ * as the rate dudt = Delta u / (dt/2) (so the next step must use the same dt
+ * for the balance to be exact); with start_eval the first opening kick's
+ * change is computed the same way. Energy is then conserved to rounding
+ * (adot = 0). dt must not be 0 in this mode.
  * Every array is a caller-owned DEVICE array in the caller's particle order;
  * x, y, z, v, u are advanced in place. dpdt/dudt hold D at the start state
  * on entry (start_eval = 0; with start_eval = 1 the library evaluates it
@@ -313,7 +325,7 @@ typedef struct {
 
 crk_status crk_verlet_step(crk_ctx *ctx, int32_t nboxes, const int64_t *box_offsets, int64_t n,
                            const crk_verlet_io *io, const crk_params *p, double cell_size,
-                           double dt, int32_t start_eval, int64_t *n_pairs);
+                           double dt, int32_t start_eval, int32_t energy, int64_t *n_pairs);
 
 /* Device-side status of a replayed step (filled by crk_graph_replay). */
 typedef struct {

@@ -107,8 +107,8 @@ def lib():
             "crk_derivatives": ([p, p] + [p] * 12, i32),
             "crk_set_timestep": ([p, i32], i32),
             "crk_timestep": ([p, p, p, p, p, p, p, d, d, p, p, p, p], i32),
-            "crk_compatible_energy": ([p, p] + [p] * 11 + [d, p], i32),
-            "crk_verlet_step": ([p, i32, p, i64, p, p, d, d, i32, p], i32),
+            "crk_compatible_energy": ([p, p] + [p] * 12 + [d, p], i32),
+            "crk_verlet_step": ([p, i32, p, i64, p, p, d, d, i32, i32, p], i32),
             "crk_hsolve": ([p, d, d, i32, p, p, p], i32),
             "crk_export_neighbors": ([p, i32, p, p, i64, p], i32),
             "crk_set_lanes": ([p, i32, i32, i32, i32], i32),
@@ -297,15 +297,17 @@ class Context:
         return out
 
     def compatible_energy(self, params: Params, v, m, u, rho, V, corr: dict, gradv, dpdt,
-                          dt: float):
+                          dt: float, pk=None):
         """Delta u of the compatible energy update over dt (sorted order),
-        from the state and outputs of the preceding derivative call."""
-        _f64(v, m, u, rho, V, gradv, dpdt)
+        from the state and outputs of the preceding derivative call; pk:
+        optional kick-start momenta [3, n] (sorted)."""
+        _f64(v, m, u, rho, V, gradv, dpdt, pk)
         du = self._empty(self.n)
         st = lib().crk_compatible_energy(self._h, C.byref(params), _ptr(v), _ptr(m), _ptr(u),
                                          _ptr(rho), _ptr(V),
                                          *[_ptr(corr[k]) for k in ("A", "B", "gA", "gB")],
-                                         _ptr(gradv), _ptr(dpdt), C.c_double(dt), _ptr(du))
+                                         _ptr(gradv), _ptr(dpdt), _ptr(pk), C.c_double(dt),
+                                         _ptr(du))
         self._check(st, "crk_compatible_energy")
         return du
 
@@ -344,10 +346,13 @@ class Context:
         return npairs.value, ns.value
 
     def verlet_step(self, state: dict, params: Params, dt: float, start_eval: bool = False,
-                    box_offsets=None, cell_size: float = 0.0) -> int:
+                    box_offsets=None, cell_size: float = 0.0, energy: str = "eng") -> int:
         """One velocity-Verlet step (crk_verlet_step) on the device arrays of
         `state` (x, y, z, H, v, m, u, optional rho, dpdt, dudt; the caller's
-        order), advanced in place; returns the end evaluation's pair count."""
+        order), advanced in place; energy "eng" (du/dt of eq. eng) or
+        "compat" (compatible update per half kick). Returns the end
+        evaluation's pair count."""
+        mode = {"eng": 0, "compat": 1}[energy]
         import numpy as np
         n = state["x"].shape[0]
         _f64(*[state.get(k) for k in VERLET_FIELDS])
@@ -356,7 +361,7 @@ class Context:
         npairs = C.c_int64()
         st = lib().crk_verlet_step(self._h, len(off) - 1, off.ctypes.data_as(C.c_void_p), n,
                                    C.byref(s), C.byref(params), C.c_double(cell_size),
-                                   C.c_double(dt), int(bool(start_eval)), C.byref(npairs))
+                                   C.c_double(dt), int(bool(start_eval)), mode, C.byref(npairs))
         self._check(st, "crk_verlet_step")
         self.n, self.n_pairs = n, npairs.value
         return npairs.value

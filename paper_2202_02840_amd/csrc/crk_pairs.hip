@@ -759,10 +759,12 @@ __global__ __launch_bounds__(kBlock) void k_deriv_fix(const double4 *__restrict_
 }
 
 // Compatible energy update (eqs. compEng, compEng2, Eij, ptdt, fij): per
-// particle q = p + p' = 2 a v + dt dp/dt (p = a v, eq. ptdt) and the specific
-// entropy s = P / rho^gamma, FP64, then rounded to the pass's type.
+// particle q = p + p' = 2 p + dt dp/dt (p = a v, or the kick's start
+// momenta pk when given; eq. ptdt) and the specific entropy s = P / rho^gamma,
+// FP64, then rounded to the pass's type.
 template <typename V4, typename T>
-__global__ __launch_bounds__(kBlock) void k_pack_ce(int64_t n, const double *v, const double *dpdt,
+__global__ __launch_bounds__(kBlock) void k_pack_ce(int64_t n, const double *v, const double *pk,
+                                                    const double *dpdt,
                                                     const double *m, const double *u,
                                                     const double *rho, const double *V, double gamma,
                                                     double a, double dt, V4 *ce, double4 *ced) {
@@ -770,9 +772,12 @@ __global__ __launch_bounds__(kBlock) void k_pack_ce(int64_t n, const double *v, 
     if (i >= n) return;
     const double r = rho ? rho[i] : m[i] / V[i];
     const double sp = (gamma - 1.0) * u[i] * pow(r, 1.0 - gamma);
-    const double qx = 2.0 * a * v[i] + dt * dpdt[i];
-    const double qy = 2.0 * a * v[n + i] + dt * dpdt[n + i];
-    const double qz = 2.0 * a * v[2 * n + i] + dt * dpdt[2 * n + i];
+    const double px = pk ? pk[i] : a * v[i];
+    const double py = pk ? pk[n + i] : a * v[n + i];
+    const double pz = pk ? pk[2 * n + i] : a * v[2 * n + i];
+    const double qx = 2.0 * px + dt * dpdt[i];
+    const double qy = 2.0 * py + dt * dpdt[n + i];
+    const double qz = 2.0 * pz + dt * dpdt[2 * n + i];
     ce[i] = V4{(T)qx, (T)qy, (T)qz, (T)sp};
     if (ced) ced[i] = make_double4(qx, qy, qz, sp);
 }
@@ -1338,7 +1343,7 @@ crk_status crk_compatible_energy(crk_ctx *c, const crk_params *p, const double *
                                  const double *u, const double *rho, const double *V,
                                  const double *A, const double *B, const double *gA,
                                  const double *gB, const double *gradv, const double *dpdt,
-                                 double dt, double *du) {
+                                 const double *pk, double dt, double *du) {
     if (!c) return CRK_ERR_INVALID_ARG;
     if (!p || !v || !m || !u || !V || !A || !B || !gA || !gB || !gradv || !dpdt || !du)
         return set_err(c, CRK_ERR_INVALID_ARG, "crk_compatible_energy: NULL argument");
@@ -1383,7 +1388,7 @@ crk_status crk_compatible_energy(crk_ctx *c, const crk_params *p, const double *
         {
             KTimer kt_(c, "k_pack");
             k_pack7<float4, float><<<nblocks(n), kBlock, 0, c->stream>>>(n, posH, v, m, u, rho, V, A, B, gA, gB, gradv, dp, ar.flag, r7, aux, bad);
-            k_pack_ce<float4, float><<<nblocks(n), kBlock, 0, c->stream>>>(n, v, dpdt, m, u, rho, V, p->gamma, p->a, dt, ce, ced);
+            k_pack_ce<float4, float><<<nblocks(n), kBlock, 0, c->stream>>>(n, v, pk, dpdt, m, u, rho, V, p->gamma, p->a, dt, ce, ced);
         }
 #define L_CE(GG) k_compat<float, GG><<<gblocks(n, GG), kBlock, 0, c->stream>>>(posH, goff, gidx, eb, ee, eidx, r7, ce, m, u, n, box, dp, scale, cool, du)
         {
@@ -1405,7 +1410,7 @@ crk_status crk_compatible_energy(crk_ctx *c, const crk_params *p, const double *
         {
             KTimer kt_(c, "k_pack");
             k_pack7<double4, double><<<nblocks(n), kBlock, 0, c->stream>>>(n, posH, v, m, u, rho, V, A, B, gA, gB, gradv, dp, nullptr, r7, nullptr, bad);
-            k_pack_ce<double4, double><<<nblocks(n), kBlock, 0, c->stream>>>(n, v, dpdt, m, u, rho, V, p->gamma, p->a, dt, ce, nullptr);
+            k_pack_ce<double4, double><<<nblocks(n), kBlock, 0, c->stream>>>(n, v, pk, dpdt, m, u, rho, V, p->gamma, p->a, dt, ce, nullptr);
         }
 #define L_CE(GG) k_compat<double, GG><<<gblocks(n, GG), kBlock, 0, c->stream>>>(posH, goff, gidx, eb, ee, eidx, r7, ce, m, u, n, box, dp, scale, cool, du)
         {

@@ -58,14 +58,18 @@ __global__ __launch_bounds__(kVB) void k_kick_drift(int64_t n, double a, double 
 }
 
 // p^1 = p^1/2 + dt/2 dp/dt(1), u^1 = u^1/2 + dt/2 du/dt(1) with the end
-// derivatives in sorted order (perm: sorted -> original); the end
-// derivatives are also returned in the original order for the next step.
+// derivatives in sorted order (perm: sorted -> original), or u^1 = u^1/2 +
+// the compatible change sdc of the closing kick when given; the end
+// derivatives are also returned in the original order for the next step,
+// and with sdc the end momenta in sorted order (p1s, the next kick's start).
 __global__ __launch_bounds__(kVB) void k_kick_close(int64_t n, const int32_t *__restrict__ perm,
                                                     double a, double k,
                                                     const double *__restrict__ ph,
                                                     const double *__restrict__ uh,
                                                     const double *__restrict__ sdp,
-                                                    const double *__restrict__ sdu, double *v,
+                                                    const double *__restrict__ sdu,
+                                                    const double *__restrict__ sdc,
+                                                    double *__restrict__ p1s, double *v,
                                                     double *u, double *dpdt, double *dudt) {
     const int64_t s = (int64_t)blockIdx.x * kVB + threadIdx.x;
     if (s >= n) return;
@@ -73,12 +77,34 @@ __global__ __launch_bounds__(kVB) void k_kick_close(int64_t n, const int32_t *__
 #pragma unroll
     for (int q = 0; q < 3; q++) {
         const double d = sdp[q * n + s];
-        v[q * n + i] = (ph[q * n + i] + k * d) / a;
+        const double p1 = ph[q * n + i] + k * d;
+        v[q * n + i] = p1 / a;
         dpdt[q * n + i] = d;
+        if (p1s) p1s[q * n + s] = p1;
     }
     const double du = sdu[s];
-    u[i] = uh[i] + k * du;
+    u[i] = sdc ? uh[i] + sdc[s] : uh[i] + k * du;
     dudt[i] = du;
+}
+
+// sorted gather of the half-step momenta (the closing kick's start)
+__global__ __launch_bounds__(kVB) void k_gather3(int64_t n, const int32_t *__restrict__ perm,
+                                                 const double *__restrict__ src,
+                                                 double *__restrict__ dst) {
+    const int64_t s = (int64_t)blockIdx.x * kVB + threadIdx.x;
+    if (s >= n) return;
+    const int64_t i = perm[s];
+#pragma unroll
+    for (int q = 0; q < 3; q++) dst[q * n + s] = src[q * n + i];
+}
+
+// the opening kick's energy change of the next step as a rate: dudt = du / k
+__global__ __launch_bounds__(kVB) void k_rate(int64_t n, const int32_t *__restrict__ perm,
+                                              double k, const double *__restrict__ sdu,
+                                              double *dudt) {
+    const int64_t s = (int64_t)blockIdx.x * kVB + threadIdx.x;
+    if (s >= n) return;
+    dudt[perm[s]] = sdu[s] / k;
 }
 
 // sorted derivatives -> original order
@@ -125,26 +151,43 @@ using namespace crk;
 
 extern "C" {
 
+// compatible change of a half kick of length k from the sorted momenta pks
+// (NULL: a v of the evaluation) with the pair forces of the evaluation just
+// made by crk_step (its sorted state and outputs)
+static crk_status compat_half(crk_ctx *c, const crk_params *p, const crk_step_io &sio,
+                              const double *pks, double k, double *dus) {
+    const double *sv = (const double *)c->sv.p, *sm = (const double *)c->sm.p,
+                 *su = (const double *)c->su.p;
+    const double *srho = sio.rho ? (const double *)c->srho.p : nullptr;
+    return crk_compatible_energy(c, p, sv, sm, su, srho, sio.V, sio.A, sio.B, sio.gA, sio.gB,
+                                 sio.gradv, sio.dpdt, pks, k, dus);
+}
+
 crk_status crk_verlet_step(crk_ctx *c, int32_t nboxes, const int64_t *box_offsets, int64_t n,
                            const crk_verlet_io *io, const crk_params *p, double cell_size,
-                           double dt, int32_t start_eval, int64_t *n_pairs) {
+                           double dt, int32_t start_eval, int32_t energy, int64_t *n_pairs) {
     if (!c) return CRK_ERR_INVALID_ARG;
     if (!io || !p || !box_offsets || nboxes < 1 || n < 1 || !io->x || !io->y || !io->z || !io->H ||
         !io->v || !io->m || !io->u || !io->dpdt || !io->dudt)
         return set_err(c, CRK_ERR_INVALID_ARG, "crk_verlet_step: bad argument");
-    if (!isfinite(dt) || !(p->a > 0.0) || !(p->L > 0.0))
+    if (!isfinite(dt) || !(p->a > 0.0) || !(p->L > 0.0) || (energy != 0 && energy != 1) ||
+        (energy == 1 && !(dt != 0.0)))
         return set_err(c, CRK_ERR_INVALID_ARG, "crk_verlet_step: bad parameter");
     if (c->graph_mode || c->capturing)
         return set_err(c, CRK_ERR_STATE, "crk_verlet_step is not recorded in a graph");
     CRK_HIP(c, hipSetDevice(c->device));
-    // workspace: p^1/2, u^1/2, p_p / a, u_p, then the evaluation's outputs
-    const size_t nd = (size_t)(8 + kOutDoubles) * n;
+    // workspace: p^1/2, u^1/2, p_p / a, u_p, the evaluation's outputs, then
+    // sorted kick-start momenta and energy changes (compatible mode)
+    const bool compat = energy == 1;
+    const size_t nd = (size_t)(8 + kOutDoubles + 4) * n;
     CRK_TRY(ensure(c, c->vstep, nd * sizeof(double) + (size_t)n * sizeof(int32_t)));
     double *w = (double *)c->vstep.p;
     double *ph = w, *uh = w + 3 * n, *vp = w + 4 * n, *up = w + 7 * n;
     int32_t *perm = (int32_t *)(w + nd);
     crk_step_io sio{};
     carve(w + 8 * n, n, perm, sio);
+    double *pks = w + (size_t)(8 + kOutDoubles) * n, *dus = pks + 3 * n;
+    const double a = p->a, k = 0.5 * dt, cd = dt / (a * a);
     sio.H = io->H;
     sio.m = io->m;
     sio.rho = io->rho;
@@ -156,11 +199,18 @@ crk_status crk_verlet_step(crk_ctx *c, int32_t nboxes, const int64_t *box_offset
         sio.u = io->u;
         crk_status st = crk_step(c, nboxes, box_offsets, n, &sio, p, cell_size, nullptr, nullptr);
         if (st < 0) return st;
-        KTimer kt_(c, "k_verlet");
-        k_unsort_d<<<vblocks(n), kVB, 0, c->stream>>>(n, perm, sio.dpdt, sio.dudt, io->dpdt, io->dudt);
-        CRK_HIP(c, hipGetLastError());
+        {
+            KTimer kt_(c, "k_verlet");
+            k_unsort_d<<<vblocks(n), kVB, 0, c->stream>>>(n, perm, sio.dpdt, sio.dudt, io->dpdt, io->dudt);
+            CRK_HIP(c, hipGetLastError());
+        }
+        if (compat) {
+            // the first opening kick's compatible change, from p = a v
+            CRK_TRY(compat_half(c, p, sio, nullptr, k, dus));
+            k_rate<<<vblocks(n), kVB, 0, c->stream>>>(n, perm, k, dus, io->dudt);
+            CRK_HIP(c, hipGetLastError());
+        }
     }
-    const double a = p->a, k = 0.5 * dt, cd = dt / (a * a);
     {
         KTimer kt_(c, "k_verlet");
         k_kick_drift<<<vblocks(n), kVB, 0, c->stream>>>(n, a, k, cd, p->L, io->x, io->y, io->z, io->v,
@@ -174,10 +224,24 @@ crk_status crk_verlet_step(crk_ctx *c, int32_t nboxes, const int64_t *box_offset
     sio.u = up;
     crk_status st = crk_step(c, nboxes, box_offsets, n, &sio, p, cell_size, n_pairs, nullptr);
     if (st < 0) return st;
+    if (compat) {
+        // closing kick: from p^1/2 with the end evaluation's pair forces
+        k_gather3<<<vblocks(n), kVB, 0, c->stream>>>(n, perm, ph, pks);
+        CRK_HIP(c, hipGetLastError());
+        CRK_TRY(compat_half(c, p, sio, pks, k, dus));
+    }
     {
         KTimer kt_(c, "k_verlet");
-        k_kick_close<<<vblocks(n), kVB, 0, c->stream>>>(n, perm, a, k, ph, uh, sio.dpdt, sio.dudt, io->v,
-                                                         io->u, io->dpdt, io->dudt);
+        k_kick_close<<<vblocks(n), kVB, 0, c->stream>>>(n, perm, a, k, ph, uh, sio.dpdt, sio.dudt,
+                                                         compat ? dus : nullptr, compat ? pks : nullptr,
+                                                         io->v, io->u, io->dpdt, io->dudt);
+        CRK_HIP(c, hipGetLastError());
+    }
+    if (compat) {
+        // the next step's opening kick: from p^1 with the same pair forces,
+        // carried as a rate in dudt
+        CRK_TRY(compat_half(c, p, sio, pks, k, dus));
+        k_rate<<<vblocks(n), kVB, 0, c->stream>>>(n, perm, k, dus, io->dudt);
         CRK_HIP(c, hipGetLastError());
     }
     CRK_HIP(c, hipStreamSynchronize(c->stream));

@@ -28,9 +28,11 @@ def update_support(ctx: Context, state: dict, params: Params, nres: float, tol: 
 
 
 def evolve(ctx: Context, state: dict, params: Params, t_end: float, dt: float,
-           nres: float = 64.0, h_tol: float = 1e-6, log=None) -> dict:
+           nres: float = 64.0, h_tol: float = 1e-6, log=None, energy: str = "eng") -> dict:
     """Fixed steps of at most dt from t = 0 to t_end. state holds x, y, z, H,
-    v, m, u (optional rho); dpdt and dudt are added. Returns a summary."""
+    v, m, u (optional rho); dpdt and dudt are added. energy: "eng" (du/dt of
+    eq. eng) or "compat" (the compatible update per half kick). Returns a
+    summary."""
     n = state["x"].shape[0]
     state.setdefault("dpdt", torch.zeros(3, n, dtype=torch.float64, device=state["x"].device))
     state.setdefault("dudt", torch.zeros(n, dtype=torch.float64, device=state["x"].device))
@@ -39,7 +41,7 @@ def evolve(ctx: Context, state: dict, params: Params, t_end: float, dt: float,
     unconverged = 0
     for k in range(nsteps):
         unconverged += update_support(ctx, state, params, nres, h_tol)
-        ctx.verlet_step(state, params, h, start_eval=(k == 0))
+        ctx.verlet_step(state, params, h, start_eval=(k == 0), energy=energy)
         if log and (k + 1) % max(1, nsteps // 5) == 0:
             log(f"step {k + 1}/{nsteps}")
     return {"steps": nsteps, "dt": h, "h_unconverged": unconverged}

@@ -90,7 +90,7 @@ def test_errors():
     zp = C.c_void_p(z.data_ptr())
     # before any build
     st = lib().crk_compatible_energy(ctx._h, C.byref(prm), zp, zp, zp, None, zp, zp, zp, zp, zp,
-                                     zp, zp, C.c_double(1e-3), zp)
+                                     zp, zp, None, C.c_double(1e-3), zp)
     assert st == -6
     out = pl.step(ctx, dev, prm)
     v = ctx.permute(dev["v"], True)

@@ -1,8 +1,9 @@
 """The shock tube (Sec. 4: two Riemann interfaces in a periodic box, states
 rho = P = 1 and rho = P = 1/8, same temperature) evolved to t = 0.15 with
 the velocity-Verlet step and the h iteration on the GPU (adaptive mixed
-precision, n_high = 20: 288,000 particles, 72 steps), against the exact
-Riemann solution on x in [0, 1):
+precision, n_high = 20: 288,000 particles, 72 steps), with the energy from
+du/dt of eq. eng or from the compatible update per half kick, against the
+exact Riemann solution on x in [0, 1):
 
 * the rarefaction head, the contact and the shock travel at the exact
   speeds (front positions within two particle spacings);
@@ -10,10 +11,9 @@ Riemann solution on x in [0, 1):
   across the contact match the exact star state within a few per cent;
 * the undisturbed states ahead of both waves are kept.
 
-The entropy of the expanded gas behind the rarefaction is not checked: with
-the conservative energy derivative of eq. eng (the partner's pressure in
-each pair term) it comes out ~25% low at these resolutions, which is what
-the paper's compatible energy update exists to correct."""
+The entropy of the expanded gas behind the rarefaction is not checked: it
+comes out ~10% low in u (~20% high in density) at this resolution in both
+modes, where the rarefaction fan spans only a few smoothing lengths."""
 import numpy as np
 import pytest
 import torch
@@ -37,15 +37,16 @@ def _front(x, q, lo, hi, level):
     return x[s].max()
 
 
-def test_shock_tube_waves_and_plateaus():
+@pytest.mark.parametrize("energy", ["eng", "compat"])
+def test_shock_tube_waves_and_plateaus(energy):
     nh = 20
     ps = ci.sod_tube(nh, gamma=G)
     d = 0.5 / nh
-    print(f"[case] shock tube n_high={nh} n={ps.n}", flush=True)
+    print(f"[case] shock tube n_high={nh} n={ps.n} energy={energy}", flush=True)
     st = pl.upload(ps)
     ctx = Context(0)
     prm = pl.params_for(ps, 64.0, CRK_MIXED_ADAPT)
-    info = ig.evolve(ctx, st, prm, T, 0.25 * d / 3.0)
+    info = ig.evolve(ctx, st, prm, T, 0.25 * d / 3.0, energy=energy)
     out = pl.step(ctx, st, prm)
     torch.cuda.synchronize()
     V = pl.to_original({"V": out["V"]}, out["perm"])["V"]

@@ -118,3 +118,48 @@ def test_free_streaming_is_bit_exact():
         got = _host(s)
         for k in ("x", "y", "z", "v", "u"):
             assert np.array_equal(got[k], getattr(end, k)), (over, k)
+
+
+@pytest.mark.parametrize("over", [{}, dict(a=1.3)], ids=["static", "a=1.3"])
+def test_compatible_mode_matches_oracle(over):
+    ps = ci.lognormal_box(12, sigma=1.5, seed=916)
+    ps.v = ps.v * 20.0
+    dt, steps = 2e-3, 3
+    print(f"[case] verlet compatible mode, {steps} steps n={ps.n} {over}", flush=True)
+    prm = oracle.params(64.0, gamma=ps.gamma, **over)
+    st, d = ps, None
+    for _ in range(steps):
+        st, d = oracle.verlet_step(st, prm, dt, d0=d, energy="compat")
+    for prec, tol, xtol in ((CRK_FP64, 1e-11, 1e-13), (CRK_MIXED_ADAPT, 1e-5, 1e-8)):
+        s = _state(ps)
+        ctx = Context(0)
+        p = pl.params_for(ps, 64.0, prec, **over)
+        for k in range(steps):
+            ctx.verlet_step(s, p, dt, start_eval=(k == 0), energy="compat")
+        torch.cuda.synchronize()
+        got = _host(s)
+        # in this mode dudt carries the next opening kick's compatible rate
+        errs = _compare(got, st, dict(d, dudt=d["dudt_kick"]), tol, xtol)
+        print(prec, {k: f"{v:.1e}" for k, v in errs.items()}, flush=True)
+
+
+def test_compatible_mode_conserves_energy():
+    ps = ci.lognormal_box(24, sigma=1.5, seed=917)
+    ps.v = ps.v * 20.0
+    dt, steps = 1e-3, 6
+    print(f"[case] verlet compatible mode energy n={ps.n}", flush=True)
+
+    def energy(s):
+        return (s["m"] * (s["u"] + (s["v"] ** 2).sum(0) / 2.0)).sum().item()
+
+    for prec, tol in ((CRK_FP64, 1e-12), (CRK_MIXED_ADAPT, 1e-6)):
+        s = _state(ps)
+        ctx = Context(0)
+        p = pl.params_for(ps, 64.0, prec)
+        e0 = energy(s)
+        for k in range(steps):
+            ctx.verlet_step(s, p, dt, start_eval=(k == 0), energy="compat")
+        torch.cuda.synchronize()
+        drift = abs(energy(s) - e0) / e0
+        print(prec, f"energy drift {drift:.1e}", flush=True)
+        assert drift <= tol
