@@ -54,16 +54,28 @@ COUNTERS = os.path.join(ROOT, "profiles", "k_deriv_counters.json")
 DERIV_SOURCE = os.path.join(ROOT, "paper_2202_02840_amd", "csrc", "crk_pairs.hip")
 
 
+def code_sha256(path: str) -> str:
+    """Hash of a C++ source with its comments and blank lines removed, so a
+    change of comments alone does not count as a change of the kernel."""
+    import hashlib
+    import re
+    src = open(path).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    src = re.sub(r"//[^\n]*", "", src)
+    lines = [ln.rstrip() for ln in src.splitlines() if ln.strip()]
+    return hashlib.sha256("\n".join(lines).encode()).hexdigest()
+
+
 def deriv_traffic(precision: str, lanes: int):
     """HBM bytes per k_deriv launch from the committed rocprofv3 counter runs
     (FETCH_SIZE and WRITE_SIZE scaled by the copy-probe factors), or None when
-    the kernel source or its launch shape differs from the one measured."""
-    import hashlib
+    the kernel source (its code, comments aside) or its launch shape differs
+    from the one measured."""
     if not os.path.exists(COUNTERS):
         return None
     rec = json.load(open(COUNTERS))
-    sha = hashlib.sha256(open(DERIV_SOURCE, "rb").read()).hexdigest()
-    if rec.get("source_sha256") != sha or rec.get("precision") != precision or rec.get("lanes") != lanes:
+    if (rec.get("source_code_sha256") != code_sha256(DERIV_SOURCE) or
+            rec.get("precision") != precision or rec.get("lanes") != lanes):
         return None
     return (rec["fetch_kib"] * rec["fetch_scale"] + rec["write_kib"] * rec["write_scale"]) * 1024.0
 
@@ -194,7 +206,7 @@ def full_size_leg(args, prec, theta=None) -> dict:
 
 
 def timestep_leg(ctx, dev, prm, args, deriv_ms_plain: float) -> dict:
-    """The Courant terms of Sec. 2.4 fused into the derivative pass: the same
+    """The Courant terms of Sec. 3.1 fused into the derivative pass: the same
     step with the terms on, the derivative pass's event time against the
     plain one, and the per-particle combination (crk_timestep)."""
     import torch
@@ -274,7 +286,7 @@ def verlet_leg(ctx, args, prec) -> dict:
     Courant steps). Reports the wall time per step, the elementwise kernels'
     share and the change of the total energy sum m (u + |p|^2 / (2 a^4)).
     The step is the smallest Courant step dt_hyd of the start state
-    (Sec. 2.4, C_CFL = 0.25)."""
+    (Sec. 3.1, C_CFL = 0.25)."""
     import torch
     import crk_inputs as ci
     from paper_2202_02840_amd import pipeline as pl

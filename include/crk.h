@@ -201,7 +201,7 @@ crk_status crk_derivatives(crk_ctx *ctx, const crk_params *p, const double *v, c
                            double *dpdt, double *dudt);
 
 /*
- * Time-step terms of the Courant criterion (Sec. 2.4; an extension beyond
+ * Time-step terms of the Courant criterion (Sec. 3.1; an extension beyond
  * the pair passes). crk_set_timestep(ctx, 1) makes every later
  * crk_derivatives call (and a step recorded after it) also keep, per
  * particle, the largest closing speed over its pair set, max_j max(-w_ij, 0)

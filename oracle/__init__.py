@@ -267,7 +267,7 @@ def compatible_energy(x, y, z, H, v, m, u, rho, V, corr, gv, soff, sidx, prm, dp
 
 
 def timestep(H, u, m, rho, V, gv, vsig, qrho, prm, zeta=4.0, c_cfl=0.25):
-    """Courant criterion of Sec. 2.4 per particle: (v_max [n], dt_hyd [n]) with
+    """Courant criterion of Sec. 3.1 per particle: (v_max [n], dt_hyd [n]) with
     v_max = max(v_sig, c_s, c_sq, (h_hat / a) |div u|), c_sq = sqrt(zeta Q/rho),
     |div u| = |Tr grad v + 3 adot|, h_hat = H / n_h, and dt_hyd = C_CFL h_hat /
     v_max in time (the caller applies dy/dt)."""

@@ -650,7 +650,7 @@ typedef struct {
 /* du_i/dt = E_i / m_i, and the conditioning sums                       */
 /*   SF_i = sum |(a^2/2) V_i V_j (P_i+Q_i+P_j+Q_j)| |D|,  SE_i = sum |E term|. */
 /* rho == NULL means rho = m / V.                                       */
-/* Time-step terms (Sec. 2.4, the signal velocity and viscous sound     */
+/* Time-step terms (Sec. 3.1, the signal velocity and viscous sound     */
 /* speed of the Courant criterion), when VS / QR are non-NULL:          */
 /*   w_ij = (xdot_ij + (adot/a) x_ij).x_ij / |x_ij|,                     */
 /*   VS_i = max_j max(-w_ij, 0)  (the closing speed of approaching pairs),*/

@@ -526,7 +526,7 @@ struct PairConst {
     T Cl, Cq, eps2, inv_a, adot, eta_c, inv_eta_f, half_a2, half_inv_a2;
 };
 
-// With TS also the pair's time-step terms (Sec. 2.4): vs = the closing speed
+// With TS also the pair's time-step terms (Sec. 3.1): vs = the closing speed
 // max(-w, 0), w = (xdot_ij + (adot/a) x_ij).x_ij / r, and qr = Q_i / rho_i.
 template <typename T, bool TS = false>
 __device__ __forceinline__ void deriv_pair(const State<T> &si, const State<T> &sj, const T d[3],
@@ -893,7 +893,7 @@ __global__ __launch_bounds__(kBlock) void k_compat_fix(const double4 *__restrict
     }
 }
 
-// Courant criterion (Sec. 2.4) per particle from the derivative pass's
+// Courant criterion (Sec. 3.1) per particle from the derivative pass's
 // maxima: c_s from the gas state, c_sq = sqrt(zeta max Q/rho), |div u| =
 // |Tr grad v + 3 adot|, h_hat = H / n_h; v_max = max(v_sig, c_s, c_sq,
 // h_hat |div u| / a) and dt_hyd = C_CFL h_hat / v_max (time; the caller

@@ -1,4 +1,4 @@
-"""GPU parity of the Courant time-step terms (Sec. 2.4) fused into the
+"""GPU parity of the Courant time-step terms (Sec. 3.1) fused into the
 derivative pass: per particle the largest closing speed over the pair set,
 the viscous sound speed from the largest Q_i / rho_i, v_max and dt_hyd, each
 against the oracle (FP64 path 1e-12, mixed paths 1e-5, normwise), in a

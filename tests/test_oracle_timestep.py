@@ -1,4 +1,4 @@
-"""Pins of the oracle's time-step terms (Sec. 2.4: the Courant criterion's
+"""Pins of the oracle's time-step terms (Sec. 3.1: the Courant criterion's
 signal velocity, viscous sound speed and velocity divergence) against
 closed forms and brute force that share none of its code:
 
