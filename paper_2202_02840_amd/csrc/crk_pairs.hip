@@ -794,8 +794,9 @@ __device__ __forceinline__ T compat_term(const V4 &ci, const V4 &cj, const T F[3
 }
 
 // Delta u_i = dt / (2 a^4 m_i) sum_j f_ij c_ij - dt (adot/a)(3(gamma-1)+2) u_i.
+// With NK = 2 a second kick (records ce2, output du2) shares the pair forces.
 // Pairs with an FP64-row flag on either side are left to k_compat_fix.
-template <typename T, int G>
+template <typename T, int G, int NK>
 __global__ __launch_bounds__(kBlock) void k_compat(const double4 *__restrict__ posH,
                                                    const int64_t *__restrict__ goff,
                                                    const int32_t *__restrict__ gidx,
@@ -804,17 +805,21 @@ __global__ __launch_bounds__(kBlock) void k_compat(const double4 *__restrict__ p
                                                    const int32_t *__restrict__ eidx,
                                                    const typename std::conditional<sizeof(T) == 4, float4, double4>::type *__restrict__ rec,
                                                    const typename std::conditional<sizeof(T) == 4, float4, double4>::type *__restrict__ ce,
+                                                   const typename std::conditional<sizeof(T) == 4, float4, double4>::type *__restrict__ ce2,
                                                    const double *__restrict__ m,
                                                    const double *__restrict__ u, int64_t n, Box box,
-                                                   DerivPrm p, double scale, double cool, double *du) {
+                                                   DerivPrm p, double scale, double cool, double *du,
+                                                   double *du2) {
+    using V4 = typename std::conditional<sizeof(T) == 4, float4, double4>::type;
     int l;
     int64_t i = group_index(G, l);
-    Acc<T> a[1];
+    Acc<T> a[NK];
     if (i < n) {
         double4 pi = posH[i];
         State<T> si;
         load_state(rec, i, si);
-        const auto cei = ce[i];
+        const V4 cei = ce[i];
+        const V4 cei2 = NK == 2 ? ce2[i] : cei;
         const PairConst<T> pc = pair_const<T>(p);
         T cwi = (T)kW * si.invH * si.invH * si.invH;
         T cgi = (T)kG * si.invH * si.invH * si.invH * si.invH * si.invH;
@@ -830,21 +835,27 @@ __global__ __launch_bounds__(kBlock) void k_compat(const double4 *__restrict__ p
             double4 pj = posH[j];
             State<T> sj;
             load_state(rec, j, sj);
-            const auto cej = ce[j];
+            const V4 cej = ce[j];
             T d[3];
             separation(pi, pj, box, d[0], d[1], d[2]);
             T F[3], E, pvs, pqr;
             deriv_pair<T, false>(si, sj, d, pc, cwi, cgi, F, E, pvs, pqr);
-            if (sj.fl == (T)0) a[0].add(compat_term<T>(cei, cej, F));
+            if (sj.fl == (T)0) {
+                a[0].add(compat_term<T>(cei, cej, F));
+                if constexpr (NK == 2) a[1].add(compat_term<T>(cei2, ce2[j], F));
+            }
         }
     }
-    group_reduce<T, G, 1>(a);
-    if (i < n && l == 0) du[i] = a[0].value() * (scale / m[i]) - cool * u[i];
+    group_reduce<T, G, NK>(a);
+    if (i < n && l == 0) {
+        du[i] = a[0].value() * (scale / m[i]) - cool * u[i];
+        if constexpr (NK == 2) du2[i] = a[1].value() * (scale / m[i]) - cool * u[i];
+    }
 }
 
 // FP64 pairs of the adaptive mode (as k_deriv_fix): adds their share of
-// the sum to the output of k_compat.
-template <int G>
+// the sum to the output(s) of k_compat.
+template <int G, int NK>
 __global__ __launch_bounds__(kBlock) void k_compat_fix(const double4 *__restrict__ posH,
                                                        const int64_t *__restrict__ goff,
                                                        const int32_t *__restrict__ gidx,
@@ -852,21 +863,24 @@ __global__ __launch_bounds__(kBlock) void k_compat_fix(const double4 *__restrict
                                                        const int32_t *__restrict__ ee,
                                                        const int32_t *__restrict__ eidx, Soa s,
                                                        const double4 *__restrict__ ced,
+                                                       const double4 *__restrict__ ced2,
                                                        const int32_t *__restrict__ flag,
                                                        const int32_t *__restrict__ list, int64_t nlist,
                                                        const double *__restrict__ m, int64_t n, Box box,
-                                                       DerivPrm p, double scale, double *du) {
+                                                       DerivPrm p, double scale, double *du,
+                                                       double *du2) {
     int l;
     int64_t g = group_index(G, l);
     const int64_t gstride = (int64_t)gridDim.x * (kBlock / G);
     for (; g < nlist; g += gstride) {
         const int64_t i = list[g];
-        Acc<double> a[1];
+        Acc<double> a[NK];
         if (i >= 0) {
             double4 pi = posH[i];
             State<double> si;
             load_state_soa(s, posH, n, i, si);
             const double4 cei = ced[i];
+            const double4 cei2 = NK == 2 ? ced2[i] : cei;
             const PairConst<double> pc = pair_const<double>(p);
             double cwi = kW * si.invH * si.invH * si.invH;
             double cgi = kG * si.invH * si.invH * si.invH * si.invH * si.invH;
@@ -886,10 +900,14 @@ __global__ __launch_bounds__(kBlock) void k_compat_fix(const double4 *__restrict
                 double F[3], E, pvs, pqr;
                 deriv_pair<double, false>(si, sj, d, pc, cwi, cgi, F, E, pvs, pqr);
                 a[0].add(compat_term<double>(cei, ced[j], F));
+                if constexpr (NK == 2) a[1].add(compat_term<double>(cei2, ced2[j], F));
             }
         }
-        group_reduce<double, G, 1>(a);
-        if (l == 0 && i >= 0) du[i] += a[0].value() * (scale / m[i]);
+        group_reduce<double, G, NK>(a);
+        if (l == 0 && i >= 0) {
+            du[i] += a[0].value() * (scale / m[i]);
+            if constexpr (NK == 2) du2[i] += a[1].value() * (scale / m[i]);
+        }
     }
 }
 
@@ -1339,12 +1357,15 @@ crk_status crk_timestep(crk_ctx *c, const crk_params *p, const double *u, const 
     return CRK_OK;
 }
 
-crk_status crk_compatible_energy(crk_ctx *c, const crk_params *p, const double *v, const double *m,
-                                 const double *u, const double *rho, const double *V,
-                                 const double *A, const double *B, const double *gA,
-                                 const double *gB, const double *gradv, const double *dpdt,
-                                 const double *pk, double dt, double *du) {
+}  // extern "C"
+
+crk_status crk::compat_pass(crk_ctx *c, const crk_params *p, const double *v, const double *m,
+                            const double *u, const double *rho, const double *V, const double *A,
+                            const double *B, const double *gA, const double *gB,
+                            const double *gradv, const double *dpdt, const double *pk,
+                            const double *pk2, double dt, double *du, double *du2) {
     if (!c) return CRK_ERR_INVALID_ARG;
+    const bool two = du2 != nullptr;
     if (!p || !v || !m || !u || !V || !A || !B || !gA || !gB || !gradv || !dpdt || !du)
         return set_err(c, CRK_ERR_INVALID_ARG, "crk_compatible_energy: NULL argument");
     if (!valid_prec(p->precision)) return set_err(c, CRK_ERR_INVALID_ARG, "bad precision");
@@ -1376,21 +1397,24 @@ crk_status crk_compatible_energy(crk_ctx *c, const crk_params *p, const double *
     if (adapt) CRK_TRY(adapt_rows(c, p, A, B, gA, gB, false, ar));
     if (f32) {
         CRK_TRY(ensure(c, c->rec7, (size_t)n * kRec7 * sizeof(float4)));
-        CRK_TRY(ensure(c, c->ce, (size_t)n * sizeof(float4)));
+        CRK_TRY(ensure(c, c->ce, (size_t)n * sizeof(float4) * (two ? 2 : 1)));
         float4 *r7 = (float4 *)c->rec7.p, *ce = (float4 *)c->ce.p;
-        double4 *aux = nullptr, *ced = nullptr;
+        float4 *ce2 = two ? ce + n : nullptr;
+        double4 *aux = nullptr, *ced = nullptr, *ced2 = nullptr;
         if (adapt) {
             CRK_TRY(ensure(c, c->aux, (size_t)n * sizeof(double4)));
-            CRK_TRY(ensure(c, c->ced, (size_t)n * sizeof(double4)));
+            CRK_TRY(ensure(c, c->ced, (size_t)n * sizeof(double4) * (two ? 2 : 1)));
             aux = (double4 *)c->aux.p;
             ced = (double4 *)c->ced.p;
+            ced2 = two ? ced + n : nullptr;
         }
         {
             KTimer kt_(c, "k_pack");
             k_pack7<float4, float><<<nblocks(n), kBlock, 0, c->stream>>>(n, posH, v, m, u, rho, V, A, B, gA, gB, gradv, dp, ar.flag, r7, aux, bad);
             k_pack_ce<float4, float><<<nblocks(n), kBlock, 0, c->stream>>>(n, v, pk, dpdt, m, u, rho, V, p->gamma, p->a, dt, ce, ced);
+            if (two) k_pack_ce<float4, float><<<nblocks(n), kBlock, 0, c->stream>>>(n, v, pk2, dpdt, m, u, rho, V, p->gamma, p->a, dt, ce2, ced2);
         }
-#define L_CE(GG) k_compat<float, GG><<<gblocks(n, GG), kBlock, 0, c->stream>>>(posH, goff, gidx, eb, ee, eidx, r7, ce, m, u, n, box, dp, scale, cool, du)
+#define L_CE(GG) if (two) k_compat<float, GG, 2><<<gblocks(n, GG), kBlock, 0, c->stream>>>(posH, goff, gidx, eb, ee, eidx, r7, ce, ce2, m, u, n, box, dp, scale, cool, du, du2); else k_compat<float, GG, 1><<<gblocks(n, GG), kBlock, 0, c->stream>>>(posH, goff, gidx, eb, ee, eidx, r7, ce, nullptr, m, u, n, box, dp, scale, cool, du, nullptr)
         {
             KTimer kt_(c, "k_compat");
             CRK_DISPATCH_G(Gd, L_CE);
@@ -1398,21 +1422,23 @@ crk_status crk_compatible_energy(crk_ctx *c, const crk_params *p, const double *
 #undef L_CE
         if (adapt && ar.ntouch > 0) {
             Soa s{v, V, A, B, gA, gB, gradv, aux};
-#define L_CEF(GG) k_compat_fix<GG><<<fix_blocks(ar.ntouch, GG, false), kBlock, 0, c->stream>>>(posH, goff, gidx, eb, ee, eidx, s, ced, ar.flag, ar.tlist, ar.ntouch, m, n, box, dp, scale, du)
+#define L_CEF(GG) if (two) k_compat_fix<GG, 2><<<fix_blocks(ar.ntouch, GG, false), kBlock, 0, c->stream>>>(posH, goff, gidx, eb, ee, eidx, s, ced, ced2, ar.flag, ar.tlist, ar.ntouch, m, n, box, dp, scale, du, du2); else k_compat_fix<GG, 1><<<fix_blocks(ar.ntouch, GG, false), kBlock, 0, c->stream>>>(posH, goff, gidx, eb, ee, eidx, s, ced, nullptr, ar.flag, ar.tlist, ar.ntouch, m, n, box, dp, scale, du, nullptr)
             KTimer kt_(c, "k_compat_fix");
             CRK_DISPATCH_G(Gd, L_CEF);
 #undef L_CEF
         }
     } else {
         CRK_TRY(ensure(c, c->rec7, (size_t)n * kRec7 * sizeof(double4)));
-        CRK_TRY(ensure(c, c->ce, (size_t)n * sizeof(double4)));
+        CRK_TRY(ensure(c, c->ce, (size_t)n * sizeof(double4) * (two ? 2 : 1)));
         double4 *r7 = (double4 *)c->rec7.p, *ce = (double4 *)c->ce.p;
+        double4 *ce2 = two ? ce + n : nullptr;
         {
             KTimer kt_(c, "k_pack");
             k_pack7<double4, double><<<nblocks(n), kBlock, 0, c->stream>>>(n, posH, v, m, u, rho, V, A, B, gA, gB, gradv, dp, nullptr, r7, nullptr, bad);
             k_pack_ce<double4, double><<<nblocks(n), kBlock, 0, c->stream>>>(n, v, pk, dpdt, m, u, rho, V, p->gamma, p->a, dt, ce, nullptr);
+            if (two) k_pack_ce<double4, double><<<nblocks(n), kBlock, 0, c->stream>>>(n, v, pk2, dpdt, m, u, rho, V, p->gamma, p->a, dt, ce2, nullptr);
         }
-#define L_CE(GG) k_compat<double, GG><<<gblocks(n, GG), kBlock, 0, c->stream>>>(posH, goff, gidx, eb, ee, eidx, r7, ce, m, u, n, box, dp, scale, cool, du)
+#define L_CE(GG) if (two) k_compat<double, GG, 2><<<gblocks(n, GG), kBlock, 0, c->stream>>>(posH, goff, gidx, eb, ee, eidx, r7, ce, ce2, m, u, n, box, dp, scale, cool, du, du2); else k_compat<double, GG, 1><<<gblocks(n, GG), kBlock, 0, c->stream>>>(posH, goff, gidx, eb, ee, eidx, r7, ce, nullptr, m, u, n, box, dp, scale, cool, du, nullptr)
         {
             KTimer kt_(c, "k_compat");
             CRK_DISPATCH_G(Gd, L_CE);
@@ -1425,6 +1451,17 @@ crk_status crk_compatible_energy(crk_ctx *c, const crk_params *p, const double *
     CRK_HIP(c, hipStreamSynchronize(c->stream));
     if (pin[0]) return set_err(c, CRK_ERR_NONFINITE, "non-finite or non-positive gas state");
     return CRK_OK;
+}
+
+extern "C" {
+
+crk_status crk_compatible_energy(crk_ctx *c, const crk_params *p, const double *v, const double *m,
+                                 const double *u, const double *rho, const double *V,
+                                 const double *A, const double *B, const double *gA,
+                                 const double *gB, const double *gradv, const double *dpdt,
+                                 const double *pk, double dt, double *du) {
+    return crk::compat_pass(c, p, v, m, u, rho, V, A, B, gA, gB, gradv, dpdt, pk, nullptr, dt, du,
+                            nullptr);
 }
 
 crk_status crk_adaptive_rows(crk_ctx *c, int64_t *n_fp64_rows, int64_t *n_touched_rows) {

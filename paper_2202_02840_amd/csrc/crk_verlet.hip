@@ -60,16 +60,14 @@ __global__ __launch_bounds__(kVB) void k_kick_drift(int64_t n, double a, double 
 // p^1 = p^1/2 + dt/2 dp/dt(1), u^1 = u^1/2 + dt/2 du/dt(1) with the end
 // derivatives in sorted order (perm: sorted -> original), or u^1 = u^1/2 +
 // the compatible change sdc of the closing kick when given; the end
-// derivatives are also returned in the original order for the next step,
-// and with sdc the end momenta in sorted order (p1s, the next kick's start).
+// derivatives are also returned in the original order for the next step.
 __global__ __launch_bounds__(kVB) void k_kick_close(int64_t n, const int32_t *__restrict__ perm,
                                                     double a, double k,
                                                     const double *__restrict__ ph,
                                                     const double *__restrict__ uh,
                                                     const double *__restrict__ sdp,
                                                     const double *__restrict__ sdu,
-                                                    const double *__restrict__ sdc,
-                                                    double *__restrict__ p1s, double *v,
+                                                    const double *__restrict__ sdc, double *v,
                                                     double *u, double *dpdt, double *dudt) {
     const int64_t s = (int64_t)blockIdx.x * kVB + threadIdx.x;
     if (s >= n) return;
@@ -80,22 +78,29 @@ __global__ __launch_bounds__(kVB) void k_kick_close(int64_t n, const int32_t *__
         const double p1 = ph[q * n + i] + k * d;
         v[q * n + i] = p1 / a;
         dpdt[q * n + i] = d;
-        if (p1s) p1s[q * n + s] = p1;
     }
     const double du = sdu[s];
     u[i] = sdc ? uh[i] + sdc[s] : uh[i] + k * du;
     dudt[i] = du;
 }
 
-// sorted gather of the half-step momenta (the closing kick's start)
-__global__ __launch_bounds__(kVB) void k_gather3(int64_t n, const int32_t *__restrict__ perm,
-                                                 const double *__restrict__ src,
-                                                 double *__restrict__ dst) {
+// the two kicks' start momenta in sorted order: p^1/2 (closing kick) and
+// p^1 = p^1/2 + dt/2 dp/dt(1) (the next opening kick), the latter with the
+// same operations as the closing kick itself
+__global__ __launch_bounds__(kVB) void k_gather_kicks(int64_t n, const int32_t *__restrict__ perm,
+                                                      double k, const double *__restrict__ ph,
+                                                      const double *__restrict__ sdp,
+                                                      double *__restrict__ phs,
+                                                      double *__restrict__ p1s) {
     const int64_t s = (int64_t)blockIdx.x * kVB + threadIdx.x;
     if (s >= n) return;
     const int64_t i = perm[s];
 #pragma unroll
-    for (int q = 0; q < 3; q++) dst[q * n + s] = src[q * n + i];
+    for (int q = 0; q < 3; q++) {
+        const double h = ph[q * n + i];
+        phs[q * n + s] = h;
+        p1s[q * n + s] = h + k * sdp[q * n + s];
+    }
 }
 
 // the opening kick's energy change of the next step as a rate: dudt = du / k
@@ -151,16 +156,17 @@ using namespace crk;
 
 extern "C" {
 
-// compatible change of a half kick of length k from the sorted momenta pks
-// (NULL: a v of the evaluation) with the pair forces of the evaluation just
-// made by crk_step (its sorted state and outputs)
+// compatible change of half kicks of length k from the sorted momenta pks
+// (NULL: a v of the evaluation) and, with dus2, pks2, with the pair forces of
+// the evaluation just made by crk_step (its sorted state and outputs)
 static crk_status compat_half(crk_ctx *c, const crk_params *p, const crk_step_io &sio,
-                              const double *pks, double k, double *dus) {
+                              const double *pks, const double *pks2, double k, double *dus,
+                              double *dus2) {
     const double *sv = (const double *)c->sv.p, *sm = (const double *)c->sm.p,
                  *su = (const double *)c->su.p;
     const double *srho = sio.rho ? (const double *)c->srho.p : nullptr;
-    return crk_compatible_energy(c, p, sv, sm, su, srho, sio.V, sio.A, sio.B, sio.gA, sio.gB,
-                                 sio.gradv, sio.dpdt, pks, k, dus);
+    return compat_pass(c, p, sv, sm, su, srho, sio.V, sio.A, sio.B, sio.gA, sio.gB, sio.gradv,
+                       sio.dpdt, pks, pks2, k, dus, dus2);
 }
 
 crk_status crk_verlet_step(crk_ctx *c, int32_t nboxes, const int64_t *box_offsets, int64_t n,
@@ -179,14 +185,15 @@ crk_status crk_verlet_step(crk_ctx *c, int32_t nboxes, const int64_t *box_offset
     // workspace: p^1/2, u^1/2, p_p / a, u_p, the evaluation's outputs, then
     // sorted kick-start momenta and energy changes (compatible mode)
     const bool compat = energy == 1;
-    const size_t nd = (size_t)(8 + kOutDoubles + 4) * n;
+    const size_t nd = (size_t)(8 + kOutDoubles + 8) * n;
     CRK_TRY(ensure(c, c->vstep, nd * sizeof(double) + (size_t)n * sizeof(int32_t)));
     double *w = (double *)c->vstep.p;
     double *ph = w, *uh = w + 3 * n, *vp = w + 4 * n, *up = w + 7 * n;
     int32_t *perm = (int32_t *)(w + nd);
     crk_step_io sio{};
     carve(w + 8 * n, n, perm, sio);
-    double *pks = w + (size_t)(8 + kOutDoubles) * n, *dus = pks + 3 * n;
+    double *pks = w + (size_t)(8 + kOutDoubles) * n, *p1s = pks + 3 * n, *dus = p1s + 3 * n,
+           *dus2 = dus + n;
     const double a = p->a, k = 0.5 * dt, cd = dt / (a * a);
     sio.H = io->H;
     sio.m = io->m;
@@ -206,7 +213,7 @@ crk_status crk_verlet_step(crk_ctx *c, int32_t nboxes, const int64_t *box_offset
         }
         if (compat) {
             // the first opening kick's compatible change, from p = a v
-            CRK_TRY(compat_half(c, p, sio, nullptr, k, dus));
+            CRK_TRY(compat_half(c, p, sio, nullptr, nullptr, k, dus, nullptr));
             k_rate<<<vblocks(n), kVB, 0, c->stream>>>(n, perm, k, dus, io->dudt);
             CRK_HIP(c, hipGetLastError());
         }
@@ -225,23 +232,26 @@ crk_status crk_verlet_step(crk_ctx *c, int32_t nboxes, const int64_t *box_offset
     crk_status st = crk_step(c, nboxes, box_offsets, n, &sio, p, cell_size, n_pairs, nullptr);
     if (st < 0) return st;
     if (compat) {
-        // closing kick: from p^1/2 with the end evaluation's pair forces
-        k_gather3<<<vblocks(n), kVB, 0, c->stream>>>(n, perm, ph, pks);
-        CRK_HIP(c, hipGetLastError());
-        CRK_TRY(compat_half(c, p, sio, pks, k, dus));
+        // the closing kick (from p^1/2) and the next step's opening kick
+        // (from p^1 = p^1/2 + dt/2 dp/dt(1)) share the end evaluation's pair
+        // forces: one pass gives both changes
+        {
+            KTimer kt_(c, "k_verlet");
+            k_gather_kicks<<<vblocks(n), kVB, 0, c->stream>>>(n, perm, k, ph, sio.dpdt, pks, p1s);
+            CRK_HIP(c, hipGetLastError());
+        }
+        CRK_TRY(compat_half(c, p, sio, pks, p1s, k, dus, dus2));
     }
     {
         KTimer kt_(c, "k_verlet");
         k_kick_close<<<vblocks(n), kVB, 0, c->stream>>>(n, perm, a, k, ph, uh, sio.dpdt, sio.dudt,
-                                                         compat ? dus : nullptr, compat ? pks : nullptr,
-                                                         io->v, io->u, io->dpdt, io->dudt);
+                                                         compat ? dus : nullptr, io->v, io->u, io->dpdt,
+                                                         io->dudt);
         CRK_HIP(c, hipGetLastError());
     }
     if (compat) {
-        // the next step's opening kick: from p^1 with the same pair forces,
-        // carried as a rate in dudt
-        CRK_TRY(compat_half(c, p, sio, pks, k, dus));
-        k_rate<<<vblocks(n), kVB, 0, c->stream>>>(n, perm, k, dus, io->dudt);
+        // the next opening kick's change, carried as a rate in dudt
+        k_rate<<<vblocks(n), kVB, 0, c->stream>>>(n, perm, k, dus2, io->dudt);
         CRK_HIP(c, hipGetLastError());
     }
     CRK_HIP(c, hipStreamSynchronize(c->stream));
