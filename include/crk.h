@@ -310,8 +310,11 @@ crk_status crk_step(crk_ctx *ctx, int32_t nboxes, const int64_t *box_offsets, in
  * fused multiply-add). box_offsets: HOST int64 [nboxes+1] as in
  * crk_build_cells_batch. *n_pairs (host, may be NULL): pairs of the end
  * evaluation. Synchronises the stream. Errors: those of crk_step (a particle
- * that moves more than L in one step fails its position check), and
- * CRK_ERR_STATE while a step is being recorded.
+ * that moves more than L in one step fails its position check) and of
+ * crk_compatible_energy (energy = 1), CRK_ERR_INVALID_ARG for a bad energy
+ * mode or dt, and CRK_ERR_STATE while a step is being recorded. After an
+ * error raised past the drift the state arrays are partly advanced and not
+ * valid; restart from a saved state.
  */
 typedef struct {
     double *x, *y, *z;    /* [n] in/out positions in [0, L)                    */
