@@ -105,8 +105,12 @@ def test_free_streaming_is_bit_exact():
     X, Y, Z = (q.ravel() for q in np.meshgrid(g, g, g, indexing="ij"))
     n = X.size
     rng = np.random.default_rng(915)
+    v = rng.normal(0, 1.0, (3, n))
+    # two particles cross the periodic boundary during the step
+    X[0], v[0, 0] = 0.995, 1.5
+    Y[1], v[1, 1] = 0.003, -1.2
     ps = ci.ParticleSet(X, Y, Z, np.full(n, 0.04), np.full(n, 1.0 / n), rng.uniform(0.5, 2.0, n),
-                        rng.normal(0, 1.0, (3, n)), None, L=1.0, meta=dict(kind="pin"))
+                        v, None, L=1.0, meta=dict(kind="pin"))
     dt = 0.02
     for over in ({}, dict(a=0.7)):
         end, d1 = oracle.verlet_step(ps, oracle.params(64.0, **over), dt)
@@ -118,6 +122,28 @@ def test_free_streaming_is_bit_exact():
         got = _host(s)
         for k in ("x", "y", "z", "v", "u"):
             assert np.array_equal(got[k], getattr(end, k)), (over, k)
+        assert got["x"][0] < 0.1 and got["y"][1] > 0.9    # wrapped
+
+
+def test_argument_errors():
+    from paper_2202_02840_amd import CrkError
+    ps = ci.lattice_box(6, seed=918)
+    ctx = Context(0)
+    p = pl.params_for(ps, 64.0, CRK_FP64)
+    for kw in (dict(dt=float("nan")), dict(dt=0.0, energy="compat")):
+        s = _state(ps)
+        with pytest.raises(CrkError) as e:
+            ctx.verlet_step(s, p, kw.pop("dt"), start_eval=True, **kw)
+        assert e.value.status == -1
+        # rejected before anything moved
+        assert torch.equal(s["x"], pl.upload(ps)["x"])
+    # a zero step in the du/dt mode changes nothing but fills the derivatives
+    s = _state(ps)
+    ctx.verlet_step(s, p, 0.0, start_eval=True)
+    torch.cuda.synchronize()
+    for k in ("x", "y", "z", "u"):
+        assert torch.equal(s[k], pl.upload(ps)[k]), k
+    assert s["dpdt"].abs().max() > 0
 
 
 @pytest.mark.parametrize("over", [{}, dict(a=1.3)], ids=["static", "a=1.3"])
