@@ -257,6 +257,27 @@ crk_status crk_compatible_energy(crk_ctx *ctx, const crk_params *p, const double
                                  const double *dpdt, const double *pk, double dt, double *du);
 
 /*
+ * Hierarchical time-step levels of the time integrator (Sec. 3.1), per
+ * particle in sorted order, from the Courant time dt_hyd (crk_timestep, in
+ * time units) and dpdt of the derivative pass:
+ *   dt_acc = sqrt(min(h_hat, r_soft) / |a_hyd|), a_hyd = dp/dt / a^2, the
+ *            hydrodynamic part of the acceleration (gravity is not part of
+ *            this library); infinite where it vanishes;
+ *   dt_min = min(dt_hyd, dt_acc);
+ *   level  = the smallest l >= 0 with dt_min > dt_sub / 2^l, where dt_sub is
+ *            the subcycle length in time units; particles that need a level
+ *            above l_max (0..60) get l_max + 1 and are counted in *n_over.
+ * h_hat = H / n_h from the last build. dt_acc and dt_min may be NULL. Per
+ * particle only: the paper's grouping of the levels by tree leaf and its
+ * limiter between neighbouring leaves are not applied. Synchronises.
+ * Errors: CRK_ERR_INVALID_ARG (NULL, r_soft or dt_sub not positive, l_max
+ * out of range), CRK_ERR_STATE (no build).
+ */
+crk_status crk_time_levels(crk_ctx *ctx, const crk_params *p, const double *dt_hyd,
+                           const double *dpdt, double r_soft, double dt_sub, int32_t l_max,
+                           double *dt_acc, double *dt_min, int32_t *level, int64_t *n_over);
+
+/*
  * One whole step: S1 build (all boxes of a batch), S2 volumes, S4 moments,
  * S5 corrections, S6 velocity gradient and S7 derivatives, i.e. the calls
  * crk_build_cells_batch, crk_moments, crk_corrections, crk_derivatives in

@@ -283,6 +283,29 @@ def timestep(H, u, m, rho, V, gv, vsig, qrho, prm, zeta=4.0, c_cfl=0.25):
     return vmax, c_cfl * hh / vmax
 
 
+def time_levels(H, dt_hyd, dvdt, prm, r_soft, dt_sub, l_max):
+    """Hierarchical time-step levels of Sec. 3.1 per particle, in time units:
+    dt_acc = sqrt(min(h_hat, r_soft) / |a_hyd|) with the hydrodynamic
+    acceleration a_hyd = dp/dt / a^2 (infinite where it vanishes; gravity is
+    not part of these passes), dt_min = min(dt_hyd, dt_acc), and the level l,
+    the smallest l >= 0 with dt_min > dt_sub / 2^l (l_max + 1 when none up
+    to l_max qualifies). Returns (dt_acc, dt_min, level int32)."""
+    H, dt_hyd, dvdt = _f64(H), _f64(dt_hyd), _f64(dvdt).reshape(3, -1)
+    hh = H / prm["nh"]
+    acc = np.sqrt((dvdt ** 2).sum(0)) / prm["a"] ** 2
+    with np.errstate(divide="ignore"):
+        dt_acc = np.where(acc > 0.0, np.sqrt(np.minimum(hh, r_soft) / np.where(acc > 0.0, acc, 1.0)),
+                          np.inf)
+    dt_min = np.minimum(dt_hyd, dt_acc)
+    level = np.empty(H.shape[0], dtype=np.int32)
+    for i in range(H.shape[0]):
+        l = 0
+        while l <= l_max and not dt_min[i] > dt_sub / 2.0 ** l:
+            l += 1
+        level[i] = l
+    return dt_acc, dt_min, level
+
+
 def thacker_step(H, N, Nres):
     return lib().orc_thacker_step(float(H), float(N), float(Nres))
 

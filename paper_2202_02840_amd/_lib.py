@@ -24,7 +24,7 @@ EXPORTS = ("crk_params_default", "crk_create", "crk_destroy", "crk_last_error", 
            "crk_hnet_features", "crk_hnet_forward", "crk_hnet_train_step", "crk_hnet_seed",
            "crk_hnet_targets", "crk_step", "crk_graph_capture", "crk_graph_replay",
            "crk_graph_destroy", "crk_set_timestep", "crk_timestep", "crk_compatible_energy",
-           "crk_verlet_step",
+           "crk_verlet_step", "crk_time_levels",
            "crk_version")
 
 # members of crk_step_io, in order
@@ -109,6 +109,7 @@ def lib():
             "crk_timestep": ([p, p, p, p, p, p, p, d, d, p, p, p, p], i32),
             "crk_compatible_energy": ([p, p] + [p] * 12 + [d, p], i32),
             "crk_verlet_step": ([p, i32, p, i64, p, p, d, d, i32, i32, p], i32),
+            "crk_time_levels": ([p, p, p, p, d, d, i32, p, p, p, p], i32),
             "crk_hsolve": ([p, d, d, i32, p, p, p], i32),
             "crk_export_neighbors": ([p, i32, p, p, i64, p], i32),
             "crk_set_lanes": ([p, i32, i32, i32, i32], i32),
@@ -310,6 +311,23 @@ class Context:
                                          _ptr(du))
         self._check(st, "crk_compatible_energy")
         return du
+
+    def time_levels(self, params: Params, dt_hyd, dpdt, r_soft: float, dt_sub: float,
+                    l_max: int = 20):
+        """Time-step levels (crk_time_levels), sorted order: dict of dt_acc,
+        dt_min, level (int32) and n_over."""
+        _f64(dt_hyd, dpdt)
+        n = self.n
+        out = dict(dt_acc=self._empty(n), dt_min=self._empty(n),
+                   level=self._empty(n, dtype=torch.int32))
+        nov = C.c_int64()
+        st = lib().crk_time_levels(self._h, C.byref(params), _ptr(dt_hyd), _ptr(dpdt),
+                                   C.c_double(r_soft), C.c_double(dt_sub), int(l_max),
+                                   _ptr(out["dt_acc"]), _ptr(out["dt_min"]), _ptr(out["level"]),
+                                   C.byref(nov))
+        self._check(st, "crk_time_levels")
+        out["n_over"] = nov.value
+        return out
 
     # ---------------------------------------------------------------- whole step / S10 graph
     def step_buffers(self, dev: dict) -> dict:

@@ -5,6 +5,9 @@
 // derivatives), and the closing half kick. The time step dt is the paper's
 // (dt/dy) Delta y; a and adot are held over the step.
 //
+// Also the hierarchical time-step levels of the time integrator (Sec. 3.1)
+// from the Courant time and the hydrodynamic acceleration.
+//
 // The state stays in the caller's (original) particle order; the
 // evaluation's outputs come back in cell-sorted order and the closing kick
 // gathers them through the sort permutation. The elementwise kernels are
@@ -123,6 +126,36 @@ __global__ __launch_bounds__(kVB) void k_unsort_d(int64_t n, const int32_t *__re
 #pragma unroll
     for (int q = 0; q < 3; q++) dpdt[q * n + i] = sdp[q * n + s];
     dudt[i] = sdu[s];
+}
+
+// dt_acc = sqrt(min(h_hat, r_soft) / |a_hyd|), a_hyd = dp/dt / a^2 (infinite
+// when it vanishes), dt_min = min(dt_hyd, dt_acc), and the smallest level
+// l >= 0 with dt_min > dt_sub / 2^l (l_max + 1, counted, when none is); the
+// halvings of dt_sub are exact, as in the definition.
+__global__ __launch_bounds__(kVB) void k_levels(int64_t n, const double4 *__restrict__ posH,
+                                                const double *__restrict__ dt_hyd,
+                                                const double *__restrict__ dpdt, double inv_nh,
+                                                double inv_a2, double r_soft, double dt_sub,
+                                                int l_max, double *dt_acc, double *dt_min,
+                                                int32_t *level,
+                                                unsigned long long *n_over) {
+    const int64_t i = (int64_t)blockIdx.x * kVB + threadIdx.x;
+    if (i >= n) return;
+    const double hh = posH[i].w * inv_nh;
+    const double gx = dpdt[i], gy = dpdt[n + i], gz = dpdt[2 * n + i];
+    const double acc = sqrt(gx * gx + gy * gy + gz * gz) * inv_a2;
+    const double ta = acc > 0.0 ? sqrt(fmin(hh, r_soft) / acc) : INFINITY;
+    const double tm = fmin(dt_hyd[i], ta);
+    int l = 0;
+    double thr = dt_sub;
+    while (l <= l_max && !(tm > thr)) {
+        thr *= 0.5;
+        l++;
+    }
+    if (dt_acc) dt_acc[i] = ta;
+    if (dt_min) dt_min[i] = tm;
+    level[i] = l;
+    if (l > l_max) atomicAdd(n_over, 1ull);
 }
 
 inline unsigned vblocks(int64_t n) { return (unsigned)((n + kVB - 1) / kVB); }
@@ -256,6 +289,32 @@ crk_status crk_verlet_step(crk_ctx *c, int32_t nboxes, const int64_t *box_offset
     }
     CRK_HIP(c, hipStreamSynchronize(c->stream));
     return st;
+}
+
+crk_status crk_time_levels(crk_ctx *c, const crk_params *p, const double *dt_hyd,
+                           const double *dpdt, double r_soft, double dt_sub, int32_t l_max,
+                           double *dt_acc, double *dt_min, int32_t *level, int64_t *n_over) {
+    if (!c) return CRK_ERR_INVALID_ARG;
+    if (!p || !dt_hyd || !dpdt || !level)
+        return set_err(c, CRK_ERR_INVALID_ARG, "crk_time_levels: NULL argument");
+    if (!(p->a > 0.0) || !(p->nh > 0.0) || !(r_soft > 0.0) || !(dt_sub > 0.0) ||
+        !isfinite(dt_sub) || l_max < 0 || l_max > 60)
+        return set_err(c, CRK_ERR_INVALID_ARG, "crk_time_levels: bad parameter");
+    if (!c->built) return set_err(c, CRK_ERR_STATE, "crk_build_cells has not run");
+    CRK_HIP(c, hipSetDevice(c->device));
+    CRK_TRY(ensure(c, c->misc, 256));
+    unsigned long long *cnt = (unsigned long long *)c->misc.p + 12;
+    CRK_HIP(c, hipMemsetAsync(cnt, 0, sizeof(*cnt), c->stream));
+    const int64_t n = c->n;
+    k_levels<<<vblocks(n), kVB, 0, c->stream>>>(n, (const double4 *)c->posH.p, dt_hyd, dpdt,
+                                                 1.0 / p->nh, 1.0 / (p->a * p->a), r_soft, dt_sub,
+                                                 l_max, dt_acc, dt_min, level, cnt);
+    CRK_HIP(c, hipGetLastError());
+    unsigned long long *pin = (unsigned long long *)c->pinned.p + 60;
+    CRK_HIP(c, hipMemcpyAsync(pin, cnt, sizeof(*cnt), hipMemcpyDeviceToHost, c->stream));
+    CRK_HIP(c, hipStreamSynchronize(c->stream));
+    if (n_over) *n_over = (int64_t)*pin;
+    return CRK_OK;
 }
 
 }  // extern "C"

@@ -83,3 +83,42 @@ def test_terms_need_a_derivative_call_with_them_on():
     with pytest.raises(CrkError) as e:
         ctx.timestep(prm, dev["u"], dev["m"], dev["rho"], out["V"], out["gradv"])
     assert e.value.status == -6
+
+
+def test_time_levels_match_oracle():
+    ps = ci.lognormal_box(16, sigma=1.5, seed=805)
+    ps.v = ps.v * 20.0
+    print(f"[case] time levels n={ps.n}", flush=True)
+    ref = _ref(ps)
+    prm_o = oracle.params(64.0, gamma=ps.gamma)
+    dt_sub = 8.0 * float(np.median(ref["dt_hyd"]))
+    r_soft = 0.5 * float(np.median(ps.H)) / prm_o["nh"]
+    l_max = 5
+    # the accelerations scaled up 30x (same scaling on both sides) so
+    # that the acceleration criterion binds for part of the particles
+    sc = 30.0
+    r_acc, r_min, r_lev = oracle.time_levels(ps.H, ref["dt_hyd"], sc * ref["dvdt"], prm_o, r_soft,
+                                             dt_sub, l_max)
+    assert 0 < (r_lev > l_max).sum() < ps.n and len(set(r_lev.tolist())) > 3
+    assert 0 < (r_min < ref["dt_hyd"]).sum() < ps.n
+    # levels whose dt_min sits within 1e-5 of a boundary may differ in the mixed paths
+    edges = dt_sub / 2.0 ** np.arange(l_max + 1)
+    near = (np.abs(r_min[:, None] / edges[None, :] - 1.0) < 1e-5).any(1)
+    for prec, tol in ((CRK_FP64, 1e-12), (CRK_MIXED_ADAPT, 1e-5)):
+        ctx = Context(0)
+        dev = pl.upload(ps)
+        prm = pl.params_for(ps, 64.0, prec)
+        out = pl.step(ctx, dev, prm, timestep=True)
+        lv = ctx.time_levels(prm, out["dt_hyd"], sc * out["dpdt"], r_soft, dt_sub, l_max)
+        torch.cuda.synchronize()
+        got = pl.to_original({k: lv[k] for k in ("dt_acc", "dt_min", "level")}, out["perm"])
+        fin = np.isfinite(r_acc)
+        assert np.array_equal(np.isfinite(got["dt_acc"]), fin)
+        assert normwise(got["dt_acc"][fin], r_acc[fin]) <= tol
+        assert normwise(got["dt_min"], r_min) <= tol
+        if prec == CRK_FP64:
+            assert np.array_equal(got["level"], r_lev)
+            assert lv["n_over"] == int((r_lev > l_max).sum())
+        else:
+            assert np.array_equal(got["level"][~near], r_lev[~near])
+        print(prec, "levels", np.bincount(got["level"]).tolist(), flush=True)

@@ -74,3 +74,29 @@ def test_uniform_compression_on_an_open_lattice():
     assert np.abs(out["vsig"] - c * rmax).max() <= 1e-12 * c
     gv = out["gradv"].reshape(9, -1)
     assert np.abs(gv[0] + gv[4] + gv[8] + 3.0 * c).max() < 1e-9
+
+
+def test_time_levels_definition():
+    """Levels against their definition written out differently (a log2
+    formula with the boundary case checked by hand), the acceleration time
+    in closed form, and the strict inequality at exact powers of two."""
+    prm = oracle.params(64.0, a=1.5)
+    H = np.array([0.2, 0.2, 0.2, 0.2, 0.2, 0.2])
+    dv = np.zeros((3, 6))
+    dv[0, 1] = 8.0            # a_hyd = 8 / 1.5^2
+    dt_sub = 0.1
+    # dt_hyd: plenty, exactly dt_sub/4 (must go one level deeper), tiny, huge, nan-free
+    dt_hyd = np.array([1.0, 1.0, 0.025, 1e-9, 0.0999999, 0.05000001])
+    dt_acc, dt_min, lev = oracle.time_levels(H, dt_hyd, dv, prm, r_soft=0.01, dt_sub=dt_sub, l_max=12)
+    hh = 0.2 / prm["nh"]
+    assert np.isinf(dt_acc[0])
+    assert abs(dt_acc[1] - math.sqrt(min(hh, 0.01) / (8.0 / 1.5 ** 2))) < 1e-15
+    assert dt_min[1] == min(1.0, dt_acc[1])
+    for i in range(6):
+        want = max(0, math.floor(math.log2(dt_sub / dt_min[i])) + 1) if dt_min[i] <= dt_sub else 0
+        if dt_min[i] <= dt_sub and dt_sub / 2.0 ** (want - 1) < dt_min[i]:
+            want -= 1
+        assert lev[i] == min(want, 13), (i, lev[i], want)
+    assert lev[0] == 0 and lev[2] == 3      # 0.025 == 0.1 / 4 is not > 0.1 / 4
+    assert lev[3] == 13                      # beyond l_max: l_max + 1
+    assert lev[4] == 1 and lev[5] == 1
