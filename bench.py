@@ -580,6 +580,7 @@ def main():
                      "frac_of_packed_fp32_peak": achieved_tf / VALU_PEAK_PACKED_FP32,
                      "hbm_algorithmic_gbs": hbm_gbs, "hbm_frac": hbm_gbs / HBM_PEAK_GBS},
         "kernel_ms": kern,
+        "workspace_bytes": ctx.workspace_bytes(),
         "max_rel_err_vs_fp64": errs,
         "err_target_met": None if errs is None else bool(max(errs.values()) <= 1e-5),
         "graph_replay": graph,

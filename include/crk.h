@@ -112,6 +112,13 @@ crk_status crk_create(crk_ctx **out, int device, void *hip_stream);
 void crk_destroy(crk_ctx *ctx);
 const char *crk_last_error(const crk_ctx *ctx);
 
+/* Device memory the context's workspace holds now, in bytes (sorted copies,
+ * neighbour lists, records, scratch; excluding the caller's arrays and a few
+ * KB of pinned host memory). The workspace grows on demand with n and with
+ * the neighbour counts of the data, so query it after a representative call
+ * (e.g. a first step) to learn the footprint. *bytes is a host pointer. */
+crk_status crk_workspace_bytes(crk_ctx *ctx, int64_t *bytes);
+
 /*
  * S1: cell list and neighbour lists (chaining mesh, Sec. 3.3).
  * In:  n particles, x, y, z in [0, L) and support radii H (original order).

@@ -24,7 +24,7 @@ EXPORTS = ("crk_params_default", "crk_create", "crk_destroy", "crk_last_error", 
            "crk_hnet_features", "crk_hnet_forward", "crk_hnet_train_step", "crk_hnet_seed",
            "crk_hnet_targets", "crk_step", "crk_graph_capture", "crk_graph_replay",
            "crk_graph_destroy", "crk_set_timestep", "crk_timestep", "crk_compatible_energy",
-           "crk_verlet_step", "crk_time_levels",
+           "crk_verlet_step", "crk_time_levels", "crk_workspace_bytes",
            "crk_version")
 
 # members of crk_step_io, in order
@@ -110,6 +110,7 @@ def lib():
             "crk_compatible_energy": ([p, p] + [p] * 12 + [d, p], i32),
             "crk_verlet_step": ([p, i32, p, i64, p, p, d, d, i32, i32, p], i32),
             "crk_time_levels": ([p, p, p, p, d, d, i32, p, p, p, p], i32),
+            "crk_workspace_bytes": ([p, p], i32),
             "crk_hsolve": ([p, d, d, i32, p, p, p], i32),
             "crk_export_neighbors": ([p, i32, p, p, i64, p], i32),
             "crk_set_lanes": ([p, i32, i32, i32, i32], i32),
@@ -311,6 +312,12 @@ class Context:
                                          _ptr(du))
         self._check(st, "crk_compatible_energy")
         return du
+
+    def workspace_bytes(self) -> int:
+        """Device bytes the context's workspace holds now."""
+        b = C.c_int64()
+        self._check(lib().crk_workspace_bytes(self._h, C.byref(b)), "crk_workspace_bytes")
+        return b.value
 
     def time_levels(self, params: Params, dt_hyd, dpdt, r_soft: float, dt_sub: float,
                     l_max: int = 20):

@@ -5,6 +5,8 @@
 
 #include <new>
 
+#include <vector>
+
 #include "crk_internal.h"
 
 namespace crk {
@@ -188,11 +190,10 @@ crk_status crk_create(crk_ctx **out, int device, void *hip_stream) {
     return CRK_OK;
 }
 
-void crk_destroy(crk_ctx *c) {
-    if (!c) return;
-    (void)hipSetDevice(c->device);
-    (void)hipStreamSynchronize(c->stream);
-    crk::Buf *all[] = {&c->posH, &c->perm,  &c->cbeg,  &c->cend, &c->goff, &c->gidx, &c->ng,
+// every device workspace buffer of a context (freed by crk_destroy, summed
+// by crk_workspace_bytes)
+static std::vector<crk::Buf *> ctx_buffers(crk_ctx *c) {
+    return {&c->posH, &c->perm,  &c->cbeg,  &c->cend, &c->goff, &c->gidx, &c->ng,
                        &c->eb,    &c->ee,   &c->eidx, &c->keyA,
                        &c->keyB, &c->valA,  &c->valB,  &c->hist, &c->scanTmp, &c->recV,
                        &c->rec6, &c->rec7,  &c->red,   &c->misc, &c->flag, &c->flist,
@@ -201,6 +202,13 @@ void crk_destroy(crk_ctx *c) {
                        &c->hs_iters, &c->hs_pool, &c->hs_rows, &c->hs_rcnt, &c->hs_R, &c->boff,
                        &c->sv, &c->sm, &c->su, &c->srho, &c->gstat, &c->gboff,
                        &c->ecnt, &c->efill, &c->eoff, &c->etmp, &c->ts_vs, &c->ts_qr, &c->ce, &c->ced, &c->vstep};
+}
+
+void crk_destroy(crk_ctx *c) {
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    (void)hipStreamSynchronize(c->stream);
+    const std::vector<crk::Buf *> all = ctx_buffers(c);
     crk::graph_release(c);
     for (crk::Buf *b : all)
         if (b->p) hipFree(b->p);
@@ -214,5 +222,13 @@ void crk_destroy(crk_ctx *c) {
 }
 
 const char *crk_last_error(const crk_ctx *c) { return c ? c->err.c_str() : "null context"; }
+
+crk_status crk_workspace_bytes(crk_ctx *c, int64_t *bytes) {
+    if (!c || !bytes) return CRK_ERR_INVALID_ARG;
+    int64_t t = 0;
+    for (const crk::Buf *b : ctx_buffers(c)) t += (int64_t)b->bytes;
+    *bytes = t;
+    return CRK_OK;
+}
 
 }  // extern "C"

@@ -193,3 +193,18 @@ def test_batch_with_empty_boxes_matches_single_boxes():
             a = np.asarray(res[k])[..., lo:hi]
             r = np.asarray(one[k])
             assert np.abs(a - r).max() <= 1e-12 * max(np.abs(r).max(), 1e-300), (b, k)
+
+
+def test_workspace_bytes_reports_what_the_context_holds():
+    ctx = Context(0)
+    before = ctx.workspace_bytes()
+    small = ci.lattice_box(8, seed=931)
+    pl.step(ctx, pl.upload(small), pl.params_for(small, 64.0, CRK_FP64))
+    after_small = ctx.workspace_bytes()
+    big = ci.lattice_box(16, seed=932)
+    pl.step(ctx, pl.upload(big), pl.params_for(big, 64.0, CRK_FP64))
+    after_big = ctx.workspace_bytes()
+    print(before, after_small, after_big, flush=True)
+    # the lists alone hold 4 B per ordered pair
+    assert after_small > before and after_small >= 4 * 64 * small.n
+    assert after_big > after_small
