@@ -328,6 +328,58 @@ def verlet_leg(ctx, args, prec) -> dict:
     return res
 
 
+def nres268_leg(args, prec) -> dict:
+    """Sensitivity point at the paper's resolution, N_res = 268 (n_h = 4,
+    Sec. 3.6): the same clustered 128^3 recipe with H sized for 268
+    neighbours, the whole step timed, the derivative pass's roofline, and
+    the error against the FP64 GPU path. Lanes from the stored table for
+    this pair density (the nearest entry)."""
+    import torch
+    import crk_inputs as ci
+    from paper_2202_02840_amd import CRK_FP64, Context
+    from paper_2202_02840_amd import autotune as at
+    from paper_2202_02840_amd import pipeline as pl
+    ps = ci.lognormal_box(args.n_side, sigma=1.5, spectral_index=-2.0, seed=2, nngb=268.0)
+    dev = pl.upload(ps)
+    ctx = Context(0)
+    prm = pl.params_for(ps, 268.0, prec, kappa_max=args.kappa)
+    first = pl.step(ctx, dev, prm, count_singular=False)
+    tuned = at.load(prec, first["n_pairs"] / ps.n)
+    if tuned:
+        at.apply(ctx, tuned)
+    for _ in range(max(args.warmup, 1)):
+        out = pl.step(ctx, dev, prm, count_singular=False)
+    torch.cuda.synchronize()
+    ctx.timing(True)
+    ctx.timing_reset()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        out = pl.step(ctx, dev, prm, count_singular=False)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / max(args.steps, 1)
+    dms, dcnt = ctx.timing_read("k_deriv")
+    ctx.timing(False)
+    npairs = int(out["n_pairs"])
+    t_der = dms / max(dcnt, 1) * 1e-3
+    tf = DERIV_FLOPS_PER_PAIR * npairs / t_der / 1e12
+    res = {"workload": f"lognormal clustered gas, {args.n_side}^3, sigma_ln_rho 1.5, P(k)~k^-2, "
+                       f"268-neighbour H, seed 2; N_res = 268",
+           "pairs_per_step": npairs, "mean_pairs_per_particle": npairs / ps.n,
+           "ms_per_step": ms, "pairs_per_s": npairs / (ms * 1e-3),
+           "k_deriv_ms": t_der * 1e3, "k_deriv_tflops": tf, "k_deriv_frac": tf / VALU_PEAK_TFLOPS,
+           "lanes": tuned}
+    if not args.no_check:
+        ref = pl.step(ctx, dev, pl.params_for(ps, 268.0, CRK_FP64), count_singular=False)
+        cur = pl.step(ctx, dev, prm, count_singular=False)
+        torch.cuda.synchronize()
+        res["max_rel_err_vs_fp64"] = max(
+            (cur[k] - ref[k]).abs().max().item() / max(ref[k].abs().max().item(), 1e-300)
+            for k in OUT_KEYS)
+    del ctx, dev
+    torch.cuda.empty_cache()
+    return res
+
+
 def graph_replay_ms(ctx, io, prm, steps: int, warmup: int, box_offsets=None) -> tuple:
     """Record the step as one HIP graph on the buffers of io and time its
     replays (synchronised wall clock); returns (ms per replay, status)."""
@@ -446,6 +498,8 @@ def main():
                     help="skip the leg timing the compatible energy pass")
     ap.add_argument("--no-verlet", action="store_true",
                     help="skip the leg timing velocity-Verlet hydro steps")
+    ap.add_argument("--no-nres268", action="store_true",
+                    help="skip the sensitivity point at N_res = 268")
     ap.add_argument("--full-side", type=int, default=256)
     ap.add_argument("--batch-boxes", type=int, default=512)
     ap.add_argument("--autotune-batch", action="store_true",
@@ -597,6 +651,10 @@ def main():
         line["verlet"] = verlet_leg(ctx, args, prec)
         log(f"verlet leg: {line['verlet']['eng']['ms_per_step']:.3f} ms per step "
             f"({line['verlet']['compat']['ms_per_step']:.3f} with the compatible energy)")
+    if not args.no_nres268:
+        line["nres268"] = nres268_leg(args, prec)
+        log(f"N_res = 268 leg: {line['nres268']['ms_per_step']:.3f} ms per step, "
+            f"{line['nres268']['mean_pairs_per_particle']:.0f} pairs per particle")
     if not args.no_batch:
         line["batch"] = batch_leg(args, prec, args.precision)
         log(f"batch leg {line['batch']['graph_ms_per_step']:.3f} ms per replay")

@@ -100,3 +100,25 @@ def test_adaptive_mode_with_every_row_fp64_equals_fp64_path():
     for k in OUTPUTS:
         den = np.abs(a[k]).max()
         assert np.abs(a[k] - b[k]).max() <= 1e-13 * max(den, 1e-300), k
+
+
+def test_paper_resolution_nres_268():
+    """The paper's resolution, N_res = 268 (n_h = 4): a clustered box with H
+    sized for 268 neighbours (rows past the walk's scratch cap take the long
+    path), lists bit-exact, FP64 path within 1e-12, adaptive within 1e-5."""
+    ps = ci.lognormal_box(24, sigma=1.5, seed=941, nngb=268.0, hcap=0.45)
+    _print_case("lognormal 24^3 N_res 268", ps)
+    ref = oracle_run(ps, nres=268.0)
+    assert ref["n_pairs"] / ps.n > 250
+    for prec, tol in ((CRK_FP64, 1e-12), (CRK_MIXED_ADAPT, 1e-5)):
+        res = gpu_run(ps, prec, nres=268.0)
+        ctx = res["ctx"]
+        off, idx = ctx.export_neighbors(1)
+        rows = rows_original(off, idx, ctx.perm)
+        for i in range(0, ps.n, 97):
+            assert np.array_equal(rows[i], ref["sidx"][ref["soff"][i]:ref["soff"][i + 1]]), i
+        assert res["n_pairs"] == ref["n_pairs"]
+        errs = compare(res, ref)
+        print(prec, {k: f"{e:.1e}" for k, e in errs.items()})
+        for k, e in errs.items():
+            assert e <= tol, (prec, k, e)
