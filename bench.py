@@ -92,11 +92,30 @@ def cpu_baseline(n_side: int) -> dict:
     t0 = time.perf_counter()
     out = oracle.pipeline(ps, prm)
     dt = time.perf_counter() - t0
-    return {"value": out["n_pairs"] / dt, "unit": "pair-interactions/s", "cores": oracle.threads(),
-            "kind": "oracle",
-            "sample": f"full FP64 oracle step (neighbour sets, volume, moments, corrections, grad v, "
-                      f"derivatives) on the same recipe at {n_side}^3 = {ps.n} particles "
-                      f"({out['n_pairs']} pairs, {dt:.2f} s)"}
+    res = {"value": out["n_pairs"] / dt, "unit": "pair-interactions/s", "cores": oracle.threads(),
+           "kind": "oracle",
+           "sample": f"full FP64 oracle step (neighbour sets, volume, moments, corrections, grad v, "
+                     f"derivatives) on the same recipe at {n_side}^3 = {ps.n} particles "
+                     f"({out['n_pairs']} pairs, {dt:.2f} s)"}
+    # the same oracle on one host thread, in a child process (its OpenMP
+    # team size is fixed when the library loads), on a 32^3 sample
+    import subprocess
+    code = ("import json, sys, time; sys.path.insert(0, %r); import bench, oracle; "
+            "ps = bench.make_workload(32); t = time.perf_counter(); "
+            "o = oracle.pipeline(ps, oracle.params(64.0)); d = time.perf_counter() - t; "
+            "print(json.dumps({'pairs': int(o['n_pairs']), 'seconds': d, 'threads': oracle.threads()}))"
+            % ROOT)
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    try:
+        r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True,
+                           timeout=300, check=True)
+        one = json.loads(r.stdout.strip().splitlines()[-1])
+        res["one_thread"] = {"value": one["pairs"] / one["seconds"], "cores": one["threads"],
+                             "sample": f"the same oracle step at 32^3 ({one['pairs']} pairs, "
+                                       f"{one['seconds']:.2f} s)"}
+    except (subprocess.SubprocessError, ValueError, KeyError, IndexError) as e:
+        res["one_thread"] = {"error": str(e)[:200]}
+    return res
 
 
 def hsurrogate_leg(ctx, args) -> dict:
