@@ -103,3 +103,20 @@ def test_errors():
     # a zero step changes nothing in a static background
     du = ctx.compatible_energy(prm, v, m, u, None, out["V"], out, out["gradv"], out["dpdt"], 0.0)
     assert torch.all(du == 0)
+
+
+@pytest.mark.parametrize("prec", [CRK_FP64, CRK_MIXED_ADAPT])
+def test_particles_without_partners_only_cool(prec):
+    """No pairs: Delta u is the expansion term alone, as the oracle gives it."""
+    g = np.arange(3) * (1.0 / 3.0) + 1.0 / 6.0
+    X, Y, Z = (q.ravel() for q in np.meshgrid(g, g, g, indexing="ij"))
+    n = X.size
+    rng = np.random.default_rng(827)
+    ps = ci.ParticleSet(X, Y, Z, np.full(n, 0.1), np.full(n, 1.0 / n), rng.uniform(0.5, 2.0, n),
+                        rng.normal(0, 1, (3, n)), None, L=1.0, meta=dict(kind="pin"))
+    over = dict(a=0.7, adot=0.3)
+    dt = 0.05
+    ref = oracle.pipeline(ps, oracle.params(64.0, **over), dt=dt)
+    assert ref["n_pairs"] == 0
+    got = _gpu(ps, prec, dt, **over)["du_compat"]
+    assert np.abs(got - ref["du_compat"]).max() <= 1e-15 * np.abs(ref["du_compat"]).max()
