@@ -97,6 +97,14 @@ def cpu_baseline(n_side: int) -> dict:
            "sample": f"full FP64 oracle step (neighbour sets, volume, moments, corrections, grad v, "
                      f"derivatives) on the same recipe at {n_side}^3 = {ps.n} particles "
                      f"({out['n_pairs']} pairs, {dt:.2f} s)"}
+    # the oracle's compatible energy pass on the same state, beside the GPU's
+    t0 = time.perf_counter()
+    oracle.compatible_energy(ps.x, ps.y, ps.z, ps.H, ps.v, ps.m, ps.u, ps.rho, out["V"], out,
+                             out["gradv"], out["soff"], out["sidx"], prm, out["dvdt"], 1e-3, ps.L)
+    dtc = time.perf_counter() - t0
+    res["compatible_energy"] = {"value": out["n_pairs"] / dtc, "cores": oracle.threads(),
+                                "sample": f"the oracle's compatible pass at {n_side}^3 "
+                                          f"({out['n_pairs']} pairs, {dtc:.2f} s)"}
     # the same oracle on one host thread, in a child process (its OpenMP
     # team size is fixed when the library loads), on a 32^3 sample
     import subprocess
