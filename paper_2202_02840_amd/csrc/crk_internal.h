@@ -133,12 +133,14 @@ crk_status build_sorted(crk_ctx *c, const double *x, const double *y, const doub
 // The compatible energy pass (crk_compatible_energy) for one kick, or, with
 // du2, for two kicks that share the pair forces of one evaluation and start
 // from the momenta pk and pk2 (a velocity-Verlet closing kick and the next
-// opening kick): one pair loop, two sums.
+// opening kick): one pair loop, two sums. reuse: the arrays are those of the
+// crk_derivatives call just made on this context (same state, same
+// precision), whose packed records and FP64-row lists are used as they are.
 crk_status compat_pass(crk_ctx *c, const crk_params *p, const double *v, const double *m,
                        const double *u, const double *rho, const double *V, const double *A,
                        const double *B, const double *gA, const double *gB, const double *gradv,
                        const double *dpdt, const double *pk, const double *pk2, double dt,
-                       double *du, double *du2);
+                       double *du, double *du2, bool reuse);
 
 // Device status of a graph-mode step (written by the step's own kernels and
 // read back by crk_graph_replay).

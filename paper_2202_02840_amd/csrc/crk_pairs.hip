@@ -1363,7 +1363,7 @@ crk_status crk::compat_pass(crk_ctx *c, const crk_params *p, const double *v, co
                             const double *u, const double *rho, const double *V, const double *A,
                             const double *B, const double *gA, const double *gB,
                             const double *gradv, const double *dpdt, const double *pk,
-                            const double *pk2, double dt, double *du, double *du2) {
+                            const double *pk2, double dt, double *du, double *du2, bool reuse) {
     if (!c) return CRK_ERR_INVALID_ARG;
     const bool two = du2 != nullptr;
     if (!p || !v || !m || !u || !V || !A || !B || !gA || !gB || !gradv || !dpdt || !du)
@@ -1394,7 +1394,18 @@ crk_status crk::compat_pass(crk_ctx *c, const crk_params *p, const double *v, co
     CRK_TRY(zero_async(c, bad, 1));
     const int Gd = c->G_der;
     AdaptRows ar;
-    if (adapt) CRK_TRY(adapt_rows(c, p, A, B, gA, gB, false, ar));
+    // the records, FP64-row flags and lists of the derivative call just made
+    // on this same state are reused when the caller says so (eager only)
+    const bool keep = reuse && c->last_ntouch >= 0 && !c->graph_mode;
+    if (adapt) {
+        if (keep) {
+            ar.flag = (int32_t *)c->flag.p;
+            ar.tlist = (int32_t *)c->tlist.p;
+            ar.ntouch = c->last_ntouch;
+        } else {
+            CRK_TRY(adapt_rows(c, p, A, B, gA, gB, false, ar));
+        }
+    }
     if (f32) {
         CRK_TRY(ensure(c, c->rec7, (size_t)n * kRec7 * sizeof(float4)));
         CRK_TRY(ensure(c, c->ce, (size_t)n * sizeof(float4) * (two ? 2 : 1)));
@@ -1410,7 +1421,7 @@ crk_status crk::compat_pass(crk_ctx *c, const crk_params *p, const double *v, co
         }
         {
             KTimer kt_(c, "k_pack");
-            k_pack7<float4, float><<<nblocks(n), kBlock, 0, c->stream>>>(n, posH, v, m, u, rho, V, A, B, gA, gB, gradv, dp, ar.flag, r7, aux, bad);
+            if (!keep) k_pack7<float4, float><<<nblocks(n), kBlock, 0, c->stream>>>(n, posH, v, m, u, rho, V, A, B, gA, gB, gradv, dp, ar.flag, r7, aux, bad);
             k_pack_ce<float4, float><<<nblocks(n), kBlock, 0, c->stream>>>(n, v, pk, dpdt, m, u, rho, V, p->gamma, p->a, dt, ce, ced);
             if (two) k_pack_ce<float4, float><<<nblocks(n), kBlock, 0, c->stream>>>(n, v, pk2, dpdt, m, u, rho, V, p->gamma, p->a, dt, ce2, ced2);
         }
@@ -1434,7 +1445,7 @@ crk_status crk::compat_pass(crk_ctx *c, const crk_params *p, const double *v, co
         double4 *ce2 = two ? ce + n : nullptr;
         {
             KTimer kt_(c, "k_pack");
-            k_pack7<double4, double><<<nblocks(n), kBlock, 0, c->stream>>>(n, posH, v, m, u, rho, V, A, B, gA, gB, gradv, dp, nullptr, r7, nullptr, bad);
+            if (!keep) k_pack7<double4, double><<<nblocks(n), kBlock, 0, c->stream>>>(n, posH, v, m, u, rho, V, A, B, gA, gB, gradv, dp, nullptr, r7, nullptr, bad);
             k_pack_ce<double4, double><<<nblocks(n), kBlock, 0, c->stream>>>(n, v, pk, dpdt, m, u, rho, V, p->gamma, p->a, dt, ce, nullptr);
             if (two) k_pack_ce<double4, double><<<nblocks(n), kBlock, 0, c->stream>>>(n, v, pk2, dpdt, m, u, rho, V, p->gamma, p->a, dt, ce2, nullptr);
         }
@@ -1461,7 +1472,7 @@ crk_status crk_compatible_energy(crk_ctx *c, const crk_params *p, const double *
                                  const double *gB, const double *gradv, const double *dpdt,
                                  const double *pk, double dt, double *du) {
     return crk::compat_pass(c, p, v, m, u, rho, V, A, B, gA, gB, gradv, dpdt, pk, nullptr, dt, du,
-                            nullptr);
+                            nullptr, false);
 }
 
 crk_status crk_adaptive_rows(crk_ctx *c, int64_t *n_fp64_rows, int64_t *n_touched_rows) {

@@ -191,7 +191,8 @@ extern "C" {
 
 // compatible change of half kicks of length k from the sorted momenta pks
 // (NULL: a v of the evaluation) and, with dus2, pks2, with the pair forces of
-// the evaluation just made by crk_step (its sorted state and outputs)
+// the evaluation just made by crk_step (its sorted state and outputs, and
+// the records its derivative pass packed)
 static crk_status compat_half(crk_ctx *c, const crk_params *p, const crk_step_io &sio,
                               const double *pks, const double *pks2, double k, double *dus,
                               double *dus2) {
@@ -199,7 +200,7 @@ static crk_status compat_half(crk_ctx *c, const crk_params *p, const crk_step_io
                  *su = (const double *)c->su.p;
     const double *srho = sio.rho ? (const double *)c->srho.p : nullptr;
     return compat_pass(c, p, sv, sm, su, srho, sio.V, sio.A, sio.B, sio.gA, sio.gB, sio.gradv,
-                       sio.dpdt, pks, pks2, k, dus, dus2);
+                       sio.dpdt, pks, pks2, k, dus, dus2, true);
 }
 
 crk_status crk_verlet_step(crk_ctx *c, int32_t nboxes, const int64_t *box_offsets, int64_t n,
