@@ -36,7 +36,7 @@ crk_status ensure(crk_ctx *c, Buf &b, size_t bytes) {
         graph_release(c);                     // a recorded graph holds the old address
         hipError_t e = hipStreamSynchronize(c->stream);
         if (e != hipSuccess) return hip_err(c, e, "hipStreamSynchronize");
-        hipFree(b.p);
+        (void)hipFree(b.p);
         b.p = nullptr;
         b.bytes = 0;
     }
@@ -81,12 +81,20 @@ KTimer::KTimer(crk_ctx *ctx, const char *nm) : c(ctx), name(nm) {
     if (!c->timing || c->capturing) return;
     a = pool_get(c);
     b = pool_get(c);
-    if (a && b) hipEventRecord(a, c->stream);
+    if (a && b && hipEventRecord(a, c->stream) == hipSuccess) return;
+    // no timing for this scope: the events go back to the pool
+    if (a) c->ev_pool.push_back(a);
+    if (b) c->ev_pool.push_back(b);
+    a = b = nullptr;
 }
 
 KTimer::~KTimer() {
     if (!a || !b) return;
-    hipEventRecord(b, c->stream);
+    if (hipEventRecord(b, c->stream) != hipSuccess) {
+        c->ev_pool.push_back(a);
+        c->ev_pool.push_back(b);
+        return;
+    }
     c->ev_pend.push_back({name, {a, b}});
 }
 
@@ -211,13 +219,13 @@ void crk_destroy(crk_ctx *c) {
     const std::vector<crk::Buf *> all = ctx_buffers(c);
     crk::graph_release(c);
     for (crk::Buf *b : all)
-        if (b->p) hipFree(b->p);
-    if (c->pinned.p) hipHostFree(c->pinned.p);
+        if (b->p) (void)hipFree(b->p);
+    if (c->pinned.p) (void)hipHostFree(c->pinned.p);
     for (auto &p : c->ev_pend) {
-        hipEventDestroy(p.second.first);
-        hipEventDestroy(p.second.second);
+        (void)hipEventDestroy(p.second.first);
+        (void)hipEventDestroy(p.second.second);
     }
-    for (hipEvent_t e : c->ev_pool) hipEventDestroy(e);
+    for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
     delete c;
 }
 

@@ -49,7 +49,7 @@ __global__ __launch_bounds__(kBlock) void k_validate(const double *x, const doub
     ssum[threadIdx.x] = hsum;
     __syncthreads();
     for (int s = kBlock / 2; s > 0; s >>= 1) {
-        if (threadIdx.x < s) {
+        if ((int)threadIdx.x < s) {
             smax[threadIdx.x] = fmax(smax[threadIdx.x], smax[threadIdx.x + s]);
             smin[threadIdx.x] = fmin(smin[threadIdx.x], smin[threadIdx.x + s]);
             ssum[threadIdx.x] += ssum[threadIdx.x + s];
@@ -574,20 +574,6 @@ __global__ __launch_bounds__(kBlock) void k_extra_rank(const int64_t *__restrict
         for (int u = 0; u < c; u++) r += tmp[b + u] < v ? 1 : 0;
         out[b + r] = v;
     }
-}
-
-__global__ __launch_bounds__(kBlock) void k_sum_i32(const int32_t *a, int64_t n, int64_t *out) {
-    __shared__ int64_t s[kBlock];
-    int64_t acc = 0;
-    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
-        acc += a[i];
-    s[threadIdx.x] = acc;
-    __syncthreads();
-    for (int k = kBlock / 2; k > 0; k >>= 1) {
-        if (threadIdx.x < k) s[threadIdx.x] += s[threadIdx.x + k];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) atomicAdd((unsigned long long *)out, (unsigned long long)s[0]);
 }
 
 __global__ __launch_bounds__(kBlock) void k_set_H(double4 *posH, const double *H, int64_t n) {

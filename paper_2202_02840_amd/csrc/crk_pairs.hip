@@ -1081,8 +1081,6 @@ crk_status crk_moments(crk_ctx *c, const crk_params *p, double *nsum, double *V,
     const double4 *posH = (const double4 *)c->posH.p;
     const int64_t *goff = (const int64_t *)c->goff.p;
     const int32_t *gidx = (const int32_t *)c->gidx.p;
-    const int32_t *eb = (const int32_t *)c->eb.p, *ee = (const int32_t *)c->ee.p,
-                  *eidx = (const int32_t *)c->eidx.p;
     bool f32 = p->precision == CRK_MIXED;
     CRK_TRY(ensure(c, c->recV, (size_t)n * (f32 ? 4 : 8)));
     int Gv = c->G_vol, Gm = c->G_mom;
