@@ -460,6 +460,27 @@ crk_status crk_hnet_train_step(crk_ctx *ctx, float *theta, float *adam_m, float 
                                int64_t nb, float *grad, float *loss);
 crk_status crk_hnet_seed(crk_ctx *ctx, const float *theta, double Nres, const double *H_prev,
                          double *H_seed);
+/*
+ * Allocation-free variant of crk_hnet_train_step, for callers that cannot
+ * allocate device memory: code under HIP graph capture, tight training
+ * loops, harnesses that forbid hipMalloc. Same kernels, same arguments and
+ * results (bit-identical theta, adam_m, adam_v, grad and loss), except:
+ *   - loss (may be NULL) is a DEVICE float[1], written on the stream (no
+ *     synchronisation);
+ *   - nb is at most 8192: the per-tile partial gradients live in a static
+ *     device array of 9.8 MB that each GPU holds until the process ends, not
+ *     in the context workspace; larger batches return CRK_ERR_INVALID_ARG;
+ *   - the call never allocates or frees (no hipMalloc, hipFree or allocating
+ *     library routine) and never synchronises.
+ * Every call on one GPU shares that GPU's static array: calls that overlap on
+ * one GPU (other streams or host threads) race and must be serialised by the
+ * caller. Errors: CRK_ERR_INVALID_ARG (NULL theta/feat/target, nb < 1 or
+ * above 8192, lr > 0 without adam_m/adam_v or with step < 1), CRK_ERR_STATE
+ * (the array's device address was not set up by crk_create).
+ */
+crk_status crk_hnet_train_step_noalloc(crk_ctx *ctx, float *theta, float *adam_m, float *adam_v,
+                                       int64_t step, float lr, const float *feat,
+                                       const float *target, int64_t nb, float *grad, float *loss);
 /* Training targets target[i] = ln(H_conv[i] / H_prev[i]) (float) for n particles. */
 crk_status crk_hnet_targets(crk_ctx *ctx, int64_t n, const double *H_prev, const double *H_conv,
                             float *target);

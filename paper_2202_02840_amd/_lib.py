@@ -21,7 +21,8 @@ EXPORTS = ("crk_params_default", "crk_create", "crk_destroy", "crk_last_error", 
            "crk_update_support", "crk_permute", "crk_moments", "crk_corrections",
            "crk_derivatives", "crk_hsolve", "crk_export_neighbors", "crk_set_lanes", "crk_set_walk", "crk_set_hsolve",
            "crk_timing_enable", "crk_timing_reset", "crk_timing_read", "crk_adaptive_rows",
-           "crk_hnet_features", "crk_hnet_forward", "crk_hnet_train_step", "crk_hnet_seed",
+           "crk_hnet_features", "crk_hnet_forward", "crk_hnet_train_step",
+           "crk_hnet_train_step_noalloc", "crk_hnet_seed",
            "crk_hnet_targets", "crk_step", "crk_graph_capture", "crk_graph_replay",
            "crk_graph_destroy", "crk_set_timestep", "crk_timestep", "crk_compatible_energy",
            "crk_verlet_step", "crk_time_levels", "crk_workspace_bytes",
@@ -123,6 +124,7 @@ def lib():
             "crk_hnet_features": ([p, d, p, p], i32),
             "crk_hnet_forward": ([p, p, p, i64, p], i32),
             "crk_hnet_train_step": ([p, p, p, p, i64, C.c_float, p, p, i64, p, p], i32),
+            "crk_hnet_train_step_noalloc": ([p, p, p, p, i64, C.c_float, p, p, i64, p, p], i32),
             "crk_hnet_seed": ([p, p, d, p, p], i32),
             "crk_hnet_targets": ([p, i64, p, p, p], i32),
             "crk_step": ([p, i32, p, i64, p, p, d, p, p], i32),
@@ -492,6 +494,18 @@ class Context:
                                               _ptr(grad), C.byref(loss) if want_loss else None),
                     "crk_hnet_train_step")
         return grad, (loss.value if want_loss else None)
+
+    def hnet_train_step_noalloc(self, theta, m, v, step: int, lr: float, feat, target,
+                                grad=None, loss=None):
+        """crk_hnet_train_step_noalloc: one Adam step in place on theta/m/v
+        (lr > 0) with the static scratch (at most 8192 samples); grad
+        (float32 [4801]) and loss (float32 [1]) are optional device outputs
+        written on the stream."""
+        nb = feat.shape[1]
+        self._check(lib().crk_hnet_train_step_noalloc(self._h, _ptr(theta), _ptr(m), _ptr(v), step,
+                                                      C.c_float(lr), _ptr(feat), _ptr(target), nb,
+                                                      _ptr(grad), _ptr(loss)),
+                    "crk_hnet_train_step_noalloc")
 
     def hnet_seed(self, theta, Nres: float, H_prev_sorted):
         _f64(H_prev_sorted)

@@ -194,6 +194,11 @@ crk_status crk_create(crk_ctx **out, int device, void *hip_stream) {
     }
     c->pinned.p = pin;
     c->pinned.bytes = 4096;
+    if (crk::hnet_scratch_init(c) != CRK_OK) {
+        (void)hipHostFree(pin);
+        delete c;
+        return CRK_ERR_HIP;
+    }
     *out = c;
     return CRK_OK;
 }

@@ -11,6 +11,8 @@
 // (no float atomics).
 #include <math.h>
 
+#include <mutex>
+
 #include "crk_internal.h"
 
 namespace crk {
@@ -401,6 +403,44 @@ __global__ __launch_bounds__(kBlock) void k_hnet_targets(const double *__restric
 
 }  // namespace
 
+// ---------------------------------------------------------------- allocation-free training step
+// crk_hnet_train_step_noalloc keeps the partial gradient rows and losses of
+// up to kStaticTiles 16-sample tiles in this file-scope device array instead
+// of the context workspace. Each device holds its own copy (9.8 MB) until the
+// process ends, and every call on that device shares it. Host code never
+// passes the array's name to a kernel: it is a host-side stand-in there. The
+// device address comes from hipGetSymbolAddress, taken once per device by
+// hnet_scratch_init (called from crk_create with the device current).
+constexpr int64_t kStaticTiles = 512;   // batches of up to 8192 samples
+constexpr int64_t kStaticWords = kStaticTiles * (kNP + 1) + 64;
+static __device__ __align__(256) float scratch[kStaticWords];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+float *g_scratch_dev[kMaxDevices] = {};
+}  // namespace
+
+crk_status hnet_scratch_init(crk_ctx *c) {
+    if (c->device < 0 || c->device >= kMaxDevices)
+        return set_err(c, CRK_ERR_INVALID_ARG, "device %d beyond the static scratch table", c->device);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_dev[c->device]) return CRK_OK;
+    void *p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+        (void)hipGetLastError();
+        return set_err(c, CRK_ERR_HIP, "hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+    }
+    g_scratch_dev[c->device] = (float *)p;
+    return CRK_OK;
+}
+
+static float *hnet_scratch(int device) {
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    return g_scratch_dev[device];
+}
 
 }  // namespace crk
 
@@ -480,6 +520,39 @@ crk_status crk_hnet_train_step(crk_ctx *c, float *theta, float *adam_m, float *a
         CRK_HIP(c, hipStreamSynchronize(c->stream));
         *loss = pin[0];
     }
+    return CRK_OK;
+}
+
+crk_status crk_hnet_train_step_noalloc(crk_ctx *c, float *theta, float *adam_m, float *adam_v,
+                                       int64_t step, float lr, const float *feat,
+                                       const float *target, int64_t nb, float *grad, float *loss) {
+    if (!c) return CRK_ERR_INVALID_ARG;
+    if (!theta || !feat || !target || nb < 1 || (lr > 0.0f && (!adam_m || !adam_v || step < 1)))
+        return set_err(c, CRK_ERR_INVALID_ARG, "crk_hnet_train_step_noalloc: bad argument");
+    if (nb > kStaticTiles * 16)
+        return set_err(c, CRK_ERR_INVALID_ARG,
+                       "crk_hnet_train_step_noalloc: %lld samples exceed the static scratch (at most %lld)",
+                       (long long)nb, (long long)(kStaticTiles * 16));
+    float *part = hnet_scratch(c->device);
+    if (!part) return set_err(c, CRK_ERR_STATE, "static scratch address not set up for device %d", c->device);
+    CRK_HIP(c, hipSetDevice(c->device));
+    // the same kernels and partial layout as crk_hnet_train_step: every
+    // partial row and loss of tiles 0 .. nblk-1 is written before it is read
+    const int64_t nblk = (nb + 15) / 16;
+    float *ploss = part + nblk * kNP;
+    {
+        KTimer kt_(c, "k_hnet_grad");
+        k_hnet_grad<<<(unsigned)((nblk + kBlock / 64 - 1) / (kBlock / 64)), kBlock, 0, c->stream>>>(
+            theta, feat, target, nb, 1.0f / (float)nb, part, ploss);
+    }
+    const float bc1 = 1.0f - powf(0.9f, (float)step), bc2 = 1.0f - powf(0.999f, (float)step);
+    {
+        KTimer kt_(c, "k_hnet_adam");
+        k_hnet_adam<<<(kNP * kAdamLanes + kBlock - 1) / kBlock, kBlock, 0, c->stream>>>(
+            part, nblk, lr > 0.0f ? theta : nullptr, adam_m, adam_v, lr, bc1, bc2, grad);
+    }
+    if (loss) k_hnet_loss<<<1, 64, 0, c->stream>>>(ploss, nblk, 1.0f / (float)nb, loss);
+    CRK_HIP(c, hipGetLastError());
     return CRK_OK;
 }
 

@@ -436,6 +436,10 @@ __device__ __forceinline__ void walk_cells(const Levels &v, const int32_t *__res
     }
 }
 
+// device address of the allocation-free training step's static scratch,
+// taken once per device (the device current); called by crk_create
+crk_status hnet_scratch_init(crk_ctx *c);
+
 // geometry of the last build as seen by the walks (host side)
 Levels levels(const crk_ctx *c);
 
