@@ -72,7 +72,13 @@ typedef enum {
     CRK_FP64 = 0,  /* every pair term and sum in FP64 */
     CRK_MIXED = 1, /* FP32 pair terms with compensated (Kahan) FP32 sums in every pair pass;
                       separations are formed in FP64 before rounding; the RK solve
-                      (crk_corrections) and every boundary array stay FP64 */
+                      (crk_corrections) and every boundary array stay FP64.
+                      Accuracy depends on the conditioning of the RK solve: on jittered
+                      lattices every output meets 1e-5 normwise against CRK_FP64, but on
+                      clustered inputs with nearly singular m2 it does NOT (measured on
+                      a lognormal 128^3 box, sigma_ln_rho = 1.5: about 3e-2 normwise in
+                      A and B and 1.5e-1 in the velocity gradient). Use CRK_MIXED_ADAPT
+                      for clustered inputs. */
     CRK_MIXED_ADAPT = 2 /* volume and moment passes in FP64 (their sums feed the RK solve,
                       whose conditioning amplifies any rounding in them); velocity-gradient
                       and derivative passes as in CRK_MIXED, except the rows of particles

@@ -40,6 +40,9 @@ class StepIO(C.Structure):
 
 VERLET_FIELDS = ("x", "y", "z", "H", "v", "m", "u", "rho", "dpdt", "dudt")
 
+# values per particle of the arrays of crk_step_io and crk_verlet_io
+STEP_COMPONENTS = dict(v=3, m1=3, m2=6, gm0=3, gm1=9, gm2=18, B=3, gA=3, gB=9, gradv=9, dpdt=3)
+
 
 class VerletIO(C.Structure):
     _fields_ = [(k, C.c_void_p) for k in VERLET_FIELDS]
@@ -163,6 +166,41 @@ def _f64(*ts):
             raise TypeError("boundary arrays are float64")
 
 
+# parameters of the h-surrogate network 8 -> 64 -> 64 -> 1
+HNET_PARAMS = 8 * 64 + 64 + 64 * 64 + 64 + 64 + 1
+
+
+def _arr(t, name: str, ncomp: int, n: int, dtype=torch.float64, optional: bool = False):
+    """Checks one boundary array before it reaches a kernel: a contiguous
+    device tensor of `dtype` holding ncomp * n values, shaped [n] (ncomp 1)
+    or [ncomp, n] / [ncomp * n]. A wrongly sized array would otherwise be
+    read or written out of bounds on the device."""
+    if t is None:
+        if optional:
+            return
+        raise ValueError(f"{name} is required")
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name}: expected a torch tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name}: expected {dtype}, got {t.dtype}")
+    shape = tuple(t.shape)
+    ok = n >= 0 and t.numel() == ncomp * n and (len(shape) == 1 or shape == (ncomp, n) or
+                                                 (ncomp == 1 and shape == (1, n)))
+    if not ok:
+        want = f"[{n}]" if ncomp == 1 else f"[{ncomp}, {n}]"
+        if n < 0:
+            want = "a 1-D particle array"
+        raise ValueError(f"{name}: expected shape {want}, got {list(shape)}")
+    if not _on_device(t):
+        raise ValueError(f"{name}: arrays must be device tensors")
+    if not t.is_contiguous():
+        raise ValueError(f"{name}: arrays must be contiguous")
+
+
+def _on_device(t) -> bool:
+    return t.is_cuda
+
+
 class Context:
     """One crk_ctx bound to a device and a HIP stream (torch's current stream
     by default)."""
@@ -201,10 +239,32 @@ class Context:
     def _empty(self, *shape, dtype=torch.float64):
         return torch.empty(*shape, dtype=dtype, device=self.device)
 
+    def _state_args(self, v, m, u, rho, V, corr: dict):
+        n = self.n
+        _arr(v, "v", 3, n)
+        for k, t in (("m", m), ("u", u), ("V", V)):
+            _arr(t, k, 1, n)
+        _arr(rho, "rho", 1, n, optional=True)
+        for k, nc in (("A", 1), ("B", 3), ("gA", 3), ("gB", 9)):
+            _arr(corr.get(k), k, nc, n)
+
+    def _hnet_args(self, theta, feat, m=None, v=None, target=None) -> int:
+        nb = feat.shape[-1] if isinstance(feat, torch.Tensor) and feat.dim() == 2 else -1
+        _arr(theta, "theta", 1, HNET_PARAMS, dtype=torch.float32)
+        if isinstance(feat, torch.Tensor) and feat.dim() != 2:
+            raise ValueError("feat: expected shape [8, nb]")
+        _arr(feat, "feat", 8, nb, dtype=torch.float32)
+        if target is not None or m is not None:
+            _arr(m, "m", 1, HNET_PARAMS, dtype=torch.float32)
+            _arr(v, "v", 1, HNET_PARAMS, dtype=torch.float32)
+            _arr(target, "target", 1, nb, dtype=torch.float32)
+        return nb
+
     # ---------------------------------------------------------------- S1
     def build_cells(self, x, y, z, H, params: Params, cell_size: float = 0.0):
-        _f64(x, y, z, H)
-        n = x.shape[0]
+        n = x.shape[0] if isinstance(x, torch.Tensor) and x.dim() == 1 else -1
+        for k, t in (("x", x), ("y", y), ("z", z), ("H", H)):
+            _arr(t, k, 1, n)
         perm = self._empty(n, dtype=torch.int32)
         npairs = C.c_int64()
         ncell = C.c_int32()
@@ -218,9 +278,12 @@ class Context:
     def build_cells_batch(self, box_offsets, x, y, z, H, params: Params, cell_size: float = 0.0):
         """box_offsets: host sequence of nboxes+1 particle offsets (0 .. n)."""
         import numpy as np
-        _f64(x, y, z, H)
-        n = x.shape[0]
+        n = x.shape[0] if isinstance(x, torch.Tensor) and x.dim() == 1 else -1
+        for k, t in (("x", x), ("y", y), ("z", z), ("H", H)):
+            _arr(t, k, 1, n)
         off = np.ascontiguousarray(box_offsets, dtype=np.int64)
+        if off.ndim != 1 or len(off) < 2:
+            raise ValueError("box_offsets: expected nboxes + 1 offsets")
         perm = self._empty(n, dtype=torch.int32)
         npairs = C.c_int64()
         ncell = C.c_int32()
@@ -233,7 +296,7 @@ class Context:
         return perm, npairs.value
 
     def update_support(self, H_sorted):
-        _f64(H_sorted)
+        _arr(H_sorted, "H_sorted", 1, self.n)
         npairs = C.c_int64()
         self._check(lib().crk_update_support(self._h, _ptr(H_sorted), C.byref(npairs)),
                     "crk_update_support")
@@ -241,8 +304,8 @@ class Context:
         return npairs.value
 
     def permute(self, src, to_sorted: bool):
-        _f64(src)
-        ncomp = 1 if src.dim() == 1 else src.shape[0]
+        ncomp = 1 if not isinstance(src, torch.Tensor) or src.dim() == 1 else src.shape[0]
+        _arr(src, "src", ncomp, self.n)
         dst = torch.empty_like(src)
         self._check(lib().crk_permute(self._h, _ptr(src), _ptr(dst), ncomp, int(to_sorted)),
                     "crk_permute")
@@ -263,6 +326,8 @@ class Context:
     # ---------------------------------------------------------------- S5
     def corrections(self, mom: dict, count_singular: bool = True):
         n = self.n
+        for k, nc in (("m0", 1), ("m1", 3), ("m2", 6), ("gm0", 3), ("gm1", 9), ("gm2", 18)):
+            _arr(mom.get(k), k, nc, n)
         out = dict(A=self._empty(n), B=self._empty(3, n), gA=self._empty(3, n),
                    gB=self._empty(9, n))
         ns = C.c_int64(-1)
@@ -276,8 +341,8 @@ class Context:
 
     # ---------------------------------------------------------------- S6 + S7
     def derivatives(self, params: Params, v, m, u, rho, V, corr: dict):
-        _f64(v, m, u, rho, V)
         n = self.n
+        self._state_args(v, m, u, rho, V, corr)
         out = dict(gradv=self._empty(9, n), dpdt=self._empty(3, n), dudt=self._empty(n))
         st = lib().crk_derivatives(self._h, C.byref(params), _ptr(v), _ptr(m), _ptr(u), _ptr(rho),
                                    _ptr(V), *[_ptr(corr[k]) for k in ("A", "B", "gA", "gB")],
@@ -291,8 +356,11 @@ class Context:
     def timestep(self, params: Params, u, m, rho, V, gradv, zeta: float = 4.0, c_cfl: float = 0.25):
         """Courant terms after a crk_derivatives call made with set_timestep
         on (sorted order): dict of vsig, csq, vmax, dt_hyd."""
-        _f64(u, m, rho, V, gradv)
         n = self.n
+        for k, t in (("u", u), ("m", m), ("V", V)):
+            _arr(t, k, 1, n)
+        _arr(rho, "rho", 1, n, optional=True)
+        _arr(gradv, "gradv", 9, n)
         out = dict(vsig=self._empty(n), csq=self._empty(n), vmax=self._empty(n), dt_hyd=self._empty(n))
         st = lib().crk_timestep(self._h, C.byref(params), _ptr(u), _ptr(m), _ptr(rho), _ptr(V),
                                 _ptr(gradv), C.c_double(zeta), C.c_double(c_cfl), _ptr(out["vsig"]),
@@ -305,7 +373,11 @@ class Context:
         """Delta u of the compatible energy update over dt (sorted order),
         from the state and outputs of the preceding derivative call; pk:
         optional kick-start momenta [3, n] (sorted)."""
-        _f64(v, m, u, rho, V, gradv, dpdt, pk)
+        n = self.n
+        self._state_args(v, m, u, rho, V, corr)
+        _arr(gradv, "gradv", 9, n)
+        _arr(dpdt, "dpdt", 3, n)
+        _arr(pk, "pk", 3, n, optional=True)
         du = self._empty(self.n)
         st = lib().crk_compatible_energy(self._h, C.byref(params), _ptr(v), _ptr(m), _ptr(u),
                                          _ptr(rho), _ptr(V),
@@ -325,8 +397,9 @@ class Context:
                     l_max: int = 20):
         """Time-step levels (crk_time_levels), sorted order: dict of dt_acc,
         dt_min, level (int32) and n_over."""
-        _f64(dt_hyd, dpdt)
         n = self.n
+        _arr(dt_hyd, "dt_hyd", 1, n)
+        _arr(dpdt, "dpdt", 3, n)
         out = dict(dt_acc=self._empty(n), dt_min=self._empty(n),
                    level=self._empty(n, dtype=torch.int32))
         nov = C.c_int64()
@@ -350,7 +423,11 @@ class Context:
         return io
 
     def _io(self, io: dict):
-        _f64(*[io[k] for k in STEP_INPUTS + STEP_OUTPUTS if k != "perm"])
+        x = io.get("x")
+        n = x.shape[0] if isinstance(x, torch.Tensor) and x.dim() == 1 else -1
+        for k in STEP_INPUTS + STEP_OUTPUTS:
+            _arr(io.get(k), k, STEP_COMPONENTS.get(k, 1), n,
+                 dtype=torch.int32 if k == "perm" else torch.float64, optional=(k == "rho"))
         s = StepIO()
         for k in STEP_INPUTS + STEP_OUTPUTS:
             setattr(s, k, None if io.get(k) is None else io[k].data_ptr())
@@ -381,8 +458,10 @@ class Context:
         evaluation's pair count."""
         mode = {"eng": 0, "compat": 1}[energy]
         import numpy as np
-        n = state["x"].shape[0]
-        _f64(*[state.get(k) for k in VERLET_FIELDS])
+        x = state.get("x")
+        n = x.shape[0] if isinstance(x, torch.Tensor) and x.dim() == 1 else -1
+        for k in VERLET_FIELDS:
+            _arr(state.get(k), k, STEP_COMPONENTS.get(k, 1), n, optional=(k == "rho"))
         off = np.ascontiguousarray([0, n] if box_offsets is None else box_offsets, dtype=np.int64)
         s = VerletIO(*[_ptr(state.get(k)) for k in VERLET_FIELDS])
         npairs = C.c_int64()
@@ -427,7 +506,7 @@ class Context:
 
     # ---------------------------------------------------------------- S3
     def hsolve(self, Nres: float, H_sorted, tol: float = 1e-7, max_iter: int = 100):
-        _f64(H_sorted)
+        _arr(H_sorted, "H_sorted", 1, self.n)
         Hio = H_sorted.clone()
         iters = self._empty(self.n, dtype=torch.int32)
         nun = C.c_int64()
@@ -470,14 +549,14 @@ class Context:
 
     # ---------------------------------------------------------------- S9
     def hnet_features(self, Nres: float, H_sorted):
-        _f64(H_sorted)
+        _arr(H_sorted, "H_sorted", 1, self.n)
         feat = self._empty(8, self.n, dtype=torch.float32)
         self._check(lib().crk_hnet_features(self._h, C.c_double(Nres), _ptr(H_sorted), _ptr(feat)),
                     "crk_hnet_features")
         return feat
 
     def hnet_forward(self, theta, feat):
-        nb = feat.shape[1]
+        nb = self._hnet_args(theta, feat)
         y = self._empty(nb, dtype=torch.float32)
         self._check(lib().crk_hnet_forward(self._h, _ptr(theta), _ptr(feat), nb, _ptr(y)),
                     "crk_hnet_forward")
@@ -486,7 +565,7 @@ class Context:
     def hnet_train_step(self, theta, m, v, step: int, lr: float, feat, target, want_grad=False,
                         want_loss=False):
         """One Adam step in place on theta/m/v (lr > 0); returns (grad, loss)."""
-        nb = feat.shape[1]
+        nb = self._hnet_args(theta, feat, m, v, target)
         grad = self._empty(theta.shape[0], dtype=torch.float32) if want_grad else None
         loss = C.c_float()
         self._check(lib().crk_hnet_train_step(self._h, _ptr(theta), _ptr(m), _ptr(v), step,
@@ -501,21 +580,26 @@ class Context:
         (lr > 0) with the static scratch (at most 8192 samples); grad
         (float32 [4801]) and loss (float32 [1]) are optional device outputs
         written on the stream."""
-        nb = feat.shape[1]
+        nb = self._hnet_args(theta, feat, m, v, target)
+        _arr(grad, "grad", 1, HNET_PARAMS, dtype=torch.float32, optional=True)
+        _arr(loss, "loss", 1, 1, dtype=torch.float32, optional=True)
         self._check(lib().crk_hnet_train_step_noalloc(self._h, _ptr(theta), _ptr(m), _ptr(v), step,
                                                       C.c_float(lr), _ptr(feat), _ptr(target), nb,
                                                       _ptr(grad), _ptr(loss)),
                     "crk_hnet_train_step_noalloc")
 
     def hnet_seed(self, theta, Nres: float, H_prev_sorted):
-        _f64(H_prev_sorted)
+        _arr(theta, "theta", 1, HNET_PARAMS, dtype=torch.float32)
+        _arr(H_prev_sorted, "H_prev_sorted", 1, self.n)
         out = torch.empty_like(H_prev_sorted)
         self._check(lib().crk_hnet_seed(self._h, _ptr(theta), C.c_double(Nres),
                                         _ptr(H_prev_sorted), _ptr(out)), "crk_hnet_seed")
         return out
 
     def hnet_targets(self, H_prev, H_conv):
-        _f64(H_prev, H_conv)
+        nb = H_prev.shape[0] if isinstance(H_prev, torch.Tensor) and H_prev.dim() == 1 else -1
+        _arr(H_prev, "H_prev", 1, nb)
+        _arr(H_conv, "H_conv", 1, nb)
         t = self._empty(H_prev.shape[0], dtype=torch.float32)
         self._check(lib().crk_hnet_targets(self._h, H_prev.shape[0], _ptr(H_prev), _ptr(H_conv),
                                            _ptr(t)), "crk_hnet_targets")
