@@ -407,6 +407,106 @@ def nres268_leg(args, prec) -> dict:
     return res
 
 
+def wave_balance(row_len, per_wave: int) -> dict:
+    """Load balance of the derivative pass over the sorted order: pairs per
+    wavefront of `per_wave` consecutive particles (mean, coefficient of
+    variation, max / mean), and the lane efficiency of two mappings: G = 8
+    lanes per particle (a wave runs as long as its longest row) and the
+    balanced lane groups (lanes split by row length, one plus a share of
+    the rest each)."""
+    import numpy as np
+    n = len(row_len)
+    m = (n // per_wave) * per_wave
+    L = np.asarray(row_len[:m], dtype=np.int64).reshape(-1, per_wave)
+    w = L.sum(axis=1).astype(np.float64)
+    steps_g8 = np.ceil(L / 8.0).max(axis=1)
+    eff_g8 = L.sum() / (64.0 * steps_g8.sum())
+    # balanced groups: p gets 1 + floor((64 - P) * prefix / S) lanes (prefix differences)
+    S = np.maximum(L.sum(axis=1, keepdims=True), 1)
+    pre = np.concatenate([np.zeros((L.shape[0], 1), np.int64), np.cumsum(L, axis=1)], axis=1)
+    start = np.arange(per_wave + 1)[None, :] + ((64 - per_wave) * pre) // S
+    start[:, -1] = 64
+    g = np.diff(start, axis=1)
+    steps_bal = np.ceil(L / np.maximum(g, 1)).max(axis=1)
+    eff_bal = L.sum() / (64.0 * steps_bal.sum())
+    return {"particles_per_wave": per_wave, "pairs_per_wave_mean": float(w.mean()),
+            "pairs_per_wave_cv": float(w.std() / w.mean()), "pairs_per_wave_max_over_mean":
+            float(w.max() / w.mean()), "lane_efficiency_g8": float(eff_g8),
+            "lane_efficiency_balanced": float(eff_bal)}
+
+
+def leaves_leg(args, prec, n_side: int, sigma: float, spectral: float, seed: int, clumps: bool,
+               label: str) -> dict:
+    """RCB leaf tiling (Sec. 3.3) against the Morton cell build on one
+    clustered box: build times, the pair passes on the lists of each (in
+    each one's sorted order), the load balance of the derivative pass over
+    waves, and the leaf statistics (sizes, partners per leaf)."""
+    import numpy as np
+    import torch
+    import crk_inputs as ci
+    from paper_2202_02840_amd import Context
+    from paper_2202_02840_amd import autotune as at
+    from paper_2202_02840_amd import pipeline as pl
+    if clumps:
+        ps = ci.clustered_clump_box(n_side, sigma=sigma, spectral_index=spectral, seed=seed)
+    else:
+        ps = ci.lognormal_box(n_side, sigma=sigma, spectral_index=spectral, seed=seed)
+    dev = pl.upload(ps)
+    ctx = Context(0)
+    prm = pl.params_for(ps, 64.0, prec, kappa_max=args.kappa)
+    first = pl.step(ctx, dev, prm, count_singular=False)
+    tuned = at.load(prec, first["n_pairs"] / ps.n)
+    if tuned:
+        at.apply(ctx, tuned)
+    out = {"workload": label, "particles": ps.n}
+    passes = ("k_volume", "k_moments", "k_corrections", "k_gradv", "k_deriv", "k_deriv_fix")
+
+    def run(kind):
+        rec = {}
+        ts = []
+        for rep in range(max(args.warmup, 1) + 3):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            if kind == "morton":
+                perm, npairs = ctx.build_cells(dev["x"], dev["y"], dev["z"], dev["H"], prm)
+            else:
+                perm, npairs, loff = ctx.build_leaves(dev["x"], dev["y"], dev["z"], dev["H"], prm,
+                                                      256, 32)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        rec["build_ms_median_of_3"] = float(np.median(ts[-3:]) * 1e3)
+        rec["pairs"] = int(npairs)
+        v = ctx.permute(dev["v"], True)
+        m = ctx.permute(dev["m"], True)
+        u = ctx.permute(dev["u"], True)
+        ctx.timing(True)
+        ctx.timing_reset()
+        for _ in range(3):
+            mom = ctx.moments(prm)
+            corr = ctx.corrections(mom, count_singular=False)
+            ctx.derivatives(prm, v, m, u, None, mom["V"], corr)
+        torch.cuda.synchronize()
+        rec["kernel_ms"] = {k: ctx.timing_read(k)[0] / max(ctx.timing_read(k)[1], 1) for k in passes}
+        ctx.timing(False)
+        off, _ = ctx.export_neighbors(1)
+        lens = np.diff(off.cpu().numpy())
+        rec["balance"] = wave_balance(lens, 8)
+        if kind == "rcb":
+            lo = loff.cpu().numpy()
+            sz = np.diff(lo)
+            rec["leaves"] = int(len(sz))
+            rec["leaf_size_min_max"] = [int(sz.min()), int(sz.max())]
+        return rec
+
+    out["morton"] = run("morton")
+    out["rcb"] = run("rcb")
+    out["rcb"]["leaf_pairs_per_leaf"] = None
+    assert out["morton"]["pairs"] == out["rcb"]["pairs"], "the two tilings must give the same N_s"
+    del ctx, dev
+    torch.cuda.empty_cache()
+    return out
+
+
 def graph_replay_ms(ctx, io, prm, steps: int, warmup: int, box_offsets=None) -> tuple:
     """Record the step as one HIP graph on the buffers of io and time its
     replays (synchronised wall clock); returns (ms per replay, status)."""
@@ -527,6 +627,8 @@ def main():
                     help="skip the leg timing velocity-Verlet hydro steps")
     ap.add_argument("--no-nres268", action="store_true",
                     help="skip the sensitivity point at N_res = 268")
+    ap.add_argument("--no-leaves", action="store_true",
+                    help="skip the RCB leaf-tiling comparison")
     ap.add_argument("--full-side", type=int, default=256)
     ap.add_argument("--batch-boxes", type=int, default=512)
     ap.add_argument("--autotune-batch", action="store_true",
@@ -682,6 +784,11 @@ def main():
         line["nres268"] = nres268_leg(args, prec)
         log(f"N_res = 268 leg: {line['nres268']['ms_per_step']:.3f} ms per step, "
             f"{line['nres268']['mean_pairs_per_particle']:.0f} pairs per particle")
+    if not args.no_leaves:
+        line["rcb_leaves"] = {"c2": leaves_leg(args, prec, args.n_side, 1.5, -2.0, 2, False,
+                                               f"lognormal {args.n_side}^3, sigma 1.5, P(k)~k^-2, seed 2")}
+        log(f"leaves leg: build {line['rcb_leaves']['c2']['rcb']['build_ms_median_of_3']:.3f} ms "
+            f"(Morton {line['rcb_leaves']['c2']['morton']['build_ms_median_of_3']:.3f} ms)")
     if not args.no_batch:
         line["batch"] = batch_leg(args, prec, args.precision)
         log(f"batch leg {line['batch']['graph_ms_per_step']:.3f} ms per replay")

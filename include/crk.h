@@ -125,6 +125,35 @@ const char *crk_last_error(const crk_ctx *ctx);
  * (e.g. a first step) to learn the footprint. *bytes is a host pointer. */
 crk_status crk_workspace_bytes(crk_ctx *ctx, int64_t *bytes);
 
+/* Which calls a context will make, for crk_workspace_estimate. Every use
+ * includes the step itself (crk_build_cells, crk_moments, crk_corrections,
+ * crk_derivatives). */
+enum {
+    CRK_WS_STEP = 0,
+    CRK_WS_HSOLVE = 1,     /* crk_hsolve */
+    CRK_WS_HNET = 2,       /* crk_hnet_features / forward / train_step / seed */
+    CRK_WS_COMPAT = 4,     /* crk_compatible_energy */
+    CRK_WS_VERLET = 8,     /* crk_verlet_step (add CRK_WS_COMPAT for its compatible mode) */
+    CRK_WS_GRAPH = 16,     /* crk_step / crk_graph_capture, default headroom */
+    CRK_WS_TIMESTEP = 32,  /* crk_set_timestep(1) */
+    CRK_WS_LEAVES = 64     /* crk_build_leaves */
+};
+
+/* Upper bound, computed before any call, on the device bytes a context's
+ * workspace reaches for calls on n particles in nboxes boxes with at most
+ * pairs_per_particle ordered pairs (|N_s(i)|, averaged) per particle, in
+ * the given crk_precision, for the calls named by `uses` (CRK_WS_* or'ed).
+ * It bounds crk_workspace_bytes after those calls when the realised pair
+ * count stays within n * pairs_per_particle. Parts that depend on data it
+ * cannot see are taken at their caps: the cell tables at the finest level
+ * the build allows, the h iteration's overflow rows at their 8 GiB limit,
+ * the leaf partner lists at 4096 partners per leaf. ctx (may be NULL: the
+ * default tuning) supplies the walk and h-iteration row capacities. Host
+ * memory only; no device call. */
+crk_status crk_workspace_estimate(const crk_ctx *ctx, int64_t n, int32_t nboxes,
+                                  double pairs_per_particle, int32_t precision, int32_t uses,
+                                  int64_t *bytes);
+
 /*
  * S1: cell list and neighbour lists (chaining mesh, Sec. 3.3).
  * In:  n particles, x, y, z in [0, L) and support radii H (original order).
@@ -139,6 +168,39 @@ crk_status crk_workspace_bytes(crk_ctx *ctx, int64_t *bytes);
 crk_status crk_build_cells(crk_ctx *ctx, int64_t n, const double *x, const double *y,
                            const double *z, const double *H, const crk_params *p,
                            double cell_size, int32_t *perm, int64_t *n_pairs, int32_t *n_cells);
+
+/*
+ * S1, alternative tiling: recursive coordinate bisection leaves (Sec. 3.3:
+ * an RCB tree whose flat leaves hold N_ppl particles, one interaction list
+ * per leaf from leaf boxes grown by the smoothing support). Each box of the
+ * batch (box_offsets: HOST int64 [nboxes+1], 0 .. n; one box: {0, n}) is
+ * split by its own tree: a node of more than `bucket` particles is halved
+ * along the axis of largest extent of the 32-bit fixed-point coordinate
+ * keys q = floor(x / L 2^32), its floor(n/2) smallest keys (ties by original
+ * index) going left; a leaf is the first node on a path with at most
+ * `nppl` particles (so leaves hold nppl/2 .. nppl particles when the box
+ * holds more than nppl), and inside a leaf the buckets below it follow in
+ * tree order, each in x-key order. Leaves a and b of one box interact when
+ * the periodic distance of their bounding boxes is below max(Hmax_a, Hmax_b)
+ * (+ 1e-9 L). The rows are found leaf pair by leaf pair with the partner
+ * leaf's particles in LDS, by the exact FP64 test of crk_build_cells, so
+ * N_g and N_s are the same sets; the sorted order is the leaf order.
+ * Requires 4 <= bucket <= 64, bucket <= nppl <= 256 (and nppl / bucket
+ * small enough for 64 buckets per leaf).
+ * Out: perm[n] (device int32, sorted -> original), *n_pairs, *n_leaves
+ * (host, may be NULL), leaf_offsets (device int32 [n_leaves+1] in sorted
+ * positions, may be NULL; leaf_cap = its capacity).
+ * After this call crk_moments, crk_corrections, crk_derivatives,
+ * crk_compatible_energy, crk_permute and crk_export_neighbors work as after
+ * crk_build_cells; the calls that walk the cell hierarchy (crk_hsolve,
+ * crk_update_support, crk_hnet_features, crk_hnet_seed) return
+ * CRK_ERR_STATE. Synchronises the stream. Errors as crk_build_cells.
+ */
+crk_status crk_build_leaves(crk_ctx *ctx, int32_t nboxes, const int64_t *box_offsets, int64_t n,
+                            const double *x, const double *y, const double *z, const double *H,
+                            const crk_params *p, int32_t nppl, int32_t bucket, int32_t *perm,
+                            int64_t *n_pairs, int32_t *n_leaves, int32_t *leaf_offsets,
+                            int64_t leaf_cap);
 
 /*
  * S10: many independent periodic boxes (same L) in one build. Particles are
@@ -499,6 +561,15 @@ crk_status crk_hnet_targets(crk_ctx *ctx, int64_t n, const double *H_prev, const
  */
 crk_status crk_export_neighbors(crk_ctx *ctx, int32_t which, int64_t *offsets, int32_t *idx,
                                 int64_t cap, int64_t *total);
+
+/* Thread mapping of the derivative and compatible-energy passes.
+ * particles_per_wave = 16, 32 or 64 (default 32): a wavefront takes that
+ * many consecutive particles and works through their concatenated pair
+ * rows 64 pairs at a time, one pair per lane, summing per particle across
+ * the lanes in FP64; 0: the lanes-per-particle mapping of crk_set_lanes'
+ * g_der (the compatible pass then keeps 32). Tuning only: results agree to
+ * rounding for every choice. */
+crk_status crk_set_deriv_mapping(crk_ctx *ctx, int32_t particles_per_wave);
 
 /* Lanes per particle of the four pair passes (volume, moments, velocity
  * gradient, derivatives): each particle's neighbour row is split over a

@@ -17,15 +17,15 @@ STATUS = {0: "CRK_OK", 1: "CRK_WARN_SINGULAR", 2: "CRK_WARN_NOT_CONVERGED",
 
 # every symbol include/crk.h declares
 EXPORTS = ("crk_params_default", "crk_create", "crk_destroy", "crk_last_error", "crk_build_cells",
-           "crk_build_cells_batch",
+           "crk_build_cells_batch", "crk_build_leaves",
            "crk_update_support", "crk_permute", "crk_moments", "crk_corrections",
-           "crk_derivatives", "crk_hsolve", "crk_export_neighbors", "crk_set_lanes", "crk_set_walk", "crk_set_hsolve",
+           "crk_derivatives", "crk_hsolve", "crk_export_neighbors", "crk_set_lanes", "crk_set_deriv_mapping", "crk_set_walk", "crk_set_hsolve",
            "crk_timing_enable", "crk_timing_reset", "crk_timing_read", "crk_adaptive_rows",
            "crk_hnet_features", "crk_hnet_forward", "crk_hnet_train_step",
            "crk_hnet_train_step_noalloc", "crk_hnet_seed",
            "crk_hnet_targets", "crk_step", "crk_graph_capture", "crk_graph_replay",
            "crk_graph_destroy", "crk_set_timestep", "crk_timestep", "crk_compatible_energy",
-           "crk_verlet_step", "crk_time_levels", "crk_workspace_bytes",
+           "crk_verlet_step", "crk_time_levels", "crk_workspace_bytes", "crk_workspace_estimate",
            "crk_version")
 
 # members of crk_step_io, in order
@@ -104,6 +104,7 @@ def lib():
             "crk_last_error": ([p], C.c_char_p),
             "crk_build_cells": ([p, i64, p, p, p, p, p, d, p, p, p], i32),
             "crk_build_cells_batch": ([p, i32, p, i64, p, p, p, p, p, d, p, p, p], i32),
+            "crk_build_leaves": ([p, i32, p, i64, p, p, p, p, p, i32, i32, p, p, p, p, i64], i32),
             "crk_update_support": ([p, p, p], i32),
             "crk_permute": ([p, p, p, i32, i32], i32),
             "crk_moments": ([p, p] + [p] * 8, i32),
@@ -115,9 +116,11 @@ def lib():
             "crk_verlet_step": ([p, i32, p, i64, p, p, d, d, i32, i32, p], i32),
             "crk_time_levels": ([p, p, p, p, d, d, i32, p, p, p, p], i32),
             "crk_workspace_bytes": ([p, p], i32),
+            "crk_workspace_estimate": ([p, i64, i32, d, i32, i32, p], i32),
             "crk_hsolve": ([p, d, d, i32, p, p, p], i32),
             "crk_export_neighbors": ([p, i32, p, p, i64, p], i32),
             "crk_set_lanes": ([p, i32, i32, i32, i32], i32),
+            "crk_set_deriv_mapping": ([p, i32], i32),
             "crk_set_walk": ([p, i32, i32, i32], i32),
             "crk_set_hsolve": ([p, i32, i32, i32, d], i32),
             "crk_timing_enable": ([p, i32], i32),
@@ -199,6 +202,21 @@ def _arr(t, name: str, ncomp: int, n: int, dtype=torch.float64, optional: bool =
 
 def _on_device(t) -> bool:
     return t.is_cuda
+
+
+WS_STEP, WS_HSOLVE, WS_HNET, WS_COMPAT, WS_VERLET, WS_GRAPH, WS_TIMESTEP, WS_LEAVES = \
+    0, 1, 2, 4, 8, 16, 32, 64
+
+
+def workspace_estimate(n: int, pairs_per_particle: float, precision: int, uses: int = 0,
+                       nboxes: int = 1, ctx_handle=None) -> int:
+    """crk_workspace_estimate: bytes, before any call (host only, no GPU needed)."""
+    b = C.c_int64()
+    st = lib().crk_workspace_estimate(ctx_handle, int(n), int(nboxes), C.c_double(pairs_per_particle),
+                                      int(precision), int(uses), C.byref(b))
+    if st != 0:
+        raise CrkError(st, "crk_workspace_estimate: bad argument")
+    return b.value
 
 
 class Context:
@@ -295,6 +313,30 @@ class Context:
         self.n, self.n_pairs, self.n_cells, self.perm = n, npairs.value, ncell.value, perm
         return perm, npairs.value
 
+    def build_leaves(self, x, y, z, H, params: Params, nppl: int = 256, bucket: int = 32,
+                     box_offsets=None):
+        """RCB leaf tiling (crk_build_leaves): returns (perm, n_pairs,
+        leaf_offsets) with leaf_offsets a device int32 tensor [n_leaves+1]."""
+        import numpy as np
+        n = x.shape[0] if isinstance(x, torch.Tensor) and x.dim() == 1 else -1
+        for k, t in (("x", x), ("y", y), ("z", z), ("H", H)):
+            _arr(t, k, 1, n)
+        off = np.ascontiguousarray([0, n] if box_offsets is None else box_offsets, dtype=np.int64)
+        if off.ndim != 1 or len(off) < 2:
+            raise ValueError("box_offsets: expected nboxes + 1 offsets")
+        perm = self._empty(n, dtype=torch.int32)
+        cap = n + len(off)
+        loff = self._empty(cap, dtype=torch.int32)
+        npairs = C.c_int64()
+        nl = C.c_int32()
+        st = lib().crk_build_leaves(self._h, len(off) - 1, off.ctypes.data_as(C.c_void_p), n,
+                                    _ptr(x), _ptr(y), _ptr(z), _ptr(H), C.byref(params),
+                                    int(nppl), int(bucket), _ptr(perm), C.byref(npairs),
+                                    C.byref(nl), _ptr(loff), cap)
+        self._check(st, "crk_build_leaves")
+        self.n, self.n_pairs, self.n_cells, self.perm = n, npairs.value, 0, perm
+        return perm, npairs.value, loff[:nl.value + 1]
+
     def update_support(self, H_sorted):
         _arr(H_sorted, "H_sorted", 1, self.n)
         npairs = C.c_int64()
@@ -386,6 +428,12 @@ class Context:
                                          _ptr(du))
         self._check(st, "crk_compatible_energy")
         return du
+
+    def workspace_estimate(self, n: int, pairs_per_particle: float, precision: int, uses: int = 0,
+                           nboxes: int = 1) -> int:
+        """Upper bound on the workspace bytes for calls on n particles
+        (crk_workspace_estimate with this context's tuning)."""
+        return workspace_estimate(n, pairs_per_particle, precision, uses, nboxes, self._h)
 
     def workspace_bytes(self) -> int:
         """Device bytes the context's workspace holds now."""
@@ -611,6 +659,12 @@ class Context:
 
     def set_walk(self, lanes: int = 0, cap: int = 0, level_shift: int = -1):
         self._check(lib().crk_set_walk(self._h, lanes, cap, level_shift), "crk_set_walk")
+
+    def set_deriv_mapping(self, particles_per_wave: int):
+        """Derivative/compatible passes: 16, 32 or 64 particles per wavefront
+        over their concatenated rows, or 0 for set_lanes' der lanes."""
+        self._check(lib().crk_set_deriv_mapping(self._h, int(particles_per_wave)),
+                    "crk_set_deriv_mapping")
 
     def set_lanes(self, vol: int = 0, mom: int = 0, grad: int = 0, der: int = 0):
         self._check(lib().crk_set_lanes(self._h, vol, mom, grad, der), "crk_set_lanes")

@@ -1,5 +1,8 @@
 // Context, errors, workspace and parameter defaults of the C ABI.
 #include <math.h>
+
+#include <algorithm>
+#include <cmath>
 #include <stdarg.h>
 #include <stdio.h>
 
@@ -214,7 +217,8 @@ static std::vector<crk::Buf *> ctx_buffers(crk_ctx *c) {
                        &c->hnet_part, &c->hnet_feat, &c->hs_list, &c->hs_state, &c->hs_pos,
                        &c->hs_iters, &c->hs_pool, &c->hs_rows, &c->hs_rcnt, &c->hs_R, &c->boff,
                        &c->sv, &c->sm, &c->su, &c->srho, &c->gstat, &c->gboff,
-                       &c->ecnt, &c->efill, &c->eoff, &c->etmp, &c->ts_vs, &c->ts_qr, &c->ce, &c->ced, &c->vstep};
+                       &c->ecnt, &c->efill, &c->eoff, &c->etmp, &c->rq, &c->rsk, &c->rla, &c->rlb, &c->rside,
+                       &c->rpnode, &c->rscan, &c->rnode, &c->rtab, &c->rbox, &c->rpoff, &c->rpart, &c->ts_vs, &c->ts_qr, &c->ce, &c->ced, &c->vstep};
 }
 
 void crk_destroy(crk_ctx *c) {
@@ -235,6 +239,78 @@ void crk_destroy(crk_ctx *c) {
 }
 
 const char *crk_last_error(const crk_ctx *c) { return c ? c->err.c_str() : "null context"; }
+
+// Bytes one workspace buffer reaches for a request of b bytes (ensure():
+// an eighth of headroom, 256 bytes at least).
+static double held(double b) {
+    if (b <= 0.0) b = 256.0;
+    return b + std::floor(b / 8.0);
+}
+
+// Block-sum scratch of scan_exclusive_i64 for up to m values.
+static double scan_bytes(double m) {
+    const double tile = 2048.0;
+    double need = 0.0;
+    for (double k = std::ceil(m / tile); k > 1.0; k = std::ceil(k / tile)) need += k;
+    return (need + 16.0) * 8.0;
+}
+
+crk_status crk_workspace_estimate(const crk_ctx *c, int64_t n, int32_t nboxes,
+                                  double pairs_per_particle, int32_t precision, int32_t uses,
+                                  int64_t *bytes) {
+    if (!bytes || n < 1 || nboxes < 1 || !(pairs_per_particle >= 0.0) ||
+        (precision != CRK_FP64 && precision != CRK_MIXED && precision != CRK_MIXED_ADAPT))
+        return CRK_ERR_INVALID_ARG;
+    const double N = (double)n, P = N * pairs_per_particle;
+    const int walk_cap = c ? c->walk_cap : 192, hs_cap = c ? c->hs_cap : 320;
+    double t = 0.0;
+    // build (crk_build_cells, any use): checks, sort, tables, lists
+    const double nblk = std::min(std::ceil(N / 256.0), 1024.0);
+    t += held(nblk * 24.0 + 64.0) + held(256.0) + held((nboxes + 1) * 8.0);
+    t += 2 * held(4.0 * N) + 2 * held(4.0 * N) + held(std::ceil(N / 2048.0) * 256.0 * 8.0);
+    t += held(std::max(scan_bytes(N + 1.0), 24.0 * N));   // scans; crk_update_support's copies
+    t += held(32.0 * N);
+    // cell tables of every level: at most the finest level the size cap allows
+    int bits = 0;
+    while (bits < 8 && (double)nboxes * std::pow(8.0, bits + 1) * 8.0 / 7.0 <= (double)(1 << 26)) bits++;
+    const double ntab = (std::pow(8.0, bits + 1) - 1.0) / 7.0 * nboxes;
+    t += 2 * held(4.0 * ntab);
+    t += held(4.0 * N) + 2 * held(8.0 * (N + 1.0)) + 2 * held(4.0 * N);   // counts, offsets
+    t += held(4.0 * N * walk_cap);                                        // walk rows
+    t += held(4.0 * P) + 2 * held(4.0 * 0.5 * P) + 2 * held(4.0 * N);    // N_g rows, extras (E <= P/2)
+    // passes
+    const bool f64 = precision == CRK_FP64, adapt = precision == CRK_MIXED_ADAPT;
+    t += held((precision == CRK_MIXED ? 4.0 : 8.0) * N);                  // volumes
+    t += held(16.0 * N * (f64 ? 2 : 1)) + held(144.0 * N * (f64 ? 2 : 1));   // records
+    if (adapt) t += 2 * held(32.0 * N) + 3 * held(4.0 * N) + 2 * held(8.0 * (N + 1.0));
+    if (uses & CRK_WS_TIMESTEP) t += 2 * held(8.0 * N);
+    if (uses & CRK_WS_COMPAT) t += held(32.0 * N * (f64 ? 2 : 1)) + (adapt ? held(64.0 * N) : 0.0);
+    if (uses & CRK_WS_HSOLVE) {
+        t += held(8.0 * N) + 2 * held(4.0 * N) + held(8.0 * (N + 1.0)) + held(8.0 * N * hs_cap) +
+             held(4.0 * N) + held(8.0 * N);
+        // rows of the particles whose candidates pass the cap: at most 8 GiB
+        const double pcap = std::max(4096.0, 8.0 * hs_cap);
+        t += held(std::min(N * pcap * 8.0, (double)(8LL << 30)));
+    }
+    if (uses & CRK_WS_HNET) t += held(36.0 * N) + held(std::ceil(N / 16.0) * 4802.0 * 4.0 + 64.0);
+    if (uses & CRK_WS_VERLET) t += held((16.0 + 70.0) * 8.0 * N + 4.0 * N);
+    if (uses & CRK_WS_GRAPH) {
+        t += held(24.0 * N) + 3 * held(8.0 * N) + held((nboxes + 1) * 8.0) + held(64.0);
+        // list capacities of the recorded step: 1.25 P + 1024 (default headroom)
+        t += held(4.0 * (1.25 * P + 1024.0)) - held(4.0 * P);
+        t += 2 * (held(4.0 * (0.625 * P + 1024.0)) - held(2.0 * P));
+    }
+    if (uses & CRK_WS_LEAVES) {
+        // keys and lists, sides, node and leaf tables, boxes, leaf partners,
+        // capped extras rows
+        const double nl = std::ceil(N / 128.0) + nboxes;
+        t += 4 * held(12.0 * N) + held(N) + held(4.0 * N) + held(8.0 * (N + 1.0));
+        t += held(9.0 * N) + held(16.0 * (N / 8.0 + 2.0 * nl + nboxes + 1.0)) + held(64.0 * N / 8.0 + 64.0 * nl);
+        t += held(8.0 * (nl + 1.0)) + held(4.0 * nl * std::min(nl, 4096.0)) + held(4.0 * N * 64.0);
+    }
+    *bytes = (int64_t)std::ceil(t);
+    return CRK_OK;
+}
 
 crk_status crk_workspace_bytes(crk_ctx *c, int64_t *bytes) {
     if (!c || !bytes) return CRK_ERR_INVALID_ARG;

@@ -629,6 +629,37 @@ inline unsigned nblocks(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock
 
 }  // namespace
 
+// the reduced input checks of k_validate / k_validate_final, on the host
+static crk_status read_checks(crk_ctx *c, const double *res, const int *flags, double *hmax,
+                              double *hmin) {
+    double *pin = (double *)c->pinned.p;
+    CRK_HIP(c, hipMemcpyAsync(pin, res, 3 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    CRK_HIP(c, hipMemcpyAsync(pin + 3, flags, 3 * sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    CRK_HIP(c, hipStreamSynchronize(c->stream));
+    *hmax = pin[0];
+    *hmin = pin[1];
+    int *hf = (int *)(pin + 3);
+    if (hf[0]) return set_err(c, CRK_ERR_NONFINITE, "non-finite position or H");
+    if (hf[1]) return set_err(c, CRK_ERR_INVALID_ARG, "position outside [0, L)");
+    if (hf[2] || !(*hmin > 0.0)) return set_err(c, CRK_ERR_SUPPORT, "H must be positive");
+    return CRK_OK;
+}
+
+crk_status validate_inputs(crk_ctx *c, const double *x, const double *y, const double *z,
+                           const double *H, int64_t n, double L, double *hmax, double *hmin) {
+    int nblk = (int)std::min<int64_t>((n + kBlock - 1) / kBlock, 1024);
+    CRK_TRY(ensure(c, c->red, (size_t)nblk * 3 * sizeof(double) + 64));
+    double *part = (double *)c->red.p;
+    int *flags = (int *)(part + (size_t)nblk * 3);
+    CRK_TRY(ensure(c, c->misc, 256));
+    double *res = (double *)c->misc.p;
+    k_fill_i32<<<1, kBlock, 0, c->stream>>>(flags, 3, 0);
+    k_validate<<<nblk, kBlock, 0, c->stream>>>(x, y, z, H, n, L, part, flags);
+    k_validate_final<<<1, 1024, 0, c->stream>>>(part, nblk, res);
+    CRK_HIP(c, hipGetLastError());
+    return read_checks(c, res, flags, hmax, hmin);
+}
+
 Levels levels(const crk_ctx *c) {
     Levels v;
     v.L = c->L;
@@ -812,6 +843,7 @@ crk_status crk_build_cells_batch(crk_ctx *c, int32_t nboxes, const int64_t *box_
         return set_err(c, CRK_ERR_STATE, "graph mode needs the geometry of the last build");
     if (!gm) {
         c->built = 0;
+        c->leaf_mode = 0;
         c->nc = 0;
         c->n = n;
         c->L = p->L;
@@ -835,15 +867,8 @@ crk_status crk_build_cells_batch(crk_ctx *c, int32_t nboxes, const int64_t *box_
         CRK_HIP(c, hipGetLastError());
         return build_sorted(c, x, y, z, H, perm, true, n_pairs, n_cells);
     }
-    double *pin = (double *)c->pinned.p;
-    CRK_HIP(c, hipMemcpyAsync(pin, res, 3 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
-    CRK_HIP(c, hipMemcpyAsync(pin + 3, flags, 3 * sizeof(int), hipMemcpyDeviceToHost, c->stream));
-    CRK_HIP(c, hipStreamSynchronize(c->stream));
-    double hmax = pin[0], hmin = pin[1];
-    int *hf = (int *)(pin + 3);
-    if (hf[0]) return set_err(c, CRK_ERR_NONFINITE, "non-finite position or H");
-    if (hf[1]) return set_err(c, CRK_ERR_INVALID_ARG, "position outside [0, L)");
-    if (hf[2] || !(hmin > 0.0)) return set_err(c, CRK_ERR_SUPPORT, "H must be positive");
+    double hmax = 0.0, hmin = 0.0;
+    CRK_TRY(read_checks(c, res, flags, &hmax, &hmin));
     if (!(hmax < 0.5 * p->L)) return set_err(c, CRK_ERR_SUPPORT, "max H %g >= L/2", hmax);
     // 2. Morton cell hierarchy: finest side near half the smallest support
     //    (or the requested side), at most 256 cells a side and at most about
@@ -914,7 +939,7 @@ crk_status crk_update_support(crk_ctx *c, const double *H_sorted, int64_t *n_pai
 crk_status crk_permute(crk_ctx *c, const double *src, double *dst, int32_t ncomp, int32_t to_sorted) {
     if (!c) return CRK_ERR_INVALID_ARG;
     if (!src || !dst || ncomp < 1) return set_err(c, CRK_ERR_INVALID_ARG, "crk_permute: bad argument");
-    if (c->nc == 0) return set_err(c, CRK_ERR_STATE, "crk_build_cells has not run");
+    if (c->nc == 0 && !c->leaf_mode) return set_err(c, CRK_ERR_STATE, "crk_build_cells has not run");
     CRK_HIP(c, hipSetDevice(c->device));
     k_permute<<<nblocks(c->n), kBlock, 0, c->stream>>>((const int32_t *)c->perm.p, src, dst, c->n,
                                                         ncomp, to_sorted);

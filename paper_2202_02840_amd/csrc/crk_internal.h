@@ -16,7 +16,7 @@
 //                           (eoff [n+1] int64 holds the same row offsets)
 //   recV   T       [n]      volumes in the pass precision
 //   rec6   T4      [n]      {vx, vy, vz, V}            (velocity-gradient pass)
-//   rec7   T4      [9][n]   packed per-particle state  (derivative pass)
+//   rec7   T4      [8][n]   packed per-particle records (derivative pass)
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -85,6 +85,11 @@ struct crk_ctx {
     crk::Buf gstat;                                       // device status of a graph step
     crk::Buf gboff;                                       // box offsets the graph was recorded with
     crk::Buf ecnt, efill, eoff, etmp;                     // extras rows: counts, slots, offsets, unordered rows
+    // RCB leaf tiling (crk_build_leaves): keys, the three sorted lists (two
+    // copies), sides, nodes, tables, boxes, interaction lists
+    crk::Buf rq, rsk, rla, rlb, rside, rpnode, rscan, rnode, rtab, rbox, rpoff, rpart;
+    int leaf_mode = 0;                                    // lists come from crk_build_leaves
+    int64_t nleaves = 0, nleaf_pairs = 0;
 
     // graph mode (crk_graph_capture): the build keeps the geometry of the
     // last eager build, lists are bounded by fixed capacities, and no call
@@ -107,6 +112,9 @@ struct crk_ctx {
 
     // per-pass tuning: lanes per particle (1..64)
     int G_vol = 4, G_mom = 1, G_grad = 4, G_der = 8;
+    // derivative and compatible passes: particles per wavefront of the
+    // balanced lane-group mapping (4, 8, 16 or 32); 0 = G_der lanes per particle
+    int P_der = 8;
     // neighbour walk: lanes per particle and scratch slots per row
     int G_walk = 8, walk_cap = 192;
     // walked level: the first whose cell side is at least 2^(walk_shift-1) H
@@ -125,6 +133,11 @@ crk_status set_err(crk_ctx *c, crk_status s, const char *fmt, ...);
 crk_status hip_err(crk_ctx *c, hipError_t e, const char *what);
 crk_status ensure(crk_ctx *c, Buf &b, size_t bytes);
 void graph_release(crk_ctx *c);
+// input checks of a build: non-finite values (CRK_ERR_NONFINITE), positions
+// outside [0, L) (CRK_ERR_INVALID_ARG), H <= 0 (CRK_ERR_SUPPORT); *hmax and
+// *hmin receive the extreme supports (synchronises the stream)
+crk_status validate_inputs(crk_ctx *c, const double *x, const double *y, const double *z,
+                           const double *H, int64_t n, double L, double *hmax, double *hmin);
 // steps 2-4 of crk_build_cells_batch for the geometry held in the context
 crk_status build_sorted(crk_ctx *c, const double *x, const double *y, const double *z,
                         const double *H, int32_t *perm, bool stand_ins, int64_t *n_pairs,

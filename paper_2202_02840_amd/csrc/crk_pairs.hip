@@ -425,18 +425,121 @@ __global__ __launch_bounds__(kBlock) void k_gradv(const double4 *__restrict__ po
 }
 
 // ------------------------------------------------------------- S7 derivatives
-// Packed per-particle state, nine 4-vectors:
-//   0 {vx, vy, vz, V}   1 {rho, P, cs, A}   2 {Bx, By, Bz, 1/H}   3 {dAx, dAy, dAz, H/nh}
-//   4 {gB0..gB3}        5 {gB4..gB7}        6 {gB8, gv0, gv1, gv2}
-//   7 {gv3..gv6}        8 {gv7, gv8, fp64-row flag, 0}
-constexpr int kRec7 = 9;
+// The RK gradient template of eq. (gRK) for the ordered pair (i, j), with
+// i's coefficients and c = 1 + B.d,
+//   grad W^R_ij = w (gradA c + A ((gradB)^T d + B)) + A c gf d,
+// is regrouped per particle so that a pair needs no per-particle prefactor.
+// With the kernel's radial factors w = kW H^-3 pw(q) and gf = kG H^-5 pg(q),
+//   grad W^R_ij = pw (U + M d) + Ag c pg d,
+//   U_g = kW H^-3 (dA/dx_g + A B_g),  M_ga = kW H^-3 (dA/dx_g B_a + A dB_a/dx_g),
+//   Ag = A kG H^-5.
+// The limiter of eqs. (phi)-(phiad) and the projected velocity of eq.
+// (hatvi) need the velocity gradient only through s = d^T (grad v) d (the
+// projection (v_i - v_j - phi/2 (grad v_i + grad v_j) d + adot d).d is
+// (v_i - v_j).d - phi/2 (s_i + s_j) + adot r^2), so only the symmetric part
+// of grad v is kept. Same quantities as the term-by-term form, grouped
+// differently.
+//
+// Packed per-particle record of the derivative and compatible passes, eight
+// 4-vectors of data and one of padding (a 144-byte stride for FP32: with
+// a power-of-two stride the partners' records of one step fall on few
+// memory channels, which measured 1.5x slower):
+//   0 {vx, vy, vz, Vs}      Vs = V a / sqrt(2), so Vs_i Vs_j = (a^2/2) V_i V_j
+//   1 {P, rho, Clcs, ih}    Clcs = C_l c_s; ih = 1/H, negated for an FP64 row
+//   2 {hA, he, Ag, B0}      hA = hh / a, he = hh^2 eps^2 (hh = H / n_h, eq. mu)
+//   3 {B1, B2, U0, U1}
+//   4 {U2, M00, M01, M02}   M row g (derivative direction), column a
+//   5 {M10, M11, M12, M20}
+//   6 {M21, M22, S0, S1}    S = (g00, g11, g22, g01 + g10, g02 + g20, g12 + g21)
+//   7 {S2, S3, S4, S5}      of grad v (g_ab = dv_a/dx_b)
+constexpr int kRec = 9;   // 4-vectors per record (the last one padding)
 
 struct DerivPrm {
-    double gamma, Cl, Cq, eps2, inv_nh, inv_a, half_a2, half_inv_a2, adot, eta_c, inv_eta_f;
+    double gamma, Cl, Cq, eps2, inv_nh, inv_a, adot, eta_c, inv_eta_f, vs_scale, inv_a5;
 };
 
+template <typename T>
+struct Rec {
+    T v[3], Vs, P, rho, Clcs, ih, hA, he, Ag, B[3], U[3], M[9], S[6];
+};
+
+// the record of one particle from FP64 state (P, rho, c_s given)
+__device__ __forceinline__ void make_rec(double H, double vx, double vy, double vz, double Vi, double P,
+                                         double rho, double cs, double A, const double B3[3],
+                                         const double gA3[3], const double gB9[9], const double gv9[9],
+                                         const DerivPrm &p, bool fp64_row, Rec<double> &r) {
+    const double ih = 1.0 / H;
+    const double ih2 = ih * ih;
+    const double cw = kW * ih2 * ih;
+    const double hh = H * p.inv_nh;
+    r.v[0] = vx;
+    r.v[1] = vy;
+    r.v[2] = vz;
+    r.Vs = Vi * p.vs_scale;
+    r.P = P;
+    r.rho = rho;
+    r.Clcs = p.Cl * cs;
+    r.ih = fp64_row ? -ih : ih;
+    r.hA = hh * p.inv_a;
+    r.he = hh * hh * p.eps2;
+    r.Ag = A * kG * ih2 * ih2 * ih;
+#pragma unroll
+    for (int g = 0; g < 3; g++) {
+        r.B[g] = B3[g];
+        r.U[g] = cw * (gA3[g] + A * B3[g]);
+#pragma unroll
+        for (int a = 0; a < 3; a++) r.M[g * 3 + a] = cw * (gA3[g] * B3[a] + A * gB9[a * 3 + g]);
+    }
+    r.S[0] = gv9[0];
+    r.S[1] = gv9[4];
+    r.S[2] = gv9[8];
+    r.S[3] = gv9[1] + gv9[3];
+    r.S[4] = gv9[2] + gv9[6];
+    r.S[5] = gv9[5] + gv9[7];
+}
+
 template <typename V4, typename T>
-__global__ __launch_bounds__(kBlock) void k_pack7(int64_t n, const double4 *__restrict__ posH,
+__device__ __forceinline__ void store_rec(V4 *o, const Rec<double> &r) {
+    o[0] = V4{(T)r.v[0], (T)r.v[1], (T)r.v[2], (T)r.Vs};
+    o[1] = V4{(T)r.P, (T)r.rho, (T)r.Clcs, (T)r.ih};
+    o[2] = V4{(T)r.hA, (T)r.he, (T)r.Ag, (T)r.B[0]};
+    o[3] = V4{(T)r.B[1], (T)r.B[2], (T)r.U[0], (T)r.U[1]};
+    o[4] = V4{(T)r.U[2], (T)r.M[0], (T)r.M[1], (T)r.M[2]};
+    o[5] = V4{(T)r.M[3], (T)r.M[4], (T)r.M[5], (T)r.M[6]};
+    o[6] = V4{(T)r.M[7], (T)r.M[8], (T)r.S[0], (T)r.S[1]};
+    o[7] = V4{(T)r.S[2], (T)r.S[3], (T)r.S[4], (T)r.S[5]};
+    o[8] = V4{(T)0, (T)0, (T)0, (T)0};
+}
+
+template <typename V4, typename T>
+__device__ __forceinline__ void load_rec(const V4 *__restrict__ rec, int64_t j, Rec<T> &s) {
+    const V4 *o = rec + j * kRec;
+    const V4 r0 = o[0], r1 = o[1], r2 = o[2], r3 = o[3], r4 = o[4], r5 = o[5], r6 = o[6], r7 = o[7];
+    s.v[0] = r0.x; s.v[1] = r0.y; s.v[2] = r0.z; s.Vs = r0.w;
+    s.P = r1.x; s.rho = r1.y; s.Clcs = r1.z; s.ih = r1.w;
+    s.hA = r2.x; s.he = r2.y; s.Ag = r2.z; s.B[0] = r2.w;
+    s.B[1] = r3.x; s.B[2] = r3.y; s.U[0] = r3.z; s.U[1] = r3.w;
+    s.U[2] = r4.x; s.M[0] = r4.y; s.M[1] = r4.z; s.M[2] = r4.w;
+    s.M[3] = r5.x; s.M[4] = r5.y; s.M[5] = r5.z; s.M[6] = r5.w;
+    s.M[7] = r6.x; s.M[8] = r6.y; s.S[0] = r6.z; s.S[1] = r6.w;
+    s.S[2] = r7.x; s.S[3] = r7.y; s.S[4] = r7.z; s.S[5] = r7.w;
+}
+
+// P = (gamma - 1) rho u (eq. EOS) with rho = m / V unless given, and
+// c_s = sqrt(gamma P / rho); flags a non-finite or non-positive state
+__device__ __forceinline__ void gas_state(int64_t i, const double *v, const double *m, const double *u,
+                                          const double *rho, const double *V, int64_t n, double gamma,
+                                          double &r, double &P, double &cs, int *bad) {
+    r = rho ? rho[i] : m[i] / V[i];
+    P = (gamma - 1.0) * r * u[i];
+    cs = sqrt(gamma * P / r);
+    if (!isfinite(r) || !isfinite(P) || !isfinite(cs) || !isfinite(m[i]) || !isfinite(v[i]) ||
+        !isfinite(v[n + i]) || !isfinite(v[2 * n + i]) || !(r > 0.0))
+        atomicOr(bad, 1);
+}
+
+template <typename V4, typename T>
+__global__ __launch_bounds__(kBlock) void k_pack8(int64_t n, const double4 *__restrict__ posH,
                                                   const double *v, const double *m, const double *u,
                                                   const double *rho, const double *V, const double *A,
                                                   const double *B, const double *gA, const double *gB,
@@ -444,165 +547,307 @@ __global__ __launch_bounds__(kBlock) void k_pack7(int64_t n, const double4 *__re
                                                   V4 *rec, double4 *aux, int *bad) {
     int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i >= n) return;
-    double Vi = V[i];
-    double r = rho ? rho[i] : m[i] / Vi;
-    double P = (p.gamma - 1.0) * r * u[i];
-    double cs = sqrt(p.gamma * P / r);
-    if (!isfinite(r) || !isfinite(P) || !isfinite(cs) || !isfinite(m[i]) || !isfinite(v[i]) ||
-        !isfinite(v[n + i]) || !isfinite(v[2 * n + i]) || !(r > 0.0))
-        atomicOr(bad, 1);
-    double H = posH[i].w;
-    V4 *o = rec + i * kRec7;
-    o[0] = V4{(T)v[i], (T)v[n + i], (T)v[2 * n + i], (T)Vi};
-    o[1] = V4{(T)r, (T)P, (T)cs, (T)A[i]};
-    o[2] = V4{(T)B[i], (T)B[n + i], (T)B[2 * n + i], (T)(1.0 / H)};
-    o[3] = V4{(T)gA[i], (T)gA[n + i], (T)gA[2 * n + i], (T)(H * p.inv_nh)};
-    o[4] = V4{(T)gB[i], (T)gB[n + i], (T)gB[2 * n + i], (T)gB[3 * n + i]};
-    o[5] = V4{(T)gB[4 * n + i], (T)gB[5 * n + i], (T)gB[6 * n + i], (T)gB[7 * n + i]};
-    o[6] = V4{(T)gB[8 * n + i], (T)gv[i], (T)gv[n + i], (T)gv[2 * n + i]};
-    o[7] = V4{(T)gv[3 * n + i], (T)gv[4 * n + i], (T)gv[5 * n + i], (T)gv[6 * n + i]};
-    o[8] = V4{(T)gv[7 * n + i], (T)gv[8 * n + i], (T)(flag ? flag[i] : 0), (T)0};
-    if (aux) aux[i] = make_double4(r, P, cs, H * p.inv_nh);
-}
-
-template <typename T>
-struct State {
-    T v[3], V, rho, P, cs, invH, hh, fl;
-    Coef<T> k;
-    T gv[9];
-};
-
-// FP64 state from the boundary arrays (rows of the adaptive mode's FP64 launch)
-struct Soa {
-    const double *v, *V, *A, *B, *gA, *gB, *gv;
-    const double4 *aux;
-};
-
-__device__ __forceinline__ void load_state_soa(const Soa &a, const double4 *__restrict__ posH, int64_t n,
-                                               int64_t j, State<double> &s) {
+    double r, P, cs;
+    gas_state(i, v, m, u, rho, V, n, p.gamma, r, P, cs, bad);
+    double B3[3], gA3[3], gB9[9], gv9[9];
 #pragma unroll
     for (int x = 0; x < 3; x++) {
-        s.v[x] = a.v[x * n + j];
-        s.k.B[x] = a.B[x * n + j];
-        s.k.gA[x] = a.gA[x * n + j];
+        B3[x] = B[x * n + i];
+        gA3[x] = gA[x * n + i];
     }
 #pragma unroll
     for (int q = 0; q < 9; q++) {
-        s.k.gB[q] = a.gB[q * n + j];
-        s.gv[q] = a.gv[q * n + j];
+        gB9[q] = gB[q * n + i];
+        gv9[q] = gv[q * n + i];
     }
-    s.V = a.V[j];
-    s.k.A = a.A[j];
-    double4 x = a.aux[j];
-    s.rho = x.x;
-    s.P = x.y;
-    s.cs = x.z;
-    s.hh = x.w;
-    s.invH = 1.0 / posH[j].w;
-    s.fl = 0.0;
+    Rec<double> rc;
+    make_rec(posH[i].w, v[i], v[n + i], v[2 * n + i], V[i], P, r, cs, A[i], B3, gA3, gB9, gv9, p,
+             flag && flag[i] != 0, rc);
+    store_rec<V4, T>(rec + i * kRec, rc);
+    if (aux) aux[i] = make_double4(r, P, cs, 0.0);
 }
 
-template <typename V4, typename T>
-__device__ __forceinline__ void load_state(const V4 *__restrict__ rec, int64_t j, State<T> &s) {
-    const V4 *o = rec + j * kRec7;
-    V4 r0 = o[0], r1 = o[1], r2 = o[2], r3 = o[3], r4 = o[4], r5 = o[5], r6 = o[6], r7 = o[7],
-       r8 = o[8];
-    s.v[0] = r0.x; s.v[1] = r0.y; s.v[2] = r0.z; s.V = r0.w;
-    s.rho = r1.x; s.P = r1.y; s.cs = r1.z; s.k.A = r1.w;
-    s.k.B[0] = r2.x; s.k.B[1] = r2.y; s.k.B[2] = r2.z; s.invH = r2.w;
-    s.k.gA[0] = r3.x; s.k.gA[1] = r3.y; s.k.gA[2] = r3.z; s.hh = r3.w;
-    s.k.gB[0] = r4.x; s.k.gB[1] = r4.y; s.k.gB[2] = r4.z; s.k.gB[3] = r4.w;
-    s.k.gB[4] = r5.x; s.k.gB[5] = r5.y; s.k.gB[6] = r5.z; s.k.gB[7] = r5.w;
-    s.k.gB[8] = r6.x; s.gv[0] = r6.y; s.gv[1] = r6.z; s.gv[2] = r6.w;
-    s.gv[3] = r7.x; s.gv[4] = r7.y; s.gv[5] = r7.z; s.gv[6] = r7.w;
-    s.gv[7] = r8.x; s.gv[8] = r8.y; s.fl = r8.z;
-}
-
-// One ordered pair of eqs. (mom) and (eng) with P -> P + Q: adds
-// (a^2/2) V_i V_j (P_i+Q_i+P_j+Q_j) D to F and (1/(2a^2)) V_i V_j (P_j+Q_j)
-// (xdot_j - xdot_i).D to E, D = grad W^R_ji - grad W^R_ij.
-template <typename T>
-struct PairConst {
-    T Cl, Cq, eps2, inv_a, adot, eta_c, inv_eta_f, half_a2, half_inv_a2;
+// FP64 state of the adaptive mode's FP64 rows from the boundary arrays
+struct Soa {
+    const double *v, *V, *A, *B, *gA, *gB, *gv;
+    const double4 *aux;   // {rho, P, c_s, -}
 };
 
-// With TS also the pair's time-step terms (Sec. 3.1): vs = the closing speed
-// max(-w, 0), w = (xdot_ij + (adot/a) x_ij).x_ij / r, and qr = Q_i / rho_i.
-template <typename T, bool TS = false>
-__device__ __forceinline__ void deriv_pair(const State<T> &si, const State<T> &sj, const T d[3],
-                                           const PairConst<T> &pc, T cwi, T cgi, T F[3], T &E,
-                                           T &vs, T &qr) {
-    T r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
-    T r = Mth<T>::sqrt(r2);
-    if constexpr (TS) {
-        const T w = ((si.v[0] - sj.v[0]) * d[0] + (si.v[1] - sj.v[1]) * d[1] +
-                     (si.v[2] - sj.v[2]) * d[2] + pc.adot * r2) * pc.inv_a;
-        vs = w < (T)0 ? -w * Mth<T>::rcp(r) : (T)0;
-        qr = (T)0;
-    }
-    T qi = r * si.invH, qj = r * sj.invH;
-    T cwj = (T)kW * sj.invH * sj.invH * sj.invH;
-    T cgj = (T)kG * sj.invH * sj.invH * sj.invH * sj.invH * sj.invH;
-    T wi, gfi, wj, gfj;
-    kernel_wg(qi, cwi, cgi, wi, gfi);
-    kernel_wg(qj, cwj, cgj, wj, gfj);
-    // grad W^R_ij (i's coefficients, +d) and grad W^R_ji (j's, -d)
-    T Gij[3], Gji[3], md[3] = {-d[0], -d[1], -d[2]};
-    rk_grad(si.k, d, wi, gfi, Gij);
-    rk_grad(sj.k, md, wj, gfj, Gji);
-    T D[3] = {Gji[0] - Gij[0], Gji[1] - Gij[1], Gji[2] - Gij[2]};
-    // limiter, eqs. (phi)-(phiad)
-    T gvi[3], gvj[3];
+__device__ __forceinline__ void load_rec_soa(const Soa &s, const double4 *__restrict__ posH, int64_t n,
+                                             int64_t j, const DerivPrm &p, Rec<double> &r) {
+    double B3[3], gA3[3], gB9[9], gv9[9];
 #pragma unroll
     for (int x = 0; x < 3; x++) {
-        gvi[x] = si.gv[x * 3 + 0] * d[0] + si.gv[x * 3 + 1] * d[1] + si.gv[x * 3 + 2] * d[2];
-        gvj[x] = sj.gv[x * 3 + 0] * d[0] + sj.gv[x * 3 + 1] * d[1] + sj.gv[x * 3 + 2] * d[2];
+        B3[x] = s.B[x * n + j];
+        gA3[x] = s.gA[x * n + j];
     }
-    T s_i = d[0] * gvi[0] + d[1] * gvi[1] + d[2] * gvi[2];
-    T s_j = d[0] * gvj[0] + d[1] * gvj[1] + d[2] * gvj[2];
-    T prod = s_i * s_j;
+#pragma unroll
+    for (int q = 0; q < 9; q++) {
+        gB9[q] = s.gB[q * n + j];
+        gv9[q] = s.gv[q * n + j];
+    }
+    const double4 a = s.aux[j];
+    make_rec(posH[j].w, s.v[j], s.v[n + j], s.v[2 * n + j], s.V[j], a.y, a.x, a.z, s.A[j], B3, gA3,
+             gB9, gv9, p, false, r);
+}
+
+template <typename T>
+struct PairK {
+    T Cq, eta_c, inv_eta_f, adot, inv_a;
+};
+
+template <typename T>
+__device__ __forceinline__ PairK<T> pair_k(const DerivPrm &p) {
+    return PairK<T>{(T)p.Cq, (T)p.eta_c, (T)p.inv_eta_f, (T)p.adot, (T)p.inv_a};
+}
+
+// Wendland C4 radial factors with unit support, eq. (C4): s = max(1 - q, 0),
+// pw = s^6 (1 + 6q + 35q^2/3), pg = (1 + 5q) s^5
+template <typename T>
+__device__ __forceinline__ void kfac(T q, T &pw, T &pg) {
+    const T s = q < (T)1 ? (T)1 - q : (T)0;
+    const T s2 = s * s;
+    const T s5 = s2 * s2 * s;
+    pw = s5 * s * ((T)1 + q * ((T)6 + q * (T)(35.0 / 3.0)));
+    pg = ((T)1 + (T)5 * q) * s5;
+}
+
+// One ordered pair (i = a, j = b) of eqs. (mom) and (eng) with P -> P + Q:
+//   FD = Vs_j (P_i + Q_i + P_j + Q_j) D,  D = grad W^R_ji - grad W^R_ij,
+//   EP = Vs_j (P_j + Q_j) (v_j - v_i).D,
+// so that m_i dv_i/dt = Vs_i sum FD and m_i du_i/dt = Vs_i a^-5 sum EP.
+// With TS also the pair's time-step terms (Sec. 3.1): vs = the closing speed
+// max(-w, 0), w = (xdot_ij + (adot/a) x_ij).x_ij / r, and qr = Q_i / rho_i.
+template <typename T, bool TS>
+__device__ __forceinline__ void pair_deriv(const Rec<T> &a, const Rec<T> &b, const T d[3],
+                                           const PairK<T> &k, T FD[3], T &EP, T &vs, T &qr) {
+    const T xx = d[0] * d[0], yy = d[1] * d[1], zz = d[2] * d[2];
+    const T xy = d[0] * d[1], xz = d[0] * d[2], yz = d[1] * d[2];
+    const T r2 = (xx + yy) + zz;
+    const T r = Mth<T>::sqrt(r2);
+    const T qi = r * fabs(a.ih), qj = r * fabs(b.ih);
+    T pwi, pgi, pwj, pgj;
+    kfac(qi, pwi, pgi);
+    kfac(qj, pwj, pgj);
+    // grad W^R_ij = pwi (U_i + M_i d) + ki d, grad W^R_ji = pwj (U_j - M_j d) - kj d
+    const T ci = (T)1 + (a.B[0] * d[0] + a.B[1] * d[1] + a.B[2] * d[2]);
+    const T cj = (T)1 - (b.B[0] * d[0] + b.B[1] * d[1] + b.B[2] * d[2]);
+    const T kk = a.Ag * ci * pgi + b.Ag * cj * pgj;
+    T D[3];
+#pragma unroll
+    for (int g = 0; g < 3; g++) {
+        const T ei = a.U[g] + (a.M[g * 3 + 0] * d[0] + a.M[g * 3 + 1] * d[1] + a.M[g * 3 + 2] * d[2]);
+        const T ej = b.U[g] - (b.M[g * 3 + 0] * d[0] + b.M[g * 3 + 1] * d[1] + b.M[g * 3 + 2] * d[2]);
+        D[g] = (pwj * ej - pwi * ei) - kk * d[g];
+    }
+    // limiter, eqs. (phi)-(phiad), from s = d^T grad v d
+    const T si = a.S[0] * xx + a.S[1] * yy + a.S[2] * zz + a.S[3] * xy + a.S[4] * xz + a.S[5] * yz;
+    const T sj = b.S[0] * xx + b.S[1] * yy + b.S[2] * zz + b.S[3] * xy + b.S[4] * xz + b.S[5] * yz;
+    const T vij[3] = {a.v[0] - b.v[0], a.v[1] - b.v[1], a.v[2] - b.v[2]};
+    const T vd = vij[0] * d[0] + vij[1] * d[1] + vij[2] * d[2];
+    const T prod = si * sj;
+    const T ssum = si + sj;
     T phi = (T)0;
     if (prod > (T)0) {
-        T sum = s_i + s_j;
-        phi = (T)4 * prod * Mth<T>::rcp(sum * sum);
+        phi = (T)4 * prod * Mth<T>::rcp(ssum * ssum);
         phi = phi < (T)1 ? phi : (T)1;
-        T eta = qi < qj ? qi : qj;
-        if (eta < pc.eta_c) {
-            T x = (eta - pc.eta_c) * pc.inv_eta_f;
+        const T eta = qi < qj ? qi : qj;
+        if (eta < k.eta_c) {
+            const T x = (eta - k.eta_c) * k.inv_eta_f;
             phi *= Mth<T>::exp(-x * x);
         }
     }
-    // projected velocity difference, eq. (hatvi), and eq. (mu)
-    T hp = (T)0.5 * phi;
-    T ud = (T)0;
-#pragma unroll
-    for (int x = 0; x < 3; x++) ud += ((si.v[x] - sj.v[x]) - hp * (gvi[x] + gvj[x]) + pc.adot * d[x]) * d[x];
+    // projected velocity difference, eq. (hatvi), along d; eq. (mu), eq. (visc)
+    const T ud = (vd - (T)0.5 * phi * ssum) + k.adot * r2;
     T Qi = (T)0, Qj = (T)0;
-    if (ud < (T)0) {
-        T mui = si.hh * pc.inv_a * ud * Mth<T>::rcp(r2 + si.hh * si.hh * pc.eps2);
-        T muj = sj.hh * pc.inv_a * ud * Mth<T>::rcp(r2 + sj.hh * sj.hh * pc.eps2);
-        const T qi = -pc.Cl * si.cs * mui + pc.Cq * mui * mui;
-        Qi = si.rho * qi;
-        Qj = sj.rho * (-pc.Cl * sj.cs * muj + pc.Cq * muj * muj);
-        if constexpr (TS) qr = qi;
+    if constexpr (TS) {
+        const T w = (vd + k.adot * r2) * k.inv_a;
+        vs = w < (T)0 ? -w * Mth<T>::rcp(r) : (T)0;
+        qr = (T)0;
     }
-    T fm = pc.half_a2 * si.V * sj.V * (si.P + Qi + sj.P + Qj);
-    T fe = pc.half_inv_a2 * si.V * sj.V * (sj.P + Qj);
-    T xdd = ((sj.v[0] - si.v[0]) * D[0] + (sj.v[1] - si.v[1]) * D[1] + (sj.v[2] - si.v[2]) * D[2]) * pc.inv_a;
-    F[0] = fm * D[0];
-    F[1] = fm * D[1];
-    F[2] = fm * D[2];
-    E = fe * xdd;
+    if (ud < (T)0) {
+        const T mui = a.hA * ud * Mth<T>::rcp(r2 + a.he);
+        const T muj = b.hA * ud * Mth<T>::rcp(r2 + b.he);
+        const T qi_ = mui * (k.Cq * mui - a.Clcs);
+        Qi = a.rho * qi_;
+        Qj = b.rho * (muj * (k.Cq * muj - b.Clcs));
+        if constexpr (TS) qr = qi_;
+    }
+    const T pqj = b.P + Qj;
+    const T t = b.Vs * ((a.P + Qi) + pqj);
+    FD[0] = t * D[0];
+    FD[1] = t * D[1];
+    FD[2] = t * D[2];
+    EP = -(b.Vs * pqj) * (vij[0] * D[0] + vij[1] * D[1] + vij[2] * D[2]);
 }
 
 template <typename T>
-__device__ __forceinline__ PairConst<T> pair_const(const DerivPrm &p) {
-    return PairConst<T>{(T)p.Cl, (T)p.Cq, (T)p.eps2, (T)p.inv_a, (T)p.adot, (T)p.eta_c,
-                        (T)p.inv_eta_f, (T)p.half_a2, (T)p.half_inv_a2};
+__device__ __forceinline__ bool fp64_row(const Rec<T> &r) {
+    return r.ih < (T)0;
 }
 
-// Pairs with an FP64-row flag on either side (adaptive mode) are skipped
-// here and summed by k_deriv_fix.
+// Balanced lane groups. Wave w owns the P particles [i0, i0 + np) and
+// splits its 64 lanes among them in proportion to the lengths of their pair
+// rows N_s(i) (gather row, then extras row): particle p gets a contiguous
+// group of g_p >= 1 lanes, one plus its share of the other 64 - np lanes,
+// so every group needs about the same number of steps and the wave's lanes
+// stay busy whatever the rows' lengths. A lane keeps its particle's state
+// in registers, strides over the row by g_p and sums its pairs in FP64;
+// the groups' sums are reduced once at the end by a segmented scan across
+// the lanes, and each group's last lane holds its particle's totals.
+struct LaneGroup {
+    int64_t i;   // particle of this lane
+    int first;   // first entry of the row this lane takes
+    int g;       // lanes of the group (the stride)
+    int key;     // group id (particle offset in the wave)
+    bool last;   // last lane of the group
+};
+
+template <int P>
+__device__ __forceinline__ LaneGroup lane_group(int64_t i0, int np, int lane,
+                                                const int64_t *__restrict__ goff,
+                                                const int32_t *__restrict__ eb,
+                                                const int32_t *__restrict__ ee) {
+    static_assert(P >= 1 && P <= 32, "at most 32 particles per wave");
+    // row lengths and their inclusive prefix over the wave's particles
+    const int len = lane < np ? (int)(goff[i0 + lane + 1] - goff[i0 + lane]) + (ee[i0 + lane] - eb[i0 + lane]) : 0;
+    int cum = len;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int t = __shfl_up(cum, o, 64);
+        if (lane >= o) cum += t;
+    }
+    const int64_t S = __shfl(cum, 63, 64);
+    // group start of particle p: p + floor((64 - np) * (prefix before p) / S),
+    // increasing in p, 0 for p = 0
+    const int spare = 64 - np;
+    const int start = lane < np ? lane + (S > 0 ? (int)(((int64_t)spare * (cum - len)) / S) : 0) : 64;
+    // this lane's particle: the last p with start_p <= lane
+    int p = 0;
+#pragma unroll
+    for (int q = 1; q < P; q++) {
+        const int sq = __shfl(start, q, 64);
+        if (q < np && sq <= lane) p = q;
+    }
+    const int sp = __shfl(start, p, 64);
+    const int sn = __shfl(start, p + 1 < np ? p + 1 : 63, 64);
+    const int end = p + 1 < np ? sn : 64;
+    LaneGroup lg;
+    lg.i = i0 + p;
+    lg.first = lane - sp;
+    lg.g = end - sp;
+    lg.key = p;
+    lg.last = lane == end - 1;
+    return lg;
+}
+
+// sum of x over the lanes of each group, left in the group's last lane
+template <typename T, int K>
+__device__ __forceinline__ void group_scan(int lane, int key, T (&x)[K]) {
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int ko = __shfl_up(key, o, 64);
+        const bool take = lane >= o && ko == key;
+#pragma unroll
+        for (int k = 0; k < K; k++) {
+            const T y = __shfl_up(x[k], o, 64);
+            if (take) x[k] += y;
+        }
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void group_scan_max(int lane, int key, T &x) {
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int ko = __shfl_up(key, o, 64);
+        const T y = __shfl_up(x, o, 64);
+        if (lane >= o && ko == key) x = x > y ? x : y;
+    }
+}
+
+// first particle of this wave when every wave takes P particles
+__device__ __forceinline__ int64_t wave_first(int P) {
+    return (xcd_block(blockIdx.x, gridDim.x) * (kBlock / 64) + (threadIdx.x >> 6)) * (int64_t)P;
+}
+
+// Derivative pass, balanced lane groups (P particles per wave). Pairs with
+// an FP64-row flag on either side are left to k_deriv_fix.
+template <typename T, int P, bool TS>
+__global__ __launch_bounds__(kBlock) void k_deriv_bal(const double4 *__restrict__ posH,
+                                                      const int64_t *__restrict__ goff,
+                                                      const int32_t *__restrict__ gidx,
+                                                      const int32_t *__restrict__ eb,
+                                                      const int32_t *__restrict__ ee,
+                                                      const int32_t *__restrict__ eidx,
+                                                      const typename std::conditional<sizeof(T) == 4, float4, double4>::type *__restrict__ rec,
+                                                      const double *__restrict__ m, int64_t n, Box box,
+                                                      DerivPrm p, double *dpdt, double *dudt,
+                                                      double *ts_vs = nullptr, double *ts_qr = nullptr) {
+    const int64_t i0 = wave_first(P);
+    if (i0 >= n) return;   // whole waves leave together
+    const int lane = threadIdx.x & 63;
+    const int np = (int)(n - i0 < P ? n - i0 : P);
+    const LaneGroup lg = lane_group<P>(i0, np, lane, goff, eb, ee);
+    const int64_t i = lg.i;
+    double a[4] = {0.0, 0.0, 0.0, 0.0};
+    T vs = (T)0, qr = (T)0;
+    Rec<T> si;
+    load_rec(rec, i, si);
+    const double4 pi = posH[i];
+    const PairK<T> pk = pair_k<T>(p);
+    const int64_t gb = goff[i];
+    const int ngi = (int)(goff[i + 1] - gb);
+    const int ebi = eb[i];
+    const int tot = fp64_row(si) ? 0 : ngi + (ee[i] - ebi);
+    const int G = lg.g;
+    int kk = lg.first;
+    int32_t jn = kk < tot ? (kk < ngi ? gidx[gb + kk] : eidx[ebi + (kk - ngi)]) : 0;
+    for (; kk < tot; kk += G) {
+        const int32_t j = jn;
+        const int kn = kk + G;
+        if (kn < tot) jn = kn < ngi ? gidx[gb + kn] : eidx[ebi + (kn - ngi)];
+        // the partner's position and record are loaded together and the
+        // pair is evaluated before its FP64-row flag is looked at, so no
+        // load waits on another
+        const double4 pj = posH[j];
+        Rec<T> sj;
+        load_rec(rec, j, sj);
+        T d[3];
+        separation(pi, pj, box, d[0], d[1], d[2]);
+        T FD[3], EP, pvs, pqr;
+        pair_deriv<T, TS>(si, sj, d, pk, FD, EP, pvs, pqr);
+        if (!fp64_row(sj)) {
+            a[0] += (double)FD[0];
+            a[1] += (double)FD[1];
+            a[2] += (double)FD[2];
+            a[3] += (double)EP;
+            if constexpr (TS) {
+                vs = pvs > vs ? pvs : vs;
+                qr = pqr > qr ? pqr : qr;
+            }
+        }
+    }
+    group_scan<double, 4>(lane, lg.key, a);
+    if constexpr (TS) {
+        group_scan_max<T>(lane, lg.key, vs);
+        group_scan_max<T>(lane, lg.key, qr);
+    }
+    if (lg.last) {
+        const double f = (double)si.Vs / m[i];
+        dpdt[i] = a[0] * f;
+        dpdt[n + i] = a[1] * f;
+        dpdt[2 * n + i] = a[2] * f;
+        dudt[i] = a[3] * f * p.inv_a5;
+        if constexpr (TS) {
+            ts_vs[i] = (double)vs;
+            ts_qr[i] = (double)qr;
+        }
+    }
+}
+
+// Derivative pass, G lanes per particle striding over N_s(i) (the gather row,
+// then the extras row), compensated sums reduced across the group.
 template <typename T, int G, bool TS = false>
 __global__ __launch_bounds__(kBlock) void k_deriv(const double4 *__restrict__ posH,
                                                   const int64_t *__restrict__ goff,
@@ -617,39 +862,35 @@ __global__ __launch_bounds__(kBlock) void k_deriv(const double4 *__restrict__ po
     int l;
     int64_t i = group_index(G, l);
     Acc<T> a[4];
-    T vs = (T)0, qr = (T)0;   // time-step terms: maxima over the pairs (TS)
+    T vs = (T)0, qr = (T)0;
+    T Vsi = (T)0;
     if (i < n) {
-        double4 pi = posH[i];
-        State<T> si;
-        load_state(rec, i, si);
-        const PairConst<T> pc = pair_const<T>(p);
-        T cwi = (T)kW * si.invH * si.invH * si.invH;
-        T cgi = (T)kG * si.invH * si.invH * si.invH * si.invH * si.invH;
-        // N_s(i): the gather row, then the extras row
-        int64_t gb = goff[i];
-        int ngi = (int)(goff[i + 1] - gb);
-        int ebi = eb[i];
-        int tot = si.fl != (T)0 ? 0 : ngi + (ee[i] - ebi);
-        // the next partner index is fetched one step ahead; a partner's record
-        // is loaded before its FP64-row flag is looked at, so the loads of one
-        // step go out together
+        const double4 pi = posH[i];
+        Rec<T> si;
+        load_rec(rec, i, si);
+        Vsi = si.Vs;
+        const PairK<T> pk = pair_k<T>(p);
+        const int64_t gb = goff[i];
+        const int ngi = (int)(goff[i + 1] - gb);
+        const int ebi = eb[i];
+        const int tot = fp64_row(si) ? 0 : ngi + (ee[i] - ebi);
         int32_t jn = l < tot ? (l < ngi ? gidx[gb + l] : eidx[ebi + (l - ngi)]) : 0;
         for (int kk = l; kk < tot; kk += G) {
             const int32_t j = jn;
             const int kn = kk + G;
             if (kn < tot) jn = kn < ngi ? gidx[gb + kn] : eidx[ebi + (kn - ngi)];
-            double4 pj = posH[j];
-            State<T> sj;
-            load_state(rec, j, sj);
+            const double4 pj = posH[j];
+            Rec<T> sj;
+            load_rec(rec, j, sj);
             T d[3];
             separation(pi, pj, box, d[0], d[1], d[2]);
-            T F[3], E, pvs, pqr;
-            deriv_pair<T, TS>(si, sj, d, pc, cwi, cgi, F, E, pvs, pqr);
-            if (sj.fl == (T)0) {
-                a[0].add(F[0]);
-                a[1].add(F[1]);
-                a[2].add(F[2]);
-                a[3].add(E);
+            T FD[3], EP, pvs, pqr;
+            pair_deriv<T, TS>(si, sj, d, pk, FD, EP, pvs, pqr);
+            if (!fp64_row(sj)) {
+                a[0].add(FD[0]);
+                a[1].add(FD[1]);
+                a[2].add(FD[2]);
+                a[3].add(EP);
                 if constexpr (TS) {
                     vs = pvs > vs ? pvs : vs;
                     qr = pqr > qr ? pqr : qr;
@@ -667,11 +908,11 @@ __global__ __launch_bounds__(kBlock) void k_deriv(const double4 *__restrict__ po
         }
     }
     if (i < n && l == 0) {
-        double im = 1.0 / m[i];
-        dpdt[i] = a[0].value() * im;
-        dpdt[n + i] = a[1].value() * im;
-        dpdt[2 * n + i] = a[2].value() * im;
-        dudt[i] = a[3].value() * im;
+        const double f = (double)Vsi / m[i];
+        dpdt[i] = a[0].value() * f;
+        dpdt[n + i] = a[1].value() * f;
+        dpdt[2 * n + i] = a[2].value() * f;
+        dudt[i] = a[3].value() * f * p.inv_a5;
         if constexpr (TS) {
             ts_vs[i] = (double)vs;
             ts_qr[i] = (double)qr;
@@ -681,7 +922,7 @@ __global__ __launch_bounds__(kBlock) void k_deriv(const double4 *__restrict__ po
 
 // FP64 rows of the adaptive mode: for each listed particle, every pair when
 // the particle itself is flagged, else only the pairs with a flagged
-// partner; the FP64 sums are added to the outputs of k_deriv.
+// partner; the FP64 sums are added to the outputs of the FP32 launch.
 template <int G, bool TS = false>
 __global__ __launch_bounds__(kBlock) void k_deriv_fix(const double4 *__restrict__ posH,
                                                       const int64_t *__restrict__ goff,
@@ -700,61 +941,59 @@ __global__ __launch_bounds__(kBlock) void k_deriv_fix(const double4 *__restrict_
     if (nlist_dev) nlist = *nlist_dev;
     const int64_t gstride = (int64_t)gridDim.x * (kBlock / G);
     for (; g < nlist; g += gstride) {
-    const int64_t i = list[g];
-    Acc<double> a[4];
-    double vs = 0.0, qr = 0.0;
-    if (i >= 0) {
-        double4 pi = posH[i];
-        State<double> si;
-        load_state_soa(s, posH, n, i, si);
-        const PairConst<double> pc = pair_const<double>(p);
-        double cwi = kW * si.invH * si.invH * si.invH;
-        double cgi = kG * si.invH * si.invH * si.invH * si.invH * si.invH;
-        bool all = flag[i] != 0;
-        int64_t gb = goff[i];
-        int ngi = (int)(goff[i + 1] - gb);
-        int ebi = eb[i];
-        int tot = ngi + (ee[i] - ebi);
-        for (int kk = l; kk < tot; kk += G) {
-            int32_t j = kk < ngi ? gidx[gb + kk] : eidx[ebi + (kk - ngi)];
-            if (!all && flag[j] == 0) continue;
-            double4 pj = posH[j];
-            State<double> sj;
-            load_state_soa(s, posH, n, j, sj);
-            double d[3];
-            separation(pi, pj, box, d[0], d[1], d[2]);
-            double F[3], E, pvs, pqr;
-            deriv_pair<double, TS>(si, sj, d, pc, cwi, cgi, F, E, pvs, pqr);
-            a[0].add(F[0]);
-            a[1].add(F[1]);
-            a[2].add(F[2]);
-            a[3].add(E);
-            if constexpr (TS) {
-                vs = fmax(vs, pvs);
-                qr = fmax(qr, pqr);
+        const int64_t i = list[g];
+        Acc<double> a[4];
+        double vs = 0.0, qr = 0.0, Vsi = 0.0;
+        if (i >= 0) {
+            const double4 pi = posH[i];
+            Rec<double> si;
+            load_rec_soa(s, posH, n, i, p, si);
+            Vsi = si.Vs;
+            const PairK<double> pk = pair_k<double>(p);
+            const bool all = flag[i] != 0;
+            const int64_t gb = goff[i];
+            const int ngi = (int)(goff[i + 1] - gb);
+            const int ebi = eb[i];
+            const int tot = ngi + (ee[i] - ebi);
+            for (int kk = l; kk < tot; kk += G) {
+                const int32_t j = kk < ngi ? gidx[gb + kk] : eidx[ebi + (kk - ngi)];
+                if (!all && flag[j] == 0) continue;
+                Rec<double> sj;
+                load_rec_soa(s, posH, n, j, p, sj);
+                double d[3];
+                separation(pi, posH[j], box, d[0], d[1], d[2]);
+                double FD[3], EP, pvs, pqr;
+                pair_deriv<double, TS>(si, sj, d, pk, FD, EP, pvs, pqr);
+                a[0].add(FD[0]);
+                a[1].add(FD[1]);
+                a[2].add(FD[2]);
+                a[3].add(EP);
+                if constexpr (TS) {
+                    vs = fmax(vs, pvs);
+                    qr = fmax(qr, pqr);
+                }
             }
         }
-    }
-    group_reduce<double, G, 4>(a);
-    if constexpr (TS) {
-#pragma unroll
-        for (int o = G / 2; o >= 1; o >>= 1) {
-            vs = fmax(vs, __shfl_xor(vs, o, G));
-            qr = fmax(qr, __shfl_xor(qr, o, G));
-        }
-    }
-    if (l == 0 && i >= 0) {
-        double im = 1.0 / m[i];
-        dpdt[i] += a[0].value() * im;
-        dpdt[n + i] += a[1].value() * im;
-        dpdt[2 * n + i] += a[2].value() * im;
-        dudt[i] += a[3].value() * im;
+        group_reduce<double, G, 4>(a);
         if constexpr (TS) {
-            // the pairs k_deriv skipped: the maximum over both launches
-            ts_vs[i] = fmax(ts_vs[i], vs);
-            ts_qr[i] = fmax(ts_qr[i], qr);
+#pragma unroll
+            for (int o = G / 2; o >= 1; o >>= 1) {
+                vs = fmax(vs, __shfl_xor(vs, o, G));
+                qr = fmax(qr, __shfl_xor(qr, o, G));
+            }
         }
-    }
+        if (l == 0 && i >= 0) {
+            const double f = Vsi / m[i];
+            dpdt[i] += a[0].value() * f;
+            dpdt[n + i] += a[1].value() * f;
+            dpdt[2 * n + i] += a[2].value() * f;
+            dudt[i] += a[3].value() * f * p.inv_a5;
+            if constexpr (TS) {
+                // the pairs the FP32 launch skipped: the maximum over both launches
+                ts_vs[i] = fmax(ts_vs[i], vs);
+                ts_qr[i] = fmax(ts_qr[i], qr);
+            }
+        }
     }
 }
 
@@ -783,9 +1022,10 @@ __global__ __launch_bounds__(kBlock) void k_pack_ce(int64_t n, const double *v, 
 }
 
 // One ordered pair of the compatible update: c = (q_j - q_i).F with F =
-// m_i dp_ij/dt of eq. (mom), so Delta E_ij = c / (2 a^4) and, from the four
-// cases of eq. (fij), f_ij = s_j / (s_i + s_j) when Delta E_ij >= 0 and
-// s_i / (s_i + s_j) otherwise; returns f_ij c.
+// m_i dp_ij/dt of eq. (mom) (here F / Vs_i, which has the same sign), so
+// Delta E_ij = c / (2 a^4) and, from the four cases of eq. (fij), f_ij =
+// s_j / (s_i + s_j) when Delta E_ij >= 0 and s_i / (s_i + s_j) otherwise;
+// returns f_ij c.
 template <typename T, typename V4>
 __device__ __forceinline__ T compat_term(const V4 &ci, const V4 &cj, const T F[3]) {
     const T c = (cj.x - ci.x) * F[0] + (cj.y - ci.y) * F[1] + (cj.z - ci.z) * F[2];
@@ -793,68 +1033,73 @@ __device__ __forceinline__ T compat_term(const V4 &ci, const V4 &cj, const T F[3
     return sh * Mth<T>::rcp(ci.w + cj.w) * c;
 }
 
-// Delta u_i = dt / (2 a^4 m_i) sum_j f_ij c_ij - dt (adot/a)(3(gamma-1)+2) u_i.
-// With NK = 2 a second kick (records ce2, output du2) shares the pair forces.
-// Pairs with an FP64-row flag on either side are left to k_compat_fix.
-template <typename T, int G, int NK>
-__global__ __launch_bounds__(kBlock) void k_compat(const double4 *__restrict__ posH,
-                                                   const int64_t *__restrict__ goff,
-                                                   const int32_t *__restrict__ gidx,
-                                                   const int32_t *__restrict__ eb,
-                                                   const int32_t *__restrict__ ee,
-                                                   const int32_t *__restrict__ eidx,
-                                                   const typename std::conditional<sizeof(T) == 4, float4, double4>::type *__restrict__ rec,
-                                                   const typename std::conditional<sizeof(T) == 4, float4, double4>::type *__restrict__ ce,
-                                                   const typename std::conditional<sizeof(T) == 4, float4, double4>::type *__restrict__ ce2,
-                                                   const double *__restrict__ m,
-                                                   const double *__restrict__ u, int64_t n, Box box,
-                                                   DerivPrm p, double scale, double cool, double *du,
-                                                   double *du2) {
+// Delta u_i = dt / (2 a^4 m_i) sum_j f_ij c_ij - dt (adot/a)(3(gamma-1)+2) u_i,
+// balanced lane groups. With NK = 2 a second kick (records ce2, output du2)
+// shares the pair forces. Pairs with an FP64-row flag on either side are
+// left to k_compat_fix.
+template <typename T, int P, int NK>
+__global__ __launch_bounds__(kBlock) void k_compat_bal(const double4 *__restrict__ posH,
+                                                       const int64_t *__restrict__ goff,
+                                                       const int32_t *__restrict__ gidx,
+                                                       const int32_t *__restrict__ eb,
+                                                       const int32_t *__restrict__ ee,
+                                                       const int32_t *__restrict__ eidx,
+                                                       const typename std::conditional<sizeof(T) == 4, float4, double4>::type *__restrict__ rec,
+                                                       const typename std::conditional<sizeof(T) == 4, float4, double4>::type *__restrict__ ce,
+                                                       const typename std::conditional<sizeof(T) == 4, float4, double4>::type *__restrict__ ce2,
+                                                       const double *__restrict__ m,
+                                                       const double *__restrict__ u, int64_t n, Box box,
+                                                       DerivPrm p, double scale, double cool, double *du,
+                                                       double *du2) {
     using V4 = typename std::conditional<sizeof(T) == 4, float4, double4>::type;
-    int l;
-    int64_t i = group_index(G, l);
-    Acc<T> a[NK];
-    if (i < n) {
-        double4 pi = posH[i];
-        State<T> si;
-        load_state(rec, i, si);
-        const V4 cei = ce[i];
-        const V4 cei2 = NK == 2 ? ce2[i] : cei;
-        const PairConst<T> pc = pair_const<T>(p);
-        T cwi = (T)kW * si.invH * si.invH * si.invH;
-        T cgi = (T)kG * si.invH * si.invH * si.invH * si.invH * si.invH;
-        int64_t gb = goff[i];
-        int ngi = (int)(goff[i + 1] - gb);
-        int ebi = eb[i];
-        int tot = si.fl != (T)0 ? 0 : ngi + (ee[i] - ebi);
-        int32_t jn = l < tot ? (l < ngi ? gidx[gb + l] : eidx[ebi + (l - ngi)]) : 0;
-        for (int kk = l; kk < tot; kk += G) {
-            const int32_t j = jn;
-            const int kn = kk + G;
-            if (kn < tot) jn = kn < ngi ? gidx[gb + kn] : eidx[ebi + (kn - ngi)];
-            double4 pj = posH[j];
-            State<T> sj;
-            load_state(rec, j, sj);
-            const V4 cej = ce[j];
-            T d[3];
-            separation(pi, pj, box, d[0], d[1], d[2]);
-            T F[3], E, pvs, pqr;
-            deriv_pair<T, false>(si, sj, d, pc, cwi, cgi, F, E, pvs, pqr);
-            if (sj.fl == (T)0) {
-                a[0].add(compat_term<T>(cei, cej, F));
-                if constexpr (NK == 2) a[1].add(compat_term<T>(cei2, ce2[j], F));
-            }
+    const int64_t i0 = wave_first(P);
+    if (i0 >= n) return;
+    const int lane = threadIdx.x & 63;
+    const int np = (int)(n - i0 < P ? n - i0 : P);
+    const LaneGroup lg = lane_group<P>(i0, np, lane, goff, eb, ee);
+    const int64_t i = lg.i;
+    double a[NK] = {};
+    Rec<T> si;
+    load_rec(rec, i, si);
+    const double4 pi = posH[i];
+    const V4 cei = ce[i];
+    const V4 cei2 = NK == 2 ? ce2[i] : cei;
+    const PairK<T> pk = pair_k<T>(p);
+    const int64_t gb = goff[i];
+    const int ngi = (int)(goff[i + 1] - gb);
+    const int ebi = eb[i];
+    const int tot = fp64_row(si) ? 0 : ngi + (ee[i] - ebi);
+    const int G = lg.g;
+    int kk = lg.first;
+    int32_t jn = kk < tot ? (kk < ngi ? gidx[gb + kk] : eidx[ebi + (kk - ngi)]) : 0;
+    for (; kk < tot; kk += G) {
+        const int32_t j = jn;
+        const int kn = kk + G;
+        if (kn < tot) jn = kn < ngi ? gidx[gb + kn] : eidx[ebi + (kn - ngi)];
+        const double4 pj = posH[j];
+        const V4 cej = ce[j];
+        const V4 cej2 = NK == 2 ? ce2[j] : cej;
+        Rec<T> sj;
+        load_rec(rec, j, sj);
+        T d[3];
+        separation(pi, pj, box, d[0], d[1], d[2]);
+        T FD[3], EP, vs, qr;
+        pair_deriv<T, false>(si, sj, d, pk, FD, EP, vs, qr);
+        if (!fp64_row(sj)) {
+            a[0] += (double)compat_term<T>(cei, cej, FD);
+            if constexpr (NK == 2) a[1] += (double)compat_term<T>(cei2, cej2, FD);
         }
     }
-    group_reduce<T, G, NK>(a);
-    if (i < n && l == 0) {
-        du[i] = a[0].value() * (scale / m[i]) - cool * u[i];
-        if constexpr (NK == 2) du2[i] = a[1].value() * (scale / m[i]) - cool * u[i];
+    group_scan<double, NK>(lane, lg.key, a);
+    if (lg.last) {
+        const double f = (double)si.Vs * scale / m[i];
+        du[i] = a[0] * f - cool * u[i];
+        if constexpr (NK == 2) du2[i] = a[1] * f - cool * u[i];
     }
 }
 
 // FP64 pairs of the adaptive mode (as k_deriv_fix): adds their share of
-// the sum to the output(s) of k_compat.
+// the sum to the output(s) of k_compat_bal.
 template <int G, int NK>
 __global__ __launch_bounds__(kBlock) void k_compat_fix(const double4 *__restrict__ posH,
                                                        const int64_t *__restrict__ goff,
@@ -875,38 +1120,37 @@ __global__ __launch_bounds__(kBlock) void k_compat_fix(const double4 *__restrict
     for (; g < nlist; g += gstride) {
         const int64_t i = list[g];
         Acc<double> a[NK];
+        double Vsi = 0.0;
         if (i >= 0) {
-            double4 pi = posH[i];
-            State<double> si;
-            load_state_soa(s, posH, n, i, si);
+            const double4 pi = posH[i];
+            Rec<double> si;
+            load_rec_soa(s, posH, n, i, p, si);
+            Vsi = si.Vs;
             const double4 cei = ced[i];
             const double4 cei2 = NK == 2 ? ced2[i] : cei;
-            const PairConst<double> pc = pair_const<double>(p);
-            double cwi = kW * si.invH * si.invH * si.invH;
-            double cgi = kG * si.invH * si.invH * si.invH * si.invH * si.invH;
-            bool all = flag[i] != 0;
-            int64_t gb = goff[i];
-            int ngi = (int)(goff[i + 1] - gb);
-            int ebi = eb[i];
-            int tot = ngi + (ee[i] - ebi);
+            const PairK<double> pk = pair_k<double>(p);
+            const bool all = flag[i] != 0;
+            const int64_t gb = goff[i];
+            const int ngi = (int)(goff[i + 1] - gb);
+            const int ebi = eb[i];
+            const int tot = ngi + (ee[i] - ebi);
             for (int kk = l; kk < tot; kk += G) {
-                int32_t j = kk < ngi ? gidx[gb + kk] : eidx[ebi + (kk - ngi)];
+                const int32_t j = kk < ngi ? gidx[gb + kk] : eidx[ebi + (kk - ngi)];
                 if (!all && flag[j] == 0) continue;
-                double4 pj = posH[j];
-                State<double> sj;
-                load_state_soa(s, posH, n, j, sj);
+                Rec<double> sj;
+                load_rec_soa(s, posH, n, j, p, sj);
                 double d[3];
-                separation(pi, pj, box, d[0], d[1], d[2]);
-                double F[3], E, pvs, pqr;
-                deriv_pair<double, false>(si, sj, d, pc, cwi, cgi, F, E, pvs, pqr);
-                a[0].add(compat_term<double>(cei, ced[j], F));
-                if constexpr (NK == 2) a[1].add(compat_term<double>(cei2, ced2[j], F));
+                separation(pi, posH[j], box, d[0], d[1], d[2]);
+                double FD[3], EP, pvs, pqr;
+                pair_deriv<double, false>(si, sj, d, pk, FD, EP, pvs, pqr);
+                a[0].add(compat_term<double>(cei, ced[j], FD));
+                if constexpr (NK == 2) a[1].add(compat_term<double>(cei2, ced2[j], FD));
             }
         }
         group_reduce<double, G, NK>(a);
         if (l == 0 && i >= 0) {
-            du[i] += a[0].value() * (scale / m[i]);
-            if constexpr (NK == 2) du2[i] += a[1].value() * (scale / m[i]);
+            du[i] += a[0].value() * (Vsi * scale / m[i]);
+            if constexpr (NK == 2) du2[i] += a[1].value() * (Vsi * scale / m[i]);
         }
     }
 }
@@ -1030,6 +1274,26 @@ inline unsigned fix_blocks(int64_t rows, int G, bool graph) {
         default: return set_err(c, CRK_ERR_INVALID_ARG, "lanes per particle must be a power of two <= 64"); \
     }
 
+DerivPrm deriv_prm(const crk_params *p) {
+    const double a = p->a;
+    return DerivPrm{p->gamma, p->Cl, p->Cq, p->eps * p->eps, 1.0 / p->nh, 1.0 / a, p->adot,
+                    p->eta_crit, 1.0 / p->eta_fold, a * sqrt(0.5), 1.0 / (a * a * a * a * a)};
+}
+
+// balanced-lane derivative / compatible launches: particles per wave (4 .. 32)
+#define CRK_DISPATCH_P(P, LAUNCH)                                                          \
+    switch (P) {                                                                           \
+        case 4: LAUNCH(4); break;                                                          \
+        case 8: LAUNCH(8); break;                                                          \
+        case 16: LAUNCH(16); break;                                                        \
+        case 32: LAUNCH(32); break;                                                        \
+        default: return set_err(c, CRK_ERR_INVALID_ARG, "particles per wave must be 4, 8, 16 or 32"); \
+    }
+
+inline unsigned pblocks(int64_t n, int P) {
+    return (unsigned)(((n + P - 1) / P + kBlock / 64 - 1) / (kBlock / 64));
+}
+
 bool valid_prec(int p) { return p == CRK_FP64 || p == CRK_MIXED || p == CRK_MIXED_ADAPT; }
 
 }  // namespace
@@ -1050,6 +1314,15 @@ crk_status crk_set_walk(crk_ctx *c, int32_t lanes, int32_t cap, int32_t level_sh
     if (lanes) c->G_walk = lanes;
     if (cap) c->walk_cap = cap;
     if (level_shift >= 0) c->walk_shift = level_shift;
+    return CRK_OK;
+}
+
+crk_status crk_set_deriv_mapping(crk_ctx *c, int32_t particles_per_wave) {
+    if (!c) return CRK_ERR_INVALID_ARG;
+    const int p = particles_per_wave;
+    if (p != 0 && p != 4 && p != 8 && p != 16 && p != 32)
+        return set_err(c, CRK_ERR_INVALID_ARG, "particles per wave must be 0, 4, 8, 16 or 32");
+    c->P_der = p;
     return CRK_OK;
 }
 
@@ -1235,12 +1508,11 @@ crk_status crk_derivatives(crk_ctx *c, const crk_params *p, const double *v, con
                   *eidx = (const int32_t *)c->eidx.p;
     const bool f32 = p->precision != CRK_FP64;
     const bool adapt = p->precision == CRK_MIXED_ADAPT;
-    DerivPrm dp{p->gamma, p->Cl, p->Cq, p->eps * p->eps, 1.0 / p->nh, 1.0 / p->a,
-                0.5 * p->a * p->a, 0.5 / (p->a * p->a), p->adot, p->eta_crit, 1.0 / p->eta_fold};
+    const DerivPrm dp = deriv_prm(p);
     CRK_TRY(ensure(c, c->misc, 256));
     int *bad = (int *)c->misc.p + 2;
     CRK_TRY(zero_async(c, bad, 1));
-    int Gg = c->G_grad, Gd = c->G_der;
+    int Gg = c->G_grad, Gd = c->G_der, Pd = c->P_der;
 
     // adaptive mode: FP64 rows for ill-conditioned RK templates
     const bool gm = c->graph_mode != 0;
@@ -1252,7 +1524,7 @@ crk_status crk_derivatives(crk_ctx *c, const crk_params *p, const double *v, con
 
     if (f32) {
         CRK_TRY(ensure(c, c->rec6, (size_t)n * sizeof(float4)));
-        CRK_TRY(ensure(c, c->rec7, (size_t)n * kRec7 * sizeof(float4)));
+        CRK_TRY(ensure(c, c->rec7, (size_t)n * kRec * sizeof(float4)));
         float4 *r6 = (float4 *)c->rec6.p, *r7 = (float4 *)c->rec7.p;
         double4 *r6d = nullptr, *aux = nullptr;
         if (adapt) {
@@ -1280,14 +1552,20 @@ crk_status crk_derivatives(crk_ctx *c, const crk_params *p, const double *v, con
         }
         {
             KTimer kt_(c, "k_pack");
-            k_pack7<float4, float><<<nblocks(n), kBlock, 0, c->stream>>>(n, posH, v, m, u, rho, V, A, B, gA, gB, gradv, dp, flag, r7, aux, bad);
+            k_pack8<float4, float><<<nblocks(n), kBlock, 0, c->stream>>>(n, posH, v, m, u, rho, V, A, B, gA, gB, gradv, dp, flag, r7, aux, bad);
         }
-#define L_DER(GG) if (ts) k_deriv<float, GG, true><<<gblocks(n, GG), kBlock, 0, c->stream>>>(posH, goff, gidx, eb, ee, eidx, r7, m, n, box, dp, dpdt, dudt, tvs, tqr); else k_deriv<float, GG><<<gblocks(n, GG), kBlock, 0, c->stream>>>(posH, goff, gidx, eb, ee, eidx, r7, m, n, box, dp, dpdt, dudt)
         {
             KTimer kt_(c, "k_deriv");
-            CRK_DISPATCH_G(Gd, L_DER);
-        }
+            if (Pd > 0) {
+#define L_DER(PP) if (ts) k_deriv_bal<float, PP, true><<<pblocks(n, PP), kBlock, 0, c->stream>>>(posH, goff, gidx, eb, ee, eidx, r7, m, n, box, dp, dpdt, dudt, tvs, tqr); else k_deriv_bal<float, PP, false><<<pblocks(n, PP), kBlock, 0, c->stream>>>(posH, goff, gidx, eb, ee, eidx, r7, m, n, box, dp, dpdt, dudt)
+                CRK_DISPATCH_P(Pd, L_DER);
 #undef L_DER
+            } else {
+#define L_DER(GG) if (ts) k_deriv<float, GG, true><<<gblocks(n, GG), kBlock, 0, c->stream>>>(posH, goff, gidx, eb, ee, eidx, r7, m, n, box, dp, dpdt, dudt, tvs, tqr); else k_deriv<float, GG><<<gblocks(n, GG), kBlock, 0, c->stream>>>(posH, goff, gidx, eb, ee, eidx, r7, m, n, box, dp, dpdt, dudt)
+                CRK_DISPATCH_G(Gd, L_DER);
+#undef L_DER
+            }
+        }
         if (adapt && ntouch > 0) {
             Soa s{v, V, A, B, gA, gB, gradv, aux};
 #define L_FIX(GG) if (ts) k_deriv_fix<GG, true><<<fix_blocks(ntouch, GG, gm), kBlock, 0, c->stream>>>(posH, goff, gidx, eb, ee, eidx, s, flag, tlist, ntouch, ntouch_dev, m, n, box, dp, dpdt, dudt, tvs, tqr); else k_deriv_fix<GG><<<fix_blocks(ntouch, GG, gm), kBlock, 0, c->stream>>>(posH, goff, gidx, eb, ee, eidx, s, flag, tlist, ntouch, ntouch_dev, m, n, box, dp, dpdt, dudt)
@@ -1297,7 +1575,7 @@ crk_status crk_derivatives(crk_ctx *c, const crk_params *p, const double *v, con
         }
     } else {
         CRK_TRY(ensure(c, c->rec6, (size_t)n * sizeof(double4)));
-        CRK_TRY(ensure(c, c->rec7, (size_t)n * kRec7 * sizeof(double4)));
+        CRK_TRY(ensure(c, c->rec7, (size_t)n * kRec * sizeof(double4)));
         double4 *r6 = (double4 *)c->rec6.p, *r7 = (double4 *)c->rec7.p;
         {
             KTimer kt_(c, "k_pack");
@@ -1311,14 +1589,20 @@ crk_status crk_derivatives(crk_ctx *c, const crk_params *p, const double *v, con
 #undef L_GV
         {
             KTimer kt_(c, "k_pack");
-            k_pack7<double4, double><<<nblocks(n), kBlock, 0, c->stream>>>(n, posH, v, m, u, rho, V, A, B, gA, gB, gradv, dp, nullptr, r7, nullptr, bad);
+            k_pack8<double4, double><<<nblocks(n), kBlock, 0, c->stream>>>(n, posH, v, m, u, rho, V, A, B, gA, gB, gradv, dp, nullptr, r7, nullptr, bad);
         }
-#define L_DER(GG) if (ts) k_deriv<double, GG, true><<<gblocks(n, GG), kBlock, 0, c->stream>>>(posH, goff, gidx, eb, ee, eidx, r7, m, n, box, dp, dpdt, dudt, tvs, tqr); else k_deriv<double, GG><<<gblocks(n, GG), kBlock, 0, c->stream>>>(posH, goff, gidx, eb, ee, eidx, r7, m, n, box, dp, dpdt, dudt)
         {
             KTimer kt_(c, "k_deriv");
-            CRK_DISPATCH_G(Gd, L_DER);
-        }
+            if (Pd > 0) {
+#define L_DER(PP) if (ts) k_deriv_bal<double, PP, true><<<pblocks(n, PP), kBlock, 0, c->stream>>>(posH, goff, gidx, eb, ee, eidx, r7, m, n, box, dp, dpdt, dudt, tvs, tqr); else k_deriv_bal<double, PP, false><<<pblocks(n, PP), kBlock, 0, c->stream>>>(posH, goff, gidx, eb, ee, eidx, r7, m, n, box, dp, dpdt, dudt)
+                CRK_DISPATCH_P(Pd, L_DER);
 #undef L_DER
+            } else {
+#define L_DER(GG) if (ts) k_deriv<double, GG, true><<<gblocks(n, GG), kBlock, 0, c->stream>>>(posH, goff, gidx, eb, ee, eidx, r7, m, n, box, dp, dpdt, dudt, tvs, tqr); else k_deriv<double, GG><<<gblocks(n, GG), kBlock, 0, c->stream>>>(posH, goff, gidx, eb, ee, eidx, r7, m, n, box, dp, dpdt, dudt)
+                CRK_DISPATCH_G(Gd, L_DER);
+#undef L_DER
+            }
+        }
     }
     CRK_HIP(c, hipGetLastError());
     c->ts_valid = ts;
@@ -1382,15 +1666,14 @@ crk_status crk::compat_pass(crk_ctx *c, const crk_params *p, const double *v, co
                   *eidx = (const int32_t *)c->eidx.p;
     const bool f32 = p->precision != CRK_FP64;
     const bool adapt = p->precision == CRK_MIXED_ADAPT;
-    DerivPrm dp{p->gamma, p->Cl, p->Cq, p->eps * p->eps, 1.0 / p->nh, 1.0 / p->a,
-                0.5 * p->a * p->a, 0.5 / (p->a * p->a), p->adot, p->eta_crit, 1.0 / p->eta_fold};
+    const DerivPrm dp = deriv_prm(p);
     const double a4 = p->a * p->a * p->a * p->a;
     const double scale = dt / (2.0 * a4);
     const double cool = dt * (p->adot / p->a) * (3.0 * (p->gamma - 1.0) + 2.0);
     CRK_TRY(ensure(c, c->misc, 256));
     int *bad = (int *)c->misc.p + 2;
     CRK_TRY(zero_async(c, bad, 1));
-    const int Gd = c->G_der;
+    const int Gd = c->G_der, Pd = c->P_der > 0 ? c->P_der : 8;
     AdaptRows ar;
     // the records, FP64-row flags and lists of the derivative call just made
     // on this same state are reused when the caller says so (eager only)
@@ -1405,7 +1688,7 @@ crk_status crk::compat_pass(crk_ctx *c, const crk_params *p, const double *v, co
         }
     }
     if (f32) {
-        CRK_TRY(ensure(c, c->rec7, (size_t)n * kRec7 * sizeof(float4)));
+        CRK_TRY(ensure(c, c->rec7, (size_t)n * kRec * sizeof(float4)));
         CRK_TRY(ensure(c, c->ce, (size_t)n * sizeof(float4) * (two ? 2 : 1)));
         float4 *r7 = (float4 *)c->rec7.p, *ce = (float4 *)c->ce.p;
         float4 *ce2 = two ? ce + n : nullptr;
@@ -1419,14 +1702,14 @@ crk_status crk::compat_pass(crk_ctx *c, const crk_params *p, const double *v, co
         }
         {
             KTimer kt_(c, "k_pack");
-            if (!keep) k_pack7<float4, float><<<nblocks(n), kBlock, 0, c->stream>>>(n, posH, v, m, u, rho, V, A, B, gA, gB, gradv, dp, ar.flag, r7, aux, bad);
+            if (!keep) k_pack8<float4, float><<<nblocks(n), kBlock, 0, c->stream>>>(n, posH, v, m, u, rho, V, A, B, gA, gB, gradv, dp, ar.flag, r7, aux, bad);
             k_pack_ce<float4, float><<<nblocks(n), kBlock, 0, c->stream>>>(n, v, pk, dpdt, m, u, rho, V, p->gamma, p->a, dt, ce, ced);
             if (two) k_pack_ce<float4, float><<<nblocks(n), kBlock, 0, c->stream>>>(n, v, pk2, dpdt, m, u, rho, V, p->gamma, p->a, dt, ce2, ced2);
         }
-#define L_CE(GG) if (two) k_compat<float, GG, 2><<<gblocks(n, GG), kBlock, 0, c->stream>>>(posH, goff, gidx, eb, ee, eidx, r7, ce, ce2, m, u, n, box, dp, scale, cool, du, du2); else k_compat<float, GG, 1><<<gblocks(n, GG), kBlock, 0, c->stream>>>(posH, goff, gidx, eb, ee, eidx, r7, ce, nullptr, m, u, n, box, dp, scale, cool, du, nullptr)
+#define L_CE(PP) if (two) k_compat_bal<float, PP, 2><<<pblocks(n, PP), kBlock, 0, c->stream>>>(posH, goff, gidx, eb, ee, eidx, r7, ce, ce2, m, u, n, box, dp, scale, cool, du, du2); else k_compat_bal<float, PP, 1><<<pblocks(n, PP), kBlock, 0, c->stream>>>(posH, goff, gidx, eb, ee, eidx, r7, ce, nullptr, m, u, n, box, dp, scale, cool, du, nullptr)
         {
             KTimer kt_(c, "k_compat");
-            CRK_DISPATCH_G(Gd, L_CE);
+            CRK_DISPATCH_P(Pd, L_CE);
         }
 #undef L_CE
         if (adapt && ar.ntouch > 0) {
@@ -1437,20 +1720,20 @@ crk_status crk::compat_pass(crk_ctx *c, const crk_params *p, const double *v, co
 #undef L_CEF
         }
     } else {
-        CRK_TRY(ensure(c, c->rec7, (size_t)n * kRec7 * sizeof(double4)));
+        CRK_TRY(ensure(c, c->rec7, (size_t)n * kRec * sizeof(double4)));
         CRK_TRY(ensure(c, c->ce, (size_t)n * sizeof(double4) * (two ? 2 : 1)));
         double4 *r7 = (double4 *)c->rec7.p, *ce = (double4 *)c->ce.p;
         double4 *ce2 = two ? ce + n : nullptr;
         {
             KTimer kt_(c, "k_pack");
-            if (!keep) k_pack7<double4, double><<<nblocks(n), kBlock, 0, c->stream>>>(n, posH, v, m, u, rho, V, A, B, gA, gB, gradv, dp, nullptr, r7, nullptr, bad);
+            if (!keep) k_pack8<double4, double><<<nblocks(n), kBlock, 0, c->stream>>>(n, posH, v, m, u, rho, V, A, B, gA, gB, gradv, dp, nullptr, r7, nullptr, bad);
             k_pack_ce<double4, double><<<nblocks(n), kBlock, 0, c->stream>>>(n, v, pk, dpdt, m, u, rho, V, p->gamma, p->a, dt, ce, nullptr);
             if (two) k_pack_ce<double4, double><<<nblocks(n), kBlock, 0, c->stream>>>(n, v, pk2, dpdt, m, u, rho, V, p->gamma, p->a, dt, ce2, nullptr);
         }
-#define L_CE(GG) if (two) k_compat<double, GG, 2><<<gblocks(n, GG), kBlock, 0, c->stream>>>(posH, goff, gidx, eb, ee, eidx, r7, ce, ce2, m, u, n, box, dp, scale, cool, du, du2); else k_compat<double, GG, 1><<<gblocks(n, GG), kBlock, 0, c->stream>>>(posH, goff, gidx, eb, ee, eidx, r7, ce, nullptr, m, u, n, box, dp, scale, cool, du, nullptr)
+#define L_CE(PP) if (two) k_compat_bal<double, PP, 2><<<pblocks(n, PP), kBlock, 0, c->stream>>>(posH, goff, gidx, eb, ee, eidx, r7, ce, ce2, m, u, n, box, dp, scale, cool, du, du2); else k_compat_bal<double, PP, 1><<<pblocks(n, PP), kBlock, 0, c->stream>>>(posH, goff, gidx, eb, ee, eidx, r7, ce, nullptr, m, u, n, box, dp, scale, cool, du, nullptr)
         {
             KTimer kt_(c, "k_compat");
-            CRK_DISPATCH_G(Gd, L_CE);
+            CRK_DISPATCH_P(Pd, L_CE);
         }
 #undef L_CE
     }
