@@ -41,9 +41,13 @@ VALU_PEAK_TFLOPS = 78.6
 VALU_PEAK_PACKED_FP32 = 157.3
 
 # algorithmic work of the derivative pass (k_deriv), counted from the kernel
-# source: flops per ordered pair and bytes per particle / per pair
-DERIV_FLOPS_PER_PAIR = 256
-DERIV_BYTES_PER_PARTICLE = {"mixed": 32 + 144 + 8 + 8 + 32, "fp64": 32 + 288 + 8 + 8 + 32}
+# source (pair_deriv in crk_pairs.hip, an FMA counted as two flops, sqrt,
+# reciprocal and exp as one, the periodic wrap of d not counted): 187 flops
+# per ordered pair, 4 of them the sums; bytes per particle: x, y, z (24), the
+# packed record (128 of its 144 bytes FP32, 256 of 288 FP64), m (8), row
+# offsets (16), outputs (32); per ordered pair its 4-byte index
+DERIV_FLOPS_PER_PAIR = 187
+DERIV_BYTES_PER_PARTICLE = {"mixed": 24 + 128 + 8 + 16 + 32, "fp64": 24 + 256 + 8 + 16 + 32}
 DERIV_BYTES_PER_PAIR = 4
 
 OUT_KEYS = ("V", "m0", "m1", "m2", "gm0", "gm1", "gm2", "A", "B", "gA", "gB", "gradv", "dpdt",
@@ -69,8 +73,9 @@ def code_sha256(path: str) -> str:
 def deriv_traffic(precision: str, lanes: int):
     """HBM bytes per k_deriv launch from the committed rocprofv3 counter runs
     (FETCH_SIZE and WRITE_SIZE scaled by the copy-probe factors), or None when
-    the kernel source (its code, comments aside) or its launch shape differs
-    from the one measured."""
+    the kernel source (its code, comments aside) or its launch shape (the
+    particles per wavefront of its balanced lane groups) differs from the
+    one measured."""
     if not os.path.exists(COUNTERS):
         return None
     rec = json.load(open(COUNTERS))
@@ -85,6 +90,24 @@ def make_workload(n_side=128, seed=2):
     return ci.lognormal_box(n_side, sigma=1.5, spectral_index=-2.0, seed=seed)
 
 
+def cpu_model() -> str:
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def oracle_step_rate(ps) -> tuple:
+    """(pairs, seconds) of the oracle's whole step on one particle set."""
+    import oracle
+    t0 = time.perf_counter()
+    out = oracle.pipeline(ps, oracle.params(64.0, gamma=ps.gamma))
+    return int(out["n_pairs"]), time.perf_counter() - t0
+
+
 def cpu_baseline(n_side: int) -> dict:
     import oracle
     ps = make_workload(n_side)
@@ -93,7 +116,7 @@ def cpu_baseline(n_side: int) -> dict:
     out = oracle.pipeline(ps, prm)
     dt = time.perf_counter() - t0
     res = {"value": out["n_pairs"] / dt, "unit": "pair-interactions/s", "cores": oracle.threads(),
-           "kind": "oracle",
+           "cpu_model": cpu_model(), "kind": "oracle",
            "sample": f"full FP64 oracle step (neighbour sets, volume, moments, corrections, grad v, "
                      f"derivatives) on the same recipe at {n_side}^3 = {ps.n} particles "
                      f"({out['n_pairs']} pairs, {dt:.2f} s)"}
@@ -123,35 +146,66 @@ def cpu_baseline(n_side: int) -> dict:
                                        f"{one['seconds']:.2f} s)"}
     except (subprocess.SubprocessError, ValueError, KeyError, IndexError) as e:
         res["one_thread"] = {"error": str(e)[:200]}
+    # the oracle on the other configurations: the 32^3 jittered lattice whole,
+    # and a sample of the 512-box batch (every 16th box)
+    import crk_inputs as ci
+    from paper_2202_02840_amd import pipeline as pl
+    c1 = ci.lattice_box(32, seed=1)
+    pr, sec = oracle_step_rate(c1)
+    res["c1_lattice_32"] = {"value": pr / sec, "cores": oracle.threads(),
+                            "sample": f"whole oracle step, 32^3 jittered lattice ({pr} pairs, {sec:.2f} s)"}
+    boxes = ci.batch_boxes(512, seed=3)[::16]
+    pr, sec = 0, 0.0
+    for b in boxes:
+        p1, s1 = oracle_step_rate(b)
+        pr += p1
+        sec += s1
+    res["c3_batch_sample"] = {"value": pr / sec, "cores": oracle.threads(),
+                              "sample": f"whole oracle step on every 16th of the 512 boxes "
+                                        f"({len(boxes)} boxes, {sum(b.n for b in boxes)} particles, "
+                                        f"{pr} pairs, {sec:.2f} s)"}
     return res
 
 
 def hsurrogate_leg(ctx, args) -> dict:
-    """Smoothing-length network: train on clustered boxes with the library's
-    own kernels (labels from the plain iteration), then on a held-out box
-    compare the plain iteration with the network-seeded one at identical
-    converged H."""
+    """Smoothing-length network: labels from the plain iteration on clustered
+    boxes of 64^3..128^3 (sigma_ln_rho drawn from U[1, 2]), each box twice:
+    cold (the generator's supports, sized from the smoothed grid density)
+    and warm (the converged supports carried over a Courant step of
+    motion); training with the library's own kernels; then, on a held-out
+    128^3 box (sigma 2.0) from a cold and from a warm start, the plain
+    iteration against the network-seeded one at identical converged H, with
+    the tail of the per-particle update counts."""
     import crk_inputs as ci
+    import torch
     from paper_2202_02840_amd import hsurrogate as hs
     t0 = time.perf_counter()
-    feats, tgts, nsamp = [], [], 0
-    for b, sigma in enumerate((1.0, 1.5, 2.0)):
-        ps = ci.lognormal_box(args.hs_train_side, sigma=sigma, seed=100 + b)
-        f, t, _ = hs.training_pairs(ctx, ps)
-        feats.append(f)
-        tgts.append(t)
-        nsamp += ps.n
+    feats, tgts, nsamp, boxes = [], [], 0, []
+    rng = np.random.default_rng(100)
+    sides = [int(v) for v in args.hs_train_sides.split(",")]
+    sigmas = rng.uniform(1.0, 2.0, size=len(sides))
+    for b, (side, sg) in enumerate(zip(sides, sigmas)):
+        ps = ci.lognormal_box(side, sigma=float(sg), seed=100 + b)
+        for start in ("cold", "warm"):
+            src = ps if start == "cold" else hs.moved(ps, hs.converged(ctx, ps))
+            f, t, _ = hs.training_pairs(ctx, src)
+            feats.append(f)
+            tgts.append(t)
+            nsamp += src.n
+        boxes.append(f"{side}^3 sigma {sg:.2f}")
     t1 = time.perf_counter()
     theta, hist = hs.train(ctx, ci.hnet_init(0), feats, tgts, steps=args.hs_steps, batch=8192,
                            log_every=max(args.hs_steps // 5, 1))
-    import torch
     torch.cuda.synchronize()
     t2 = time.perf_counter()
+    del feats, tgts
     held = ci.lognormal_box(args.hs_eval_side, sigma=2.0, seed=4)
-    r = hs.evaluate(ctx, held, theta, tol=1e-8, repeats=2)
-    r.update(train_samples=nsamp, train_steps=args.hs_steps, label_seconds=t1 - t0,
-             train_seconds=t2 - t1, loss_history=hist,
-             eval_box=f"lognormal {args.hs_eval_side}^3, sigma 2.0, seed 4")
+    r = {"cold": hs.evaluate(ctx, held, theta, tol=1e-8, repeats=2)}
+    r["warm"] = hs.evaluate(ctx, hs.moved(held, hs.converged(ctx, held)), theta, tol=1e-8, repeats=2)
+    r.update(speedup=r["cold"]["speedup"], max_rel_dH=max(r["cold"]["max_rel_dH"], r["warm"]["max_rel_dH"]),
+             train_samples=nsamp, train_boxes=boxes, train_starts="cold and warm per box",
+             train_steps=args.hs_steps, label_seconds=t1 - t0, train_seconds=t2 - t1,
+             loss_history=hist, eval_box=f"lognormal {args.hs_eval_side}^3, sigma 2.0, seed 4")
     return r, theta
 
 
@@ -595,7 +649,7 @@ def batch_leg(args, prec, precision_name: str) -> dict:
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n-side", type=int, default=128)
     ap.add_argument("--precision", choices=("mixed", "adapt", "fp64"), default="adapt")
@@ -604,7 +658,8 @@ def main():
     ap.add_argument("--no-check", action="store_true")
     ap.add_argument("--no-hsurrogate", action="store_true",
                     help="skip the smoothing-length network leg (train + plain vs seeded iteration)")
-    ap.add_argument("--hs-train-side", type=int, default=64)
+    ap.add_argument("--hs-train-sides", type=str, default="64,80,96,112,128",
+                    help="sides of the network's training boxes (each labelled cold and warm)")
     ap.add_argument("--hs-eval-side", type=int, default=128)
     ap.add_argument("--hs-steps", type=int, default=1500)
     ap.add_argument("--lanes", type=str, default="", help="vol,mom,grad,der lanes per particle")
@@ -685,12 +740,18 @@ def main():
     ctx.timing(True)
     ctx.timing_reset()
     torch.cuda.synchronize()
+    # every step is timed on its own (synchronised); the line reports the
+    # median step, and the mean over the whole timed region beside it
+    step_ms = []
     t0 = time.perf_counter()
     for _ in range(args.steps):
+        ts = time.perf_counter()
         out = pl.step(ctx, dev, prm, count_singular=False)
-    torch.cuda.synchronize()
+        torch.cuda.synchronize()
+        step_ms.append((time.perf_counter() - ts) * 1e3)
     t1 = time.perf_counter()
-    ms_step = (t1 - t0) * 1e3 / max(args.steps, 1)
+    ms_mean = (t1 - t0) * 1e3 / max(args.steps, 1)
+    ms_step = float(np.median(step_ms))
     kern = {}
     for k in ("sort", "k_walk", "k_compact_rows", "k_walk_long", "k_extra_rank", "k_volume", "k_moments",
               "k_corrections", "k_flag", "k_pack", "k_gradv", "k_gradv_fix", "k_deriv",
@@ -741,6 +802,7 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": ms_step,
+        "ms_per_step_mean": ms_mean,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -756,7 +818,7 @@ def main():
                    "lanes": tuned},
         "roofline": {"bound": "alu", "achieved": achieved_tf, "peak": VALU_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved_tf / VALU_PEAK_TFLOPS,
-                     "traffic": deriv_traffic(args.precision, (tuned or {}).get("der")),
+                     "traffic": deriv_traffic(args.precision, (tuned or {}).get("der_wave", 8)),
                      "traffic_unit": "bytes per launch", "algorithmic_bytes": bytes_alg,
                      "kernel": "k_deriv", "kernel_ms": kern["k_deriv"],
                      "flops_per_pair": DERIV_FLOPS_PER_PAIR,

@@ -75,10 +75,12 @@ typedef enum {
                       (crk_corrections) and every boundary array stay FP64.
                       Accuracy depends on the conditioning of the RK solve: on jittered
                       lattices every output meets 1e-5 normwise against CRK_FP64, but on
-                      clustered inputs with nearly singular m2 it does NOT (measured on
-                      a lognormal 128^3 box, sigma_ln_rho = 1.5: about 3e-2 normwise in
-                      A and B and 1.5e-1 in the velocity gradient). Use CRK_MIXED_ADAPT
-                      for clustered inputs. */
+                      clustered inputs with nearly singular m2 it does NOT. Measured on
+                      a lognormal 128^3 box (sigma_ln_rho = 1.5), normwise against
+                      CRK_FP64: A 4e-4, B 7e-2, grad A 7e-2, grad B 6e+1 (the FP32
+                      moment sums of the few nearly singular particles), velocity
+                      gradient 1e-1, dv/dt 7e-2, du/dt 4e-2. Use CRK_MIXED_ADAPT for
+                      clustered inputs (all outputs within 1e-5 there). */
     CRK_MIXED_ADAPT = 2 /* volume and moment passes in FP64 (their sums feed the RK solve,
                       whose conditioning amplifies any rounding in them); velocity-gradient
                       and derivative passes as in CRK_MIXED, except the rows of particles
@@ -562,14 +564,17 @@ crk_status crk_hnet_targets(crk_ctx *ctx, int64_t n, const double *H_prev, const
 crk_status crk_export_neighbors(crk_ctx *ctx, int32_t which, int64_t *offsets, int32_t *idx,
                                 int64_t cap, int64_t *total);
 
-/* Thread mapping of the derivative and compatible-energy passes.
- * particles_per_wave = 16, 32 or 64 (default 32): a wavefront takes that
- * many consecutive particles and works through their concatenated pair
- * rows 64 pairs at a time, one pair per lane, summing per particle across
- * the lanes in FP64; 0: the lanes-per-particle mapping of crk_set_lanes'
- * g_der (the compatible pass then keeps 32). Tuning only: results agree to
- * rounding for every choice. */
-crk_status crk_set_deriv_mapping(crk_ctx *ctx, int32_t particles_per_wave);
+/* Thread mapping of the volume, moment, velocity-gradient and derivative
+ * (with the compatible-energy) passes: 4, 8, 16 or 32 particles per
+ * wavefront (default 8 for the derivative pass, 0 for the others), whose
+ * 64 lanes are split among them in proportion
+ * to their row lengths (each lane strides over its particle's row; the
+ * lanes of a particle are summed in FP64 at the end, so the wavefront's
+ * lanes stay busy however uneven the rows are); 0: the lanes-per-particle
+ * mapping of crk_set_lanes (the compatible pass then keeps 8); -1 keeps the
+ * current value. Tuning only: results agree to rounding for every choice. */
+crk_status crk_set_wave_mapping(crk_ctx *ctx, int32_t vol_ppw, int32_t mom_ppw, int32_t grad_ppw,
+                                int32_t deriv_ppw);
 
 /* Lanes per particle of the four pair passes (volume, moments, velocity
  * gradient, derivatives): each particle's neighbour row is split over a

@@ -19,7 +19,7 @@ STATUS = {0: "CRK_OK", 1: "CRK_WARN_SINGULAR", 2: "CRK_WARN_NOT_CONVERGED",
 EXPORTS = ("crk_params_default", "crk_create", "crk_destroy", "crk_last_error", "crk_build_cells",
            "crk_build_cells_batch", "crk_build_leaves",
            "crk_update_support", "crk_permute", "crk_moments", "crk_corrections",
-           "crk_derivatives", "crk_hsolve", "crk_export_neighbors", "crk_set_lanes", "crk_set_deriv_mapping", "crk_set_walk", "crk_set_hsolve",
+           "crk_derivatives", "crk_hsolve", "crk_export_neighbors", "crk_set_lanes", "crk_set_wave_mapping", "crk_set_walk", "crk_set_hsolve",
            "crk_timing_enable", "crk_timing_reset", "crk_timing_read", "crk_adaptive_rows",
            "crk_hnet_features", "crk_hnet_forward", "crk_hnet_train_step",
            "crk_hnet_train_step_noalloc", "crk_hnet_seed",
@@ -120,7 +120,7 @@ def lib():
             "crk_hsolve": ([p, d, d, i32, p, p, p], i32),
             "crk_export_neighbors": ([p, i32, p, p, i64, p], i32),
             "crk_set_lanes": ([p, i32, i32, i32, i32], i32),
-            "crk_set_deriv_mapping": ([p, i32], i32),
+            "crk_set_wave_mapping": ([p, i32, i32, i32, i32], i32),
             "crk_set_walk": ([p, i32, i32, i32], i32),
             "crk_set_hsolve": ([p, i32, i32, i32, d], i32),
             "crk_timing_enable": ([p, i32], i32),
@@ -660,11 +660,12 @@ class Context:
     def set_walk(self, lanes: int = 0, cap: int = 0, level_shift: int = -1):
         self._check(lib().crk_set_walk(self._h, lanes, cap, level_shift), "crk_set_walk")
 
-    def set_deriv_mapping(self, particles_per_wave: int):
-        """Derivative/compatible passes: 16, 32 or 64 particles per wavefront
-        over their concatenated rows, or 0 for set_lanes' der lanes."""
-        self._check(lib().crk_set_deriv_mapping(self._h, int(particles_per_wave)),
-                    "crk_set_deriv_mapping")
+    def set_wave_mapping(self, vol: int = -1, mom: int = -1, grad: int = -1, deriv: int = -1):
+        """Volume / moment / velocity-gradient / derivative passes: 4, 8, 16
+        or 32 particles per wavefront with lanes split by row length, 0 for
+        set_lanes' lanes per particle, -1 to keep."""
+        self._check(lib().crk_set_wave_mapping(self._h, int(vol), int(mom), int(grad), int(deriv)),
+                    "crk_set_wave_mapping")
 
     def set_lanes(self, vol: int = 0, mom: int = 0, grad: int = 0, der: int = 0):
         self._check(lib().crk_set_lanes(self._h, vol, mom, grad, der), "crk_set_lanes")

@@ -1,4 +1,5 @@
-"""Autotuner for the lanes-per-particle of every pass.
+"""Autotuner for the lanes-per-particle of every pass (and the particles
+per wavefront of the derivative pass's balanced mapping).
 
 Each pair pass, the neighbour walk and the smoothing-length iteration split a
 particle's work over a group of G lanes of a wave64 (crk_set_lanes,
@@ -23,7 +24,8 @@ from . import pipeline as pl
 HERE = os.path.dirname(os.path.abspath(__file__))
 TABLE = os.path.join(HERE, "tune_table.json")
 
-DEFAULT = {"walk": 8, "walk_level": 0, "vol": 4, "mom": 1, "grad": 4, "der": 8, "hsolve": 16}
+DEFAULT = {"walk": 8, "walk_level": 0, "vol": 4, "mom": 1, "grad": 4, "der": 8, "vol_wave": 0,
+           "mom_wave": 0, "grad_wave": 0, "der_wave": 8, "hsolve": 16}
 CANDIDATES = {
     "walk": (2, 4, 8, 16),
     "walk_level": (0, 1, 2),
@@ -31,10 +33,15 @@ CANDIDATES = {
     "mom": (1, 2, 4, 8),
     "grad": (2, 4, 8, 16),
     "der": (4, 8, 16, 32),
+    "vol_wave": (0, 4, 8, 16),
+    "mom_wave": (0, 4, 8, 16),
+    "grad_wave": (0, 4, 8, 16),
+    "der_wave": (0, 4, 8, 16),
     "hsolve": (4, 8, 16, 32),
 }
 KERNEL = {"walk": "k_walk", "walk_level": "k_walk", "vol": "k_volume", "mom": "k_moments", "grad": "k_gradv",
-          "der": "k_deriv"}
+          "der": "k_deriv", "vol_wave": "k_volume", "mom_wave": "k_moments", "grad_wave": "k_gradv",
+          "der_wave": "k_deriv"}
 
 
 def key_for(precision: int, pairs_per_particle: float, kind: str = "") -> str:
@@ -51,6 +58,11 @@ def _kind(key: str) -> str:
 
 def apply(ctx: Context, cfg: dict) -> None:
     ctx.set_lanes(cfg["vol"], cfg["mom"], cfg["grad"], cfg["der"])
+    # volume, moment, velocity-gradient and derivative passes: balanced lane
+    # groups of *_wave particles per wave (0: the lanes per particle above);
+    # tables written before the knobs existed take the defaults
+    ctx.set_wave_mapping(*(cfg.get(k, DEFAULT[k]) for k in ("vol_wave", "mom_wave", "grad_wave",
+                                                             "der_wave")))
     ctx.set_walk(cfg["walk"], 0, cfg.get("walk_level", 0))
     ctx.set_hsolve(cfg["hsolve"], 0, 0, 0.0)
 

@@ -112,9 +112,10 @@ struct crk_ctx {
 
     // per-pass tuning: lanes per particle (1..64)
     int G_vol = 4, G_mom = 1, G_grad = 4, G_der = 8;
-    // derivative and compatible passes: particles per wavefront of the
-    // balanced lane-group mapping (4, 8, 16 or 32); 0 = G_der lanes per particle
-    int P_der = 8;
+    // volume, moment, velocity-gradient, derivative (and compatible)
+    // passes: particles per wavefront of the balanced lane-group mapping
+    // (4, 8, 16 or 32); 0 = the G_* lanes per particle above
+    int P_vol = 0, P_mom = 0, P_grad = 0, P_der = 8;
     // neighbour walk: lanes per particle and scratch slots per row
     int G_walk = 8, walk_cap = 192;
     // walked level: the first whose cell side is at least 2^(walk_shift-1) H

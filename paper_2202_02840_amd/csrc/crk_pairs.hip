@@ -703,6 +703,7 @@ struct LaneGroup {
     bool last;   // last lane of the group
 };
 
+// (eb == nullptr: gather rows only)
 template <int P>
 __device__ __forceinline__ LaneGroup lane_group(int64_t i0, int np, int lane,
                                                 const int64_t *__restrict__ goff,
@@ -710,7 +711,9 @@ __device__ __forceinline__ LaneGroup lane_group(int64_t i0, int np, int lane,
                                                 const int32_t *__restrict__ ee) {
     static_assert(P >= 1 && P <= 32, "at most 32 particles per wave");
     // row lengths and their inclusive prefix over the wave's particles
-    const int len = lane < np ? (int)(goff[i0 + lane + 1] - goff[i0 + lane]) + (ee[i0 + lane] - eb[i0 + lane]) : 0;
+    const int len = lane < np ? (int)(goff[i0 + lane + 1] - goff[i0 + lane]) +
+                                    (eb ? ee[i0 + lane] - eb[i0 + lane] : 0)
+                              : 0;
     int cum = len;
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
@@ -844,6 +847,209 @@ __global__ __launch_bounds__(kBlock) void k_deriv_bal(const double4 *__restrict_
             ts_qr[i] = (double)qr;
         }
     }
+}
+
+// Volume pass, balanced lane groups (gather rows only): n_i = W(0, H_i) +
+// sum_j W(r, H_i), the self term taken by the group's first lane.
+template <typename T, int P>
+__global__ __launch_bounds__(kBlock) void k_volume_bal(const double4 *__restrict__ posH,
+                                                       const int64_t *__restrict__ goff,
+                                                       const int32_t *__restrict__ gidx, int64_t n,
+                                                       Box box, double *nsum_out, double *V_out, T *recV) {
+    const int64_t i0 = wave_first(P);
+    if (i0 >= n) return;
+    const int lane = threadIdx.x & 63;
+    const int np = (int)(n - i0 < P ? n - i0 : P);
+    const LaneGroup lg = lane_group<P>(i0, np, lane, goff, nullptr, nullptr);
+    const int64_t i = lg.i;
+    const double4 pi = posH[i];
+    const T invH = (T)(1.0 / pi.w);
+    const T cw = (T)kW * invH * invH * invH;
+    double a[1] = {lg.first == 0 ? (double)cw : 0.0};
+    const int64_t gb = goff[i];
+    const int tot = (int)(goff[i + 1] - gb);
+    const int G = lg.g;
+    int kk = lg.first;
+    int32_t jn = kk < tot ? gidx[gb + kk] : 0;
+    for (; kk < tot; kk += G) {
+        const int32_t j = jn;
+        if (kk + G < tot) jn = gidx[gb + kk + G];
+        const double4 pj = posH[j];
+        T dx, dy, dz;
+        separation(pi, pj, box, dx, dy, dz);
+        const T q = Mth<T>::sqrt(dx * dx + dy * dy + dz * dz) * invH;
+        a[0] += (double)kernel_w(q, cw);
+    }
+    group_scan<double, 1>(lane, lg.key, a);
+    if (lg.last) {
+        if (nsum_out) nsum_out[i] = a[0];
+        V_out[i] = 1.0 / a[0];
+        recV[i] = (T)(1.0 / a[0]);
+    }
+}
+
+// Moment pass, balanced lane groups (gather rows only): the 29 sums of
+// k_moments, assembled into the 40 outputs by the group's last lane.
+template <typename T, int P>
+__global__ __launch_bounds__(kBlock) void k_moments_bal(const double4 *__restrict__ posH,
+                                                        const int64_t *__restrict__ goff,
+                                                        const int32_t *__restrict__ gidx,
+                                                        const T *__restrict__ recV, int64_t n, Box box,
+                                                        double *m0, double *m1, double *m2, double *gm0,
+                                                        double *gm1, double *gm2) {
+    const int64_t i0 = wave_first(P);
+    if (i0 >= n) return;
+    const int lane = threadIdx.x & 63;
+    const int np = (int)(n - i0 < P ? n - i0 : P);
+    const LaneGroup lg = lane_group<P>(i0, np, lane, goff, nullptr, nullptr);
+    const int64_t i = lg.i;
+    // sums: 0 m0 | 1-3 m1 | 4-9 m2 | 10-12 gm0 | 13-18 Q2 | 19-28 Q3
+    double a[29] = {};
+    const double4 pi = posH[i];
+    const T invH = (T)(1.0 / pi.w);
+    const T invH2 = invH * invH;
+    const T cw = (T)kW * invH2 * invH;
+    const T cg = (T)kG * invH2 * invH2 * invH;
+    if (lg.first == 0) a[0] = (double)(recV[i] * cw);   // self pair: d = 0, so m0 only
+    const int64_t gb = goff[i];
+    const int tot = (int)(goff[i + 1] - gb);
+    const int G = lg.g;
+    int kk = lg.first;
+    int32_t jn = kk < tot ? gidx[gb + kk] : 0;
+    for (; kk < tot; kk += G) {
+        const int32_t j = jn;
+        if (kk + G < tot) jn = gidx[gb + kk + G];
+        const double4 pj = posH[j];
+        const T Vj = recV[j];
+        T d[3];
+        separation(pi, pj, box, d[0], d[1], d[2]);
+        const T q = Mth<T>::sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]) * invH;
+        T w, gf;
+        kernel_wg(q, cw, cg, w, gf);
+        const T t = Vj * w, u = Vj * gf;
+        a[0] += (double)t;
+        T dd[6];
+#pragma unroll
+        for (int x = 0; x < 3; x++) {
+            a[1 + x] += (double)(t * d[x]);
+            a[10 + x] += (double)(u * d[x]);
+#pragma unroll
+            for (int y = x; y < 3; y++) dd[kSym2[x][y]] = d[x] * d[y];
+        }
+#pragma unroll
+        for (int e = 0; e < 6; e++) {
+            a[4 + e] += (double)(t * dd[e]);
+            a[13 + e] += (double)(u * dd[e]);
+        }
+#pragma unroll
+        for (int x = 0; x < 3; x++)
+#pragma unroll
+            for (int y = x; y < 3; y++)
+#pragma unroll
+                for (int z = y; z < 3; z++) a[19 + kSym3[x][y][z]] += (double)(u * dd[kSym2[x][y]] * d[z]);
+    }
+    group_scan<double, 29>(lane, lg.key, a);
+    if (lg.last) {
+        const double p0 = a[0];
+        const double p1[3] = {a[1], a[2], a[3]};
+        m0[i] = p0;
+#pragma unroll
+        for (int x = 0; x < 3; x++) {
+            m1[x * n + i] = p1[x];
+            gm0[x * n + i] = a[10 + x];
+        }
+#pragma unroll
+        for (int e = 0; e < 6; e++) m2[e * n + i] = a[4 + e];
+#pragma unroll
+        for (int x = 0; x < 3; x++)
+#pragma unroll
+            for (int c = 0; c < 3; c++) gm1[(x * 3 + c) * n + i] = a[13 + kSym2[x][c]] + (x == c ? p0 : 0.0);
+        int s = 0;
+#pragma unroll
+        for (int x = 0; x < 3; x++)
+#pragma unroll
+            for (int y = x; y < 3; y++, s++)
+#pragma unroll
+                for (int c = 0; c < 3; c++)
+                    gm2[(s * 3 + c) * n + i] = a[19 + kSym3[x][y][c]] + (x == c ? p1[y] : 0.0) +
+                                               (y == c ? p1[x] : 0.0);
+    }
+}
+
+// Velocity gradient, balanced lane groups (P particles per wave, gather
+// rows only). i's RK template is regrouped once per lane as in the
+// derivative pass: grad W^R_ij = pw (U + M d) + Ag c pg d. Rows with
+// skip[i] set are left to the FP64 launch.
+template <typename T, int P>
+__global__ __launch_bounds__(kBlock) void k_gradv_bal(const double4 *__restrict__ posH,
+                                                      const int64_t *__restrict__ goff,
+                                                      const int32_t *__restrict__ gidx,
+                                                      const typename std::conditional<sizeof(T) == 4, float4, double4>::type *__restrict__ rec6,
+                                                      const double *__restrict__ A, const double *__restrict__ B,
+                                                      const double *__restrict__ gA,
+                                                      const double *__restrict__ gB, int64_t n, Box box,
+                                                      const int32_t *__restrict__ skip, double *gradv) {
+    const int64_t i0 = wave_first(P);
+    if (i0 >= n) return;   // whole waves leave together
+    const int lane = threadIdx.x & 63;
+    const int np = (int)(n - i0 < P ? n - i0 : P);
+    const LaneGroup lg = lane_group<P>(i0, np, lane, goff, nullptr, nullptr);
+    const int64_t i = lg.i;
+    const bool run = !(skip && skip[i]);
+    // i's template
+    const double4 pi = posH[i];
+    const double ihd = 1.0 / pi.w, cwd = kW * ihd * ihd * ihd;
+    const double Ad = A[i];
+    double Bd[3], gAd[3];
+#pragma unroll
+    for (int x = 0; x < 3; x++) {
+        Bd[x] = B[x * n + i];
+        gAd[x] = gA[x * n + i];
+    }
+    T U[3], M[9], Bt[3];
+#pragma unroll
+    for (int g = 0; g < 3; g++) {
+        Bt[g] = (T)Bd[g];
+        U[g] = (T)(cwd * (gAd[g] + Ad * Bd[g]));
+#pragma unroll
+        for (int a = 0; a < 3; a++) M[g * 3 + a] = (T)(cwd * (gAd[g] * Bd[a] + Ad * gB[(a * 3 + g) * n + i]));
+    }
+    const T Ag = (T)(Ad * kG * ihd * ihd * ihd * ihd * ihd);
+    const T ih = (T)ihd;
+    const auto ri = rec6[i];
+    const T vi[3] = {(T)ri.x, (T)ri.y, (T)ri.z};
+    double a[9] = {};
+    const int64_t gb = goff[i];
+    const int tot = run ? (int)(goff[i + 1] - gb) : 0;
+    const int G = lg.g;
+    int kk = lg.first;
+    int32_t jn = kk < tot ? gidx[gb + kk] : 0;
+    for (; kk < tot; kk += G) {
+        const int32_t j = jn;
+        if (kk + G < tot) jn = gidx[gb + kk + G];
+        const double4 pj = posH[j];
+        const auto rj = rec6[j];
+        T d[3];
+        separation(pi, pj, box, d[0], d[1], d[2]);
+        const T r = Mth<T>::sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+        T pw, pg;
+        kfac(r * ih, pw, pg);
+        const T k = Ag * ((T)1 + (Bt[0] * d[0] + Bt[1] * d[1] + Bt[2] * d[2])) * pg;
+        T Gr[3];
+#pragma unroll
+        for (int g = 0; g < 3; g++)
+            Gr[g] = pw * (U[g] + (M[g * 3 + 0] * d[0] + M[g * 3 + 1] * d[1] + M[g * 3 + 2] * d[2])) + k * d[g];
+        // -V_j (v_i - v_j) (x) grad W^R_ij
+        const T w[3] = {((T)rj.x - vi[0]) * (T)rj.w, ((T)rj.y - vi[1]) * (T)rj.w, ((T)rj.z - vi[2]) * (T)rj.w};
+#pragma unroll
+        for (int x = 0; x < 3; x++)
+#pragma unroll
+            for (int y = 0; y < 3; y++) a[x * 3 + y] += (double)(w[x] * Gr[y]);
+    }
+    group_scan<double, 9>(lane, lg.key, a);
+    if (lg.last && run)
+#pragma unroll
+        for (int q = 0; q < 9; q++) gradv[q * n + i] = a[q];
 }
 
 // Derivative pass, G lanes per particle striding over N_s(i) (the gather row,
@@ -1294,6 +1500,41 @@ inline unsigned pblocks(int64_t n, int P) {
     return (unsigned)(((n + P - 1) / P + kBlock / 64 - 1) / (kBlock / 64));
 }
 
+// volume then (optionally) moment pass in type T, with the lane mapping of
+// the context (balanced groups of P particles per wave, or G lanes each)
+template <typename T>
+crk_status volume_moments(crk_ctx *c, const double4 *posH, const int64_t *goff, const int32_t *gidx,
+                          int64_t n, Box box, double *nsum, double *V, T *rv, bool want_m, double *m0,
+                          double *m1, double *m2, double *gm0, double *gm1, double *gm2) {
+    const int Gv = c->G_vol, Gm = c->G_mom, Pv = c->P_vol, Pm = c->P_mom;
+    {
+        KTimer kt_(c, "k_volume");
+        if (Pv > 0) {
+#define L_VOL(PP) k_volume_bal<T, PP><<<pblocks(n, PP), kBlock, 0, c->stream>>>(posH, goff, gidx, n, box, nsum, V, rv)
+            CRK_DISPATCH_P(Pv, L_VOL);
+#undef L_VOL
+        } else {
+#define L_VOL(GG) k_volume<T, GG><<<gblocks(n, GG), kBlock, 0, c->stream>>>(posH, goff, gidx, n, box, nsum, V, rv)
+            CRK_DISPATCH_G(Gv, L_VOL);
+#undef L_VOL
+        }
+    }
+    if (want_m) {
+        KTimer kt_(c, "k_moments");
+        if (Pm > 0) {
+#define L_MOM(PP) k_moments_bal<T, PP><<<pblocks(n, PP), kBlock, 0, c->stream>>>(posH, goff, gidx, rv, n, box, m0, m1, m2, gm0, gm1, gm2)
+            CRK_DISPATCH_P(Pm, L_MOM);
+#undef L_MOM
+        } else {
+#define L_MOM(GG) k_moments<T, GG><<<gblocks(n, GG), kBlock, 0, c->stream>>>(posH, goff, gidx, rv, n, box, m0, m1, m2, gm0, gm1, gm2)
+            CRK_DISPATCH_G(Gm, L_MOM);
+#undef L_MOM
+        }
+    }
+    CRK_HIP(c, hipGetLastError());
+    return CRK_OK;
+}
+
 bool valid_prec(int p) { return p == CRK_FP64 || p == CRK_MIXED || p == CRK_MIXED_ADAPT; }
 
 }  // namespace
@@ -1317,12 +1558,16 @@ crk_status crk_set_walk(crk_ctx *c, int32_t lanes, int32_t cap, int32_t level_sh
     return CRK_OK;
 }
 
-crk_status crk_set_deriv_mapping(crk_ctx *c, int32_t particles_per_wave) {
+crk_status crk_set_wave_mapping(crk_ctx *c, int32_t vol_ppw, int32_t mom_ppw, int32_t grad_ppw,
+                                int32_t deriv_ppw) {
     if (!c) return CRK_ERR_INVALID_ARG;
-    const int p = particles_per_wave;
-    if (p != 0 && p != 4 && p != 8 && p != 16 && p != 32)
-        return set_err(c, CRK_ERR_INVALID_ARG, "particles per wave must be 0, 4, 8, 16 or 32");
-    c->P_der = p;
+    for (int p : {vol_ppw, mom_ppw, grad_ppw, deriv_ppw})
+        if (p != -1 && p != 0 && p != 4 && p != 8 && p != 16 && p != 32)
+            return set_err(c, CRK_ERR_INVALID_ARG, "particles per wave must be -1, 0, 4, 8, 16 or 32");
+    if (vol_ppw >= 0) c->P_vol = vol_ppw;
+    if (mom_ppw >= 0) c->P_mom = mom_ppw;
+    if (grad_ppw >= 0) c->P_grad = grad_ppw;
+    if (deriv_ppw >= 0) c->P_der = deriv_ppw;
     return CRK_OK;
 }
 
@@ -1356,39 +1601,12 @@ crk_status crk_moments(crk_ctx *c, const crk_params *p, double *nsum, double *V,
     const int32_t *gidx = (const int32_t *)c->gidx.p;
     bool f32 = p->precision == CRK_MIXED;
     CRK_TRY(ensure(c, c->recV, (size_t)n * (f32 ? 4 : 8)));
-    int Gv = c->G_vol, Gm = c->G_mom;
     if (f32) {
         float *rv = (float *)c->recV.p;
-#define L_VOL(GG) k_volume<float, GG><<<gblocks(n, GG), kBlock, 0, c->stream>>>(posH, goff, gidx, n, box, nsum, V, rv)
-        {
-            KTimer kt_(c, "k_volume");
-            CRK_DISPATCH_G(Gv, L_VOL);
-        }
-#undef L_VOL
-        if (want_m) {
-#define L_MOM(GG) k_moments<float, GG><<<gblocks(n, GG), kBlock, 0, c->stream>>>(posH, goff, gidx, rv, n, box, m0, m1, m2, gm0, gm1, gm2)
-            {
-                KTimer kt_(c, "k_moments");
-                CRK_DISPATCH_G(Gm, L_MOM);
-            }
-#undef L_MOM
-        }
+        CRK_TRY(volume_moments<float>(c, posH, goff, gidx, n, box, nsum, V, rv, want_m, m0, m1, m2, gm0, gm1, gm2));
     } else {
         double *rv = (double *)c->recV.p;
-#define L_VOL(GG) k_volume<double, GG><<<gblocks(n, GG), kBlock, 0, c->stream>>>(posH, goff, gidx, n, box, nsum, V, rv)
-        {
-            KTimer kt_(c, "k_volume");
-            CRK_DISPATCH_G(Gv, L_VOL);
-        }
-#undef L_VOL
-        if (want_m) {
-#define L_MOM(GG) k_moments<double, GG><<<gblocks(n, GG), kBlock, 0, c->stream>>>(posH, goff, gidx, rv, n, box, m0, m1, m2, gm0, gm1, gm2)
-            {
-                KTimer kt_(c, "k_moments");
-                CRK_DISPATCH_G(Gm, L_MOM);
-            }
-#undef L_MOM
-        }
+        CRK_TRY(volume_moments<double>(c, posH, goff, gidx, n, box, nsum, V, rv, want_m, m0, m1, m2, gm0, gm1, gm2));
     }
     CRK_HIP(c, hipGetLastError());
     c->have_V = 1;
@@ -1512,7 +1730,7 @@ crk_status crk_derivatives(crk_ctx *c, const crk_params *p, const double *v, con
     CRK_TRY(ensure(c, c->misc, 256));
     int *bad = (int *)c->misc.p + 2;
     CRK_TRY(zero_async(c, bad, 1));
-    int Gg = c->G_grad, Gd = c->G_der, Pd = c->P_der;
+    int Gg = c->G_grad, Gd = c->G_der, Pd = c->P_der, Pg = c->P_grad;
 
     // adaptive mode: FP64 rows for ill-conditioned RK templates
     const bool gm = c->graph_mode != 0;
@@ -1538,12 +1756,18 @@ crk_status crk_derivatives(crk_ctx *c, const crk_params *p, const double *v, con
             k_pack6_f<<<nblocks(n), kBlock, 0, c->stream>>>(n, v, V, r6);
             if (adapt) k_pack6_d<<<nblocks(n), kBlock, 0, c->stream>>>(n, v, V, r6d);
         }
-#define L_GV(GG) k_gradv<float, GG><<<gblocks(n, GG), kBlock, 0, c->stream>>>(posH, goff, gidx, r6, A, B, gA, gB, n, box, nullptr, 0, nullptr, flag, gradv)
         {
             KTimer kt_(c, "k_gradv");
-            CRK_DISPATCH_G(Gg, L_GV);
-        }
+            if (Pg > 0) {
+#define L_GV(PP) k_gradv_bal<float, PP><<<pblocks(n, PP), kBlock, 0, c->stream>>>(posH, goff, gidx, r6, A, B, gA, gB, n, box, flag, gradv)
+                CRK_DISPATCH_P(Pg, L_GV);
 #undef L_GV
+            } else {
+#define L_GV(GG) k_gradv<float, GG><<<gblocks(n, GG), kBlock, 0, c->stream>>>(posH, goff, gidx, r6, A, B, gA, gB, n, box, nullptr, 0, nullptr, flag, gradv)
+                CRK_DISPATCH_G(Gg, L_GV);
+#undef L_GV
+            }
+        }
         if (adapt && nflag > 0) {
 #define L_GV(GG) k_gradv<double, GG><<<fix_blocks(nflag, GG, gm), kBlock, 0, c->stream>>>(posH, goff, gidx, r6d, A, B, gA, gB, n, box, flist, nflag, nflag_dev, nullptr, gradv)
             KTimer kt_(c, "k_gradv_fix");
@@ -1581,12 +1805,18 @@ crk_status crk_derivatives(crk_ctx *c, const crk_params *p, const double *v, con
             KTimer kt_(c, "k_pack");
             k_pack6_d<<<nblocks(n), kBlock, 0, c->stream>>>(n, v, V, r6);
         }
-#define L_GV(GG) k_gradv<double, GG><<<gblocks(n, GG), kBlock, 0, c->stream>>>(posH, goff, gidx, r6, A, B, gA, gB, n, box, nullptr, 0, nullptr, nullptr, gradv)
         {
             KTimer kt_(c, "k_gradv");
-            CRK_DISPATCH_G(Gg, L_GV);
-        }
+            if (Pg > 0) {
+#define L_GV(PP) k_gradv_bal<double, PP><<<pblocks(n, PP), kBlock, 0, c->stream>>>(posH, goff, gidx, r6, A, B, gA, gB, n, box, nullptr, gradv)
+                CRK_DISPATCH_P(Pg, L_GV);
 #undef L_GV
+            } else {
+#define L_GV(GG) k_gradv<double, GG><<<gblocks(n, GG), kBlock, 0, c->stream>>>(posH, goff, gidx, r6, A, B, gA, gB, n, box, nullptr, 0, nullptr, nullptr, gradv)
+                CRK_DISPATCH_G(Gg, L_GV);
+#undef L_GV
+            }
+        }
         {
             KTimer kt_(c, "k_pack");
             k_pack8<double4, double><<<nblocks(n), kBlock, 0, c->stream>>>(n, posH, v, m, u, rho, V, A, B, gA, gB, gradv, dp, nullptr, r7, nullptr, bad);

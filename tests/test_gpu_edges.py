@@ -208,3 +208,27 @@ def test_workspace_bytes_reports_what_the_context_holds():
     # the lists alone hold 4 B per ordered pair
     assert after_small > before and after_small >= 4 * 64 * small.n
     assert after_big > after_small
+
+
+@pytest.mark.parametrize("prec", [CRK_FP64, CRK_MIXED_ADAPT])
+def test_workspace_estimate_bounds_a_step(prec):
+    # the bound, computed before any call from n and the pairs per particle,
+    # holds what a step, the h iteration, the compatible pass, the time-step
+    # terms and a leaf build leave in the context
+    from paper_2202_02840_amd._lib import WS_COMPAT, WS_HSOLVE, WS_LEAVES, WS_TIMESTEP
+    ps = ci.lognormal_box(32, sigma=1.5, seed=933)
+    ctx = Context(0)
+    import oracle
+    ref_pairs = oracle.neighbors(ps.x, ps.y, ps.z, ps.H, ps.L, True, 1)[0][-1]
+    uses = WS_HSOLVE | WS_COMPAT | WS_TIMESTEP | WS_LEAVES
+    bound = ctx.workspace_estimate(ps.n, ref_pairs / ps.n, prec, uses)
+    dev = pl.upload(ps)
+    prm = pl.params_for(ps, 64.0, prec)
+    out = pl.step(ctx, dev, prm, timestep=True, compat_dt=1e-3)
+    Hs = ctx.permute(dev["H"], True)
+    ctx.hsolve(64.0, Hs)
+    ctx.build_leaves(dev["x"], dev["y"], dev["z"], dev["H"], prm)
+    held = ctx.workspace_bytes()
+    print(f"[case] n={ps.n} pairs={out['n_pairs']} held={held} bound={bound}", flush=True)
+    assert out["n_pairs"] == ref_pairs
+    assert held <= bound

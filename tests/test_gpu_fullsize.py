@@ -91,7 +91,8 @@ def test_benchmark_workload_sampled_parity():
 def test_largest_set_sampled_parity_and_h_iteration():
     ps = ci.clustered_clump_box(256)
     g = np.random.default_rng(2025)
-    T = np.sort(g.choice(ps.n, 1000, replace=False))
+    # the 10^4-particle subset the full-size workload names
+    T = np.sort(g.choice(ps.n, 10000, replace=False))
     print(f"[case] lognormal+clumps 256^3 n={ps.n}, sample {T.size}", flush=True)
     # every pass at the generator's supports
     ref = oracle.spot_check(ps, T, oracle.params(64.0))

@@ -92,6 +92,8 @@ def test_leaf_passes_match_oracle(name, prec, tol):
 def test_leaf_batch_matches_oracle_per_box():
     boxes = [ci.lognormal_box(9, sigma=1.5, seed=210), ci.lattice_box(11, seed=211),
              ci.lognormal_box(6, sigma=1.0, seed=212)]
+    for b in boxes:
+        b.rho = None   # the concatenated set takes rho = m / V for every box
     ps, off = pl.concat(boxes)
     print(f"[case] batch n={ps.n} boxes={len(boxes)}", flush=True)
     ctx, perm, loff, res = leaf_step(ps, CRK_FP64, box_offsets=off)
