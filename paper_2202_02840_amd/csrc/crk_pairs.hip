@@ -106,6 +106,17 @@ __device__ __forceinline__ void kernel_wg(T q, T cw, T cg, T &w, T &gf) {
     gf = cg * ((T)1 + (T)5 * q) * s5;
 }
 
+// Wendland C4 radial factors with unit support, eq. (C4): s = max(1 - q, 0),
+// pw = s^6 (1 + 6q + 35q^2/3), pg = (1 + 5q) s^5
+template <typename T>
+__device__ __forceinline__ void kfac(T q, T &pw, T &pg) {
+    const T s = q < (T)1 ? (T)1 - q : (T)0;
+    const T s2 = s * s;
+    const T s5 = s2 * s2 * s;
+    pw = s5 * s * ((T)1 + q * ((T)6 + q * (T)(35.0 / 3.0)));
+    pg = ((T)1 + (T)5 * q) * s5;
+}
+
 template <typename T>
 __device__ __forceinline__ T kernel_w(T q, T cw) {
     T s = q < (T)1 ? (T)1 - q : (T)0;
@@ -333,8 +344,17 @@ __global__ __launch_bounds__(kBlock) void k_corrections(int64_t n, const double 
 
 // ------------------------------------------------------------- S6 grad v
 // RK gradient template of eq. (gRK) for the ordered pair (i, j) with i's
-// coefficients: c = 1 + B.d, (gradB^T d)_g = sum_a d_a dB_a/dx_g,
+// coefficients, c = 1 + B.d, (gradB^T d)_g = sum_a d_a dB_a/dx_g:
 //   grad W^R_g = w (dA_g c + A ((gradB^T d)_g + B_g)) + A c gf d_g.
+// The FP64 pass evaluates it term by term as written. It is linear in the
+// kernel's radial factors w = kW H^-3 pw(q) and gf = kG H^-5 pg(q), so the
+// FP32 pass groups it per particle:
+//   grad W^R = pw (U + M d) + Ag c pg d,
+//   U_g = kW H^-3 (dA_g + A B_g), M_ga = kW H^-3 (dA_g B_a + A dB_a/dx_g),
+//   Ag = A kG H^-5,
+// the same sum with fewer operations per pair (its rounding differs, which
+// the FP32 pass's error budget absorbs; the FP64 pass keeps the order of
+// the written form, whose rounding the ill-conditioned sets show).
 template <typename T>
 struct Coef {
     T A, B[3], gA[3], gB[9];
@@ -376,47 +396,99 @@ __global__ __launch_bounds__(kBlock) void k_gradv(const double4 *__restrict__ po
     } else if (g < n && !(skip && skip[g])) {
         i = g;
     }
-    Acc<T> a[9];
+    // FP64 sums of the pair terms (in the FP32 pass a conversion and an add
+    // per term, cheaper than a compensated FP32 sum on this VALU, with FP64
+    // vector adds at full rate)
+    Acc<double> a[9];
     if (i >= 0) {
-        double4 pi = posH[i];
-        T invH = (T)(1.0 / pi.w);
-        T invH2 = invH * invH;
-        T cw = (T)kW * invH2 * invH;
-        T cg = (T)kG * invH2 * invH2 * invH;
-        Coef<T> k;
-        k.A = (T)A[i];
-#pragma unroll
-        for (int x = 0; x < 3; x++) {
-            k.B[x] = (T)B[x * n + i];
-            k.gA[x] = (T)gA[x * n + i];
-        }
-#pragma unroll
-        for (int s = 0; s < 9; s++) k.gB[s] = (T)gB[s * n + i];
+        const double4 pi = posH[i];
         auto ri = rec6[i];
-        T vi[3] = {ri.x, ri.y, ri.z};
-        int64_t b = goff[i];
-        int cnt = (int)(goff[i + 1] - b);
-        int32_t jn = l < cnt ? gidx[b + l] : 0;
-        for (int kk = l; kk < cnt; kk += G) {
-            const int32_t j = jn;
-            if (kk + G < cnt) jn = gidx[b + kk + G];
-            double4 pj = posH[j];
-            auto rj = rec6[j];
-            T d[3];
-            separation(pi, pj, box, d[0], d[1], d[2]);
-            T q = Mth<T>::sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]) * invH;
-            T w, gf;
-            kernel_wg(q, cw, cg, w, gf);
-            T G3[3];
-            rk_grad(k, d, w, gf, G3);
-            T dv[3] = {(vi[0] - (T)rj.x) * rj.w, (vi[1] - (T)rj.y) * rj.w, (vi[2] - (T)rj.z) * rj.w};
+        const T vi[3] = {ri.x, ri.y, ri.z};
+        const int64_t b = goff[i];
+        const int cnt = (int)(goff[i + 1] - b);
+        if constexpr (sizeof(T) == 8) {
+            // eq. (gRK) term by term
+            const T invH = (T)(1.0 / pi.w);
+            const T invH2 = invH * invH;
+            const T cw = (T)kW * invH2 * invH;
+            const T cg = (T)kG * invH2 * invH2 * invH;
+            Coef<T> k;
+            k.A = (T)A[i];
 #pragma unroll
-            for (int x = 0; x < 3; x++)
+            for (int x = 0; x < 3; x++) {
+                k.B[x] = (T)B[x * n + i];
+                k.gA[x] = (T)gA[x * n + i];
+            }
 #pragma unroll
-                for (int y = 0; y < 3; y++) a[x * 3 + y].add(-dv[x] * G3[y]);
+            for (int s = 0; s < 9; s++) k.gB[s] = (T)gB[s * n + i];
+            int32_t jn = l < cnt ? gidx[b + l] : 0;
+            for (int kk = l; kk < cnt; kk += G) {
+                const int32_t j = jn;
+                if (kk + G < cnt) jn = gidx[b + kk + G];
+                const double4 pj = posH[j];
+                auto rj = rec6[j];
+                T d[3];
+                separation(pi, pj, box, d[0], d[1], d[2]);
+                const T q = Mth<T>::sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]) * invH;
+                T w, gf;
+                kernel_wg(q, cw, cg, w, gf);
+                T G3[3];
+                rk_grad(k, d, w, gf, G3);
+                const T dv[3] = {(vi[0] - (T)rj.x) * rj.w, (vi[1] - (T)rj.y) * rj.w, (vi[2] - (T)rj.z) * rj.w};
+#pragma unroll
+                for (int x = 0; x < 3; x++)
+#pragma unroll
+                    for (int y = 0; y < 3; y++) a[x * 3 + y].add(-dv[x] * G3[y]);
+            }
+        } else {
+            // the regrouped template: grad W^R_ij = pw (U + M d) + Ag c pg d
+            const double ihd = 1.0 / pi.w, cwd = kW * ihd * ihd * ihd;
+            const double Ad = A[i];
+            double Bd[3], gAd[3];
+#pragma unroll
+            for (int x = 0; x < 3; x++) {
+                Bd[x] = B[x * n + i];
+                gAd[x] = gA[x * n + i];
+            }
+            T U[3], M[9], Bt[3];
+#pragma unroll
+            for (int g = 0; g < 3; g++) {
+                Bt[g] = (T)Bd[g];
+                U[g] = (T)(cwd * (gAd[g] + Ad * Bd[g]));
+#pragma unroll
+                for (int c = 0; c < 3; c++)
+                    M[g * 3 + c] = (T)(cwd * (gAd[g] * Bd[c] + Ad * gB[(c * 3 + g) * n + i]));
+            }
+            const T Ag = (T)(Ad * kG * ihd * ihd * ihd * ihd * ihd);
+            const T ih = (T)ihd;
+            int32_t jn = l < cnt ? gidx[b + l] : 0;
+            for (int kk = l; kk < cnt; kk += G) {
+                const int32_t j = jn;
+                if (kk + G < cnt) jn = gidx[b + kk + G];
+                const double4 pj = posH[j];
+                auto rj = rec6[j];
+                T d[3];
+                separation(pi, pj, box, d[0], d[1], d[2]);
+                const T r = Mth<T>::sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+                T pw, pg;
+                kfac(r * ih, pw, pg);
+                const T kc = Ag * ((T)1 + (Bt[0] * d[0] + Bt[1] * d[1] + Bt[2] * d[2])) * pg;
+                T G3[3];
+#pragma unroll
+                for (int g = 0; g < 3; g++)
+                    G3[g] = pw * (U[g] + (M[g * 3 + 0] * d[0] + M[g * 3 + 1] * d[1] + M[g * 3 + 2] * d[2])) +
+                            kc * d[g];
+                // -V_j (v_i - v_j) (x) grad W^R_ij
+                const T w[3] = {((T)rj.x - vi[0]) * (T)rj.w, ((T)rj.y - vi[1]) * (T)rj.w,
+                                ((T)rj.z - vi[2]) * (T)rj.w};
+#pragma unroll
+                for (int x = 0; x < 3; x++)
+#pragma unroll
+                    for (int y = 0; y < 3; y++) a[x * 3 + y].add((double)(w[x] * G3[y]));
+            }
         }
     }
-    group_reduce<T, G, 9>(a);
+    group_reduce<double, G, 9>(a);
     if (i >= 0 && l == 0)
 #pragma unroll
         for (int s = 0; s < 9; s++) gradv[s * n + i] = a[s].value();
@@ -599,17 +671,6 @@ struct PairK {
 template <typename T>
 __device__ __forceinline__ PairK<T> pair_k(const DerivPrm &p) {
     return PairK<T>{(T)p.Cq, (T)p.eta_c, (T)p.inv_eta_f, (T)p.adot, (T)p.inv_a};
-}
-
-// Wendland C4 radial factors with unit support, eq. (C4): s = max(1 - q, 0),
-// pw = s^6 (1 + 6q + 35q^2/3), pg = (1 + 5q) s^5
-template <typename T>
-__device__ __forceinline__ void kfac(T q, T &pw, T &pg) {
-    const T s = q < (T)1 ? (T)1 - q : (T)0;
-    const T s2 = s * s;
-    const T s5 = s2 * s2 * s;
-    pw = s5 * s * ((T)1 + q * ((T)6 + q * (T)(35.0 / 3.0)));
-    pg = ((T)1 + (T)5 * q) * s5;
 }
 
 // One ordered pair (i = a, j = b) of eqs. (mom) and (eng) with P -> P + Q:
