@@ -217,7 +217,7 @@ static std::vector<crk::Buf *> ctx_buffers(crk_ctx *c) {
                        &c->hnet_part, &c->hnet_feat, &c->hs_list, &c->hs_state, &c->hs_pos,
                        &c->hs_iters, &c->hs_pool, &c->hs_rows, &c->hs_rcnt, &c->hs_R, &c->boff,
                        &c->sv, &c->sm, &c->su, &c->srho, &c->gstat, &c->gboff,
-                       &c->ecnt, &c->efill, &c->eoff, &c->etmp, &c->rq, &c->rsk, &c->rla, &c->rlb, &c->rside,
+                       &c->ecnt, &c->efill, &c->eoff, &c->etmp, &c->longs, &c->rq, &c->rsk, &c->rla, &c->rlb, &c->rside,
                        &c->rpnode, &c->rscan, &c->rnode, &c->rtab, &c->rbox, &c->rpoff, &c->rpart, &c->ts_vs, &c->ts_qr, &c->ce, &c->ced, &c->vstep};
 }
 
@@ -262,7 +262,10 @@ crk_status crk_workspace_estimate(const crk_ctx *c, int64_t n, int32_t nboxes,
         (precision != CRK_FP64 && precision != CRK_MIXED && precision != CRK_MIXED_ADAPT))
         return CRK_ERR_INVALID_ARG;
     const double N = (double)n, P = N * pairs_per_particle;
-    const int walk_cap = c ? c->walk_cap : 192, hs_cap = c ? c->hs_cap : 320;
+    // the walk's row slots: the set cap, or the adaptive one for rows as long
+    // as the pairs per particle (gather rows are never longer)
+    const int walk_cap = std::max(c ? c->walk_cap : 192, crk::walk_cap_for(N * pairs_per_particle, N)),
+              hs_cap = c ? c->hs_cap : 320;
     double t = 0.0;
     // build (crk_build_cells, any use): checks, sort, tables, lists
     const double nblk = std::min(std::ceil(N / 256.0), 1024.0);
@@ -276,7 +279,7 @@ crk_status crk_workspace_estimate(const crk_ctx *c, int64_t n, int32_t nboxes,
     const double ntab = (std::pow(8.0, bits + 1) - 1.0) / 7.0 * nboxes;
     t += 2 * held(4.0 * ntab);
     t += held(4.0 * N) + 2 * held(8.0 * (N + 1.0)) + 2 * held(4.0 * N);   // counts, offsets
-    t += held(4.0 * N * walk_cap);                                        // walk rows
+    t += held(4.0 * N * walk_cap) + held(4.0 * (N + 1.0));                // walk rows, long rows
     t += held(4.0 * P) + 2 * held(4.0 * 0.5 * P) + 2 * held(4.0 * N);    // N_g rows, extras (E <= P/2)
     // passes
     const bool f64 = precision == CRK_FP64, adapt = precision == CRK_MIXED_ADAPT;

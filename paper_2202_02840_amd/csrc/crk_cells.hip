@@ -286,11 +286,30 @@ __device__ __forceinline__ void walk_row(const double4 *__restrict__ posH, int64
 // Flattened form of the same walk. The cells of a wavefront's groups hold
 // different numbers of particles, so a cell-by-cell loop keeps most lanes
 // idle; here a group first lists its non-empty, non-skipped cells as ranges
-// of sorted particles (in walk order, up to flat_ranges<G>() at a time, in
-// LDS, each with the image shift of its particles) and
-// then takes the concatenated candidates G at a time across cell
-// boundaries. The candidate order, hence every row, is the same as the
-// cell-by-cell walk's.
+// of sorted particles (in walk order, up to walk_ranges<G>() at a time, in
+// LDS, each with the code of its periodic image shift) and then takes the
+// concatenated candidates G at a time across cell boundaries. The candidate
+// order, hence every row, is the same as the cell-by-cell walk's.
+//
+// The group first fills its axis tables (fill_axes); a listed cell then
+// costs three table reads, and its range carries the one-byte code of its
+// image shift (the 27 shift triples are a table of the block).
+
+// cell ranges a group lists at a time: four steps of G cells, at most 64
+template <int G>
+__host__ __device__ constexpr int walk_ranges() {
+    return 4 * G > 64 ? 64 : 4 * G;
+}
+
+// the 27 image shift triples (dx, dy, dz) by code cx + 3 cy + 9 cz
+__device__ __forceinline__ void fill_shifts(double (*sh)[3], double L) {
+    const int c = threadIdx.x;
+    if (c < 27) {
+        const int q[3] = {c % 3, (c / 3) % 3, c / 9};
+#pragma unroll
+        for (int a = 0; a < 3; a++) sh[c][a] = q[a] == 1 ? L : (q[a] == 2 ? -L : 0.0);
+    }
+}
 
 template <int G, bool DIRECT, bool CULL>
 __device__ __forceinline__ void walk_row_flat(const double4 *__restrict__ posH, int64_t i,
@@ -302,40 +321,31 @@ __device__ __forceinline__ void walk_row_flat(const double4 *__restrict__ posH, 
                                               int32_t *gidx, int32_t *rcnt,
                                               const int64_t *__restrict__ eoff, int32_t *efill,
                                               int32_t *etmp, int32_t &cg, int32_t *sb, int32_t *sc,
-                                              double *sx) {
+                                              uint8_t *scode, AxisTab &tab, const double (*shifts)[3]) {
+    constexpr int NR = walk_ranges<G>();
     const double H2 = pi.w * pi.w;
-    const double L = v.L;
     const int ncell = mx * my * mz;
-    // cell index -> (a, b, e) without integer division: the quotients are
-    // taken in FP64, exact for these small integers
-    const double inv_mx = 1.0 / (double)mx, inv_my = 1.0 / (double)my;
+    // 1. axis tables
+    fill_axes<G, CULL, false>(tab, pi, l, lx, ly, lz, mx, my, mz, nck, cs, v.L);
+    const uint32_t dx_ = div16(mx), dy_ = div16(my);
     int c0 = 0;
     while (c0 < ncell) {
-        // 1. list up to flat_ranges<G>() non-empty cells, G cells per step
+        // 2. list up to NR non-empty cells, G cells per step
         int nr = 0, cum = 0;
-        while (c0 < ncell && nr + G <= flat_ranges<G>()) {
+        while (c0 < ncell && nr + G <= NR) {
             const int cidx = c0 + l;
-            int jb = 0, len = 0;
-            double cx = 0.0, cy = 0.0, cz = 0.0;
+            int jb = 0, len = 0, code = 0;
             if (cidx < ncell) {
-                const int t = (int)(((double)cidx + 0.5) * inv_mx);
+                const int t = (int)(((uint32_t)cidx * dx_) >> 16);
                 const int e = cidx - t * mx;
-                const int a = (int)(((double)t + 0.5) * inv_my);
+                const int a = (int)(((uint32_t)t * dy_) >> 16);
                 const int b = t - a * my;
-                const int kx = lx + e, ky = ly + b, kz = lz + a;
                 bool keep = true;
-                if (CULL) {
-                    const double gz = cell_gap(pi.z, kz, cs), gy = cell_gap(pi.y, ky, cs),
-                                 gx = cell_gap(pi.x, kx, cs);
-                    keep = (gz * gz + gy * gy) + gx * gx <= Hc2;
-                    // image shift of the cell's particles (0, L or -L per axis)
-                    cx = kx < 0 ? L : (kx >= nck ? -L : 0.0);
-                    cy = ky < 0 ? L : (ky >= nck ? -L : 0.0);
-                    cz = kz < 0 ? L : (kz >= nck ? -L : 0.0);
-                }
+                if (CULL) keep = (tab.g2[2][a] + tab.g2[1][b]) + tab.g2[0][e] <= Hc2;
                 if (keep) {
-                    const uint32_t id = (spread3(wrapc(kz, nck)) << 2) | (spread3(wrapc(ky, nck)) << 1) |
-                                        spread3(wrapc(kx, nck));
+                    const uint32_t ix = tab.id[0][e], iy = tab.id[1][b], iz = tab.id[2][a];
+                    const uint32_t id = (ix | iy | iz) & 0x3fffffffu;
+                    code = (int)(ix >> 30) + 3 * (int)(iy >> 30) + 9 * (int)(iz >> 30);
                     jb = cb[id];
                     len = ce_[id] - jb;
                 }
@@ -343,20 +353,12 @@ __device__ __forceinline__ void walk_row_flat(const double4 *__restrict__ posH, 
             int tot;
             const int pre = group_excl_scan<G>(len, l, tot);
             const bool has = len > 0;
-            uint32_t hm;
-            if (G == 1) {
-                hm = has;
-            } else {
-                uint64_t m = __ballot(has);
-                hm = (uint32_t)((m >> gshift) & ((G == 64) ? ~0ull : (((uint64_t)1 << G) - 1)));
-            }
+            const uint32_t hm = (uint32_t)((__ballot(has) >> gshift) & (((uint64_t)1 << G) - 1));
             if (has) {
-                const int pos = nr + (G == 1 ? 0 : __popc(hm & below));
+                const int pos = nr + __popc(hm & below);
                 sb[pos] = jb;
                 sc[pos] = cum + pre;
-                sx[3 * pos + 0] = cx;
-                sx[3 * pos + 1] = cy;
-                sx[3 * pos + 2] = cz;
+                scode[pos] = (uint8_t)code;
             }
             nr += __popc(hm);
             cum += tot;
@@ -366,7 +368,7 @@ __device__ __forceinline__ void walk_row_flat(const double4 *__restrict__ posH, 
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        // 2. the listed candidates, G at a time
+        // 3. the listed candidates, G at a time
         int r = 0;
         for (int f0 = 0; f0 < cum; f0 += G) {
             const int f = f0 + l;
@@ -378,9 +380,10 @@ __device__ __forceinline__ void walk_row_flat(const double4 *__restrict__ posH, 
                 const double4 pj = posH[j];
                 double dx, dy, dz;
                 if (CULL) {
-                    dx = (pi.x - pj.x) + sx[3 * r + 0];
-                    dy = (pi.y - pj.y) + sx[3 * r + 1];
-                    dz = (pi.z - pj.z) + sx[3 * r + 2];
+                    const double *sh = shifts[scode[r]];
+                    dx = (pi.x - pj.x) + sh[0];
+                    dy = (pi.y - pj.y) + sh[1];
+                    dz = (pi.z - pj.z) + sh[2];
                 } else {
                     dx = min_image(pi.x - pj.x, v.L, v.hL);
                     dy = min_image(pi.y - pj.y, v.L, v.hL);
@@ -390,15 +393,9 @@ __device__ __forceinline__ void walk_row_flat(const double4 *__restrict__ posH, 
                 hit = r2 < H2 && (int64_t)j != i;
                 extra = hit && !(r2 < pj.w * pj.w);
             }
-            uint32_t hm;
-            if (G == 1) {
-                hm = hit;
-            } else {
-                uint64_t mh = __ballot(hit);
-                hm = (uint32_t)((mh >> gshift) & ((G == 64) ? ~0ull : (((uint64_t)1 << G) - 1)));
-            }
+            const uint32_t hm = (uint32_t)((__ballot(hit) >> gshift) & (((uint64_t)1 << G) - 1));
             if (hit) {
-                const int pos = cg + (G == 1 ? 0 : __popc(hm & below));
+                const int pos = cg + __popc(hm & below);
                 if (DIRECT) {
                     gidx[goff[i] + pos] = j;
                     if (extra) etmp[eoff[j] + atomicAdd(&efill[j], 1)] = (int32_t)i;
@@ -421,30 +418,25 @@ __device__ __forceinline__ void walk_row_flat(const double4 *__restrict__ posH, 
 // time (consecutive, so the loads coalesce). A ballot over the group orders
 // the hits exactly as a serial walk would, so row i is the same list for
 // every G. Row entries go to a per-particle scratch of `cap` slots, with bit
-// 31 marking the pairs that are extras of j; ng/nes count every hit, so a
-// row longer than cap is detected and walked again (DIRECT) into its final
-// place.
-// DIRECT = true is the second walk of rows longer than cap: it writes the
-// gather row and the extras straight to their final places.
+// 31 marking the pairs that are extras of j; the returned count covers every
+// hit, so a row longer than cap is detected and walked again (DIRECT) into
+// its final place.
+// DIRECT = true is that second walk: it writes the gather row and the
+// extras straight to their final places.
 template <int G, bool DIRECT>
-__global__ __launch_bounds__(kBlock) void k_walk_scratch(const double4 *__restrict__ posH, int64_t n,
-                                                         Levels v, const int32_t *__restrict__ cbeg,
-                                                         const int32_t *__restrict__ cend, int cap,
-                                                         uint32_t *scratch, int32_t *ng, int32_t *rcnt,
-                                                         const int64_t *__restrict__ goff, int32_t *gidx,
-                                                         const int64_t *__restrict__ eoff, int32_t *efill,
-                                                         int32_t *etmp, int shift) {
-    int64_t gid = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
-    const int l = (int)(gid % G);
-    const int64_t i = gid / G;
-    if (i >= n) return;   // whole groups leave together (G divides the block)
-    if (DIRECT && ng[i] <= cap) return;
+__device__ __forceinline__ int32_t walk_one(const double4 *__restrict__ posH, int64_t i, int l,
+                                            const Levels &v, const int32_t *__restrict__ cbeg,
+                                            const int32_t *__restrict__ cend, int cap, uint32_t *scratch,
+                                            int32_t *rcnt, const int64_t *__restrict__ goff,
+                                            int32_t *gidx, const int64_t *__restrict__ eoff,
+                                            int32_t *efill, int32_t *etmp, int shift,
+                                            const double (*s_shift)[3]) {
     const double4 pi = posH[i];
     const int lane = threadIdx.x & 63;
     const int gshift = lane - l;
     const uint32_t below = (l == 0) ? 0u : ((1u << l) - 1u);
     int32_t cg = 0;
-    uint32_t *row = scratch + (size_t)i * cap;
+    uint32_t *row = DIRECT ? nullptr : scratch + (size_t)i * cap;
     int k = level_for(pi.w * (double)(1 << shift), v);
     int nck = 1 << (v.bits - k);
     Grid g{v.L, v.hL, (double)nck / v.L, v.margin, nck};
@@ -462,20 +454,23 @@ __global__ __launch_bounds__(kBlock) void k_walk_scratch(const double4 *__restri
     if constexpr (G >= 4) {
         // the flattened walk (narrower groups would need too much LDS for
         // their range lists, and walk cell by cell)
-        {
+        if (mx <= kAxisCells && my <= kAxisCells && mz <= kAxisCells) {
             constexpr int NG = kBlock / G;
-            constexpr int NR = flat_ranges<G>();
+            constexpr int NR = walk_ranges<G>();
             __shared__ int32_t s_b[NG][NR], s_c[NG][NR + 1];
-            __shared__ double s_x[NG][3 * NR];
+            __shared__ uint8_t s_code[NG][NR];
+            __shared__ AxisTab s_ax[NG];
             const int grp = threadIdx.x / G;
             if (cull)
                 walk_row_flat<G, DIRECT, true>(posH, i, pi, l, gshift, below, v, cb, ce_, nck, lx, ly, lz,
                                                mx, my, mz, cs, Hc * Hc, cap, row, goff, gidx, rcnt, eoff,
-                                               efill, etmp, cg, s_b[grp], s_c[grp], s_x[grp]);
+                                               efill, etmp, cg, s_b[grp], s_c[grp], s_code[grp], s_ax[grp],
+                                               s_shift);
             else
                 walk_row_flat<G, DIRECT, false>(posH, i, pi, l, gshift, below, v, cb, ce_, nck, lx, ly, lz,
                                                 mx, my, mz, cs, INFINITY, cap, row, goff, gidx, rcnt, eoff,
-                                                efill, etmp, cg, s_b[grp], s_c[grp], s_x[grp]);
+                                                efill, etmp, cg, s_b[grp], s_c[grp], s_code[grp], s_ax[grp],
+                                                s_shift);
             done = true;
         }
     }
@@ -487,31 +482,107 @@ __global__ __launch_bounds__(kBlock) void k_walk_scratch(const double4 *__restri
         walk_row<G, DIRECT, false>(posH, i, pi, l, gshift, below, v, cb, ce_, nck, lx, ly, lz, mx, my,
                                    mz, cs, INFINITY, cap, row, goff, gidx, rcnt, eoff, efill, etmp, cg);
     }
-    if (!DIRECT && l == 0) ng[i] = cg;
+    return cg;
+}
+
+// First walk (DIRECT = false): one group per particle; ng[i] gets the full
+// count. Second walk (DIRECT = true): a grid of any size whose groups take
+// the particles that compaction listed in longs (rows past cap; longs[0]
+// counts them, the list follows) in turn, so it costs nothing when no row
+// is long.
+template <int G, bool DIRECT>
+__global__ __launch_bounds__(kBlock) void k_walk_scratch(const double4 *__restrict__ posH, int64_t n,
+                                                         Levels v, const int32_t *__restrict__ cbeg,
+                                                         const int32_t *__restrict__ cend, int cap,
+                                                         uint32_t *scratch, int32_t *ng, int32_t *rcnt,
+                                                         const int64_t *__restrict__ goff, int32_t *gidx,
+                                                         const int64_t *__restrict__ eoff, int32_t *efill,
+                                                         int32_t *etmp, int shift, int32_t *longs) {
+    // the shift table first: every wave of the block is still running
+    __shared__ double s_shift[27][3];
+    fill_shifts(s_shift, v.L);
+    __syncthreads();
+    // the first walk maps blocks to XCDs in contiguous runs of particles; the
+    // list of the second is short, so its blocks go round the XCDs in order
+    const int64_t gid = (DIRECT ? (int64_t)blockIdx.x : xcd_block(blockIdx.x, gridDim.x)) * kBlock + threadIdx.x;
+    const int l = (int)(gid % G);
+    if constexpr (!DIRECT) {
+        const int64_t i = gid / G;
+        if (i >= n) return;   // whole groups leave together (G divides the block)
+        const int32_t cg = walk_one<G, false>(posH, i, l, v, cbeg, cend, cap, scratch, rcnt, goff, gidx,
+                                              eoff, efill, etmp, shift, s_shift);
+        if (l == 0) ng[i] = cg;
+    } else {
+        const int64_t nl = longs[0];
+        const int64_t stride = (int64_t)gridDim.x * (kBlock / G);
+        for (int64_t t = gid / G; t < nl; t += stride) {
+            const int64_t i = longs[1 + t];
+            // a recorded step whose lists overflowed their capacities has
+            // its counts cleared: then nothing is written
+            if (ng[i] <= cap) continue;
+            walk_one<G, true>(posH, i, l, v, cbeg, cend, cap, scratch, rcnt, goff, gidx, eoff, efill, etmp,
+                              shift, s_shift);
+        }
+    }
 }
 
 // scratch rows -> gather rows, for rows that fit in cap (G lanes per row
-// read and write consecutive slots); each extra (j, i) goes to a slot of
-// row j of the transposed lists (slot order is fixed later by rank)
-template <int G>
+// read and write consecutive slots; longer rows are listed for the second
+// walk); each extra (j, i) goes to a slot of row j of the transposed lists
+// (slot order is fixed later by rank). A lane takes U entries of its row at
+// a time: their loads, then the slot atomics of their extras, then the
+// dependent stores, so the atomics' round trips overlap instead of
+// following one another.
+template <int G, int U>
 __global__ __launch_bounds__(kBlock) void k_compact_rows(const uint32_t *__restrict__ scratch, int cap,
                                                          int64_t n, const int32_t *__restrict__ ng,
                                                          const int64_t *__restrict__ goff, int32_t *gidx,
                                                          const int64_t *__restrict__ eoff, int32_t *efill,
-                                                         int32_t *etmp) {
+                                                         int32_t *etmp, int32_t *longs) {
     int64_t gid = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
     const int l = (int)(gid % G);
     const int64_t i = gid / G;
     if (i >= n) return;
     const int cnt = ng[i];
-    if (cnt > cap) return;
+    if (cnt > cap) {
+        // walked again into place (the list order is immaterial)
+        if (l == 0) longs[1 + atomicAdd(&longs[0], 1)] = (int32_t)i;
+        return;
+    }
     const uint32_t *row = scratch + (size_t)i * cap;
     const int64_t gw = goff[i];
-    for (int k = l; k < cnt; k += G) {
-        const uint32_t w = row[k];
-        const int32_t j = (int32_t)(w & 0x7fffffffu);
-        gidx[gw + k] = j;
-        if (w & 0x80000000u) etmp[eoff[j] + atomicAdd(&efill[j], 1)] = (int32_t)i;
+    for (int k0 = l; k0 < cnt; k0 += G * U) {
+        uint32_t w[U];
+#pragma unroll
+        for (int u = 0; u < U; u++) w[u] = k0 + u * G < cnt ? row[k0 + u * G] : 0u;
+        bool ex[U];
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            const int k = k0 + u * G;
+            ex[u] = k < cnt && (w[u] & 0x80000000u);
+            if (k < cnt) gidx[gw + k] = (int32_t)(w[u] & 0x7fffffffu);
+        }
+        // the returned slots are used only after every atomic is issued
+        int64_t eo[U];
+        int32_t sl[U];
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            eo[u] = 0;
+            sl[u] = 0;
+            if (ex[u]) {
+                const int32_t j = (int32_t)(w[u] & 0x7fffffffu);
+                eo[u] = eoff[j];
+                sl[u] = atomicAdd(&efill[j], 1);
+            }
+        }
+        // every target address before the first store (a store counts in
+        // the same in-order counter as the loads it would otherwise wait for)
+        int64_t at[U];
+#pragma unroll
+        for (int u = 0; u < U; u++) at[u] = ex[u] ? eo[u] + sl[u] : -1;
+#pragma unroll
+        for (int u = 0; u < U; u++)
+            if (at[u] >= 0) etmp[at[u]] = (int32_t)i;
     }
 }
 
@@ -690,15 +761,19 @@ static crk_status build_lists(crk_ctx *c) {
     const int32_t *cbeg = (const int32_t *)c->cbeg.p, *cend = (const int32_t *)c->cend.p;
     // one walk into a capped scratch row per particle; exact counts come
     // with it, and the extras are counted per receiving particle
-    const int cap = c->walk_cap;
+    const int cap = std::max(c->walk_cap, c->walk_cap_auto);
     CRK_TRY(ensure(c, c->scratch, (size_t)n * cap * sizeof(uint32_t)));
     uint32_t *scratch = (uint32_t *)c->scratch.p;
+    // long rows: longs[0] counts them, their particles follow
+    CRK_TRY(ensure(c, c->longs, (size_t)(n + 1) * sizeof(int32_t)));
+    int32_t *longs = (int32_t *)c->longs.p;
     k_fill_i32<<<nblocks(n), kBlock, 0, c->stream>>>(ecnt, n, 0);
     k_fill_i32<<<nblocks(n), kBlock, 0, c->stream>>>(efill, n, 0);
+    k_fill_i32<<<1, kBlock, 0, c->stream>>>(longs, 1, 0);
     {
         KTimer kt_(c, "k_walk");
         int G = c->G_walk;
-#define L_WALK(GG) k_walk_scratch<GG, false><<<(unsigned)((n * GG + kBlock - 1) / kBlock), kBlock, 0, c->stream>>>(posH, n, v, cbeg, cend, cap, scratch, ng, ecnt, nullptr, nullptr, nullptr, nullptr, nullptr, c->walk_shift)
+#define L_WALK(GG) k_walk_scratch<GG, false><<<(unsigned)((n * GG + kBlock - 1) / kBlock), kBlock, 0, c->stream>>>(posH, n, v, cbeg, cend, cap, scratch, ng, ecnt, nullptr, nullptr, nullptr, nullptr, nullptr, c->walk_shift, longs)
         switch (G) {
             case 1: L_WALK(1); break;
             case 2: L_WALK(2); break;
@@ -740,18 +815,19 @@ static crk_status build_lists(crk_ctx *c) {
     int32_t *etmp = (int32_t *)c->etmp.p, *eidx = (int32_t *)c->eidx.p;
     {
         KTimer kt_(c, "k_compact_rows");
-        constexpr int GC = 16;
-        k_compact_rows<GC><<<(unsigned)((n * GC + kBlock - 1) / kBlock), kBlock, 0, c->stream>>>(
-            scratch, cap, n, ng, goff, (int32_t *)c->gidx.p, eoff, efill, etmp);
+        constexpr int GC = 16, UC = 8;
+        k_compact_rows<GC, UC><<<(unsigned)((n * GC + kBlock - 1) / kBlock), kBlock, 0, c->stream>>>(
+            scratch, cap, n, ng, goff, (int32_t *)c->gidx.p, eoff, efill, etmp, longs);
     }
     {
         // the rows over the cap are few and long: 32 lanes each (the row is
-        // the same list for any lane count)
+        // the same list for any lane count), over the list the compaction made
         KTimer kt_(c, "k_walk_long");
         constexpr int GL = 32;
-        k_walk_scratch<GL, true><<<(unsigned)((n * GL + kBlock - 1) / kBlock), kBlock, 0, c->stream>>>(
+        const unsigned nb = (unsigned)std::min<int64_t>((n * GL + kBlock - 1) / kBlock, 4096);
+        k_walk_scratch<GL, true><<<nb, kBlock, 0, c->stream>>>(
             posH, n, v, cbeg, cend, cap, nullptr, ng, nullptr, goff, (int32_t *)c->gidx.p, eoff, efill,
-            etmp, c->walk_shift);
+            etmp, c->walk_shift, longs);
     }
     CRK_HIP(c, hipGetLastError());
     // each extras row ascending in the emitting particle
@@ -769,6 +845,7 @@ static crk_status build_lists(crk_ctx *c) {
         c->ngather = G;
         c->nextra = E;
         c->npairs = G + E;
+        c->walk_cap_auto = walk_cap_for(G, n);
     }
     c->built = 1;
     c->have_V = 0;

@@ -343,6 +343,7 @@ __global__ __launch_bounds__(kBlock) void k_hnet_features(const double4 *__restr
     constexpr int NR = flat_ranges<G>();
     __shared__ int32_t s_b[kBlock / G][NR], s_c[kBlock / G][NR + 1];
     __shared__ double s_x[kBlock / G][3 * NR];
+    __shared__ AxisTab s_ax[kBlock / G];
     if (goff && h == pi.w) {
         if (l == 0) add(0.0);   // self
         for (int64_t k = goff[i] + l; k < goff[i + 1]; k += G) {
@@ -352,7 +353,7 @@ __global__ __launch_bounds__(kBlock) void k_hnet_features(const double4 *__restr
         }
     } else {
         const int grp = threadIdx.x / G;
-        flat_candidates<G, NR>(posH, cbeg, cend, v, i, pi, h, l, s_b[grp], s_c[grp], s_x[grp],
+        flat_candidates<G, NR>(posH, cbeg, cend, v, i, pi, h, l, s_b[grp], s_c[grp], s_x[grp], s_ax[grp],
                                [&](bool valid, double r2) {
                                    if (valid) add(r2);
                                    return false;

@@ -138,13 +138,13 @@ __device__ __forceinline__ int build_row_flat(const double4 *__restrict__ posH,
                                               const int32_t *__restrict__ cend, const Levels &v,
                                               int64_t i, const double4 &pi, double R, int cap,
                                               double *row, int l, int32_t *sb, int32_t *sc,
-                                              double *sx) {
+                                              double *sx, AxisTab &tab) {
     const double R2 = R * R;
     const int gshift = (threadIdx.x & 63) - l;
     const uint64_t gmask = ((uint64_t)1 << G) - 1;
     const uint64_t below = ((uint64_t)1 << l) - 1;
     int c = 0;
-    flat_candidates<G, flat_ranges<G>()>(posH, cbeg, cend, v, i, pi, R, l, sb, sc, sx,
+    flat_candidates<G, flat_ranges<G>()>(posH, cbeg, cend, v, i, pi, R, l, sb, sc, sx, tab,
                                          [&](bool valid, double r2) {
         const bool hit = valid && r2 < R2;
         const uint64_t hm = (__ballot(hit) >> gshift) & gmask;
@@ -232,15 +232,16 @@ __device__ __forceinline__ int thacker_updates(const HsArgs &a, double &H, int &
 // A row at f H for particle i (which then serves every update with H <= f H
 // without a cell walk); when f H holds more candidates than the row, a row
 // just past H is tried (it still serves the updates that shrink H).
-// (FLAT: the flattened walk, with the group's LDS lists sb, sc, sx)
+// (FLAT: the flattened walk, with the group's LDS lists sb, sc, sx and axis
+// tables)
 template <int G, bool FLAT = false>
 __device__ __forceinline__ int make_row(const HsArgs &a, int64_t i, const double4 &pi, double H,
                                         int rcap, double *row, double &Rmax, int l,
                                         int32_t *sb = nullptr, int32_t *sc = nullptr,
-                                        double *sx = nullptr) {
+                                        double *sx = nullptr, AxisTab *tab = nullptr) {
     auto build = [&](double R) {
         if constexpr (FLAT)
-            return build_row_flat<G>(a.posH, a.cbeg, a.cend, a.v, i, pi, R, rcap, row, l, sb, sc, sx);
+            return build_row_flat<G>(a.posH, a.cbeg, a.cend, a.v, i, pi, R, rcap, row, l, sb, sc, sx, *tab);
         else
             return build_row<G>(a.posH, a.cbeg, a.cend, a.v, i, pi, R, rcap, row, l);
     };
@@ -354,8 +355,9 @@ __device__ __forceinline__ void narrow_body(const HsArgs &a, const int32_t *__re
         constexpr int NR = flat_ranges<G>();
         __shared__ int32_t s_b[kBlock / G][NR], s_c[kBlock / G][NR + 1];
         __shared__ double s_x[kBlock / G][3 * NR];
+        __shared__ AxisTab s_ax[kBlock / G];
         const int grp = (threadIdx.x & (kBlock - 1)) / G;
-        c = make_row<G, true>(a, i, pi, H, a.cap, row, Rmax, l, s_b[grp], s_c[grp], s_x[grp]);
+        c = make_row<G, true>(a, i, pi, H, a.cap, row, Rmax, l, s_b[grp], s_c[grp], s_x[grp], &s_ax[grp]);
         if (l == 0) {
             a.rcnt[i] = c;
             a.Rlist[i] = Rmax;

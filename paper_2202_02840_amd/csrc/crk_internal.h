@@ -22,6 +22,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <cmath>
 #include <map>
 #include <string>
 #include <utility>
@@ -85,6 +86,7 @@ struct crk_ctx {
     crk::Buf gstat;                                       // device status of a graph step
     crk::Buf gboff;                                       // box offsets the graph was recorded with
     crk::Buf ecnt, efill, eoff, etmp;                     // extras rows: counts, slots, offsets, unordered rows
+    crk::Buf longs;                                       // rows past the walk cap: count, then particles
     // RCB leaf tiling (crk_build_leaves): keys, the three sorted lists (two
     // copies), sides, nodes, tables, boxes, interaction lists
     crk::Buf rq, rsk, rla, rlb, rside, rpnode, rscan, rnode, rtab, rbox, rpoff, rpart;
@@ -118,6 +120,11 @@ struct crk_ctx {
     int P_vol = 0, P_mom = 0, P_grad = 0, P_der = 8;
     // neighbour walk: lanes per particle and scratch slots per row
     int G_walk = 8, walk_cap = 192;
+    // scratch row slots the next walk uses at least: 2.5x the mean gather
+    // row of the last eager build (a multiple of 64, at most 1024), so that
+    // rows past the cap, walked twice, stay rare when supports hold many
+    // more neighbours than the default cap
+    int walk_cap_auto = 0;
     // walked level: the first whose cell side is at least 2^(walk_shift-1) H
     int walk_shift = 0;
 
@@ -297,6 +304,73 @@ __device__ __forceinline__ int level_for(double R, const Levels &v) {
     return k;
 }
 
+// scratch row slots for gather rows of g entries in all over n particles:
+// 2.5 times the mean row, rounded up to a multiple of 64, at most 1024
+__host__ __device__ inline int walk_cap_for(double g, double n) {
+    const double m = n > 0.0 ? 2.5 * g / n : 0.0;
+    const double c = 64.0 * std::ceil(m / 64.0);
+    return (int)(c < 1024.0 ? c : 1024.0);
+}
+
+// Per-axis tables of a flattened walk. The walked cells form an
+// mx x my x mz box, so the work per cell is separable: a group first
+// tabulates, for the cells lo_a .. lo_a + m_a - 1 along each axis a, the
+// Morton bits of the wrapped index (bits 0..29) with the axis's image shift
+// code above them (bits 30..31: 0 none, 1 +L, 2 -L), the shift itself and
+// the squared gap from the particle to the unwrapped cell; a listed cell
+// then costs three table reads instead of three bit spreads and three gap
+// evaluations. At most 6 cells a side: the walked level's side is at least
+// half the radius, so a support spans at most 5 cell boundaries.
+constexpr int kAxisCells = 8;
+struct AxisTab {
+    uint32_t id[3][kAxisCells];
+    double g2[3][kAxisCells];
+    double sh[3][kAxisCells];
+};
+
+// ceil(2^16 / m): (x * it) >> 16 is x / m rounded down for every x < 512 and
+// m <= 8 (the error, below 512 / 2^16, stays under the 1/8 gap)
+__device__ __forceinline__ uint32_t div16(int m) { return (uint32_t)((65536 + m - 1) / m); }
+
+// fill the tables of one particle (G lanes of a group; SH: the shifts too);
+// coordinates are selected as values (a selected reference would put pi in
+// private memory)
+template <int G, bool CULL, bool SH = true>
+__device__ __forceinline__ void fill_axes(AxisTab &tab, const double4 &pi, int l, int lx, int ly, int lz,
+                                          int mx, int my, int mz, int nck, double cs, double L) {
+    const double px = pi.x, py = pi.y, pz = pi.z;
+    for (int t = l; t < mx + my + mz; t += G) {
+        int ax = 0, idx = t, k = lx + t;
+        double p = px;
+        if (t >= mx + my) {
+            ax = 2;
+            idx = t - mx - my;
+            k = lz + idx;
+            p = pz;
+        } else if (t >= mx) {
+            ax = 1;
+            idx = t - mx;
+            k = ly + idx;
+            p = py;
+        }
+        uint32_t id = spread3(wrapc(k, nck)) << ax;
+        double g2 = 0.0, sh = 0.0;
+        if (CULL) {
+            const int code = k < 0 ? 1 : (k >= nck ? 2 : 0);
+            id |= (uint32_t)code << 30;
+            sh = code == 1 ? L : (code == 2 ? -L : 0.0);
+            const double g = cell_gap(p, k, cs);
+            g2 = g * g;
+        }
+        tab.id[ax][idx] = id;
+        tab.g2[ax][idx] = g2;
+        if (SH) tab.sh[ax][idx] = sh;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Flattened walk of the cells that a sphere of radius R about particle i
 // overlaps, by an aligned group of G lanes (4 <= G <= NR) of one wavefront.
 // The group lists its cells as ranges of sorted particles in LDS (sb: first
@@ -315,7 +389,7 @@ __device__ __forceinline__ void flat_candidates(const double4 *__restrict__ posH
                                                 const int32_t *__restrict__ cbeg,
                                                 const int32_t *__restrict__ cend, const Levels &v,
                                                 int64_t i, const double4 &pi, double R, int l,
-                                                int32_t *sb, int32_t *sc, double *sx,
+                                                int32_t *sb, int32_t *sc, double *sx, AxisTab &tab,
                                                 Visit &&visit) {
     static_assert(G >= 4 && G <= NR, "the flattened walk needs 4..NR lanes");
     const int gshift = (threadIdx.x & 63) - l;
@@ -336,7 +410,11 @@ __device__ __forceinline__ void flat_candidates(const double4 *__restrict__ posH
     const double Rc2 = Rc * Rc;
     const double L = v.L;
     const int ncell = mx * my * mz;
-    const double inv_mx = 1.0 / (double)mx, inv_my = 1.0 / (double)my;
+    if (cull)
+        fill_axes<G, true>(tab, pi, l, lx, ly, lz, mx, my, mz, nck, cs, L);
+    else
+        fill_axes<G, false>(tab, pi, l, lx, ly, lz, mx, my, mz, nck, cs, L);
+    const uint32_t dvx = div16(mx), dvy = div16(my);
     int c0 = 0;
     bool stop = false;
     while (c0 < ncell && !stop) {
@@ -346,24 +424,16 @@ __device__ __forceinline__ void flat_candidates(const double4 *__restrict__ posH
             int jb = 0, len = 0;
             double cx = 0.0, cy = 0.0, cz = 0.0;
             if (cidx < ncell) {
-                // cell index -> (a, b, e); FP64 quotients, exact for these small integers
-                const int t = (int)(((double)cidx + 0.5) * inv_mx);
+                const int t = (int)(((uint32_t)cidx * dvx) >> 16);
                 const int e = cidx - t * mx;
-                const int a = (int)(((double)t + 0.5) * inv_my);
+                const int a = (int)(((uint32_t)t * dvy) >> 16);
                 const int b = t - a * my;
-                const int kx = lx + e, ky = ly + b, kz = lz + a;
-                bool keep = true;
-                if (cull) {
-                    const double gz = cell_gap(pi.z, kz, cs), gy = cell_gap(pi.y, ky, cs),
-                                 gx = cell_gap(pi.x, kx, cs);
-                    keep = (gz * gz + gy * gy) + gx * gx <= Rc2;
-                    cx = kx < 0 ? L : (kx >= nck ? -L : 0.0);
-                    cy = ky < 0 ? L : (ky >= nck ? -L : 0.0);
-                    cz = kz < 0 ? L : (kz >= nck ? -L : 0.0);
-                }
+                const bool keep = !cull || (tab.g2[2][a] + tab.g2[1][b]) + tab.g2[0][e] <= Rc2;
                 if (keep) {
-                    const uint32_t id = (spread3(wrapc(kz, nck)) << 2) | (spread3(wrapc(ky, nck)) << 1) |
-                                        spread3(wrapc(kx, nck));
+                    const uint32_t id = (tab.id[0][e] | tab.id[1][b] | tab.id[2][a]) & 0x3fffffffu;
+                    cx = tab.sh[0][e];
+                    cy = tab.sh[1][b];
+                    cz = tab.sh[2][a];
                     jb = cb[id];
                     len = ce[id] - jb;
                 }

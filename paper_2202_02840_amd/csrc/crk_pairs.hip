@@ -1482,7 +1482,8 @@ __global__ __launch_bounds__(kBlock) void k_flag(int64_t n, const double4 *__res
 // rows that need an FP64 launch in the derivative pass: the flagged
 // particles and their partners (N_s is symmetric, so the partners of a
 // flagged particle are exactly the particles with a flagged partner).
-// One thread per flagged particle; the count is read from the scan's end.
+// Sixteen lanes per flagged particle, over a grid of any size; the count is
+// read from the scan's end.
 __global__ __launch_bounds__(kBlock) void k_mark(const int32_t *__restrict__ flist,
                                                  const int64_t *__restrict__ fpos, int64_t n,
                                                  const int64_t *__restrict__ goff,
@@ -1490,12 +1491,17 @@ __global__ __launch_bounds__(kBlock) void k_mark(const int32_t *__restrict__ fli
                                                  const int32_t *__restrict__ eb,
                                                  const int32_t *__restrict__ ee,
                                                  const int32_t *__restrict__ eidx, int64_t *t64) {
-    int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (k >= fpos[n]) return;
-    int32_t i = flist[k];
-    t64[i] = 1;
-    for (int64_t q = goff[i]; q < goff[i + 1]; q++) t64[gidx[q]] = 1;
-    for (int q = eb[i]; q < ee[i]; q++) t64[eidx[q]] = 1;
+    constexpr int G = 16;
+    const int64_t gid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int l = (int)(gid % G);
+    const int64_t nf = fpos[n];
+    const int64_t stride = (int64_t)gridDim.x * (kBlock / G);
+    for (int64_t k = gid / G; k < nf; k += stride) {
+        const int32_t i = flist[k];
+        if (l == 0) t64[i] = 1;
+        for (int64_t q = goff[i] + l; q < goff[i + 1]; q += G) t64[gidx[q]] = 1;
+        for (int q = eb[i] + l; q < ee[i]; q += G) t64[eidx[q]] = 1;
+    }
 }
 
 __global__ __launch_bounds__(kBlock) void k_zero_i64(int64_t *a, int64_t n) {
@@ -1732,7 +1738,8 @@ static crk_status adapt_rows(crk_ctx *c, const crk_params *p, const double *A, c
         CRK_TRY(scan_exclusive_i64(c, fpos, fpos, n + 1));
         k_compact<<<nblocks(n), kBlock, 0, c->stream>>>(n, fpos, r.flist);
         k_zero_i64<<<nblocks(n + 1), kBlock, 0, c->stream>>>(tpos, n + 1);
-        k_mark<<<nblocks(n), kBlock, 0, c->stream>>>(r.flist, fpos, n, goff, gidx, eb, ee, eidx, tpos);
+        k_mark<<<(unsigned)std::min<int64_t>(nblocks(n * 16), 1024), kBlock, 0, c->stream>>>(
+            r.flist, fpos, n, goff, gidx, eb, ee, eidx, tpos);
         CRK_TRY(scan_exclusive_i64(c, tpos, tpos, n + 1));
         k_compact<<<nblocks(n), kBlock, 0, c->stream>>>(n, tpos, r.tlist);
     }
