@@ -851,6 +851,13 @@ def main():
                                                f"lognormal {args.n_side}^3, sigma 1.5, P(k)~k^-2, seed 2")}
         log(f"leaves leg: build {line['rcb_leaves']['c2']['rcb']['build_ms_median_of_3']:.3f} ms "
             f"(Morton {line['rcb_leaves']['c2']['morton']['build_ms_median_of_3']:.3f} ms)")
+        if not args.no_full_size:
+            line["rcb_leaves"]["c5"] = leaves_leg(
+                args, prec, args.full_side, 2.0, -2.5, 5, True,
+                f"lognormal {args.full_side}^3 sigma 2.0, P(k)~k^-2.5, 1% in 64 clumps, seed 5; "
+                "the generator's supports")
+            log(f"leaves leg (clumps): build {line['rcb_leaves']['c5']['rcb']['build_ms_median_of_3']:.3f} ms "
+                f"(Morton {line['rcb_leaves']['c5']['morton']['build_ms_median_of_3']:.3f} ms)")
     if not args.no_batch:
         line["batch"] = batch_leg(args, prec, args.precision)
         log(f"batch leg {line['batch']['graph_ms_per_step']:.3f} ms per replay")
