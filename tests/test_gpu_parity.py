@@ -10,7 +10,7 @@ import pytest
 import crk_inputs as ci
 import oracle
 from gpu_helpers import OUTPUTS, compare, gpu_run, oracle_run, rows_original
-from paper_2202_02840_amd import CRK_FP64, CRK_MIXED, CRK_MIXED_ADAPT
+from paper_2202_02840_amd import CRK_FP64, CRK_MIXED, CRK_MIXED_ADAPT, Context
 
 pytestmark = pytest.mark.gpu
 
@@ -122,3 +122,27 @@ def test_paper_resolution_nres_268():
         print(prec, {k: f"{e:.1e}" for k, e in errs.items()})
         for k, e in errs.items():
             assert e <= tol, (prec, k, e)
+
+
+def test_walk_cap_grows_after_long_rows():
+    """Supports for 268 neighbours overflow the default 192-slot walk rows,
+    so the first build walks nearly every row twice; the next build on the
+    same context sizes its scratch rows from the first one's mean row (more
+    workspace) and gives the same lists and the same sums bit for bit."""
+    ps = ci.lognormal_box(24, sigma=1.5, seed=941, nngb=268.0, hcap=0.45)
+    _print_case("lognormal 24^3 N_res 268, two builds", ps)
+    ref = oracle_run(ps, nres=268.0)
+    ctx = Context(0)
+    outs, held = [], []
+    for _ in range(2):
+        res = gpu_run(ps, CRK_FP64, nres=268.0, ctx=ctx)
+        held.append(ctx.workspace_bytes())
+        off, idx = ctx.export_neighbors(1)
+        rows = rows_original(off, idx, ctx.perm)
+        for i in range(ps.n):
+            assert np.array_equal(rows[i], ref["sidx"][ref["soff"][i]:ref["soff"][i + 1]]), i
+        assert res["n_pairs"] == ref["n_pairs"]
+        outs.append({k: np.array(res[k]) for k in OUTPUTS})
+    assert held[1] > held[0]
+    for k in OUTPUTS:
+        assert np.array_equal(outs[0][k], outs[1][k]), k
