@@ -42,12 +42,13 @@ VALU_PEAK_PACKED_FP32 = 157.3
 
 # algorithmic work of the derivative pass (k_deriv), counted from the kernel
 # source (pair_deriv in crk_pairs.hip, an FMA counted as two flops, sqrt,
-# reciprocal and exp as one, the periodic wrap of d not counted): 187 flops
-# per ordered pair, 4 of them the sums; bytes per particle: x, y, z (24), the
-# packed record (128 of its 144 bytes FP32, 256 of 288 FP64), m (8), row
-# offsets (16), outputs (32); per ordered pair its 4-byte index
+# reciprocal and exp as one, the separation d not counted): 187 flops per
+# ordered pair, 4 of them the sums; bytes per particle: the packed record
+# (FP32: 144 bytes, the position riding in its padding as 42-bit fixed
+# point; FP64: 256 of 288, plus x, y, z (24)), m (8), row offsets (16),
+# outputs (32); per ordered pair its 4-byte index
 DERIV_FLOPS_PER_PAIR = 187
-DERIV_BYTES_PER_PARTICLE = {"mixed": 24 + 128 + 8 + 16 + 32, "fp64": 24 + 256 + 8 + 16 + 32}
+DERIV_BYTES_PER_PARTICLE = {"mixed": 144 + 8 + 16 + 32, "fp64": 24 + 256 + 8 + 16 + 32}
 DERIV_BYTES_PER_PAIR = 4
 
 OUT_KEYS = ("V", "m0", "m1", "m2", "gm0", "gm1", "gm2", "A", "B", "gA", "gB", "gradv", "dpdt",

@@ -87,12 +87,52 @@ __device__ __forceinline__ double pair_image(double d, const Box &b) {
     return fma(-b.L, rint(d * b.invL), d);
 }
 
+// Fixed-point coordinate of x in [0, L): Q = floor(x 2^42 / L), kept as
+// its high 32 bits q and its low 10 bits f (qinv = 2^42 / L; 2^42 fl(1 / L)
+// is the same double)
+struct Fixed {
+    uint32_t q, f;
+};
+__device__ __forceinline__ Fixed fixed_q(double x, double qinv) {
+    const double t = floor(x * qinv);
+    const uint64_t Q = (uint64_t)(t < 4398046511103.0 ? t : 4398046511103.0);
+    return Fixed{(uint32_t)(Q >> 10), (uint32_t)(Q & 1023u)};
+}
+
+// FP32 separation of two fixed-point coordinates: the 32-bit difference of
+// the high parts wraps to the minimum image; the low parts add their
+// difference at 2^-10 of the step (qs = L 2^-32), so d is within L 2^-42
+// of the exact separation before the FP32 rounding
+__device__ __forceinline__ float fixed_d(uint32_t qi, uint32_t fi, uint32_t qj, uint32_t fj, float qs) {
+    return fmaf((float)((int32_t)fi - (int32_t)fj), qs * (1.0f / 1024.0f), (float)(int32_t)(qi - qj) * qs);
+}
+
+// the three low parts packed in one word (10 bits each)
+__device__ __forceinline__ uint32_t pack_f(const Fixed &a, const Fixed &b, const Fixed &c) {
+    return a.f | (b.f << 10) | (c.f << 20);
+}
+__device__ __forceinline__ uint32_t unpack_f(uint32_t w, int k) { return (w >> (10 * k)) & 1023u; }
+
+// d = x_i - x_j of a listed pair: FP64 with the minimum image, or, for the
+// FP32 passes, from the fixed-point coordinates, so that every FP32 pass
+// (those reading positions and those reading packed records) sees the same
+// d and the RK corrections cancel on the d they were built from
 template <typename T>
 __device__ __forceinline__ void separation(const double4 &pi, const double4 &pj, const Box &b,
                                            T &dx, T &dy, T &dz) {
-    dx = (T)pair_image(pi.x - pj.x, b);
-    dy = (T)pair_image(pi.y - pj.y, b);
-    dz = (T)pair_image(pi.z - pj.z, b);
+    if constexpr (sizeof(T) == 4) {
+        const double qinv = 4398046511104.0 * b.invL;
+        const float qs = (float)(b.L * 2.3283064365386962890625e-10);
+        const Fixed ix = fixed_q(pi.x, qinv), iy = fixed_q(pi.y, qinv), iz = fixed_q(pi.z, qinv);
+        const Fixed jx = fixed_q(pj.x, qinv), jy = fixed_q(pj.y, qinv), jz = fixed_q(pj.z, qinv);
+        dx = fixed_d(ix.q, ix.f, jx.q, jx.f, qs);
+        dy = fixed_d(iy.q, iy.f, jy.q, jy.f, qs);
+        dz = fixed_d(iz.q, iz.f, jz.q, jz.f, qs);
+    } else {
+        dx = (T)pair_image(pi.x - pj.x, b);
+        dy = (T)pair_image(pi.y - pj.y, b);
+        dz = (T)pair_image(pi.z - pj.z, b);
+    }
 }
 
 // Wendland C4 with unit support, eq. (C4): with q = r/H and s = max(1 - q, 0),
@@ -402,7 +442,9 @@ __global__ __launch_bounds__(kBlock) void k_gradv(const double4 *__restrict__ po
     Acc<double> a[9];
     if (i >= 0) {
         const double4 pi = posH[i];
-        auto ri = rec6[i];
+        // FP32 records are two 4-vectors (v, V) and the fixed-point position
+        constexpr int S6 = sizeof(T) == 4 ? 2 : 1;
+        auto ri = rec6[S6 * i];
         const T vi[3] = {ri.x, ri.y, ri.z};
         const int64_t b = goff[i];
         const int cnt = (int)(goff[i + 1] - b);
@@ -461,14 +503,21 @@ __global__ __launch_bounds__(kBlock) void k_gradv(const double4 *__restrict__ po
             }
             const T Ag = (T)(Ad * kG * ihd * ihd * ihd * ihd * ihd);
             const T ih = (T)ihd;
+            const auto qv = rec6[S6 * i + 1];
+            const uint32_t qi[3] = {__float_as_uint(qv.x), __float_as_uint(qv.y), __float_as_uint(qv.z)};
+            const uint32_t fi = __float_as_uint(qv.w);
+            const T qs = (T)(box.L * 2.3283064365386962890625e-10);
             int32_t jn = l < cnt ? gidx[b + l] : 0;
             for (int kk = l; kk < cnt; kk += G) {
                 const int32_t j = jn;
                 if (kk + G < cnt) jn = gidx[b + kk + G];
-                const double4 pj = posH[j];
-                auto rj = rec6[j];
+                auto rj = rec6[S6 * j];
+                const auto qj = rec6[S6 * j + 1];
                 T d[3];
-                separation(pi, pj, box, d[0], d[1], d[2]);
+                // d from the fixed-point positions (as in the derivative pass)
+                d[0] = fixed_d(qi[0], unpack_f(fi, 0), __float_as_uint(qj.x), unpack_f(__float_as_uint(qj.w), 0), qs);
+                d[1] = fixed_d(qi[1], unpack_f(fi, 1), __float_as_uint(qj.y), unpack_f(__float_as_uint(qj.w), 1), qs);
+                d[2] = fixed_d(qi[2], unpack_f(fi, 2), __float_as_uint(qj.z), unpack_f(__float_as_uint(qj.w), 2), qs);
                 const T r = Mth<T>::sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
                 T pw, pg;
                 kfac(r * ih, pw, pg);
@@ -528,11 +577,18 @@ constexpr int kRec = 9;   // 4-vectors per record (the last one padding)
 
 struct DerivPrm {
     double gamma, Cl, Cq, eps2, inv_nh, inv_a, adot, eta_c, inv_eta_f, vs_scale, inv_a5;
+    // fixed-point positions of the FP32 records: Q = floor(x 2^42 / L)
+    // (qinv = 2^42 / L; qs = L 2^-32, the step of Q's high 32 bits)
+    double qinv, qs;
 };
 
 template <typename T>
 struct Rec {
     T v[3], Vs, P, rho, Clcs, ih, hA, he, Ag, B[3], U[3], M[9], S[6];
+    // FP32 records: the position in fixed point (the record's ninth
+    // 4-vector): high parts q (q_i - q_j taken mod 2^32 is the minimum
+    // image) and the packed low parts qf
+    uint32_t q[3], qf;
 };
 
 // the record of one particle from FP64 state (P, rho, c_s given)
@@ -587,6 +643,13 @@ template <typename V4, typename T>
 __device__ __forceinline__ void load_rec(const V4 *__restrict__ rec, int64_t j, Rec<T> &s) {
     const V4 *o = rec + j * kRec;
     const V4 r0 = o[0], r1 = o[1], r2 = o[2], r3 = o[3], r4 = o[4], r5 = o[5], r6 = o[6], r7 = o[7];
+    if constexpr (sizeof(T) == 4) {
+        const V4 r8 = o[8];
+        s.q[0] = __float_as_uint(r8.x);
+        s.q[1] = __float_as_uint(r8.y);
+        s.q[2] = __float_as_uint(r8.z);
+        s.qf = __float_as_uint(r8.w);
+    }
     s.v[0] = r0.x; s.v[1] = r0.y; s.v[2] = r0.z; s.Vs = r0.w;
     s.P = r1.x; s.rho = r1.y; s.Clcs = r1.z; s.ih = r1.w;
     s.hA = r2.x; s.he = r2.y; s.Ag = r2.z; s.B[0] = r2.w;
@@ -636,6 +699,12 @@ __global__ __launch_bounds__(kBlock) void k_pack8(int64_t n, const double4 *__re
     make_rec(posH[i].w, v[i], v[n + i], v[2 * n + i], V[i], P, r, cs, A[i], B3, gA3, gB9, gv9, p,
              flag && flag[i] != 0, rc);
     store_rec<V4, T>(rec + i * kRec, rc);
+    if constexpr (sizeof(T) == 4) {
+        const double4 x = posH[i];
+        const Fixed fx = fixed_q(x.x, p.qinv), fy = fixed_q(x.y, p.qinv), fz = fixed_q(x.z, p.qinv);
+        rec[i * kRec + 8] = V4{__uint_as_float(fx.q), __uint_as_float(fy.q), __uint_as_float(fz.q),
+                               __uint_as_float(pack_f(fx, fy, fz))};
+    }
     if (aux) aux[i] = make_double4(r, P, cs, 0.0);
 }
 
@@ -665,12 +734,12 @@ __device__ __forceinline__ void load_rec_soa(const Soa &s, const double4 *__rest
 
 template <typename T>
 struct PairK {
-    T Cq, eta_c, inv_eta_f, adot, inv_a;
+    T Cq, eta_c, inv_eta_f, adot, inv_a, qs;
 };
 
 template <typename T>
 __device__ __forceinline__ PairK<T> pair_k(const DerivPrm &p) {
-    return PairK<T>{(T)p.Cq, (T)p.eta_c, (T)p.inv_eta_f, (T)p.adot, (T)p.inv_a};
+    return PairK<T>{(T)p.Cq, (T)p.eta_c, (T)p.inv_eta_f, (T)p.adot, (T)p.inv_a, (T)p.qs};
 }
 
 // One ordered pair (i = a, j = b) of eqs. (mom) and (eng) with P -> P + Q:
@@ -874,11 +943,19 @@ __global__ __launch_bounds__(kBlock) void k_deriv_bal(const double4 *__restrict_
         // the partner's position and record are loaded together and the
         // pair is evaluated before its FP64-row flag is looked at, so no
         // load waits on another
-        const double4 pj = posH[j];
         Rec<T> sj;
         load_rec(rec, j, sj);
         T d[3];
-        separation(pi, pj, box, d[0], d[1], d[2]);
+        if constexpr (sizeof(T) == 4) {
+            // FP32 pair terms: d from the fixed-point positions, whose
+            // 32-bit difference wraps to the minimum image (error at most
+            // L 2^-32 per component, then the FP32 rounding); the position
+            // rides in the record, so no separate position load
+#pragma unroll
+            for (int x = 0; x < 3; x++) d[x] = fixed_d(si.q[x], unpack_f(si.qf, x), sj.q[x], unpack_f(sj.qf, x), pk.qs);
+        } else {
+            separation(pi, posH[j], box, d[0], d[1], d[2]);
+        }
         T FD[3], EP, pvs, pqr;
         pair_deriv<T, TS>(si, sj, d, pk, FD, EP, pvs, pqr);
         if (!fp64_row(sj)) {
@@ -1077,7 +1154,8 @@ __global__ __launch_bounds__(kBlock) void k_gradv_bal(const double4 *__restrict_
     }
     const T Ag = (T)(Ad * kG * ihd * ihd * ihd * ihd * ihd);
     const T ih = (T)ihd;
-    const auto ri = rec6[i];
+    constexpr int S6 = sizeof(T) == 4 ? 2 : 1;   // FP32 records: (v, V), position
+    const auto ri = rec6[S6 * i];
     const T vi[3] = {(T)ri.x, (T)ri.y, (T)ri.z};
     double a[9] = {};
     const int64_t gb = goff[i];
@@ -1089,7 +1167,7 @@ __global__ __launch_bounds__(kBlock) void k_gradv_bal(const double4 *__restrict_
         const int32_t j = jn;
         if (kk + G < tot) jn = gidx[gb + kk + G];
         const double4 pj = posH[j];
-        const auto rj = rec6[j];
+        const auto rj = rec6[S6 * j];
         T d[3];
         separation(pi, pj, box, d[0], d[1], d[2]);
         const T r = Mth<T>::sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
@@ -1343,13 +1421,18 @@ __global__ __launch_bounds__(kBlock) void k_compat_bal(const double4 *__restrict
         const int32_t j = jn;
         const int kn = kk + G;
         if (kn < tot) jn = kn < ngi ? gidx[gb + kn] : eidx[ebi + (kn - ngi)];
-        const double4 pj = posH[j];
         const V4 cej = ce[j];
         const V4 cej2 = NK == 2 ? ce2[j] : cej;
         Rec<T> sj;
         load_rec(rec, j, sj);
         T d[3];
-        separation(pi, pj, box, d[0], d[1], d[2]);
+        if constexpr (sizeof(T) == 4) {
+            // as in the derivative pass: d from the records' fixed-point positions
+#pragma unroll
+            for (int x = 0; x < 3; x++) d[x] = fixed_d(si.q[x], unpack_f(si.qf, x), sj.q[x], unpack_f(sj.qf, x), pk.qs);
+        } else {
+            separation(pi, posH[j], box, d[0], d[1], d[2]);
+        }
         T FD[3], EP, vs, qr;
         pair_deriv<T, false>(si, sj, d, pk, FD, EP, vs, qr);
         if (!fp64_row(sj)) {
@@ -1515,10 +1598,18 @@ __global__ __launch_bounds__(kBlock) void k_compact(int64_t n, const int64_t *__
     if (i < n && pos[i + 1] != pos[i]) list[pos[i]] = (int32_t)i;
 }
 
+// FP32 velocity-gradient records: (v, V), then the 32-bit fixed-point
+// position q = floor(x 2^32 / L) (the bits in the float slots)
 __global__ __launch_bounds__(kBlock) void k_pack6_f(int64_t n, const double *v, const double *V,
+                                                    const double4 *__restrict__ posH, double qinv,
                                                     float4 *rec) {
     int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i < n) rec[i] = make_float4((float)v[i], (float)v[n + i], (float)v[2 * n + i], (float)V[i]);
+    if (i >= n) return;
+    rec[2 * i] = make_float4((float)v[i], (float)v[n + i], (float)v[2 * n + i], (float)V[i]);
+    const double4 x = posH[i];
+    const Fixed fx = fixed_q(x.x, qinv), fy = fixed_q(x.y, qinv), fz = fixed_q(x.z, qinv);
+    rec[2 * i + 1] = make_float4(__uint_as_float(fx.q), __uint_as_float(fy.q), __uint_as_float(fz.q),
+                                 __uint_as_float(pack_f(fx, fy, fz)));
 }
 __global__ __launch_bounds__(kBlock) void k_pack6_d(int64_t n, const double *v, const double *V,
                                                     double4 *rec) {
@@ -1550,7 +1641,8 @@ inline unsigned fix_blocks(int64_t rows, int G, bool graph) {
 DerivPrm deriv_prm(const crk_params *p) {
     const double a = p->a;
     return DerivPrm{p->gamma, p->Cl, p->Cq, p->eps * p->eps, 1.0 / p->nh, 1.0 / a, p->adot,
-                    p->eta_crit, 1.0 / p->eta_fold, a * sqrt(0.5), 1.0 / (a * a * a * a * a)};
+                    p->eta_crit, 1.0 / p->eta_fold, a * sqrt(0.5), 1.0 / (a * a * a * a * a),
+                    4398046511104.0 / p->L, p->L / 4294967296.0};
 }
 
 // balanced-lane derivative / compatible launches: particles per wave (4 .. 32)
@@ -1809,7 +1901,7 @@ crk_status crk_derivatives(crk_ctx *c, const crk_params *p, const double *v, con
     const int64_t *nflag_dev = ar.nflag_dev, *ntouch_dev = ar.ntouch_dev;
 
     if (f32) {
-        CRK_TRY(ensure(c, c->rec6, (size_t)n * sizeof(float4)));
+        CRK_TRY(ensure(c, c->rec6, (size_t)n * 2 * sizeof(float4)));
         CRK_TRY(ensure(c, c->rec7, (size_t)n * kRec * sizeof(float4)));
         float4 *r6 = (float4 *)c->rec6.p, *r7 = (float4 *)c->rec7.p;
         double4 *r6d = nullptr, *aux = nullptr;
@@ -1821,7 +1913,7 @@ crk_status crk_derivatives(crk_ctx *c, const crk_params *p, const double *v, con
         }
         {
             KTimer kt_(c, "k_pack");
-            k_pack6_f<<<nblocks(n), kBlock, 0, c->stream>>>(n, v, V, r6);
+            k_pack6_f<<<nblocks(n), kBlock, 0, c->stream>>>(n, v, V, posH, dp.qinv, r6);
             if (adapt) k_pack6_d<<<nblocks(n), kBlock, 0, c->stream>>>(n, v, V, r6d);
         }
         {
