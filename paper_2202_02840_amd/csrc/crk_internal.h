@@ -87,6 +87,7 @@ struct crk_ctx {
     crk::Buf gboff;                                       // box offsets the graph was recorded with
     crk::Buf ecnt, efill, eoff, etmp;                     // extras rows: counts, slots, offsets, unordered rows
     crk::Buf longs;                                       // rows past the walk cap: count, then particles
+    crk::Buf posV;                                        // sorted x, y, z and V (the moment pass reads both at once)
     // RCB leaf tiling (crk_build_leaves): keys, the three sorted lists (two
     // copies), sides, nodes, tables, boxes, interaction lists
     crk::Buf rq, rsk, rla, rlb, rside, rpnode, rscan, rnode, rtab, rbox, rpoff, rpart;

@@ -175,7 +175,8 @@ template <typename T, int G>
 __global__ __launch_bounds__(kBlock) void k_volume(const double4 *__restrict__ posH,
                                                    const int64_t *__restrict__ goff,
                                                    const int32_t *__restrict__ gidx, int64_t n, Box box,
-                                                   double *nsum_out, double *V_out, T *recV) {
+                                                   double *nsum_out, double *V_out, T *recV,
+                                                   double4 *posV) {
     int l;
     int64_t i = group_index(G, l);
     Acc<T> acc[1];
@@ -204,6 +205,8 @@ __global__ __launch_bounds__(kBlock) void k_volume(const double4 *__restrict__ p
         if (nsum_out) nsum_out[i] = s;
         V_out[i] = 1.0 / s;
         recV[i] = (T)(1.0 / s);
+        // the moment pass reads a partner's position and volume in one load
+        posV[i] = make_double4(posH[i].x, posH[i].y, posH[i].z, 1.0 / s);
     }
 }
 
@@ -225,7 +228,7 @@ template <typename T, int G>
 __global__ __launch_bounds__(kBlock) void k_moments(const double4 *__restrict__ posH,
                                                     const int64_t *__restrict__ goff,
                                                     const int32_t *__restrict__ gidx,
-                                                    const T *__restrict__ recV, int64_t n, Box box,
+                                                    const double4 *__restrict__ posV, int64_t n, Box box,
                                                     double *m0, double *m1, double *m2, double *gm0,
                                                     double *gm1, double *gm2) {
     // sums: 0 m0 | 1-3 m1 | 4-9 m2 | 10-12 gm0 | 13-18 Q2 | 19-28 Q3
@@ -238,15 +241,15 @@ __global__ __launch_bounds__(kBlock) void k_moments(const double4 *__restrict__ 
         T invH2 = invH * invH;
         T cw = (T)kW * invH2 * invH;
         T cg = (T)kG * invH2 * invH2 * invH;
-        if (l == 0) a[0].add(recV[i] * cw);   // self pair: d = 0, so m0 only
+        if (l == 0) a[0].add((T)posV[i].w * cw);   // self pair: d = 0, so m0 only
         int64_t b = goff[i];
         int cnt = (int)(goff[i + 1] - b);
         int32_t jn = l < cnt ? gidx[b + l] : 0;
         for (int k = l; k < cnt; k += G) {
             const int32_t j = jn;
             if (k + G < cnt) jn = gidx[b + k + G];
-            double4 pj = posH[j];
-            T Vj = recV[j];
+            const double4 pj = posV[j];   // x, y, z and V
+            T Vj = (T)pj.w;
             T d[3];
             separation(pi, pj, box, d[0], d[1], d[2]);
             T q = Mth<T>::sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]) * invH;
@@ -993,7 +996,8 @@ template <typename T, int P>
 __global__ __launch_bounds__(kBlock) void k_volume_bal(const double4 *__restrict__ posH,
                                                        const int64_t *__restrict__ goff,
                                                        const int32_t *__restrict__ gidx, int64_t n,
-                                                       Box box, double *nsum_out, double *V_out, T *recV) {
+                                                       Box box, double *nsum_out, double *V_out, T *recV,
+                                                       double4 *posV) {
     const int64_t i0 = wave_first(P);
     if (i0 >= n) return;
     const int lane = threadIdx.x & 63;
@@ -1023,6 +1027,8 @@ __global__ __launch_bounds__(kBlock) void k_volume_bal(const double4 *__restrict
         if (nsum_out) nsum_out[i] = a[0];
         V_out[i] = 1.0 / a[0];
         recV[i] = (T)(1.0 / a[0]);
+        // the moment pass reads a partner's position and volume in one load
+        posV[i] = make_double4(pi.x, pi.y, pi.z, 1.0 / a[0]);
     }
 }
 
@@ -1032,7 +1038,7 @@ template <typename T, int P>
 __global__ __launch_bounds__(kBlock) void k_moments_bal(const double4 *__restrict__ posH,
                                                         const int64_t *__restrict__ goff,
                                                         const int32_t *__restrict__ gidx,
-                                                        const T *__restrict__ recV, int64_t n, Box box,
+                                                        const double4 *__restrict__ posV, int64_t n, Box box,
                                                         double *m0, double *m1, double *m2, double *gm0,
                                                         double *gm1, double *gm2) {
     const int64_t i0 = wave_first(P);
@@ -1048,7 +1054,7 @@ __global__ __launch_bounds__(kBlock) void k_moments_bal(const double4 *__restric
     const T invH2 = invH * invH;
     const T cw = (T)kW * invH2 * invH;
     const T cg = (T)kG * invH2 * invH2 * invH;
-    if (lg.first == 0) a[0] = (double)(recV[i] * cw);   // self pair: d = 0, so m0 only
+    if (lg.first == 0) a[0] = (double)((T)posV[i].w * cw);   // self pair: d = 0, so m0 only
     const int64_t gb = goff[i];
     const int tot = (int)(goff[i + 1] - gb);
     const int G = lg.g;
@@ -1057,8 +1063,8 @@ __global__ __launch_bounds__(kBlock) void k_moments_bal(const double4 *__restric
     for (; kk < tot; kk += G) {
         const int32_t j = jn;
         if (kk + G < tot) jn = gidx[gb + kk + G];
-        const double4 pj = posH[j];
-        const T Vj = recV[j];
+        const double4 pj = posV[j];   // x, y, z and V
+        const T Vj = (T)pj.w;
         T d[3];
         separation(pi, pj, box, d[0], d[1], d[2]);
         const T q = Mth<T>::sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]) * invH;
@@ -1666,14 +1672,16 @@ crk_status volume_moments(crk_ctx *c, const double4 *posH, const int64_t *goff, 
                           int64_t n, Box box, double *nsum, double *V, T *rv, bool want_m, double *m0,
                           double *m1, double *m2, double *gm0, double *gm1, double *gm2) {
     const int Gv = c->G_vol, Gm = c->G_mom, Pv = c->P_vol, Pm = c->P_mom;
+    CRK_TRY(ensure(c, c->posV, (size_t)n * sizeof(double4)));
+    double4 *posV = (double4 *)c->posV.p;
     {
         KTimer kt_(c, "k_volume");
         if (Pv > 0) {
-#define L_VOL(PP) k_volume_bal<T, PP><<<pblocks(n, PP), kBlock, 0, c->stream>>>(posH, goff, gidx, n, box, nsum, V, rv)
+#define L_VOL(PP) k_volume_bal<T, PP><<<pblocks(n, PP), kBlock, 0, c->stream>>>(posH, goff, gidx, n, box, nsum, V, rv, posV)
             CRK_DISPATCH_P(Pv, L_VOL);
 #undef L_VOL
         } else {
-#define L_VOL(GG) k_volume<T, GG><<<gblocks(n, GG), kBlock, 0, c->stream>>>(posH, goff, gidx, n, box, nsum, V, rv)
+#define L_VOL(GG) k_volume<T, GG><<<gblocks(n, GG), kBlock, 0, c->stream>>>(posH, goff, gidx, n, box, nsum, V, rv, posV)
             CRK_DISPATCH_G(Gv, L_VOL);
 #undef L_VOL
         }
@@ -1681,11 +1689,11 @@ crk_status volume_moments(crk_ctx *c, const double4 *posH, const int64_t *goff, 
     if (want_m) {
         KTimer kt_(c, "k_moments");
         if (Pm > 0) {
-#define L_MOM(PP) k_moments_bal<T, PP><<<pblocks(n, PP), kBlock, 0, c->stream>>>(posH, goff, gidx, rv, n, box, m0, m1, m2, gm0, gm1, gm2)
+#define L_MOM(PP) k_moments_bal<T, PP><<<pblocks(n, PP), kBlock, 0, c->stream>>>(posH, goff, gidx, posV, n, box, m0, m1, m2, gm0, gm1, gm2)
             CRK_DISPATCH_P(Pm, L_MOM);
 #undef L_MOM
         } else {
-#define L_MOM(GG) k_moments<T, GG><<<gblocks(n, GG), kBlock, 0, c->stream>>>(posH, goff, gidx, rv, n, box, m0, m1, m2, gm0, gm1, gm2)
+#define L_MOM(GG) k_moments<T, GG><<<gblocks(n, GG), kBlock, 0, c->stream>>>(posH, goff, gidx, posV, n, box, m0, m1, m2, gm0, gm1, gm2)
             CRK_DISPATCH_G(Gm, L_MOM);
 #undef L_MOM
         }
