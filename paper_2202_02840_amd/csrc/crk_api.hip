@@ -247,12 +247,13 @@ static double held(double b) {
     return b + std::floor(b / 8.0);
 }
 
-// Block-sum scratch of scan_exclusive_i64 for up to m values.
+// Block-sum scratch of scan_exclusive_i64 for up to m values, and of
+// scan_counts2 (two arrays' block sums, then the scan of one of them).
 static double scan_bytes(double m) {
     const double tile = 2048.0;
     double need = 0.0;
     for (double k = std::ceil(m / tile); k > 1.0; k = std::ceil(k / tile)) need += k;
-    return (need + 16.0) * 8.0;
+    return (need + 2.0 * std::ceil(m / tile) + 16.0) * 8.0;
 }
 
 crk_status crk_workspace_estimate(const crk_ctx *c, int64_t n, int32_t nboxes,

@@ -683,10 +683,7 @@ crk_status crk_build_leaves(crk_ctx *c, int32_t nboxes, const int64_t *box_offse
                                                          nullptr, nullptr, nullptr, nullptr);
         CRK_HIP(c, hipGetLastError());
     }
-    k_count_i64<<<lblocks(n + 1), kBlock, 0, c->stream>>>(ng, n, goff);
-    k_count_i64<<<lblocks(n + 1), kBlock, 0, c->stream>>>(ne, n, eoff);
-    CRK_TRY(scan_exclusive_i64(c, goff, goff, n + 1));
-    CRK_TRY(scan_exclusive_i64(c, eoff, eoff, n + 1));
+    CRK_TRY(scan_counts2(c, ng, ne, n, goff, eoff));
     int *over = (int *)c->misc.p + 8;
     CRK_TRY(zero_async(c, over, 1));
     k_any_over<<<lblocks(n), kBlock, 0, c->stream>>>(ng, ne, n, gcap, xcap, over);

@@ -677,14 +677,12 @@ __device__ __forceinline__ void gas_state(int64_t i, const double *v, const doub
 }
 
 template <typename V4, typename T>
-__global__ __launch_bounds__(kBlock) void k_pack8(int64_t n, const double4 *__restrict__ posH,
-                                                  const double *v, const double *m, const double *u,
-                                                  const double *rho, const double *V, const double *A,
-                                                  const double *B, const double *gA, const double *gB,
-                                                  const double *gv, DerivPrm p, const int32_t *flag,
-                                                  V4 *rec, double4 *aux, int *bad) {
-    int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i >= n) return;
+__device__ __forceinline__ void pack8_one(int64_t i, int64_t n, const double4 *__restrict__ posH,
+                                          const double *v, const double *m, const double *u,
+                                          const double *rho, const double *V, const double *A,
+                                          const double *B, const double *gA, const double *gB,
+                                          const double *gv, const DerivPrm &p, const int32_t *flag,
+                                          V4 *o, double4 *aux, int *bad) {
     double r, P, cs;
     gas_state(i, v, m, u, rho, V, n, p.gamma, r, P, cs, bad);
     double B3[3], gA3[3], gB9[9], gv9[9];
@@ -701,14 +699,38 @@ __global__ __launch_bounds__(kBlock) void k_pack8(int64_t n, const double4 *__re
     Rec<double> rc;
     make_rec(posH[i].w, v[i], v[n + i], v[2 * n + i], V[i], P, r, cs, A[i], B3, gA3, gB9, gv9, p,
              flag && flag[i] != 0, rc);
-    store_rec<V4, T>(rec + i * kRec, rc);
+    store_rec<V4, T>(o, rc);
     if constexpr (sizeof(T) == 4) {
         const double4 x = posH[i];
         const Fixed fx = fixed_q(x.x, p.qinv), fy = fixed_q(x.y, p.qinv), fz = fixed_q(x.z, p.qinv);
-        rec[i * kRec + 8] = V4{__uint_as_float(fx.q), __uint_as_float(fy.q), __uint_as_float(fz.q),
-                               __uint_as_float(pack_f(fx, fy, fz))};
+        o[8] = V4{__uint_as_float(fx.q), __uint_as_float(fy.q), __uint_as_float(fz.q),
+                  __uint_as_float(pack_f(fx, fy, fz))};
     }
     if (aux) aux[i] = make_double4(r, P, cs, 0.0);
+}
+
+template <typename V4, typename T>
+__global__ __launch_bounds__(kBlock) void k_pack8(int64_t n, const double4 *__restrict__ posH,
+                                                  const double *v, const double *m, const double *u,
+                                                  const double *rho, const double *V, const double *A,
+                                                  const double *B, const double *gA, const double *gB,
+                                                  const double *gv, DerivPrm p, const int32_t *flag,
+                                                  V4 *rec, double4 *aux, int *bad) {
+    // FP32 records are assembled in LDS and leave as one contiguous run per
+    // block (consecutive lanes, consecutive 16 bytes) instead of nine
+    // 16-byte stores 144 bytes apart per lane
+    constexpr bool STAGE = sizeof(T) == 4;
+    __shared__ V4 s_rec[STAGE ? kBlock * kRec : 1];
+    const int64_t b0 = (int64_t)blockIdx.x * kBlock;
+    const int64_t i = b0 + threadIdx.x;
+    if (i < n) pack8_one<V4, T>(i, n, posH, v, m, u, rho, V, A, B, gA, gB, gv, p, flag,
+                                STAGE ? s_rec + threadIdx.x * kRec : rec + i * kRec, aux, bad);
+    if constexpr (STAGE) {
+        __syncthreads();
+        const int cnt = (int)((n - b0 < kBlock ? n - b0 : kBlock) * kRec);
+        V4 *dst = rec + b0 * kRec;
+        for (int k = threadIdx.x; k < cnt; k += kBlock) dst[k] = s_rec[k];
+    }
 }
 
 // FP64 state of the adaptive mode's FP64 rows from the boundary arrays

@@ -59,6 +59,68 @@ __global__ __launch_bounds__(kBlock) void k_scan_apply(const int64_t *in, int64_
     }
 }
 
+// The same two kernels for a pair of int32 count arrays (blockIdx.y picks
+// the array): each array's first nin values, then zeros up to nout, scanned
+// into int64 offsets, so the offsets of n rows come out with the total as
+// their (n + 1)-th entry without a widening copy first.
+__global__ __launch_bounds__(kBlock) void k_scan_sums2(const int32_t *in0, const int32_t *in1, int64_t nin,
+                                                       int64_t *bs0, int64_t *bs1) {
+    __shared__ int64_t lds[4];
+    const int32_t *in = blockIdx.y ? in1 : in0;
+    int64_t *bsum = blockIdx.y ? bs1 : bs0;
+    int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    int64_t s = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; k++)
+        if (base + k < nin) s += in[base + k];
+    s = block_inclusive_scan(s, lds);
+    if (threadIdx.x == kBlock - 1) bsum[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_apply2(const int32_t *in0, const int32_t *in1, int64_t nin,
+                                                        int64_t nout, int64_t *out0, int64_t *out1,
+                                                        const int64_t *bo0, const int64_t *bo1) {
+    __shared__ int64_t lds[4];
+    const int32_t *in = blockIdx.y ? in1 : in0;
+    int64_t *out = blockIdx.y ? out1 : out0;
+    const int64_t *boff = blockIdx.y ? bo1 : bo0;
+    int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    int64_t v[kScanItems];
+    int64_t s = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; k++) {
+        v[k] = (base + k < nin) ? (int64_t)in[base + k] : 0;
+        s += v[k];
+    }
+    int64_t incl = block_inclusive_scan(s, lds);
+    int64_t run = incl - s + boff[blockIdx.x];
+#pragma unroll
+    for (int k = 0; k < kScanItems; k++) {
+        if (base + k < nout) out[base + k] = run;
+        run += v[k];
+    }
+}
+
+// block sums of both arrays scanned in place in one single-block launch
+__global__ __launch_bounds__(kBlock) void k_scan_bsum2(int64_t *bs0, int64_t *bs1, int64_t m) {
+    __shared__ int64_t lds[4];
+    int64_t *b = blockIdx.y ? bs1 : bs0;
+    int64_t v[kScanItems];
+    int64_t s = 0;
+    const int64_t base = (int64_t)threadIdx.x * kScanItems;
+#pragma unroll
+    for (int k = 0; k < kScanItems; k++) {
+        v[k] = (base + k < m) ? b[base + k] : 0;
+        s += v[k];
+    }
+    int64_t run = block_inclusive_scan(s, lds) - s;
+#pragma unroll
+    for (int k = 0; k < kScanItems; k++) {
+        if (base + k < m) b[base + k] = run;
+        run += v[k];
+    }
+}
+
 // ---------------------------------------------------------------- radix sort
 constexpr int kRadixBits = 8;
 constexpr int kBuckets = 1 << kRadixBits;
@@ -125,7 +187,9 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(const uint32_t *kin, c
 
 }  // namespace
 
-crk_status scan_exclusive_i64(crk_ctx *c, const int64_t *in, int64_t *out, int64_t n) {
+// exclusive scan with its block sums at tmp (room for the sum over levels
+// of ceil(n / 2048^k), k >= 1, plus 16)
+static crk_status scan_with(crk_ctx *c, const int64_t *in, int64_t *out, int64_t n, int64_t *bsum) {
     if (n <= 0) return CRK_OK;
     int64_t nblk = (n + kScanTile - 1) / kScanTile;
     if (nblk == 1) {
@@ -133,11 +197,6 @@ crk_status scan_exclusive_i64(crk_ctx *c, const int64_t *in, int64_t *out, int64
         CRK_HIP(c, hipGetLastError());
         return CRK_OK;
     }
-    // block sums live in a scratch buffer; the recursion uses the tail of it
-    size_t need = 0;
-    for (int64_t m = nblk; m > 1; m = (m + kScanTile - 1) / kScanTile) need += (size_t)m;
-    CRK_TRY(ensure(c, c->scanTmp, (need + 16) * sizeof(int64_t)));
-    int64_t *bsum = (int64_t *)c->scanTmp.p;
     k_scan_sums<<<(unsigned)nblk, kBlock, 0, c->stream>>>(in, n, bsum);
     CRK_HIP(c, hipGetLastError());
     // scan the block sums in place (recursion on a disjoint region is not
@@ -160,6 +219,41 @@ crk_status scan_exclusive_i64(crk_ctx *c, const int64_t *in, int64_t *out, int64
         }
     }
     k_scan_apply<<<(unsigned)nblk, kBlock, 0, c->stream>>>(in, out, n, bsum);
+    CRK_HIP(c, hipGetLastError());
+    return CRK_OK;
+}
+
+static size_t scan_need(int64_t n) {
+    size_t need = 0;
+    for (int64_t m = (n + kScanTile - 1) / kScanTile; m > 1; m = (m + kScanTile - 1) / kScanTile)
+        need += (size_t)m;
+    return need;
+}
+
+crk_status scan_exclusive_i64(crk_ctx *c, const int64_t *in, int64_t *out, int64_t n) {
+    if (n <= 0) return CRK_OK;
+    // block sums live in a scratch buffer; the recursion uses the tail of it
+    CRK_TRY(ensure(c, c->scanTmp, (scan_need(n) + 16) * sizeof(int64_t)));
+    return scan_with(c, in, out, n, (int64_t *)c->scanTmp.p);
+}
+
+crk_status scan_counts2(crk_ctx *c, const int32_t *a, const int32_t *b, int64_t n, int64_t *oa,
+                        int64_t *ob) {
+    if (n < 0) return set_err(c, CRK_ERR_INVALID_ARG, "negative count");
+    const int64_t nout = n + 1, nblk = (nout + kScanTile - 1) / kScanTile;
+    const size_t need = scan_need(nblk);
+    CRK_TRY(ensure(c, c->scanTmp, (2 * (size_t)nblk + need + 16) * sizeof(int64_t)));
+    int64_t *bs0 = (int64_t *)c->scanTmp.p, *bs1 = bs0 + nblk, *tail = bs1 + nblk;
+    k_scan_sums2<<<dim3((unsigned)nblk, 2), kBlock, 0, c->stream>>>(a, b, n, bs0, bs1);
+    CRK_HIP(c, hipGetLastError());
+    if (nblk <= kScanTile) {
+        k_scan_bsum2<<<dim3(1, 2), kBlock, 0, c->stream>>>(bs0, bs1, nblk);
+        CRK_HIP(c, hipGetLastError());
+    } else {
+        CRK_TRY(scan_with(c, bs0, bs0, nblk, tail));
+        CRK_TRY(scan_with(c, bs1, bs1, nblk, tail));
+    }
+    k_scan_apply2<<<dim3((unsigned)nblk, 2), kBlock, 0, c->stream>>>(a, b, n, nout, oa, ob, bs0, bs1);
     CRK_HIP(c, hipGetLastError());
     return CRK_OK;
 }
