@@ -248,12 +248,13 @@ static double held(double b) {
 }
 
 // Block-sum scratch of scan_exclusive_i64 for up to m values, and of
-// scan_counts2 (two arrays' block sums, then the scan of one of them).
+// scan_counts2 (two arrays' block sums and one's block maxima, then the
+// scan of one of them).
 static double scan_bytes(double m) {
     const double tile = 2048.0;
     double need = 0.0;
     for (double k = std::ceil(m / tile); k > 1.0; k = std::ceil(k / tile)) need += k;
-    return (need + 2.0 * std::ceil(m / tile) + 16.0) * 8.0;
+    return (need + 3.0 * std::ceil(m / tile) + 16.0) * 8.0;
 }
 
 crk_status crk_workspace_estimate(const crk_ctx *c, int64_t n, int32_t nboxes,
@@ -263,9 +264,11 @@ crk_status crk_workspace_estimate(const crk_ctx *c, int64_t n, int32_t nboxes,
         (precision != CRK_FP64 && precision != CRK_MIXED && precision != CRK_MIXED_ADAPT))
         return CRK_ERR_INVALID_ARG;
     const double N = (double)n, P = N * pairs_per_particle;
-    // the walk's row slots: the set cap, or the adaptive one for rows as long
-    // as the pairs per particle (gather rows are never longer)
-    const int walk_cap = std::max(c ? c->walk_cap : 192, crk::walk_cap_for(N * pairs_per_particle, N)),
+    // the walk's row slots: the set cap, or the adaptive one, which follows
+    // the mean row (gather rows are never longer than the pairs per
+    // particle) and the longest row within walk_cap_limit
+    const int walk_cap = std::max({c ? c->walk_cap : 192, crk::walk_cap_for(N * pairs_per_particle, N),
+                                   crk::walk_cap_limit(N)}),
               hs_cap = c ? c->hs_cap : 320;
     double t = 0.0;
     // build (crk_build_cells, any use): checks, sort, tables, lists
@@ -279,7 +282,7 @@ crk_status crk_workspace_estimate(const crk_ctx *c, int64_t n, int32_t nboxes,
     while (bits < 8 && (double)nboxes * std::pow(8.0, bits + 1) * 8.0 / 7.0 <= (double)(1 << 26)) bits++;
     const double ntab = (std::pow(8.0, bits + 1) - 1.0) / 7.0 * nboxes;
     t += 2 * held(4.0 * ntab);
-    t += held(4.0 * N) + 2 * held(8.0 * (N + 1.0)) + 2 * held(4.0 * N);   // counts, offsets
+    t += held(4.0 * N) + held(8.0 * (N + 2.0)) + held(8.0 * (N + 1.0)) + 2 * held(4.0 * N);   // counts, offsets
     t += held(4.0 * N * walk_cap) + held(4.0 * (N + 1.0));                // walk rows, long rows
     t += held(4.0 * P) + 2 * held(4.0 * 0.5 * P) + 2 * held(4.0 * N);    // N_g rows, extras (E <= P/2)
     // passes

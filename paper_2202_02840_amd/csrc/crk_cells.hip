@@ -757,7 +757,8 @@ static crk_status build_lists(crk_ctx *c) {
     int64_t n = c->n;
     Levels v = levels(c);
     CRK_TRY(ensure(c, c->ng, (size_t)n * sizeof(int32_t)));
-    CRK_TRY(ensure(c, c->goff, (size_t)(n + 1) * sizeof(int64_t)));
+    // goff[n + 1]: the longest gather row, for the next build's scratch rows
+    CRK_TRY(ensure(c, c->goff, (size_t)(n + 2) * sizeof(int64_t)));
     CRK_TRY(ensure(c, c->ecnt, (size_t)n * sizeof(int32_t)));
     CRK_TRY(ensure(c, c->efill, (size_t)n * sizeof(int32_t)));
     CRK_TRY(ensure(c, c->eoff, (size_t)(n + 1) * sizeof(int64_t)));
@@ -792,8 +793,8 @@ static crk_status build_lists(crk_ctx *c) {
 #undef L_WALK
     }
     CRK_HIP(c, hipGetLastError());
-    CRK_TRY(scan_counts2(c, ng, ecnt, n, goff, eoff));
-    int64_t G, E;
+    CRK_TRY(scan_counts2(c, ng, ecnt, n, goff, eoff, goff + n + 1));
+    int64_t G, E, longest = 0;
     GraphStat *gst = (GraphStat *)c->gstat.p;
     if (c->graph_mode) {
         // fixed capacities; the counts stay on the device
@@ -806,9 +807,11 @@ static crk_status build_lists(crk_ctx *c) {
         int64_t *pin = (int64_t *)c->pinned.p;
         CRK_HIP(c, hipMemcpyAsync(pin, goff + n, sizeof(int64_t), hipMemcpyDeviceToHost, c->stream));
         CRK_HIP(c, hipMemcpyAsync(pin + 1, eoff + n, sizeof(int64_t), hipMemcpyDeviceToHost, c->stream));
+        CRK_HIP(c, hipMemcpyAsync(pin + 2, goff + n + 1, sizeof(int64_t), hipMemcpyDeviceToHost, c->stream));
         CRK_HIP(c, hipStreamSynchronize(c->stream));
         G = pin[0];
         E = pin[1];
+        longest = pin[2];
     }
     if (E > INT32_MAX - 1) return set_err(c, CRK_ERR_INVALID_ARG, "more than 2^31 extra pairs");
     CRK_TRY(ensure(c, c->gidx, (size_t)(G > 0 ? G : 1) * sizeof(int32_t)));
@@ -849,7 +852,7 @@ static crk_status build_lists(crk_ctx *c) {
         c->ngather = G;
         c->nextra = E;
         c->npairs = G + E;
-        c->walk_cap_auto = walk_cap_for(G, n);
+        c->walk_cap_auto = walk_cap_next((double)G, (double)n, longest);
     }
     c->built = 1;
     c->have_V = 0;

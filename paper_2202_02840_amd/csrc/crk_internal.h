@@ -186,9 +186,10 @@ struct KTimer {
 // device-wide exclusive scan of n values (int64 in/out may alias)
 crk_status scan_exclusive_i64(crk_ctx *c, const int64_t *in, int64_t *out, int64_t n);
 // offsets of n rows from two int32 count arrays at once: oa[k] = sum of
-// a[0..k) for k = 0..n (oa[n] the total), likewise ob from b
+// a[0..k) for k = 0..n (oa[n] the total), likewise ob from b; with amax
+// (device) also the largest entry of a (0 when n = 0)
 crk_status scan_counts2(crk_ctx *c, const int32_t *a, const int32_t *b, int64_t n, int64_t *oa,
-                        int64_t *ob);
+                        int64_t *ob, int64_t *amax = nullptr);
 // stable LSD radix sort of (key, value) pairs on the low `bits` bits of the keys
 crk_status radix_sort_pairs(crk_ctx *c, uint32_t *keys, int32_t *vals, int64_t n, int bits);
 
@@ -315,6 +316,25 @@ __host__ __device__ inline int walk_cap_for(double g, double n) {
     const double m = n > 0.0 ? 2.5 * g / n : 0.0;
     const double c = 64.0 * std::ceil(m / 64.0);
     return (int)(c < 1024.0 ? c : 1024.0);
+}
+
+// The most slots per scratch row that still fit 2^31 slots (8 GiB) for n
+// particles, a multiple of 64 and at most 1024.
+inline int walk_cap_limit(double n) {
+    const double c = n > 0.0 ? 64.0 * std::floor(2147483648.0 / n / 64.0) : 1024.0;
+    return (int)(c < 1024.0 ? c : 1024.0);
+}
+
+// Slots of the next walk's scratch rows after a build with g gather pairs
+// whose longest row held `longest`: room for that row and an eighth more
+// (rounded up to 64) within walk_cap_limit, and never below walk_cap_for, so
+// that rows of the next step are walked twice only where they grew past it.
+inline int walk_cap_next(double g, double n, int64_t longest) {
+    const double want = 64.0 * std::ceil(((double)longest + (double)longest / 8.0) / 64.0);
+    const double lim = (double)walk_cap_limit(n);
+    const int c = (int)(want < lim ? want : lim);
+    const int f = walk_cap_for(g, n);
+    return c > f ? c : f;
 }
 
 // Per-axis tables of a flattened walk. The walked cells form an

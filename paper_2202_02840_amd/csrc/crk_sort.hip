@@ -63,18 +63,51 @@ __global__ __launch_bounds__(kBlock) void k_scan_apply(const int64_t *in, int64_
 // the array): each array's first nin values, then zeros up to nout, scanned
 // into int64 offsets, so the offsets of n rows come out with the total as
 // their (n + 1)-th entry without a widening copy first.
+// largest value of one per thread across a 256-thread block (thread 0 holds it)
+__device__ int64_t block_max(int64_t v, int64_t *lds /* [4] */) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const int64_t u = __shfl_xor(v, o, 64);
+        v = u > v ? u : v;
+    }
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0)
+        for (int k = 1; k < kBlock / 64; k++) v = lds[k] > v ? lds[k] : v;
+    return v;
+}
+
+// (with bm: also each block's largest value of the first array)
 __global__ __launch_bounds__(kBlock) void k_scan_sums2(const int32_t *in0, const int32_t *in1, int64_t nin,
-                                                       int64_t *bs0, int64_t *bs1) {
+                                                       int64_t *bs0, int64_t *bs1, int64_t *bm) {
     __shared__ int64_t lds[4];
     const int32_t *in = blockIdx.y ? in1 : in0;
     int64_t *bsum = blockIdx.y ? bs1 : bs0;
     int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
-    int64_t s = 0;
+    int64_t s = 0, mx = 0;
 #pragma unroll
     for (int k = 0; k < kScanItems; k++)
-        if (base + k < nin) s += in[base + k];
+        if (base + k < nin) {
+            const int64_t x = in[base + k];
+            s += x;
+            mx = x > mx ? x : mx;
+        }
     s = block_inclusive_scan(s, lds);
     if (threadIdx.x == kBlock - 1) bsum[blockIdx.x] = s;
+    if (bm && blockIdx.y == 0) {
+        mx = block_max(mx, lds);
+        if (threadIdx.x == 0) bm[blockIdx.x] = mx;
+    }
+}
+
+// the largest of m block maxima (one block)
+__global__ __launch_bounds__(kBlock) void k_max_i64(const int64_t *bm, int64_t m, int64_t *out) {
+    __shared__ int64_t lds[4];
+    int64_t mx = 0;
+    for (int64_t k = threadIdx.x; k < m; k += kBlock) mx = bm[k] > mx ? bm[k] : mx;
+    mx = block_max(mx, lds);
+    if (threadIdx.x == 0) *out = mx;
 }
 
 __global__ __launch_bounds__(kBlock) void k_scan_apply2(const int32_t *in0, const int32_t *in1, int64_t nin,
@@ -238,14 +271,15 @@ crk_status scan_exclusive_i64(crk_ctx *c, const int64_t *in, int64_t *out, int64
 }
 
 crk_status scan_counts2(crk_ctx *c, const int32_t *a, const int32_t *b, int64_t n, int64_t *oa,
-                        int64_t *ob) {
+                        int64_t *ob, int64_t *amax) {
     if (n < 0) return set_err(c, CRK_ERR_INVALID_ARG, "negative count");
     const int64_t nout = n + 1, nblk = (nout + kScanTile - 1) / kScanTile;
     const size_t need = scan_need(nblk);
-    CRK_TRY(ensure(c, c->scanTmp, (2 * (size_t)nblk + need + 16) * sizeof(int64_t)));
-    int64_t *bs0 = (int64_t *)c->scanTmp.p, *bs1 = bs0 + nblk, *tail = bs1 + nblk;
-    k_scan_sums2<<<dim3((unsigned)nblk, 2), kBlock, 0, c->stream>>>(a, b, n, bs0, bs1);
+    CRK_TRY(ensure(c, c->scanTmp, (3 * (size_t)nblk + need + 16) * sizeof(int64_t)));
+    int64_t *bs0 = (int64_t *)c->scanTmp.p, *bs1 = bs0 + nblk, *bm = bs1 + nblk, *tail = bm + nblk;
+    k_scan_sums2<<<dim3((unsigned)nblk, 2), kBlock, 0, c->stream>>>(a, b, n, bs0, bs1, amax ? bm : nullptr);
     CRK_HIP(c, hipGetLastError());
+    if (amax) k_max_i64<<<1, kBlock, 0, c->stream>>>(bm, nblk, amax);
     if (nblk <= kScanTile) {
         k_scan_bsum2<<<dim3(1, 2), kBlock, 0, c->stream>>>(bs0, bs1, nblk);
         CRK_HIP(c, hipGetLastError());

@@ -127,8 +127,9 @@ def test_paper_resolution_nres_268():
 def test_walk_cap_grows_after_long_rows():
     """Supports for 268 neighbours overflow the default 192-slot walk rows,
     so the first build walks nearly every row twice; the next build on the
-    same context sizes its scratch rows from the first one's mean row (more
-    workspace) and gives the same lists and the same sums bit for bit."""
+    same context sizes its scratch rows from the first one's mean and longest
+    rows (more workspace) and gives the same lists and the same sums bit for
+    bit."""
     ps = ci.lognormal_box(24, sigma=1.5, seed=941, nngb=268.0, hcap=0.45)
     _print_case("lognormal 24^3 N_res 268, two builds", ps)
     ref = oracle_run(ps, nres=268.0)
