@@ -186,8 +186,9 @@ struct KTimer {
 // device-wide exclusive scan of n values (int64 in/out may alias)
 crk_status scan_exclusive_i64(crk_ctx *c, const int64_t *in, int64_t *out, int64_t n);
 // offsets of n rows from two int32 count arrays at once: oa[k] = sum of
-// a[0..k) for k = 0..n (oa[n] the total), likewise ob from b; with amax
-// (device) also the largest entry of a (0 when n = 0)
+// a[0..k) for k = 0..n (oa[n] the total), likewise ob from b (b and ob
+// both null: a alone); with amax (device) also the largest entry of a (0
+// when n = 0)
 crk_status scan_counts2(crk_ctx *c, const int32_t *a, const int32_t *b, int64_t n, int64_t *oa,
                         int64_t *ob, int64_t *amax = nullptr);
 // stable LSD radix sort of (key, value) pairs on the low `bits` bits of the keys

@@ -1568,56 +1568,73 @@ __global__ __launch_bounds__(kBlock) void k_timestep(int64_t n, const double4 *_
 // carry B.d, (gradB)^T d and gradA / A, which reach |B| H, |gradB| H^2 and
 // |gradA| H / |A| relative to the O(1) part; their sum bounds how much a
 // rounding of the terms is amplified in the (cancelling) row sums.
+// Appends i to list when `take` (one atomic per wavefront; the list order
+// is that of the arrivals, and every user treats the rows independently).
+__device__ __forceinline__ void append_row(bool take, int64_t i, int32_t *list,
+                                           unsigned long long *count) {
+    const uint64_t m = __ballot(take);
+    if (m == 0) return;
+    const int lane = threadIdx.x & 63;
+    const int lead = __ffsll((unsigned long long)m) - 1;
+    unsigned long long base = 0;
+    if (lane == lead) base = atomicAdd(count, (unsigned long long)__popcll(m));
+    base = __shfl(base, lead, 64);
+    if (take) list[base + __popcll(m & ((1ull << lane) - 1ull))] = (int32_t)i;
+}
+
 __global__ __launch_bounds__(kBlock) void k_flag(int64_t n, const double4 *__restrict__ posH,
                                                  const double *A, const double *B, const double *gA,
                                                  const double *gB, double kappa_max, int32_t *flag,
-                                                 int64_t *fl64) {
-    int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i >= n) return;
-    double H = posH[i].w;
-    double b2 = 0.0, a2 = 0.0, g2 = 0.0;
+                                                 int32_t *flist, unsigned long long *nflag) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    int f = 0;
+    if (i < n) {
+        double H = posH[i].w;
+        double b2 = 0.0, a2 = 0.0, g2 = 0.0;
 #pragma unroll
-    for (int x = 0; x < 3; x++) {
-        b2 += B[x * n + i] * B[x * n + i];
-        a2 += gA[x * n + i] * gA[x * n + i];
+        for (int x = 0; x < 3; x++) {
+            b2 += B[x * n + i] * B[x * n + i];
+            a2 += gA[x * n + i] * gA[x * n + i];
+        }
+#pragma unroll
+        for (int q = 0; q < 9; q++) g2 += gB[q * n + i] * gB[q * n + i];
+        double kap = 1.0 + sqrt(b2) * H + sqrt(g2) * H * H + sqrt(a2) * H / fabs(A[i]);
+        f = !(kap <= kappa_max);
+        flag[i] = f;
     }
-#pragma unroll
-    for (int q = 0; q < 9; q++) g2 += gB[q * n + i] * gB[q * n + i];
-    double kap = 1.0 + sqrt(b2) * H + sqrt(g2) * H * H + sqrt(a2) * H / fabs(A[i]);
-    int f = !(kap <= kappa_max);
-    flag[i] = f;
-    fl64[i] = f;
-    if (i == 0) fl64[n] = 0;
+    append_row(f != 0, i, flist, nflag);
 }
 
 // rows that need an FP64 launch in the derivative pass: the flagged
 // particles and their partners (N_s is symmetric, so the partners of a
 // flagged particle are exactly the particles with a flagged partner).
 // Sixteen lanes per flagged particle, over a grid of any size; the count is
-// read from the scan's end.
+// *nf, where k_flag counted its appends.
 __global__ __launch_bounds__(kBlock) void k_mark(const int32_t *__restrict__ flist,
-                                                 const int64_t *__restrict__ fpos, int64_t n,
+                                                 const int64_t *__restrict__ nf,
                                                  const int64_t *__restrict__ goff,
                                                  const int32_t *__restrict__ gidx,
                                                  const int32_t *__restrict__ eb,
                                                  const int32_t *__restrict__ ee,
-                                                 const int32_t *__restrict__ eidx, int64_t *t64) {
+                                                 const int32_t *__restrict__ eidx, int32_t *mark) {
     constexpr int G = 16;
     const int64_t gid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     const int l = (int)(gid % G);
-    const int64_t nf = fpos[n];
+    const int64_t cnt = *nf;
     const int64_t stride = (int64_t)gridDim.x * (kBlock / G);
-    for (int64_t k = gid / G; k < nf; k += stride) {
+    for (int64_t k = gid / G; k < cnt; k += stride) {
         const int32_t i = flist[k];
-        if (l == 0) t64[i] = 1;
-        for (int64_t q = goff[i] + l; q < goff[i + 1]; q += G) t64[gidx[q]] = 1;
-        for (int q = eb[i] + l; q < ee[i]; q += G) t64[eidx[q]] = 1;
+        if (l == 0) mark[i] = 1;
+        for (int64_t q = goff[i] + l; q < goff[i + 1]; q += G) mark[gidx[q]] = 1;
+        for (int q = eb[i] + l; q < ee[i]; q += G) mark[eidx[q]] = 1;
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_zero_i64(int64_t *a, int64_t n) {
+// marks a[0..n) and the flag counter cleared
+__global__ __launch_bounds__(kBlock) void k_zero_marks(int32_t *a, int64_t n, int64_t *c0) {
     int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i < n) a[i] = 0;
+    if (i == 0) *c0 = 0;
 }
 
 __global__ __launch_bounds__(kBlock) void k_compact(int64_t n, const int64_t *__restrict__ pos,
@@ -1830,7 +1847,8 @@ crk_status crk_corrections(crk_ctx *c, int64_t n, const double *m0, const double
 
 // FP64 rows of the adaptive mode: flags the particles whose RK template is
 // ill-conditioned (flist) and lists every particle with a flagged pair side
-// (tlist). In graph mode the counts stay on the device.
+// (tlist), each list in no particular order. In graph mode the counts stay
+// on the device.
 struct AdaptRows {
     int32_t *flag = nullptr, *flist = nullptr, *tlist = nullptr;
     int64_t nflag = 0, ntouch = 0;
@@ -1856,13 +1874,17 @@ static crk_status adapt_rows(crk_ctx *c, const crk_params *p, const double *A, c
     int64_t *fpos = (int64_t *)c->fpos.p, *tpos = (int64_t *)c->tpos.p;
     {
         KTimer kt_(c, "k_flag");
-        k_flag<<<nblocks(n), kBlock, 0, c->stream>>>(n, posH, A, B, gA, gB, p->kappa_max, r.flag, fpos);
-        CRK_TRY(scan_exclusive_i64(c, fpos, fpos, n + 1));
-        k_compact<<<nblocks(n), kBlock, 0, c->stream>>>(n, fpos, r.flist);
-        k_zero_i64<<<nblocks(n + 1), kBlock, 0, c->stream>>>(tpos, n + 1);
+        // fpos[n] counts the flagged rows (appended in any order: their fix
+        // is per row), the int32 words below it mark the touched rows, whose
+        // offsets tpos list them in ascending order (rows of neighbouring
+        // particles side by side share their partners' loads in the fix)
+        int32_t *mark = (int32_t *)fpos;
+        k_zero_marks<<<nblocks(n), kBlock, 0, c->stream>>>(mark, n, fpos + n);
+        k_flag<<<nblocks(n), kBlock, 0, c->stream>>>(n, posH, A, B, gA, gB, p->kappa_max, r.flag, r.flist,
+                                                     (unsigned long long *)(fpos + n));
         k_mark<<<(unsigned)std::min<int64_t>(nblocks(n * 16), 1024), kBlock, 0, c->stream>>>(
-            r.flist, fpos, n, goff, gidx, eb, ee, eidx, tpos);
-        CRK_TRY(scan_exclusive_i64(c, tpos, tpos, n + 1));
+            r.flist, fpos + n, goff, gidx, eb, ee, eidx, mark);
+        CRK_TRY(scan_counts2(c, mark, nullptr, n, tpos, nullptr));
         k_compact<<<nblocks(n), kBlock, 0, c->stream>>>(n, tpos, r.tlist);
     }
     CRK_HIP(c, hipGetLastError());

@@ -78,21 +78,37 @@ __device__ int64_t block_max(int64_t v, int64_t *lds /* [4] */) {
     return v;
 }
 
+// a thread's kScanItems (8) consecutive int32 inputs, zeros past nin; VEC:
+// two 16-byte loads where all eight are in range (the array 16-byte aligned)
+template <bool VEC>
+__device__ __forceinline__ void load8(const int32_t *in, int64_t base, int64_t nin, int64_t v[8]) {
+    if (VEC && base + 8 <= nin) {
+        const int4 a = *(const int4 *)(in + base), b = *(const int4 *)(in + base + 4);
+        v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+        v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+    } else {
+#pragma unroll
+        for (int k = 0; k < 8; k++) v[k] = base + k < nin ? (int64_t)in[base + k] : 0;
+    }
+}
+
 // (with bm: also each block's largest value of the first array)
+template <bool VEC>
 __global__ __launch_bounds__(kBlock) void k_scan_sums2(const int32_t *in0, const int32_t *in1, int64_t nin,
                                                        int64_t *bs0, int64_t *bs1, int64_t *bm) {
+    static_assert(kScanItems == 8, "eight items per thread");
     __shared__ int64_t lds[4];
     const int32_t *in = blockIdx.y ? in1 : in0;
     int64_t *bsum = blockIdx.y ? bs1 : bs0;
     int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    int64_t v[8];
+    load8<VEC>(in, base, nin, v);
     int64_t s = 0, mx = 0;
 #pragma unroll
-    for (int k = 0; k < kScanItems; k++)
-        if (base + k < nin) {
-            const int64_t x = in[base + k];
-            s += x;
-            mx = x > mx ? x : mx;
-        }
+    for (int k = 0; k < 8; k++) {
+        s += v[k];
+        mx = v[k] > mx ? v[k] : mx;
+    }
     s = block_inclusive_scan(s, lds);
     if (threadIdx.x == kBlock - 1) bsum[blockIdx.x] = s;
     if (bm && blockIdx.y == 0) {
@@ -110,6 +126,7 @@ __global__ __launch_bounds__(kBlock) void k_max_i64(const int64_t *bm, int64_t m
     if (threadIdx.x == 0) *out = mx;
 }
 
+template <bool VEC>
 __global__ __launch_bounds__(kBlock) void k_scan_apply2(const int32_t *in0, const int32_t *in1, int64_t nin,
                                                         int64_t nout, int64_t *out0, int64_t *out1,
                                                         const int64_t *bo0, const int64_t *bo1) {
@@ -118,19 +135,27 @@ __global__ __launch_bounds__(kBlock) void k_scan_apply2(const int32_t *in0, cons
     int64_t *out = blockIdx.y ? out1 : out0;
     const int64_t *boff = blockIdx.y ? bo1 : bo0;
     int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
-    int64_t v[kScanItems];
+    int64_t v[8];
+    load8<VEC>(in, base, nin, v);
     int64_t s = 0;
 #pragma unroll
-    for (int k = 0; k < kScanItems; k++) {
-        v[k] = (base + k < nin) ? (int64_t)in[base + k] : 0;
-        s += v[k];
-    }
+    for (int k = 0; k < 8; k++) s += v[k];
     int64_t incl = block_inclusive_scan(s, lds);
     int64_t run = incl - s + boff[blockIdx.x];
+    int64_t o[8];
 #pragma unroll
-    for (int k = 0; k < kScanItems; k++) {
-        if (base + k < nout) out[base + k] = run;
+    for (int k = 0; k < 8; k++) {
+        o[k] = run;
         run += v[k];
+    }
+    if (VEC && base + 8 <= nout) {
+        // four 16-byte stores (the output 16-byte aligned, base a multiple of 8)
+#pragma unroll
+        for (int k = 0; k < 8; k += 2) *(longlong2 *)(out + base + k) = make_longlong2(o[k], o[k + 1]);
+    } else {
+#pragma unroll
+        for (int k = 0; k < 8; k++)
+            if (base + k < nout) out[base + k] = o[k];
     }
 }
 
@@ -273,21 +298,31 @@ crk_status scan_exclusive_i64(crk_ctx *c, const int64_t *in, int64_t *out, int64
 crk_status scan_counts2(crk_ctx *c, const int32_t *a, const int32_t *b, int64_t n, int64_t *oa,
                         int64_t *ob, int64_t *amax) {
     if (n < 0) return set_err(c, CRK_ERR_INVALID_ARG, "negative count");
+    if ((b == nullptr) != (ob == nullptr)) return set_err(c, CRK_ERR_INVALID_ARG, "scan_counts2: b without ob");
+    const unsigned ny = b ? 2u : 1u;
     const int64_t nout = n + 1, nblk = (nout + kScanTile - 1) / kScanTile;
     const size_t need = scan_need(nblk);
     CRK_TRY(ensure(c, c->scanTmp, (3 * (size_t)nblk + need + 16) * sizeof(int64_t)));
     int64_t *bs0 = (int64_t *)c->scanTmp.p, *bs1 = bs0 + nblk, *bm = bs1 + nblk, *tail = bm + nblk;
-    k_scan_sums2<<<dim3((unsigned)nblk, 2), kBlock, 0, c->stream>>>(a, b, n, bs0, bs1, amax ? bm : nullptr);
+    auto al16 = [](const void *q) { return ((uintptr_t)q & 15u) == 0; };
+    const bool vec = al16(a) && al16(oa) && (!b || (al16(b) && al16(ob)));
+    if (vec)
+        k_scan_sums2<true><<<dim3((unsigned)nblk, ny), kBlock, 0, c->stream>>>(a, b, n, bs0, bs1, amax ? bm : nullptr);
+    else
+        k_scan_sums2<false><<<dim3((unsigned)nblk, ny), kBlock, 0, c->stream>>>(a, b, n, bs0, bs1, amax ? bm : nullptr);
     CRK_HIP(c, hipGetLastError());
     if (amax) k_max_i64<<<1, kBlock, 0, c->stream>>>(bm, nblk, amax);
     if (nblk <= kScanTile) {
-        k_scan_bsum2<<<dim3(1, 2), kBlock, 0, c->stream>>>(bs0, bs1, nblk);
+        k_scan_bsum2<<<dim3(1, ny), kBlock, 0, c->stream>>>(bs0, bs1, nblk);
         CRK_HIP(c, hipGetLastError());
     } else {
         CRK_TRY(scan_with(c, bs0, bs0, nblk, tail));
-        CRK_TRY(scan_with(c, bs1, bs1, nblk, tail));
+        if (b) CRK_TRY(scan_with(c, bs1, bs1, nblk, tail));
     }
-    k_scan_apply2<<<dim3((unsigned)nblk, 2), kBlock, 0, c->stream>>>(a, b, n, nout, oa, ob, bs0, bs1);
+    if (vec)
+        k_scan_apply2<true><<<dim3((unsigned)nblk, ny), kBlock, 0, c->stream>>>(a, b, n, nout, oa, ob, bs0, bs1);
+    else
+        k_scan_apply2<false><<<dim3((unsigned)nblk, ny), kBlock, 0, c->stream>>>(a, b, n, nout, oa, ob, bs0, bs1);
     CRK_HIP(c, hipGetLastError());
     return CRK_OK;
 }
