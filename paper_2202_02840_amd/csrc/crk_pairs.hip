@@ -33,9 +33,31 @@ template <> struct Mth<float> {
     static __device__ __forceinline__ float sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
     static __device__ __forceinline__ float exp(float x) { return __expf(x); }
 };
+// Square root of a squared distance x >= 0: Newton-Raphson refinement of the
+// hardware reciprocal square root estimate y ~ 1/sqrt(x), as coupled
+// iterations for s ~ sqrt(x) and h ~ 1/(2 sqrt(x)) (one coupled step, then
+// two corrections of s by the residual x - s^2), the same steps the
+// correctly rounded library square root takes for arguments of normal range.
+// x is first raised to 2^-767, the bound below which the library rescales
+// its argument: no distance of distinct particles comes near it, and at
+// x = 0 the result (about 7e-116) leaves every kernel factor of the passes
+// exactly as at 0.
+__device__ __forceinline__ double sqrt_dist(double x) {
+    x = fmax(x, 0x1p-767);
+    const double y = __builtin_amdgcn_rsq(x);
+    double s = x * y, h = 0.5 * y;
+    const double r = fma(-h, s, 0.5);
+    s = fma(s, r, s);
+    h = fma(h, r, h);
+    double d = fma(-s, s, x);
+    s = fma(d, h, s);
+    d = fma(-s, s, x);
+    return fma(d, h, s);
+}
+
 template <> struct Mth<double> {
     static __device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
-    static __device__ __forceinline__ double sqrt(double x) { return ::sqrt(x); }
+    static __device__ __forceinline__ double sqrt(double x) { return sqrt_dist(x); }
     static __device__ __forceinline__ double exp(double x) { return ::exp(x); }
 };
 
