@@ -613,8 +613,12 @@ crk_status crk_set_walk(crk_ctx *ctx, int32_t lanes, int32_t cap, int32_t level_
  * kernel name ("sort", "k_walk", "k_compact_rows", "k_walk_long",
  * "k_extra_rank", "k_volume", "k_moments", "k_corrections", "k_flag",
  * "k_pack", "k_gradv", "k_gradv_fix", "k_deriv", "k_deriv_fix", "k_hsolve",
- * ...); crk_timing_reset clears the sums. */
+ * ...); crk_timing_reset clears the sums. crk_timing_only limits the
+ * events to one kernel name (NULL or "" times every kernel again), so a
+ * caller can time one kernel inside a run without bracketing the others
+ * (each pair of events costs a few microseconds of host and queue time). */
 crk_status crk_timing_enable(crk_ctx *ctx, int32_t on);
+crk_status crk_timing_only(crk_ctx *ctx, const char *kernel);
 crk_status crk_timing_reset(crk_ctx *ctx);
 crk_status crk_timing_read(crk_ctx *ctx, const char *kernel, double *total_ms, int64_t *launches);
 

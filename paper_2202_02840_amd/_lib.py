@@ -20,7 +20,7 @@ EXPORTS = ("crk_params_default", "crk_create", "crk_destroy", "crk_last_error", 
            "crk_build_cells_batch", "crk_build_leaves",
            "crk_update_support", "crk_permute", "crk_moments", "crk_corrections",
            "crk_derivatives", "crk_hsolve", "crk_export_neighbors", "crk_set_lanes", "crk_set_wave_mapping", "crk_set_walk", "crk_set_hsolve",
-           "crk_timing_enable", "crk_timing_reset", "crk_timing_read", "crk_adaptive_rows",
+           "crk_timing_enable", "crk_timing_only", "crk_timing_reset", "crk_timing_read", "crk_adaptive_rows",
            "crk_hnet_features", "crk_hnet_forward", "crk_hnet_train_step",
            "crk_hnet_train_step_noalloc", "crk_hnet_seed",
            "crk_hnet_targets", "crk_step", "crk_graph_capture", "crk_graph_replay",
@@ -124,6 +124,7 @@ def lib():
             "crk_set_walk": ([p, i32, i32, i32], i32),
             "crk_set_hsolve": ([p, i32, i32, i32, d], i32),
             "crk_timing_enable": ([p, i32], i32),
+            "crk_timing_only": ([p, C.c_char_p], i32),
             "crk_timing_reset": ([p], i32),
             "crk_timing_read": ([p, C.c_char_p, p, p], i32),
             "crk_adaptive_rows": ([p, p, p], i32),
@@ -577,6 +578,11 @@ class Context:
 
     def timing(self, on: bool):
         self._check(lib().crk_timing_enable(self._h, int(on)), "crk_timing_enable")
+
+    def timing_only(self, kernel=None):
+        """Time only this kernel name while timing is on (None: every kernel)."""
+        self._check(lib().crk_timing_only(self._h, kernel.encode() if kernel else None),
+                    "crk_timing_only")
 
     def timing_reset(self):
         self._check(lib().crk_timing_reset(self._h), "crk_timing_reset")

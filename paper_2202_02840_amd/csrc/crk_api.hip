@@ -82,6 +82,7 @@ static hipEvent_t pool_get(crk_ctx *c) {
 
 KTimer::KTimer(crk_ctx *ctx, const char *nm) : c(ctx), name(nm) {
     if (!c->timing || c->capturing) return;
+    if (!c->timing_only.empty() && c->timing_only != nm) return;
     a = pool_get(c);
     b = pool_get(c);
     if (a && b && hipEventRecord(a, c->stream) == hipSuccess) return;
@@ -128,6 +129,13 @@ crk_status crk_timing_enable(crk_ctx *c, int32_t on) {
     if (!c) return CRK_ERR_INVALID_ARG;
     CRK_TRY(crk::timing_flush(c));
     c->timing = on ? 1 : 0;
+    return CRK_OK;
+}
+
+crk_status crk_timing_only(crk_ctx *c, const char *kernel) {
+    if (!c) return CRK_ERR_INVALID_ARG;
+    CRK_TRY(crk::timing_flush(c));
+    c->timing_only = kernel ? kernel : "";
     return CRK_OK;
 }
 

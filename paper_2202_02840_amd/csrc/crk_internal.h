@@ -131,6 +131,7 @@ struct crk_ctx {
 
     // per-kernel timing with HIP events on `stream` (crk_timing_*)
     int timing = 0;
+    std::string timing_only;   // non-empty: only this kernel name is timed
     std::vector<hipEvent_t> ev_pool;
     std::vector<std::pair<std::string, std::pair<hipEvent_t, hipEvent_t>>> ev_pend;
     std::map<std::string, std::pair<double, int64_t>> ev_total;

@@ -232,3 +232,28 @@ def test_workspace_estimate_bounds_a_step(prec):
     print(f"[case] n={ps.n} pairs={out['n_pairs']} held={held} bound={bound}", flush=True)
     assert out["n_pairs"] == ref_pairs
     assert held <= bound
+
+
+def test_timing_only_one_kernel():
+    # with the filter only the named kernel is bracketed by events; without
+    # it every kernel of the step is, and the outputs do not depend on either
+    ps = ci.lognormal_box(16, sigma=1.5, seed=57)
+    print(f"[case] timing filter n={ps.n}", flush=True)
+    ctx = Context(0)
+    dev = pl.upload(ps)
+    prm = pl.params_for(ps, 64.0, CRK_MIXED_ADAPT)
+    base = pl.step(ctx, dev, prm, count_singular=False)
+    ctx.timing(True)
+    ctx.timing_only("k_deriv")
+    ctx.timing_reset()
+    one = pl.step(ctx, dev, prm, count_singular=False)
+    assert ctx.timing_read("k_deriv")[1] == 1
+    assert ctx.timing_read("k_walk")[1] == 0 and ctx.timing_read("k_moments")[1] == 0
+    ctx.timing_only(None)
+    ctx.timing_reset()
+    pl.step(ctx, dev, prm, count_singular=False)
+    assert ctx.timing_read("k_deriv")[1] == 1 and ctx.timing_read("k_walk")[1] == 1
+    assert ctx.timing_read("k_moments")[1] == 1
+    ctx.timing(False)
+    for k in ("gradv", "dpdt", "dudt"):
+        assert torch.equal(base[k], one[k]), k
