@@ -184,17 +184,17 @@ __global__ __launch_bounds__(kBlock) void k_fill_i32(int32_t *a, int64_t n, int3
     if (i < n) a[i] = v;
 }
 
-// zeros into two int32 arrays of n entries (16-byte aligned), four entries
-// per store, one launch for both
+// zeros into two int32 arrays of n entries (16-byte aligned; b may be
+// null), four entries per store, one launch for both
 __global__ __launch_bounds__(kBlock) void k_zero2_i32(int32_t *a, int32_t *b, int64_t n) {
     const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x, n4 = n >> 2;
     const int4 z = make_int4(0, 0, 0, 0);
     if (t < n4) {
         ((int4 *)a)[t] = z;
-        ((int4 *)b)[t] = z;
+        if (b) ((int4 *)b)[t] = z;
     } else if (t < n4 + (n & 3)) {
         a[4 * n4 + (t - n4)] = 0;
-        b[4 * n4 + (t - n4)] = 0;
+        if (b) b[4 * n4 + (t - n4)] = 0;
     }
 }
 
@@ -284,7 +284,7 @@ __device__ __forceinline__ void walk_row(const double4 *__restrict__ posH, int64
                         int pos = cg + (G == 1 ? 0 : __popc(hm & below));
                         if (DIRECT) {
                             gidx[goff[i] + pos] = j;
-                            if (extra) etmp[eoff[j] + atomicAdd(&efill[j], 1)] = (int32_t)i;
+                            if (extra) etmp[atomicAdd(&efill[j], 1)] = (int32_t)i;
                         } else {
                             if (pos < cap) row[pos] = (uint32_t)j | (extra ? 0x80000000u : 0u);
                             if (extra) atomicAdd(&rcnt[j], 1);
@@ -412,7 +412,7 @@ __device__ __forceinline__ void walk_row_flat(const double4 *__restrict__ posH, 
                 const int pos = cg + __popc(hm & below);
                 if (DIRECT) {
                     gidx[goff[i] + pos] = j;
-                    if (extra) etmp[eoff[j] + atomicAdd(&efill[j], 1)] = (int32_t)i;
+                    if (extra) etmp[atomicAdd(&efill[j], 1)] = (int32_t)i;
                 } else {
                     if (pos < cap) row[pos] = (uint32_t)j | (extra ? 0x80000000u : 0u);
                     if (extra) atomicAdd(&rcnt[j], 1);
@@ -543,7 +543,8 @@ __global__ __launch_bounds__(kBlock) void k_walk_scratch(const double4 *__restri
 // scratch rows -> gather rows, for rows that fit in cap (G lanes per row
 // read and write consecutive slots; longer rows are listed for the second
 // walk); each extra (j, i) goes to a slot of row j of the transposed lists
-// (slot order is fixed later by rank). A lane takes U entries of its row at
+// (efill[j], which the offsets scan set to row j's start, hands out its
+// places; slot order is fixed later by rank). A lane takes U entries of its row at
 // a time: their loads, then the slot atomics of their extras, then the
 // dependent stores, so the atomics' round trips overlap instead of
 // following one another.
@@ -551,8 +552,7 @@ template <int G, int U>
 __global__ __launch_bounds__(kBlock) void k_compact_rows(const uint32_t *__restrict__ scratch, int cap,
                                                          int64_t n, const int32_t *__restrict__ ng,
                                                          const int64_t *__restrict__ goff, int32_t *gidx,
-                                                         const int64_t *__restrict__ eoff, int32_t *efill,
-                                                         int32_t *etmp, int32_t *longs) {
+                                                         int32_t *efill, int32_t *etmp, int32_t *longs) {
     int64_t gid = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
     const int l = (int)(gid % G);
     const int64_t i = gid / G;
@@ -576,24 +576,14 @@ __global__ __launch_bounds__(kBlock) void k_compact_rows(const uint32_t *__restr
             ex[u] = k < cnt && (w[u] & 0x80000000u);
             if (k < cnt) gidx[gw + k] = (int32_t)(w[u] & 0x7fffffffu);
         }
-        // the returned slots are used only after every atomic is issued
-        int64_t eo[U];
-        int32_t sl[U];
+        // the returned places are used only after every atomic is issued
+        // (efill[j] starts at row j's offset, so the atomic returns the place)
+        int32_t at[U];
 #pragma unroll
         for (int u = 0; u < U; u++) {
-            eo[u] = 0;
-            sl[u] = 0;
-            if (ex[u]) {
-                const int32_t j = (int32_t)(w[u] & 0x7fffffffu);
-                eo[u] = eoff[j];
-                sl[u] = atomicAdd(&efill[j], 1);
-            }
+            at[u] = -1;
+            if (ex[u]) at[u] = atomicAdd(&efill[(int32_t)(w[u] & 0x7fffffffu)], 1);
         }
-        // every target address before the first store (a store counts in
-        // the same in-order counter as the loads it would otherwise wait for)
-        int64_t at[U];
-#pragma unroll
-        for (int u = 0; u < U; u++) at[u] = ex[u] ? eo[u] + sl[u] : -1;
 #pragma unroll
         for (int u = 0; u < U; u++)
             if (at[u] >= 0) etmp[at[u]] = (int32_t)i;
@@ -776,7 +766,7 @@ static crk_status build_lists(crk_ctx *c) {
     // long rows: longs[0] counts them, their particles follow
     CRK_TRY(ensure(c, c->longs, (size_t)(n + 1) * sizeof(int32_t)));
     int32_t *longs = (int32_t *)c->longs.p;
-    k_zero2_i32<<<nblocks((n >> 2) + (n & 3)), kBlock, 0, c->stream>>>(ecnt, efill, n);
+    k_zero2_i32<<<nblocks((n >> 2) + (n & 3)), kBlock, 0, c->stream>>>(ecnt, nullptr, n);
     k_fill_i32<<<1, kBlock, 0, c->stream>>>(longs, 1, 0);
     {
         KTimer kt_(c, "k_walk");
@@ -793,7 +783,9 @@ static crk_status build_lists(crk_ctx *c) {
 #undef L_WALK
     }
     CRK_HIP(c, hipGetLastError());
-    CRK_TRY(scan_counts2(c, ng, ecnt, n, goff, eoff, goff + n + 1));
+    // efill[j] = eoff[j]: the slot counters of the extras rows start at
+    // their rows' offsets
+    CRK_TRY(scan_counts2(c, ng, ecnt, n, goff, eoff, goff + n + 1, efill));
     int64_t G, E, longest = 0;
     GraphStat *gst = (GraphStat *)c->gstat.p;
     if (c->graph_mode) {
@@ -824,7 +816,7 @@ static crk_status build_lists(crk_ctx *c) {
         KTimer kt_(c, "k_compact_rows");
         constexpr int GC = 16, UC = 8;
         k_compact_rows<GC, UC><<<(unsigned)((n * GC + kBlock - 1) / kBlock), kBlock, 0, c->stream>>>(
-            scratch, cap, n, ng, goff, (int32_t *)c->gidx.p, eoff, efill, etmp, longs);
+            scratch, cap, n, ng, goff, (int32_t *)c->gidx.p, efill, etmp, longs);
     }
     {
         // the rows over the cap are few and long: 32 lanes each (the row is

@@ -189,9 +189,9 @@ crk_status scan_exclusive_i64(crk_ctx *c, const int64_t *in, int64_t *out, int64
 // offsets of n rows from two int32 count arrays at once: oa[k] = sum of
 // a[0..k) for k = 0..n (oa[n] the total), likewise ob from b (b and ob
 // both null: a alone); with amax (device) also the largest entry of a (0
-// when n = 0)
+// when n = 0); with ob32 also ob[0..n) as int32 (the totals fit in 31 bits)
 crk_status scan_counts2(crk_ctx *c, const int32_t *a, const int32_t *b, int64_t n, int64_t *oa,
-                        int64_t *ob, int64_t *amax = nullptr);
+                        int64_t *ob, int64_t *amax = nullptr, int32_t *ob32 = nullptr);
 // stable LSD radix sort of (key, value) pairs on the low `bits` bits of the keys
 crk_status radix_sort_pairs(crk_ctx *c, uint32_t *keys, int32_t *vals, int64_t n, int bits);
 

@@ -126,10 +126,12 @@ __global__ __launch_bounds__(kBlock) void k_max_i64(const int64_t *bm, int64_t m
     if (threadIdx.x == 0) *out = mx;
 }
 
+// (with o32: the first nin offsets of the second array also as int32)
 template <bool VEC>
 __global__ __launch_bounds__(kBlock) void k_scan_apply2(const int32_t *in0, const int32_t *in1, int64_t nin,
                                                         int64_t nout, int64_t *out0, int64_t *out1,
-                                                        const int64_t *bo0, const int64_t *bo1) {
+                                                        const int64_t *bo0, const int64_t *bo1,
+                                                        int32_t *o32) {
     __shared__ int64_t lds[4];
     const int32_t *in = blockIdx.y ? in1 : in0;
     int64_t *out = blockIdx.y ? out1 : out0;
@@ -156,6 +158,16 @@ __global__ __launch_bounds__(kBlock) void k_scan_apply2(const int32_t *in0, cons
 #pragma unroll
         for (int k = 0; k < 8; k++)
             if (base + k < nout) out[base + k] = o[k];
+    }
+    if (o32 && blockIdx.y == 1) {
+        if (VEC && base + 8 <= nin) {
+            *(int4 *)(o32 + base) = make_int4((int32_t)o[0], (int32_t)o[1], (int32_t)o[2], (int32_t)o[3]);
+            *(int4 *)(o32 + base + 4) = make_int4((int32_t)o[4], (int32_t)o[5], (int32_t)o[6], (int32_t)o[7]);
+        } else {
+#pragma unroll
+            for (int k = 0; k < 8; k++)
+                if (base + k < nin) o32[base + k] = (int32_t)o[k];
+        }
     }
 }
 
@@ -296,16 +308,17 @@ crk_status scan_exclusive_i64(crk_ctx *c, const int64_t *in, int64_t *out, int64
 }
 
 crk_status scan_counts2(crk_ctx *c, const int32_t *a, const int32_t *b, int64_t n, int64_t *oa,
-                        int64_t *ob, int64_t *amax) {
+                        int64_t *ob, int64_t *amax, int32_t *ob32) {
     if (n < 0) return set_err(c, CRK_ERR_INVALID_ARG, "negative count");
-    if ((b == nullptr) != (ob == nullptr)) return set_err(c, CRK_ERR_INVALID_ARG, "scan_counts2: b without ob");
+    if ((b == nullptr) != (ob == nullptr) || (ob32 && !b))
+        return set_err(c, CRK_ERR_INVALID_ARG, "scan_counts2: b, ob and ob32 do not match");
     const unsigned ny = b ? 2u : 1u;
     const int64_t nout = n + 1, nblk = (nout + kScanTile - 1) / kScanTile;
     const size_t need = scan_need(nblk);
     CRK_TRY(ensure(c, c->scanTmp, (3 * (size_t)nblk + need + 16) * sizeof(int64_t)));
     int64_t *bs0 = (int64_t *)c->scanTmp.p, *bs1 = bs0 + nblk, *bm = bs1 + nblk, *tail = bm + nblk;
     auto al16 = [](const void *q) { return ((uintptr_t)q & 15u) == 0; };
-    const bool vec = al16(a) && al16(oa) && (!b || (al16(b) && al16(ob)));
+    const bool vec = al16(a) && al16(oa) && (!b || (al16(b) && al16(ob))) && (!ob32 || al16(ob32));
     if (vec)
         k_scan_sums2<true><<<dim3((unsigned)nblk, ny), kBlock, 0, c->stream>>>(a, b, n, bs0, bs1, amax ? bm : nullptr);
     else
@@ -320,9 +333,9 @@ crk_status scan_counts2(crk_ctx *c, const int32_t *a, const int32_t *b, int64_t 
         if (b) CRK_TRY(scan_with(c, bs1, bs1, nblk, tail));
     }
     if (vec)
-        k_scan_apply2<true><<<dim3((unsigned)nblk, ny), kBlock, 0, c->stream>>>(a, b, n, nout, oa, ob, bs0, bs1);
+        k_scan_apply2<true><<<dim3((unsigned)nblk, ny), kBlock, 0, c->stream>>>(a, b, n, nout, oa, ob, bs0, bs1, ob32);
     else
-        k_scan_apply2<false><<<dim3((unsigned)nblk, ny), kBlock, 0, c->stream>>>(a, b, n, nout, oa, ob, bs0, bs1);
+        k_scan_apply2<false><<<dim3((unsigned)nblk, ny), kBlock, 0, c->stream>>>(a, b, n, nout, oa, ob, bs0, bs1, ob32);
     CRK_HIP(c, hipGetLastError());
     return CRK_OK;
 }
