@@ -32,7 +32,8 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# MI355X peaks: HBM3E bandwidth, and the vector ALU rate of this build.
+# MI355X peaks: HBM3E bandwidth, and the vector ALU rate of code compiled
+# without packed FP32 instructions (as the library is).
 # 256 CUs x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz = 78.6 TFLOP/s for
 # FP64 and for unpacked FP32; the 157.3 TFLOP/s FP32 figure needs packed
 # FP32 instructions, which this library is compiled without.

@@ -497,8 +497,8 @@ crk_status crk_hsolve(crk_ctx *ctx, double Nres, double tol, int32_t max_iter, d
 
 /*
  * S9: smoothing-length network (an addition to the paper's method: a learned
- * starting value for the iteration of eq. (thacker); the iteration stays the
- * judge of the converged H). An 8 -> 64 -> 64 -> 1 MLP, exact-erf GELU, FP32:
+ * starting value for the iteration of eq. (thacker); the iteration alone
+ * decides the converged H). An 8 -> 64 -> 64 -> 1 MLP, exact-erf GELU, FP32:
  *   z1 = W1 f + b1, a1 = gelu(z1), z2 = W2 a1 + b2, a2 = gelu(z2), y = w3.a2 + b3,
  * y = ln(H_conv / H_prev). theta[4801] (device, float) holds W1 [64][8]
  * (row-major), b1 [64], W2 [64][64], b2 [64], w3 [64], b3.

@@ -6,7 +6,7 @@ Training pairs come from the plain iteration of eq. (thacker): for a box
 with starting support radii H_prev, the features at H_prev and the target
 ln(H_conv / H_prev), H_conv being the converged radius. At use, the network
 proposes H_seed = H_prev exp(y) and the same plain iteration finishes from
-there; it stays the judge of the converged H.
+there; the iteration alone decides the converged H.
 """
 from __future__ import annotations
 
