@@ -108,7 +108,7 @@ struct crk_ctx {
         double L, cell;
         int nc, bits;
     } geo{};                              // geometry the graph was recorded with
-    int G_hsolve = 16, hs_round = 8, hs_cap = 320;
+    int G_hsolve = 16, hs_round = 12, hs_cap = 320;
     double hs_factor = 1.15;
     int64_t last_nflag = 0, last_ntouch = 0;
     crk::Buf pinned;        // small host-pinned readback area
