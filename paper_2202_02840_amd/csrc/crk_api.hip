@@ -225,7 +225,7 @@ static std::vector<crk::Buf *> ctx_buffers(crk_ctx *c) {
                        &c->hnet_part, &c->hnet_feat, &c->hs_list, &c->hs_state, &c->hs_pos,
                        &c->hs_iters, &c->hs_pool, &c->hs_rows, &c->hs_rcnt, &c->hs_R, &c->boff,
                        &c->sv, &c->sm, &c->su, &c->srho, &c->gstat, &c->gboff,
-                       &c->ecnt, &c->efill, &c->eoff, &c->etmp, &c->longs, &c->posV, &c->rq, &c->rsk, &c->rla, &c->rlb, &c->rside,
+                       &c->ecnt, &c->efill, &c->eoff, &c->etmp, &c->vnsum, &c->longs, &c->posV, &c->rq, &c->rsk, &c->rla, &c->rlb, &c->rside,
                        &c->rpnode, &c->rscan, &c->rnode, &c->rtab, &c->rbox, &c->rpoff, &c->rpart, &c->ts_vs, &c->ts_qr, &c->ce, &c->ced, &c->vstep};
 }
 
@@ -293,6 +293,7 @@ crk_status crk_workspace_estimate(const crk_ctx *c, int64_t n, int32_t nboxes,
     t += held(4.0 * N) + held(8.0 * (N + 2.0)) + held(8.0 * (N + 1.0)) + 2 * held(4.0 * N);   // counts, offsets
     t += held(4.0 * N * walk_cap) + held(4.0 * (N + 1.0));                // walk rows, long rows
     t += held(4.0 * P) + 2 * held(4.0 * 0.5 * P) + 2 * held(4.0 * N);    // N_g rows, extras (E <= P/2)
+    if (precision != CRK_MIXED) t += held(8.0 * N);                       // the build's FP64 volumes
     // passes
     const bool f64 = precision == CRK_FP64, adapt = precision == CRK_MIXED_ADAPT;
     t += held((precision == CRK_MIXED ? 4.0 : 8.0) * N) + held(32.0 * N);   // volumes; positions with V

@@ -548,11 +548,20 @@ __global__ __launch_bounds__(kBlock) void k_walk_scratch(const double4 *__restri
 // a time: their loads, then the slot atomics of their extras, then the
 // dependent stores, so the atomics' round trips overlap instead of
 // following one another.
+//
+// With vnsum, each row's FP64 volume sum of eq. (vol) comes along: the
+// group re-reads its row (in cache) and adds W(r_ij, H_i) over the self
+// pair and every gather entry, the terms of the volume pass (same
+// separations, square root and weight) in another order; n_i goes to
+// vnsum[i] and (x_i, V_i = 1 / n_i) to posV[i]. The rows past cap get
+// theirs from k_volume_longs after the second walk.
 template <int G, int U>
 __global__ __launch_bounds__(kBlock) void k_compact_rows(const uint32_t *__restrict__ scratch, int cap,
                                                          int64_t n, const int32_t *__restrict__ ng,
                                                          const int64_t *__restrict__ goff, int32_t *gidx,
-                                                         int32_t *efill, int32_t *etmp, int32_t *longs) {
+                                                         int32_t *efill, int32_t *etmp, int32_t *longs,
+                                                         const double4 *__restrict__ posH, Box box,
+                                                         double *vnsum, double4 *posV) {
     int64_t gid = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
     const int l = (int)(gid % G);
     const int64_t i = gid / G;
@@ -587,6 +596,74 @@ __global__ __launch_bounds__(kBlock) void k_compact_rows(const uint32_t *__restr
 #pragma unroll
         for (int u = 0; u < U; u++)
             if (at[u] >= 0) etmp[at[u]] = (int32_t)i;
+    }
+    if (vnsum) {
+        const double4 pi = posH[i];
+        const double invH = 1.0 / pi.w;
+        const double cw = kW * invH * invH * invH;
+        double s = l == 0 ? cw : 0.0;   // the self pair: W(0, H_i)
+        // four partners' positions in flight at a time; the terms are added
+        // in the order k = l, l + G, ... all the same
+        constexpr int VB = 4;
+        for (int k0 = l; k0 < cnt; k0 += VB * G) {
+            double4 pj[VB];
+#pragma unroll
+            for (int u = 0; u < VB; u++)
+                if (k0 + u * G < cnt) pj[u] = posH[row[k0 + u * G] & 0x7fffffffu];
+#pragma unroll
+            for (int u = 0; u < VB; u++) {
+                if (k0 + u * G >= cnt) break;
+                const double dx = pair_image(pi.x - pj[u].x, box), dy = pair_image(pi.y - pj[u].y, box),
+                             dz = pair_image(pi.z - pj[u].z, box);
+                const double q = sqrt_dist(dx * dx + dy * dy + dz * dz) * invH;
+                s += kernel_w(q, cw);
+            }
+        }
+#pragma unroll
+        for (int m = G / 2; m >= 1; m >>= 1) s += __shfl_xor(s, m, G);
+        if (l == 0) {
+            vnsum[i] = s;
+            posV[i] = make_double4(pi.x, pi.y, pi.z, 1.0 / s);
+        }
+    }
+}
+
+// The FP64 volume sums of the rows listed in longs (those over the scratch
+// rows' cap, written into place by the second walk), as k_compact_rows
+// forms them (with its G, lane l adds entries l, l + G, ... and the same
+// reduction follows, so the sum is bit for bit the compaction's), over a
+// grid of any size.
+template <int G>
+__global__ __launch_bounds__(kBlock) void k_volume_longs(const int32_t *__restrict__ longs,
+                                                         const int32_t *__restrict__ ng, int cap,
+                                                         const int64_t *__restrict__ goff,
+                                                         const int32_t *__restrict__ gidx,
+                                                         const double4 *__restrict__ posH, Box box,
+                                                         double *vnsum, double4 *posV) {
+    const int64_t gid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int l = (int)(gid % G);
+    const int64_t nl = longs[0];
+    const int64_t stride = (int64_t)gridDim.x * (kBlock / G);
+    for (int64_t t = gid / G; t < nl; t += stride) {
+        const int64_t i = longs[1 + t];
+        if (ng[i] <= cap) continue;   // cleared by an overflowed recorded step
+        const double4 pi = posH[i];
+        const double invH = 1.0 / pi.w;
+        const double cw = kW * invH * invH * invH;
+        double s = l == 0 ? cw : 0.0;
+        for (int64_t k = goff[i] + l; k < goff[i + 1]; k += G) {
+            const double4 pj = posH[gidx[k]];
+            const double dx = pair_image(pi.x - pj.x, box), dy = pair_image(pi.y - pj.y, box),
+                         dz = pair_image(pi.z - pj.z, box);
+            const double q = sqrt_dist(dx * dx + dy * dy + dz * dz) * invH;
+            s += kernel_w(q, cw);
+        }
+#pragma unroll
+        for (int m = G / 2; m >= 1; m >>= 1) s += __shfl_xor(s, m, G);
+        if (l == 0) {
+            vnsum[i] = s;
+            posV[i] = make_double4(pi.x, pi.y, pi.z, 1.0 / s);
+        }
     }
 }
 
@@ -812,11 +889,24 @@ static crk_status build_lists(crk_ctx *c) {
     CRK_TRY(ensure(c, c->eb, (size_t)n * sizeof(int32_t)));
     CRK_TRY(ensure(c, c->ee, (size_t)n * sizeof(int32_t)));
     int32_t *etmp = (int32_t *)c->etmp.p, *eidx = (int32_t *)c->eidx.p;
+    // the FP64 volumes of eq. (vol) come with the compaction when wanted
+    const bool vol = c->vol_in_build != 0;
+    double *vnsum = nullptr;
+    double4 *posV = nullptr;
+    if (vol) {
+        CRK_TRY(ensure(c, c->vnsum, (size_t)n * sizeof(double)));
+        CRK_TRY(ensure(c, c->posV, (size_t)n * sizeof(double4)));
+        vnsum = (double *)c->vnsum.p;
+        posV = (double4 *)c->posV.p;
+    }
+    const Box box{c->L, 1.0 / c->L};
+    // (the long rows' volumes take the same lanes per row, so a row's sum
+    // does not depend on which of the two kernels forms it)
+    constexpr int GC = 16, UC = 8;
     {
         KTimer kt_(c, "k_compact_rows");
-        constexpr int GC = 16, UC = 8;
         k_compact_rows<GC, UC><<<(unsigned)((n * GC + kBlock - 1) / kBlock), kBlock, 0, c->stream>>>(
-            scratch, cap, n, ng, goff, (int32_t *)c->gidx.p, efill, etmp, longs);
+            scratch, cap, n, ng, goff, (int32_t *)c->gidx.p, efill, etmp, longs, posH, box, vnsum, posV);
     }
     {
         // the rows over the cap are few and long: 32 lanes each (the row is
@@ -829,6 +919,12 @@ static crk_status build_lists(crk_ctx *c) {
             etmp, c->walk_shift, longs);
     }
     CRK_HIP(c, hipGetLastError());
+    if (vol) {
+        const unsigned nb = (unsigned)std::min<int64_t>((n * GC + kBlock - 1) / kBlock, 1024);
+        k_volume_longs<GC><<<nb, kBlock, 0, c->stream>>>(longs, ng, cap, goff, (const int32_t *)c->gidx.p,
+                                                          posH, box, vnsum, posV);
+        CRK_HIP(c, hipGetLastError());
+    }
     // each extras row ascending in the emitting particle
     {
         KTimer kt_(c, "k_extra_rank");
@@ -848,6 +944,7 @@ static crk_status build_lists(crk_ctx *c) {
     }
     c->built = 1;
     c->have_V = 0;
+    c->vol_ready = vol ? 1 : 0;
     return CRK_OK;
 }
 
@@ -926,6 +1023,10 @@ crk_status crk_build_cells_batch(crk_ctx *c, int32_t nboxes, const int64_t *box_
         c->nboxes = nboxes;
     }
     c->have_V = 0;
+    c->vol_ready = 0;
+    // the FP64 volumes come with the lists unless the pure FP32 mode is asked
+    // for (its volume pass sums in FP32)
+    c->vol_in_build = p->precision != CRK_MIXED;
     // 1. validate and reduce H
     int nblk = (int)std::min<int64_t>((n + kBlock - 1) / kBlock, 1024);
     CRK_TRY(ensure(c, c->red, (size_t)nblk * 3 * sizeof(double) + 64));

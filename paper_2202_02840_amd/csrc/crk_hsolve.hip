@@ -609,6 +609,7 @@ crk_status crk_hsolve(crk_ctx *c, double Nres, double tol, int32_t max_iter, dou
     // the lists no longer match the support radii
     c->built = 0;
     c->have_V = 0;
+    c->vol_ready = 0;
     k_set_H2<<<nb, kBlock, 0, c->stream>>>((double4 *)c->posH.p, H_inout, n);
     CRK_HIP(c, hipGetLastError());
     if (pc[0]) return CRK_WARN_NOT_CONVERGED;

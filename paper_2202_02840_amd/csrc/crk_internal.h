@@ -63,6 +63,10 @@ struct crk_ctx {
     int64_t nboxes = 1;
     int built = 0;          // lists valid
     int have_V = 0;         // recV valid (after crk_moments)
+    // FP64 volumes summed by the build's compaction (vnsum, and V in posV.w)
+    // for the current lists: wanted when the build's precision is not the
+    // pure FP32 one, valid until the lists or the supports change
+    int vol_in_build = 0, vol_ready = 0;
     int prec_V = -1;        // precision recV was written in
     int64_t npairs = 0;     // sum of |N_s(i)|
     int64_t ngather = 0;    // sum of ng (excludes self)
@@ -86,6 +90,7 @@ struct crk_ctx {
     crk::Buf gstat;                                       // device status of a graph step
     crk::Buf gboff;                                       // box offsets the graph was recorded with
     crk::Buf ecnt, efill, eoff, etmp;                     // extras rows: counts, slots, offsets, unordered rows
+    crk::Buf vnsum;                                       // FP64 n_i of the build (vol_ready)
     crk::Buf longs;                                       // rows past the walk cap: count, then particles
     crk::Buf posV;                                        // sorted x, y, z and V (the moment pass reads both at once)
     // RCB leaf tiling (crk_build_leaves): keys, the three sorted lists (two
@@ -215,6 +220,52 @@ __device__ __forceinline__ double r2_exact(double dx, double dy, double dz) {
 #pragma clang fp contract(off)
     return (dx * dx + dy * dy) + dz * dz;
 }
+
+// ---- the FP64 volume sum of eq. (vol): shared by the volume pass and the
+// build's compaction, which forms the same terms
+
+// Square root of a squared distance x >= 0: Newton-Raphson refinement of the
+// hardware reciprocal square root estimate y ~ 1/sqrt(x), as coupled
+// iterations for s ~ sqrt(x) and h ~ 1/(2 sqrt(x)) (one coupled step, then
+// two corrections of s by the residual x - s^2), the same steps the
+// correctly rounded library square root takes for arguments of normal range.
+// x is first raised to 2^-767, the bound below which the library rescales
+// its argument: no distance of distinct particles comes near it, and at
+// x = 0 the result (about 7e-116) leaves every kernel factor of the passes
+// exactly as at 0.
+__device__ __forceinline__ double sqrt_dist(double x) {
+    x = fmax(x, 0x1p-767);
+    const double y = __builtin_amdgcn_rsq(x);
+    double s = x * y, h = 0.5 * y;
+    const double r = fma(-h, s, 0.5);
+    s = fma(s, r, s);
+    h = fma(h, r, h);
+    double d = fma(-s, s, x);
+    s = fma(d, h, s);
+    d = fma(-s, s, x);
+    return fma(d, h, s);
+}
+
+struct Box {
+    double L, invL;
+};
+
+// Minimum image of a listed pair: d - L rint(d / L), one fused rounding,
+// so the value equals d, d - L or d + L exactly as the branch form gives;
+// a listed pair has |d| < H < L/2 per component, far from the tie at L/2
+// (neighbour decisions themselves use the branch form).
+__device__ __forceinline__ double pair_image(double d, const Box &b) {
+    return fma(-b.L, rint(d * b.invL), d);
+}
+
+// Wendland C4 weight of eq. (C4) at q = r/H with the prefactor cw = kW H^-3
+template <typename T>
+__device__ __forceinline__ T kernel_w(T q, T cw) {
+    T s = q < (T)1 ? (T)1 - q : (T)0;
+    T s2 = s * s;
+    return cw * s2 * s2 * s2 * ((T)1 + q * ((T)6 + q * (T)(35.0 / 3.0)));
+}
+
 
 // Uniform periodic cell grid of side c = L / nc over the sorted particles.
 struct Grid {

@@ -531,6 +531,7 @@ crk_status crk_build_leaves(crk_ctx *c, int32_t nboxes, const int64_t *box_offse
     CRK_HIP(c, hipSetDevice(c->device));
     c->built = 0;
     c->have_V = 0;
+    c->vol_ready = 0;
     c->leaf_mode = 0;
     c->nc = 0;   // no cell hierarchy: the calls that walk cells refuse
     c->n = n;

@@ -33,28 +33,6 @@ template <> struct Mth<float> {
     static __device__ __forceinline__ float sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
     static __device__ __forceinline__ float exp(float x) { return __expf(x); }
 };
-// Square root of a squared distance x >= 0: Newton-Raphson refinement of the
-// hardware reciprocal square root estimate y ~ 1/sqrt(x), as coupled
-// iterations for s ~ sqrt(x) and h ~ 1/(2 sqrt(x)) (one coupled step, then
-// two corrections of s by the residual x - s^2), the same steps the
-// correctly rounded library square root takes for arguments of normal range.
-// x is first raised to 2^-767, the bound below which the library rescales
-// its argument: no distance of distinct particles comes near it, and at
-// x = 0 the result (about 7e-116) leaves every kernel factor of the passes
-// exactly as at 0.
-__device__ __forceinline__ double sqrt_dist(double x) {
-    x = fmax(x, 0x1p-767);
-    const double y = __builtin_amdgcn_rsq(x);
-    double s = x * y, h = 0.5 * y;
-    const double r = fma(-h, s, 0.5);
-    s = fma(s, r, s);
-    h = fma(h, r, h);
-    double d = fma(-s, s, x);
-    s = fma(d, h, s);
-    d = fma(-s, s, x);
-    return fma(d, h, s);
-}
-
 template <> struct Mth<double> {
     static __device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
     static __device__ __forceinline__ double sqrt(double x) { return sqrt_dist(x); }
@@ -95,18 +73,6 @@ __device__ __forceinline__ void group_reduce(Acc<T> (&a)[K]) {
     for (int m = G / 2; m >= 1; m >>= 1)
 #pragma unroll
         for (int k = 0; k < K; k++) a[k].merge_xor(m, G);
-}
-
-struct Box {
-    double L, invL;
-};
-
-// Minimum image of a listed pair: d - L rint(d / L), one fused rounding,
-// so the value equals d, d - L or d + L exactly as the branch form gives;
-// a listed pair has |d| < H < L/2 per component, far from the tie at L/2
-// (neighbour decisions themselves use the branch form).
-__device__ __forceinline__ double pair_image(double d, const Box &b) {
-    return fma(-b.L, rint(d * b.invL), d);
 }
 
 // Fixed-point coordinate of x in [0, L): Q = floor(x 2^42 / L), kept as
@@ -177,13 +143,6 @@ __device__ __forceinline__ void kfac(T q, T &pw, T &pg) {
     const T s5 = s2 * s2 * s;
     pw = s5 * s * ((T)1 + q * ((T)6 + q * (T)(35.0 / 3.0)));
     pg = ((T)1 + (T)5 * q) * s5;
-}
-
-template <typename T>
-__device__ __forceinline__ T kernel_w(T q, T cw) {
-    T s = q < (T)1 ? (T)1 - q : (T)0;
-    T s2 = s * s;
-    return cw * s2 * s2 * s2 * ((T)1 + q * ((T)6 + q * (T)(35.0 / 3.0)));
 }
 
 __device__ __forceinline__ int64_t group_index(int G, int &lane) {
@@ -1728,6 +1687,17 @@ inline unsigned pblocks(int64_t n, int P) {
 
 // volume then (optionally) moment pass in type T, with the lane mapping of
 // the context (balanced groups of P particles per wave, or G lanes each)
+// n_i and V_i of the volumes the build summed (vnsum, posV.w) into the
+// caller's arrays
+__global__ __launch_bounds__(kBlock) void k_volume_out(int64_t n, const double *__restrict__ vnsum,
+                                                       const double4 *__restrict__ posV, double *nsum,
+                                                       double *V) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    if (nsum) nsum[i] = vnsum[i];
+    V[i] = posV[i].w;
+}
+
 template <typename T>
 crk_status volume_moments(crk_ctx *c, const double4 *posH, const int64_t *goff, const int32_t *gidx,
                           int64_t n, Box box, double *nsum, double *V, T *rv, bool want_m, double *m0,
@@ -1735,7 +1705,11 @@ crk_status volume_moments(crk_ctx *c, const double4 *posH, const int64_t *goff, 
     const int Gv = c->G_vol, Gm = c->G_mom, Pv = c->P_vol, Pm = c->P_mom;
     CRK_TRY(ensure(c, c->posV, (size_t)n * sizeof(double4)));
     double4 *posV = (double4 *)c->posV.p;
-    {
+    if (sizeof(T) == 8 && c->vol_ready) {
+        // the build's compaction summed these FP64 volumes with the lists
+        KTimer kt_(c, "k_volume");
+        k_volume_out<<<nblocks(n), kBlock, 0, c->stream>>>(n, (const double *)c->vnsum.p, posV, nsum, V);
+    } else {
         KTimer kt_(c, "k_volume");
         if (Pv > 0) {
 #define L_VOL(PP) k_volume_bal<T, PP><<<pblocks(n, PP), kBlock, 0, c->stream>>>(posH, goff, gidx, n, box, nsum, V, rv, posV)
