@@ -268,13 +268,25 @@ def full_size_leg(args, prec, theta=None) -> dict:
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t2) * 1e3 / max(args.steps, 1)
     npairs = int(out["n_pairs"])
+    # per-kernel event times from two more steps (every kernel bracketed)
+    ctx.timing(True)
+    ctx.timing_reset()
+    for _ in range(2):
+        pl.step(ctx, dev, prm, count_singular=False)
+    torch.cuda.synchronize()
+    kern = {}
+    for k in ("sort", "k_walk", "k_compact_rows", "k_walk_long", "k_extra_rank", "k_volume", "k_moments",
+              "k_corrections", "k_flag", "k_pack", "k_gradv", "k_gradv_fix", "k_deriv", "k_deriv_fix"):
+        kms, cnt = ctx.timing_read(k)
+        kern[k] = kms / max(cnt, 1)
+    ctx.timing(False)
     res = {"workload": f"lognormal {args.full_side}^3 sigma 2.0, P(k)~k^-2.5, 1% in 64 clumps at "
                        f"100x mean density, seed 5; h iteration from the generator's H to 1e-8, "
                        f"then the {args.precision} step at the converged H",
            "particles": ps.n, "pairs_per_step": npairs, "step_ms": ms,
            "step_pairs_per_s": npairs / (ms * 1e-3), "h_iteration": hres,
            "h_iteration_used": use,
-           "full_step_ms": ms + hres[use]["seconds"] * 1e3, "lanes": cfg,
+           "full_step_ms": ms + hres[use]["seconds"] * 1e3, "lanes": cfg, "kernel_ms": kern,
            "generate_seconds": gen_s}
     if not args.no_check:
         ref = pl.step(ctx, dev, pl.params_for(ps, 64.0, CRK_FP64), count_singular=False)

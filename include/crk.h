@@ -601,8 +601,8 @@ crk_status crk_set_hsolve(crk_ctx *ctx, int32_t lanes, int32_t round, int32_t ca
  * place (0 keeps either value). After an eager build the next walk uses at
  * least 2.5 times that build's mean gather row and, where its longest gather
  * row was longer, that row plus an eighth, as far as n x slots stays within
- * 2^31 (multiples of 64, at most 1024 slots; so at 2^21 particles up to 8
- * GiB of rows), so cap is a floor (default 192). level_shift s (0..3; -1 keeps) walks the
+ * 2^33 (multiples of 64, at most 1024 slots; so at 2^21 particles up to 8
+ * GiB of rows, at 2^24 up to 32 GiB), so cap is a floor (default 192). level_shift s (0..3; -1 keeps) walks the
  * first hierarchy level whose cell side is at least 2^(s-1) H: larger cells
  * mean fewer cells and more candidates per particle. The order of a gather
  * row is the walk order, so it follows the walked level. */

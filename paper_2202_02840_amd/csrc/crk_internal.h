@@ -371,10 +371,10 @@ __host__ __device__ inline int walk_cap_for(double g, double n) {
     return (int)(c < 1024.0 ? c : 1024.0);
 }
 
-// The most slots per scratch row that still fit 2^31 slots (8 GiB) for n
+// The most slots per scratch row that still fit 2^33 slots (32 GiB) for n
 // particles, a multiple of 64 and at most 1024.
 inline int walk_cap_limit(double n) {
-    const double c = n > 0.0 ? 64.0 * std::floor(2147483648.0 / n / 64.0) : 1024.0;
+    const double c = n > 0.0 ? 64.0 * std::floor(8589934592.0 / n / 64.0) : 1024.0;
     return (int)(c < 1024.0 ? c : 1024.0);
 }
 
