@@ -164,7 +164,9 @@ crk_status crk_workspace_estimate(const crk_ctx *ctx, int64_t n, int32_t nboxes,
  *      *n_pairs (host, may be NULL): number of ordered pairs (i, j), j in N_s(i).
  *      *n_cells (host, may be NULL): cells per dimension.
  * The context keeps the sorted positions and H, the gather lists N_g and the
- * pair lists N_s. Synchronises the stream. Errors: CRK_ERR_INVALID_ARG,
+ * pair lists N_s; unless p->precision is CRK_MIXED also the FP64 volumes of
+ * eq. (vol) over N_g, summed as the lists are placed (crk_moments hands
+ * them out). Synchronises the stream. Errors: CRK_ERR_INVALID_ARG,
  * CRK_ERR_NONFINITE, CRK_ERR_SUPPORT, CRK_ERR_WORKSPACE, CRK_ERR_HIP.
  */
 crk_status crk_build_cells(crk_ctx *ctx, int64_t n, const double *x, const double *y,
@@ -236,7 +238,10 @@ crk_status crk_permute(crk_ctx *ctx, const double *src, double *dst, int32_t nco
  *   gm0[3][n], gm1[9][n], gm2[18][n]: their gradients in x_i with H_i and
  *   every V_j held fixed (d d / d x_i = I).
  * Any output pointer except V may be NULL when the call is only needed for the
- * volumes. The context also keeps V for the later passes.
+ * volumes. The context also keeps V for the later passes. In FP64 and
+ * adaptive precision the build (crk_build_cells, crk_update_support) has
+ * already summed the FP64 volumes over its lists, and this call copies them
+ * out; after crk_build_leaves, or in CRK_MIXED, it sums them itself.
  */
 crk_status crk_moments(crk_ctx *ctx, const crk_params *p, double *nsum, double *V, double *m0,
                        double *m1, double *m2, double *gm0, double *gm1, double *gm2);
