@@ -657,12 +657,44 @@ __device__ __forceinline__ void gas_state(int64_t i, const double *v, const doub
         atomicOr(bad, 1);
 }
 
+// Appends i to list when `take` (one atomic per wavefront; the list order
+// is that of the arrivals, and every user treats the rows independently).
+__device__ __forceinline__ void append_row(bool take, int64_t i, int32_t *list,
+                                           unsigned long long *count) {
+    const uint64_t m = __ballot(take);
+    if (m == 0) return;
+    const int lane = threadIdx.x & 63;
+    const int lead = __ffsll((unsigned long long)m) - 1;
+    unsigned long long base = 0;
+    if (lane == lead) base = atomicAdd(count, (unsigned long long)__popcll(m));
+    base = __shfl(base, lead, 64);
+    if (take) list[base + __popcll(m & ((1ull << lane) - 1ull))] = (int32_t)i;
+}
+
+// Conditioning of particle i's RK template (see k_flag): 1 when it exceeds
+// kappa_max, so that the row runs in FP64
+__device__ __forceinline__ int kappa_flag(int64_t i, int64_t n, const double4 *__restrict__ posH,
+                                          const double *A, const double *B, const double *gA,
+                                          const double *gB, double kappa_max) {
+    double H = posH[i].w;
+    double b2 = 0.0, a2 = 0.0, g2 = 0.0;
+#pragma unroll
+    for (int x = 0; x < 3; x++) {
+        b2 += B[x * n + i] * B[x * n + i];
+        a2 += gA[x * n + i] * gA[x * n + i];
+    }
+#pragma unroll
+    for (int q = 0; q < 9; q++) g2 += gB[q * n + i] * gB[q * n + i];
+    double kap = 1.0 + sqrt(b2) * H + sqrt(g2) * H * H + sqrt(a2) * H / fabs(A[i]);
+    return !(kap <= kappa_max);
+}
+
 template <typename V4, typename T>
 __device__ __forceinline__ void pack8_one(int64_t i, int64_t n, const double4 *__restrict__ posH,
                                           const double *v, const double *m, const double *u,
                                           const double *rho, const double *V, const double *A,
                                           const double *B, const double *gA, const double *gB,
-                                          const double *gv, const DerivPrm &p, const int32_t *flag,
+                                          const double *gv, const DerivPrm &p, bool fp64row,
                                           V4 *o, double4 *aux, int *bad) {
     double r, P, cs;
     gas_state(i, v, m, u, rho, V, n, p.gamma, r, P, cs, bad);
@@ -679,7 +711,7 @@ __device__ __forceinline__ void pack8_one(int64_t i, int64_t n, const double4 *_
     }
     Rec<double> rc;
     make_rec(posH[i].w, v[i], v[n + i], v[2 * n + i], V[i], P, r, cs, A[i], B3, gA3, gB9, gv9, p,
-             flag && flag[i] != 0, rc);
+             fp64row, rc);
     store_rec<V4, T>(o, rc);
     if constexpr (sizeof(T) == 4) {
         const double4 x = posH[i];
@@ -696,7 +728,9 @@ __global__ __launch_bounds__(kBlock) void k_pack8(int64_t n, const double4 *__re
                                                   const double *rho, const double *V, const double *A,
                                                   const double *B, const double *gA, const double *gB,
                                                   const double *gv, DerivPrm p, const int32_t *flag,
-                                                  V4 *rec, double4 *aux, int *bad) {
+                                                  V4 *rec, double4 *aux, int *bad, double kappa_max,
+                                                  int32_t *flag_out, int32_t *flist,
+                                                  unsigned long long *nflag) {
     // FP32 records are assembled in LDS and leave as one contiguous run per
     // block (consecutive lanes, consecutive 16 bytes) instead of nine
     // 16-byte stores 144 bytes apart per lane
@@ -704,8 +738,20 @@ __global__ __launch_bounds__(kBlock) void k_pack8(int64_t n, const double4 *__re
     __shared__ V4 s_rec[STAGE ? kBlock * kRec : 1];
     const int64_t b0 = (int64_t)blockIdx.x * kBlock;
     const int64_t i = b0 + threadIdx.x;
-    if (i < n) pack8_one<V4, T>(i, n, posH, v, m, u, rho, V, A, B, gA, gB, gv, p, flag,
-                                STAGE ? s_rec + threadIdx.x * kRec : rec + i * kRec, aux, bad);
+    // with flag_out the FP64 rows are decided here (as k_flag does), from
+    // the corrections the record is made of
+    int f = 0;
+    if (i < n) {
+        if (flag_out) {
+            f = kappa_flag(i, n, posH, A, B, gA, gB, kappa_max);
+            flag_out[i] = f;
+        } else {
+            f = flag && flag[i] != 0;
+        }
+        pack8_one<V4, T>(i, n, posH, v, m, u, rho, V, A, B, gA, gB, gv, p, f != 0,
+                         STAGE ? s_rec + threadIdx.x * kRec : rec + i * kRec, aux, bad);
+    }
+    if (flag_out) append_row(f != 0, i, flist, nflag);
     if constexpr (STAGE) {
         __syncthreads();
         const int cnt = (int)((n - b0 < kBlock ? n - b0 : kBlock) * kRec);
@@ -1549,20 +1595,6 @@ __global__ __launch_bounds__(kBlock) void k_timestep(int64_t n, const double4 *_
 // carry B.d, (gradB)^T d and gradA / A, which reach |B| H, |gradB| H^2 and
 // |gradA| H / |A| relative to the O(1) part; their sum bounds how much a
 // rounding of the terms is amplified in the (cancelling) row sums.
-// Appends i to list when `take` (one atomic per wavefront; the list order
-// is that of the arrivals, and every user treats the rows independently).
-__device__ __forceinline__ void append_row(bool take, int64_t i, int32_t *list,
-                                           unsigned long long *count) {
-    const uint64_t m = __ballot(take);
-    if (m == 0) return;
-    const int lane = threadIdx.x & 63;
-    const int lead = __ffsll((unsigned long long)m) - 1;
-    unsigned long long base = 0;
-    if (lane == lead) base = atomicAdd(count, (unsigned long long)__popcll(m));
-    base = __shfl(base, lead, 64);
-    if (take) list[base + __popcll(m & ((1ull << lane) - 1ull))] = (int32_t)i;
-}
-
 __global__ __launch_bounds__(kBlock) void k_flag(int64_t n, const double4 *__restrict__ posH,
                                                  const double *A, const double *B, const double *gA,
                                                  const double *gB, double kappa_max, int32_t *flag,
@@ -1570,17 +1602,7 @@ __global__ __launch_bounds__(kBlock) void k_flag(int64_t n, const double4 *__res
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     int f = 0;
     if (i < n) {
-        double H = posH[i].w;
-        double b2 = 0.0, a2 = 0.0, g2 = 0.0;
-#pragma unroll
-        for (int x = 0; x < 3; x++) {
-            b2 += B[x * n + i] * B[x * n + i];
-            a2 += gA[x * n + i] * gA[x * n + i];
-        }
-#pragma unroll
-        for (int q = 0; q < 9; q++) g2 += gB[q * n + i] * gB[q * n + i];
-        double kap = 1.0 + sqrt(b2) * H + sqrt(g2) * H * H + sqrt(a2) * H / fabs(A[i]);
-        f = !(kap <= kappa_max);
+        f = kappa_flag(i, n, posH, A, B, gA, gB, kappa_max);
         flag[i] = f;
     }
     append_row(f != 0, i, flist, nflag);
@@ -1851,14 +1873,14 @@ struct AdaptRows {
     const int64_t *nflag_dev = nullptr, *ntouch_dev = nullptr;
 };
 
-static crk_status adapt_rows(crk_ctx *c, const crk_params *p, const double *A, const double *B,
-                             const double *gA, const double *gB, bool gm, AdaptRows &r) {
+// fpos[n] counts the flagged rows (appended in any order: their fix is per
+// row), the int32 words below it mark the touched rows, whose offsets tpos
+// list them in ascending order (rows of neighbouring particles side by side
+// share their partners' loads in the fix). First the buffers, the cleared
+// marks and counter; the flagging follows (k_flag, or the record packing of
+// the derivative call), then adapt_finish.
+static crk_status adapt_prep(crk_ctx *c, AdaptRows &r) {
     const int64_t n = c->n;
-    const double4 *posH = (const double4 *)c->posH.p;
-    const int64_t *goff = (const int64_t *)c->goff.p;
-    const int32_t *gidx = (const int32_t *)c->gidx.p;
-    const int32_t *eb = (const int32_t *)c->eb.p, *ee = (const int32_t *)c->ee.p,
-                  *eidx = (const int32_t *)c->eidx.p;
     CRK_TRY(ensure(c, c->flag, (size_t)n * sizeof(int32_t)));
     CRK_TRY(ensure(c, c->flist, (size_t)n * sizeof(int32_t)));
     CRK_TRY(ensure(c, c->tlist, (size_t)n * sizeof(int32_t)));
@@ -1867,17 +1889,23 @@ static crk_status adapt_rows(crk_ctx *c, const crk_params *p, const double *A, c
     r.flag = (int32_t *)c->flag.p;
     r.flist = (int32_t *)c->flist.p;
     r.tlist = (int32_t *)c->tlist.p;
+    int64_t *fpos = (int64_t *)c->fpos.p;
+    k_zero_marks<<<nblocks(n), kBlock, 0, c->stream>>>((int32_t *)fpos, n, fpos + n);
+    CRK_HIP(c, hipGetLastError());
+    return CRK_OK;
+}
+
+// the flagged rows' partners marked and listed, and the counts
+static crk_status adapt_finish(crk_ctx *c, bool gm, AdaptRows &r) {
+    const int64_t n = c->n;
+    const int64_t *goff = (const int64_t *)c->goff.p;
+    const int32_t *gidx = (const int32_t *)c->gidx.p;
+    const int32_t *eb = (const int32_t *)c->eb.p, *ee = (const int32_t *)c->ee.p,
+                  *eidx = (const int32_t *)c->eidx.p;
     int64_t *fpos = (int64_t *)c->fpos.p, *tpos = (int64_t *)c->tpos.p;
     {
         KTimer kt_(c, "k_flag");
-        // fpos[n] counts the flagged rows (appended in any order: their fix
-        // is per row), the int32 words below it mark the touched rows, whose
-        // offsets tpos list them in ascending order (rows of neighbouring
-        // particles side by side share their partners' loads in the fix)
         int32_t *mark = (int32_t *)fpos;
-        k_zero_marks<<<nblocks(n), kBlock, 0, c->stream>>>(mark, n, fpos + n);
-        k_flag<<<nblocks(n), kBlock, 0, c->stream>>>(n, posH, A, B, gA, gB, p->kappa_max, r.flag, r.flist,
-                                                     (unsigned long long *)(fpos + n));
         k_mark<<<(unsigned)std::min<int64_t>(nblocks(n * 16), 1024), kBlock, 0, c->stream>>>(
             r.flist, fpos + n, goff, gidx, eb, ee, eidx, mark);
         CRK_TRY(scan_counts2(c, mark, nullptr, n, tpos, nullptr));
@@ -1901,6 +1929,21 @@ static crk_status adapt_rows(crk_ctx *c, const crk_params *p, const double *A, c
         c->last_ntouch = r.ntouch;
     }
     return CRK_OK;
+}
+
+// FP64 rows from the corrections given (k_flag), then adapt_finish
+static crk_status adapt_rows(crk_ctx *c, const crk_params *p, const double *A, const double *B,
+                             const double *gA, const double *gB, bool gm, AdaptRows &r) {
+    const int64_t n = c->n;
+    CRK_TRY(adapt_prep(c, r));
+    {
+        KTimer kt_(c, "k_flag");
+        k_flag<<<nblocks(n), kBlock, 0, c->stream>>>(n, (const double4 *)c->posH.p, A, B, gA, gB,
+                                                     p->kappa_max, r.flag, r.flist,
+                                                     (unsigned long long *)((int64_t *)c->fpos.p + n));
+    }
+    CRK_HIP(c, hipGetLastError());
+    return adapt_finish(c, gm, r);
 }
 
 crk_status crk_derivatives(crk_ctx *c, const crk_params *p, const double *v, const double *m,
@@ -1940,13 +1983,14 @@ crk_status crk_derivatives(crk_ctx *c, const crk_params *p, const double *v, con
     CRK_TRY(zero_async(c, bad, 1));
     int Gg = c->G_grad, Gd = c->G_der, Pd = c->P_der, Pg = c->P_grad;
 
-    // adaptive mode: FP64 rows for ill-conditioned RK templates
+    // adaptive mode: FP64 rows for ill-conditioned RK templates, flagged by
+    // the record packing (which reads the corrections anyway) after the FP32
+    // velocity gradient has summed every row; the flagged rows' gradients
+    // are then redone in FP64, and the FP32 passes never read the grad v
+    // part of a flagged particle's record (its pairs are left to FP64)
     const bool gm = c->graph_mode != 0;
     AdaptRows ar;
-    if (adapt) CRK_TRY(adapt_rows(c, p, A, B, gA, gB, gm, ar));
-    int32_t *flag = ar.flag, *flist = ar.flist, *tlist = ar.tlist;
-    const int64_t nflag = ar.nflag, ntouch = ar.ntouch;
-    const int64_t *nflag_dev = ar.nflag_dev, *ntouch_dev = ar.ntouch_dev;
+    if (adapt) CRK_TRY(adapt_prep(c, ar));
 
     if (f32) {
         CRK_TRY(ensure(c, c->rec6, (size_t)n * 2 * sizeof(float4)));
@@ -1967,24 +2011,35 @@ crk_status crk_derivatives(crk_ctx *c, const crk_params *p, const double *v, con
         {
             KTimer kt_(c, "k_gradv");
             if (Pg > 0) {
-#define L_GV(PP) k_gradv_bal<float, PP><<<pblocks(n, PP), kBlock, 0, c->stream>>>(posH, goff, gidx, r6, A, B, gA, gB, n, box, flag, gradv)
+#define L_GV(PP) k_gradv_bal<float, PP><<<pblocks(n, PP), kBlock, 0, c->stream>>>(posH, goff, gidx, r6, A, B, gA, gB, n, box, nullptr, gradv)
                 CRK_DISPATCH_P(Pg, L_GV);
 #undef L_GV
             } else {
-#define L_GV(GG) k_gradv<float, GG><<<gblocks(n, GG), kBlock, 0, c->stream>>>(posH, goff, gidx, r6, A, B, gA, gB, n, box, nullptr, 0, nullptr, flag, gradv)
+#define L_GV(GG) k_gradv<float, GG><<<gblocks(n, GG), kBlock, 0, c->stream>>>(posH, goff, gidx, r6, A, B, gA, gB, n, box, nullptr, 0, nullptr, nullptr, gradv)
                 CRK_DISPATCH_G(Gg, L_GV);
 #undef L_GV
             }
         }
+        {
+            KTimer kt_(c, "k_pack");
+            if (adapt)
+                k_pack8<float4, float><<<nblocks(n), kBlock, 0, c->stream>>>(
+                    n, posH, v, m, u, rho, V, A, B, gA, gB, gradv, dp, nullptr, r7, aux, bad, p->kappa_max,
+                    ar.flag, ar.flist, (unsigned long long *)((int64_t *)c->fpos.p + n));
+            else
+                k_pack8<float4, float><<<nblocks(n), kBlock, 0, c->stream>>>(
+                    n, posH, v, m, u, rho, V, A, B, gA, gB, gradv, dp, nullptr, r7, aux, bad, 0.0, nullptr,
+                    nullptr, nullptr);
+        }
+        if (adapt) CRK_TRY(adapt_finish(c, gm, ar));
+        int32_t *flag = ar.flag, *flist = ar.flist, *tlist = ar.tlist;
+        const int64_t nflag = ar.nflag, ntouch = ar.ntouch;
+        const int64_t *nflag_dev = ar.nflag_dev, *ntouch_dev = ar.ntouch_dev;
         if (adapt && nflag > 0) {
 #define L_GV(GG) k_gradv<double, GG><<<fix_blocks(nflag, GG, gm), kBlock, 0, c->stream>>>(posH, goff, gidx, r6d, A, B, gA, gB, n, box, flist, nflag, nflag_dev, nullptr, gradv)
             KTimer kt_(c, "k_gradv_fix");
             CRK_DISPATCH_G(Gg, L_GV);
 #undef L_GV
-        }
-        {
-            KTimer kt_(c, "k_pack");
-            k_pack8<float4, float><<<nblocks(n), kBlock, 0, c->stream>>>(n, posH, v, m, u, rho, V, A, B, gA, gB, gradv, dp, flag, r7, aux, bad);
         }
         {
             KTimer kt_(c, "k_deriv");
@@ -2027,7 +2082,7 @@ crk_status crk_derivatives(crk_ctx *c, const crk_params *p, const double *v, con
         }
         {
             KTimer kt_(c, "k_pack");
-            k_pack8<double4, double><<<nblocks(n), kBlock, 0, c->stream>>>(n, posH, v, m, u, rho, V, A, B, gA, gB, gradv, dp, nullptr, r7, nullptr, bad);
+            k_pack8<double4, double><<<nblocks(n), kBlock, 0, c->stream>>>(n, posH, v, m, u, rho, V, A, B, gA, gB, gradv, dp, nullptr, r7, nullptr, bad, 0.0, nullptr, nullptr, nullptr);
         }
         {
             KTimer kt_(c, "k_deriv");
@@ -2140,7 +2195,7 @@ crk_status crk::compat_pass(crk_ctx *c, const crk_params *p, const double *v, co
         }
         {
             KTimer kt_(c, "k_pack");
-            if (!keep) k_pack8<float4, float><<<nblocks(n), kBlock, 0, c->stream>>>(n, posH, v, m, u, rho, V, A, B, gA, gB, gradv, dp, ar.flag, r7, aux, bad);
+            if (!keep) k_pack8<float4, float><<<nblocks(n), kBlock, 0, c->stream>>>(n, posH, v, m, u, rho, V, A, B, gA, gB, gradv, dp, ar.flag, r7, aux, bad, 0.0, nullptr, nullptr, nullptr);
             k_pack_ce<float4, float><<<nblocks(n), kBlock, 0, c->stream>>>(n, v, pk, dpdt, m, u, rho, V, p->gamma, p->a, dt, ce, ced);
             if (two) k_pack_ce<float4, float><<<nblocks(n), kBlock, 0, c->stream>>>(n, v, pk2, dpdt, m, u, rho, V, p->gamma, p->a, dt, ce2, ced2);
         }
@@ -2164,7 +2219,7 @@ crk_status crk::compat_pass(crk_ctx *c, const crk_params *p, const double *v, co
         double4 *ce2 = two ? ce + n : nullptr;
         {
             KTimer kt_(c, "k_pack");
-            if (!keep) k_pack8<double4, double><<<nblocks(n), kBlock, 0, c->stream>>>(n, posH, v, m, u, rho, V, A, B, gA, gB, gradv, dp, nullptr, r7, nullptr, bad);
+            if (!keep) k_pack8<double4, double><<<nblocks(n), kBlock, 0, c->stream>>>(n, posH, v, m, u, rho, V, A, B, gA, gB, gradv, dp, nullptr, r7, nullptr, bad, 0.0, nullptr, nullptr, nullptr);
             k_pack_ce<double4, double><<<nblocks(n), kBlock, 0, c->stream>>>(n, v, pk, dpdt, m, u, rho, V, p->gamma, p->a, dt, ce, nullptr);
             if (two) k_pack_ce<double4, double><<<nblocks(n), kBlock, 0, c->stream>>>(n, v, pk2, dpdt, m, u, rho, V, p->gamma, p->a, dt, ce2, nullptr);
         }
